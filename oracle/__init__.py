@@ -1,0 +1,182 @@
+"""CPU oracle for state-vector circuit simulation (complex128, FP64 sums).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()``
+and the benchmark's ``cpu_baseline`` leg may import this package; the GPU
+library never does, and this package imports nothing from it.
+
+The arithmetic lives in ``sv_oracle.c`` (plain C, OpenMP over independent
+amplitude groups only); this module marshals numpy arrays into it and builds
+whole-circuit runs out of single-gate applications.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "sv_oracle.c")
+
+CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fcx-limited-range", "-fPIC", "-shared",
+          "-std=c11"]
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` with gcc.  Building the checker is not using it."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+        L.orc_gate_matrix.argtypes = [ctypes.c_char_p, dp, ctypes.c_int, dp, ip, ip]
+        L.orc_gate_matrix.restype = ctypes.c_int
+        L.orc_apply.argtypes = [vp, ctypes.c_int, vp, ip, ctypes.c_int, ip, ip, ctypes.c_int]
+        L.orc_apply.restype = ctypes.c_int
+        L.orc_norm.argtypes = [vp, ctypes.c_int]
+        L.orc_norm.restype = ctypes.c_double
+        L.orc_expect_pauli.argtypes = [vp, ctypes.c_int, ip, ctypes.c_char_p, ctypes.c_int, dp]
+        L.orc_expect_pauli.restype = ctypes.c_int
+        L.orc_sample.argtypes = [vp, ctypes.c_int, dp, ctypes.c_int64, ip, ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_uint64), dp]
+        L.orc_sample.restype = ctypes.c_int
+        L.orc_set_basis.argtypes = [vp, ctypes.c_int, ctypes.c_uint64]
+        L.orc_set_basis.restype = None
+        _lib = L
+    return _lib
+
+
+def _ints(seq):
+    seq = list(seq)
+    return (ctypes.c_int * max(1, len(seq)))(*seq)
+
+
+def _nqubits(psi: np.ndarray) -> int:
+    n = int(psi.size).bit_length() - 1
+    if psi.dtype != np.complex128 or psi.ndim != 1 or (1 << n) != psi.size or not psi.flags.c_contiguous:
+        raise ValueError("state must be a contiguous 1-D complex128 array of length 2^n")
+    return n
+
+
+def gate_matrix(name: str, params=()) -> tuple:
+    """(matrix complex128 [2^k, 2^k], k, n_controls) from the oracle's own gate table."""
+    p = (ctypes.c_double * 3)(*[float(v) for v in params])
+    out = np.zeros((4, 4), dtype=np.complex128)
+    k = ctypes.c_int()
+    nc = ctypes.c_int()
+    rc = lib().orc_gate_matrix(name.encode(), p, len(params), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.byref(k), ctypes.byref(nc))
+    if rc != 0:
+        raise ValueError(f"unknown gate {name!r} or bad params {params!r}")
+    d = 1 << k.value
+    return out.reshape(-1)[: d * d].reshape(d, d).copy(), k.value, nc.value
+
+
+def apply(psi: np.ndarray, matrix, targets, controls=(), cvals=None) -> None:
+    """In-place dense gate application (targets[0] is the matrix LSB)."""
+    n = _nqubits(psi)
+    m = np.ascontiguousarray(matrix, dtype=np.complex128)
+    k = len(targets)
+    if m.shape != (1 << k, 1 << k):
+        raise ValueError("matrix shape does not match the number of targets")
+    cv = None if cvals is None else _ints(cvals)
+    rc = lib().orc_apply(psi.ctypes.data, n, m.ctypes.data, _ints(targets), k, _ints(controls), cv,
+                         len(controls))
+    if rc != 0:
+        raise ValueError("invalid gate arguments")
+
+
+def apply_gate(psi: np.ndarray, gate) -> None:
+    """Apply one workload gate (name, qubits, params)."""
+    name, qubits, params = gate
+    if name in ("mat", "mat_dg"):
+        m = np.asarray(params, dtype=np.complex128)
+        if name == "mat_dg":
+            m = np.conj(m).T
+        apply(psi, m, qubits)
+        return
+    m, k, nc = gate_matrix(name, params)
+    if len(qubits) != k + nc:
+        raise ValueError(f"gate {name} takes {k + nc} qubits")
+    apply(psi, m, qubits[nc:], qubits[:nc])
+
+
+def basis_state(n: int, x: int = 0) -> np.ndarray:
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[x] = 1.0
+    return psi
+
+
+def run(n: int, gates, basis: int = 0, psi: np.ndarray | None = None) -> np.ndarray:
+    """The ordered product of the gates applied to |basis> (or to a copy of psi)."""
+    psi = basis_state(n, basis) if psi is None else np.array(psi, dtype=np.complex128, copy=True)
+    for g in gates:
+        apply_gate(psi, g)
+    return psi
+
+
+def norm(psi: np.ndarray) -> float:
+    """sum_i |psi_i|^2 (compensated, FP64)."""
+    return float(lib().orc_norm(psi.ctypes.data, _nqubits(psi)))
+
+
+def expect_pauli(psi: np.ndarray, term) -> float:
+    """<psi|P|psi>/<psi|psi> for a Pauli string given as [(qubit, 'X'|'Y'|'Z'), ...]."""
+    n = _nqubits(psi)
+    qs = [int(q) for q, _ in term]
+    ops = "".join(o for _, o in term)
+    out = (ctypes.c_double * 3)()
+    rc = lib().orc_expect_pauli(psi.ctypes.data, n, _ints(qs), ops.encode(), len(qs), out)
+    if rc != 0:
+        raise ValueError("invalid Pauli term")
+    return float(out[0])
+
+
+def expect_pauli_full(psi: np.ndarray, term) -> tuple:
+    """(real part, imaginary part, norm) of the expectation."""
+    n = _nqubits(psi)
+    qs = [int(q) for q, _ in term]
+    ops = "".join(o for _, o in term)
+    out = (ctypes.c_double * 3)()
+    rc = lib().orc_expect_pauli(psi.ctypes.data, n, _ints(qs), ops.encode(), len(qs), out)
+    if rc != 0:
+        raise ValueError("invalid Pauli term")
+    return float(out[0]), float(out[1]), float(out[2])
+
+
+def sample(psi: np.ndarray, u, bit_ordering=None, return_cdf: bool = False):
+    """Outcomes for the uniforms ``u`` (upper-bound inverse CDF, input order)."""
+    n = _nqubits(psi)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(u.size, dtype=np.uint64)
+    cdf = np.zeros(psi.size, dtype=np.float64) if return_cdf else None
+    bo = None if bit_ordering is None else _ints(bit_ordering)
+    nb = 0 if bit_ordering is None else len(bit_ordering)
+    rc = lib().orc_sample(psi.ctypes.data, n, u.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), u.size,
+                          bo, nb, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                          None if cdf is None else cdf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != 0:
+        raise ValueError("invalid sampling arguments (uniforms must lie in [0, 1))")
+    return (out, cdf) if return_cdf else out
+
+
+def fidelity(a: np.ndarray, b: np.ndarray) -> float:
+    """|<a|b>|^2 / (<a|a><b|b>) in FP64."""
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    ov = np.vdot(a, b)
+    return float(abs(ov) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real))
