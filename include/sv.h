@@ -1,0 +1,231 @@
+/*
+ * sv.h -- C ABI of libsv, an MI355X (gfx950) state-vector simulation core.
+ *
+ * The problem statement follows the cuQuantum SDK paper, Sec. II: a state of
+ * n qubits is a complex vector of 2^n amplitudes held in GPU memory; gates are
+ * applied to it in place; measurement outcomes are sampled from the
+ * probability distribution without collapsing it; expectation values of
+ * Pauli strings are computed from it; a library handle owns a small
+ * workspace (a few tens of MB, Table I "resource management").
+ *
+ * Conventions used by every entry point:
+ *   - Qubit j is bit j of the amplitude index (qubit 0 is the least
+ *     significant bit); the paper maps each qubit to one index bit (Sec. II-C).
+ *   - Amplitudes are interleaved (re, im): 8 bytes per amplitude for
+ *     SV_C64 (two floats), 16 bytes for SV_C128 (two doubles).
+ *   - A k-qubit gate matrix is passed as 2^k x 2^k complex128, row-major,
+ *     interleaved (re, im) doubles; bit a of its row/column index is the
+ *     state of targets[a] (targets[0] is the matrix least-significant bit).
+ *     For SV_C64 states the library rounds it once to complex64.
+ *   - Control values default to 1.
+ *   - Every call validates all arguments before any device work; invalid
+ *     input returns SV_ERR_INVALID_VALUE and leaves the state untouched.
+ *   - Host arrays passed in are copied before the call returns; the caller
+ *     may free them immediately.
+ *   - sv_apply_* calls are asynchronous on the handle's stream; sv_norm,
+ *     sv_expect_pauli, sv_sample, sv_copy_* and sv_sync block until their
+ *     results are in host memory.
+ *   - HIP runtime errors map to SV_ERR_DEVICE; allocation failure maps to
+ *     SV_ERR_OUT_OF_MEMORY.  sv_last_error() returns a thread-local message
+ *     for the last non-OK status.  No C++ exception crosses this ABI.
+ *   - A handle may be used by one host thread at a time; different handles
+ *     may be used concurrently from different threads.
+ */
+#ifndef SV_H
+#define SV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SV_OK = 0,
+    SV_ERR_INVALID_VALUE = 1,
+    SV_ERR_OUT_OF_MEMORY = 2,
+    SV_ERR_NOT_SUPPORTED = 3,
+    SV_ERR_DEVICE = 4,
+    SV_ERR_INTERNAL = 5
+} sv_status_t;
+
+typedef enum { SV_C64 = 0, SV_C128 = 1 } sv_dtype_t;
+
+/* Largest qubit count of one state (2^36 complex64 amplitudes = 512 GiB is
+ * beyond one MI355X; 34 qubits complex64 / 33 complex128 = 128 GiB fit). */
+#define SV_MAX_QUBITS 36
+/* Largest number of targets of one dense gate or fused block. */
+#define SV_MAX_TARGETS 10
+
+typedef struct sv_handle_s* sv_handle_t;
+typedef struct sv_state_s* sv_state_t;
+typedef struct sv_fused_s* sv_fused_t;
+
+/* One gate of a circuit, as input to gate fusion.  `matrix` is
+ * 2^n_targets x 2^n_targets complex128 (see conventions). */
+typedef struct {
+    int32_t n_targets;
+    const int32_t* targets;
+    const double* matrix;
+    int32_t n_controls;
+    const int32_t* controls;
+    const int32_t* control_values; /* NULL: all 1 */
+} sv_gate_t;
+
+/* A Pauli string: ops[a] in {'I','X','Y','Z'} acts on qubits[a]. */
+typedef struct {
+    int32_t n_ops;
+    const int32_t* qubits;
+    const char* ops;
+} sv_pauli_term_t;
+
+/* ---------------------------------------------------------------- handles */
+
+/* Creates a handle bound to `hip_stream` (a hipStream_t; NULL means the null
+ * stream) on the current device, with a device workspace of
+ * `workspace_bytes` (0: 64 MiB; minimum 12 MiB) used for reduction partials,
+ * sampler tables and gate matrices (Table I: the handle holds a few tens of
+ * MB of GPU memory).  The stream is borrowed, never destroyed by libsv. */
+sv_status_t sv_handle_create(sv_handle_t* out, void* hip_stream, size_t workspace_bytes);
+
+/* Waits for the handle's stream, then frees the workspace and the handle. */
+sv_status_t sv_handle_destroy(sv_handle_t h);
+
+/* Rebinds the handle to another stream (the caller synchronises the switch). */
+sv_status_t sv_handle_set_stream(sv_handle_t h, void* hip_stream);
+
+/* Blocks until all work issued on the handle's stream has finished. */
+sv_status_t sv_sync(sv_handle_t h);
+
+/* ----------------------------------------------------------------- states */
+
+/* Creates a state of n_qubits in [1, SV_MAX_QUBITS] and the given dtype.
+ * device_ptr == NULL: libsv allocates 2^n amplitudes and sets |0..0>.
+ * Otherwise the state borrows device_ptr, which must hold 2^n amplitudes of
+ * the dtype, be 256-byte aligned and outlive the state; its contents are
+ * left as they are (the relaxed memory model of Sec. II-A: the vector only
+ * has to live in GPU memory).  The state is used with handle h. */
+sv_status_t sv_create(sv_handle_t h, int32_t n_qubits, sv_dtype_t dtype, void* device_ptr,
+                      sv_state_t* out);
+
+/* Frees the state (and its amplitudes if libsv allocated them). */
+sv_status_t sv_destroy(sv_state_t s);
+
+/* Device address of the amplitudes. */
+sv_status_t sv_state_device_ptr(sv_state_t s, void** out);
+
+/* Sets the state to the computational basis state |x>, x < 2^n (async). */
+sv_status_t sv_set_basis_state(sv_state_t s, uint64_t x);
+
+/* ------------------------------------------------------- gate application */
+
+/*
+ * Applies a dense k-qubit gate in place (Table I: gate application with a
+ * dense matrix; Sec. II-B: gate application is the most time-consuming
+ * operation).  For every index i whose target bits are 0 and whose control
+ * bits equal the control values, the 2^k amplitudes psi[i + off(c)], with
+ * off(c) = sum over set bits a of c of 2^targets[a], are replaced by
+ * M (or M^dagger if adjoint != 0) times them; all other amplitudes are
+ * unchanged.  1 <= k <= min(n, SV_MAX_TARGETS); targets and controls are
+ * distinct and in [0, n); control_values may be NULL (all 1) or hold 0/1.
+ * Asynchronous on the handle's stream.
+ */
+sv_status_t sv_apply_matrix(sv_state_t s, const double* matrix, const int32_t* targets, int32_t k,
+                            const int32_t* controls, const int32_t* control_values,
+                            int32_t n_controls, int32_t adjoint);
+
+/*
+ * Named standard gates (host only).  Writes the target matrix of `name`
+ * into matrix_out (room for 16 complex128), its number of targets into
+ * *n_targets and its number of leading control qubits into *n_controls.
+ * Names: "u3" (theta, phi, lambda; OpenQASM convention), "h", "x", "y",
+ * "z", "cx", "cz", "cp" (phi), "swap"; a "_dg" suffix yields the adjoint.
+ * For the controlled gates the first qubit of a gate is its control.
+ */
+sv_status_t sv_gate_matrix(const char* name, const double* params, int32_t n_params,
+                           double* matrix_out, int32_t* n_targets, int32_t* n_controls);
+
+/* ------------------------------------------------------------ gate fusion */
+
+/*
+ * Gate fusion (Sec. II-B, after qHiPSTER; the fused-gate-size option of
+ * Sec. II-D): groups consecutive gates into blocks of at most
+ * max_fused_qubits (1..SV_MAX_TARGETS) qubits, each block one dense unitary
+ * equal to the ordered product of its gates embedded on the block's qubits
+ * (controls become dense qubits of the block).  Host only; FP64 products.
+ * Applying the blocks in order equals applying the gates in order.
+ */
+sv_status_t sv_fuse_gates(const sv_gate_t* gates, int32_t n_gates, int32_t max_fused_qubits,
+                          sv_fused_t* out);
+
+/* Number of blocks. */
+sv_status_t sv_fused_count(sv_fused_t f, int32_t* n_blocks);
+
+/* Block i: its qubit count into *k, its ascending targets into targets
+ * (room for SV_MAX_TARGETS), and, if matrix != NULL, its 2^k x 2^k
+ * complex128 matrix. */
+sv_status_t sv_fused_block(sv_fused_t f, int32_t i, int32_t* k, int32_t* targets, double* matrix);
+
+sv_status_t sv_fused_free(sv_fused_t f);
+
+/* Applies all blocks of f in order (async).  Block matrices are uploaded in
+ * batches of up to 1 MiB, one host-to-device copy per batch. */
+sv_status_t sv_apply_fused(sv_state_t s, sv_fused_t f);
+
+/* Applies blocks [first, first + count) of f in order (async), so a caller
+ * can interleave its own work (timing events, measurements) between blocks.
+ * Requires 0 <= first and first + count <= the block count. */
+sv_status_t sv_apply_fused_range(sv_state_t s, sv_fused_t f, int32_t first, int32_t count);
+
+/* ------------------------------------------------------------- reductions */
+
+/* *out = sum_i |psi_i|^2 accumulated in FP64 in a fixed order (bitwise
+ * reproducible for a given state).  Blocks. */
+sv_status_t sv_norm(sv_state_t s, double* out);
+
+/* Scales the state by 1/sqrt(norm) (FP64 norm, scale applied in the state's
+ * precision).  *norm_out (may be NULL) receives the norm before scaling. */
+sv_status_t sv_renormalize(sv_state_t s, double* norm_out);
+
+/*
+ * Expectation values of Pauli strings (Table I: expectation value with
+ * Pauli strings): out[t] = <psi|P_t|psi> / <psi|psi>, FP64 accumulation in a
+ * fixed order.  A term may not name a qubit twice.  Blocks.
+ */
+sv_status_t sv_expect_pauli(sv_state_t s, const sv_pauli_term_t* terms, int32_t n_terms,
+                            double* out);
+
+/*
+ * Sampler (Table I: bit strings as measurement outcomes without collapsing
+ * the state; Sec. II: from the numerically computed probability
+ * distribution).  For each uniform u in [0, 1), the outcome is the
+ * smallest index i with u * N < C_i, C_i the FP64 cumulative sum of
+ * |psi_j|^2 over j <= i and N its total; zero-probability indices are never
+ * returned.  With bit_ordering (q_0 .. q_{m-1}, distinct), bit a of each
+ * output is bit q_a of the outcome; NULL returns the full index.  Outputs
+ * are in the order of the uniforms.  Blocks.
+ */
+sv_status_t sv_sample(sv_state_t s, const double* uniforms, int64_t n_shots,
+                      const int32_t* bit_ordering, int32_t n_bits, uint64_t* out);
+
+/* ------------------------------------------------------------------ copies */
+
+/* Copies amplitudes [first, first + count) to / from host memory (Table I:
+ * accessor, here without reordering).  Blocks. */
+sv_status_t sv_copy_to_host(sv_state_t s, void* dst, uint64_t first, uint64_t count);
+sv_status_t sv_copy_from_host(sv_state_t s, const void* src, uint64_t first, uint64_t count);
+
+/* ------------------------------------------------------------------ errors */
+
+/* Thread-local text for the last non-OK status of this thread. */
+const char* sv_last_error(void);
+
+/* Library version string. */
+const char* sv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SV_H */

@@ -56,6 +56,8 @@ def lib():
         L.orc_sample.restype = ctypes.c_int
         L.orc_set_basis.argtypes = [vp, ctypes.c_int, ctypes.c_uint64]
         L.orc_set_basis.restype = None
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -172,6 +174,11 @@ def sample(psi: np.ndarray, u, bit_ordering=None, return_cdf: bool = False):
     if rc != 0:
         raise ValueError("invalid sampling arguments (uniforms must lie in [0, 1))")
     return (out, cdf) if return_cdf else out
+
+
+def threads() -> int:
+    """OpenMP threads used by the oracle's parallel loops."""
+    return int(lib().orc_threads())
 
 
 def fidelity(a: np.ndarray, b: np.ndarray) -> float:

@@ -25,6 +25,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double _Complex cplx;
 
@@ -294,6 +297,16 @@ int orc_sample(const double* psi_ri, int n, const double* u, int64_t nshots,
     }
     if (!cdf_out) free(cdf);
     return ORC_OK;
+}
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* |0..0> or |x> */

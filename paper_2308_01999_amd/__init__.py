@@ -1,0 +1,412 @@
+"""Python binding of libsv, the MI355X state-vector simulation core.
+
+A thin ctypes layer over the C ABI declared in ``include/sv.h``: the
+``sv_*`` functions below have the names of the C entry points and only
+marshal arguments; every step of the computation runs in libsv's HIP kernels
+(or, for gate fusion and the gate table, in its host C++).  PyTorch provides
+device memory and streams: states are ``torch`` tensors on ``cuda:0`` whose
+storage libsv borrows, and handles run on torch streams.
+
+Importing the package loads ``libsv.so`` and raises ``ImportError`` if it has
+not been built (``python paper_2308_01999_amd/build.py``): there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsv.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libsv.so is not built at {LIB_PATH}; run paper_2308_01999_amd/build.py")
+
+_L = ctypes.CDLL(LIB_PATH)
+
+SV_OK, SV_ERR_INVALID_VALUE, SV_ERR_OUT_OF_MEMORY, SV_ERR_NOT_SUPPORTED, SV_ERR_DEVICE, SV_ERR_INTERNAL = range(6)
+SV_C64, SV_C128 = 0, 1
+SV_MAX_QUBITS = 36
+SV_MAX_TARGETS = 10
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_pi32 = ctypes.POINTER(ctypes.c_int32)
+_pd = ctypes.POINTER(ctypes.c_double)
+_pu64 = ctypes.POINTER(ctypes.c_uint64)
+
+
+class sv_gate_t(ctypes.Structure):
+    _fields_ = [("n_targets", _i32), ("targets", _pi32), ("matrix", _pd), ("n_controls", _i32),
+                ("controls", _pi32), ("control_values", _pi32)]
+
+
+class sv_pauli_term_t(ctypes.Structure):
+    _fields_ = [("n_ops", _i32), ("qubits", _pi32), ("ops", ctypes.c_char_p)]
+
+
+# name -> (argtypes); every entry point returns sv_status_t except the two
+# string getters
+_SIGS = {
+    "sv_handle_create": [ctypes.POINTER(_vp), _vp, ctypes.c_size_t],
+    "sv_handle_destroy": [_vp],
+    "sv_handle_set_stream": [_vp, _vp],
+    "sv_sync": [_vp],
+    "sv_create": [_vp, _i32, ctypes.c_int, _vp, ctypes.POINTER(_vp)],
+    "sv_destroy": [_vp],
+    "sv_state_device_ptr": [_vp, ctypes.POINTER(_vp)],
+    "sv_set_basis_state": [_vp, _u64],
+    "sv_apply_matrix": [_vp, _pd, _pi32, _i32, _pi32, _pi32, _i32, _i32],
+    "sv_gate_matrix": [ctypes.c_char_p, _pd, _i32, _pd, _pi32, _pi32],
+    "sv_fuse_gates": [ctypes.POINTER(sv_gate_t), _i32, _i32, ctypes.POINTER(_vp)],
+    "sv_fused_count": [_vp, _pi32],
+    "sv_fused_block": [_vp, _i32, _pi32, _pi32, _pd],
+    "sv_fused_free": [_vp],
+    "sv_apply_fused": [_vp, _vp],
+    "sv_apply_fused_range": [_vp, _vp, _i32, _i32],
+    "sv_norm": [_vp, _pd],
+    "sv_renormalize": [_vp, _pd],
+    "sv_expect_pauli": [_vp, ctypes.POINTER(sv_pauli_term_t), _i32, _pd],
+    "sv_sample": [_vp, _pd, _i64, _pi32, _i32, _pu64],
+    "sv_copy_to_host": [_vp, _vp, _u64, _u64],
+    "sv_copy_from_host": [_vp, _vp, _u64, _u64],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_L, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_L.sv_last_error.argtypes = []
+_L.sv_last_error.restype = ctypes.c_char_p
+_L.sv_version.argtypes = []
+_L.sv_version.restype = ctypes.c_char_p
+
+EXPORTED = sorted(list(_SIGS) + ["sv_last_error", "sv_version"])
+
+
+class SVError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libsv status {status}: {msg}")
+        self.status = status
+
+
+def _check(status: int) -> None:
+    if status != SV_OK:
+        raise SVError(status, _L.sv_last_error().decode(errors="replace"))
+
+
+def _i32arr(seq):
+    seq = [int(v) for v in seq]
+    return (ctypes.c_int32 * max(1, len(seq)))(*seq)
+
+
+def _mat(m) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_pd)
+
+
+# --------------------------------------------------------------------------
+# 1:1 entry points
+# --------------------------------------------------------------------------
+
+def sv_version() -> str:
+    return _L.sv_version().decode()
+
+
+def sv_last_error() -> str:
+    return _L.sv_last_error().decode(errors="replace")
+
+
+def sv_handle_create(stream_ptr: int = 0, workspace_bytes: int = 0) -> int:
+    h = _vp()
+    _check(_L.sv_handle_create(ctypes.byref(h), _vp(stream_ptr or None), workspace_bytes))
+    return h.value
+
+
+def sv_handle_destroy(h: int) -> None:
+    _check(_L.sv_handle_destroy(_vp(h)))
+
+
+def sv_handle_set_stream(h: int, stream_ptr: int) -> None:
+    _check(_L.sv_handle_set_stream(_vp(h), _vp(stream_ptr or None)))
+
+
+def sv_sync(h: int) -> None:
+    _check(_L.sv_sync(_vp(h)))
+
+
+def sv_create(h: int, n_qubits: int, dtype: int, device_ptr: int = 0) -> int:
+    s = _vp()
+    _check(_L.sv_create(_vp(h), n_qubits, dtype, _vp(device_ptr or None), ctypes.byref(s)))
+    return s.value
+
+
+def sv_destroy(s: int) -> None:
+    _check(_L.sv_destroy(_vp(s)))
+
+
+def sv_state_device_ptr(s: int) -> int:
+    p = _vp()
+    _check(_L.sv_state_device_ptr(_vp(s), ctypes.byref(p)))
+    return p.value
+
+
+def sv_set_basis_state(s: int, x: int) -> None:
+    _check(_L.sv_set_basis_state(_vp(s), x))
+
+
+def sv_apply_matrix(s: int, matrix, targets, controls=(), control_values=None, adjoint: bool = False) -> None:
+    m = _mat(matrix)
+    cv = None if control_values is None else _i32arr(control_values)
+    _check(_L.sv_apply_matrix(_vp(s), m.ctypes.data_as(_pd), _i32arr(targets), len(targets),
+                              _i32arr(controls), cv, len(controls), int(bool(adjoint))))
+
+
+def sv_gate_matrix(name: str, params=()) -> tuple:
+    """(matrix [2^k, 2^k] complex128, n_targets, n_controls) of a named gate."""
+    p = (ctypes.c_double * 3)(*[float(v) for v in params])
+    out = np.zeros(16, dtype=np.complex128)
+    nt = _i32()
+    nc = _i32()
+    _check(_L.sv_gate_matrix(name.encode(), p, len(params), _dptr(out), ctypes.byref(nt), ctypes.byref(nc)))
+    d = 1 << nt.value
+    return out[: d * d].reshape(d, d).copy(), nt.value, nc.value
+
+
+def _gate_struct(targets, matrix, controls=(), control_values=None, keep=None):
+    m = _mat(matrix)
+    t = _i32arr(targets)
+    c = _i32arr(controls)
+    cv = None if control_values is None else _i32arr(control_values)
+    keep.extend([m, t, c, cv])
+    return sv_gate_t(len(targets), t, m.ctypes.data_as(_pd), len(controls), c, cv)
+
+
+def sv_fuse_gates(gates, max_fused_qubits: int) -> int:
+    """gates: list of (targets, matrix, controls, control_values)."""
+    keep = []
+    arr = (sv_gate_t * max(1, len(gates)))()
+    for i, (t, m, c, cv) in enumerate(gates):
+        arr[i] = _gate_struct(t, m, c, cv, keep)
+    f = _vp()
+    _check(_L.sv_fuse_gates(arr, len(gates), max_fused_qubits, ctypes.byref(f)))
+    return f.value
+
+
+def sv_fused_count(f: int) -> int:
+    n = _i32()
+    _check(_L.sv_fused_count(_vp(f), ctypes.byref(n)))
+    return n.value
+
+
+def sv_fused_block(f: int, i: int) -> tuple:
+    k = _i32()
+    t = (ctypes.c_int32 * SV_MAX_TARGETS)()
+    _check(_L.sv_fused_block(_vp(f), i, ctypes.byref(k), t, None))
+    m = np.zeros((1 << k.value) ** 2, dtype=np.complex128)
+    _check(_L.sv_fused_block(_vp(f), i, ctypes.byref(k), t, _dptr(m)))
+    d = 1 << k.value
+    return tuple(t[: k.value]), m.reshape(d, d)
+
+
+def sv_fused_free(f: int) -> None:
+    _check(_L.sv_fused_free(_vp(f)))
+
+
+def sv_apply_fused(s: int, f: int) -> None:
+    _check(_L.sv_apply_fused(_vp(s), _vp(f)))
+
+
+def sv_apply_fused_range(s: int, f: int, first: int, count: int) -> None:
+    _check(_L.sv_apply_fused_range(_vp(s), _vp(f), first, count))
+
+
+def sv_norm(s: int) -> float:
+    out = ctypes.c_double()
+    _check(_L.sv_norm(_vp(s), ctypes.byref(out)))
+    return out.value
+
+
+def sv_renormalize(s: int) -> float:
+    out = ctypes.c_double()
+    _check(_L.sv_renormalize(_vp(s), ctypes.byref(out)))
+    return out.value
+
+
+def sv_expect_pauli(s: int, terms) -> np.ndarray:
+    """terms: list of [(qubit, 'X'|'Y'|'Z'|'I'), ...]."""
+    keep = []
+    arr = (sv_pauli_term_t * max(1, len(terms)))()
+    for i, term in enumerate(terms):
+        q = _i32arr([qq for qq, _ in term])
+        ops = "".join(o for _, o in term).encode()
+        keep.extend([q, ops])
+        arr[i] = sv_pauli_term_t(len(term), q, ops)
+    out = np.zeros(max(1, len(terms)), dtype=np.float64)
+    _check(_L.sv_expect_pauli(_vp(s), arr, len(terms), _dptr(out)))
+    return out[: len(terms)]
+
+
+def sv_sample(s: int, uniforms, bit_ordering=None) -> np.ndarray:
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    out = np.zeros(max(1, u.size), dtype=np.uint64)
+    bo = None if bit_ordering is None else _i32arr(bit_ordering)
+    nb = 0 if bit_ordering is None else len(bit_ordering)
+    _check(_L.sv_sample(_vp(s), _dptr(u), u.size, bo, nb, out.ctypes.data_as(_pu64)))
+    return out[: u.size]
+
+
+def sv_copy_to_host(s: int, dst: np.ndarray, first: int = 0, count: int | None = None) -> None:
+    count = dst.size if count is None else count
+    _check(_L.sv_copy_to_host(_vp(s), dst.ctypes.data, first, count))
+
+
+def sv_copy_from_host(s: int, src: np.ndarray, first: int = 0) -> None:
+    src = np.ascontiguousarray(src)
+    _check(_L.sv_copy_from_host(_vp(s), src.ctypes.data, first, src.size))
+
+
+# --------------------------------------------------------------------------
+# small conveniences over the entry points (no arithmetic of the method)
+# --------------------------------------------------------------------------
+
+DTYPES = {"c64": SV_C64, "c128": SV_C128}
+NP_DTYPES = {SV_C64: np.complex64, SV_C128: np.complex128}
+
+
+class Handle:
+    """A libsv handle on a torch stream (default: torch's current stream)."""
+
+    def __init__(self, stream=None, workspace_bytes: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libsv needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.h = sv_handle_create(self.stream.cuda_stream, workspace_bytes)
+
+    def sync(self):
+        sv_sync(self.h)
+
+    def close(self):
+        if self.h:
+            sv_handle_destroy(self.h)
+            self.h = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class State:
+    """A state of n qubits in a torch tensor that libsv borrows."""
+
+    def __init__(self, handle: Handle, n: int, dtype: str = "c64", basis: int = 0, tensor=None):
+        import torch
+        self.handle = handle
+        self.n = n
+        self.dt = DTYPES[dtype]
+        tdt = torch.complex64 if self.dt == SV_C64 else torch.complex128
+        if tensor is None:
+            with torch.cuda.stream(handle.stream):
+                tensor = torch.empty(1 << n, dtype=tdt, device="cuda")
+        if tensor.dtype != tdt or tensor.numel() != (1 << n) or not tensor.is_contiguous():
+            raise ValueError("tensor must be contiguous with 2^n elements of the state's dtype")
+        self.tensor = tensor
+        self.s = sv_create(handle.h, n, self.dt, tensor.data_ptr())
+        if basis is not None:
+            sv_set_basis_state(self.s, basis)
+
+    def apply_matrix(self, matrix, targets, controls=(), control_values=None, adjoint=False):
+        sv_apply_matrix(self.s, matrix, targets, controls, control_values, adjoint)
+
+    def apply_gate(self, gate):
+        """One workload gate (name, qubits, params) via the library's gate table."""
+        name, qubits, params = gate
+        if name in ("mat", "mat_dg"):
+            sv_apply_matrix(self.s, params, qubits, adjoint=(name == "mat_dg"))
+            return
+        m, nt, nc = sv_gate_matrix(name, params)
+        sv_apply_matrix(self.s, m, qubits[nc:], qubits[:nc])
+
+    def run(self, gates, max_fused_qubits: int | None = None):
+        if not max_fused_qubits:
+            for g in gates:
+                self.apply_gate(g)
+            return None
+        f = fuse(gates, max_fused_qubits)
+        try:
+            sv_apply_fused(self.s, f.f)
+            return f.count
+        finally:
+            f.free()
+
+    def norm(self):
+        return sv_norm(self.s)
+
+    def expect(self, terms):
+        return sv_expect_pauli(self.s, terms)
+
+    def sample(self, uniforms, bit_ordering=None):
+        return sv_sample(self.s, uniforms, bit_ordering)
+
+    def to_numpy(self):
+        out = np.empty(1 << self.n, dtype=NP_DTYPES[self.dt])
+        sv_copy_to_host(self.s, out)
+        return out
+
+    def close(self):
+        if self.s:
+            sv_destroy(self.s)
+            self.s = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gate_entries(gates):
+    """Workload gates -> (targets, matrix, controls, control_values) via the
+    library's gate table."""
+    out = []
+    for name, qubits, params in gates:
+        if name in ("mat", "mat_dg"):
+            m = _mat(params)
+            out.append((tuple(qubits), np.conj(m).T if name == "mat_dg" else m, (), None))
+        else:
+            m, nt, nc = sv_gate_matrix(name, params)
+            out.append((tuple(qubits[nc:]), m, tuple(qubits[:nc]), None))
+    return out
+
+
+class Fused:
+    def __init__(self, f: int):
+        self.f = f
+        self.count = sv_fused_count(f)
+
+    def blocks(self):
+        return [sv_fused_block(self.f, i) for i in range(self.count)]
+
+    def free(self):
+        if self.f:
+            sv_fused_free(self.f)
+            self.f = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def fuse(gates, max_fused_qubits: int) -> Fused:
+    return Fused(sv_fuse_gates(gate_entries(gates), max_fused_qubits))

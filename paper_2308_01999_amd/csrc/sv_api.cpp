@@ -1,0 +1,548 @@
+// The C ABI of libsv (declared in include/sv.h): argument validation, handle
+// and state bookkeeping, matrix staging, and dispatch to the HIP kernels.
+// No exception crosses the ABI: every entry point catches and maps to a
+// status code with a thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sv_internal.h"
+
+namespace sv {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax);
+void gate_matrix(const char* name, const double* params, int n_params, double* out, int* n_targets,
+                 int* n_controls);
+
+namespace {
+
+size_t amp_bytes(sv_dtype_t dt) { return dt == SV_C64 ? 8 : 16; }
+
+template <typename F>
+sv_status_t guarded(F&& f)
+{
+    try {
+        f();
+        return SV_OK;
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return SV_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+        set_error("internal error");
+        return SV_ERR_INTERNAL;
+    }
+}
+
+void check_state(const sv_state_s* s)
+{
+    SV_CHECK(s != nullptr && s->h != nullptr && s->d != nullptr, "invalid state");
+}
+
+// Validates targets/controls of one gate on an n-qubit state and fills the
+// sweep descriptor.
+GateDesc make_desc(int n, const int32_t* targets, int k, const int32_t* controls, const int32_t* cvals,
+                   int n_controls)
+{
+    SV_CHECK(k >= 1 && k <= SV_MAX_TARGETS, "k must be in [1, 10]");
+    SV_CHECK(k <= n, "more targets than qubits");
+    SV_CHECK(targets != nullptr, "targets is NULL");
+    SV_CHECK(n_controls >= 0, "n_controls is negative");
+    SV_CHECK(n_controls == 0 || controls != nullptr, "controls is NULL");
+    SV_CHECK(k + n_controls <= n, "targets plus controls exceed the qubit count");
+    GateDesc d;
+    d.k = k;
+    uint64_t used = 0;
+    int minq = n;
+    for (int a = 0; a < k; ++a) {
+        const int q = targets[a];
+        SV_CHECK(q >= 0 && q < n, "target out of range");
+        SV_CHECK(!((used >> q) & 1), "repeated target");
+        used |= uint64_t(1) << q;
+        d.tbit[a] = uint64_t(1) << q;
+        minq = std::min(minq, q);
+    }
+    d.min_target = minq;
+    for (int a = 0; a < n_controls; ++a) {
+        const int q = controls[a];
+        SV_CHECK(q >= 0 && q < n, "control out of range");
+        SV_CHECK(!((used >> q) & 1), "control repeats a target or another control");
+        used |= uint64_t(1) << q;
+        const int v = cvals ? cvals[a] : 1;
+        SV_CHECK(v == 0 || v == 1, "control values must be 0 or 1");
+        if (v) d.cval |= uint64_t(1) << q;
+    }
+    d.n_fixed = 0;
+    for (int q = 0; q < n; ++q)
+        if ((used >> q) & 1) d.fixed_sorted[d.n_fixed++] = q;
+    d.n_groups = uint64_t(1) << (n - k - n_controls);
+    return d;
+}
+
+// Converts a complex128 matrix (optionally its adjoint) into the state's
+// precision in `dst` (host).
+void convert_matrix(const double* m, int k, int adjoint, sv_dtype_t dt, void* dst)
+{
+    const int d = 1 << k;
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+            const int src = adjoint ? (c * d + r) : (r * d + c);
+            double re = m[2 * src], im = m[2 * src + 1];
+            if (adjoint) im = -im;
+            if (dt == SV_C64) {
+                float* o = static_cast<float*>(dst);
+                o[2 * (r * d + c)] = float(re);
+                o[2 * (r * d + c) + 1] = float(im);
+            } else {
+                double* o = static_cast<double*>(dst);
+                o[2 * (r * d + c)] = re;
+                o[2 * (r * d + c) + 1] = im;
+            }
+        }
+}
+
+void check_matrix_finite(const double* m, int k)
+{
+    SV_CHECK(m != nullptr, "matrix is NULL");
+    const size_t n = size_t(2) << (2 * k);
+    for (size_t i = 0; i < n; ++i) SV_CHECK(std::isfinite(m[i]), "matrix entry is not finite");
+}
+
+}  // namespace
+
+// Matrix ring: the device region [0, kMatRingBytes) of the workspace mirrors
+// the pinned host region of the same size, in kMatRingSegments segments.
+// Before host bytes of a segment are rewritten, the copies that last read
+// that segment must have completed: an event is recorded when the ring
+// leaves a segment and waited on when it comes back to it.  On the device
+// side, stream order puts every later copy after the kernels that read the
+// earlier contents.
+const void* stage_matrix(sv_handle_s* h, const void* host, size_t bytes)
+{
+    const size_t seg = kMatRingBytes / kMatRingSegments;
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes > seg) {
+        // large gates (k >= 9): copy into the scratch part of the workspace
+        // and wait, so that the host buffer may be released on return
+        SV_CHECK(kMatRingBytes + bytes <= h->ws_bytes, "matrix larger than the handle's workspace");
+        char* dst = h->ws + kMatRingBytes;
+        SV_HIP(hipMemcpyAsync(dst, host, bytes, hipMemcpyHostToDevice, h->stream));
+        SV_HIP(hipStreamSynchronize(h->stream));
+        return dst;
+    }
+    size_t pos = h->ring_pos;
+    if ((pos % seg) + bytes > seg) pos = (pos / seg + 1) * seg;  // does not fit: next segment
+    if (pos >= kMatRingBytes) pos = 0;
+    const int new_seg = int(pos / seg);
+    if (new_seg != h->ring_seg) {
+        // leaving ring_seg: mark its last use; entering new_seg: wait for its last use
+        SV_HIP(hipEventRecord(h->seg_event[h->ring_seg], h->stream));
+        h->seg_event_live[h->ring_seg] = true;
+        if (h->seg_event_live[new_seg]) {
+            SV_HIP(hipEventSynchronize(h->seg_event[new_seg]));
+            h->seg_event_live[new_seg] = false;
+        }
+        h->ring_seg = new_seg;
+    }
+    std::memcpy(h->pinned + pos, host, bytes);
+    SV_HIP(hipMemcpyAsync(h->ws + pos, h->pinned + pos, bytes, hipMemcpyHostToDevice, h->stream));
+    h->ring_pos = pos + bytes;
+    return h->ws + pos;
+}
+
+}  // namespace sv
+
+using namespace sv;
+
+extern "C" {
+
+const char* sv_last_error(void) { return g_last_error.c_str(); }
+
+const char* sv_version(void) { return "libsv 0.1 (gfx950)"; }
+
+sv_status_t sv_handle_create(sv_handle_t* out, void* hip_stream, size_t workspace_bytes)
+{
+    return guarded([&] {
+        SV_CHECK(out != nullptr, "out is NULL");
+        *out = nullptr;
+        if (workspace_bytes == 0) workspace_bytes = kDefaultWorkspace;
+        SV_CHECK(workspace_bytes >= kMinWorkspace, "workspace must be at least 12 MiB");
+        auto* h = new sv_handle_s;
+        try {
+            h->stream = static_cast<hipStream_t>(hip_stream);
+            SV_HIP(hipGetDevice(&h->device));
+            SV_HIP(hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, h->device));
+            SV_HIP(hipMalloc(&h->ws, workspace_bytes));
+            h->ws_bytes = workspace_bytes;
+            SV_HIP(hipHostMalloc(&h->pinned, kMatRingBytes, hipHostMallocDefault));
+            h->pinned_bytes = kMatRingBytes;
+            for (int i = 0; i < kMatRingSegments; ++i)
+                SV_HIP(hipEventCreateWithFlags(&h->seg_event[i], hipEventDisableTiming));
+        } catch (...) {
+            for (int i = 0; i < kMatRingSegments; ++i)
+                if (h->seg_event[i]) (void)hipEventDestroy(h->seg_event[i]);
+            if (h->pinned) (void)hipHostFree(h->pinned);
+            if (h->ws) (void)hipFree(h->ws);
+            delete h;
+            throw;
+        }
+        *out = h;
+    });
+}
+
+sv_status_t sv_handle_destroy(sv_handle_t h)
+{
+    return guarded([&] {
+        SV_CHECK(h != nullptr, "handle is NULL");
+        const hipError_t e = hipStreamSynchronize(h->stream);
+        for (int i = 0; i < kMatRingSegments; ++i)
+            if (h->seg_event[i]) (void)hipEventDestroy(h->seg_event[i]);
+        if (h->pinned) (void)hipHostFree(h->pinned);
+        if (h->ws) (void)hipFree(h->ws);
+        delete h;
+        SV_HIP(e);
+    });
+}
+
+sv_status_t sv_handle_set_stream(sv_handle_t h, void* hip_stream)
+{
+    return guarded([&] {
+        SV_CHECK(h != nullptr, "handle is NULL");
+        h->stream = static_cast<hipStream_t>(hip_stream);
+    });
+}
+
+sv_status_t sv_sync(sv_handle_t h)
+{
+    return guarded([&] {
+        SV_CHECK(h != nullptr, "handle is NULL");
+        SV_HIP(hipStreamSynchronize(h->stream));
+    });
+}
+
+sv_status_t sv_create(sv_handle_t h, int32_t n_qubits, sv_dtype_t dtype, void* device_ptr, sv_state_t* out)
+{
+    return guarded([&] {
+        SV_CHECK(out != nullptr, "out is NULL");
+        *out = nullptr;
+        SV_CHECK(h != nullptr, "handle is NULL");
+        SV_CHECK(n_qubits >= 1 && n_qubits <= SV_MAX_QUBITS, "n_qubits must be in [1, 36]");
+        SV_CHECK(dtype == SV_C64 || dtype == SV_C128, "dtype must be SV_C64 or SV_C128");
+        SV_CHECK(device_ptr == nullptr || (reinterpret_cast<uintptr_t>(device_ptr) & 255) == 0,
+                 "device_ptr must be 256-byte aligned");
+        auto* s = new sv_state_s;
+        s->h = h;
+        s->n = n_qubits;
+        s->dt = dtype;
+        if (device_ptr) {
+            s->d = device_ptr;
+            s->owned = false;
+        } else {
+            const size_t bytes = amp_bytes(dtype) << n_qubits;
+            const hipError_t e = hipMalloc(&s->d, bytes);
+            if (e != hipSuccess) {
+                delete s;
+                (void)hipGetLastError();
+                throw Error{SV_ERR_OUT_OF_MEMORY, "hipMalloc of the state failed: " + std::string(hipGetErrorString(e))};
+            }
+            s->owned = true;
+            try {
+                launch_set_basis(h, dtype, s->d, n_qubits, 0);
+            } catch (...) {
+                (void)hipFree(s->d);
+                delete s;
+                throw;
+            }
+        }
+        *out = s;
+    });
+}
+
+sv_status_t sv_destroy(sv_state_t s)
+{
+    return guarded([&] {
+        SV_CHECK(s != nullptr, "state is NULL");
+        hipError_t e = hipSuccess;
+        if (s->owned) {
+            e = hipStreamSynchronize(s->h->stream);
+            const hipError_t e2 = hipFree(s->d);
+            if (e == hipSuccess) e = e2;
+        }
+        delete s;
+        SV_HIP(e);
+    });
+}
+
+sv_status_t sv_state_device_ptr(sv_state_t s, void** out)
+{
+    return guarded([&] {
+        check_state(s);
+        SV_CHECK(out != nullptr, "out is NULL");
+        *out = s->d;
+    });
+}
+
+sv_status_t sv_set_basis_state(sv_state_t s, uint64_t x)
+{
+    return guarded([&] {
+        check_state(s);
+        SV_CHECK(x < (uint64_t(1) << s->n), "basis index out of range");
+        launch_set_basis(s->h, s->dt, s->d, s->n, x);
+    });
+}
+
+sv_status_t sv_apply_matrix(sv_state_t s, const double* matrix, const int32_t* targets, int32_t k,
+                            const int32_t* controls, const int32_t* control_values, int32_t n_controls,
+                            int32_t adjoint)
+{
+    return guarded([&] {
+        check_state(s);
+        const GateDesc d = make_desc(s->n, targets, k, controls, control_values, n_controls);
+        check_matrix_finite(matrix, k);
+        const size_t bytes = (amp_bytes(s->dt)) << (2 * k);
+        std::vector<char> tmp(bytes);
+        convert_matrix(matrix, k, adjoint, s->dt, tmp.data());
+        const void* dm = stage_matrix(s->h, tmp.data(), bytes);
+        launch_apply(s->h, s->dt, s->d, dm, d);
+    });
+}
+
+sv_status_t sv_gate_matrix(const char* name, const double* params, int32_t n_params, double* matrix_out,
+                           int32_t* n_targets, int32_t* n_controls)
+{
+    return guarded([&] {
+        int nt = 0, nc = 0;
+        gate_matrix(name, params, n_params, matrix_out, &nt, &nc);
+        if (n_targets) *n_targets = nt;
+        if (n_controls) *n_controls = nc;
+    });
+}
+
+sv_status_t sv_fuse_gates(const sv_gate_t* gates, int32_t n_gates, int32_t max_fused_qubits, sv_fused_t* out)
+{
+    return guarded([&] {
+        SV_CHECK(out != nullptr, "out is NULL");
+        *out = nullptr;
+        *out = fuse(gates, n_gates, max_fused_qubits);
+    });
+}
+
+sv_status_t sv_fused_count(sv_fused_t f, int32_t* n_blocks)
+{
+    return guarded([&] {
+        SV_CHECK(f != nullptr && n_blocks != nullptr, "NULL argument");
+        *n_blocks = f->n_blocks;
+    });
+}
+
+sv_status_t sv_fused_block(sv_fused_t f, int32_t i, int32_t* k, int32_t* targets, double* matrix)
+{
+    return guarded([&] {
+        SV_CHECK(f != nullptr && k != nullptr && targets != nullptr, "NULL argument");
+        SV_CHECK(i >= 0 && i < f->n_blocks, "block index out of range");
+        const FusedBlock& b = f->blocks[i];
+        *k = b.k;
+        for (int a = 0; a < b.k; ++a) targets[a] = b.targets[a];
+        if (matrix) std::memcpy(matrix, b.m, sizeof(double) * (size_t(2) << (2 * b.k)));
+    });
+}
+
+sv_status_t sv_fused_free(sv_fused_t f)
+{
+    return guarded([&] {
+        if (!f) return;
+        delete[] f->blocks;
+        delete[] f->storage;
+        delete f;
+    });
+}
+
+}  // extern "C"
+
+namespace sv {
+namespace {
+
+void apply_fused_blocks(sv_state_s* s, sv_fused_s* f, int first, int count)
+{
+    check_state(s);
+    SV_CHECK(f != nullptr, "fused gates are NULL");
+    SV_CHECK(first >= 0 && count >= 0 && first <= f->n_blocks && count <= f->n_blocks - first,
+             "block range out of bounds");
+    const int end = first + count;
+    std::vector<GateDesc> descs(f->n_blocks);
+    for (int b = first; b < end; ++b) {
+        const FusedBlock& blk = f->blocks[b];
+        descs[b] = make_desc(s->n, blk.targets, blk.k, nullptr, nullptr, 0);
+    }
+    {
+        const size_t ab = amp_bytes(s->dt);
+        // stage in segment-sized batches: one copy per batch of blocks
+        const size_t seg = kMatRingBytes / kMatRingSegments;
+        int b = first;
+        while (b < end) {
+            std::vector<size_t> offs;
+            size_t bytes = 0;
+            int e = b;
+            while (e < end) {
+                const size_t mb = ((ab << (2 * f->blocks[e].k)) + 255) & ~size_t(255);
+                if (bytes + mb > seg) break;
+                offs.push_back(bytes);
+                bytes += mb;
+                ++e;
+            }
+            if (e == b) {
+                // one block larger than a ring segment: stage it on its own
+                const size_t mb = ab << (2 * f->blocks[b].k);
+                std::vector<char> one(mb);
+                convert_matrix(f->blocks[b].m, f->blocks[b].k, 0, s->dt, one.data());
+                launch_apply(s->h, s->dt, s->d, stage_matrix(s->h, one.data(), mb), descs[b]);
+                ++b;
+                continue;
+            }
+            std::vector<char> tmp(bytes);
+            for (int j = b; j < e; ++j)
+                convert_matrix(f->blocks[j].m, f->blocks[j].k, 0, s->dt, tmp.data() + offs[j - b]);
+            const char* dm = static_cast<const char*>(stage_matrix(s->h, tmp.data(), bytes));
+            for (int j = b; j < e; ++j) launch_apply(s->h, s->dt, s->d, dm + offs[j - b], descs[j]);
+            b = e;
+        }
+    }
+}
+
+}  // namespace
+}  // namespace sv
+
+extern "C" {
+
+sv_status_t sv_apply_fused(sv_state_t s, sv_fused_t f)
+{
+    return guarded([&] {
+        SV_CHECK(f != nullptr, "fused gates are NULL");
+        apply_fused_blocks(s, f, 0, f->n_blocks);
+    });
+}
+
+sv_status_t sv_apply_fused_range(sv_state_t s, sv_fused_t f, int32_t first, int32_t count)
+{
+    return guarded([&] { apply_fused_blocks(s, f, first, count); });
+}
+
+sv_status_t sv_norm(sv_state_t s, double* out)
+{
+    return guarded([&] {
+        check_state(s);
+        SV_CHECK(out != nullptr, "out is NULL");
+        *out = run_norm(s->h, s->dt, s->d, s->n);
+    });
+}
+
+sv_status_t sv_renormalize(sv_state_t s, double* norm_out)
+{
+    return guarded([&] {
+        check_state(s);
+        const double nrm = run_norm(s->h, s->dt, s->d, s->n);
+        SV_CHECK(nrm > 0.0 && std::isfinite(nrm), "state norm is zero or not finite");
+        launch_scale(s->h, s->dt, s->d, s->n, 1.0 / std::sqrt(nrm));
+        if (norm_out) *norm_out = nrm;
+    });
+}
+
+sv_status_t sv_expect_pauli(sv_state_t s, const sv_pauli_term_t* terms, int32_t n_terms, double* out)
+{
+    return guarded([&] {
+        check_state(s);
+        SV_CHECK(n_terms >= 0, "n_terms is negative");
+        SV_CHECK(n_terms == 0 || (terms != nullptr && out != nullptr), "NULL argument");
+        std::vector<PauliMasks> pm(n_terms);
+        for (int t = 0; t < n_terms; ++t) {
+            const sv_pauli_term_t& T = terms[t];
+            SV_CHECK(T.n_ops >= 0 && T.n_ops <= s->n, "term has a bad number of operators");
+            SV_CHECK(T.n_ops == 0 || (T.qubits && T.ops), "term has NULL arrays");
+            uint64_t seen = 0;
+            for (int a = 0; a < T.n_ops; ++a) {
+                const int q = T.qubits[a];
+                SV_CHECK(q >= 0 && q < s->n, "Pauli qubit out of range");
+                SV_CHECK(!((seen >> q) & 1), "Pauli term names a qubit twice");
+                seen |= uint64_t(1) << q;
+                const uint64_t b = uint64_t(1) << q;
+                switch (T.ops[a]) {
+                    case 'I': break;
+                    case 'X': pm[t].x |= b; break;
+                    case 'Y': pm[t].x |= b; pm[t].z |= b; pm[t].ny++; break;
+                    case 'Z': pm[t].z |= b; break;
+                    default: SV_CHECK(false, "Pauli operator must be one of I, X, Y, Z");
+                }
+            }
+        }
+        if (n_terms > 0) run_expect(s->h, s->dt, s->d, s->n, pm.data(), n_terms, out);
+    });
+}
+
+sv_status_t sv_sample(sv_state_t s, const double* uniforms, int64_t n_shots, const int32_t* bit_ordering,
+                      int32_t n_bits, uint64_t* out)
+{
+    return guarded([&] {
+        check_state(s);
+        SV_CHECK(n_shots >= 0, "n_shots is negative");
+        if (n_shots == 0) return;
+        SV_CHECK(uniforms != nullptr && out != nullptr, "NULL argument");
+        for (int64_t i = 0; i < n_shots; ++i)
+            SV_CHECK(uniforms[i] >= 0.0 && uniforms[i] < 1.0, "uniforms must lie in [0, 1)");
+        if (bit_ordering) {
+            SV_CHECK(n_bits >= 1 && n_bits <= s->n, "n_bits must be in [1, n]");
+            uint64_t seen = 0;
+            for (int b = 0; b < n_bits; ++b) {
+                const int q = bit_ordering[b];
+                SV_CHECK(q >= 0 && q < s->n, "bit_ordering entry out of range");
+                SV_CHECK(!((seen >> q) & 1), "bit_ordering repeats a qubit");
+                seen |= uint64_t(1) << q;
+            }
+        } else {
+            n_bits = 0;
+        }
+        run_sample(s->h, s->dt, s->d, s->n, uniforms, n_shots, bit_ordering, n_bits, out);
+    });
+}
+
+sv_status_t sv_copy_to_host(sv_state_t s, void* dst, uint64_t first, uint64_t count)
+{
+    return guarded([&] {
+        check_state(s);
+        const uint64_t dim = uint64_t(1) << s->n;
+        SV_CHECK(first <= dim && count <= dim - first, "range out of bounds");
+        if (count == 0) return;
+        SV_CHECK(dst != nullptr, "dst is NULL");
+        const size_t ab = amp_bytes(s->dt);
+        SV_HIP(hipMemcpyAsync(dst, static_cast<char*>(s->d) + first * ab, count * ab, hipMemcpyDeviceToHost,
+                              s->h->stream));
+        SV_HIP(hipStreamSynchronize(s->h->stream));
+    });
+}
+
+sv_status_t sv_copy_from_host(sv_state_t s, const void* src, uint64_t first, uint64_t count)
+{
+    return guarded([&] {
+        check_state(s);
+        const uint64_t dim = uint64_t(1) << s->n;
+        SV_CHECK(first <= dim && count <= dim - first, "range out of bounds");
+        if (count == 0) return;
+        SV_CHECK(src != nullptr, "src is NULL");
+        const size_t ab = amp_bytes(s->dt);
+        SV_HIP(hipMemcpyAsync(static_cast<char*>(s->d) + first * ab, src, count * ab, hipMemcpyHostToDevice,
+                              s->h->stream));
+        SV_HIP(hipStreamSynchronize(s->h->stream));
+    });
+}
+
+}  // extern "C"

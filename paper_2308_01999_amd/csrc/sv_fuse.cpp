@@ -1,0 +1,291 @@
+// Host side: the standard gate table and gate fusion.
+//
+// Gate fusion follows the idea the paper takes from qHiPSTER (Sec. II-B):
+// many small gates are multiplied into one multi-qubit matrix so that the
+// state is swept once per fused block instead of once per gate; the block
+// size is capped by a "max fused gate size" option (Sec. II-D).  The paper
+// does not give the fusion algorithm; this one is our own (see fuse_blocks).
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sv_internal.h"
+
+namespace sv {
+
+using cd = std::complex<double>;
+
+// ------------------------------------------------------------- gate table
+
+namespace {
+
+struct NamedGate {
+    const char* name;
+    int n_params;
+    int n_targets;
+    int n_controls;
+};
+
+const NamedGate kGates[] = {
+    {"u3", 3, 1, 0}, {"h", 0, 1, 0},  {"x", 0, 1, 0},  {"y", 0, 1, 0},    {"z", 0, 1, 0},
+    {"cx", 0, 1, 1}, {"cz", 0, 1, 1}, {"cp", 1, 1, 1}, {"swap", 0, 2, 0},
+};
+
+// Target matrix of a named gate, row-major, in std::complex.
+void named_matrix(const std::string& name, const double* p, cd* m)
+{
+    const cd I(0.0, 1.0);
+    if (name == "u3") {
+        // OpenQASM U3: [[cos, -e^{i lambda} sin], [e^{i phi} sin, e^{i(phi+lambda)} cos]]
+        const double c = std::cos(0.5 * p[0]), s = std::sin(0.5 * p[0]);
+        m[0] = c;
+        m[1] = -std::polar(1.0, p[2]) * s;
+        m[2] = std::polar(1.0, p[1]) * s;
+        m[3] = std::polar(1.0, p[1] + p[2]) * c;
+    } else if (name == "h") {
+        const double r = 1.0 / std::sqrt(2.0);
+        m[0] = r; m[1] = r; m[2] = r; m[3] = -r;
+    } else if (name == "x" || name == "cx") {
+        m[0] = 0; m[1] = 1; m[2] = 1; m[3] = 0;
+    } else if (name == "y") {
+        m[0] = 0; m[1] = -I; m[2] = I; m[3] = 0;
+    } else if (name == "z" || name == "cz") {
+        m[0] = 1; m[1] = 0; m[2] = 0; m[3] = -1;
+    } else if (name == "cp") {
+        m[0] = 1; m[1] = 0; m[2] = 0; m[3] = std::polar(1.0, p[0]);
+    } else if (name == "swap") {
+        // basis |b1 b0>: swaps |01> and |10>
+        for (int i = 0; i < 16; ++i) m[i] = 0;
+        m[0] = 1; m[1 * 4 + 2] = 1; m[2 * 4 + 1] = 1; m[3 * 4 + 3] = 1;
+    }
+}
+
+}  // namespace
+
+void gate_matrix(const char* name_c, const double* params, int n_params, double* out, int* n_targets,
+                 int* n_controls)
+{
+    SV_CHECK(name_c != nullptr, "gate name is NULL");
+    std::string name(name_c);
+    bool adj = false;
+    if (name.size() > 3 && name.compare(name.size() - 3, 3, "_dg") == 0) {
+        adj = true;
+        name.resize(name.size() - 3);
+    }
+    const NamedGate* g = nullptr;
+    for (const auto& e : kGates)
+        if (name == e.name) g = &e;
+    SV_CHECK(g != nullptr, "unknown gate name '" + std::string(name_c) + "'");
+    SV_CHECK(n_params == g->n_params, "gate '" + name + "' takes " + std::to_string(g->n_params) + " parameters");
+    SV_CHECK(g->n_params == 0 || params != nullptr, "gate parameters are NULL");
+    for (int i = 0; i < n_params; ++i) SV_CHECK(std::isfinite(params[i]), "gate parameter is not finite");
+    SV_CHECK(out != nullptr, "matrix output is NULL");
+    cd m[16];
+    named_matrix(name, params, m);
+    const int d = 1 << g->n_targets;
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+            const cd v = adj ? std::conj(m[c * d + r]) : m[r * d + c];
+            out[2 * (r * d + c)] = v.real();
+            out[2 * (r * d + c) + 1] = v.imag();
+        }
+    if (n_targets) *n_targets = g->n_targets;
+    if (n_controls) *n_controls = g->n_controls;
+}
+
+// ------------------------------------------------------------------ fusion
+
+namespace {
+
+struct HostGate {
+    std::vector<int> targets, controls, cvals;
+    std::vector<cd> m;
+    uint64_t qmask = 0;  // targets | controls
+};
+
+// U <- G * U where G acts on positions pos_t (matrix bit order) with
+// controls at positions pos_c having values cv; U is 2^m x 2^m row-major.
+// Each column of U is updated like a state of m qubits.
+void left_multiply(std::vector<cd>& U, int m, const HostGate& g, const std::vector<int>& pos_t,
+                   const std::vector<int>& pos_c)
+{
+    const int k = int(pos_t.size());
+    const int d = 1 << k;
+    const uint64_t dim = uint64_t(1) << m;
+    uint64_t tmask = 0, cmask = 0, cset = 0;
+    for (int p : pos_t) tmask |= uint64_t(1) << p;
+    for (size_t a = 0; a < pos_c.size(); ++a) {
+        cmask |= uint64_t(1) << pos_c[a];
+        if (g.cvals[a]) cset |= uint64_t(1) << pos_c[a];
+    }
+    std::vector<uint64_t> off(d);
+    for (int r = 0; r < d; ++r) {
+        uint64_t o = 0;
+        for (int a = 0; a < k; ++a)
+            if ((r >> a) & 1) o |= uint64_t(1) << pos_t[a];
+        off[r] = o;
+    }
+    std::vector<cd> v(d);
+    for (uint64_t col = 0; col < dim; ++col) {
+        for (uint64_t row = 0; row < dim; ++row) {
+            if ((row & tmask) || (row & cmask) != cset) continue;
+            for (int c = 0; c < d; ++c) v[c] = U[(row + off[c]) * dim + col];
+            for (int r = 0; r < d; ++r) {
+                cd acc = 0;
+                for (int c = 0; c < d; ++c) acc += g.m[r * d + c] * v[c];
+                U[(row + off[r]) * dim + col] = acc;
+            }
+        }
+    }
+}
+
+int popcount64(uint64_t v) { return __builtin_popcountll(v); }
+
+// Greedy block selection over the gate dependency order.
+//
+// While gates remain: for every "ready" gate (no unfused predecessor on any
+// of its qubits) grow a candidate block seeded by it: scan the remaining
+// gates in order and take a gate when none of its qubits is blocked and the
+// block's qubit set stays within kmax after adding the gate's qubits;
+// otherwise block the gate's qubits (every later gate on them must wait).
+// Taken gates never depend on a skipped gate, so the block can be emitted
+// before all remaining gates.  The candidate that absorbs the most gates
+// becomes the next block.
+std::vector<std::vector<int>> select_blocks(const std::vector<HostGate>& gates, int n_qubits_hint, int kmax)
+{
+    (void)n_qubits_hint;
+    const int G = int(gates.size());
+    std::vector<char> done(G, 0);
+    std::vector<std::vector<int>> blocks;
+    int remaining = G;
+    int first_live = 0;
+    std::vector<int> taken, best_taken;
+    while (remaining > 0) {
+        while (first_live < G && done[first_live]) ++first_live;
+        // ready gates: first remaining gate on each of their qubits
+        std::vector<int> ready;
+        uint64_t seen = 0;
+        for (int i = first_live; i < G; ++i) {
+            if (done[i]) continue;
+            if ((gates[i].qmask & seen) == 0) ready.push_back(i);
+            seen |= gates[i].qmask;
+        }
+        int best_score = -1;
+        for (int seed : ready) {
+            uint64_t S = gates[seed].qmask;
+            const int cap = std::max(kmax, popcount64(S));
+            uint64_t blocked = 0;
+            taken.clear();
+            for (int i = first_live; i < G; ++i) {
+                if (done[i]) continue;
+                const uint64_t Q = gates[i].qmask;
+                if (Q & blocked) {
+                    blocked |= Q;
+                } else if (popcount64(S | Q) <= cap) {
+                    S |= Q;
+                    taken.push_back(i);
+                } else {
+                    blocked |= Q;
+                }
+                // nothing more can join once every qubit of S is blocked and
+                // S cannot grow
+                if ((S & ~blocked) == 0 && popcount64(S) >= cap) break;
+            }
+            if (int(taken.size()) > best_score) {
+                best_score = int(taken.size());
+                best_taken = taken;
+            }
+        }
+        for (int i : best_taken) done[i] = 1;
+        remaining -= int(best_taken.size());
+        blocks.push_back(best_taken);
+    }
+    return blocks;
+}
+
+}  // namespace
+
+sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax)
+{
+    SV_CHECK(n_gates >= 0, "n_gates is negative");
+    SV_CHECK(n_gates == 0 || gates != nullptr, "gates is NULL");
+    SV_CHECK(kmax >= 1 && kmax <= SV_MAX_TARGETS, "max_fused_qubits must be in [1, 10]");
+    std::vector<HostGate> hg(n_gates);
+    for (int i = 0; i < n_gates; ++i) {
+        const sv_gate_t& g = gates[i];
+        SV_CHECK(g.n_targets >= 1 && g.n_targets <= SV_MAX_TARGETS, "gate " + std::to_string(i) + ": bad n_targets");
+        SV_CHECK(g.n_controls >= 0 && g.n_targets + g.n_controls <= SV_MAX_TARGETS,
+                 "gate " + std::to_string(i) + ": more than 10 qubits with controls");
+        SV_CHECK(g.targets && g.matrix, "gate " + std::to_string(i) + ": NULL targets or matrix");
+        SV_CHECK(g.n_controls == 0 || g.controls, "gate " + std::to_string(i) + ": NULL controls");
+        HostGate& h = hg[i];
+        for (int a = 0; a < g.n_targets; ++a) {
+            const int q = g.targets[a];
+            SV_CHECK(q >= 0 && q < 64 && !((h.qmask >> q) & 1), "gate " + std::to_string(i) + ": bad or repeated qubit");
+            h.qmask |= uint64_t(1) << q;
+            h.targets.push_back(q);
+        }
+        for (int a = 0; a < g.n_controls; ++a) {
+            const int q = g.controls[a];
+            SV_CHECK(q >= 0 && q < 64 && !((h.qmask >> q) & 1), "gate " + std::to_string(i) + ": bad or repeated qubit");
+            h.qmask |= uint64_t(1) << q;
+            h.controls.push_back(q);
+            const int cv = g.control_values ? g.control_values[a] : 1;
+            SV_CHECK(cv == 0 || cv == 1, "control values must be 0 or 1");
+            h.cvals.push_back(cv);
+        }
+        const int d = 1 << g.n_targets;
+        h.m.resize(size_t(d) * d);
+        for (int e = 0; e < d * d; ++e) {
+            h.m[e] = cd(g.matrix[2 * e], g.matrix[2 * e + 1]);
+            SV_CHECK(std::isfinite(g.matrix[2 * e]) && std::isfinite(g.matrix[2 * e + 1]),
+                     "gate " + std::to_string(i) + ": matrix entry is not finite");
+        }
+    }
+    const auto sel = select_blocks(hg, 64, kmax);
+    // build matrices
+    std::vector<std::vector<int>> qs(sel.size());
+    size_t total = 0;
+    for (size_t b = 0; b < sel.size(); ++b) {
+        uint64_t S = 0;
+        for (int i : sel[b]) S |= hg[i].qmask;
+        for (int q = 0; q < 64; ++q)
+            if ((S >> q) & 1) qs[b].push_back(q);
+        const size_t d = size_t(1) << qs[b].size();
+        total += d * d;
+    }
+    auto* f = new sv_fused_s;
+    f->n_blocks = int(sel.size());
+    f->blocks = new FusedBlock[sel.size()];
+    f->storage = new double[2 * std::max<size_t>(total, 1)];
+    size_t at = 0;
+    for (size_t b = 0; b < sel.size(); ++b) {
+        const int m = int(qs[b].size());
+        const uint64_t dim = uint64_t(1) << m;
+        std::vector<cd> U(dim * dim, cd(0.0));
+        for (uint64_t i = 0; i < dim; ++i) U[i * dim + i] = 1.0;
+        for (int gi : sel[b]) {
+            const HostGate& g = hg[gi];
+            auto pos = [&](int q) { return int(std::lower_bound(qs[b].begin(), qs[b].end(), q) - qs[b].begin()); };
+            std::vector<int> pt, pc;
+            for (int q : g.targets) pt.push_back(pos(q));
+            for (int q : g.controls) pc.push_back(pos(q));
+            left_multiply(U, m, g, pt, pc);
+        }
+        FusedBlock& blk = f->blocks[b];
+        blk.k = m;
+        for (int a = 0; a < m; ++a) blk.targets[a] = qs[b][a];
+        blk.m = f->storage + 2 * at;
+        for (uint64_t e = 0; e < dim * dim; ++e) {
+            blk.m[2 * e] = U[e].real();
+            blk.m[2 * e + 1] = U[e].imag();
+        }
+        at += dim * dim;
+    }
+    return f;
+}
+
+}  // namespace sv

@@ -1,0 +1,122 @@
+// Internal declarations shared by the host side of libsv and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "sv.h"
+
+namespace sv {
+
+// ------------------------------------------------------------------ errors
+
+void set_error(const std::string& msg);
+
+struct Error {
+    sv_status_t status;
+    std::string msg;
+};
+
+#define SV_HIP(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            throw ::sv::Error{e_ == hipErrorOutOfMemory ? SV_ERR_OUT_OF_MEMORY : SV_ERR_DEVICE, \
+                              std::string(#call) + ": " + hipGetErrorString(e_)};        \
+    } while (0)
+
+#define SV_CHECK(cond, msg)                                                              \
+    do {                                                                                 \
+        if (!(cond)) throw ::sv::Error{SV_ERR_INVALID_VALUE, (msg)};                     \
+    } while (0)
+
+// ------------------------------------------------------------- workspace
+
+// Layout of the handle's device workspace (bytes from its start).  The
+// matrix ring sits at the front; the rest is scratch for one blocking
+// reduction at a time (reductions never overlap on one handle).
+constexpr size_t kMatRingBytes = 4u << 20;     // gate matrices (device copy)
+constexpr int kMatRingSegments = 4;            // host staging reuse granularity
+constexpr size_t kDefaultWorkspace = 64u << 20;
+constexpr size_t kMinWorkspace = 12u << 20;
+
+}  // namespace sv
+
+struct sv_handle_s {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int cu_count = 256;
+    char* ws = nullptr;             // device workspace
+    size_t ws_bytes = 0;
+    char* pinned = nullptr;         // pinned host staging: matrix ring + result readback
+    size_t pinned_bytes = 0;
+    size_t ring_pos = 0;            // next free byte of the matrix ring
+    int ring_seg = 0;               // segment the ring is writing into
+    hipEvent_t seg_event[sv::kMatRingSegments] = {};
+    bool seg_event_live[sv::kMatRingSegments] = {};
+};
+
+struct sv_state_s {
+    sv_handle_s* h = nullptr;
+    int n = 0;
+    sv_dtype_t dt = SV_C64;
+    void* d = nullptr;
+    bool owned = false;
+};
+
+struct FusedBlock {
+    int k = 0;
+    int targets[SV_MAX_TARGETS] = {};
+    // 2^k x 2^k complex128, row-major, interleaved
+    double* m = nullptr;
+};
+
+struct sv_fused_s {
+    int n_blocks = 0;
+    FusedBlock* blocks = nullptr;
+    double* storage = nullptr;
+};
+
+namespace sv {
+
+// --------------------------------------------------- device-side launchers
+
+// Arguments of one dense gate sweep, prepared on the host.
+struct GateDesc {
+    int k = 0;                     // number of targets
+    int n_fixed = 0;               // targets + controls
+    int fixed_sorted[SV_MAX_QUBITS] = {};  // ascending positions of targets and controls
+    uint64_t cval = 0;             // control bits that must be set
+    uint64_t n_groups = 0;         // 2^(n - k - n_controls)
+    uint64_t tbit[SV_MAX_TARGETS] = {};    // 1 << targets[a], matrix bit order
+    int min_target = 0;
+};
+
+// psi: amplitudes; mat: device copy of the matrix in the state's precision
+// (complex, row-major); desc: the sweep.
+void launch_apply(sv_handle_s* h, sv_dtype_t dt, void* psi, const void* mat, const GateDesc& desc);
+
+void launch_set_basis(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, uint64_t x);
+void launch_scale(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, double factor);
+
+// Blocking reductions; results land in host memory.
+double run_norm(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n);
+
+struct PauliMasks {
+    uint64_t x = 0, z = 0;
+    int ny = 0;
+};
+void run_expect(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const PauliMasks* terms,
+                int n_terms, double* out);
+
+void run_sample(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const double* u,
+                int64_t n_shots, const int32_t* bit_ordering, int n_bits, uint64_t* out);
+
+// Copies `bytes` of host data into the matrix ring and returns the device
+// address (stream-ordered before any later launch on the handle).
+const void* stage_matrix(sv_handle_s* h, const void* host, size_t bytes);
+
+}  // namespace sv

@@ -1,0 +1,625 @@
+// Read-only sweeps over the state: norm, Pauli-string expectations and the
+// sampler (Table I: expectation, sampler; Sec. II: outcomes from the
+// numerically computed probability distribution, without collapse), plus the
+// two write sweeps set-basis and scale.
+//
+// Every reduction accumulates in FP64 in an order that depends only on n
+// (never on the grid size or on other work on the device): a fixed partition
+// into blocks, a fixed per-thread order inside a block, a fixed LDS tree, and
+// a fixed final pass.  Results are therefore bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "sv_internal.h"
+
+namespace sv {
+namespace {
+
+template <typename R>
+struct Cx;
+template <>
+struct Cx<float> {
+    using T = float2;
+};
+template <>
+struct Cx<double> {
+    using T = double2;
+};
+
+constexpr int kThreads = 256;
+
+// |a|^2 in FP64 with a fixed rounding sequence (no contraction freedom):
+// complex64 components square exactly in FP64.
+template <typename T2>
+__device__ __forceinline__ double prob(const T2 a)
+{
+    const double re = double(a.x), im = double(a.y);
+    return fma(re, re, __dmul_rn(im, im));
+}
+
+// Fixed-shape LDS tree over kThreads values; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* lds)
+{
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (int(threadIdx.x) < s) lds[threadIdx.x] = __dadd_rn(lds[threadIdx.x], lds[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const double r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+// ------------------------------------------------------------ write sweeps
+
+template <typename T2>
+__global__ __launch_bounds__(kThreads) void k_set_basis(T2* __restrict__ psi, uint64_t dim, uint64_t x)
+{
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < dim; i += stride) {
+        T2 v;
+        v.x = (i == x) ? 1 : 0;
+        v.y = 0;
+        psi[i] = v;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_scale(typename Cx<R>::T* __restrict__ psi, uint64_t dim,
+                                                   R f)
+{
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < dim; i += stride) {
+        auto v = psi[i];
+        v.x *= f;
+        v.y *= f;
+        psi[i] = v;
+    }
+}
+
+unsigned grid_for(sv_handle_s* h, uint64_t items)
+{
+    uint64_t b = (items + kThreads - 1) / kThreads;
+    const uint64_t cap = uint64_t(h->cu_count) * 16;
+    return unsigned(std::max<uint64_t>(1, std::min(b, cap)));
+}
+
+// ------------------------------------------------------------ norm / expect
+
+// Partition of `items` work items into `nb` blocks of `per` items (powers of
+// two), a function of the item count only.
+struct Partition {
+    uint64_t nb, per;
+};
+
+Partition partition(uint64_t items)
+{
+    uint64_t nb = items / 2048;
+    if (nb < 1) nb = 1;
+    if (nb > 8192) nb = 8192;
+    return {nb, items / nb};
+}
+
+constexpr int kMaxTermsPerSweep = 16;
+
+struct ExpectArgs {
+    uint64_t per;        // items per block
+    uint64_t x;          // common X/Y mask of the terms
+    int32_t hbit;        // highest bit of x (pair sweeps)
+    int32_t n_terms;
+    uint64_t z[kMaxTermsPerSweep];
+    int32_t ny[kMaxTermsPerSweep];
+};
+
+// Per block: FP64 partials of every term and of the norm, written to
+// part[t * nb + block] (t = n_terms is the norm).
+//
+// x == 0: item i contributes |psi_i|^2 * (-1)^popcount(i & z).
+// x != 0: item q is the pair (i, j = i ^ x) with bit hbit of i clear; with
+//         w = conj(psi_j) psi_i the pair contributes
+//         2 Re(w * i^ny) * (-1)^popcount(i & z), because P|i> = ph(i)|j> and
+//         ph(j) = conj(ph(i)) for a Hermitian Pauli string.
+template <typename R, bool kPairs>
+__global__ __launch_bounds__(kThreads) void k_expect(const typename Cx<R>::T* __restrict__ psi,
+                                                    ExpectArgs a, double* __restrict__ part)
+{
+    __shared__ double lds[kThreads];
+    double acc[kMaxTermsPerSweep + 1];
+#pragma unroll
+    for (int t = 0; t <= kMaxTermsPerSweep; ++t) acc[t] = 0.0;
+    const uint64_t first = uint64_t(blockIdx.x) * a.per;
+    for (uint64_t it = threadIdx.x; it < a.per; it += kThreads) {
+        const uint64_t q = first + it;
+        if (!kPairs) {
+            const double p = prob(psi[q]);
+            acc[kMaxTermsPerSweep] = __dadd_rn(acc[kMaxTermsPerSweep], p);
+#pragma unroll
+            for (int t = 0; t < kMaxTermsPerSweep; ++t) {
+                if (t < a.n_terms) {
+                    const double s = (__popcll(q & a.z[t]) & 1) ? -p : p;
+                    acc[t] = __dadd_rn(acc[t], s);
+                }
+            }
+        } else {
+            const uint64_t lo = q & ((uint64_t(1) << a.hbit) - 1);
+            const uint64_t i = ((q >> a.hbit) << (a.hbit + 1)) | lo;
+            const uint64_t j = i ^ a.x;
+            const auto ai = psi[i];
+            const auto aj = psi[j];
+            const double ir = double(ai.x), ii = double(ai.y), jr = double(aj.x), ji = double(aj.y);
+            // w = conj(a_j) * a_i
+            const double wr = fma(jr, ir, __dmul_rn(ji, ii));
+            const double wi = fma(jr, ii, -__dmul_rn(ji, ir));
+            acc[kMaxTermsPerSweep] = __dadd_rn(acc[kMaxTermsPerSweep], __dadd_rn(prob(ai), prob(aj)));
+#pragma unroll
+            for (int t = 0; t < kMaxTermsPerSweep; ++t) {
+                if (t < a.n_terms) {
+                    const int m = a.ny[t] & 3;
+                    double v = (m == 0) ? wr : (m == 1) ? -wi : (m == 2) ? -wr : wi;
+                    v = 2.0 * v;
+                    if (__popcll(i & a.z[t]) & 1) v = -v;
+                    acc[t] = __dadd_rn(acc[t], v);
+                }
+            }
+        }
+    }
+    for (int t = 0; t <= kMaxTermsPerSweep; ++t) {
+        if (t < a.n_terms || t == kMaxTermsPerSweep) {
+            const double s = block_sum(acc[t], lds);
+            const int slot = (t == kMaxTermsPerSweep) ? a.n_terms : t;
+            if (threadIdx.x == 0) part[uint64_t(slot) * gridDim.x + blockIdx.x] = s;
+        }
+    }
+}
+
+// out[t] = sum over blocks of part[t * nb + b], fixed order.  One block per t.
+__global__ __launch_bounds__(kThreads) void k_finish_sums(const double* __restrict__ part, uint64_t nb,
+                                                         double* __restrict__ out)
+{
+    __shared__ double lds[kThreads];
+    const double* p = part + uint64_t(blockIdx.x) * nb;
+    double acc = 0.0;
+    for (uint64_t b = threadIdx.x; b < nb; b += kThreads) acc = __dadd_rn(acc, p[b]);
+    const double s = block_sum(acc, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// ----------------------------------------------------------------- sampler
+//
+// Two-level inverse CDF with a boundary structure that is monotone bit for
+// bit, so the search is always consistent and never lands on a
+// zero-probability index:
+//   chunk sums S[c] (any fixed order);
+//   chunk boundaries B[0..nc] from S by per-thread sequential prefixes plus
+//     a sequential pass over thread totals (monotone, and B[c+1] == B[c]
+//     whenever S[c] == 0);
+//   for a shot, r = u * B[nc]; chunk = smallest c with r < B[c+1];
+//   inside the chunk, segment boundaries sb[] and amplitude boundaries are
+//     built the same way, and the outcome is the smallest i with
+//     r < B[c] + (sb[s] + running sum of p up to i).
+
+struct SampleLayout {
+    uint64_t nc;     // chunks
+    uint64_t cs;     // amplitudes per chunk
+};
+
+SampleLayout sample_layout(int n)
+{
+    const uint64_t dim = uint64_t(1) << n;
+    uint64_t nc = dim / 4096;
+    if (nc < 1) nc = 1;
+    if (nc > 65536) nc = 65536;
+    return {nc, dim / nc};
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_chunk_sums(const typename Cx<R>::T* __restrict__ psi,
+                                                        uint64_t nc, uint64_t cs, double* __restrict__ S)
+{
+    __shared__ double lds[kThreads];
+    for (uint64_t c = blockIdx.x; c < nc; c += gridDim.x) {
+        double acc = 0.0;
+        for (uint64_t i = threadIdx.x; i < cs; i += kThreads) acc = __dadd_rn(acc, prob(psi[c * cs + i]));
+        const double s = block_sum(acc, lds);
+        if (threadIdx.x == 0) S[c] = s;
+    }
+}
+
+constexpr int kScanThreads = 1024;
+
+// B[0..nc] from S[0..nc-1] (single block).
+__global__ __launch_bounds__(kScanThreads) void k_scan_chunks(const double* __restrict__ S, uint64_t nc,
+                                                             double* __restrict__ B)
+{
+    __shared__ double tot[kScanThreads];
+    __shared__ double off[kScanThreads];
+    const uint64_t per = (nc + kScanThreads - 1) / kScanThreads;
+    const uint64_t lo = std::min<uint64_t>(nc, threadIdx.x * per);
+    const uint64_t hi = std::min<uint64_t>(nc, lo + per);
+    double run = 0.0;
+    for (uint64_t c = lo; c < hi; ++c) {
+        run = __dadd_rn(run, S[c]);
+        B[c + 1] = run;  // local inclusive prefix for now
+    }
+    tot[threadIdx.x] = run;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double o = 0.0;
+        for (int t = 0; t < kScanThreads; ++t) {
+            off[t] = o;
+            o = __dadd_rn(o, tot[t]);
+        }
+    }
+    __syncthreads();
+    const double o = off[threadIdx.x];
+    for (uint64_t c = lo; c < hi; ++c) B[c + 1] = __dadd_rn(o, B[c + 1]);
+    if (threadIdx.x == 0) B[0] = 0.0;
+}
+
+__device__ __forceinline__ double shot_r(double u, double total)
+{
+    double r = __dmul_rn(u, total);
+    if (!(r < total)) r = nextafter(total, 0.0);
+    return r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_locate(const double* __restrict__ u, uint64_t ns,
+                                                    const double* __restrict__ B, uint64_t nc,
+                                                    uint32_t* __restrict__ chunk_of,
+                                                    uint32_t* __restrict__ counts)
+{
+    const uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    const double r = shot_r(u[s], B[nc]);
+    uint64_t lo = 0, hi = nc - 1;  // smallest c with r < B[c+1]
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (r < B[mid + 1])
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    chunk_of[s] = uint32_t(lo);
+    atomicAdd(&counts[lo], 1u);
+}
+
+// Exclusive scan of integer counts (exact in any order); single block.
+__global__ __launch_bounds__(kScanThreads) void k_scan_counts(const uint32_t* __restrict__ counts,
+                                                             uint64_t nc, uint32_t* __restrict__ start,
+                                                             uint32_t* __restrict__ cursor)
+{
+    __shared__ uint32_t tot[kScanThreads];
+    const uint64_t per = (nc + kScanThreads - 1) / kScanThreads;
+    const uint64_t lo = std::min<uint64_t>(nc, threadIdx.x * per);
+    const uint64_t hi = std::min<uint64_t>(nc, lo + per);
+    uint32_t run = 0;
+    for (uint64_t c = lo; c < hi; ++c) run += counts[c];
+    tot[threadIdx.x] = run;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t o = 0;
+        for (int t = 0; t < kScanThreads; ++t) {
+            const uint32_t v = tot[t];
+            tot[t] = o;
+            o += v;
+        }
+    }
+    __syncthreads();
+    uint32_t o = tot[threadIdx.x];
+    for (uint64_t c = lo; c < hi; ++c) {
+        start[c] = o;
+        cursor[c] = 0;
+        o += counts[c];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_bucket(const uint32_t* __restrict__ chunk_of, uint64_t ns,
+                                                    const uint32_t* __restrict__ start,
+                                                    uint32_t* __restrict__ cursor, uint32_t* __restrict__ list)
+{
+    const uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    const uint32_t c = chunk_of[s];
+    const uint32_t pos = atomicAdd(&cursor[c], 1u);
+    list[start[c] + pos] = uint32_t(s);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_resolve(const typename Cx<R>::T* __restrict__ psi,
+                                                     SampleLayout L, const double* __restrict__ B,
+                                                     const uint32_t* __restrict__ counts,
+                                                     const uint32_t* __restrict__ start,
+                                                     const uint32_t* __restrict__ list,
+                                                     const double* __restrict__ u,
+                                                     uint64_t* __restrict__ idx_out)
+{
+    __shared__ double sb[kThreads + 1];
+    const uint64_t nseg = std::min<uint64_t>(kThreads, L.cs);
+    const uint64_t seg = L.cs / nseg;
+    const double total = B[L.nc];
+    for (uint64_t c = blockIdx.x; c < L.nc; c += gridDim.x) {
+        const uint32_t cnt = counts[c];
+        if (cnt == 0) continue;
+        const uint64_t c0 = c * L.cs;
+        double run = 0.0;
+        if (threadIdx.x < nseg) {
+            const uint64_t s0 = c0 + threadIdx.x * seg;
+            for (uint64_t i = 0; i < seg; ++i) run = __dadd_rn(run, prob(psi[s0 + i]));
+            sb[threadIdx.x + 1] = run;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double o = 0.0;
+            sb[0] = 0.0;
+            for (uint64_t s = 0; s < nseg; ++s) {
+                o = __dadd_rn(o, sb[s + 1]);
+                sb[s + 1] = o;
+            }
+        }
+        __syncthreads();
+        const double bc = B[c];
+        for (uint32_t j = threadIdx.x; j < cnt; j += kThreads) {
+            const uint32_t shot = list[start[c] + j];
+            const double r = shot_r(u[shot], total);
+            // smallest segment s with r < bc + sb[s+1]
+            uint64_t lo = 0, hi = nseg;  // hi == nseg: not found
+            while (lo < hi) {
+                const uint64_t mid = lo + (hi - lo) / 2;
+                if (r < __dadd_rn(bc, sb[mid + 1]))
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            uint64_t found = ~uint64_t(0);
+            if (lo < nseg) {
+                const uint64_t s0 = c0 + lo * seg;
+                const double base = sb[lo];
+                double acc = 0.0;
+                for (uint64_t i = 0; i < seg; ++i) {
+                    acc = __dadd_rn(acc, prob(psi[s0 + i]));
+                    if (r < __dadd_rn(bc, __dadd_rn(base, acc))) {
+                        found = s0 + i;
+                        break;
+                    }
+                }
+            }
+            if (found == ~uint64_t(0)) {
+                // rounding left r past the chunk's own total: take the last
+                // amplitude of the chunk with non-zero probability
+                for (uint64_t i = L.cs; i-- > 0;) {
+                    if (prob(psi[c0 + i]) > 0.0) {
+                        found = c0 + i;
+                        break;
+                    }
+                }
+            }
+            idx_out[shot] = found;
+        }
+        __syncthreads();
+    }
+}
+
+struct BitArgs {
+    int32_t n_bits;
+    int32_t bits[SV_MAX_QUBITS];
+};
+
+__global__ __launch_bounds__(kThreads) void k_extract_bits(uint64_t* __restrict__ idx, uint64_t ns, BitArgs a)
+{
+    const uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    const uint64_t v = idx[s];
+    uint64_t o = 0;
+    for (int b = 0; b < a.n_bits; ++b) o |= ((v >> a.bits[b]) & 1u) << b;
+    idx[s] = o;
+}
+
+template <typename R>
+double run_norm_t(sv_handle_s* h, const void* psi_v, int n)
+{
+    using T2 = typename Cx<R>::T;
+    const T2* psi = static_cast<const T2*>(psi_v);
+    const uint64_t dim = uint64_t(1) << n;
+    const Partition P = partition(dim);
+    double* part = reinterpret_cast<double*>(h->ws + kMatRingBytes);
+    double* res = part + P.nb;
+    ExpectArgs a{};
+    a.per = P.per;
+    a.n_terms = 0;
+    hipLaunchKernelGGL((k_expect<R, false>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a, part);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_finish_sums, dim3(1), dim3(kThreads), 0, h->stream, part, P.nb, res);
+    SV_HIP(hipGetLastError());
+    double out = 0.0;
+    SV_HIP(hipMemcpyAsync(&out, res, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    SV_HIP(hipStreamSynchronize(h->stream));
+    return out;
+}
+
+int highest_bit(uint64_t v)
+{
+    int b = -1;
+    while (v) {
+        v >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+template <typename R>
+void run_expect_t(sv_handle_s* h, const void* psi_v, int n, const PauliMasks* terms, int n_terms, double* out)
+{
+    using T2 = typename Cx<R>::T;
+    const T2* psi = static_cast<const T2*>(psi_v);
+    const uint64_t dim = uint64_t(1) << n;
+    // group terms by their X/Y mask: one sweep per distinct mask and per
+    // kMaxTermsPerSweep terms
+    std::vector<int> order(n_terms);
+    for (int t = 0; t < n_terms; ++t) order[t] = t;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return terms[a].x < terms[b].x; });
+    double* part = reinterpret_cast<double*>(h->ws + kMatRingBytes);
+    std::vector<double> sums(n_terms, 0.0);
+    double norm = -1.0;
+    std::vector<std::pair<int, int>> launches;  // (first index into order, count)
+    for (int i = 0; i < n_terms;) {
+        int j = i;
+        while (j < n_terms && terms[order[j]].x == terms[order[i]].x && j - i < kMaxTermsPerSweep) ++j;
+        launches.push_back({i, j - i});
+        i = j;
+    }
+    double* res_dev = part;  // reused per launch after the partials are consumed
+    for (auto& L : launches) {
+        const uint64_t x = terms[order[L.first]].x;
+        const bool pairs = x != 0;
+        const uint64_t items = pairs ? dim / 2 : dim;
+        const Partition P = partition(items);
+        double* p = part + 64;  // first 64 doubles hold the finished sums
+        ExpectArgs a{};
+        a.per = P.per;
+        a.x = x;
+        a.hbit = pairs ? highest_bit(x) : 0;
+        a.n_terms = L.second;
+        for (int t = 0; t < L.second; ++t) {
+            a.z[t] = terms[order[L.first + t]].z;
+            a.ny[t] = terms[order[L.first + t]].ny;
+        }
+        if (pairs)
+            hipLaunchKernelGGL((k_expect<R, true>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a, p);
+        else
+            hipLaunchKernelGGL((k_expect<R, false>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a, p);
+        SV_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_finish_sums, dim3(unsigned(L.second + 1)), dim3(kThreads), 0, h->stream, p, P.nb,
+                           res_dev);
+        SV_HIP(hipGetLastError());
+        double host[kMaxTermsPerSweep + 1];
+        SV_HIP(hipMemcpyAsync(host, res_dev, sizeof(double) * (L.second + 1), hipMemcpyDeviceToHost, h->stream));
+        SV_HIP(hipStreamSynchronize(h->stream));
+        for (int t = 0; t < L.second; ++t) sums[order[L.first + t]] = host[t];
+        if (norm < 0.0) norm = host[L.second];
+    }
+    if (!(norm > 0.0)) throw Error{SV_ERR_INVALID_VALUE, "state has zero norm"};
+    for (int t = 0; t < n_terms; ++t) out[t] = sums[t] / norm;
+}
+
+template <typename R>
+void run_sample_t(sv_handle_s* h, const void* psi_v, int n, const double* u, int64_t n_shots,
+                  const int32_t* bit_ordering, int n_bits, uint64_t* out)
+{
+    using T2 = typename Cx<R>::T;
+    const T2* psi = static_cast<const T2*>(psi_v);
+    const SampleLayout L = sample_layout(n);
+    char* w = h->ws + kMatRingBytes;
+    auto take = [&](size_t bytes) {
+        char* p = w;
+        w += (bytes + 255) & ~size_t(255);
+        return p;
+    };
+    double* S = reinterpret_cast<double*>(take(sizeof(double) * L.nc));
+    double* B = reinterpret_cast<double*>(take(sizeof(double) * (L.nc + 1)));
+    uint32_t* counts = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * L.nc));
+    uint32_t* start = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * L.nc));
+    uint32_t* cursor = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * L.nc));
+    const size_t used = size_t(w - h->ws);
+    if (used >= h->ws_bytes) throw Error{SV_ERR_OUT_OF_MEMORY, "workspace too small for the sampler"};
+    const size_t per_shot = sizeof(double) + 2 * sizeof(uint32_t) + sizeof(uint64_t);
+    int64_t batch = int64_t((h->ws_bytes - used) / per_shot) - 1024;
+    if (batch > (int64_t(1) << 22)) batch = int64_t(1) << 22;
+    if (batch < 1) throw Error{SV_ERR_OUT_OF_MEMORY, "workspace too small for the sampler"};
+    double* du = reinterpret_cast<double*>(take(sizeof(double) * batch));
+    uint32_t* chunk_of = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * batch));
+    uint32_t* list = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * batch));
+    uint64_t* didx = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * batch));
+    if (size_t(w - h->ws) > h->ws_bytes) throw Error{SV_ERR_INTERNAL, "sampler workspace layout"};
+
+    hipLaunchKernelGGL((k_chunk_sums<R>), dim3(unsigned(std::min<uint64_t>(L.nc, uint64_t(h->cu_count) * 16))),
+                       dim3(kThreads), 0, h->stream, psi, L.nc, L.cs, S);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(kScanThreads), 0, h->stream, S, L.nc, B);
+    SV_HIP(hipGetLastError());
+    double total = 0.0;
+    SV_HIP(hipMemcpyAsync(&total, B + L.nc, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    SV_HIP(hipStreamSynchronize(h->stream));
+    if (!(total > 0.0)) throw Error{SV_ERR_INVALID_VALUE, "state has zero norm"};
+
+    BitArgs ba{};
+    ba.n_bits = n_bits;
+    for (int b = 0; b < n_bits; ++b) ba.bits[b] = bit_ordering[b];
+    for (int64_t s0 = 0; s0 < n_shots; s0 += batch) {
+        const uint64_t ns = uint64_t(std::min<int64_t>(batch, n_shots - s0));
+        SV_HIP(hipMemcpyAsync(du, u + s0, sizeof(double) * ns, hipMemcpyHostToDevice, h->stream));
+        SV_HIP(hipMemsetAsync(counts, 0, sizeof(uint32_t) * L.nc, h->stream));
+        const unsigned sg = unsigned((ns + kThreads - 1) / kThreads);
+        hipLaunchKernelGGL(k_locate, dim3(sg), dim3(kThreads), 0, h->stream, du, ns, B, L.nc, chunk_of, counts);
+        SV_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(kScanThreads), 0, h->stream, counts, L.nc, start, cursor);
+        SV_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_bucket, dim3(sg), dim3(kThreads), 0, h->stream, chunk_of, ns, start, cursor, list);
+        SV_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_resolve<R>), dim3(unsigned(std::min<uint64_t>(L.nc, uint64_t(h->cu_count) * 16))),
+                           dim3(kThreads), 0, h->stream, psi, L, B, counts, start, list, du, didx);
+        SV_HIP(hipGetLastError());
+        if (n_bits > 0) {
+            hipLaunchKernelGGL(k_extract_bits, dim3(sg), dim3(kThreads), 0, h->stream, didx, ns, ba);
+            SV_HIP(hipGetLastError());
+        }
+        SV_HIP(hipMemcpyAsync(out + s0, didx, sizeof(uint64_t) * ns, hipMemcpyDeviceToHost, h->stream));
+        SV_HIP(hipStreamSynchronize(h->stream));
+    }
+}
+
+}  // namespace
+
+void launch_set_basis(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, uint64_t x)
+{
+    const uint64_t dim = uint64_t(1) << n;
+    if (dt == SV_C64)
+        hipLaunchKernelGGL(k_set_basis<float2>, dim3(grid_for(h, dim)), dim3(kThreads), 0, h->stream,
+                           static_cast<float2*>(psi), dim, x);
+    else
+        hipLaunchKernelGGL(k_set_basis<double2>, dim3(grid_for(h, dim)), dim3(kThreads), 0, h->stream,
+                           static_cast<double2*>(psi), dim, x);
+    SV_HIP(hipGetLastError());
+}
+
+void launch_scale(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, double f)
+{
+    const uint64_t dim = uint64_t(1) << n;
+    if (dt == SV_C64)
+        hipLaunchKernelGGL(k_scale<float>, dim3(grid_for(h, dim)), dim3(kThreads), 0, h->stream,
+                           static_cast<float2*>(psi), dim, float(f));
+    else
+        hipLaunchKernelGGL(k_scale<double>, dim3(grid_for(h, dim)), dim3(kThreads), 0, h->stream,
+                           static_cast<double2*>(psi), dim, f);
+    SV_HIP(hipGetLastError());
+}
+
+double run_norm(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n)
+{
+    return dt == SV_C64 ? run_norm_t<float>(h, psi, n) : run_norm_t<double>(h, psi, n);
+}
+
+void run_expect(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const PauliMasks* terms, int n_terms,
+                double* out)
+{
+    if (dt == SV_C64)
+        run_expect_t<float>(h, psi, n, terms, n_terms, out);
+    else
+        run_expect_t<double>(h, psi, n, terms, n_terms, out);
+}
+
+void run_sample(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const double* u, int64_t n_shots,
+                const int32_t* bit_ordering, int n_bits, uint64_t* out)
+{
+    if (dt == SV_C64)
+        run_sample_t<float>(h, psi, n, u, n_shots, bit_ordering, n_bits, out);
+    else
+        run_sample_t<double>(h, psi, n, u, n_shots, bit_ordering, n_bits, out);
+}
+
+}  // namespace sv

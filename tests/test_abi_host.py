@@ -1,0 +1,162 @@
+"""CPU checks of libsv: the shared library loads and exports every entry
+point that include/sv.h declares, and its host logic (the gate table and gate
+fusion) is right.  No compute call touches a GPU here."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+import oracle
+import workloads as W
+from tests.kron_ref import PAULI
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2308_01999_amd as P
+    return P
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sv_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(P):
+    import ctypes
+    lib = ctypes.CDLL(P.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    # the binding wraps exactly the declared entry points
+    assert sorted(P.EXPORTED) == names
+
+
+def test_version_string(P):
+    assert "gfx950" in P.sv_version()
+
+
+def _u3_ref(th, ph, la):
+    rz = lambda a: expm(-0.5j * a * PAULI["Z"])
+    ry = lambda a: expm(-0.5j * a * PAULI["Y"])
+    return np.exp(0.5j * (ph + la)) * rz(ph) @ ry(th) @ rz(la)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_gate_table_u3(P, seed):
+    th, ph, la = np.random.default_rng(seed).uniform(0, 2 * math.pi, 3)
+    m, nt, nc = P.sv_gate_matrix("u3", (th, ph, la))
+    assert (nt, nc) == (1, 0)
+    np.testing.assert_allclose(m, _u3_ref(th, ph, la), atol=1e-14)
+    md, _, _ = P.sv_gate_matrix("u3_dg", (th, ph, la))
+    np.testing.assert_allclose(md @ m, np.eye(2), atol=1e-14)
+
+
+def test_gate_table_named(P):
+    for name, ref, nt, nc in [("h", (PAULI["X"] + PAULI["Z"]) / math.sqrt(2), 1, 0), ("x", PAULI["X"], 1, 0),
+                              ("y", PAULI["Y"], 1, 0), ("z", PAULI["Z"], 1, 0), ("cx", PAULI["X"], 1, 1),
+                              ("cz", PAULI["Z"], 1, 1), ("swap", np.eye(4)[[0, 2, 1, 3]], 2, 0)]:
+        m, a, b = P.sv_gate_matrix(name)
+        assert (a, b) == (nt, nc), name
+        np.testing.assert_allclose(m, ref, atol=1e-15, err_msg=name)
+    m, nt, nc = P.sv_gate_matrix("cp", (0.7,))
+    np.testing.assert_allclose(m, np.diag([1, np.exp(0.7j)]), atol=1e-15)
+    m, _, _ = P.sv_gate_matrix("cp_dg", (0.7,))
+    np.testing.assert_allclose(m, np.diag([1, np.exp(-0.7j)]), atol=1e-15)
+
+
+def test_gate_table_rejects_bad_input(P):
+    for args in [("nope", ()), ("u3", (1.0,)), ("cp", ()), ("u3", (float("nan"), 0, 0))]:
+        with pytest.raises(P.SVError) as e:
+            P.sv_gate_matrix(*args)
+        assert e.value.status == P.SV_ERR_INVALID_VALUE
+
+
+def _apply_blocks_with_oracle(n, blocks, basis=0):
+    psi = oracle.basis_state(n, basis)
+    for targets, m in blocks:
+        oracle.apply(psi, m, targets)
+    return psi
+
+
+@pytest.mark.parametrize("kmax", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("circuit", ["brickwork", "cxcp", "qft", "dense"])
+def test_fusion_equals_unfused(P, kmax, circuit):
+    n = 8
+    if circuit == "brickwork":
+        gates = W.brickwork(n, 6, kmax)
+    elif circuit == "cxcp":
+        gates = W.random_cx_cp(n, 5, kmax)
+    elif circuit == "qft":
+        gates = W.qft(n)
+    else:
+        gates = [W.Gate("mat", t, m) for t, c, cv, m in W.random_dense_circuit(n, 12, 3, kmax, with_controls=False)]
+    x = W.random_basis_state(n, kmax)
+    ref = oracle.run(n, gates, basis=x)
+    f = P.fuse(gates, kmax)
+    blocks = f.blocks()
+    f.free()
+    for targets, m in blocks:
+        assert list(targets) == sorted(targets)
+        assert len(targets) <= max(kmax, 3 if circuit == "dense" else 2)
+        np.testing.assert_allclose(m @ m.conj().T, np.eye(m.shape[0]), atol=1e-13)
+    got = _apply_blocks_with_oracle(n, blocks, basis=x)
+    np.testing.assert_allclose(got, ref, atol=1e-12)
+
+
+def test_fusion_with_controls_and_values(P):
+    n = 7
+    ops = W.random_dense_circuit(n, 30, 2, 77)
+    ref = oracle.basis_state(n, 3)
+    for t, c, cv, m in ops:
+        oracle.apply(ref, m, t, c, cv)
+    entries = [(t, m, c, cv if c else None) for t, c, cv, m in ops]
+    f = P.sv_fuse_gates(entries, 5)
+    blocks = [P.sv_fused_block(f, i) for i in range(P.sv_fused_count(f))]
+    P.sv_fused_free(f)
+    got = _apply_blocks_with_oracle(n, blocks, basis=3)
+    np.testing.assert_allclose(got, ref, atol=1e-12)
+
+
+def test_fusion_reduces_sweeps_on_brickwork(P):
+    # the block count is reported, not pinned; it must beat one sweep per
+    # two-qubit brick by a wide margin
+    gates = W.brickwork(30, 20, 0)
+    counts = {k: P.fuse(gates, k).count for k in (4, 5, 6)}
+    assert counts[5] < 100 and counts[6] <= counts[5] <= counts[4]
+
+
+def test_fusion_rejects_bad_input(P):
+    with pytest.raises(P.SVError):
+        P.sv_fuse_gates([((0,), np.eye(2), (), None)], 0)
+    with pytest.raises(P.SVError):
+        P.sv_fuse_gates([((0, 0), np.eye(4), (), None)], 5)
+    with pytest.raises(P.SVError):
+        P.sv_fuse_gates([((0,), np.eye(2), (0,), None)], 5)
+    with pytest.raises(P.SVError):
+        P.sv_fuse_gates([((0,), np.full((2, 2), np.inf), (), None)], 5)
+    with pytest.raises(P.SVError):
+        P.sv_fuse_gates([((1,), np.eye(2), (0,), (2,))], 5)
+    assert P.sv_last_error()
+
+
+def test_empty_fusion(P):
+    f = P.sv_fuse_gates([], 5)
+    assert P.sv_fused_count(f) == 0
+    P.sv_fused_free(f)
+
+
+def test_handle_create_without_gpu_reports_device_error(P):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(P.SVError) as e:
+        P.sv_handle_create(0, 0)
+    assert e.value.status == P.SV_ERR_DEVICE
