@@ -42,8 +42,23 @@ def parse():
     ap.add_argument("--shots", type=int, default=1 << 20)
     ap.add_argument("--no-c128", action="store_true", help="skip the complex128 leg")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing leg")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target length of the oracle sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run plain device copies of known size (for HBM counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy(torch):
+    """Plain device-to-device copies of a known size: a reference for the
+    HBM byte counters of a profiler (2 GiB read + 2 GiB written per copy)."""
+    a = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    del a, b
+    return {"copy_bytes_read": 1 << 31, "copy_bytes_written": 1 << 31, "launches": 3,
+            "kernel": "torch elementwise mul(a, 1.0) on 2^29 float32"}
 
 
 def run_leg(P, W, torch, H, gates, n, dt, kmax, shots, steps, warmup):
@@ -72,6 +87,7 @@ def run_leg(P, W, torch, H, gates, n, dt, kmax, shots, steps, warmup):
             evs[i].record(stream)
             P.sv_apply_fused_range(st.s, f.f, i, 1)
         evs[nb].record(stream)
+        evs[nb].synchronize()
         t2 = time.perf_counter()
         z = P.sv_expect_pauli(st.s, zterms)
         t3 = time.perf_counter()
@@ -227,6 +243,8 @@ def main():
         "c64": r64,
         **extra,
     }
+    if args.calibrate_copy:
+        line["copy_calibration"] = calibrate_copy(torch)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(W, P, gates, n, kmax, args.cpu_seconds)

@@ -62,7 +62,9 @@ GateDesc make_desc(int n, const int32_t* targets, int k, const int32_t* controls
     SV_CHECK(n_controls == 0 || controls != nullptr, "controls is NULL");
     SV_CHECK(k + n_controls <= n, "targets plus controls exceed the qubit count");
     GateDesc d;
+    d.n = n;
     d.k = k;
+    d.n_controls = n_controls;
     uint64_t used = 0;
     int minq = n;
     for (int a = 0; a < k; ++a) {
@@ -88,28 +90,6 @@ GateDesc make_desc(int n, const int32_t* targets, int k, const int32_t* controls
         if ((used >> q) & 1) d.fixed_sorted[d.n_fixed++] = q;
     d.n_groups = uint64_t(1) << (n - k - n_controls);
     return d;
-}
-
-// Converts a complex128 matrix (optionally its adjoint) into the state's
-// precision in `dst` (host).
-void convert_matrix(const double* m, int k, int adjoint, sv_dtype_t dt, void* dst)
-{
-    const int d = 1 << k;
-    for (int r = 0; r < d; ++r)
-        for (int c = 0; c < d; ++c) {
-            const int src = adjoint ? (c * d + r) : (r * d + c);
-            double re = m[2 * src], im = m[2 * src + 1];
-            if (adjoint) im = -im;
-            if (dt == SV_C64) {
-                float* o = static_cast<float*>(dst);
-                o[2 * (r * d + c)] = float(re);
-                o[2 * (r * d + c) + 1] = float(im);
-            } else {
-                double* o = static_cast<double*>(dst);
-                o[2 * (r * d + c)] = re;
-                o[2 * (r * d + c) + 1] = im;
-            }
-        }
 }
 
 void check_matrix_finite(const double* m, int k)
@@ -310,9 +290,9 @@ sv_status_t sv_apply_matrix(sv_state_t s, const double* matrix, const int32_t* t
         check_state(s);
         const GateDesc d = make_desc(s->n, targets, k, controls, control_values, n_controls);
         check_matrix_finite(matrix, k);
-        const size_t bytes = (amp_bytes(s->dt)) << (2 * k);
+        const size_t bytes = packed_matrix_bytes(s->dt, s->n, k, n_controls);
         std::vector<char> tmp(bytes);
-        convert_matrix(matrix, k, adjoint, s->dt, tmp.data());
+        pack_matrix(s->dt, s->n, k, n_controls, matrix, adjoint, tmp.data());
         const void* dm = stage_matrix(s->h, tmp.data(), bytes);
         launch_apply(s->h, s->dt, s->d, dm, d);
     });
@@ -386,7 +366,6 @@ void apply_fused_blocks(sv_state_s* s, sv_fused_s* f, int first, int count)
         descs[b] = make_desc(s->n, blk.targets, blk.k, nullptr, nullptr, 0);
     }
     {
-        const size_t ab = amp_bytes(s->dt);
         // stage in segment-sized batches: one copy per batch of blocks
         const size_t seg = kMatRingBytes / kMatRingSegments;
         int b = first;
@@ -395,7 +374,7 @@ void apply_fused_blocks(sv_state_s* s, sv_fused_s* f, int first, int count)
             size_t bytes = 0;
             int e = b;
             while (e < end) {
-                const size_t mb = ((ab << (2 * f->blocks[e].k)) + 255) & ~size_t(255);
+                const size_t mb = (packed_matrix_bytes(s->dt, s->n, f->blocks[e].k, 0) + 255) & ~size_t(255);
                 if (bytes + mb > seg) break;
                 offs.push_back(bytes);
                 bytes += mb;
@@ -403,16 +382,16 @@ void apply_fused_blocks(sv_state_s* s, sv_fused_s* f, int first, int count)
             }
             if (e == b) {
                 // one block larger than a ring segment: stage it on its own
-                const size_t mb = ab << (2 * f->blocks[b].k);
+                const size_t mb = packed_matrix_bytes(s->dt, s->n, f->blocks[b].k, 0);
                 std::vector<char> one(mb);
-                convert_matrix(f->blocks[b].m, f->blocks[b].k, 0, s->dt, one.data());
+                pack_matrix(s->dt, s->n, f->blocks[b].k, 0, f->blocks[b].m, 0, one.data());
                 launch_apply(s->h, s->dt, s->d, stage_matrix(s->h, one.data(), mb), descs[b]);
                 ++b;
                 continue;
             }
             std::vector<char> tmp(bytes);
             for (int j = b; j < e; ++j)
-                convert_matrix(f->blocks[j].m, f->blocks[j].k, 0, s->dt, tmp.data() + offs[j - b]);
+                pack_matrix(s->dt, s->n, f->blocks[j].k, 0, f->blocks[j].m, 0, tmp.data() + offs[j - b]);
             const char* dm = static_cast<const char*>(stage_matrix(s->h, tmp.data(), bytes));
             for (int j = b; j < e; ++j) launch_apply(s->h, s->dt, s->d, dm + offs[j - b], descs[j]);
             b = e;

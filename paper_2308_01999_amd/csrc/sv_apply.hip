@@ -84,6 +84,393 @@ __global__ __launch_bounds__(256) void k_apply_dense(typename Cx<R>::T* __restri
     }
 }
 
+// ------------------------------------------------------------------ MFMA
+//
+// For complex64 with k = 4, 5 and complex128 with k = 5, the update of many
+// groups at once is the complex GEMM Y = M X, with one group per column of X.
+// It runs on the matrix cores as three real GEMMs (Gauss's product: three
+// real products per complex product instead of four):
+//     P1 = Re M Re X,  P2 = Im M Im X,  P3 = (Re M + Im M)(Re X + Im X),
+//     Re Y = P1 - P2,  Im Y = P3 - P1 - P2.
+// The host packs the three real matrices A_0 = Re M, A_1 = Im M,
+// A_2 = Re M + Im M in the order each lane consumes its A-operand slices, so
+// a lane loads its slice with a few 16-byte loads (pack_matrix below).
+//
+// Lane layouts (measured on gfx950):
+//   v_mfma_f32_32x32x2_f32: A[i][k] lane i + 32k; B[k][j] lane j + 32k;
+//     D[i][j] lane j + 32((i/4)%2), register 4(i/8) + i%4.
+//   v_mfma_f32_16x16x4_f32: A[i][k] lane i + 16k; B[k][j] lane j + 16k;
+//     D[i][j] lane j + 16(i/4), register i%4.
+//   v_mfma_f64_16x16x4_f64: A[i][k] lane i + 16k; B[k][j] lane j + 16k;
+//     D[i][j] lane j + 16(i%4), register i/4.
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// c64, k = 5: 16 floats of each A_g per lane (k index 2j + half)
+__device__ __forceinline__ void load_a_c64k5(const float4* __restrict__ m4, int lane, float* ar, float* ai,
+                                             float* as)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        float4 v = m4[(0 * 64 + lane) * 4 + q];
+        ar[4 * q] = v.x; ar[4 * q + 1] = v.y; ar[4 * q + 2] = v.z; ar[4 * q + 3] = v.w;
+        v = m4[(1 * 64 + lane) * 4 + q];
+        ai[4 * q] = v.x; ai[4 * q + 1] = v.y; ai[4 * q + 2] = v.z; ai[4 * q + 3] = v.w;
+        v = m4[(2 * 64 + lane) * 4 + q];
+        as[4 * q] = v.x; as[4 * q + 1] = v.y; as[4 * q + 2] = v.z; as[4 * q + 3] = v.w;
+    }
+}
+
+// c64, k = 4: 4 floats of each A_g per lane (k index 4s + q)
+__device__ __forceinline__ void load_a_c64k4(const float4* __restrict__ m4, int lane, float* ar, float* ai,
+                                             float* as)
+{
+    float4 v = m4[0 * 64 + lane];
+    ar[0] = v.x; ar[1] = v.y; ar[2] = v.z; ar[3] = v.w;
+    v = m4[1 * 64 + lane];
+    ai[0] = v.x; ai[1] = v.y; ai[2] = v.z; ai[3] = v.w;
+    v = m4[2 * 64 + lane];
+    as[0] = v.x; as[1] = v.y; as[2] = v.z; as[3] = v.w;
+}
+
+__device__ __forceinline__ void mfma_c64k5(const float* ar, const float* ai, const float* as, const float2* x,
+                                           f32x16& p1, f32x16& p2, f32x16& p3)
+{
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[j], x[j].x, p1, 0, 0, 0);
+        p2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[j], x[j].y, p2, 0, 0, 0);
+        p3 = __builtin_amdgcn_mfma_f32_32x32x2f32(as[j], x[j].x + x[j].y, p3, 0, 0, 0);
+    }
+}
+
+__device__ __forceinline__ void mfma_c64k4(const float* ar, const float* ai, const float* as, const float2* x,
+                                           f32x4& p1, f32x4& p2, f32x4& p3)
+{
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+        p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[s4], x[s4].x, p1, 0, 0, 0);
+        p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[s4], x[s4].y, p2, 0, 0, 0);
+        p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(as[s4], x[s4].x + x[s4].y, p3, 0, 0, 0);
+    }
+}
+
+// Direct MFMA kernels: used when the LDS-tiled kernels below do not apply
+// (gates with controls, states of fewer than 12 qubits).  One wave takes 32
+// (k = 5) or 16 (k = 4) consecutive groups per step of a grid-stride loop;
+// the A operands stay in registers for the whole kernel.
+__global__ __launch_bounds__(256) void k_apply_mfma_c64_k5(float2* __restrict__ psi,
+                                                          const float4* __restrict__ mats, ApplyArgs a,
+                                                          uint64_t n_tiles)
+{
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 31;
+    const int half = lane >> 5;
+    float ar[16], ai[16], as[16];
+    load_a_c64k5(mats, lane, ar, ai, as);
+    // The lane loads matrix index 2j + half and stores row 8(r/4) + 4 half +
+    // r%4: the lane-dependent part is bit 0 (loads) or bit 2 (stores) of the
+    // matrix index, i.e. target 0 or target 2; the rest of each offset is
+    // uniform across the wave.
+    const uint64_t lane_in = half ? a.off[1] : 0;
+    const uint64_t lane_out = half ? a.off[4] : 0;
+    const uint64_t n_waves = uint64_t(gridDim.x) * (blockDim.x >> 6);
+    for (uint64_t t = uint64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); t < n_tiles; t += n_waves) {
+        const uint64_t g = t * 32 + col;
+        const bool valid = g < a.n_groups;
+        const uint64_t base = valid ? group_base(g, a) : 0;
+        float2 x[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) x[j] = valid ? psi[base + lane_in + a.off[2 * j]] : float2{0.f, 0.f};
+        f32x16 p1 = {0}, p2 = {0}, p3 = {0};
+        mfma_c64k5(ar, ai, as, x, p1, p2, p3);
+        if (valid) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                psi[base + lane_out + a.off[8 * (r / 4) + (r % 4)]] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_apply_mfma_c64_k4(float2* __restrict__ psi,
+                                                          const float4* __restrict__ mats, ApplyArgs a,
+                                                          uint64_t n_tiles)
+{
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15;
+    const int q = lane >> 4;
+    float ar[4], ai[4], as[4];
+    load_a_c64k4(mats, lane, ar, ai, as);
+    // loads use matrix index 4 s4 + q, stores row 4 q + r: the lane part is
+    // bits 0-1 (targets 0, 1) for loads and bits 2-3 (targets 2, 3) for stores
+    const uint64_t lane_in = ((q & 1) ? a.off[1] : 0) + ((q & 2) ? a.off[2] : 0);
+    const uint64_t lane_out = ((q & 1) ? a.off[4] : 0) + ((q & 2) ? a.off[8] : 0);
+    const uint64_t n_waves = uint64_t(gridDim.x) * (blockDim.x >> 6);
+    for (uint64_t t = uint64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); t < n_tiles; t += n_waves) {
+        const uint64_t g = t * 16 + col;
+        const bool valid = g < a.n_groups;
+        const uint64_t base = valid ? group_base(g, a) : 0;
+        float2 x[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) x[s4] = valid ? psi[base + lane_in + a.off[4 * s4]] : float2{0.f, 0.f};
+        f32x4 p1 = {0}, p2 = {0}, p3 = {0};
+        mfma_c64k4(ar, ai, as, x, p1, p2, p3);
+        if (valid) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) psi[base + lane_out + a.off[r]] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
+        }
+    }
+}
+
+// ------------------------------------------------------- LDS-staged tiles
+//
+// The main sweep for uncontrolled gates on states of >= 12 (complex64) or
+// >= 11 (complex128) qubits.  A tile is the 2^12 (complex64) or 2^11
+// (complex128) amplitudes = 32 KiB whose index bits outside {0..L-1} and
+// the targets >= L are fixed, with L the smallest width that leaves 2^(TB-k)
+// whole groups in the tile.  The tile is 2^(k_hi) contiguous runs of 2^L
+// amplitudes (one run per setting of the high targets), so every global
+// access is a coalesced 16-byte load or store over runs of >= 1 KiB,
+// whatever the targets are; the gather of each group's 2^k amplitudes
+// happens in LDS.  A workgroup sweeps `tiles_per_wg` consecutive tiles,
+// loading its A operands once and prefetching tile t+1 into registers while
+// tile t is in LDS.  Each wave owns whole groups, so the in-place update in
+// LDS needs no synchronisation beyond the three barriers per tile.
+
+struct TileArgs {
+    uint64_t n_tiles;
+    uint64_t tiles_per_wg;
+    int32_t L;
+    int32_t n_hi;
+    int32_t hi_pos[SV_MAX_TARGETS];
+    int32_t n_lo;
+    int32_t lo_pos[SV_MAX_TARGETS];
+    int32_t lds_off[64];  // matrix index -> LDS offset from the group's base
+};
+
+__device__ __forceinline__ uint64_t insert_zero_bits(uint64_t v, const int32_t* pos, int n)
+{
+    for (int j = 0; j < n; ++j) {
+        const int p = pos[j];
+        const uint64_t lo = v & ((uint64_t(1) << p) - 1);
+        v = ((v >> p) << (p + 1)) | lo;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t deposit_bits(uint32_t r, const int32_t* pos, int n)
+{
+    uint64_t o = 0;
+    for (int b = 0; b < n; ++b) o |= uint64_t((r >> b) & 1u) << pos[b];
+    return o;
+}
+
+constexpr int kTileThreads = 256;
+constexpr int kTileVecs = 8;  // 16-byte vectors per thread per tile (32 KiB / 256 / 16)
+
+// The 8 per-thread vectors live in named registers (an array carried across
+// the tile loop would be placed in scratch memory by the compiler).
+#define SV_REP8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
+
+// Global offsets (relative to a tile's base) of the thread's 8 vectors;
+// vector u of thread tid holds tile-local amplitudes starting at
+// i = (u * 256 + tid) * amps_per_vec, which is also its LDS position.
+template <int APV>
+__device__ __forceinline__ void tile_offsets(const TileArgs& a, uint64_t* goff)
+{
+    const int mask = (1 << a.L) - 1;
+#pragma unroll
+    for (int u = 0; u < kTileVecs; ++u) {
+        const int i = (u * kTileThreads + int(threadIdx.x)) * APV;
+        goff[u] = deposit_bits(uint32_t(i >> a.L), a.hi_pos, a.n_hi) + uint64_t(i & mask);
+    }
+}
+
+__device__ __forceinline__ uint64_t tile_base(uint64_t t, const TileArgs& a)
+{
+    return insert_zero_bits(t << a.L, a.hi_pos, a.n_hi);
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_tile_c64_k5(float2* __restrict__ psi,
+                                                             const float4* __restrict__ mats, TileArgs a)
+{
+    __shared__ float4 lds[kTileThreads * kTileVecs];
+    const uint64_t t0 = uint64_t(blockIdx.x) * a.tiles_per_wg;
+    if (t0 >= a.n_tiles) return;
+    const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 31, half = lane >> 5;
+    float ar[16], ai[16], as[16];
+    load_a_c64k5(mats, lane, ar, ai, as);
+    uint64_t goff[kTileVecs];
+    tile_offsets<2>(a, goff);
+    const int pb = int(insert_zero_bits(uint64_t(wave * 32 + col), a.lo_pos, a.n_lo));
+    const int pin = pb + (half ? a.lds_off[1] : 0);
+    const int pout = pb + (half ? a.lds_off[4] : 0);
+    float2* lds2 = reinterpret_cast<float2*>(lds);
+#define SV_DECL(u) float4 buf##u;
+    SV_REP8(SV_DECL)
+#undef SV_DECL
+    uint64_t base = tile_base(t0, a);
+#define SV_LOAD(u) buf##u = *reinterpret_cast<const float4*>(psi + base + goff[u]);
+    SV_REP8(SV_LOAD)
+#undef SV_LOAD
+    for (uint64_t t = t0; t < t1; ++t) {
+#define SV_STAGE(u) lds[u * kTileThreads + tid] = buf##u;
+        SV_REP8(SV_STAGE)
+#undef SV_STAGE
+        __syncthreads();
+        uint64_t nbase = 0;
+        if (t + 1 < t1) {
+            nbase = tile_base(t + 1, a);
+#define SV_PREFETCH(u) buf##u = *reinterpret_cast<const float4*>(psi + nbase + goff[u]);
+            SV_REP8(SV_PREFETCH)
+#undef SV_PREFETCH
+        }
+        float2 x[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) x[j] = lds2[pin + a.lds_off[2 * j]];
+        f32x16 p1 = {0}, p2 = {0}, p3 = {0};
+        mfma_c64k5(ar, ai, as, x, p1, p2, p3);
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            lds2[pout + a.lds_off[8 * (r / 4) + (r % 4)]] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kTileVecs; ++u)
+            *reinterpret_cast<float4*>(psi + base + goff[u]) = lds[u * kTileThreads + tid];
+        base = nbase;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict__ psi,
+                                                             const float4* __restrict__ mats, TileArgs a)
+{
+    __shared__ float4 lds[kTileThreads * kTileVecs];
+    const uint64_t t0 = uint64_t(blockIdx.x) * a.tiles_per_wg;
+    if (t0 >= a.n_tiles) return;
+    const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, q = lane >> 4;
+    float ar[4], ai[4], as[4];
+    load_a_c64k4(mats, lane, ar, ai, as);
+    uint64_t goff[kTileVecs];
+    tile_offsets<2>(a, goff);
+    // each wave owns 4 column tiles of 16 groups: 256 groups per tile
+    const int lin = ((q & 1) ? a.lds_off[1] : 0) + ((q & 2) ? a.lds_off[2] : 0);
+    const int lout = ((q & 1) ? a.lds_off[4] : 0) + ((q & 2) ? a.lds_off[8] : 0);
+    int pb[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) pb[ct] = int(insert_zero_bits(uint64_t(wave * 64 + ct * 16 + col), a.lo_pos, a.n_lo));
+    float2* lds2 = reinterpret_cast<float2*>(lds);
+#define SV_DECL(u) float4 buf##u;
+    SV_REP8(SV_DECL)
+#undef SV_DECL
+    uint64_t base = tile_base(t0, a);
+#define SV_LOAD(u) buf##u = *reinterpret_cast<const float4*>(psi + base + goff[u]);
+    SV_REP8(SV_LOAD)
+#undef SV_LOAD
+    for (uint64_t t = t0; t < t1; ++t) {
+#define SV_STAGE(u) lds[u * kTileThreads + tid] = buf##u;
+        SV_REP8(SV_STAGE)
+#undef SV_STAGE
+        __syncthreads();
+        uint64_t nbase = 0;
+        if (t + 1 < t1) {
+            nbase = tile_base(t + 1, a);
+#define SV_PREFETCH(u) buf##u = *reinterpret_cast<const float4*>(psi + nbase + goff[u]);
+            SV_REP8(SV_PREFETCH)
+#undef SV_PREFETCH
+        }
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            float2 x[4];
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) x[s4] = lds2[pb[ct] + lin + a.lds_off[4 * s4]];
+            f32x4 p1 = {0}, p2 = {0}, p3 = {0};
+            mfma_c64k4(ar, ai, as, x, p1, p2, p3);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                lds2[pb[ct] + lout + a.lds_off[r]] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kTileVecs; ++u)
+            *reinterpret_cast<float4*>(psi + base + goff[u]) = lds[u * kTileThreads + tid];
+        base = nbase;
+        __syncthreads();
+    }
+}
+
+// complex128, k = 5 on v_mfma_f64_16x16x4_f64: 64 groups per tile, one
+// 16-column tile per wave; two 16-row tiles cover the 32 output amplitudes.
+// A_g slices per lane: 2 row tiles x 8 k-steps = 16 doubles.
+__global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restrict__ psi,
+                                                              const double2* __restrict__ mats, TileArgs a)
+{
+    __shared__ double2 lds[kTileThreads * kTileVecs];
+    const uint64_t t0 = uint64_t(blockIdx.x) * a.tiles_per_wg;
+    if (t0 >= a.n_tiles) return;
+    const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, q = lane >> 4;
+    double A[3][16];
+#pragma unroll
+    for (int g = 0; g < 3; ++g)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const double2 v = mats[(g * 64 + lane) * 8 + e];
+            A[g][2 * e] = v.x;
+            A[g][2 * e + 1] = v.y;
+        }
+    uint64_t goff[kTileVecs];
+    tile_offsets<1>(a, goff);
+    const int pb = int(insert_zero_bits(uint64_t(wave * 16 + col), a.lo_pos, a.n_lo));
+    // loads: matrix index 4s + q; stores: row 16 rt + 4 v + q: bits 0-1 = q
+    const int pq = pb + ((q & 1) ? a.lds_off[1] : 0) + ((q & 2) ? a.lds_off[2] : 0);
+#define SV_DECL(u) double2 buf##u;
+    SV_REP8(SV_DECL)
+#undef SV_DECL
+    uint64_t base = tile_base(t0, a);
+#define SV_LOAD(u) buf##u = psi[base + goff[u]];
+    SV_REP8(SV_LOAD)
+#undef SV_LOAD
+    for (uint64_t t = t0; t < t1; ++t) {
+#define SV_STAGE(u) lds[u * kTileThreads + tid] = buf##u;
+        SV_REP8(SV_STAGE)
+#undef SV_STAGE
+        __syncthreads();
+        uint64_t nbase = 0;
+        if (t + 1 < t1) {
+            nbase = tile_base(t + 1, a);
+#define SV_PREFETCH(u) buf##u = psi[nbase + goff[u]];
+            SV_REP8(SV_PREFETCH)
+#undef SV_PREFETCH
+        }
+        double2 x[8];
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8) x[s8] = lds[pq + a.lds_off[4 * s8]];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            f64x4 p1 = {0}, p2 = {0}, p3 = {0};
+#pragma unroll
+            for (int s8 = 0; s8 < 8; ++s8) {
+                p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[0][rt * 8 + s8], x[s8].x, p1, 0, 0, 0);
+                p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[1][rt * 8 + s8], x[s8].y, p2, 0, 0, 0);
+                p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[2][rt * 8 + s8], x[s8].x + x[s8].y, p3, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                lds[pq + a.lds_off[16 * rt + 4 * v]] = double2{p1[v] - p2[v], p3[v] - p1[v] - p2[v]};
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kTileVecs; ++u) psi[base + goff[u]] = lds[u * kTileThreads + tid];
+        base = nbase;
+        __syncthreads();
+    }
+}
+
 // Large gates (k = 7..10, compute-bound): one workgroup per group.  The
 // group's 2^k amplitudes are staged in LDS; each thread forms whole rows.
 struct ApplyArgsLarge {
@@ -137,6 +524,132 @@ __global__ __launch_bounds__(256) void k_apply_large(typename Cx<R>::T* __restri
     }
 }
 
+enum class Path { kValu, kLarge, kMfmaC64K5, kMfmaC64K4, kTileC64K5, kTileC64K4, kTileC128K5 };
+
+Path choose(sv_dtype_t dt, int n, int k, int n_controls)
+{
+    if (k > kMaxUnrolledK) return Path::kLarge;
+    const bool tile_ok = n_controls == 0;
+    if (dt == SV_C64 && k == 5) return (tile_ok && n >= 12) ? Path::kTileC64K5 : Path::kMfmaC64K5;
+    if (dt == SV_C64 && k == 4) return (tile_ok && n >= 12) ? Path::kTileC64K4 : Path::kMfmaC64K4;
+    if (dt == SV_C128 && k == 5 && tile_ok && n >= 11) return Path::kTileC128K5;
+    return Path::kValu;
+}
+
+void fill_args(ApplyArgs& a, const GateDesc& d)
+{
+    a.n_groups = d.n_groups;
+    a.cval = d.cval;
+    a.n_fixed = d.n_fixed;
+    for (int j = 0; j < d.n_fixed; ++j) a.fixed[j] = d.fixed_sorted[j];
+    for (int r = 0; r < (1 << d.k); ++r) {
+        uint64_t off = 0;
+        for (int b = 0; b < d.k; ++b)
+            if ((r >> b) & 1) off |= d.tbit[b];
+        a.off[r] = off;
+    }
+}
+
+void launch_mfma_c64(sv_handle_s* h, float2* psi, const float4* mats, const GateDesc& d)
+{
+    ApplyArgs a{};
+    fill_args(a, d);
+    const uint64_t cols = d.k == 5 ? 32 : 16;
+    const uint64_t n_tiles = (d.n_groups + cols - 1) / cols;
+    const uint64_t waves_per_block = 4;
+    uint64_t blocks = (n_tiles + waves_per_block - 1) / waves_per_block;
+    const uint64_t cap = uint64_t(h->cu_count) * 8;
+    if (blocks > cap) blocks = cap;
+    if (d.k == 5)
+        hipLaunchKernelGGL(k_apply_mfma_c64_k5, dim3(unsigned(blocks)), dim3(256), 0, h->stream, psi, mats, a,
+                           n_tiles);
+    else
+        hipLaunchKernelGGL(k_apply_mfma_c64_k4, dim3(unsigned(blocks)), dim3(256), 0, h->stream, psi, mats, a,
+                           n_tiles);
+    SV_HIP(hipGetLastError());
+}
+
+// Tile geometry for a gate with targets d.tbit (matrix order) on n qubits;
+// tb = log2 of the tile's amplitude count.
+TileArgs make_tile_args(const GateDesc& d, int n, int tb, int cu_count)
+{
+    int tq[SV_MAX_TARGETS];
+    for (int a = 0; a < d.k; ++a) {
+        int q = 0;
+        while ((uint64_t(1) << q) != d.tbit[a]) ++q;
+        tq[a] = q;
+    }
+    const int gbits = tb - d.k;  // log2 groups per tile
+    int L = gbits;
+    for (;;) {
+        int klo = 0;
+        for (int a = 0; a < d.k; ++a) klo += tq[a] < L;
+        if (L - klo >= gbits) break;
+        ++L;
+    }
+    TileArgs t{};
+    t.L = L;
+    int hi[SV_MAX_TARGETS], lo[SV_MAX_TARGETS], nh = 0, nl = 0;
+    for (int q = 0; q < n; ++q)
+        for (int a = 0; a < d.k; ++a)
+            if (tq[a] == q) {
+                if (q < L)
+                    lo[nl++] = q;
+                else
+                    hi[nh++] = q;
+            }
+    t.n_hi = nh;
+    t.n_lo = nl;
+    for (int j = 0; j < nh; ++j) t.hi_pos[j] = hi[j];
+    for (int j = 0; j < nl; ++j) t.lo_pos[j] = lo[j];
+    for (int c = 0; c < (1 << d.k); ++c) {
+        int run = 0, low = 0;
+        for (int a = 0; a < d.k; ++a) {
+            if (!((c >> a) & 1)) continue;
+            if (tq[a] < L) {
+                low |= 1 << tq[a];
+            } else {
+                int rank = 0;
+                while (hi[rank] != tq[a]) ++rank;
+                run |= 1 << rank;
+            }
+        }
+        t.lds_off[c] = (run << L) + low;
+    }
+    t.n_tiles = uint64_t(1) << (n - tb);
+    // about 32 workgroups per CU over the sweep, each on consecutive tiles
+    const uint64_t target_wgs = uint64_t(cu_count) * 32;
+    uint64_t per = t.n_tiles / target_wgs;
+    if (per < 1) per = 1;
+    if (per > 64) per = 64;
+    t.tiles_per_wg = per;
+    return t;
+}
+
+void launch_tile(sv_handle_s* h, Path p, void* psi, const void* mats, const GateDesc& d)
+{
+    const int tb = (p == Path::kTileC128K5) ? 11 : 12;
+    const TileArgs t = make_tile_args(d, d.n, tb, h->cu_count);
+    const uint64_t blocks = (t.n_tiles + t.tiles_per_wg - 1) / t.tiles_per_wg;
+    switch (p) {
+        case Path::kTileC64K5:
+            hipLaunchKernelGGL(k_tile_c64_k5, dim3(unsigned(blocks)), dim3(kTileThreads), 0, h->stream,
+                               static_cast<float2*>(psi), static_cast<const float4*>(mats), t);
+            break;
+        case Path::kTileC64K4:
+            hipLaunchKernelGGL(k_tile_c64_k4, dim3(unsigned(blocks)), dim3(kTileThreads), 0, h->stream,
+                               static_cast<float2*>(psi), static_cast<const float4*>(mats), t);
+            break;
+        case Path::kTileC128K5:
+            hipLaunchKernelGGL(k_tile_c128_k5, dim3(unsigned(blocks)), dim3(kTileThreads), 0, h->stream,
+                               static_cast<double2*>(psi), static_cast<const double2*>(mats), t);
+            break;
+        default:
+            throw Error{SV_ERR_INTERNAL, "not a tile path"};
+    }
+    SV_HIP(hipGetLastError());
+}
+
 template <typename R>
 void launch_apply_t(sv_handle_s* h, void* psi_v, const void* mat_v, const GateDesc& d)
 {
@@ -145,16 +658,7 @@ void launch_apply_t(sv_handle_s* h, void* psi_v, const void* mat_v, const GateDe
     const T2* mat = static_cast<const T2*>(mat_v);
     if (d.k <= kMaxUnrolledK) {
         ApplyArgs a{};
-        a.n_groups = d.n_groups;
-        a.cval = d.cval;
-        a.n_fixed = d.n_fixed;
-        for (int j = 0; j < d.n_fixed; ++j) a.fixed[j] = d.fixed_sorted[j];
-        for (int r = 0; r < (1 << d.k); ++r) {
-            uint64_t off = 0;
-            for (int b = 0; b < d.k; ++b)
-                if ((r >> b) & 1) off |= d.tbit[b];
-            a.off[r] = off;
-        }
+        fill_args(a, d);
         // a dispatch counts at most 2^32 - 1 work-items per grid dimension:
         // spread the blocks over x and y
         const uint64_t threads = 256;
@@ -197,12 +701,93 @@ void launch_apply_t(sv_handle_s* h, void* psi_v, const void* mat_v, const GateDe
 
 }  // namespace
 
+size_t packed_matrix_bytes(sv_dtype_t dt, int n, int k, int n_controls)
+{
+    const size_t d2 = size_t(1) << (2 * k);
+    switch (choose(dt, n, k, n_controls)) {
+        case Path::kMfmaC64K4:
+        case Path::kMfmaC64K5:
+        case Path::kTileC64K4:
+        case Path::kTileC64K5:
+            return 3 * d2 * sizeof(float);
+        case Path::kTileC128K5:
+            return 3 * d2 * sizeof(double);
+        default:
+            return d2 * (dt == SV_C64 ? 8 : 16);
+    }
+}
+
+void pack_matrix(sv_dtype_t dt, int n, int k, int n_controls, const double* m, int adjoint, void* dst)
+{
+    const int d = 1 << k;
+    // A_g[i][c] with g = 0: Re M, 1: Im M, 2: Re M + Im M (of M or M^dagger)
+    auto A = [&](int g, int i, int c) {
+        const int src = adjoint ? (c * d + i) : (i * d + c);
+        const double re = m[2 * src];
+        const double im = adjoint ? -m[2 * src + 1] : m[2 * src + 1];
+        return g == 0 ? re : g == 1 ? im : re + im;
+    };
+    const Path p = choose(dt, n, k, n_controls);
+    if (p == Path::kMfmaC64K5 || p == Path::kTileC64K5) {
+        // lane l = col + 32 half: 16 floats A_g[col][2j + half], j = 0..15
+        float* o = static_cast<float*>(dst);
+        for (int g = 0; g < 3; ++g)
+            for (int l = 0; l < 64; ++l)
+                for (int j = 0; j < 16; ++j) o[(g * 64 + l) * 16 + j] = float(A(g, l & 31, 2 * j + (l >> 5)));
+        return;
+    }
+    if (p == Path::kMfmaC64K4 || p == Path::kTileC64K4) {
+        // lane l = col + 16 q: 4 floats A_g[col][4s + q], s = 0..3
+        float* o = static_cast<float*>(dst);
+        for (int g = 0; g < 3; ++g)
+            for (int l = 0; l < 64; ++l)
+                for (int s4 = 0; s4 < 4; ++s4) o[(g * 64 + l) * 4 + s4] = float(A(g, l & 15, 4 * s4 + (l >> 4)));
+        return;
+    }
+    if (p == Path::kTileC128K5) {
+        // lane l = i0 + 16 q: 16 doubles A_g[i0 + 16 rt][4s + q], (rt, s)
+        double* o = static_cast<double*>(dst);
+        for (int g = 0; g < 3; ++g)
+            for (int l = 0; l < 64; ++l)
+                for (int rt = 0; rt < 2; ++rt)
+                    for (int s8 = 0; s8 < 8; ++s8)
+                        o[(g * 64 + l) * 16 + rt * 8 + s8] = A(g, (l & 15) + 16 * rt, 4 * s8 + (l >> 4));
+        return;
+    }
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+            const double re = A(0, r, c), im = A(1, r, c);
+            if (dt == SV_C64) {
+                float* o = static_cast<float*>(dst);
+                o[2 * (r * d + c)] = float(re);
+                o[2 * (r * d + c) + 1] = float(im);
+            } else {
+                double* o = static_cast<double*>(dst);
+                o[2 * (r * d + c)] = re;
+                o[2 * (r * d + c) + 1] = im;
+            }
+        }
+}
+
 void launch_apply(sv_handle_s* h, sv_dtype_t dt, void* psi, const void* mat, const GateDesc& d)
 {
-    if (dt == SV_C64)
-        launch_apply_t<float>(h, psi, mat, d);
-    else
-        launch_apply_t<double>(h, psi, mat, d);
+    const Path p = choose(dt, d.n, d.k, d.n_controls);
+    switch (p) {
+        case Path::kMfmaC64K4:
+        case Path::kMfmaC64K5:
+            launch_mfma_c64(h, static_cast<float2*>(psi), static_cast<const float4*>(mat), d);
+            break;
+        case Path::kTileC64K4:
+        case Path::kTileC64K5:
+        case Path::kTileC128K5:
+            launch_tile(h, p, psi, mat, d);
+            break;
+        default:
+            if (dt == SV_C64)
+                launch_apply_t<float>(h, psi, mat, d);
+            else
+                launch_apply_t<double>(h, psi, mat, d);
+    }
 }
 
 }  // namespace sv

@@ -86,7 +86,9 @@ namespace sv {
 
 // Arguments of one dense gate sweep, prepared on the host.
 struct GateDesc {
+    int n = 0;                     // qubits of the state
     int k = 0;                     // number of targets
+    int n_controls = 0;
     int n_fixed = 0;               // targets + controls
     int fixed_sorted[SV_MAX_QUBITS] = {};  // ascending positions of targets and controls
     uint64_t cval = 0;             // control bits that must be set
@@ -95,8 +97,14 @@ struct GateDesc {
     int min_target = 0;
 };
 
-// psi: amplitudes; mat: device copy of the matrix in the state's precision
-// (complex, row-major); desc: the sweep.
+// Device format of a gate matrix for the sweep kernel chosen for (dt, n, k,
+// controls):
+// its size, and packing of a complex128 row-major matrix (or its adjoint)
+// into it on the host.
+size_t packed_matrix_bytes(sv_dtype_t dt, int n, int k, int n_controls);
+void pack_matrix(sv_dtype_t dt, int n, int k, int n_controls, const double* m, int adjoint, void* dst);
+
+// psi: amplitudes; mat: device copy of the packed matrix; desc: the sweep.
 void launch_apply(sv_handle_s* h, sv_dtype_t dt, void* psi, const void* mat, const GateDesc& desc);
 
 void launch_set_basis(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, uint64_t x);
