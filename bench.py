@@ -43,6 +43,13 @@ def parse():
     ap.add_argument("--no-c128", action="store_true", help="skip the complex128 leg")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing leg")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target length of the oracle sample")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-circuit leg")
+    ap.add_argument("--batch-circuits", type=int, default=4096)
+    ap.add_argument("--baseline-sample", type=int, default=48,
+                    help="circuits of the batch run through the plain complex128 per-circuit path")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain device copies of known size (for HBM counter calibration)")
     return ap.parse_args()
@@ -173,6 +180,123 @@ def cpu_baseline(W, P, gates, n, kmax, seconds):
                       f"{el:.1f} s; bytes counted as 2*2^{n}*16 per block"}
 
 
+def batched_leg(P, W, torch, H, count, steps, warmup, sample):
+    """4096 independent complex64 brickwork circuits (qubits uniform in
+    8..20, depth uniform in 10..40), each returning <Z_i Z_i+1> for all i, in
+    one persistent launch with autotuned fusion widths; per-circuit latency
+    from the device wall clock.  Baseline: a sample of the same circuits run
+    one at a time through the plain complex128 path (one sv_apply_matrix per
+    gate, then sv_expect_pauli), timed on the host."""
+    import numpy as np
+    items = W.batched(count, seed=0)
+    ns = [it.n for it in items]
+    circuits = [it.gates for it in items]
+    terms = [[(1 << q) | (1 << (q + 1)) for q in range(it.n - 1)] for it in items]
+    t0 = time.perf_counter()
+    b = P.Batch(H, ns, circuits, terms, max_fused_qubits=0)
+    prep = time.perf_counter() - t0
+    for _ in range(warmup):
+        b.run()
+    lats, kts = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        exps, lat, ks = b.run()
+        lats.append(lat)
+        kts.append(ks)
+    wall = (time.perf_counter() - t0) / steps
+    lat = np.concatenate(lats)
+    widths = {str(n): b.fusion_width(n) for n in sorted(set(ns))}
+    blocks = b.blocks()
+    state_gb = sum((1 << n) * 8 for n in ns) / 1e9
+    b.close()
+    # baseline: plain complex128 per-circuit path on a sample
+    rng = np.random.default_rng(1)
+    pick = sorted(rng.choice(count, size=min(sample, count), replace=False).tolist())
+    base_lat = []
+    for i in pick:
+        it = items[i]
+        st = P.State(H, it.n, "c128")
+        zz = [[(q, "Z"), (q + 1, "Z")] for q in range(it.n - 1)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st.run(it.gates)
+        st.expect(zz)
+        base_lat.append(time.perf_counter() - t1)
+        st.close()
+    base_lat = np.array(base_lat)
+    return {
+        "workload": f"{count} complex64 brickwork circuits, qubits uniform 8-20, depth uniform 10-40, "
+                    f"<Z_i Z_i+1> for all i, one persistent launch",
+        "circuits": count,
+        "states_GB": round(state_gb, 3),
+        "kernel_ms": round(1e3 * float(np.median(kts)), 3),
+        "wall_ms_per_batch": round(1e3 * wall, 3),
+        "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+        "circuits_per_s": round(count / float(np.median(kts)), 1),
+        "fusion_widths": widths,
+        "fused_blocks_total": int(blocks.sum()),
+        "host_prep_s": round(prep, 3),
+        "baseline_c128_per_circuit": {
+            "sample": len(pick),
+            "p50_ms": round(1e3 * float(np.percentile(base_lat, 50)), 3),
+            "p99_ms": round(1e3 * float(np.percentile(base_lat, 99)), 3),
+            "circuits_per_s": round(len(pick) / float(base_lat.sum()), 1),
+            "path": "one circuit at a time, unfused sv_apply_matrix per gate, then sv_expect_pauli; host wall time",
+        },
+    }
+
+
+def serving_leg(P, W, torch, n_requests, slots):
+    """Poisson stream of circuit requests (qubits log-uniform 10..28, depth
+    10..100, random U3 + CZ/CNOT pairs; 16 random Pauli strings and 1024
+    samples each) through the continuous-batching server (complex64 states,
+    FP64 reductions).  The offered load is 0.75 of the capacity measured by
+    submitting a calibration set at once.  Baseline: a complex128 FIFO that
+    serves one request at a time, on the first requests of the same stream."""
+    import numpy as np
+    from paper_2308_01999_amd.serve import Server, replay
+    cal = W.serving_requests(max(8, slots * 4), rate_per_s=1e9, seed=11)
+    srv = Server(slots=slots, budget_bytes=96 << 30, dtype="c64", kmax=5)
+    t0 = time.monotonic()
+    replay(srv, cal, time_scale=0.0)
+    capacity = len(cal) / (time.monotonic() - t0)
+    rate = 0.75 * capacity
+    reqs = W.serving_requests(n_requests, rate_per_s=rate, seed=0)
+    t0 = time.monotonic()
+    res = replay(srv, reqs)
+    span = time.monotonic() - t0
+    srv.close()
+    lat = np.array([res[r.rid].latency for r in reqs])
+    base_n = min(16, n_requests)
+    bsrv = Server(slots=1, budget_bytes=96 << 30, dtype="c128", kmax=0)
+    t0 = time.monotonic()
+    bres = replay(bsrv, reqs[:base_n])
+    bspan = time.monotonic() - t0
+    bsrv.close()
+    blat = np.array([bres[r.rid].latency for r in reqs[:base_n]])
+    return {
+        "workload": "Poisson requests: qubits log-uniform 10-28, depth 10-100, U3 + CZ/CNOT on random pairs, "
+                    "16 Pauli strings + 1024 samples each; complex64, fused k<=5, FP64 reductions",
+        "requests": n_requests,
+        "slots": slots,
+        "capacity_req_per_s": round(capacity, 2),
+        "offered_req_per_s": round(rate, 2),
+        "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+        "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
+        "circuits_per_s": round(n_requests / span, 2),
+        "qubits_mean": round(float(np.mean([r.n for r in reqs])), 2),
+        "baseline_c128_fifo": {
+            "requests": base_n,
+            "p50_ms": round(1e3 * float(np.percentile(blat, 50)), 2),
+            "p99_ms": round(1e3 * float(np.percentile(blat, 99)), 2),
+            "circuits_per_s": round(base_n / bspan, 2),
+            "path": "same stream, one request at a time, complex128 states, one sv_apply_matrix sweep per gate",
+        },
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -243,6 +367,15 @@ def main():
         "c64": r64,
         **extra,
     }
+    if not args.no_batched:
+        print("[bench] batched leg", file=sys.stderr, flush=True)
+        H2 = P.Handle()
+        line["batched"] = batched_leg(P, W, torch, H2, args.batch_circuits, max(1, args.steps), 1,
+                                      args.baseline_sample)
+        H2.close()
+    if not args.no_serving:
+        print("[bench] serving leg", file=sys.stderr, flush=True)
+        line["serving"] = serving_leg(P, W, torch, args.serve_requests, args.serve_slots)
     if args.calibrate_copy:
         line["copy_calibration"] = calibrate_copy(torch)
     if not args.no_cpu_baseline:

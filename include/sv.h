@@ -159,6 +159,33 @@ sv_status_t sv_gate_matrix(const char* name, const double* params, int32_t n_par
 sv_status_t sv_fuse_gates(const sv_gate_t* gates, int32_t n_gates, int32_t max_fused_qubits,
                           sv_fused_t* out);
 
+/* Codes of the named gates for sv_fuse_gate_list (the matrices of
+ * sv_gate_matrix); SV_GATE_ADJOINT may be or-ed into a code to ask for the
+ * adjoint. */
+typedef enum {
+    SV_GATE_U3 = 0,
+    SV_GATE_H = 1,
+    SV_GATE_X = 2,
+    SV_GATE_Y = 3,
+    SV_GATE_Z = 4,
+    SV_GATE_CX = 5,
+    SV_GATE_CZ = 6,
+    SV_GATE_CP = 7,
+    SV_GATE_SWAP = 8,
+    SV_GATE_ADJOINT = 256
+} sv_gate_code_t;
+
+/*
+ * Gate fusion of a circuit of named gates given as flat arrays (host only):
+ * gate g has code codes[g], qubits qubits[2g] (and qubits[2g + 1] for the
+ * two-qubit gates; for CX and CP the first is the control) and parameters
+ * params[3g .. 3g + 2] (theta, phi, lambda for U3; phi for CP; ignored
+ * otherwise).  Equivalent to sv_fuse_gates over the matrices of
+ * sv_gate_matrix, without building them on the caller's side.
+ */
+sv_status_t sv_fuse_gate_list(const int32_t* codes, const int32_t* qubits, const double* params,
+                              int32_t n_gates, int32_t max_fused_qubits, sv_fused_t* out);
+
 /* Number of blocks. */
 sv_status_t sv_fused_count(sv_fused_t f, int32_t* n_blocks);
 
@@ -215,6 +242,52 @@ sv_status_t sv_sample(sv_state_t s, const double* uniforms, int64_t n_shots,
  * accessor, here without reordering).  Blocks. */
 sv_status_t sv_copy_to_host(sv_state_t s, void* dst, uint64_t first, uint64_t count);
 sv_status_t sv_copy_from_host(sv_state_t s, const void* src, uint64_t first, uint64_t count);
+
+/* ------------------------------------------------------ batched circuits */
+
+typedef struct sv_batch_s* sv_batch_t;
+
+/*
+ * A batch of independent complex64 circuits run together by one persistent
+ * kernel launch (the batched execution of many small states; the paper's
+ * fused-gate path of Sec. II-B applied to each).  Circuit i has n_qubits[i]
+ * in [1, 30] qubits, starts from |0..0>, and is the named-gate list
+ * [gate_offsets[i], gate_offsets[i+1]) of the flat arrays codes, qubits
+ * (2 per gate) and params (3 per gate), coded as for sv_fuse_gate_list.
+ * Its observables are the Z-type Pauli strings z_masks[term_offsets[i] ..
+ * term_offsets[i+1]) (bit q set = Z on qubit q), at most 32 per circuit;
+ * each result is <psi|Z..Z|psi> / <psi|psi> accumulated in FP64.
+ * max_fused_qubits in [1, 5] fixes the fusion width; 0 lets the autotuner
+ * pick it per qubit count by timing the batch kernel at widths 3..5 on the
+ * batch's own circuits (cached for the process).  Circuits are fused on host
+ * threads and their descriptors uploaded once.  Host arrays may be freed on
+ * return.
+ */
+sv_status_t sv_batch_create(sv_handle_t h, int32_t n_circuits, const int32_t* n_qubits,
+                            const int32_t* gate_offsets, const int32_t* codes, const int32_t* qubits,
+                            const double* params, const int32_t* term_offsets, const uint64_t* z_masks,
+                            int32_t max_fused_qubits, sv_batch_t* out);
+
+/* Bytes of device memory the batch's states need (*state_bytes) and, if
+ * byte_offsets is not NULL, the byte offset of each circuit's state. */
+sv_status_t sv_batch_state_layout(sv_batch_t b, uint64_t* state_bytes, uint64_t* byte_offsets);
+
+/* Fusion width used for circuits of n_qubits (0 if the batch has none) and
+ * the fused block count of every circuit (blocks_per_circuit may be NULL). */
+sv_status_t sv_batch_info(sv_batch_t b, int32_t n_qubits, int32_t* max_fused_qubits, int32_t* blocks_per_circuit);
+
+/*
+ * Runs the whole batch in one launch on the handle's stream and blocks.
+ * states: device buffer of sv_batch_state_layout bytes, 256-byte aligned; on
+ * return it holds every circuit's final state.  expect_out (host, may be
+ * NULL): all term results in term order.  latency_s (host, may be NULL):
+ * per circuit, the device wall-clock time from the first workgroup's start
+ * to that circuit's completion.  kernel_s (may be NULL): the launch's event
+ * time.
+ */
+sv_status_t sv_batch_run(sv_batch_t b, void* states, double* expect_out, double* latency_s, double* kernel_s);
+
+sv_status_t sv_batch_destroy(sv_batch_t b);
 
 /* ------------------------------------------------------------------ errors */
 

@@ -63,6 +63,7 @@ _SIGS = {
     "sv_apply_matrix": [_vp, _pd, _pi32, _i32, _pi32, _pi32, _i32, _i32],
     "sv_gate_matrix": [ctypes.c_char_p, _pd, _i32, _pd, _pi32, _pi32],
     "sv_fuse_gates": [ctypes.POINTER(sv_gate_t), _i32, _i32, ctypes.POINTER(_vp)],
+    "sv_fuse_gate_list": [_pi32, _pi32, _pd, _i32, _i32, ctypes.POINTER(_vp)],
     "sv_fused_count": [_vp, _pi32],
     "sv_fused_block": [_vp, _i32, _pi32, _pi32, _pd],
     "sv_fused_free": [_vp],
@@ -74,6 +75,11 @@ _SIGS = {
     "sv_sample": [_vp, _pd, _i64, _pi32, _i32, _pu64],
     "sv_copy_to_host": [_vp, _vp, _u64, _u64],
     "sv_copy_from_host": [_vp, _vp, _u64, _u64],
+    "sv_batch_create": [_vp, _i32, _pi32, _pi32, _pi32, _pi32, _pd, _pi32, _pu64, _i32, ctypes.POINTER(_vp)],
+    "sv_batch_state_layout": [_vp, _pu64, _pu64],
+    "sv_batch_info": [_vp, _i32, _pi32, _pi32],
+    "sv_batch_run": [_vp, _vp, _pd, _pd, _pd],
+    "sv_batch_destroy": [_vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_L, _name)
@@ -197,6 +203,38 @@ def sv_fuse_gates(gates, max_fused_qubits: int) -> int:
     f = _vp()
     _check(_L.sv_fuse_gates(arr, len(gates), max_fused_qubits, ctypes.byref(f)))
     return f.value
+
+
+GATE_CODES = {"u3": 0, "h": 1, "x": 2, "y": 3, "z": 4, "cx": 5, "cz": 6, "cp": 7, "swap": 8}
+SV_GATE_ADJOINT = 256
+
+
+def sv_fuse_gate_list(codes, qubits, params, max_fused_qubits: int) -> int:
+    """codes int32[G], qubits int32[G, 2], params float64[G, 3] (see sv.h)."""
+    c = np.ascontiguousarray(codes, dtype=np.int32)
+    q = np.ascontiguousarray(qubits, dtype=np.int32)
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    if q.shape != (c.size, 2) or p.shape != (c.size, 3):
+        raise ValueError("qubits must be [G, 2] and params [G, 3]")
+    f = _vp()
+    _check(_L.sv_fuse_gate_list(c.ctypes.data_as(_pi32), q.ctypes.data_as(_pi32), _dptr(p), c.size,
+                                max_fused_qubits, ctypes.byref(f)))
+    return f.value
+
+
+def gate_list_arrays(gates):
+    """Workload gates (named gates only) -> (codes, qubits, params) arrays."""
+    G = len(gates)
+    codes = np.zeros(G, dtype=np.int32)
+    qubits = np.zeros((G, 2), dtype=np.int32)
+    params = np.zeros((G, 3), dtype=np.float64)
+    for g, (name, qs, ps) in enumerate(gates):
+        adj = name.endswith("_dg")
+        base = name[:-3] if adj else name
+        codes[g] = GATE_CODES[base] | (SV_GATE_ADJOINT if adj else 0)
+        qubits[g, : len(qs)] = qs
+        params[g, : len(ps)] = ps
+    return codes, qubits, params
 
 
 def sv_fused_count(f: int) -> int:
@@ -409,4 +447,123 @@ class Fused:
 
 
 def fuse(gates, max_fused_qubits: int) -> Fused:
-    return Fused(sv_fuse_gates(gate_entries(gates), max_fused_qubits))
+    if any(g[0] in ("mat", "mat_dg") for g in gates):
+        return Fused(sv_fuse_gates(gate_entries(gates), max_fused_qubits))
+    return Fused(sv_fuse_gate_list(*gate_list_arrays(gates), max_fused_qubits))
+
+
+# --------------------------------------------------------------------------
+# batched circuits
+# --------------------------------------------------------------------------
+
+def z_mask(qubits) -> int:
+    """Bit mask of a Z-type Pauli string acting on `qubits`."""
+    m = 0
+    for q in qubits:
+        m |= 1 << int(q)
+    return m
+
+
+def sv_batch_create(h: int, n_qubits, circuits, z_masks, max_fused_qubits: int = 0) -> int:
+    """n_qubits[i], circuits[i] (workload gate list of named gates),
+    z_masks[i] (list of Z-type term masks)."""
+    nc = len(n_qubits)
+    arrays = [gate_list_arrays(g) for g in circuits]
+    goff = np.zeros(nc + 1, dtype=np.int32)
+    goff[1:] = np.cumsum([a[0].size for a in arrays])
+    codes = np.concatenate([a[0] for a in arrays]) if nc else np.zeros(0, np.int32)
+    qubits = np.concatenate([a[1] for a in arrays]) if nc else np.zeros((0, 2), np.int32)
+    params = np.concatenate([a[2] for a in arrays]) if nc else np.zeros((0, 3), np.float64)
+    codes = np.ascontiguousarray(codes, dtype=np.int32)
+    qubits = np.ascontiguousarray(qubits, dtype=np.int32)
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    toff = np.zeros(nc + 1, dtype=np.int32)
+    toff[1:] = np.cumsum([len(z) for z in z_masks])
+    zm = np.ascontiguousarray(np.array([int(m) for z in z_masks for m in z], dtype=np.uint64))
+    if zm.size == 0:
+        zm = np.zeros(1, dtype=np.uint64)
+    nq = np.ascontiguousarray(n_qubits, dtype=np.int32)
+    b = _vp()
+    _check(_L.sv_batch_create(_vp(h), nc, nq.ctypes.data_as(_pi32), goff.ctypes.data_as(_pi32),
+                              codes.ctypes.data_as(_pi32), qubits.ctypes.data_as(_pi32), _dptr(params),
+                              toff.ctypes.data_as(_pi32), zm.ctypes.data_as(_pu64), max_fused_qubits,
+                              ctypes.byref(b)))
+    return b.value
+
+
+def sv_batch_state_layout(b: int, n_circuits: int):
+    total = ctypes.c_uint64()
+    offs = np.zeros(max(1, n_circuits), dtype=np.uint64)
+    _check(_L.sv_batch_state_layout(_vp(b), ctypes.byref(total), offs.ctypes.data_as(_pu64)))
+    return total.value, offs[:n_circuits]
+
+
+def sv_batch_info(b: int, n_qubits: int, n_circuits: int):
+    k = _i32()
+    blocks = np.zeros(max(1, n_circuits), dtype=np.int32)
+    _check(_L.sv_batch_info(_vp(b), n_qubits, ctypes.byref(k), blocks.ctypes.data_as(_pi32)))
+    return k.value, blocks[:n_circuits]
+
+
+def sv_batch_run(b: int, states_ptr: int, n_terms_total: int, n_circuits: int):
+    exp = np.zeros(max(1, n_terms_total), dtype=np.float64)
+    lat = np.zeros(max(1, n_circuits), dtype=np.float64)
+    ks = ctypes.c_double()
+    _check(_L.sv_batch_run(_vp(b), _vp(states_ptr), _dptr(exp), _dptr(lat), ctypes.byref(ks)))
+    return exp[:n_terms_total], lat[:n_circuits], ks.value
+
+
+def sv_batch_destroy(b: int) -> None:
+    _check(_L.sv_batch_destroy(_vp(b)))
+
+
+class Batch:
+    """A batch of complex64 circuits run by one persistent launch; the states
+    live in one torch buffer that libsv borrows."""
+
+    def __init__(self, handle: Handle, n_qubits, circuits, z_masks, max_fused_qubits: int = 0):
+        import torch
+        self.handle = handle
+        self.n_qubits = [int(v) for v in n_qubits]
+        self.z_masks = [list(z) for z in z_masks]
+        self.n_terms = sum(len(z) for z in self.z_masks)
+        self.b = sv_batch_create(handle.h, self.n_qubits, circuits, self.z_masks, max_fused_qubits)
+        total, self.offsets = sv_batch_state_layout(self.b, len(self.n_qubits))
+        with torch.cuda.stream(handle.stream):
+            self.buffer = torch.empty(int(total) // 8 + 32, dtype=torch.complex64, device="cuda")
+        self.base = self.buffer.data_ptr()
+        pad = (-self.base) % 256
+        self.base += pad
+
+    def run(self):
+        """(expectations split per circuit, latencies in s, kernel time in s)"""
+        exp, lat, ks = sv_batch_run(self.b, self.base, self.n_terms, len(self.n_qubits))
+        out, at = [], 0
+        for z in self.z_masks:
+            out.append(exp[at: at + len(z)])
+            at += len(z)
+        return out, lat, ks
+
+    def fusion_width(self, n: int) -> int:
+        return sv_batch_info(self.b, n, len(self.n_qubits))[0]
+
+    def blocks(self):
+        return sv_batch_info(self.b, 0, len(self.n_qubits))[1]
+
+    def state(self, i: int) -> np.ndarray:
+        import torch
+        n = self.n_qubits[i]
+        off = int(self.offsets[i]) // 8 + (self.base - self.buffer.data_ptr()) // 8
+        torch.cuda.synchronize()
+        return self.buffer[off: off + (1 << n)].cpu().numpy()
+
+    def close(self):
+        if self.b:
+            sv_batch_destroy(self.b)
+            self.b = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

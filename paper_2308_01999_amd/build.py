@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsv.so")
 
-SOURCES = ["sv_api.cpp", "sv_fuse.cpp", "sv_apply.hip", "sv_reduce.hip"]
+SOURCES = ["sv_api.cpp", "sv_fuse.cpp", "sv_batch.cpp", "sv_apply.hip", "sv_reduce.hip", "sv_batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -31,7 +31,7 @@ COMMON = [
 
 
 def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    obj = os.path.join(BUILD, src + ".o")
     cmd = [HIPCC, *COMMON]
     if src.endswith(".cpp"):
         cmd += ["-x", "hip"]

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "sv_batch.h"
 #include "sv_internal.h"
 
 namespace sv {
@@ -19,7 +20,16 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+sv_batch_s* batch_create(sv_handle_s* h, int n_circuits, const int32_t* n_qubits, const int32_t* gate_offsets,
+                         const int32_t* codes, const int32_t* qubits, const double* params,
+                         const int32_t* term_offsets, const uint64_t* z_masks, int max_fused_qubits);
+void batch_run(sv_batch_s* b, void* states, double* expect_out, double* latency_s, double* kernel_s);
+void batch_destroy(sv_batch_s* b);
+void batch_layout(sv_batch_s* b, uint64_t* state_bytes, uint64_t* byte_offsets);
+void batch_info(sv_batch_s* b, int n_qubits, int32_t* kmax, int32_t* blocks);
 sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax);
+sv_fused_s* fuse_gate_list(const int32_t* codes, const int32_t* qubits, const double* params, int n_gates,
+                           int kmax);
 void gate_matrix(const char* name, const double* params, int n_params, double* out, int* n_targets,
                  int* n_controls);
 
@@ -318,6 +328,16 @@ sv_status_t sv_fuse_gates(const sv_gate_t* gates, int32_t n_gates, int32_t max_f
     });
 }
 
+sv_status_t sv_fuse_gate_list(const int32_t* codes, const int32_t* qubits, const double* params, int32_t n_gates,
+                              int32_t max_fused_qubits, sv_fused_t* out)
+{
+    return guarded([&] {
+        SV_CHECK(out != nullptr, "out is NULL");
+        *out = nullptr;
+        *out = fuse_gate_list(codes, qubits, params, n_gates, max_fused_qubits);
+    });
+}
+
 sv_status_t sv_fused_count(sv_fused_t f, int32_t* n_blocks)
 {
     return guarded([&] {
@@ -522,6 +542,45 @@ sv_status_t sv_copy_from_host(sv_state_t s, const void* src, uint64_t first, uin
                               s->h->stream));
         SV_HIP(hipStreamSynchronize(s->h->stream));
     });
+}
+
+sv_status_t sv_batch_create(sv_handle_t h, int32_t n_circuits, const int32_t* n_qubits, const int32_t* gate_offsets,
+                            const int32_t* codes, const int32_t* qubits, const double* params,
+                            const int32_t* term_offsets, const uint64_t* z_masks, int32_t max_fused_qubits,
+                            sv_batch_t* out)
+{
+    return guarded([&] {
+        SV_CHECK(out != nullptr, "out is NULL");
+        *out = nullptr;
+        *out = batch_create(h, n_circuits, n_qubits, gate_offsets, codes, qubits, params, term_offsets, z_masks,
+                            max_fused_qubits);
+    });
+}
+
+sv_status_t sv_batch_state_layout(sv_batch_t b, uint64_t* state_bytes, uint64_t* byte_offsets)
+{
+    return guarded([&] {
+        SV_CHECK(b != nullptr && state_bytes != nullptr, "NULL argument");
+        batch_layout(b, state_bytes, byte_offsets);
+    });
+}
+
+sv_status_t sv_batch_info(sv_batch_t b, int32_t n_qubits, int32_t* max_fused_qubits, int32_t* blocks_per_circuit)
+{
+    return guarded([&] {
+        SV_CHECK(b != nullptr && max_fused_qubits != nullptr, "NULL argument");
+        batch_info(b, n_qubits, max_fused_qubits, blocks_per_circuit);
+    });
+}
+
+sv_status_t sv_batch_run(sv_batch_t b, void* states, double* expect_out, double* latency_s, double* kernel_s)
+{
+    return guarded([&] { batch_run(b, states, expect_out, latency_s, kernel_s); });
+}
+
+sv_status_t sv_batch_destroy(sv_batch_t b)
+{
+    return guarded([&] { batch_destroy(b); });
 }
 
 }  // extern "C"

@@ -10,6 +10,8 @@
 // to k = 5 on MI355X and its job is to keep the loads wide and coalesced.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "sv_internal.h"
 
 namespace sv {
@@ -270,6 +272,48 @@ __device__ __forceinline__ uint64_t deposit_bits(uint32_t r, const int32_t* pos,
 constexpr int kTileThreads = 256;
 constexpr int kTileVecs = 8;  // 16-byte vectors per thread per tile (32 KiB / 256 / 16)
 
+#ifndef SV_TILE_NT
+#define SV_TILE_NT 1
+#endif
+#ifndef SV_TILE_WGS_PER_CU
+#define SV_TILE_WGS_PER_CU 32
+#endif
+#ifndef SV_TILES_PER_WG_MAX
+#define SV_TILES_PER_WG_MAX 64
+#endif
+
+typedef float nf4 __attribute__((ext_vector_type(4)));
+typedef double nd2 __attribute__((ext_vector_type(2)));
+
+template <typename V>
+__device__ __forceinline__ V gload(const V* p)
+{
+    if (SV_TILE_NT) {
+        if constexpr (sizeof(V) == 16 && std::is_same<V, float4>::value) {
+            const nf4 v = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(p));
+            return V{v.x, v.y, v.z, v.w};
+        } else {
+            const nd2 v = __builtin_nontemporal_load(reinterpret_cast<const nd2*>(p));
+            return V{v.x, v.y};
+        }
+    }
+    return *p;
+}
+
+template <typename V>
+__device__ __forceinline__ void gstore(V* p, const V v)
+{
+    if (SV_TILE_NT) {
+        if constexpr (std::is_same<V, float4>::value) {
+            __builtin_nontemporal_store(nf4{v.x, v.y, v.z, v.w}, reinterpret_cast<nf4*>(p));
+        } else {
+            __builtin_nontemporal_store(nd2{v.x, v.y}, reinterpret_cast<nd2*>(p));
+        }
+        return;
+    }
+    *p = v;
+}
+
 // The 8 per-thread vectors live in named registers (an array carried across
 // the tile loop would be placed in scratch memory by the compiler).
 #define SV_REP8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
@@ -313,7 +357,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k5(float2* __restrict
     SV_REP8(SV_DECL)
 #undef SV_DECL
     uint64_t base = tile_base(t0, a);
-#define SV_LOAD(u) buf##u = *reinterpret_cast<const float4*>(psi + base + goff[u]);
+#define SV_LOAD(u) buf##u = gload(reinterpret_cast<const float4*>(psi + base + goff[u]));
     SV_REP8(SV_LOAD)
 #undef SV_LOAD
     for (uint64_t t = t0; t < t1; ++t) {
@@ -324,7 +368,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k5(float2* __restrict
         uint64_t nbase = 0;
         if (t + 1 < t1) {
             nbase = tile_base(t + 1, a);
-#define SV_PREFETCH(u) buf##u = *reinterpret_cast<const float4*>(psi + nbase + goff[u]);
+#define SV_PREFETCH(u) buf##u = gload(reinterpret_cast<const float4*>(psi + nbase + goff[u]));
             SV_REP8(SV_PREFETCH)
 #undef SV_PREFETCH
         }
@@ -339,7 +383,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k5(float2* __restrict
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kTileVecs; ++u)
-            *reinterpret_cast<float4*>(psi + base + goff[u]) = lds[u * kTileThreads + tid];
+            gstore(reinterpret_cast<float4*>(psi + base + goff[u]), lds[u * kTileThreads + tid]);
         base = nbase;
         __syncthreads();
     }
@@ -368,7 +412,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict
     SV_REP8(SV_DECL)
 #undef SV_DECL
     uint64_t base = tile_base(t0, a);
-#define SV_LOAD(u) buf##u = *reinterpret_cast<const float4*>(psi + base + goff[u]);
+#define SV_LOAD(u) buf##u = gload(reinterpret_cast<const float4*>(psi + base + goff[u]));
     SV_REP8(SV_LOAD)
 #undef SV_LOAD
     for (uint64_t t = t0; t < t1; ++t) {
@@ -379,7 +423,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict
         uint64_t nbase = 0;
         if (t + 1 < t1) {
             nbase = tile_base(t + 1, a);
-#define SV_PREFETCH(u) buf##u = *reinterpret_cast<const float4*>(psi + nbase + goff[u]);
+#define SV_PREFETCH(u) buf##u = gload(reinterpret_cast<const float4*>(psi + nbase + goff[u]));
             SV_REP8(SV_PREFETCH)
 #undef SV_PREFETCH
         }
@@ -397,7 +441,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kTileVecs; ++u)
-            *reinterpret_cast<float4*>(psi + base + goff[u]) = lds[u * kTileThreads + tid];
+            gstore(reinterpret_cast<float4*>(psi + base + goff[u]), lds[u * kTileThreads + tid]);
         base = nbase;
         __syncthreads();
     }
@@ -432,7 +476,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restri
     SV_REP8(SV_DECL)
 #undef SV_DECL
     uint64_t base = tile_base(t0, a);
-#define SV_LOAD(u) buf##u = psi[base + goff[u]];
+#define SV_LOAD(u) buf##u = gload(psi + base + goff[u]);
     SV_REP8(SV_LOAD)
 #undef SV_LOAD
     for (uint64_t t = t0; t < t1; ++t) {
@@ -443,7 +487,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restri
         uint64_t nbase = 0;
         if (t + 1 < t1) {
             nbase = tile_base(t + 1, a);
-#define SV_PREFETCH(u) buf##u = psi[nbase + goff[u]];
+#define SV_PREFETCH(u) buf##u = gload(psi + nbase + goff[u]);
             SV_REP8(SV_PREFETCH)
 #undef SV_PREFETCH
         }
@@ -465,7 +509,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restri
         }
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < kTileVecs; ++u) psi[base + goff[u]] = lds[u * kTileThreads + tid];
+        for (int u = 0; u < kTileVecs; ++u) gstore(psi + base + goff[u], lds[u * kTileThreads + tid]);
         base = nbase;
         __syncthreads();
     }
@@ -618,10 +662,10 @@ TileArgs make_tile_args(const GateDesc& d, int n, int tb, int cu_count)
     }
     t.n_tiles = uint64_t(1) << (n - tb);
     // about 32 workgroups per CU over the sweep, each on consecutive tiles
-    const uint64_t target_wgs = uint64_t(cu_count) * 32;
+    const uint64_t target_wgs = uint64_t(cu_count) * SV_TILE_WGS_PER_CU;
     uint64_t per = t.n_tiles / target_wgs;
     if (per < 1) per = 1;
-    if (per > 64) per = 64;
+    if (per > SV_TILES_PER_WG_MAX) per = SV_TILES_PER_WG_MAX;
     t.tiles_per_wg = per;
     return t;
 }

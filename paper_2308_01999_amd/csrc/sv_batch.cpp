@@ -1,0 +1,500 @@
+// Host side of the batched path: fuses every circuit of a batch (in
+// parallel host threads), chooses the fusion width per qubit count (fixed,
+// or measured by the autotuner), lays out the states, packs block
+// descriptors and matrices, uploads them once, and runs the persistent batch
+// kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "sv_batch.h"
+
+namespace sv {
+
+sv_fused_s* fuse_gate_list(const int32_t* codes, const int32_t* qubits, const double* params, int n_gates,
+                           int kmax);
+
+struct BatchHost {
+    std::vector<BatchCircuit> circuits;
+    std::vector<uint32_t> order;
+    std::vector<BatchBlock> blocks;
+    std::vector<float> mats;
+    std::vector<uint64_t> z_masks;
+    uint64_t state_amps = 0;
+};
+
+}  // namespace sv
+
+struct sv_batch_s {
+    sv_handle_s* h = nullptr;
+    int n_circuits = 0;
+    int total_terms = 0;
+    std::vector<int> n;
+    std::vector<uint64_t> state_off;  // amplitudes
+    uint64_t state_amps = 0;
+    std::map<int, int> kmax_for_n;
+    std::vector<int> blocks_per_circuit;
+    char* dev = nullptr;  // one arena for all device-side descriptors
+    sv::BatchArgs args{};
+    double tick_hz = 1e8;
+};
+
+namespace sv {
+namespace {
+
+// Region geometry of a block with sorted targets tq on n qubits: the whole
+// state when n <= 12, else a 4096-amplitude tile.
+void block_geometry(BatchBlock& b, const int* tq, int k, int n)
+{
+    b.k = k;
+    int L;
+    if (n <= 12) {
+        L = n;
+    } else {
+        const int gbits = 12 - k;
+        L = gbits;
+        for (;;) {
+            int klo = 0;
+            for (int a = 0; a < k; ++a) klo += tq[a] < L;
+            if (L - klo >= gbits) break;
+            ++L;
+        }
+    }
+    b.L = L;
+    int nh = 0, nl = 0;
+    int hi[8], lo[8];
+    for (int a = 0; a < k; ++a) {
+        if (tq[a] < L)
+            lo[nl++] = tq[a];
+        else
+            hi[nh++] = tq[a];
+    }
+    b.n_hi = nh;
+    b.n_lo = nl;
+    for (int j = 0; j < 8; ++j) {
+        b.hi_pos[j] = int8_t(j < nh ? hi[j] : 0);
+        b.lo_pos[j] = int8_t(j < nl ? lo[j] : 0);
+    }
+    for (int c = 0; c < 32; ++c) {
+        if (c >= (1 << k)) {
+            b.lds_off[c] = 0;
+            continue;
+        }
+        int run = 0, low = 0;
+        for (int a = 0; a < k; ++a) {
+            if (!((c >> a) & 1)) continue;
+            if (tq[a] < L) {
+                low |= 1 << tq[a];
+            } else {
+                int rank = 0;
+                while (hi[rank] != tq[a]) ++rank;
+                run |= 1 << rank;
+            }
+        }
+        b.lds_off[c] = int16_t((run << L) + low);
+    }
+}
+
+// Packs block matrix m (complex128, row-major, 2^k x 2^k) for the batch
+// kernel: the per-lane A-operand layout of the matrix-core path for k = 4,
+// 5, plain complex64 for k <= 3.  Returns the number of floats appended.
+size_t pack_batch_matrix(const double* m, int k, std::vector<float>& out)
+{
+    const int d = 1 << k;
+    auto A = [&](int g, int i, int c) {
+        const double re = m[2 * (i * d + c)], im = m[2 * (i * d + c) + 1];
+        return float(g == 0 ? re : g == 1 ? im : re + im);
+    };
+    const size_t start = out.size();
+    if (k == 5) {
+        for (int g = 0; g < 3; ++g)
+            for (int l = 0; l < 64; ++l)
+                for (int j = 0; j < 16; ++j) out.push_back(A(g, l & 31, 2 * j + (l >> 5)));
+    } else if (k == 4) {
+        for (int g = 0; g < 3; ++g)
+            for (int l = 0; l < 64; ++l)
+                for (int s4 = 0; s4 < 4; ++s4) out.push_back(A(g, l & 15, 4 * s4 + (l >> 4)));
+    } else {
+        for (int e = 0; e < d * d; ++e) {
+            out.push_back(float(m[2 * e]));
+            out.push_back(float(m[2 * e + 1]));
+        }
+    }
+    while (out.size() % 4) out.push_back(0.f);  // keep 16-byte alignment
+    return out.size() - start;
+}
+
+struct CircuitInput {
+    int n;
+    const int32_t* codes;
+    const int32_t* qubits;
+    const double* params;
+    int n_gates;
+};
+
+// Fuses all circuits with the given per-circuit widths on host threads.
+std::vector<sv_fused_s*> fuse_all(const std::vector<CircuitInput>& in, const std::vector<int>& kmax)
+{
+    std::vector<sv_fused_s*> out(in.size(), nullptr);
+    std::atomic<size_t> next{0};
+    std::mutex err_mu;
+    std::string err;
+    sv_status_t err_status = SV_OK;
+    unsigned nt = std::thread::hardware_concurrency();
+    if (nt == 0) nt = 4;
+    nt = std::min<unsigned>(nt, 16);
+    auto work = [&] {
+        for (;;) {
+            const size_t i = next.fetch_add(1);
+            if (i >= in.size()) return;
+            try {
+                out[i] = fuse_gate_list(in[i].codes, in[i].qubits, in[i].params, in[i].n_gates, kmax[i]);
+            } catch (const Error& e) {
+                std::lock_guard<std::mutex> g(err_mu);
+                if (err.empty()) {
+                    err = "circuit " + std::to_string(i) + ": " + e.msg;
+                    err_status = e.status;
+                }
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t) th.emplace_back(work);
+    for (auto& t : th) t.join();
+    if (!err.empty()) {
+        for (auto* f : out) {
+            if (f) {
+                delete[] f->blocks;
+                delete[] f->storage;
+                delete f;
+            }
+        }
+        throw Error{err_status, err};
+    }
+    return out;
+}
+
+void free_fused(sv_fused_s* f)
+{
+    if (!f) return;
+    delete[] f->blocks;
+    delete[] f->storage;
+    delete f;
+}
+
+// Builds the device-side descriptors for circuits `sel` with widths kmax.
+BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>& sel,
+                     const std::vector<int>& kmax, const std::vector<int>& term0, const std::vector<int>& nterms,
+                     const uint64_t* z_masks, std::vector<int>* blocks_out)
+{
+    std::vector<CircuitInput> sub;
+    std::vector<int> ks;
+    for (int i : sel) {
+        sub.push_back(in[i]);
+        ks.push_back(kmax[i]);
+    }
+    auto fused = fuse_all(sub, ks);
+    BatchHost H;
+    H.circuits.resize(sel.size());
+    uint64_t off = 0;
+    for (size_t j = 0; j < sel.size(); ++j) {
+        const int i = sel[j];
+        BatchCircuit& c = H.circuits[j];
+        c.n = in[i].n;
+        c.block0 = uint32_t(H.blocks.size());
+        c.n_blocks = uint32_t(fused[j]->n_blocks);
+        c.term0 = uint32_t(H.z_masks.size());
+        c.n_terms = uint32_t(nterms[i]);
+        for (int t = 0; t < nterms[i]; ++t) H.z_masks.push_back(z_masks[term0[i] + t]);
+        c.state_off = off;
+        off += std::max<uint64_t>(uint64_t(1) << c.n, 32);  // 256-byte aligned starts
+        for (int bidx = 0; bidx < fused[j]->n_blocks; ++bidx) {
+            const FusedBlock& fb = fused[j]->blocks[bidx];
+            BatchBlock b{};
+            block_geometry(b, fb.targets, fb.k, c.n);
+            b.mat_off = uint32_t(H.mats.size());
+            pack_batch_matrix(fb.m, fb.k, H.mats);
+            H.blocks.push_back(b);
+        }
+        if (blocks_out) (*blocks_out)[i] = fused[j]->n_blocks;
+    }
+    H.state_amps = off;
+    for (auto* f : fused) free_fused(f);
+    // largest work first
+    H.order.resize(sel.size());
+    std::iota(H.order.begin(), H.order.end(), 0u);
+    std::stable_sort(H.order.begin(), H.order.end(), [&](uint32_t a, uint32_t b) {
+        const double wa = double(uint64_t(1) << H.circuits[a].n) * (H.circuits[a].n_blocks + 1);
+        const double wb = double(uint64_t(1) << H.circuits[b].n) * (H.circuits[b].n_blocks + 1);
+        return wa > wb;
+    });
+    return H;
+}
+
+template <typename T>
+size_t align_up(size_t v)
+{
+    return (v + 255) & ~size_t(255);
+}
+
+// Uploads H into one device arena and fills args (states excluded).
+char* upload(const BatchHost& H, BatchArgs& a, hipStream_t stream)
+{
+    const size_t s_c = align_up<int>(H.circuits.size() * sizeof(BatchCircuit));
+    const size_t s_o = align_up<int>(H.order.size() * sizeof(uint32_t));
+    const size_t s_b = align_up<int>(std::max<size_t>(1, H.blocks.size()) * sizeof(BatchBlock));
+    const size_t s_m = align_up<int>(std::max<size_t>(1, H.mats.size()) * sizeof(float));
+    const size_t s_z = align_up<int>(std::max<size_t>(1, H.z_masks.size()) * sizeof(uint64_t));
+    const size_t s_e = align_up<int>(std::max<size_t>(1, H.z_masks.size()) * sizeof(double));
+    const size_t s_t = align_up<int>(H.circuits.size() * sizeof(uint64_t));
+    const size_t total = s_c + s_o + s_b + s_m + s_z + s_e + s_t + 256 + 256;
+    char* dev = nullptr;
+    SV_HIP(hipMalloc(&dev, total));
+    char* p = dev;
+    auto put = [&](const void* src, size_t bytes, size_t room) {
+        char* d = p;
+        if (bytes) {
+            const hipError_t e = hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, stream);
+            if (e != hipSuccess) {
+                (void)hipFree(dev);
+                throw Error{SV_ERR_DEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e)};
+            }
+        }
+        p += room;
+        return d;
+    };
+    a.circuits = reinterpret_cast<const BatchCircuit*>(put(H.circuits.data(), H.circuits.size() * sizeof(BatchCircuit), s_c));
+    a.order = reinterpret_cast<const uint32_t*>(put(H.order.data(), H.order.size() * sizeof(uint32_t), s_o));
+    a.blocks = reinterpret_cast<const BatchBlock*>(put(H.blocks.data(), H.blocks.size() * sizeof(BatchBlock), s_b));
+    a.mats = reinterpret_cast<const float*>(put(H.mats.data(), H.mats.size() * sizeof(float), s_m));
+    a.z_masks = reinterpret_cast<const uint64_t*>(put(H.z_masks.data(), H.z_masks.size() * sizeof(uint64_t), s_z));
+    a.expect = reinterpret_cast<double*>(put(nullptr, 0, s_e));
+    a.t_done = reinterpret_cast<uint64_t*>(put(nullptr, 0, s_t));
+    a.t_start = reinterpret_cast<uint64_t*>(put(nullptr, 0, 256));
+    a.queue = reinterpret_cast<uint32_t*>(put(nullptr, 0, 256));
+    a.n_circuits = uint32_t(H.circuits.size());
+    const hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        throw Error{SV_ERR_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e)};
+    }
+    return dev;
+}
+
+// Autotuner: for each qubit count, time the batch kernel on (up to 64)
+// circuits of that size fused at each candidate width, on scratch states,
+// and keep the fastest width.  Results are cached per process.
+std::mutex g_tune_mu;
+std::map<int, int> g_tuned;  // n -> kmax
+
+int tune_width(sv_handle_s* h, const std::vector<CircuitInput>& in, const std::vector<int>& idx, int n,
+               const std::vector<int>& term0, const std::vector<int>& nterms, const uint64_t* z_masks)
+{
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tuned.find(n);
+        if (it != g_tuned.end()) return it->second;
+    }
+    std::vector<int> sel;
+    for (int i : idx)
+        if (int(sel.size()) < 64) sel.push_back(i);
+    // replicate so that the sample fills the device
+    const size_t want = std::max<size_t>(sel.size(), size_t(h->cu_count) * 2);
+    std::vector<int> sample;
+    while (sample.size() < want) sample.push_back(sel[sample.size() % sel.size()]);
+    float best_ms = 1e30f;
+    int best_k = std::min(5, n);
+    hipEvent_t e0, e1;
+    SV_HIP(hipEventCreate(&e0));
+    SV_HIP(hipEventCreate(&e1));
+    for (int k = 3; k <= std::min(5, n); ++k) {
+        std::vector<int> km(in.size(), k);
+        BatchHost H = build_host(in, sample, km, term0, nterms, z_masks, nullptr);
+        BatchArgs a{};
+        char* dev = upload(H, a, h->stream);
+        void* states = nullptr;
+        hipError_t e = hipMalloc(&states, H.state_amps * sizeof(float) * 2);
+        if (e != hipSuccess) {
+            (void)hipFree(dev);
+            break;
+        }
+        a.states = states;
+        float ms = 0.f;
+        try {
+            launch_batch_reset(h->stream, a);
+            launch_batch(h->stream, h->cu_count, a);  // warm-up
+            launch_batch_reset(h->stream, a);
+            SV_HIP(hipEventRecord(e0, h->stream));
+            launch_batch(h->stream, h->cu_count, a);
+            SV_HIP(hipEventRecord(e1, h->stream));
+            SV_HIP(hipEventSynchronize(e1));
+            SV_HIP(hipEventElapsedTime(&ms, e0, e1));
+        } catch (...) {
+            (void)hipFree(states);
+            (void)hipFree(dev);
+            throw;
+        }
+        (void)hipFree(states);
+        (void)hipFree(dev);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_k = k;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tuned[n] = best_k;
+    return best_k;
+}
+
+}  // namespace
+}  // namespace sv
+
+using namespace sv;
+
+namespace sv {
+
+sv_batch_s* batch_create(sv_handle_s* h, int n_circuits, const int32_t* n_qubits, const int32_t* gate_offsets,
+                         const int32_t* codes, const int32_t* qubits, const double* params,
+                         const int32_t* term_offsets, const uint64_t* z_masks, int max_fused_qubits)
+{
+    SV_CHECK(h != nullptr, "handle is NULL");
+    SV_CHECK(n_circuits >= 1, "n_circuits must be positive");
+    SV_CHECK(n_qubits && gate_offsets && term_offsets, "NULL batch arrays");
+    SV_CHECK(max_fused_qubits >= 0 && max_fused_qubits <= kBatchMaxK, "max_fused_qubits must be in [0, 5]");
+    const int total_gates = gate_offsets[n_circuits];
+    const int total_terms = term_offsets[n_circuits];
+    SV_CHECK(gate_offsets[0] == 0 && term_offsets[0] == 0, "offsets must start at 0");
+    SV_CHECK(total_gates == 0 || (codes && qubits && params), "NULL gate arrays");
+    SV_CHECK(total_terms == 0 || z_masks, "NULL z_masks");
+    std::vector<CircuitInput> in(n_circuits);
+    std::vector<int> term0(n_circuits), nterms(n_circuits);
+    for (int i = 0; i < n_circuits; ++i) {
+        const int n = n_qubits[i];
+        SV_CHECK(n >= 1 && n <= kBatchMaxQubits, "batch circuits must have 1..30 qubits");
+        SV_CHECK(gate_offsets[i + 1] >= gate_offsets[i], "gate offsets must not decrease");
+        SV_CHECK(term_offsets[i + 1] >= term_offsets[i], "term offsets must not decrease");
+        const int nt = term_offsets[i + 1] - term_offsets[i];
+        SV_CHECK(nt <= kBatchMaxTerms, "at most 32 Z-type terms per circuit");
+        for (int t = 0; t < nt; ++t)
+            SV_CHECK(n == 64 || (z_masks[term_offsets[i] + t] >> n) == 0, "Z mask names a qubit outside the circuit");
+        in[i] = {n, codes + gate_offsets[i], qubits + 2 * size_t(gate_offsets[i]), params + 3 * size_t(gate_offsets[i]),
+                 gate_offsets[i + 1] - gate_offsets[i]};
+        for (int g = 0; g < in[i].n_gates; ++g) {
+            const int code = in[i].codes[g] & ~int(SV_GATE_ADJOINT);
+            const int q0 = in[i].qubits[2 * g], q1 = in[i].qubits[2 * g + 1];
+            const bool two = code == SV_GATE_CX || code == SV_GATE_CZ || code == SV_GATE_CP || code == SV_GATE_SWAP;
+            SV_CHECK(q0 >= 0 && q0 < n && (!two || (q1 >= 0 && q1 < n && q1 != q0)),
+                     "circuit " + std::to_string(i) + ": gate qubit out of range");
+        }
+        term0[i] = term_offsets[i];
+        nterms[i] = nt;
+    }
+    // fusion width per qubit count
+    std::map<int, std::vector<int>> by_n;
+    for (int i = 0; i < n_circuits; ++i) by_n[n_qubits[i]].push_back(i);
+    auto* b = new sv_batch_s;
+    try {
+        b->h = h;
+        b->n_circuits = n_circuits;
+        b->total_terms = total_terms;
+        b->n.assign(n_qubits, n_qubits + n_circuits);
+        std::vector<int> kmax(n_circuits);
+        for (auto& kv : by_n) {
+            const int k = max_fused_qubits > 0 ? std::min(max_fused_qubits, kv.first)
+                                               : tune_width(h, in, kv.second, kv.first, term0, nterms, z_masks);
+            b->kmax_for_n[kv.first] = k;
+            for (int i : kv.second) kmax[i] = k;
+        }
+        std::vector<int> all(n_circuits);
+        std::iota(all.begin(), all.end(), 0);
+        b->blocks_per_circuit.assign(n_circuits, 0);
+        BatchHost H = build_host(in, all, kmax, term0, nterms, z_masks, &b->blocks_per_circuit);
+        b->state_off.resize(n_circuits);
+        for (int i = 0; i < n_circuits; ++i) b->state_off[i] = H.circuits[i].state_off;
+        b->state_amps = H.state_amps;
+        b->dev = upload(H, b->args, h->stream);
+        int khz = 0;
+        SV_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device));
+        b->tick_hz = khz > 0 ? double(khz) * 1e3 : 1e8;
+    } catch (...) {
+        delete b;
+        throw;
+    }
+    return b;
+}
+
+void batch_run(sv_batch_s* b, void* states, double* expect_out, double* latency_s, double* kernel_s)
+{
+    SV_CHECK(b != nullptr, "batch is NULL");
+    SV_CHECK(states != nullptr && (reinterpret_cast<uintptr_t>(states) & 255) == 0,
+             "states must be a 256-byte aligned device buffer");
+    sv_handle_s* h = b->h;
+    b->args.states = states;
+    hipEvent_t e0, e1;
+    SV_HIP(hipEventCreate(&e0));
+    SV_HIP(hipEventCreate(&e1));
+    float ms = 0.f;
+    std::vector<uint64_t> done(b->n_circuits);
+    uint64_t t0 = 0;
+    try {
+        launch_batch_reset(h->stream, b->args);
+        SV_HIP(hipEventRecord(e0, h->stream));
+        launch_batch(h->stream, h->cu_count, b->args);
+        SV_HIP(hipEventRecord(e1, h->stream));
+        if (expect_out && b->total_terms > 0)
+            SV_HIP(hipMemcpyAsync(expect_out, b->args.expect, sizeof(double) * b->total_terms,
+                                  hipMemcpyDeviceToHost, h->stream));
+        SV_HIP(hipMemcpyAsync(done.data(), b->args.t_done, sizeof(uint64_t) * b->n_circuits, hipMemcpyDeviceToHost,
+                              h->stream));
+        SV_HIP(hipMemcpyAsync(&t0, b->args.t_start, sizeof(uint64_t), hipMemcpyDeviceToHost, h->stream));
+        SV_HIP(hipStreamSynchronize(h->stream));
+        SV_HIP(hipEventElapsedTime(&ms, e0, e1));
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (latency_s)
+        for (int i = 0; i < b->n_circuits; ++i) latency_s[i] = double(done[i] - t0) / b->tick_hz;
+    if (kernel_s) *kernel_s = double(ms) * 1e-3;
+}
+
+void batch_layout(sv_batch_s* b, uint64_t* state_bytes, uint64_t* byte_offsets)
+{
+    *state_bytes = b->state_amps * 8;
+    if (byte_offsets)
+        for (int i = 0; i < b->n_circuits; ++i) byte_offsets[i] = b->state_off[i] * 8;
+}
+
+void batch_info(sv_batch_s* b, int n_qubits, int32_t* kmax, int32_t* blocks)
+{
+    auto it = b->kmax_for_n.find(n_qubits);
+    *kmax = it == b->kmax_for_n.end() ? 0 : it->second;
+    if (blocks)
+        for (int i = 0; i < b->n_circuits; ++i) blocks[i] = b->blocks_per_circuit[i];
+}
+
+void batch_destroy(sv_batch_s* b)
+{
+    if (!b) return;
+    if (b->dev) {
+        (void)hipStreamSynchronize(b->h->stream);
+        (void)hipFree(b->dev);
+    }
+    delete b;
+}
+
+}  // namespace sv

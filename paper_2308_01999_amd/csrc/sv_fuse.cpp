@@ -107,9 +107,11 @@ struct HostGate {
 };
 
 // U <- G * U where G acts on positions pos_t (matrix bit order) with
-// controls at positions pos_c having values cv; U is 2^m x 2^m row-major.
-// Each column of U is updated like a state of m qubits.
-void left_multiply(std::vector<cd>& U, int m, const HostGate& g, const std::vector<int>& pos_t,
+// controls at positions pos_c having values cv; U is 2^m x 2^m row-major,
+// interleaved (re, im).  Each column of U is updated like a state of m
+// qubits.  Plain real arithmetic: std::complex products would go through
+// the C99 special-value path.
+void left_multiply(std::vector<double>& U, int m, const HostGate& g, const std::vector<int>& pos_t,
                    const std::vector<int>& pos_c)
 {
     const int k = int(pos_t.size());
@@ -121,22 +123,38 @@ void left_multiply(std::vector<cd>& U, int m, const HostGate& g, const std::vect
         cmask |= uint64_t(1) << pos_c[a];
         if (g.cvals[a]) cset |= uint64_t(1) << pos_c[a];
     }
-    std::vector<uint64_t> off(d);
+    uint64_t off[1 << SV_MAX_TARGETS];
     for (int r = 0; r < d; ++r) {
         uint64_t o = 0;
         for (int a = 0; a < k; ++a)
             if ((r >> a) & 1) o |= uint64_t(1) << pos_t[a];
         off[r] = o;
     }
-    std::vector<cd> v(d);
-    for (uint64_t col = 0; col < dim; ++col) {
-        for (uint64_t row = 0; row < dim; ++row) {
-            if ((row & tmask) || (row & cmask) != cset) continue;
-            for (int c = 0; c < d; ++c) v[c] = U[(row + off[c]) * dim + col];
-            for (int r = 0; r < d; ++r) {
-                cd acc = 0;
-                for (int c = 0; c < d; ++c) acc += g.m[r * d + c] * v[c];
-                U[(row + off[r]) * dim + col] = acc;
+    std::vector<double> gm(2 * size_t(d) * d);
+    for (size_t e = 0; e < size_t(d) * d; ++e) {
+        gm[2 * e] = g.m[e].real();
+        gm[2 * e + 1] = g.m[e].imag();
+    }
+    // Row-oriented: the 2^k rows of a group are combined element by element
+    // along the (contiguous) columns.
+    const size_t rowlen = 2 * dim;
+    std::vector<double> in(size_t(d) * rowlen);
+    for (uint64_t row = 0; row < dim; ++row) {
+        if ((row & tmask) || (row & cmask) != cset) continue;
+        for (int c = 0; c < d; ++c)
+            std::memcpy(&in[c * rowlen], &U[(row + off[c]) * rowlen], sizeof(double) * rowlen);
+        for (int r = 0; r < d; ++r) {
+            double* out = &U[(row + off[r]) * rowlen];
+            for (size_t e = 0; e < rowlen; ++e) out[e] = 0.0;
+            for (int c = 0; c < d; ++c) {
+                const double mr = gm[2 * (size_t(r) * d + c)], mi = gm[2 * (size_t(r) * d + c) + 1];
+                if (mr == 0.0 && mi == 0.0) continue;
+                const double* x = &in[c * rowlen];
+                for (uint64_t col = 0; col < dim; ++col) {
+                    const double xr = x[2 * col], xi = x[2 * col + 1];
+                    out[2 * col] += mr * xr - mi * xi;
+                    out[2 * col + 1] += mr * xi + mi * xr;
+                }
             }
         }
     }
@@ -154,59 +172,111 @@ int popcount64(uint64_t v) { return __builtin_popcountll(v); }
 // Taken gates never depend on a skipped gate, so the block can be emitted
 // before all remaining gates.  The candidate that absorbs the most gates
 // becomes the next block.
-std::vector<std::vector<int>> select_blocks(const std::vector<HostGate>& gates, int n_qubits_hint, int kmax)
+std::vector<std::vector<int>> select_blocks(const std::vector<HostGate>& gates, int kmax)
 {
-    (void)n_qubits_hint;
-    const int G = int(gates.size());
-    std::vector<char> done(G, 0);
+    // live: remaining gates in circuit order, as (index, qubit mask)
+    std::vector<int> live(gates.size());
+    std::vector<uint64_t> mask(gates.size());
+    for (size_t i = 0; i < gates.size(); ++i) {
+        live[i] = int(i);
+        mask[i] = gates[i].qmask;
+    }
     std::vector<std::vector<int>> blocks;
-    int remaining = G;
-    int first_live = 0;
-    std::vector<int> taken, best_taken;
-    while (remaining > 0) {
-        while (first_live < G && done[first_live]) ++first_live;
+    std::vector<int> ready;
+    std::vector<char> take;
+    // grows the block seeded by live[seed_pos]; returns the number of gates
+    // it absorbs and, if `mark`, flags them in `take`
+    auto grow = [&](size_t seed_pos, bool mark) {
+        uint64_t S = mask[seed_pos];
+        const int cap = std::max(kmax, popcount64(S));
+        uint64_t blocked = 0;
+        int count = 0;
+        for (size_t j = 0; j < live.size(); ++j) {
+            const uint64_t Q = mask[j];
+            if ((Q & blocked) == 0 && popcount64(S | Q) <= cap) {
+                S |= Q;
+                ++count;
+                if (mark) take[j] = 1;
+            } else {
+                blocked |= Q;
+            }
+            // nothing more can join once every qubit of S is blocked and S
+            // cannot grow
+            if ((S & ~blocked) == 0 && popcount64(S) >= cap) break;
+        }
+        return count;
+    };
+    while (!live.empty()) {
         // ready gates: first remaining gate on each of their qubits
-        std::vector<int> ready;
+        ready.clear();
         uint64_t seen = 0;
-        for (int i = first_live; i < G; ++i) {
-            if (done[i]) continue;
-            if ((gates[i].qmask & seen) == 0) ready.push_back(i);
-            seen |= gates[i].qmask;
+        for (size_t j = 0; j < live.size(); ++j) {
+            if ((mask[j] & seen) == 0) ready.push_back(int(j));
+            seen |= mask[j];
         }
-        int best_score = -1;
-        for (int seed : ready) {
-            uint64_t S = gates[seed].qmask;
-            const int cap = std::max(kmax, popcount64(S));
-            uint64_t blocked = 0;
-            taken.clear();
-            for (int i = first_live; i < G; ++i) {
-                if (done[i]) continue;
-                const uint64_t Q = gates[i].qmask;
-                if (Q & blocked) {
-                    blocked |= Q;
-                } else if (popcount64(S | Q) <= cap) {
-                    S |= Q;
-                    taken.push_back(i);
-                } else {
-                    blocked |= Q;
-                }
-                // nothing more can join once every qubit of S is blocked and
-                // S cannot grow
-                if ((S & ~blocked) == 0 && popcount64(S) >= cap) break;
-            }
-            if (int(taken.size()) > best_score) {
-                best_score = int(taken.size());
-                best_taken = taken;
+        int best = -1, best_count = -1;
+        for (int pos : ready) {
+            const int c = grow(size_t(pos), false);
+            if (c > best_count) {
+                best_count = c;
+                best = pos;
             }
         }
-        for (int i : best_taken) done[i] = 1;
-        remaining -= int(best_taken.size());
-        blocks.push_back(best_taken);
+        take.assign(live.size(), 0);
+        grow(size_t(best), true);
+        std::vector<int> blk;
+        size_t w = 0;
+        for (size_t j = 0; j < live.size(); ++j) {
+            if (take[j]) {
+                blk.push_back(live[j]);
+            } else {
+                live[w] = live[j];
+                mask[w] = mask[j];
+                ++w;
+            }
+        }
+        live.resize(w);
+        mask.resize(w);
+        blocks.push_back(std::move(blk));
     }
     return blocks;
 }
 
 }  // namespace
+
+sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax);
+
+sv_fused_s* fuse_gate_list(const int32_t* codes, const int32_t* qubits, const double* params, int n_gates,
+                           int kmax)
+{
+    SV_CHECK(n_gates >= 0, "n_gates is negative");
+    SV_CHECK(n_gates == 0 || (codes && qubits && params), "NULL gate arrays");
+    static const char* kNames[] = {"u3", "h", "x", "y", "z", "cx", "cz", "cp", "swap"};
+    std::vector<sv_gate_t> gates(n_gates);
+    std::vector<double> mats(size_t(n_gates) * 32);
+    std::vector<int32_t> qs(size_t(n_gates) * 2);
+    for (int g = 0; g < n_gates; ++g) {
+        const int code = codes[g] & ~int(SV_GATE_ADJOINT);
+        const bool adj = (codes[g] & SV_GATE_ADJOINT) != 0;
+        SV_CHECK(code >= SV_GATE_U3 && code <= SV_GATE_SWAP, "gate " + std::to_string(g) + ": unknown code");
+        std::string name = kNames[code];
+        if (adj) name += "_dg";
+        const int np = code == SV_GATE_U3 ? 3 : code == SV_GATE_CP ? 1 : 0;
+        int nt = 0, nc = 0;
+        gate_matrix(name.c_str(), params + 3 * size_t(g), np, &mats[size_t(g) * 32], &nt, &nc);
+        // qubit order: controls first, then targets
+        qs[2 * g] = qubits[2 * g];
+        qs[2 * g + 1] = qubits[2 * g + 1];
+        sv_gate_t& e = gates[g];
+        e.n_controls = nc;
+        e.controls = nc ? &qs[2 * g] : nullptr;
+        e.control_values = nullptr;
+        e.n_targets = nt;
+        e.targets = &qs[2 * g + nc];
+        e.matrix = &mats[size_t(g) * 32];
+    }
+    return fuse(gates.data(), n_gates, kmax);
+}
 
 sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax)
 {
@@ -245,7 +315,7 @@ sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax)
                      "gate " + std::to_string(i) + ": matrix entry is not finite");
         }
     }
-    const auto sel = select_blocks(hg, 64, kmax);
+    const auto sel = select_blocks(hg, kmax);
     // build matrices
     std::vector<std::vector<int>> qs(sel.size());
     size_t total = 0;
@@ -265,8 +335,8 @@ sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax)
     for (size_t b = 0; b < sel.size(); ++b) {
         const int m = int(qs[b].size());
         const uint64_t dim = uint64_t(1) << m;
-        std::vector<cd> U(dim * dim, cd(0.0));
-        for (uint64_t i = 0; i < dim; ++i) U[i * dim + i] = 1.0;
+        std::vector<double> U(2 * dim * dim, 0.0);
+        for (uint64_t i = 0; i < dim; ++i) U[2 * (i * dim + i)] = 1.0;
         for (int gi : sel[b]) {
             const HostGate& g = hg[gi];
             auto pos = [&](int q) { return int(std::lower_bound(qs[b].begin(), qs[b].end(), q) - qs[b].begin()); };
@@ -279,10 +349,7 @@ sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax)
         blk.k = m;
         for (int a = 0; a < m; ++a) blk.targets[a] = qs[b][a];
         blk.m = f->storage + 2 * at;
-        for (uint64_t e = 0; e < dim * dim; ++e) {
-            blk.m[2 * e] = U[e].real();
-            blk.m[2 * e + 1] = U[e].imag();
-        }
+        std::memcpy(blk.m, U.data(), sizeof(double) * 2 * dim * dim);
         at += dim * dim;
     }
     return f;

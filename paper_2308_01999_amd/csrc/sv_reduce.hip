@@ -191,27 +191,32 @@ __global__ __launch_bounds__(kThreads) void k_finish_sums(const double* __restri
 
 // ----------------------------------------------------------------- sampler
 //
-// Two-level inverse CDF with a boundary structure that is monotone bit for
-// bit, so the search is always consistent and never lands on a
-// zero-probability index:
+// Two-level inverse CDF whose boundaries are monotone bit for bit, so the
+// search is always consistent and never lands on a zero-probability index:
 //   chunk sums S[c] (any fixed order);
 //   chunk boundaries B[0..nc] from S by per-thread sequential prefixes plus
 //     a sequential pass over thread totals (monotone, and B[c+1] == B[c]
 //     whenever S[c] == 0);
 //   for a shot, r = u * B[nc]; chunk = smallest c with r < B[c+1];
-//   inside the chunk, segment boundaries sb[] and amplitude boundaries are
-//     built the same way, and the outcome is the smallest i with
-//     r < B[c] + (sb[s] + running sum of p up to i).
+//   inside the chunk, sub-tiles of 4096 amplitudes are scanned in order with
+//     a running carry; a sub-tile's inclusive prefix is built the same way
+//     (16 contiguous values per thread, sequential thread offsets), and the
+//     outcome is the smallest i with r < B[c] + (carry + prefix_i).
+// Every boundary that follows a zero-probability amplitude repeats the
+// previous boundary exactly, so such an amplitude can never be the first
+// index whose boundary exceeds r.
 
 struct SampleLayout {
     uint64_t nc;     // chunks
     uint64_t cs;     // amplitudes per chunk
 };
 
+constexpr uint64_t kSub = 4096;  // amplitudes per sub-tile of a chunk
+
 SampleLayout sample_layout(int n)
 {
     const uint64_t dim = uint64_t(1) << n;
-    uint64_t nc = dim / 4096;
+    uint64_t nc = dim / (4 * kSub);
     if (nc < 1) nc = 1;
     if (nc > 65536) nc = 65536;
     return {nc, dim / nc};
@@ -320,15 +325,22 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_counts(const uint32_t* __
 
 __global__ __launch_bounds__(kThreads) void k_bucket(const uint32_t* __restrict__ chunk_of, uint64_t ns,
                                                     const uint32_t* __restrict__ start,
-                                                    uint32_t* __restrict__ cursor, uint32_t* __restrict__ list)
+                                                    uint32_t* __restrict__ cursor, uint32_t* __restrict__ list,
+                                                    uint64_t* __restrict__ idx_out)
 {
     const uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (s >= ns) return;
     const uint32_t c = chunk_of[s];
     const uint32_t pos = atomicAdd(&cursor[c], 1u);
     list[start[c] + pos] = uint32_t(s);
+    idx_out[s] = ~uint64_t(0);
 }
 
+// One workgroup per chunk that holds shots.  The chunk is read once,
+// coalesced, in sub-tiles; each sub-tile's probabilities go to LDS (padded
+// by one slot per 16 so the per-thread contiguous scans are conflict-free),
+// are prefix-summed there, and every unresolved shot of the chunk whose r
+// falls below the sub-tile's upper boundary is resolved by binary search.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_resolve(const typename Cx<R>::T* __restrict__ psi,
                                                      SampleLayout L, const double* __restrict__ B,
@@ -338,64 +350,81 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const typename Cx<R>::T* _
                                                      const double* __restrict__ u,
                                                      uint64_t* __restrict__ idx_out)
 {
-    __shared__ double sb[kThreads + 1];
-    const uint64_t nseg = std::min<uint64_t>(kThreads, L.cs);
-    const uint64_t seg = L.cs / nseg;
+    constexpr int kPad = 16;
+    __shared__ double cdf[kSub + kSub / kPad];
+    __shared__ double off[kThreads];
+    const uint64_t sub_len = L.cs < kSub ? L.cs : kSub;
+    const uint64_t nsub = L.cs / sub_len;
+    const int seg = sub_len >= kThreads ? int(sub_len / kThreads) : 1;  // values per thread
+    const int active = int(sub_len / seg);                            // threads with a segment
     const double total = B[L.nc];
+    const int tid = threadIdx.x;
+    auto slot = [](int i) { return i + i / kPad; };
     for (uint64_t c = blockIdx.x; c < L.nc; c += gridDim.x) {
         const uint32_t cnt = counts[c];
         if (cnt == 0) continue;
         const uint64_t c0 = c * L.cs;
-        double run = 0.0;
-        if (threadIdx.x < nseg) {
-            const uint64_t s0 = c0 + threadIdx.x * seg;
-            for (uint64_t i = 0; i < seg; ++i) run = __dadd_rn(run, prob(psi[s0 + i]));
-            sb[threadIdx.x + 1] = run;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double o = 0.0;
-            sb[0] = 0.0;
-            for (uint64_t s = 0; s < nseg; ++s) {
-                o = __dadd_rn(o, sb[s + 1]);
-                sb[s + 1] = o;
-            }
-        }
-        __syncthreads();
         const double bc = B[c];
-        for (uint32_t j = threadIdx.x; j < cnt; j += kThreads) {
-            const uint32_t shot = list[start[c] + j];
-            const double r = shot_r(u[shot], total);
-            // smallest segment s with r < bc + sb[s+1]
-            uint64_t lo = 0, hi = nseg;  // hi == nseg: not found
-            while (lo < hi) {
-                const uint64_t mid = lo + (hi - lo) / 2;
-                if (r < __dadd_rn(bc, sb[mid + 1]))
-                    hi = mid;
-                else
-                    lo = mid + 1;
+        const uint32_t* shots = list + start[c];
+        double carry = 0.0;
+        for (uint64_t sidx = 0; sidx < nsub; ++sidx) {
+            const uint64_t s0 = c0 + sidx * sub_len;
+            for (int i = tid; i < int(sub_len); i += kThreads) cdf[slot(i)] = prob(psi[s0 + i]);
+            __syncthreads();
+            double run = 0.0;
+            if (tid < active) {
+                for (int i = 0; i < seg; ++i) {
+                    run = __dadd_rn(run, cdf[slot(tid * seg + i)]);
+                    cdf[slot(tid * seg + i)] = run;
+                }
+                off[tid] = run;
             }
-            uint64_t found = ~uint64_t(0);
-            if (lo < nseg) {
-                const uint64_t s0 = c0 + lo * seg;
-                const double base = sb[lo];
-                double acc = 0.0;
-                for (uint64_t i = 0; i < seg; ++i) {
-                    acc = __dadd_rn(acc, prob(psi[s0 + i]));
-                    if (r < __dadd_rn(bc, __dadd_rn(base, acc))) {
-                        found = s0 + i;
-                        break;
-                    }
+            __syncthreads();
+            if (tid == 0) {
+                double o = 0.0;
+                for (int t = 0; t < active; ++t) {
+                    const double v = off[t];
+                    off[t] = o;
+                    o = __dadd_rn(o, v);
                 }
             }
-            if (found == ~uint64_t(0)) {
-                // rounding left r past the chunk's own total: take the last
-                // amplitude of the chunk with non-zero probability
-                for (uint64_t i = L.cs; i-- > 0;) {
-                    if (prob(psi[c0 + i]) > 0.0) {
-                        found = c0 + i;
-                        break;
-                    }
+            __syncthreads();
+            if (tid < active) {
+                const double o = off[tid];
+                for (int i = 0; i < seg; ++i) cdf[slot(tid * seg + i)] = __dadd_rn(o, cdf[slot(tid * seg + i)]);
+            }
+            __syncthreads();
+            const double last = cdf[slot(int(sub_len) - 1)];
+            const double upper = __dadd_rn(bc, __dadd_rn(carry, last));
+            for (uint32_t j = tid; j < cnt; j += kThreads) {
+                const uint32_t shot = shots[j];
+                if (idx_out[shot] != ~uint64_t(0)) continue;
+                const double r = shot_r(u[shot], total);
+                if (!(r < upper)) continue;
+                int lo = 0, hi = int(sub_len) - 1;  // smallest i with r < bc + (carry + cdf_i)
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (r < __dadd_rn(bc, __dadd_rn(carry, cdf[slot(mid)])))
+                        hi = mid;
+                    else
+                        lo = mid + 1;
+                }
+                idx_out[shot] = s0 + uint64_t(lo);
+            }
+            carry = __dadd_rn(carry, last);
+            __syncthreads();
+        }
+        // rounding left r past the chunk's own total (the chunk sum S[c]
+        // and the in-chunk scan add in different orders): take the last
+        // amplitude of the chunk with non-zero probability
+        for (uint32_t j = tid; j < cnt; j += kThreads) {
+            const uint32_t shot = shots[j];
+            if (idx_out[shot] != ~uint64_t(0)) continue;
+            uint64_t found = c0;
+            for (uint64_t i = L.cs; i-- > 0;) {
+                if (prob(psi[c0 + i]) > 0.0) {
+                    found = c0 + i;
+                    break;
                 }
             }
             idx_out[shot] = found;
@@ -559,7 +588,7 @@ void run_sample_t(sv_handle_s* h, const void* psi_v, int n, const double* u, int
         SV_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(kScanThreads), 0, h->stream, counts, L.nc, start, cursor);
         SV_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_bucket, dim3(sg), dim3(kThreads), 0, h->stream, chunk_of, ns, start, cursor, list);
+        hipLaunchKernelGGL(k_bucket, dim3(sg), dim3(kThreads), 0, h->stream, chunk_of, ns, start, cursor, list, didx);
         SV_HIP(hipGetLastError());
         hipLaunchKernelGGL((k_resolve<R>), dim3(unsigned(std::min<uint64_t>(L.nc, uint64_t(h->cu_count) * 16))),
                            dim3(kThreads), 0, h->stream, psi, L, B, counts, start, list, du, didx);

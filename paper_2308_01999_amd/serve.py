@@ -1,0 +1,214 @@
+"""Continuous-batching server for circuit requests on one GPU.
+
+Requests (a named-gate circuit on n qubits, Pauli strings to evaluate, and
+uniforms to sample with) arrive over time.  A dispatcher admits them in
+arrival order as soon as a slot is free and the request's state fits the
+HBM budget; later requests may pass a blocked head only a bounded number of
+times, so large requests do not starve.  Each slot is a worker thread with
+its own torch stream and libsv handle, so the work of admitted requests
+overlaps on the device.  A request's state stays resident in HBM from
+admission until its results are read back, then its memory is returned to
+the budget and the next request is admitted.
+
+All computation happens in libsv (host fusion in its C++, everything else
+in its kernels); this module only schedules.  Every reduction in libsv is
+deterministic, so a request's results are bitwise the same whether it runs
+alone or among others.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import Handle, State, fuse, sv_apply_fused, sv_expect_pauli, sv_sample
+
+STATE_BYTES = {"c64": 8, "c128": 16}
+
+
+@dataclass
+class Request:
+    rid: int
+    n: int
+    gates: list
+    terms: list
+    uniforms: np.ndarray
+    arrival: float = 0.0          # host monotonic time of arrival (set on submit)
+
+
+@dataclass
+class Result:
+    rid: int
+    expectations: np.ndarray
+    samples: np.ndarray
+    fused_blocks: int
+    arrival: float
+    admitted: float
+    done: float
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class Admission:
+    """Pure admission policy (no GPU): FIFO with bounded bypass under a
+    byte budget and a slot count.  Unit-tested on the CPU."""
+
+    def __init__(self, budget_bytes: int, slots: int, max_bypass: int = 8):
+        self.budget = budget_bytes
+        self.slots = slots
+        self.max_bypass = max_bypass
+        self.used = 0
+        self.busy = 0
+        self.queue = collections.deque()  # (rid, footprint)
+        self.head_bypassed = 0
+
+    def add(self, rid: int, footprint: int) -> None:
+        if footprint > self.budget:
+            raise ValueError(f"request {rid} needs {footprint} B, more than the budget {self.budget} B")
+        self.queue.append((rid, footprint))
+
+    def pick(self):
+        """Next request to admit, or None.  Reserves its slot and bytes."""
+        if self.busy >= self.slots or not self.queue:
+            return None
+        rid, fp = self.queue[0]
+        if self.used + fp <= self.budget:
+            self.queue.popleft()
+            self.head_bypassed = 0
+            return self._take(rid, fp)
+        if self.head_bypassed >= self.max_bypass:
+            return None
+        for i in range(1, len(self.queue)):
+            r2, f2 = self.queue[i]
+            if self.used + f2 <= self.budget:
+                del self.queue[i]
+                self.head_bypassed += 1
+                return self._take(r2, f2)
+        return None
+
+    def _take(self, rid, fp):
+        self.used += fp
+        self.busy += 1
+        return rid, fp
+
+    def release(self, footprint: int) -> None:
+        self.used -= footprint
+        self.busy -= 1
+
+
+class Server:
+    """Serves requests on `slots` concurrent streams within `budget_bytes`
+    of state memory, complex64 (or complex128) states, fusion width kmax
+    (0: no fusion, one sweep per gate)."""
+
+    def __init__(self, slots: int = 4, budget_bytes: int = 64 << 30, dtype: str = "c64", kmax: int = 5,
+                 max_bypass: int = 8):
+        import torch
+        self.dtype = dtype
+        self.kmax = kmax
+        self.adm = Admission(budget_bytes, slots, max_bypass)
+        self.cv = threading.Condition()
+        self.pending = {}        # rid -> Request
+        self.results = {}        # rid -> Result
+        self.ready = collections.deque()  # admitted, waiting for a worker
+        self.stop = False
+        self.handles = [Handle(stream=torch.cuda.Stream()) for _ in range(slots)]
+        self.workers = [threading.Thread(target=self._worker, args=(i,), daemon=True) for i in range(slots)]
+        self.dispatcher = threading.Thread(target=self._dispatch, daemon=True)
+        for w in self.workers:
+            w.start()
+        self.dispatcher.start()
+
+    def footprint(self, n: int) -> int:
+        return (1 << n) * STATE_BYTES[self.dtype]
+
+    def submit(self, req: Request) -> None:
+        req.arrival = time.monotonic()
+        with self.cv:
+            self.pending[req.rid] = req
+            self.adm.add(req.rid, self.footprint(req.n))
+            self.cv.notify_all()
+
+    def _dispatch(self) -> None:
+        with self.cv:
+            while not self.stop:
+                picked = self.adm.pick()
+                if picked is None:
+                    self.cv.wait(timeout=0.05)
+                    continue
+                rid, _ = picked
+                self.ready.append((rid, time.monotonic()))
+                self.cv.notify_all()
+
+    def _worker(self, slot: int) -> None:
+        import torch
+        h = self.handles[slot]
+        while True:
+            with self.cv:
+                while not self.ready and not self.stop:
+                    self.cv.wait(timeout=0.05)
+                if self.stop and not self.ready:
+                    return
+                rid, admitted = self.ready.popleft()
+                req = self.pending.pop(rid)
+            with torch.cuda.stream(h.stream):
+                res = self._run(h, req, admitted)
+            with self.cv:
+                self.results[rid] = res
+                self.adm.release(self.footprint(req.n))
+                self.cv.notify_all()
+
+    def _run(self, h: Handle, req: Request, admitted: float) -> Result:
+        st = State(h, req.n, self.dtype)
+        f = fuse(req.gates, self.kmax) if self.kmax > 0 else None
+        try:
+            if f is not None:
+                sv_apply_fused(st.s, f.f)
+                nb = f.count
+            else:
+                st.run(req.gates)  # one sweep per gate
+                nb = len(req.gates)
+            exps = sv_expect_pauli(st.s, req.terms)
+            smp = sv_sample(st.s, req.uniforms)
+        finally:
+            if f is not None:
+                f.free()
+            st.close()
+        return Result(req.rid, exps, smp, nb, req.arrival, admitted, time.monotonic())
+
+    def wait(self, rids, timeout: float = 600.0) -> dict:
+        end = time.monotonic() + timeout
+        with self.cv:
+            while not all(r in self.results for r in rids):
+                left = end - time.monotonic()
+                if left <= 0:
+                    raise TimeoutError("requests did not finish in time")
+                self.cv.wait(timeout=min(left, 0.1))
+            return {r: self.results[r] for r in rids}
+
+    def close(self) -> None:
+        with self.cv:
+            self.stop = True
+            self.cv.notify_all()
+        self.dispatcher.join()
+        for w in self.workers:
+            w.join()
+        for h in self.handles:
+            h.close()
+
+
+def replay(server: Server, requests, time_scale: float = 1.0) -> dict:
+    """Submits `requests` (workloads.Request) at their arrival times (scaled)
+    and waits for all; returns rid -> Result."""
+    t0 = time.monotonic()
+    for r in requests:
+        delay = t0 + r.arrival * time_scale - time.monotonic()
+        if delay > 0:
+            time.sleep(delay)
+        server.submit(Request(r.rid, r.n, r.gates, r.terms, np.asarray(r.uniforms)))
+    return server.wait([r.rid for r in requests])

@@ -1,0 +1,107 @@
+"""GPU parity of the batched path: every circuit of a mixed batch (resident
+and streamed states, fused at each width and by the autotuner) against the
+oracle, and each circuit's result alone versus in the mix (bitwise equal,
+since all reductions run in a fixed order)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+C64_FID = 1.0 - 1e-5
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_01999_amd as P
+    return P
+
+
+@pytest.fixture(scope="module")
+def H(P):
+    h = P.Handle()
+    yield h
+    h.close()
+
+
+def _mixed(seed, sizes, depth_lo=4, depth_hi=12):
+    rng = np.random.default_rng(seed)
+    ns, circuits, terms = [], [], []
+    for i, n in enumerate(sizes):
+        d = int(rng.integers(depth_lo, depth_hi + 1))
+        ns.append(n)
+        circuits.append(W.brickwork(n, d, 1000 * seed + i))
+        zz = [1 << q | 1 << (q + 1) for q in range(n - 1)]
+        terms.append(zz + [1 << (n - 1)])
+    return ns, circuits, terms
+
+
+def _check(P, batch, ns, circuits, terms, exps):
+    for i, (n, g, zm) in enumerate(zip(ns, circuits, terms)):
+        ref = oracle.run(n, g)
+        got = batch.state(i).astype(np.complex128)
+        fid = oracle.fidelity(ref, got)
+        assert fid >= C64_FID, (i, n, fid)
+        zr = []
+        for m in zm:
+            term = [(q, "Z") for q in range(n) if (m >> q) & 1]
+            zr.append(oracle.expect_pauli(ref, term))
+        assert np.max(np.abs(exps[i] - np.array(zr))) <= 1e-4, (i, n)
+
+
+@pytest.mark.parametrize("kmax", [1, 2, 3, 4, 5])
+def test_batch_fixed_width_matches_oracle(P, H, kmax):
+    sizes = [2, 3, 5, 8, 11, 12, 13, 14, 16, 4, 9, 12, 13]
+    ns, circuits, terms = _mixed(kmax, sizes)
+    b = P.Batch(H, ns, circuits, terms, max_fused_qubits=kmax)
+    exps, lat, ks = b.run()
+    _check(P, b, ns, circuits, terms, exps)
+    assert (lat > 0).all() and ks > 0
+    assert lat.max() <= ks * 1.5 + 1e-3
+    b.close()
+
+
+def test_batch_autotuned_width_matches_oracle(P, H):
+    sizes = [8, 10, 12, 13, 14, 15] * 3
+    ns, circuits, terms = _mixed(77, sizes, 10, 20)
+    b = P.Batch(H, ns, circuits, terms, max_fused_qubits=0)
+    for n in set(sizes):
+        assert 3 <= b.fusion_width(n) <= 5
+    exps, lat, ks = b.run()
+    _check(P, b, ns, circuits, terms, exps)
+    b.close()
+
+
+def test_batch_alone_equals_in_mix(P, H):
+    sizes = [8, 14, 10, 16, 12, 9, 13, 15]
+    ns, circuits, terms = _mixed(5, sizes)
+    mix = P.Batch(H, ns, circuits, terms, max_fused_qubits=5)
+    exps, _, _ = mix.run()
+    states = [mix.state(i) for i in range(len(ns))]
+    for i in (0, 3, 6):
+        alone = P.Batch(H, [ns[i]], [circuits[i]], [terms[i]], max_fused_qubits=5)
+        e1, _, _ = alone.run()
+        np.testing.assert_array_equal(e1[0], exps[i])
+        np.testing.assert_array_equal(alone.state(0), states[i])
+        alone.close()
+    # a second run of the same batch gives the same results
+    exps2, _, _ = mix.run()
+    for a, c in zip(exps, exps2):
+        np.testing.assert_array_equal(a, c)
+    mix.close()
+
+
+def test_batch_rejects_bad_input(P, H):
+    with pytest.raises(P.SVError):
+        P.Batch(H, [31], [W.brickwork(2, 1, 0)], [[1]], 5)
+    with pytest.raises(P.SVError):
+        P.Batch(H, [4], [W.brickwork(4, 1, 0)], [[1 << 4]], 5)
+    with pytest.raises(P.SVError):
+        P.Batch(H, [4], [W.brickwork(5, 1, 0)], [[1]], 5)
+    with pytest.raises(P.SVError):
+        P.Batch(H, [4], [W.brickwork(4, 1, 0)], [[1]], 6)
