@@ -30,6 +30,45 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged over the 30-qubit
+# complex64 launches), each scaled by what the same counter reads for a plain
+# copy of known size (FETCH_SIZE reads half the bytes a copy fetches, so x2.0;
+# WRITE_SIZE reads them all, x1.0).  Valid only for the kernel source the
+# counters were taken on: its SHA-256 is recorded and checked at run time.
+PMC_TRAFFIC = {
+    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194402.8, "write_kib": 8394700.7,
+                      "fetch_scale": 2.0, "write_scale": 1.0,
+                      "source": "paper_2308_01999_amd/csrc/sv_apply.hip",
+                      "source_sha256": "eed91692a4f101ea1fa2b32df4242ca39ca1a61bc2f09a1c06ebe1e87a188e18"},
+}
+
+
+def pmc_traffic(kernel, n):
+    """Calibrated HBM bytes per launch of `kernel` at n qubits from the
+    recorded counters, or None if none were taken for it or its source has
+    changed since."""
+    import hashlib
+    rec = PMC_TRAFFIC.get(kernel)
+    if rec is None or rec["n"] != n or rec["source_sha256"] is None:
+        return None
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return int(rec["fetch_kib"] * 1024 * rec["fetch_scale"] + rec["write_kib"] * 1024 * rec["write_scale"])
+
+
+def dominant_kernel_name(dt, k, n):
+    """Kernel that libsv launches for an uncontrolled fused k-qubit block on
+    an n-qubit state (mirrors the path choice in sv_apply.hip)."""
+    if dt == "c64" and k in (4, 5) and n >= 12:
+        return f"k_tile_c64_k{k}"
+    if dt == "c128" and k == 5 and n >= 11:
+        return "k_tile_c128_k5"
+    if dt == "c64" and k in (4, 5):
+        return f"k_apply_mfma_c64_k{k}"
+    return f"k_apply_dense<{'float' if dt == 'c64' else 'double'}, {k}>"
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -50,6 +89,9 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--gate-sweep", action="store_true",
+                    help="also time single k-qubit gates (k = 1..6) on random target sets, both dtypes")
+    ap.add_argument("--sweep-sets", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain device copies of known size (for HBM counter calibration)")
     return ap.parse_args()
@@ -178,6 +220,59 @@ def cpu_baseline(W, P, gates, n, kmax, seconds):
             "sample": f"first {done} of {len(blocks)} fused blocks (k<={kmax}) of the {n}-qubit brickwork "
                       f"depth-20 circuit applied by the complex128 oracle to a 2^{n} state in host memory; "
                       f"{el:.1f} s; bytes counted as 2*2^{n}*16 per block"}
+
+
+def copy_ceiling(torch, n):
+    """In-place read+write bandwidth of torch's elementwise kernel on a
+    2^n complex64-sized buffer: the achievable ceiling for in-place sweeps."""
+    a = torch.ones(1 << (n + 1), dtype=torch.float32, device="cuda")
+    a.mul_(1.0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        a.mul_(1.0)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    del a
+    torch.cuda.empty_cache()
+    return 2 * (1 << n) * 8 / (ms * 1e-3) / 1e9
+
+
+def gate_sweep(P, W, torch, H, n, sets, reps=3):
+    """Single dense k-qubit gates (Haar random) on `sets` random target sets
+    per k, after the paper's gate-application measurement (Sec. II-B, Fig. 2:
+    bandwidth from many random target sets).  Median GB/s per k and dtype,
+    timed with HIP events on the handle's stream."""
+    import numpy as np
+    out = {}
+    for dt, ab in (("c64", 8), ("c128", 16)):
+        st = P.State(H, n, dt)
+        rng = np.random.default_rng(1000)
+        res = {}
+        for k in range(1, 7):
+            bws = []
+            for j in range(sets):
+                ts = W.random_targets(n, k, np.random.default_rng(1000 * k + j))
+                m = W.haar_unitary(k, rng)
+                st.apply_matrix(m, ts)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(H.stream)
+                for _ in range(reps):
+                    st.apply_matrix(m, ts)
+                e1.record(H.stream)
+                e1.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                bws.append(2 * (1 << n) * ab / (ms * 1e-3) / 1e9)
+            res[str(k)] = {"median_GBps": round(float(np.median(bws)), 1),
+                           "p10_GBps": round(float(np.percentile(bws, 10)), 1),
+                           "p90_GBps": round(float(np.percentile(bws, 90)), 1)}
+        out[dt] = res
+        st.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
 
 
 def batched_leg(P, W, torch, H, count, steps, warmup, sample):
@@ -343,6 +438,8 @@ def main():
     torch.cuda.synchronize()
     dk = r64["dominant_kernel"]
     achieved = dk["GBps"]
+    kname = dominant_kernel_name("c64", dk["k"], n)
+    traffic = pmc_traffic(kname, n)
     line = {
         "metric": "fused-gate HBM GB/s at 30q c64/c128; batched-circuit p50/p99 latency",
         "value": round(r64["fused_gate_GBps"], 2),
@@ -361,8 +458,8 @@ def main():
                                f"{args.shots} samples",
                    "n_qubits": n, "depth": depth, "max_fused_qubits": kmax, "state_dtype": "complex64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": f"k_apply_dense<float, {dk['k']}>", "bytes_per_launch": dk["bytes_per_launch"],
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": kname, "bytes_per_launch": dk["bytes_per_launch"],
                      "avg_launch_ms": round(dk["avg_ms"], 4)},
         "c64": r64,
         **extra,
@@ -376,6 +473,13 @@ def main():
     if not args.no_serving:
         print("[bench] serving leg", file=sys.stderr, flush=True)
         line["serving"] = serving_leg(P, W, torch, args.serve_requests, args.serve_slots)
+    line["copy_ceiling_GBps"] = round(copy_ceiling(torch, n), 1)
+    line["frac_of_copy_ceiling"] = round(r64["fused_gate_GBps"] / line["copy_ceiling_GBps"], 4)
+    if args.gate_sweep:
+        print("[bench] gate sweep", file=sys.stderr, flush=True)
+        H3 = P.Handle()
+        line["gate_sweep"] = gate_sweep(P, W, torch, H3, n, args.sweep_sets)
+        H3.close()
     if args.calibrate_copy:
         line["copy_calibration"] = calibrate_copy(torch)
     if not args.no_cpu_baseline:

@@ -24,6 +24,12 @@ LIB_PATH = os.path.join(_HERE, "libsv.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libsv.so is not built at {LIB_PATH}; run paper_2308_01999_amd/build.py")
 
+# torch ships its own HIP and HSA runtimes (soname libamdhip64.so.7, like
+# ROCm's).  Loading torch first makes libsv bind to that same runtime; loading
+# libsv first would bring in a second HIP/HSA runtime whose device enumeration
+# fails once torch's has opened the GPU.
+import torch  # noqa: E402,F401
+
 _L = ctypes.CDLL(LIB_PATH)
 
 SV_OK, SV_ERR_INVALID_VALUE, SV_ERR_OUT_OF_MEMORY, SV_ERR_NOT_SUPPORTED, SV_ERR_DEVICE, SV_ERR_INTERNAL = range(6)

@@ -318,17 +318,23 @@ __device__ __forceinline__ void gstore(V* p, const V v)
 // the tile loop would be placed in scratch memory by the compiler).
 #define SV_REP8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
-// Global offsets (relative to a tile's base) of the thread's 8 vectors;
-// vector u of thread tid holds tile-local amplitudes starting at
-// i = (u * 256 + tid) * amps_per_vec, which is also its LDS position.
+// Offsets (relative to a tile's base) of the thread's 8 vectors; vector u
+// of thread tid holds tile-local amplitudes starting at
+// i = (u * 256 + tid) * amps_per_vec, which is also its LDS position.  Its
+// run index i >> L is the same for the whole wave (L >= 6 for complex128 and
+// >= 7 for complex64, so the lane bits of tid stay below L), so the 64-bit
+// run offset is a scalar and only the 32-bit offset inside the run is
+// per lane.
 template <int APV>
-__device__ __forceinline__ void tile_offsets(const TileArgs& a, uint64_t* goff)
+__device__ __forceinline__ void tile_offsets(const TileArgs& a, uint64_t* roff, uint32_t* poff)
 {
     const int mask = (1 << a.L) - 1;
 #pragma unroll
     for (int u = 0; u < kTileVecs; ++u) {
         const int i = (u * kTileThreads + int(threadIdx.x)) * APV;
-        goff[u] = deposit_bits(uint32_t(i >> a.L), a.hi_pos, a.n_hi) + uint64_t(i & mask);
+        const uint32_t r = uint32_t(__builtin_amdgcn_readfirstlane(i >> a.L));
+        roff[u] = deposit_bits(r, a.hi_pos, a.n_hi);
+        poff[u] = uint32_t(i & mask);
     }
 }
 
@@ -341,14 +347,17 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k5(float2* __restrict
                                                              const float4* __restrict__ mats, TileArgs a)
 {
     __shared__ float4 lds[kTileThreads * kTileVecs];
+    // the packed A operands (same for every wave): 3 x 64 lanes x 4 float4,
+    // read back four k-steps at a time so only 12 of them are live at once
+    __shared__ float4 amat[3 * 64 * 4];
     const uint64_t t0 = uint64_t(blockIdx.x) * a.tiles_per_wg;
     if (t0 >= a.n_tiles) return;
     const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 31, half = lane >> 5;
-    float ar[16], ai[16], as[16];
-    load_a_c64k5(mats, lane, ar, ai, as);
-    uint64_t goff[kTileVecs];
-    tile_offsets<2>(a, goff);
+    for (int e = tid; e < 3 * 64 * 4; e += kTileThreads) amat[e] = mats[e];
+    uint64_t roff[kTileVecs];
+    uint32_t poff[kTileVecs];
+    tile_offsets<2>(a, roff, poff);
     const int pb = int(insert_zero_bits(uint64_t(wave * 32 + col), a.lo_pos, a.n_lo));
     const int pin = pb + (half ? a.lds_off[1] : 0);
     const int pout = pb + (half ? a.lds_off[4] : 0);
@@ -357,7 +366,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k5(float2* __restrict
     SV_REP8(SV_DECL)
 #undef SV_DECL
     uint64_t base = tile_base(t0, a);
-#define SV_LOAD(u) buf##u = gload(reinterpret_cast<const float4*>(psi + base + goff[u]));
+#define SV_LOAD(u) buf##u = gload(reinterpret_cast<const float4*>(psi + base + roff[u] + poff[u]));
     SV_REP8(SV_LOAD)
 #undef SV_LOAD
     for (uint64_t t = t0; t < t1; ++t) {
@@ -368,7 +377,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k5(float2* __restrict
         uint64_t nbase = 0;
         if (t + 1 < t1) {
             nbase = tile_base(t + 1, a);
-#define SV_PREFETCH(u) buf##u = gload(reinterpret_cast<const float4*>(psi + nbase + goff[u]));
+#define SV_PREFETCH(u) buf##u = gload(reinterpret_cast<const float4*>(psi + nbase + roff[u] + poff[u]));
             SV_REP8(SV_PREFETCH)
 #undef SV_PREFETCH
         }
@@ -376,14 +385,29 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k5(float2* __restrict
 #pragma unroll
         for (int j = 0; j < 16; ++j) x[j] = lds2[pin + a.lds_off[2 * j]];
         f32x16 p1 = {0}, p2 = {0}, p3 = {0};
-        mfma_c64k5(ar, ai, as, x, p1, p2, p3);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 vr = amat[(0 * 64 + lane) * 4 + q];
+            const float4 vi = amat[(1 * 64 + lane) * 4 + q];
+            const float4 vs = amat[(2 * 64 + lane) * 4 + q];
+            const float ar[4] = {vr.x, vr.y, vr.z, vr.w};
+            const float ai[4] = {vi.x, vi.y, vi.z, vi.w};
+            const float as[4] = {vs.x, vs.y, vs.z, vs.w};
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const float2 xv = x[4 * q + jj];
+                p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[jj], xv.x, p1, 0, 0, 0);
+                p2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[jj], xv.y, p2, 0, 0, 0);
+                p3 = __builtin_amdgcn_mfma_f32_32x32x2f32(as[jj], xv.x + xv.y, p3, 0, 0, 0);
+            }
+        }
 #pragma unroll
         for (int r = 0; r < 16; ++r)
             lds2[pout + a.lds_off[8 * (r / 4) + (r % 4)]] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kTileVecs; ++u)
-            gstore(reinterpret_cast<float4*>(psi + base + goff[u]), lds[u * kTileThreads + tid]);
+            gstore(reinterpret_cast<float4*>(psi + base + roff[u] + poff[u]), lds[u * kTileThreads + tid]);
         base = nbase;
         __syncthreads();
     }
@@ -399,8 +423,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, q = lane >> 4;
     float ar[4], ai[4], as[4];
     load_a_c64k4(mats, lane, ar, ai, as);
-    uint64_t goff[kTileVecs];
-    tile_offsets<2>(a, goff);
+    uint64_t roff[kTileVecs];
+    uint32_t poff[kTileVecs];
+    tile_offsets<2>(a, roff, poff);
     // each wave owns 4 column tiles of 16 groups: 256 groups per tile
     const int lin = ((q & 1) ? a.lds_off[1] : 0) + ((q & 2) ? a.lds_off[2] : 0);
     const int lout = ((q & 1) ? a.lds_off[4] : 0) + ((q & 2) ? a.lds_off[8] : 0);
@@ -412,7 +437,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict
     SV_REP8(SV_DECL)
 #undef SV_DECL
     uint64_t base = tile_base(t0, a);
-#define SV_LOAD(u) buf##u = gload(reinterpret_cast<const float4*>(psi + base + goff[u]));
+#define SV_LOAD(u) buf##u = gload(reinterpret_cast<const float4*>(psi + base + roff[u] + poff[u]));
     SV_REP8(SV_LOAD)
 #undef SV_LOAD
     for (uint64_t t = t0; t < t1; ++t) {
@@ -423,7 +448,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict
         uint64_t nbase = 0;
         if (t + 1 < t1) {
             nbase = tile_base(t + 1, a);
-#define SV_PREFETCH(u) buf##u = gload(reinterpret_cast<const float4*>(psi + nbase + goff[u]));
+#define SV_PREFETCH(u) buf##u = gload(reinterpret_cast<const float4*>(psi + nbase + roff[u] + poff[u]));
             SV_REP8(SV_PREFETCH)
 #undef SV_PREFETCH
         }
@@ -441,7 +466,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kTileVecs; ++u)
-            gstore(reinterpret_cast<float4*>(psi + base + goff[u]), lds[u * kTileThreads + tid]);
+            gstore(reinterpret_cast<float4*>(psi + base + roff[u] + poff[u]), lds[u * kTileThreads + tid]);
         base = nbase;
         __syncthreads();
     }
@@ -467,8 +492,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restri
             A[g][2 * e] = v.x;
             A[g][2 * e + 1] = v.y;
         }
-    uint64_t goff[kTileVecs];
-    tile_offsets<1>(a, goff);
+    uint64_t roff[kTileVecs];
+    uint32_t poff[kTileVecs];
+    tile_offsets<1>(a, roff, poff);
     const int pb = int(insert_zero_bits(uint64_t(wave * 16 + col), a.lo_pos, a.n_lo));
     // loads: matrix index 4s + q; stores: row 16 rt + 4 v + q: bits 0-1 = q
     const int pq = pb + ((q & 1) ? a.lds_off[1] : 0) + ((q & 2) ? a.lds_off[2] : 0);
@@ -476,7 +502,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restri
     SV_REP8(SV_DECL)
 #undef SV_DECL
     uint64_t base = tile_base(t0, a);
-#define SV_LOAD(u) buf##u = gload(psi + base + goff[u]);
+#define SV_LOAD(u) buf##u = gload(psi + base + roff[u] + poff[u]);
     SV_REP8(SV_LOAD)
 #undef SV_LOAD
     for (uint64_t t = t0; t < t1; ++t) {
@@ -487,7 +513,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restri
         uint64_t nbase = 0;
         if (t + 1 < t1) {
             nbase = tile_base(t + 1, a);
-#define SV_PREFETCH(u) buf##u = gload(psi + nbase + goff[u]);
+#define SV_PREFETCH(u) buf##u = gload(psi + nbase + roff[u] + poff[u]);
             SV_REP8(SV_PREFETCH)
 #undef SV_PREFETCH
         }
@@ -509,7 +535,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restri
         }
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < kTileVecs; ++u) gstore(psi + base + goff[u], lds[u * kTileThreads + tid]);
+        for (int u = 0; u < kTileVecs; ++u) gstore(psi + base + roff[u] + poff[u], lds[u * kTileThreads + tid]);
         base = nbase;
         __syncthreads();
     }

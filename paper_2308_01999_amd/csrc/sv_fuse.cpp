@@ -162,19 +162,22 @@ void left_multiply(std::vector<double>& U, int m, const HostGate& g, const std::
 
 int popcount64(uint64_t v) { return __builtin_popcountll(v); }
 
-// Greedy block selection over the gate dependency order.
+// Block selection over the gate dependency order.
 //
-// While gates remain: for every "ready" gate (no unfused predecessor on any
-// of its qubits) grow a candidate block seeded by it: scan the remaining
-// gates in order and take a gate when none of its qubits is blocked and the
-// block's qubit set stays within kmax after adding the gate's qubits;
-// otherwise block the gate's qubits (every later gate on them must wait).
-// Taken gates never depend on a skipped gate, so the block can be emitted
-// before all remaining gates.  The candidate that absorbs the most gates
-// becomes the next block.
+// Absorbing into a qubit set S: scan the remaining gates in circuit order
+// and take a gate when its qubits lie in S and none of them is blocked;
+// otherwise block its qubits (every later gate on them must wait).  Taken
+// gates never depend on a skipped gate, so the block they form can be
+// emitted before all remaining gates.
+//
+// While gates remain, for every "ready" gate (no remaining predecessor on
+// any of its qubits) grow a qubit set from the seed's qubits one qubit at a
+// time, up to kmax: the candidates are the qubits of the near-future gates
+// that touch the set, and the one whose addition lets the most gates be
+// absorbed wins (lowest qubit on ties).  The seed whose grown set absorbs
+// the most gates becomes the next block.
 std::vector<std::vector<int>> select_blocks(const std::vector<HostGate>& gates, int kmax)
 {
-    // live: remaining gates in circuit order, as (index, qubit mask)
     std::vector<int> live(gates.size());
     std::vector<uint64_t> mask(gates.size());
     for (size_t i = 0; i < gates.size(); ++i) {
@@ -184,46 +187,61 @@ std::vector<std::vector<int>> select_blocks(const std::vector<HostGate>& gates, 
     std::vector<std::vector<int>> blocks;
     std::vector<int> ready;
     std::vector<char> take;
-    // grows the block seeded by live[seed_pos]; returns the number of gates
-    // it absorbs and, if `mark`, flags them in `take`
-    auto grow = [&](size_t seed_pos, bool mark) {
-        uint64_t S = mask[seed_pos];
-        const int cap = std::max(kmax, popcount64(S));
+    constexpr size_t kWindow = 256;  // gates looked at for candidate qubits
+    auto absorb = [&](uint64_t S, bool mark) {
         uint64_t blocked = 0;
         int count = 0;
         for (size_t j = 0; j < live.size(); ++j) {
             const uint64_t Q = mask[j];
-            if ((Q & blocked) == 0 && popcount64(S | Q) <= cap) {
-                S |= Q;
+            if ((Q & blocked) == 0 && (Q & ~S) == 0) {
                 ++count;
                 if (mark) take[j] = 1;
             } else {
                 blocked |= Q;
             }
-            // nothing more can join once every qubit of S is blocked and S
-            // cannot grow
-            if ((S & ~blocked) == 0 && popcount64(S) >= cap) break;
+            if ((S & ~blocked) == 0) break;  // every qubit of S is blocked
         }
         return count;
     };
+    auto grow = [&](uint64_t S) {
+        while (popcount64(S) < kmax) {
+            uint64_t cand = 0;
+            const size_t lim = std::min(live.size(), kWindow);
+            for (size_t j = 0; j < lim; ++j)
+                if (mask[j] & S) cand |= mask[j] & ~S;
+            if (!cand) break;
+            int best_q = -1, best_c = -1;
+            for (int q = 0; q < 64; ++q) {
+                if (!((cand >> q) & 1)) continue;
+                const int c = absorb(S | (uint64_t(1) << q), false);
+                if (c > best_c) {
+                    best_c = c;
+                    best_q = q;
+                }
+            }
+            S |= uint64_t(1) << best_q;
+        }
+        return S;
+    };
     while (!live.empty()) {
-        // ready gates: first remaining gate on each of their qubits
         ready.clear();
         uint64_t seen = 0;
         for (size_t j = 0; j < live.size(); ++j) {
             if ((mask[j] & seen) == 0) ready.push_back(int(j));
             seen |= mask[j];
         }
-        int best = -1, best_count = -1;
+        uint64_t best_S = 0;
+        int best_count = -1;
         for (int pos : ready) {
-            const int c = grow(size_t(pos), false);
+            const uint64_t S = grow(mask[size_t(pos)]);
+            const int c = absorb(S, false);
             if (c > best_count) {
                 best_count = c;
-                best = pos;
+                best_S = S;
             }
         }
         take.assign(live.size(), 0);
-        grow(size_t(best), true);
+        absorb(best_S, true);
         std::vector<int> blk;
         size_t w = 0;
         for (size_t j = 0; j < live.size(); ++j) {

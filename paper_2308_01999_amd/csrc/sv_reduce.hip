@@ -133,15 +133,21 @@ __global__ __launch_bounds__(kThreads) void k_expect(const typename Cx<R>::T* __
 #pragma unroll
     for (int t = 0; t <= kMaxTermsPerSweep; ++t) acc[t] = 0.0;
     const uint64_t first = uint64_t(blockIdx.x) * a.per;
+    // index bits that change across one thread's items (x == 0 sweeps)
+    const uint64_t vary = (a.per - 1) & ~uint64_t(kThreads - 1);
     for (uint64_t it = threadIdx.x; it < a.per; it += kThreads) {
         const uint64_t q = first + it;
         if (!kPairs) {
+            // q = first | tid | (it - tid): only the bits of `it` above the
+            // thread index vary inside the loop.  A term whose Z mask misses
+            // them has a constant sign per thread and shares the plain sum
+            // (the norm slot); the others flip with parity(it & vary & z).
             const double p = prob(psi[q]);
             acc[kMaxTermsPerSweep] = __dadd_rn(acc[kMaxTermsPerSweep], p);
 #pragma unroll
             for (int t = 0; t < kMaxTermsPerSweep; ++t) {
-                if (t < a.n_terms) {
-                    const double s = (__popcll(q & a.z[t]) & 1) ? -p : p;
+                if (t < a.n_terms && (a.z[t] & vary) != 0) {
+                    const double s = (__popcll(it & vary & a.z[t]) & 1) ? -p : p;
                     acc[t] = __dadd_rn(acc[t], s);
                 }
             }
@@ -165,6 +171,21 @@ __global__ __launch_bounds__(kThreads) void k_expect(const typename Cx<R>::T* __
                     if (__popcll(i & a.z[t]) & 1) v = -v;
                     acc[t] = __dadd_rn(acc[t], v);
                 }
+            }
+        }
+    }
+    if (!kPairs) {
+        // apply the per-thread constant signs: a term that misses the
+        // varying bits takes the plain sum with the sign of
+        // parity((first | tid) & z); a term that hits them accumulated the
+        // varying part of its sign, and the constant part flips the total
+        const uint64_t fixed = first | threadIdx.x;
+#pragma unroll
+        for (int t = 0; t < kMaxTermsPerSweep; ++t) {
+            if (t < a.n_terms) {
+                const bool neg = (__popcll(fixed & a.z[t]) & 1) != 0;
+                const double v = ((a.z[t] & vary) != 0) ? acc[t] : acc[kMaxTermsPerSweep];
+                acc[t] = neg ? -v : v;
             }
         }
     }

@@ -20,7 +20,7 @@ from __future__ import annotations
 import collections
 import threading
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 
@@ -48,6 +48,7 @@ class Result:
     arrival: float
     admitted: float
     done: float
+    error: str = ""               # set if libsv rejected or failed the request
 
     @property
     def latency(self) -> float:
@@ -156,8 +157,12 @@ class Server:
                     return
                 rid, admitted = self.ready.popleft()
                 req = self.pending.pop(rid)
-            with torch.cuda.stream(h.stream):
-                res = self._run(h, req, admitted)
+            try:
+                with torch.cuda.stream(h.stream):
+                    res = self._run(h, req, admitted)
+            except Exception as e:  # report the failure, keep serving others
+                res = Result(req.rid, np.zeros(0), np.zeros(0, dtype=np.uint64), 0, req.arrival, admitted,
+                             time.monotonic(), error=str(e))
             with self.cv:
                 self.results[rid] = res
                 self.adm.release(self.footprint(req.n))

@@ -160,3 +160,17 @@ def test_handle_create_without_gpu_reports_device_error(P):
     with pytest.raises(P.SVError) as e:
         P.sv_handle_create(0, 0)
     assert e.value.status == P.SV_ERR_DEVICE
+
+
+def test_package_binds_one_hip_runtime():
+    """Importing the package before torch must not load a second HIP/HSA
+    runtime next to torch's (the second one enumerates no device)."""
+    import subprocess
+    import sys
+    code = ("import paper_2308_01999_amd, torch\n"
+            "m = open('/proc/self/maps').read().splitlines()\n"
+            "libs = {l.split()[-1] for l in m if 'libamdhip64' in l or 'libhsa-runtime64' in l}\n"
+            "print(len([x for x in libs if 'amdhip' in x]), len([x for x in libs if 'hsa-runtime' in x]))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, check=True)
+    assert out.stdout.split() == ["1", "1"], out.stdout
