@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--no-kmax-sweep", action="store_true",
+                    help="skip the unfused / kmax 4, 5, 6 comparison on the same circuit")
     ap.add_argument("--gate-sweep", action="store_true",
                     help="also time single k-qubit gates (k = 1..6) on random target sets, both dtypes")
     ap.add_argument("--sweep-sets", type=int, default=100)
@@ -194,6 +196,52 @@ def run_leg(P, W, torch, H, gates, n, dt, kmax, shots, steps, warmup):
     }
     state = st
     return out, state
+
+
+def kmax_leg(P, W, torch, H, gates, n):
+    """The same circuit unfused (one sweep per gate, controlled gates touching
+    only their 2^(n-c) amplitudes) and fused at kmax = 4, 5, 6, complex64 and
+    complex128: one warm pass, then one pass timed with HIP events on the
+    handle's stream around all its sweeps."""
+    out = {}
+    for dt, s in (("c64", 8), ("c128", 16)):
+        st = P.State(H, n, dt)
+        res = {}
+        for kmax in (0, 4, 5, 6):
+            if kmax == 0:
+                entries = P.gate_entries(gates)
+                nbytes = sum(2 * (1 << (n - len(c))) * s for _, _, c, _ in entries)
+                sweeps = len(entries)
+
+                def go():
+                    for t, m, c, cv in entries:
+                        st.apply_matrix(m, t, c, cv)
+            else:
+                f = P.fuse(gates, kmax)
+                sweeps = f.count
+                nbytes = sweeps * 2 * (1 << n) * s
+
+                def go():
+                    P.sv_apply_fused(st.s, f.f)
+            go()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(H.stream)
+            go()
+            e1.record(H.stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            if kmax:
+                f.free()
+            res["unfused" if kmax == 0 else f"kmax{kmax}"] = {
+                "sweeps": sweeps, "apply_ms": round(ms, 2), "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+        base = res["unfused"]["apply_ms"]
+        for k in ("kmax4", "kmax5", "kmax6"):
+            res[k]["speedup_vs_unfused"] = round(base / res[k]["apply_ms"], 2)
+        out[dt] = res
+        st.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(W, P, gates, n, kmax, seconds):
@@ -464,6 +512,11 @@ def main():
         "c64": r64,
         **extra,
     }
+    if not args.no_kmax_sweep:
+        print("[bench] unfused / kmax sweep", file=sys.stderr, flush=True)
+        H4 = P.Handle()
+        line["fusion_widths"] = kmax_leg(P, W, torch, H4, gates, n)
+        H4.close()
     if not args.no_batched:
         print("[bench] batched leg", file=sys.stderr, flush=True)
         H2 = P.Handle()

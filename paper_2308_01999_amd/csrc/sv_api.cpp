@@ -151,6 +151,26 @@ const void* stage_matrix(sv_handle_s* h, const void* host, size_t bytes)
     return h->ws + pos;
 }
 
+char* ensure_aux(sv_handle_s* h, size_t bytes)
+{
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes <= h->aux_bytes) return h->aux;
+    SV_HIP(hipStreamSynchronize(h->stream));
+    if (h->aux) {
+        SV_HIP(hipFree(h->aux));
+        h->aux = nullptr;
+        h->aux_bytes = 0;
+    }
+    const hipError_t e = hipMalloc(&h->aux, bytes);
+    if (e != hipSuccess) {
+        h->aux = nullptr;
+        (void)hipGetLastError();
+        throw Error{SV_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " B of scratch failed"};
+    }
+    h->aux_bytes = bytes;
+    return h->aux;
+}
+
 }  // namespace sv
 
 using namespace sv;
@@ -200,6 +220,7 @@ sv_status_t sv_handle_destroy(sv_handle_t h)
             if (h->seg_event[i]) (void)hipEventDestroy(h->seg_event[i]);
         if (h->pinned) (void)hipHostFree(h->pinned);
         if (h->ws) (void)hipFree(h->ws);
+        if (h->aux) (void)hipFree(h->aux);
         delete h;
         SV_HIP(e);
     });

@@ -57,6 +57,8 @@ struct sv_handle_s {
     int ring_seg = 0;               // segment the ring is writing into
     hipEvent_t seg_event[sv::kMatRingSegments] = {};
     bool seg_event_live[sv::kMatRingSegments] = {};
+    char* aux = nullptr;            // device scratch that grows with the state (sampler prefixes)
+    size_t aux_bytes = 0;
 };
 
 struct sv_state_s {
@@ -109,6 +111,10 @@ void launch_apply(sv_handle_s* h, sv_dtype_t dt, void* psi, const void* mat, con
 
 void launch_set_basis(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, uint64_t x);
 void launch_scale(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, double factor);
+
+// Device scratch of at least `bytes` owned by the handle, grown on demand
+// (the stream is synchronised before an old buffer is freed).
+char* ensure_aux(sv_handle_s* h, size_t bytes);
 
 // Blocking reductions; results land in host memory.
 double run_norm(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n);

@@ -105,7 +105,8 @@ Partition partition(uint64_t items)
     return {nb, items / nb};
 }
 
-constexpr int kMaxTermsPerSweep = 16;
+constexpr int kMaxTermsPerSweep = 32;
+constexpr int kExpectUnroll = 4;  // items loaded ahead per thread
 
 struct ExpectArgs {
     uint64_t per;        // items per block
@@ -135,41 +136,63 @@ __global__ __launch_bounds__(kThreads) void k_expect(const typename Cx<R>::T* __
     const uint64_t first = uint64_t(blockIdx.x) * a.per;
     // index bits that change across one thread's items (x == 0 sweeps)
     const uint64_t vary = (a.per - 1) & ~uint64_t(kThreads - 1);
-    for (uint64_t it = threadIdx.x; it < a.per; it += kThreads) {
-        const uint64_t q = first + it;
-        if (!kPairs) {
-            // q = first | tid | (it - tid): only the bits of `it` above the
-            // thread index vary inside the loop.  A term whose Z mask misses
-            // them has a constant sign per thread and shares the plain sum
-            // (the norm slot); the others flip with parity(it & vary & z).
-            const double p = prob(psi[q]);
-            acc[kMaxTermsPerSweep] = __dadd_rn(acc[kMaxTermsPerSweep], p);
+    using T2 = typename Cx<R>::T;
+    // items it0 + u * kThreads + tid, u < kExpectUnroll: all loads of a
+    // round are issued before any arithmetic, so each thread keeps several
+    // HBM requests in flight
+    for (uint64_t it0 = 0; it0 < a.per; it0 += uint64_t(kExpectUnroll) * kThreads) {
+        T2 vi[kExpectUnroll] = {}, vj[kExpectUnroll] = {};
+        uint64_t ii[kExpectUnroll] = {};
 #pragma unroll
-            for (int t = 0; t < kMaxTermsPerSweep; ++t) {
-                if (t < a.n_terms && (a.z[t] & vary) != 0) {
-                    const double s = (__popcll(it & vary & a.z[t]) & 1) ? -p : p;
-                    acc[t] = __dadd_rn(acc[t], s);
+        for (int u = 0; u < kExpectUnroll; ++u) {
+            const uint64_t it = it0 + uint64_t(u) * kThreads + threadIdx.x;
+            const uint64_t q = first + it;
+            if (!kPairs) {
+                if (it < a.per) vi[u] = psi[q];
+            } else {
+                const uint64_t lo = q & ((uint64_t(1) << a.hbit) - 1);
+                ii[u] = ((q >> a.hbit) << (a.hbit + 1)) | lo;
+                if (it < a.per) {
+                    vi[u] = psi[ii[u]];
+                    vj[u] = psi[ii[u] ^ a.x];
                 }
             }
-        } else {
-            const uint64_t lo = q & ((uint64_t(1) << a.hbit) - 1);
-            const uint64_t i = ((q >> a.hbit) << (a.hbit + 1)) | lo;
-            const uint64_t j = i ^ a.x;
-            const auto ai = psi[i];
-            const auto aj = psi[j];
-            const double ir = double(ai.x), ii = double(ai.y), jr = double(aj.x), ji = double(aj.y);
-            // w = conj(a_j) * a_i
-            const double wr = fma(jr, ir, __dmul_rn(ji, ii));
-            const double wi = fma(jr, ii, -__dmul_rn(ji, ir));
-            acc[kMaxTermsPerSweep] = __dadd_rn(acc[kMaxTermsPerSweep], __dadd_rn(prob(ai), prob(aj)));
+        }
 #pragma unroll
-            for (int t = 0; t < kMaxTermsPerSweep; ++t) {
-                if (t < a.n_terms) {
-                    const int m = a.ny[t] & 3;
-                    double v = (m == 0) ? wr : (m == 1) ? -wi : (m == 2) ? -wr : wi;
-                    v = 2.0 * v;
-                    if (__popcll(i & a.z[t]) & 1) v = -v;
-                    acc[t] = __dadd_rn(acc[t], v);
+        for (int u = 0; u < kExpectUnroll; ++u) {
+            const uint64_t it = it0 + uint64_t(u) * kThreads + threadIdx.x;
+            if (it >= a.per) continue;
+            if (!kPairs) {
+                // q = first | tid | (it - tid): only the bits of `it` above
+                // the thread index vary inside the loop.  A term whose Z
+                // mask misses them has a constant sign per thread and shares
+                // the plain sum (the norm slot); the others flip with
+                // parity(it & vary & z).
+                const double p = prob(vi[u]);
+                acc[kMaxTermsPerSweep] = __dadd_rn(acc[kMaxTermsPerSweep], p);
+#pragma unroll
+                for (int t = 0; t < kMaxTermsPerSweep; ++t) {
+                    if (t < a.n_terms && (a.z[t] & vary) != 0) {
+                        const double sg = (__popcll(it & vary & a.z[t]) & 1) ? -p : p;
+                        acc[t] = __dadd_rn(acc[t], sg);
+                    }
+                }
+            } else {
+                const T2 ai = vi[u], aj = vj[u];
+                const double ir = double(ai.x), im = double(ai.y), jr = double(aj.x), jm = double(aj.y);
+                // w = conj(a_j) * a_i
+                const double wr = fma(jr, ir, __dmul_rn(jm, im));
+                const double wi = fma(jr, im, -__dmul_rn(jm, ir));
+                acc[kMaxTermsPerSweep] = __dadd_rn(acc[kMaxTermsPerSweep], __dadd_rn(prob(ai), prob(aj)));
+#pragma unroll
+                for (int t = 0; t < kMaxTermsPerSweep; ++t) {
+                    if (t < a.n_terms) {
+                        const int m = a.ny[t] & 3;
+                        double v = (m == 0) ? wr : (m == 1) ? -wi : (m == 2) ? -wr : wi;
+                        v = 2.0 * v;
+                        if (__popcll(ii[u] & a.z[t]) & 1) v = -v;
+                        acc[t] = __dadd_rn(acc[t], v);
+                    }
                 }
             }
         }
@@ -189,6 +212,7 @@ __global__ __launch_bounds__(kThreads) void k_expect(const typename Cx<R>::T* __
             }
         }
     }
+#pragma unroll
     for (int t = 0; t <= kMaxTermsPerSweep; ++t) {
         if (t < a.n_terms || t == kMaxTermsPerSweep) {
             const double s = block_sum(acc[t], lds);
@@ -212,27 +236,40 @@ __global__ __launch_bounds__(kThreads) void k_finish_sums(const double* __restri
 
 // ----------------------------------------------------------------- sampler
 //
-// Two-level inverse CDF whose boundaries are monotone bit for bit, so the
-// search is always consistent and never lands on a zero-probability index:
-//   chunk sums S[c] (any fixed order);
-//   chunk boundaries B[0..nc] from S by per-thread sequential prefixes plus
-//     a sequential pass over thread totals (monotone, and B[c+1] == B[c]
-//     whenever S[c] == 0);
-//   for a shot, r = u * B[nc]; chunk = smallest c with r < B[c+1];
-//   inside the chunk, sub-tiles of 4096 amplitudes are scanned in order with
-//     a running carry; a sub-tile's inclusive prefix is built the same way
-//     (16 contiguous values per thread, sequential thread offsets), and the
-//     outcome is the smallest i with r < B[c] + (carry + prefix_i).
-// Every boundary that follows a zero-probability amplitude repeats the
-// previous boundary exactly, so such an amplitude can never be the first
-// index whose boundary exceeds r.
+// Three-level inverse CDF whose boundaries are monotone bit for bit, so the
+// search is always consistent and never lands on a zero-probability index.
+// The state splits into nc chunks of cs amplitudes, each chunk into blocks
+// of W = 64 amplitudes (W = dim below 64):
+//   block sums: the sequential FP64 sum of a block's probabilities in index
+//     order;
+//   block prefixes C: inside a chunk, the sequential running sum of its
+//     block sums (C[b] = C[b-1] + sum_b); the chunk total S[c] is its last C;
+//   chunk boundaries B[0..nc] from S by per-thread sequential prefixes plus a
+//     sequential pass over thread totals (B[c+1] == B[c] whenever S[c] == 0);
+//   for a shot, r = u * B[nc]; chunk c = smallest c with r < B[c+1]; block
+//     b = smallest b with r < B[c] + C[b]; inside the block, the outcome is
+//     the smallest i with r < B[c] + (E + l_i), where E = C[b-1] (0 for the
+//     first block) and l_i the sequential running sum of the block's
+//     probabilities.  Its last value equals the block sum bit for bit, so
+//     E + l_last == C[b] and the boundaries join up exactly.
+// A zero-probability amplitude repeats the previous boundary exactly (inside
+// a block, across blocks, and at the start of a chunk, which only a shot with
+// r >= B[c] reaches), so it can never be the first index whose boundary
+// exceeds r.
+//
+// Only the block prefixes need the whole state: one coalesced read sweep.
+// Each shot then reads one block of W amplitudes, so a sample costs about one
+// state read plus W amplitudes per shot, at any number of shots.
 
 struct SampleLayout {
     uint64_t nc;     // chunks
     uint64_t cs;     // amplitudes per chunk
+    int w;           // amplitudes per block
+    uint64_t nbk;    // blocks per chunk
 };
 
-constexpr uint64_t kSub = 4096;  // amplitudes per sub-tile of a chunk
+constexpr int kBlk = 64;         // amplitudes per block (states of >= 64 amplitudes)
+constexpr uint64_t kSub = 4096;  // amplitudes per LDS sub-tile of the prefix sweep
 
 SampleLayout sample_layout(int n)
 {
@@ -240,19 +277,71 @@ SampleLayout sample_layout(int n)
     uint64_t nc = dim / (4 * kSub);
     if (nc < 1) nc = 1;
     if (nc > 65536) nc = 65536;
-    return {nc, dim / nc};
+    const uint64_t cs = dim / nc;
+    const int w = int(std::min<uint64_t>(kBlk, cs));
+    return {nc, cs, w, cs / uint64_t(w)};
 }
 
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_chunk_sums(const typename Cx<R>::T* __restrict__ psi,
-                                                        uint64_t nc, uint64_t cs, double* __restrict__ S)
+__device__ __forceinline__ double readlane_f64(double v, int lane)
 {
-    __shared__ double lds[kThreads];
-    for (uint64_t c = blockIdx.x; c < nc; c += gridDim.x) {
-        double acc = 0.0;
-        for (uint64_t i = threadIdx.x; i < cs; i += kThreads) acc = __dadd_rn(acc, prob(psi[c * cs + i]));
-        const double s = block_sum(acc, lds);
-        if (threadIdx.x == 0) S[c] = s;
+    const uint64_t b = uint64_t(__double_as_longlong(v));
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(b)), lane));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(b >> 32)), lane));
+    return __longlong_as_double((long long)((uint64_t(hi) << 32) | lo));
+}
+
+// Block prefixes C and chunk totals S.  One workgroup per chunk (grid-
+// stride); a chunk is read in sub-tiles of up to kSub amplitudes, coalesced,
+// whose probabilities go to LDS as rows of one block each (padded by one
+// slot).  Lane l of wave 0 then sums row l in index order, and the wave
+// extends the chunk's running prefix over the rows in order, lane by lane,
+// with the running value held identically in every lane.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_block_prefix(const typename Cx<R>::T* __restrict__ psi,
+                                                          SampleLayout L, double* __restrict__ C,
+                                                          double* __restrict__ S)
+{
+    using T2 = typename Cx<R>::T;
+    constexpr int kRow = kBlk + 1;
+    __shared__ double p[(kSub / kBlk) * kRow];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const uint64_t sub_len = L.cs < kSub ? L.cs : kSub;
+    const uint64_t nsub = L.cs / sub_len;
+    const int rows = int(sub_len / uint64_t(L.w));
+    const int wshift = __ffs(L.w) - 1;
+    for (uint64_t c = blockIdx.x; c < L.nc; c += gridDim.x) {
+        double carry = 0.0;
+        for (uint64_t sb = 0; sb < nsub; ++sb) {
+            const T2* src = psi + c * L.cs + sb * sub_len;
+            if (sub_len == kSub) {
+                constexpr int kPer = int(kSub) / kThreads;
+                T2 v[kPer];
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) v[u] = src[u * kThreads + tid];
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) {
+                    const int i = u * kThreads + tid;
+                    p[(i >> wshift) * kRow + (i & (L.w - 1))] = prob(v[u]);
+                }
+            } else {
+                for (int i = tid; i < int(sub_len); i += kThreads)
+                    p[(i >> wshift) * kRow + (i & (L.w - 1))] = prob(src[i]);
+            }
+            __syncthreads();
+            if (tid < 64) {
+                double sum = 0.0;
+                if (lane < rows)
+                    for (int j = 0; j < L.w; ++j) sum = __dadd_rn(sum, p[lane * kRow + j]);
+                double mine = 0.0;
+                for (int l = 0; l < rows; ++l) {
+                    carry = __dadd_rn(carry, readlane_f64(sum, l));
+                    if (lane == l) mine = carry;
+                }
+                if (lane < rows) C[c * L.nbk + sb * uint64_t(rows) + lane] = mine;
+            }
+            __syncthreads();
+        }
+        if (tid == 0) S[c] = carry;
     }
 }
 
@@ -294,15 +383,20 @@ __device__ __forceinline__ double shot_r(double u, double total)
     return r;
 }
 
-__global__ __launch_bounds__(kThreads) void k_locate(const double* __restrict__ u, uint64_t ns,
-                                                    const double* __restrict__ B, uint64_t nc,
-                                                    uint32_t* __restrict__ chunk_of,
-                                                    uint32_t* __restrict__ counts)
+// One thread per shot: chunk by binary search over B, block by binary search
+// over the chunk's C, then the block's amplitudes in order.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_resolve(const typename Cx<R>::T* __restrict__ psi,
+                                                     SampleLayout L, const double* __restrict__ B,
+                                                     const double* __restrict__ C,
+                                                     const double* __restrict__ u, uint64_t ns,
+                                                     uint64_t* __restrict__ idx_out)
 {
+    using T2 = typename Cx<R>::T;
     const uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (s >= ns) return;
-    const double r = shot_r(u[s], B[nc]);
-    uint64_t lo = 0, hi = nc - 1;  // smallest c with r < B[c+1]
+    const double r = shot_r(u[s], B[L.nc]);
+    uint64_t lo = 0, hi = L.nc - 1;  // smallest c with r < B[c+1]
     while (lo < hi) {
         const uint64_t mid = lo + (hi - lo) / 2;
         if (r < B[mid + 1])
@@ -310,148 +404,52 @@ __global__ __launch_bounds__(kThreads) void k_locate(const double* __restrict__ 
         else
             lo = mid + 1;
     }
-    chunk_of[s] = uint32_t(lo);
-    atomicAdd(&counts[lo], 1u);
-}
-
-// Exclusive scan of integer counts (exact in any order); single block.
-__global__ __launch_bounds__(kScanThreads) void k_scan_counts(const uint32_t* __restrict__ counts,
-                                                             uint64_t nc, uint32_t* __restrict__ start,
-                                                             uint32_t* __restrict__ cursor)
-{
-    __shared__ uint32_t tot[kScanThreads];
-    const uint64_t per = (nc + kScanThreads - 1) / kScanThreads;
-    const uint64_t lo = std::min<uint64_t>(nc, threadIdx.x * per);
-    const uint64_t hi = std::min<uint64_t>(nc, lo + per);
-    uint32_t run = 0;
-    for (uint64_t c = lo; c < hi; ++c) run += counts[c];
-    tot[threadIdx.x] = run;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t o = 0;
-        for (int t = 0; t < kScanThreads; ++t) {
-            const uint32_t v = tot[t];
-            tot[t] = o;
-            o += v;
+    const uint64_t c = lo;
+    const double base = B[c];
+    const double* cc = C + c * L.nbk;
+    const T2* chunk = psi + c * L.cs;
+    uint64_t found = ~uint64_t(0);
+    if (r < __dadd_rn(base, cc[L.nbk - 1])) {
+        uint64_t b0 = 0, b1 = L.nbk - 1;  // smallest b with r < base + C[b]
+        while (b0 < b1) {
+            const uint64_t mid = b0 + (b1 - b0) / 2;
+            if (r < __dadd_rn(base, cc[mid]))
+                b1 = mid;
+            else
+                b0 = mid + 1;
+        }
+        const double e = b0 ? cc[b0 - 1] : 0.0;
+        const T2* blk = chunk + b0 * uint64_t(L.w);
+        double run = 0.0;
+        constexpr int kAhead = 16;
+        for (int j0 = 0; j0 < L.w && found == ~uint64_t(0); j0 += kAhead) {
+            T2 v[kAhead];
+#pragma unroll
+            for (int j = 0; j < kAhead; ++j)
+                if (j0 + j < L.w) v[j] = blk[j0 + j];
+#pragma unroll
+            for (int j = 0; j < kAhead; ++j) {
+                if (j0 + j < L.w && found == ~uint64_t(0)) {
+                    run = __dadd_rn(run, prob(v[j]));
+                    if (r < __dadd_rn(base, __dadd_rn(e, run))) found = c * L.cs + b0 * uint64_t(L.w) + uint64_t(j0 + j);
+                }
+            }
         }
     }
-    __syncthreads();
-    uint32_t o = tot[threadIdx.x];
-    for (uint64_t c = lo; c < hi; ++c) {
-        start[c] = o;
-        cursor[c] = 0;
-        o += counts[c];
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_bucket(const uint32_t* __restrict__ chunk_of, uint64_t ns,
-                                                    const uint32_t* __restrict__ start,
-                                                    uint32_t* __restrict__ cursor, uint32_t* __restrict__ list,
-                                                    uint64_t* __restrict__ idx_out)
-{
-    const uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= ns) return;
-    const uint32_t c = chunk_of[s];
-    const uint32_t pos = atomicAdd(&cursor[c], 1u);
-    list[start[c] + pos] = uint32_t(s);
-    idx_out[s] = ~uint64_t(0);
-}
-
-// One workgroup per chunk that holds shots.  The chunk is read once,
-// coalesced, in sub-tiles; each sub-tile's probabilities go to LDS (padded
-// by one slot per 16 so the per-thread contiguous scans are conflict-free),
-// are prefix-summed there, and every unresolved shot of the chunk whose r
-// falls below the sub-tile's upper boundary is resolved by binary search.
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_resolve(const typename Cx<R>::T* __restrict__ psi,
-                                                     SampleLayout L, const double* __restrict__ B,
-                                                     const uint32_t* __restrict__ counts,
-                                                     const uint32_t* __restrict__ start,
-                                                     const uint32_t* __restrict__ list,
-                                                     const double* __restrict__ u,
-                                                     uint64_t* __restrict__ idx_out)
-{
-    constexpr int kPad = 16;
-    __shared__ double cdf[kSub + kSub / kPad];
-    __shared__ double off[kThreads];
-    const uint64_t sub_len = L.cs < kSub ? L.cs : kSub;
-    const uint64_t nsub = L.cs / sub_len;
-    const int seg = sub_len >= kThreads ? int(sub_len / kThreads) : 1;  // values per thread
-    const int active = int(sub_len / seg);                            // threads with a segment
-    const double total = B[L.nc];
-    const int tid = threadIdx.x;
-    auto slot = [](int i) { return i + i / kPad; };
-    for (uint64_t c = blockIdx.x; c < L.nc; c += gridDim.x) {
-        const uint32_t cnt = counts[c];
-        if (cnt == 0) continue;
-        const uint64_t c0 = c * L.cs;
-        const double bc = B[c];
-        const uint32_t* shots = list + start[c];
-        double carry = 0.0;
-        for (uint64_t sidx = 0; sidx < nsub; ++sidx) {
-            const uint64_t s0 = c0 + sidx * sub_len;
-            for (int i = tid; i < int(sub_len); i += kThreads) cdf[slot(i)] = prob(psi[s0 + i]);
-            __syncthreads();
-            double run = 0.0;
-            if (tid < active) {
-                for (int i = 0; i < seg; ++i) {
-                    run = __dadd_rn(run, cdf[slot(tid * seg + i)]);
-                    cdf[slot(tid * seg + i)] = run;
-                }
-                off[tid] = run;
+    if (found == ~uint64_t(0)) {
+        // rounding left r at or past B[c] + C[last] (B[c+1] comes from a
+        // different summation order): take the chunk's last amplitude with
+        // non-zero probability (the chunk has one, since S[c] > 0 whenever
+        // the chunk can be chosen)
+        found = c * L.cs;
+        for (uint64_t i = L.cs; i-- > 0;) {
+            if (prob(chunk[i]) > 0.0) {
+                found = c * L.cs + i;
+                break;
             }
-            __syncthreads();
-            if (tid == 0) {
-                double o = 0.0;
-                for (int t = 0; t < active; ++t) {
-                    const double v = off[t];
-                    off[t] = o;
-                    o = __dadd_rn(o, v);
-                }
-            }
-            __syncthreads();
-            if (tid < active) {
-                const double o = off[tid];
-                for (int i = 0; i < seg; ++i) cdf[slot(tid * seg + i)] = __dadd_rn(o, cdf[slot(tid * seg + i)]);
-            }
-            __syncthreads();
-            const double last = cdf[slot(int(sub_len) - 1)];
-            const double upper = __dadd_rn(bc, __dadd_rn(carry, last));
-            for (uint32_t j = tid; j < cnt; j += kThreads) {
-                const uint32_t shot = shots[j];
-                if (idx_out[shot] != ~uint64_t(0)) continue;
-                const double r = shot_r(u[shot], total);
-                if (!(r < upper)) continue;
-                int lo = 0, hi = int(sub_len) - 1;  // smallest i with r < bc + (carry + cdf_i)
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (r < __dadd_rn(bc, __dadd_rn(carry, cdf[slot(mid)])))
-                        hi = mid;
-                    else
-                        lo = mid + 1;
-                }
-                idx_out[shot] = s0 + uint64_t(lo);
-            }
-            carry = __dadd_rn(carry, last);
-            __syncthreads();
         }
-        // rounding left r past the chunk's own total (the chunk sum S[c]
-        // and the in-chunk scan add in different orders): take the last
-        // amplitude of the chunk with non-zero probability
-        for (uint32_t j = tid; j < cnt; j += kThreads) {
-            const uint32_t shot = shots[j];
-            if (idx_out[shot] != ~uint64_t(0)) continue;
-            uint64_t found = c0;
-            for (uint64_t i = L.cs; i-- > 0;) {
-                if (prob(psi[c0 + i]) > 0.0) {
-                    found = c0 + i;
-                    break;
-                }
-            }
-            idx_out[shot] = found;
-        }
-        __syncthreads();
     }
+    idx_out[s] = found;
 }
 
 struct BitArgs {
@@ -564,6 +562,7 @@ void run_sample_t(sv_handle_s* h, const void* psi_v, int n, const double* u, int
     using T2 = typename Cx<R>::T;
     const T2* psi = static_cast<const T2*>(psi_v);
     const SampleLayout L = sample_layout(n);
+    double* C = reinterpret_cast<double*>(ensure_aux(h, sizeof(double) * L.nc * L.nbk));
     char* w = h->ws + kMatRingBytes;
     auto take = [&](size_t bytes) {
         char* p = w;
@@ -572,23 +571,18 @@ void run_sample_t(sv_handle_s* h, const void* psi_v, int n, const double* u, int
     };
     double* S = reinterpret_cast<double*>(take(sizeof(double) * L.nc));
     double* B = reinterpret_cast<double*>(take(sizeof(double) * (L.nc + 1)));
-    uint32_t* counts = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * L.nc));
-    uint32_t* start = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * L.nc));
-    uint32_t* cursor = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * L.nc));
     const size_t used = size_t(w - h->ws);
     if (used >= h->ws_bytes) throw Error{SV_ERR_OUT_OF_MEMORY, "workspace too small for the sampler"};
-    const size_t per_shot = sizeof(double) + 2 * sizeof(uint32_t) + sizeof(uint64_t);
+    const size_t per_shot = sizeof(double) + sizeof(uint64_t);
     int64_t batch = int64_t((h->ws_bytes - used) / per_shot) - 1024;
     if (batch > (int64_t(1) << 22)) batch = int64_t(1) << 22;
     if (batch < 1) throw Error{SV_ERR_OUT_OF_MEMORY, "workspace too small for the sampler"};
     double* du = reinterpret_cast<double*>(take(sizeof(double) * batch));
-    uint32_t* chunk_of = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * batch));
-    uint32_t* list = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * batch));
     uint64_t* didx = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * batch));
     if (size_t(w - h->ws) > h->ws_bytes) throw Error{SV_ERR_INTERNAL, "sampler workspace layout"};
 
-    hipLaunchKernelGGL((k_chunk_sums<R>), dim3(unsigned(std::min<uint64_t>(L.nc, uint64_t(h->cu_count) * 16))),
-                       dim3(kThreads), 0, h->stream, psi, L.nc, L.cs, S);
+    hipLaunchKernelGGL((k_block_prefix<R>), dim3(unsigned(std::min<uint64_t>(L.nc, uint64_t(h->cu_count) * 8))),
+                       dim3(kThreads), 0, h->stream, psi, L, C, S);
     SV_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(kScanThreads), 0, h->stream, S, L.nc, B);
     SV_HIP(hipGetLastError());
@@ -603,16 +597,8 @@ void run_sample_t(sv_handle_s* h, const void* psi_v, int n, const double* u, int
     for (int64_t s0 = 0; s0 < n_shots; s0 += batch) {
         const uint64_t ns = uint64_t(std::min<int64_t>(batch, n_shots - s0));
         SV_HIP(hipMemcpyAsync(du, u + s0, sizeof(double) * ns, hipMemcpyHostToDevice, h->stream));
-        SV_HIP(hipMemsetAsync(counts, 0, sizeof(uint32_t) * L.nc, h->stream));
         const unsigned sg = unsigned((ns + kThreads - 1) / kThreads);
-        hipLaunchKernelGGL(k_locate, dim3(sg), dim3(kThreads), 0, h->stream, du, ns, B, L.nc, chunk_of, counts);
-        SV_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(kScanThreads), 0, h->stream, counts, L.nc, start, cursor);
-        SV_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_bucket, dim3(sg), dim3(kThreads), 0, h->stream, chunk_of, ns, start, cursor, list, didx);
-        SV_HIP(hipGetLastError());
-        hipLaunchKernelGGL((k_resolve<R>), dim3(unsigned(std::min<uint64_t>(L.nc, uint64_t(h->cu_count) * 16))),
-                           dim3(kThreads), 0, h->stream, psi, L, B, counts, start, list, du, didx);
+        hipLaunchKernelGGL((k_resolve<R>), dim3(sg), dim3(kThreads), 0, h->stream, psi, L, B, C, du, ns, didx);
         SV_HIP(hipGetLastError());
         if (n_bits > 0) {
             hipLaunchKernelGGL(k_extract_bits, dim3(sg), dim3(kThreads), 0, h->stream, didx, ns, ba);

@@ -333,6 +333,31 @@ def test_sampling_zero_probability_blocks(P, H):
     st.close()
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n", [5, 14, 18])
+def test_sampling_block_and_chunk_boundaries(P, H, dt, n):
+    # mass on both sides of 64-amplitude block and chunk boundaries, zeros in
+    # between, and amplitudes far too small to move a running sum: every
+    # outcome must carry non-zero probability and obey the epsilon rule
+    dim = 1 << n
+    psi = np.zeros(dim, dtype=np.complex128)
+    heavy = sorted({i % dim for i in (0, 63, 64, 127, 4095, 4096, 16383, 16384, dim - 1)})
+    psi[heavy] = 1.0
+    psi[heavy[1:-1]] = 0.5j
+    for i in (1, 65, 4097):
+        if i < dim and psi[i] == 0:
+            psi[i] = 1e-13  # probability 1e-26: absorbed by the prefix
+    psi /= np.linalg.norm(psi)
+    st = _state(P, H, n, dt, basis=None)
+    P.sv_copy_from_host(st.s, psi.astype(P.NP_DTYPES[st.dt]))
+    gpu = st.to_numpy()
+    u = np.concatenate([W.uniforms(40000, 2 + n), np.linspace(0.0, 1.0, 4097)[:-1]])
+    got = st.sample(u)
+    assert (np.abs(gpu[got]) > 0).all()
+    _eps_rule(gpu, gpu.astype(np.complex128), u, got)
+    st.close()
+
+
 # ---------------------------------------------------------------- edge cases
 
 def test_invalid_arguments_leave_state_untouched(P, H):
