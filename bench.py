@@ -352,6 +352,8 @@ def batched_leg(P, W, torch, H, count, steps, warmup, sample):
     widths = {str(n): b.fusion_width(n) for n in sorted(set(ns))}
     blocks = b.blocks()
     state_gb = sum((1 << n) * 8 for n in ns) / 1e9
+    # every fused block reads and writes its state once
+    sweep_bytes = sum(int(nb) * 2 * (1 << n) * 8 for nb, n in zip(blocks, ns))
     b.close()
     # baseline: plain complex128 per-circuit path on a sample
     rng = np.random.default_rng(1)
@@ -378,6 +380,8 @@ def batched_leg(P, W, torch, H, count, steps, warmup, sample):
         "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
         "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
         "circuits_per_s": round(count / float(np.median(kts)), 1),
+        "sweep_GB": round(sweep_bytes / 1e9, 2),
+        "effective_GBps": round(sweep_bytes / float(np.median(kts)) / 1e9, 1),
         "fusion_widths": widths,
         "fused_blocks_total": int(blocks.sum()),
         "host_prep_s": round(prep, 3),

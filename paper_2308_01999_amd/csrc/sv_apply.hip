@@ -281,6 +281,9 @@ constexpr int kTileVecs = 8;  // 16-byte vectors per thread per tile (32 KiB / 2
 #ifndef SV_TILES_PER_WG_MAX
 #define SV_TILES_PER_WG_MAX 64
 #endif
+#ifndef SV_TILES_PER_WG_MAX_K5
+#define SV_TILES_PER_WG_MAX_K5 4
+#endif
 
 typedef float nf4 __attribute__((ext_vector_type(4)));
 typedef double nd2 __attribute__((ext_vector_type(2)));
@@ -343,18 +346,58 @@ __device__ __forceinline__ uint64_t tile_base(uint64_t t, const TileArgs& a)
     return insert_zero_bits(t << a.L, a.hi_pos, a.n_hi);
 }
 
+// Workgroup ids are handed round-robin to the chip's 8 XCDs (each with its
+// own L2 and address-translation cache).  With SV_TILE_XCD, workgroup b takes
+// tile group (b % 8) * (G / 8) + b / 8, so each XCD sweeps one contiguous
+// eighth of the state instead of every eighth tile group.
+#ifndef SV_TILE_XCD
+#define SV_TILE_XCD 0
+#endif
+constexpr uint32_t kXcds = 8;
+
+__device__ __forceinline__ uint64_t tile_group()
+{
+    const uint32_t b = blockIdx.x, g = gridDim.x;
+    if (SV_TILE_XCD && g % kXcds == 0) return uint64_t(b % kXcds) * (g / kXcds) + b / kXcds;
+    return b;
+}
+
+// LDS slot of tile-local amplitude a: its low five bits are XORed with bits
+// 5-9.  The gathers read, per instruction, the amplitudes of consecutive
+// groups; when the low target bits spread those groups 2^m amplitudes apart
+// (m <= 5), they would all map to one LDS bank without this.  Bijective on
+// every aligned block of 1024 amplitudes, so it only permutes a tile.
+__device__ __forceinline__ int lds_swz(int a) { return a ^ ((a >> 5) & 31); }
+
+// complex64 staging moves pairs (i, i + 1), i even: both land in one aligned
+// 16-byte slot, in swapped order when bit 0 of the XOR is set.
+__device__ __forceinline__ int pair_slot(int i) { return i ^ ((i >> 5) & 30); }
+__device__ __forceinline__ bool pair_swapped(int i) { return ((i >> 5) & 1) != 0; }
+__device__ __forceinline__ float4 swap_pair(const float4 v, bool sw)
+{
+    return sw ? float4{v.z, v.w, v.x, v.y} : v;
+}
+
+// With SV_K5_A2_FLY the third operand Re M + Im M is summed in registers
+// instead of kept in LDS: 40 KiB of LDS per workgroup instead of 44, so four
+// workgroups fit a CU's 160 KiB instead of three.
+#ifndef SV_K5_A2_FLY
+#define SV_K5_A2_FLY 0
+#endif
+constexpr int kK5AParts = SV_K5_A2_FLY ? 2 : 3;
+
 __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k5(float2* __restrict__ psi,
                                                              const float4* __restrict__ mats, TileArgs a)
 {
     __shared__ float4 lds[kTileThreads * kTileVecs];
     // the packed A operands (same for every wave): 3 x 64 lanes x 4 float4,
     // read back four k-steps at a time so only 12 of them are live at once
-    __shared__ float4 amat[3 * 64 * 4];
-    const uint64_t t0 = uint64_t(blockIdx.x) * a.tiles_per_wg;
+    __shared__ float4 amat[kK5AParts * 64 * 4];
+    const uint64_t t0 = tile_group() * a.tiles_per_wg;
     if (t0 >= a.n_tiles) return;
     const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 31, half = lane >> 5;
-    for (int e = tid; e < 3 * 64 * 4; e += kTileThreads) amat[e] = mats[e];
+    for (int e = tid; e < kK5AParts * 64 * 4; e += kTileThreads) amat[e] = mats[e];
     uint64_t roff[kTileVecs];
     uint32_t poff[kTileVecs];
     tile_offsets<2>(a, roff, poff);
@@ -370,7 +413,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k5(float2* __restrict
     SV_REP8(SV_LOAD)
 #undef SV_LOAD
     for (uint64_t t = t0; t < t1; ++t) {
-#define SV_STAGE(u) lds[u * kTileThreads + tid] = buf##u;
+#define SV_STAGE(u)                                                                        \
+    {                                                                                      \
+        const int i = (u * kTileThreads + tid) * 2;                                        \
+        *reinterpret_cast<float4*>(lds2 + pair_slot(i)) = swap_pair(buf##u, pair_swapped(i)); \
+    }
         SV_REP8(SV_STAGE)
 #undef SV_STAGE
         __syncthreads();
@@ -383,13 +430,14 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k5(float2* __restrict
         }
         float2 x[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) x[j] = lds2[pin + a.lds_off[2 * j]];
+        for (int j = 0; j < 16; ++j) x[j] = lds2[lds_swz(pin + a.lds_off[2 * j])];
         f32x16 p1 = {0}, p2 = {0}, p3 = {0};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const float4 vr = amat[(0 * 64 + lane) * 4 + q];
             const float4 vi = amat[(1 * 64 + lane) * 4 + q];
-            const float4 vs = amat[(2 * 64 + lane) * 4 + q];
+            const float4 vs = (kK5AParts == 3) ? amat[((kK5AParts - 1) * 64 + lane) * 4 + q]
+                                               : float4{vr.x + vi.x, vr.y + vi.y, vr.z + vi.z, vr.w + vi.w};
             const float ar[4] = {vr.x, vr.y, vr.z, vr.w};
             const float ai[4] = {vi.x, vi.y, vi.z, vi.w};
             const float as[4] = {vs.x, vs.y, vs.z, vs.w};
@@ -403,11 +451,14 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k5(float2* __restrict
         }
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-            lds2[pout + a.lds_off[8 * (r / 4) + (r % 4)]] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
+            lds2[lds_swz(pout + a.lds_off[8 * (r / 4) + (r % 4)])] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < kTileVecs; ++u)
-            gstore(reinterpret_cast<float4*>(psi + base + roff[u] + poff[u]), lds[u * kTileThreads + tid]);
+        for (int u = 0; u < kTileVecs; ++u) {
+            const int i = (u * kTileThreads + tid) * 2;
+            gstore(reinterpret_cast<float4*>(psi + base + roff[u] + poff[u]),
+                   swap_pair(*reinterpret_cast<const float4*>(lds2 + pair_slot(i)), pair_swapped(i)));
+        }
         base = nbase;
         __syncthreads();
     }
@@ -417,7 +468,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict
                                                              const float4* __restrict__ mats, TileArgs a)
 {
     __shared__ float4 lds[kTileThreads * kTileVecs];
-    const uint64_t t0 = uint64_t(blockIdx.x) * a.tiles_per_wg;
+    const uint64_t t0 = tile_group() * a.tiles_per_wg;
     if (t0 >= a.n_tiles) return;
     const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, q = lane >> 4;
@@ -441,7 +492,11 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict
     SV_REP8(SV_LOAD)
 #undef SV_LOAD
     for (uint64_t t = t0; t < t1; ++t) {
-#define SV_STAGE(u) lds[u * kTileThreads + tid] = buf##u;
+#define SV_STAGE(u)                                                                        \
+    {                                                                                      \
+        const int i = (u * kTileThreads + tid) * 2;                                        \
+        *reinterpret_cast<float4*>(lds2 + pair_slot(i)) = swap_pair(buf##u, pair_swapped(i)); \
+    }
         SV_REP8(SV_STAGE)
 #undef SV_STAGE
         __syncthreads();
@@ -456,17 +511,20 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict
         for (int ct = 0; ct < 4; ++ct) {
             float2 x[4];
 #pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) x[s4] = lds2[pb[ct] + lin + a.lds_off[4 * s4]];
+            for (int s4 = 0; s4 < 4; ++s4) x[s4] = lds2[lds_swz(pb[ct] + lin + a.lds_off[4 * s4])];
             f32x4 p1 = {0}, p2 = {0}, p3 = {0};
             mfma_c64k4(ar, ai, as, x, p1, p2, p3);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                lds2[pb[ct] + lout + a.lds_off[r]] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
+                lds2[lds_swz(pb[ct] + lout + a.lds_off[r])] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
         }
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < kTileVecs; ++u)
-            gstore(reinterpret_cast<float4*>(psi + base + roff[u] + poff[u]), lds[u * kTileThreads + tid]);
+        for (int u = 0; u < kTileVecs; ++u) {
+            const int i = (u * kTileThreads + tid) * 2;
+            gstore(reinterpret_cast<float4*>(psi + base + roff[u] + poff[u]),
+                   swap_pair(*reinterpret_cast<const float4*>(lds2 + pair_slot(i)), pair_swapped(i)));
+        }
         base = nbase;
         __syncthreads();
     }
@@ -479,7 +537,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restri
                                                               const double2* __restrict__ mats, TileArgs a)
 {
     __shared__ double2 lds[kTileThreads * kTileVecs];
-    const uint64_t t0 = uint64_t(blockIdx.x) * a.tiles_per_wg;
+    const uint64_t t0 = tile_group() * a.tiles_per_wg;
     if (t0 >= a.n_tiles) return;
     const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, q = lane >> 4;
@@ -506,7 +564,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restri
     SV_REP8(SV_LOAD)
 #undef SV_LOAD
     for (uint64_t t = t0; t < t1; ++t) {
-#define SV_STAGE(u) lds[u * kTileThreads + tid] = buf##u;
+#define SV_STAGE(u) lds[lds_swz(u * kTileThreads + tid)] = buf##u;
         SV_REP8(SV_STAGE)
 #undef SV_STAGE
         __syncthreads();
@@ -519,7 +577,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restri
         }
         double2 x[8];
 #pragma unroll
-        for (int s8 = 0; s8 < 8; ++s8) x[s8] = lds[pq + a.lds_off[4 * s8]];
+        for (int s8 = 0; s8 < 8; ++s8) x[s8] = lds[lds_swz(pq + a.lds_off[4 * s8])];
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
             f64x4 p1 = {0}, p2 = {0}, p3 = {0};
@@ -531,11 +589,12 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restri
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                lds[pq + a.lds_off[16 * rt + 4 * v]] = double2{p1[v] - p2[v], p3[v] - p1[v] - p2[v]};
+                lds[lds_swz(pq + a.lds_off[16 * rt + 4 * v])] = double2{p1[v] - p2[v], p3[v] - p1[v] - p2[v]};
         }
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < kTileVecs; ++u) gstore(psi + base + roff[u] + poff[u], lds[u * kTileThreads + tid]);
+        for (int u = 0; u < kTileVecs; ++u)
+            gstore(psi + base + roff[u] + poff[u], lds[lds_swz(u * kTileThreads + tid)]);
         base = nbase;
         __syncthreads();
     }
@@ -691,7 +750,8 @@ TileArgs make_tile_args(const GateDesc& d, int n, int tb, int cu_count)
     const uint64_t target_wgs = uint64_t(cu_count) * SV_TILE_WGS_PER_CU;
     uint64_t per = t.n_tiles / target_wgs;
     if (per < 1) per = 1;
-    if (per > SV_TILES_PER_WG_MAX) per = SV_TILES_PER_WG_MAX;
+    const uint64_t cap = d.k >= 5 ? SV_TILES_PER_WG_MAX_K5 : SV_TILES_PER_WG_MAX;
+    if (per > cap) per = cap;
     t.tiles_per_wg = per;
     return t;
 }

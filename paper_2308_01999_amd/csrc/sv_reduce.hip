@@ -106,120 +106,201 @@ Partition partition(uint64_t items)
 }
 
 constexpr int kMaxTermsPerSweep = 32;
-constexpr int kExpectUnroll = 4;  // items loaded ahead per thread
+constexpr int kMaxActive = 16;     // Z-type terms that need per-item work in one sweep
+constexpr int kExpectUnroll = 4;   // items loaded per thread per round
 
 struct ExpectArgs {
     uint64_t per;        // items per block
     uint64_t x;          // common X/Y mask of the terms
     int32_t hbit;        // highest bit of x (pair sweeps)
     int32_t n_terms;
+    int32_t n_active;    // x == 0: terms [0, n_active) meet the varying bits
     uint64_t z[kMaxTermsPerSweep];
     int32_t ny[kMaxTermsPerSweep];
 };
 
-// Per block: FP64 partials of every term and of the norm, written to
-// part[t * nb + block] (t = n_terms is the norm).
-//
-// x == 0: item i contributes |psi_i|^2 * (-1)^popcount(i & z).
-// x != 0: item q is the pair (i, j = i ^ x) with bit hbit of i clear; with
-//         w = conj(psi_j) psi_i the pair contributes
-//         2 Re(w * i^ny) * (-1)^popcount(i & z), because P|i> = ph(i)|j> and
-//         ph(j) = conj(ph(i)) for a Hermitian Pauli string.
-template <typename R, bool kPairs>
-__global__ __launch_bounds__(kThreads) void k_expect(const typename Cx<R>::T* __restrict__ psi,
-                                                    ExpectArgs a, double* __restrict__ part)
+// Fixed-order sum over the 64 lanes of a wave (butterfly), valid in every lane.
+__device__ __forceinline__ double wave_sum(double v)
 {
-    __shared__ double lds[kThreads];
-    double acc[kMaxTermsPerSweep + 1];
 #pragma unroll
-    for (int t = 0; t <= kMaxTermsPerSweep; ++t) acc[t] = 0.0;
-    const uint64_t first = uint64_t(blockIdx.x) * a.per;
-    // index bits that change across one thread's items (x == 0 sweeps)
-    const uint64_t vary = (a.per - 1) & ~uint64_t(kThreads - 1);
+    for (int o = 32; o > 0; o >>= 1) v = __dadd_rn(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block partials of terms [0, n) and of the norm: part[t * nb + block]
+// (t = n is the norm).  Each value is summed over its wave by a butterfly,
+// then the four wave sums in order.
+__device__ __forceinline__ void write_partials(const double* val, double norm, int n, double* part,
+                                               double (*wsum)[kThreads / 64])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int t = 0; t <= kMaxTermsPerSweep; ++t) {
+        if (t <= n) {
+            const double w = wave_sum(t == n ? norm : val[t < kMaxTermsPerSweep ? t : 0]);
+            if (lane == 0) wsum[t][wave] = w;
+        }
+    }
+    __syncthreads();
+    if (int(threadIdx.x) <= n) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) s = __dadd_rn(s, wsum[threadIdx.x][w]);
+        part[uint64_t(threadIdx.x) * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// x == 0 sweeps (Z-type terms and the norm).  Item i contributes
+// |psi_i|^2 * (-1)^popcount(i & z).  Block b covers items
+// [b * per, (b + 1) * per); thread tid takes items it0 + u * 256 + tid.
+// Only the bits of `it` above the thread index vary inside a thread
+// ("vary"); a term whose Z mask misses them has a constant sign per thread
+// and shares the plain sum (the norm).  The others (the first n_active,
+// arranged by the host) need per-item work, done per round of four items:
+// those differ only in bits 8-9 of `it`, so a term's sign over the round is
+// (-1)^parity(it0 & z & vary) * (-1)^parity(u & m), m = bits 8-9 of
+// z & vary, and the round adds +-h[m], h the Walsh-Hadamard transform of the
+// round's four probabilities.  The next round's loads are in flight while a
+// round is summed.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_expect_z(const typename Cx<R>::T* __restrict__ psi,
+                                                      ExpectArgs a, double* __restrict__ part)
+{
     using T2 = typename Cx<R>::T;
-    // items it0 + u * kThreads + tid, u < kExpectUnroll: all loads of a
-    // round are issued before any arithmetic, so each thread keeps several
-    // HBM requests in flight
-    for (uint64_t it0 = 0; it0 < a.per; it0 += uint64_t(kExpectUnroll) * kThreads) {
-        T2 vi[kExpectUnroll] = {}, vj[kExpectUnroll] = {};
-        uint64_t ii[kExpectUnroll] = {};
+    static_assert(kExpectUnroll == 4 && kThreads == 256, "a round spans bits 8-9 of it");
+    __shared__ double wsum[kMaxTermsPerSweep + 1][kThreads / 64];
+    constexpr uint64_t kRound = uint64_t(kExpectUnroll) * kThreads;
+    const uint64_t first = uint64_t(blockIdx.x) * a.per;
+    const uint64_t vary = (a.per - 1) & ~uint64_t(kThreads - 1);
+    double acc[kMaxActive];
+#pragma unroll
+    for (int t = 0; t < kMaxActive; ++t) acc[t] = 0.0;
+    double norm = 0.0;
+    // two register buffers in turn: while one round is summed the next
+    // one's loads are in flight (no copy between them, which would wait)
+    T2 va[kExpectUnroll] = {}, vb[kExpectUnroll] = {};
+    // items past the block's end (per < 1024) load a valid amplitude and are
+    // not summed: unconditional loads keep the wait counts exact
+    auto load = [&](T2 (&v)[kExpectUnroll], uint64_t it0) {
 #pragma unroll
         for (int u = 0; u < kExpectUnroll; ++u) {
             const uint64_t it = it0 + uint64_t(u) * kThreads + threadIdx.x;
-            const uint64_t q = first + it;
-            if (!kPairs) {
-                if (it < a.per) vi[u] = psi[q];
-            } else {
-                const uint64_t lo = q & ((uint64_t(1) << a.hbit) - 1);
-                ii[u] = ((q >> a.hbit) << (a.hbit + 1)) | lo;
-                if (it < a.per) {
-                    vi[u] = psi[ii[u]];
-                    vj[u] = psi[ii[u] ^ a.x];
-                }
+            v[u] = psi[first + (it < a.per ? it : a.per - 1)];
+        }
+    };
+    auto sum_round = [&](const T2 (&v)[kExpectUnroll], uint64_t it0) {
+        double pr[kExpectUnroll];
+#pragma unroll
+        for (int u = 0; u < kExpectUnroll; ++u)
+            pr[u] = (it0 + uint64_t(u) * kThreads + threadIdx.x < a.per) ? prob(v[u]) : 0.0;
+        const double s01 = __dadd_rn(pr[0], pr[1]), d01 = __dsub_rn(pr[0], pr[1]);
+        const double s23 = __dadd_rn(pr[2], pr[3]), d23 = __dsub_rn(pr[2], pr[3]);
+        const double h0 = __dadd_rn(s01, s23), h1 = __dadd_rn(d01, d23);
+        const double h2 = __dsub_rn(s01, s23), h3 = __dsub_rn(d01, d23);
+        norm = __dadd_rn(norm, h0);
+#pragma unroll
+        for (int t = 0; t < kMaxActive; ++t) {
+            if (t < a.n_active) {
+                const uint64_t zv = a.z[t] & vary;
+                const uint32_t m = uint32_t(zv >> 8);
+                const double lo = (m & 1) ? h1 : h0;
+                const double hi = (m & 1) ? h3 : h2;
+                const double hv = (m & 2) ? hi : lo;
+                const double sg = (__popcll(it0 & zv) & 1) ? -1.0 : 1.0;
+                acc[t] = fma(hv, sg, acc[t]);  // exact sign, one rounding
             }
         }
+    };
+    // the prefetch is unconditional (past the end it re-reads the block's
+    // last amplitude), so the compiler can wait for the older round only
+    load(va, 0);
+    for (uint64_t it0 = 0; it0 < a.per; it0 += 2 * kRound) {
+        load(vb, it0 + kRound);
+        sum_round(va, it0);
+        if (it0 + kRound >= a.per) break;
+        load(va, it0 + 2 * kRound);
+        sum_round(vb, it0 + kRound);
+    }
+    // constant signs: (-1)^parity((first | tid) & z)
+    const uint64_t fixed = first | threadIdx.x;
+    double val[kMaxTermsPerSweep];
+#pragma unroll
+    for (int t = 0; t < kMaxTermsPerSweep; ++t) {
+        if (t < a.n_terms) {
+            const double x = (t < kMaxActive && t < a.n_active) ? acc[t < kMaxActive ? t : 0] : norm;
+            val[t] = (__popcll(fixed & a.z[t]) & 1) ? -x : x;
+        } else {
+            val[t] = 0.0;
+        }
+    }
+    write_partials(val, norm, a.n_terms, part, wsum);
+}
+
+// Pair sweeps for terms sharing one X/Y mask x != 0: item q is the pair
+// (i, j = i ^ x), i = q with a zero inserted at bit hbit (the highest bit
+// of x).  With w = conj(psi_j) psi_i the pair contributes
+// 2 Re(w * i^ny) * (-1)^popcount(i & z), because P|i> = ph(i)|j> and
+// ph(j) = conj(ph(i)) for a Hermitian Pauli string.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_expect_xy(const typename Cx<R>::T* __restrict__ psi,
+                                                       ExpectArgs a, double* __restrict__ part)
+{
+    using T2 = typename Cx<R>::T;
+    __shared__ double wsum[kMaxTermsPerSweep + 1][kThreads / 64];
+    constexpr uint64_t kRound = uint64_t(kExpectUnroll) * kThreads;
+    const uint64_t first = uint64_t(blockIdx.x) * a.per;
+    const uint64_t lomask = (uint64_t(1) << a.hbit) - 1;
+    double acc[kMaxTermsPerSweep];
+#pragma unroll
+    for (int t = 0; t < kMaxTermsPerSweep; ++t) acc[t] = 0.0;
+    double norm = 0.0;
+    auto index = [&](uint64_t it) {
+        const uint64_t q = first + it;
+        return ((q >> a.hbit) << (a.hbit + 1)) | (q & lomask);
+    };
+    T2 ai[kExpectUnroll] = {}, aj[kExpectUnroll] = {}, bi[kExpectUnroll] = {}, bj[kExpectUnroll] = {};
+    auto load = [&](T2 (&vi)[kExpectUnroll], T2 (&vj)[kExpectUnroll], uint64_t it0) {
+#pragma unroll
+        for (int u = 0; u < kExpectUnroll; ++u) {
+            const uint64_t it = it0 + uint64_t(u) * kThreads + threadIdx.x;
+            const uint64_t i = index(it < a.per ? it : a.per - 1);
+            vi[u] = psi[i];
+            vj[u] = psi[i ^ a.x];
+        }
+    };
+    auto sum_round = [&](const T2 (&vi)[kExpectUnroll], const T2 (&vj)[kExpectUnroll], uint64_t it0) {
 #pragma unroll
         for (int u = 0; u < kExpectUnroll; ++u) {
             const uint64_t it = it0 + uint64_t(u) * kThreads + threadIdx.x;
             if (it >= a.per) continue;
-            if (!kPairs) {
-                // q = first | tid | (it - tid): only the bits of `it` above
-                // the thread index vary inside the loop.  A term whose Z
-                // mask misses them has a constant sign per thread and shares
-                // the plain sum (the norm slot); the others flip with
-                // parity(it & vary & z).
-                const double p = prob(vi[u]);
-                acc[kMaxTermsPerSweep] = __dadd_rn(acc[kMaxTermsPerSweep], p);
+            const uint64_t i = index(it);
+            const double ir = double(vi[u].x), im = double(vi[u].y), jr = double(vj[u].x), jm = double(vj[u].y);
+            // w = conj(a_j) * a_i
+            const double wr = fma(jr, ir, __dmul_rn(jm, im));
+            const double wi = fma(jr, im, -__dmul_rn(jm, ir));
+            norm = __dadd_rn(norm, __dadd_rn(prob(vi[u]), prob(vj[u])));
 #pragma unroll
-                for (int t = 0; t < kMaxTermsPerSweep; ++t) {
-                    if (t < a.n_terms && (a.z[t] & vary) != 0) {
-                        const double sg = (__popcll(it & vary & a.z[t]) & 1) ? -p : p;
-                        acc[t] = __dadd_rn(acc[t], sg);
-                    }
-                }
-            } else {
-                const T2 ai = vi[u], aj = vj[u];
-                const double ir = double(ai.x), im = double(ai.y), jr = double(aj.x), jm = double(aj.y);
-                // w = conj(a_j) * a_i
-                const double wr = fma(jr, ir, __dmul_rn(jm, im));
-                const double wi = fma(jr, im, -__dmul_rn(jm, ir));
-                acc[kMaxTermsPerSweep] = __dadd_rn(acc[kMaxTermsPerSweep], __dadd_rn(prob(ai), prob(aj)));
-#pragma unroll
-                for (int t = 0; t < kMaxTermsPerSweep; ++t) {
-                    if (t < a.n_terms) {
-                        const int m = a.ny[t] & 3;
-                        double v = (m == 0) ? wr : (m == 1) ? -wi : (m == 2) ? -wr : wi;
-                        v = 2.0 * v;
-                        if (__popcll(ii[u] & a.z[t]) & 1) v = -v;
-                        acc[t] = __dadd_rn(acc[t], v);
-                    }
+            for (int t = 0; t < kMaxTermsPerSweep; ++t) {
+                if (t < a.n_terms) {
+                    const int m = a.ny[t] & 3;
+                    double w = (m & 1) ? wi : wr;
+                    if (m == 1 || m == 2) w = -w;
+                    w = 2.0 * w;
+                    if (__popcll(i & a.z[t]) & 1) w = -w;
+                    acc[t] = __dadd_rn(acc[t], w);
                 }
             }
         }
+    };
+    load(ai, aj, 0);
+    for (uint64_t it0 = 0; it0 < a.per; it0 += 2 * kRound) {
+        load(bi, bj, it0 + kRound);
+        sum_round(ai, aj, it0);
+        if (it0 + kRound >= a.per) break;
+        load(ai, aj, it0 + 2 * kRound);
+        sum_round(bi, bj, it0 + kRound);
     }
-    if (!kPairs) {
-        // apply the per-thread constant signs: a term that misses the
-        // varying bits takes the plain sum with the sign of
-        // parity((first | tid) & z); a term that hits them accumulated the
-        // varying part of its sign, and the constant part flips the total
-        const uint64_t fixed = first | threadIdx.x;
-#pragma unroll
-        for (int t = 0; t < kMaxTermsPerSweep; ++t) {
-            if (t < a.n_terms) {
-                const bool neg = (__popcll(fixed & a.z[t]) & 1) != 0;
-                const double v = ((a.z[t] & vary) != 0) ? acc[t] : acc[kMaxTermsPerSweep];
-                acc[t] = neg ? -v : v;
-            }
-        }
-    }
-#pragma unroll
-    for (int t = 0; t <= kMaxTermsPerSweep; ++t) {
-        if (t < a.n_terms || t == kMaxTermsPerSweep) {
-            const double s = block_sum(acc[t], lds);
-            const int slot = (t == kMaxTermsPerSweep) ? a.n_terms : t;
-            if (threadIdx.x == 0) part[uint64_t(slot) * gridDim.x + blockIdx.x] = s;
-        }
-    }
+    write_partials(acc, norm, a.n_terms, part, wsum);
 }
 
 // out[t] = sum over blocks of part[t * nb + b], fixed order.  One block per t.
@@ -303,45 +384,62 @@ __global__ __launch_bounds__(kThreads) void k_block_prefix(const typename Cx<R>:
 {
     using T2 = typename Cx<R>::T;
     constexpr int kRow = kBlk + 1;
+    constexpr int kPer = int(kSub) / kThreads;
     __shared__ double p[(kSub / kBlk) * kRow];
     const int tid = threadIdx.x, lane = tid & 63;
+    if (blockIdx.x >= L.nc) return;
     const uint64_t sub_len = L.cs < kSub ? L.cs : kSub;
     const uint64_t nsub = L.cs / sub_len;
     const int rows = int(sub_len / uint64_t(L.w));
     const int wshift = __ffs(L.w) - 1;
-    for (uint64_t c = blockIdx.x; c < L.nc; c += gridDim.x) {
-        double carry = 0.0;
-        for (uint64_t sb = 0; sb < nsub; ++sb) {
-            const T2* src = psi + c * L.cs + sb * sub_len;
-            if (sub_len == kSub) {
-                constexpr int kPer = int(kSub) / kThreads;
-                T2 v[kPer];
+    // this workgroup's sub-tiles in order: step k is sub-tile k % nsub of
+    // chunk blockIdx.x + (k / nsub) * gridDim.x
+    const uint64_t steps = ((L.nc - blockIdx.x + gridDim.x - 1) / gridDim.x) * nsub;
+    auto src_of = [&](uint64_t k) {
+        return psi + (blockIdx.x + (k / nsub) * gridDim.x) * L.cs + (k % nsub) * sub_len;
+    };
+    const bool full = sub_len == kSub;
+    T2 v[kPer];
+    if (full) {
+        const T2* src = src_of(0);
 #pragma unroll
-                for (int u = 0; u < kPer; ++u) v[u] = src[u * kThreads + tid];
+        for (int u = 0; u < kPer; ++u) v[u] = src[u * kThreads + tid];
+    }
+    double carry = 0.0;
+    for (uint64_t k = 0; k < steps; ++k) {
+        const uint64_t c = blockIdx.x + (k / nsub) * gridDim.x, sb = k % nsub;
+        if (sb == 0) carry = 0.0;
+        if (full) {
 #pragma unroll
-                for (int u = 0; u < kPer; ++u) {
-                    const int i = u * kThreads + tid;
-                    p[(i >> wshift) * kRow + (i & (L.w - 1))] = prob(v[u]);
-                }
-            } else {
-                for (int i = tid; i < int(sub_len); i += kThreads)
-                    p[(i >> wshift) * kRow + (i & (L.w - 1))] = prob(src[i]);
+            for (int u = 0; u < kPer; ++u) {
+                const int i = u * kThreads + tid;
+                p[(i >> wshift) * kRow + (i & (L.w - 1))] = prob(v[u]);
             }
-            __syncthreads();
-            if (tid < 64) {
-                double sum = 0.0;
-                if (lane < rows)
-                    for (int j = 0; j < L.w; ++j) sum = __dadd_rn(sum, p[lane * kRow + j]);
-                double mine = 0.0;
-                for (int l = 0; l < rows; ++l) {
-                    carry = __dadd_rn(carry, readlane_f64(sum, l));
-                    if (lane == l) mine = carry;
-                }
-                if (lane < rows) C[c * L.nbk + sb * uint64_t(rows) + lane] = mine;
-            }
-            __syncthreads();
+        } else {
+            const T2* src = src_of(k);
+            for (int i = tid; i < int(sub_len); i += kThreads)
+                p[(i >> wshift) * kRow + (i & (L.w - 1))] = prob(src[i]);
         }
-        if (tid == 0) S[c] = carry;
+        __syncthreads();
+        // the next sub-tile streams in while wave 0 sums this one
+        if (full && k + 1 < steps) {
+            const T2* src = src_of(k + 1);
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) v[u] = src[u * kThreads + tid];
+        }
+        if (tid < 64) {
+            double sum = 0.0;
+            if (lane < rows)
+                for (int j = 0; j < L.w; ++j) sum = __dadd_rn(sum, p[lane * kRow + j]);
+            double mine = 0.0;
+            for (int l = 0; l < rows; ++l) {
+                carry = __dadd_rn(carry, readlane_f64(sum, l));
+                if (lane == l) mine = carry;
+            }
+            if (lane < rows) C[c * L.nbk + sb * uint64_t(rows) + lane] = mine;
+            if (tid == 0 && sb == nsub - 1) S[c] = carry;
+        }
+        __syncthreads();
     }
 }
 
@@ -479,7 +577,8 @@ double run_norm_t(sv_handle_s* h, const void* psi_v, int n)
     ExpectArgs a{};
     a.per = P.per;
     a.n_terms = 0;
-    hipLaunchKernelGGL((k_expect<R, false>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a, part);
+    a.n_active = 0;
+    hipLaunchKernelGGL((k_expect_z<R>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a, part);
     SV_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_finish_sums, dim3(1), dim3(kThreads), 0, h->stream, part, P.nb, res);
     SV_HIP(hipGetLastError());
@@ -505,8 +604,10 @@ void run_expect_t(sv_handle_s* h, const void* psi_v, int n, const PauliMasks* te
     using T2 = typename Cx<R>::T;
     const T2* psi = static_cast<const T2*>(psi_v);
     const uint64_t dim = uint64_t(1) << n;
-    // group terms by their X/Y mask: one sweep per distinct mask and per
-    // kMaxTermsPerSweep terms
+    // Sweeps: one per distinct X/Y mask and per kMaxTermsPerSweep terms.
+    // Z-type terms (x == 0) whose mask meets the bits that vary inside a
+    // thread need per-item work: at most kMaxActive of them per sweep, placed
+    // first; the others only flip the sign of the plain sum.
     std::vector<int> order(n_terms);
     for (int t = 0; t < n_terms; ++t) order[t] = t;
     std::stable_sort(order.begin(), order.end(),
@@ -514,16 +615,40 @@ void run_expect_t(sv_handle_s* h, const void* psi_v, int n, const PauliMasks* te
     double* part = reinterpret_cast<double*>(h->ws + kMatRingBytes);
     std::vector<double> sums(n_terms, 0.0);
     double norm = -1.0;
-    std::vector<std::pair<int, int>> launches;  // (first index into order, count)
+    struct Launch {
+        std::vector<int> idx;  // term indices, active ones first
+        int n_active;
+    };
+    std::vector<Launch> launches;
+    const uint64_t zvary = (partition(dim).per - 1) & ~uint64_t(kThreads - 1);
     for (int i = 0; i < n_terms;) {
         int j = i;
-        while (j < n_terms && terms[order[j]].x == terms[order[i]].x && j - i < kMaxTermsPerSweep) ++j;
-        launches.push_back({i, j - i});
+        while (j < n_terms && terms[order[j]].x == terms[order[i]].x) ++j;
+        if (terms[order[i]].x == 0) {
+            std::vector<int> act, pas;
+            for (int k = i; k < j; ++k) ((terms[order[k]].z & zvary) ? act : pas).push_back(order[k]);
+            size_t ia = 0, ip = 0;
+            while (ia < act.size() || ip < pas.size()) {
+                Launch L;
+                while (ia < act.size() && L.idx.size() < size_t(kMaxActive)) L.idx.push_back(act[ia++]);
+                L.n_active = int(L.idx.size());
+                while (ip < pas.size() && L.idx.size() < size_t(kMaxTermsPerSweep)) L.idx.push_back(pas[ip++]);
+                launches.push_back(std::move(L));
+            }
+        } else {
+            for (int k = i; k < j; k += kMaxTermsPerSweep) {
+                Launch L;
+                for (int m = k; m < std::min(j, k + kMaxTermsPerSweep); ++m) L.idx.push_back(order[m]);
+                L.n_active = int(L.idx.size());
+                launches.push_back(std::move(L));
+            }
+        }
         i = j;
     }
     double* res_dev = part;  // reused per launch after the partials are consumed
-    for (auto& L : launches) {
-        const uint64_t x = terms[order[L.first]].x;
+    for (const Launch& L : launches) {
+        const int nt = int(L.idx.size());
+        const uint64_t x = terms[L.idx[0]].x;
         const bool pairs = x != 0;
         const uint64_t items = pairs ? dim / 2 : dim;
         const Partition P = partition(items);
@@ -532,24 +657,24 @@ void run_expect_t(sv_handle_s* h, const void* psi_v, int n, const PauliMasks* te
         a.per = P.per;
         a.x = x;
         a.hbit = pairs ? highest_bit(x) : 0;
-        a.n_terms = L.second;
-        for (int t = 0; t < L.second; ++t) {
-            a.z[t] = terms[order[L.first + t]].z;
-            a.ny[t] = terms[order[L.first + t]].ny;
+        a.n_terms = nt;
+        a.n_active = L.n_active;
+        for (int t = 0; t < nt; ++t) {
+            a.z[t] = terms[L.idx[t]].z;
+            a.ny[t] = terms[L.idx[t]].ny;
         }
         if (pairs)
-            hipLaunchKernelGGL((k_expect<R, true>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a, p);
+            hipLaunchKernelGGL((k_expect_xy<R>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a, p);
         else
-            hipLaunchKernelGGL((k_expect<R, false>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a, p);
+            hipLaunchKernelGGL((k_expect_z<R>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a, p);
         SV_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_finish_sums, dim3(unsigned(L.second + 1)), dim3(kThreads), 0, h->stream, p, P.nb,
-                           res_dev);
+        hipLaunchKernelGGL(k_finish_sums, dim3(unsigned(nt + 1)), dim3(kThreads), 0, h->stream, p, P.nb, res_dev);
         SV_HIP(hipGetLastError());
         double host[kMaxTermsPerSweep + 1];
-        SV_HIP(hipMemcpyAsync(host, res_dev, sizeof(double) * (L.second + 1), hipMemcpyDeviceToHost, h->stream));
+        SV_HIP(hipMemcpyAsync(host, res_dev, sizeof(double) * (nt + 1), hipMemcpyDeviceToHost, h->stream));
         SV_HIP(hipStreamSynchronize(h->stream));
-        for (int t = 0; t < L.second; ++t) sums[order[L.first + t]] = host[t];
-        if (norm < 0.0) norm = host[L.second];
+        for (int t = 0; t < nt; ++t) sums[L.idx[t]] = host[t];
+        if (norm < 0.0) norm = host[nt];
     }
     if (!(norm > 0.0)) throw Error{SV_ERR_INVALID_VALUE, "state has zero norm"};
     for (int t = 0; t < n_terms; ++t) out[t] = sums[t] / norm;
