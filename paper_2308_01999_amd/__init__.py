@@ -61,6 +61,7 @@ _SIGS = {
     "sv_handle_create": [ctypes.POINTER(_vp), _vp, ctypes.c_size_t],
     "sv_handle_destroy": [_vp],
     "sv_handle_set_stream": [_vp, _vp],
+    "sv_handle_set_tile_mode": [_vp, _i32],
     "sv_sync": [_vp],
     "sv_create": [_vp, _i32, ctypes.c_int, _vp, ctypes.POINTER(_vp)],
     "sv_destroy": [_vp],
@@ -147,6 +148,13 @@ def sv_handle_destroy(h: int) -> None:
 
 def sv_handle_set_stream(h: int, stream_ptr: int) -> None:
     _check(_L.sv_handle_set_stream(_vp(h), _vp(stream_ptr or None)))
+
+
+SV_TILE_AUTO, SV_TILE_NARROW, SV_TILE_WIDE = 0, 1, 2
+
+
+def sv_handle_set_tile_mode(h: int, mode: int) -> None:
+    _check(_L.sv_handle_set_tile_mode(_vp(h), _i32(mode)))
 
 
 def sv_sync(h: int) -> None:
@@ -336,6 +344,9 @@ class Handle:
 
     def sync(self):
         sv_sync(self.h)
+
+    def set_tile_mode(self, mode: int) -> None:
+        sv_handle_set_tile_mode(self.h, mode)
 
     def close(self):
         if self.h:

@@ -199,7 +199,9 @@ sv_status_t sv_handle_create(sv_handle_t* out, void* hip_stream, size_t workspac
             h->pinned_bytes = kMatRingBytes;
             for (int i = 0; i < kMatRingSegments; ++i)
                 SV_HIP(hipEventCreateWithFlags(&h->seg_event[i], hipEventDisableTiming));
+            h->tuner = new TileTuner;
         } catch (...) {
+            delete h->tuner;
             for (int i = 0; i < kMatRingSegments; ++i)
                 if (h->seg_event[i]) (void)hipEventDestroy(h->seg_event[i]);
             if (h->pinned) (void)hipHostFree(h->pinned);
@@ -221,6 +223,14 @@ sv_status_t sv_handle_destroy(sv_handle_t h)
         if (h->pinned) (void)hipHostFree(h->pinned);
         if (h->ws) (void)hipFree(h->ws);
         if (h->aux) (void)hipFree(h->aux);
+        if (h->tuner) {
+            for (auto& t : h->tuner->pending) {
+                (void)hipEventDestroy(t.e0);
+                (void)hipEventDestroy(t.e1);
+            }
+            for (hipEvent_t ev : h->tuner->pool) (void)hipEventDestroy(ev);
+            delete h->tuner;
+        }
         delete h;
         SV_HIP(e);
     });
@@ -231,6 +241,16 @@ sv_status_t sv_handle_set_stream(sv_handle_t h, void* hip_stream)
     return guarded([&] {
         SV_CHECK(h != nullptr, "handle is NULL");
         h->stream = static_cast<hipStream_t>(hip_stream);
+    });
+}
+
+sv_status_t sv_handle_set_tile_mode(sv_handle_t h, int32_t mode)
+{
+    return guarded([&] {
+        SV_CHECK(h != nullptr, "handle is NULL");
+        SV_CHECK(mode == SV_TILE_AUTO || mode == SV_TILE_NARROW || mode == SV_TILE_WIDE,
+                 "tile mode must be SV_TILE_AUTO, SV_TILE_NARROW or SV_TILE_WIDE");
+        h->tile_mode = mode;
     });
 }
 

@@ -328,13 +328,13 @@ __device__ __forceinline__ void gstore(V* p, const V v)
 // >= 7 for complex64, so the lane bits of tid stay below L), so the 64-bit
 // run offset is a scalar and only the 32-bit offset inside the run is
 // per lane.
-template <int APV>
+template <int APV, int NT = kTileThreads>
 __device__ __forceinline__ void tile_offsets(const TileArgs& a, uint64_t* roff, uint32_t* poff)
 {
     const int mask = (1 << a.L) - 1;
 #pragma unroll
     for (int u = 0; u < kTileVecs; ++u) {
-        const int i = (u * kTileThreads + int(threadIdx.x)) * APV;
+        const int i = (u * NT + int(threadIdx.x)) * APV;
         const uint32_t r = uint32_t(__builtin_amdgcn_readfirstlane(i >> a.L));
         roff[u] = deposit_bits(r, a.hi_pos, a.n_hi);
         poff[u] = uint32_t(i & mask);
@@ -386,10 +386,22 @@ __device__ __forceinline__ float4 swap_pair(const float4 v, bool sw)
 #endif
 constexpr int kK5AParts = SV_K5_A2_FLY ? 2 : 3;
 
-__global__ __launch_bounds__(kTileThreads) void k_tile_c64_k5(float2* __restrict__ psi,
+// The wide shape of the complex64 k = 5 sweep: 64 KiB tiles in 512-thread
+// workgroups (8 waves, 256 groups), so every run of a tile is 2 KiB long
+// instead of 1 KiB.  Which shape runs is chosen per handle (tile_shape).
+constexpr int kK5Threads = 512;
+constexpr int kK5TileBits = 13;
+
+// 512-thread workgroups: two per CU (LDS), so four waves per SIMD must fit
+// the register file (<= 128 VGPRs)
+#ifndef SV_K5_WIDE_WAVES
+#define SV_K5_WIDE_WAVES 2
+#endif
+template <int NT>
+__global__ __launch_bounds__(NT, NT == 512 ? SV_K5_WIDE_WAVES : 1) void k_tile_c64_k5(float2* __restrict__ psi,
                                                              const float4* __restrict__ mats, TileArgs a)
 {
-    __shared__ float4 lds[kTileThreads * kTileVecs];
+    __shared__ float4 lds[NT * kTileVecs];
     // the packed A operands (same for every wave): 3 x 64 lanes x 4 float4,
     // read back four k-steps at a time so only 12 of them are live at once
     __shared__ float4 amat[kK5AParts * 64 * 4];
@@ -397,10 +409,10 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k5(float2* __restrict
     if (t0 >= a.n_tiles) return;
     const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 31, half = lane >> 5;
-    for (int e = tid; e < kK5AParts * 64 * 4; e += kTileThreads) amat[e] = mats[e];
+    for (int e = tid; e < kK5AParts * 64 * 4; e += NT) amat[e] = mats[e];
     uint64_t roff[kTileVecs];
     uint32_t poff[kTileVecs];
-    tile_offsets<2>(a, roff, poff);
+    tile_offsets<2, NT>(a, roff, poff);
     const int pb = int(insert_zero_bits(uint64_t(wave * 32 + col), a.lo_pos, a.n_lo));
     const int pin = pb + (half ? a.lds_off[1] : 0);
     const int pout = pb + (half ? a.lds_off[4] : 0);
@@ -415,7 +427,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k5(float2* __restrict
     for (uint64_t t = t0; t < t1; ++t) {
 #define SV_STAGE(u)                                                                        \
     {                                                                                      \
-        const int i = (u * kTileThreads + tid) * 2;                                        \
+        const int i = (u * NT + tid) * 2;                                        \
         *reinterpret_cast<float4*>(lds2 + pair_slot(i)) = swap_pair(buf##u, pair_swapped(i)); \
     }
         SV_REP8(SV_STAGE)
@@ -455,7 +467,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k5(float2* __restrict
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kTileVecs; ++u) {
-            const int i = (u * kTileThreads + tid) * 2;
+            const int i = (u * NT + tid) * 2;
             gstore(reinterpret_cast<float4*>(psi + base + roff[u] + poff[u]),
                    swap_pair(*reinterpret_cast<const float4*>(lds2 + pair_slot(i)), pair_swapped(i)));
         }
@@ -756,15 +768,104 @@ TileArgs make_tile_args(const GateDesc& d, int n, int tb, int cu_count)
     return t;
 }
 
+// ------------------------------------------------- tile shape autotuning
+
+hipEvent_t tuner_event(TileTuner& T)
+{
+    if (!T.pool.empty()) {
+        hipEvent_t e = T.pool.back();
+        T.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    SV_HIP(hipEventCreate(&e));
+    return e;
+}
+
+// Folds finished trials into their entries.
+void tuner_poll(TileTuner& T)
+{
+    for (size_t i = 0; i < T.pending.size();) {
+        TileTrial& tr = T.pending[i];
+        const hipError_t q = hipEventQuery(tr.e1);
+        if (q == hipErrorNotReady) {
+            ++i;
+            continue;
+        }
+        TileTuneEntry& e = T.entries[tr.key];
+        float ms = 0.f;
+        if (q == hipSuccess && hipEventElapsedTime(&ms, tr.e0, tr.e1) == hipSuccess) {
+            e.best_ms[tr.shape] = e.measured[tr.shape] ? std::min(e.best_ms[tr.shape], ms) : ms;
+            ++e.measured[tr.shape];
+        } else {
+            (void)hipGetLastError();
+            e.measured[tr.shape] = kTileTrials;  // unusable: stop trying it
+            e.best_ms[tr.shape] = 1e30f;
+        }
+        --e.in_flight[tr.shape];
+        T.pool.push_back(tr.e0);
+        T.pool.push_back(tr.e1);
+        T.pending[i] = T.pending.back();
+        T.pending.pop_back();
+    }
+}
+
+// Shape for a complex64 k = 5 sweep: 0 narrow, 1 wide.  *trial is set when
+// this launch is to be timed.
+int tile_shape(sv_handle_s* h, const GateDesc& d, bool* trial)
+{
+    *trial = false;
+    if (d.n < kK5TileBits) return 0;
+    if (h->tile_mode == SV_TILE_NARROW) return 0;
+    if (h->tile_mode == SV_TILE_WIDE) return 1;
+    TileTuner& T = *h->tuner;
+    uint64_t key = uint64_t(d.n) << 40;
+    for (int a = 0; a < d.k; ++a) key |= d.tbit[a];
+    tuner_poll(T);
+    TileTuneEntry& e = T.entries[key];
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const bool capturing = hipStreamIsCapturing(h->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+    if (capturing) (void)hipGetLastError();
+    if (!capturing) {
+        // the shape with fewer timings started, narrow first
+        int s = -1;
+        for (int c = 0; c < kTileShapes; ++c)
+            if (e.measured[c] + e.in_flight[c] < kTileTrials &&
+                (s < 0 || e.measured[c] + e.in_flight[c] < e.measured[s] + e.in_flight[s]))
+                s = c;
+        if (s >= 0) {
+            *trial = true;
+            return s;
+        }
+    }
+    if (e.measured[0] && e.measured[1]) return e.best_ms[1] < e.best_ms[0] ? 1 : 0;
+    return 0;
+}
+
 void launch_tile(sv_handle_s* h, Path p, void* psi, const void* mats, const GateDesc& d)
 {
-    const int tb = (p == Path::kTileC128K5) ? 11 : 12;
+    bool trial = false;
+    const bool wide = p == Path::kTileC64K5 && tile_shape(h, d, &trial) == 1;
+    TileTrial tr{};
+    if (trial) {
+        tr.key = uint64_t(d.n) << 40;
+        for (int a = 0; a < d.k; ++a) tr.key |= d.tbit[a];
+        tr.shape = wide ? 1 : 0;
+        tr.e0 = tuner_event(*h->tuner);
+        tr.e1 = tuner_event(*h->tuner);
+        SV_HIP(hipEventRecord(tr.e0, h->stream));
+    }
+    const int tb = (p == Path::kTileC128K5) ? 11 : wide ? kK5TileBits : 12;
     const TileArgs t = make_tile_args(d, d.n, tb, h->cu_count);
     const uint64_t blocks = (t.n_tiles + t.tiles_per_wg - 1) / t.tiles_per_wg;
     switch (p) {
         case Path::kTileC64K5:
-            hipLaunchKernelGGL(k_tile_c64_k5, dim3(unsigned(blocks)), dim3(kTileThreads), 0, h->stream,
-                               static_cast<float2*>(psi), static_cast<const float4*>(mats), t);
+            if (wide)
+                hipLaunchKernelGGL(k_tile_c64_k5<kK5Threads>, dim3(unsigned(blocks)), dim3(kK5Threads), 0,
+                                   h->stream, static_cast<float2*>(psi), static_cast<const float4*>(mats), t);
+            else
+                hipLaunchKernelGGL(k_tile_c64_k5<kTileThreads>, dim3(unsigned(blocks)), dim3(kTileThreads), 0,
+                                   h->stream, static_cast<float2*>(psi), static_cast<const float4*>(mats), t);
             break;
         case Path::kTileC64K4:
             hipLaunchKernelGGL(k_tile_c64_k4, dim3(unsigned(blocks)), dim3(kTileThreads), 0, h->stream,
@@ -778,6 +879,11 @@ void launch_tile(sv_handle_s* h, Path p, void* psi, const void* mats, const Gate
             throw Error{SV_ERR_INTERNAL, "not a tile path"};
     }
     SV_HIP(hipGetLastError());
+    if (trial) {
+        SV_HIP(hipEventRecord(tr.e1, h->stream));
+        h->tuner->entries[tr.key].in_flight[tr.shape]++;
+        h->tuner->pending.push_back(tr);
+    }
 }
 
 template <typename R>

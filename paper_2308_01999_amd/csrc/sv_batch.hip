@@ -33,12 +33,22 @@ __device__ __forceinline__ uint64_t insert_zeros(uint64_t v, const int8_t* pos, 
     return v;
 }
 
+// LDS slot of region amplitude a: its low five bits XOR bits 5-9, so that
+// the group gathers (consecutive groups 2^m amplitudes apart when the low
+// bits are targets) spread over the LDS banks.  Bijective on aligned blocks
+// of 1024 amplitudes and the identity below 32, so a resident state of any
+// size stays inside its own 2^n slots.
+__device__ __forceinline__ int swz(int a) { return a ^ ((a >> 5) & 31); }
+
+// LDS operand block for k = 4, 5: Re M, Im M, Re M + Im M in the per-lane
+// order of the MFMA A operand (k = 5: 4 float4 per lane each; k = 4: 1).
+constexpr int kAmat = 3 * 64 * 4;
+
 // ---------------------------------------------------------- block kernels
 
 // v_mfma_f32_32x32x2_f32: A[i][k] lane i + 32k, B[k][j] lane j + 32k,
 // D[i][j] lane j + 32((i/4)%2), register 4(i/8) + i%4.
-__device__ __forceinline__ void region_mfma5(float2* lds, const BatchBlock& b, const float* ar, const float* ai,
-                                             const float* as)
+__device__ __forceinline__ void region_mfma5(float2* lds, const BatchBlock& b, const float4* amat)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 31, half = lane >> 5;
     const int groups = 1 << (b.L - b.n_lo);
@@ -50,28 +60,41 @@ __device__ __forceinline__ void region_mfma5(float2* lds, const BatchBlock& b, c
         const int pout = pb + (half ? b.lds_off[4] : 0);
         float2 x[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) x[j] = valid ? lds[pin + b.lds_off[2 * j]] : float2{0.f, 0.f};
+        for (int j = 0; j < 16; ++j) x[j] = valid ? lds[swz(pin + b.lds_off[2 * j])] : float2{0.f, 0.f};
         f32x16 p1 = {0}, p2 = {0}, p3 = {0};
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[j], x[j].x, p1, 0, 0, 0);
-            p2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[j], x[j].y, p2, 0, 0, 0);
-            p3 = __builtin_amdgcn_mfma_f32_32x32x2f32(as[j], x[j].x + x[j].y, p3, 0, 0, 0);
+        for (int q = 0; q < 4; ++q) {
+            const float4 vr = amat[(0 * 64 + lane) * 4 + q];
+            const float4 vi = amat[(1 * 64 + lane) * 4 + q];
+            const float4 vs = amat[(2 * 64 + lane) * 4 + q];
+            const float ar[4] = {vr.x, vr.y, vr.z, vr.w};
+            const float ai[4] = {vi.x, vi.y, vi.z, vi.w};
+            const float as[4] = {vs.x, vs.y, vs.z, vs.w};
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const float2 xv = x[4 * q + jj];
+                p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[jj], xv.x, p1, 0, 0, 0);
+                p2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[jj], xv.y, p2, 0, 0, 0);
+                p3 = __builtin_amdgcn_mfma_f32_32x32x2f32(as[jj], xv.x + xv.y, p3, 0, 0, 0);
+            }
         }
         if (valid) {
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                lds[pout + b.lds_off[8 * (r / 4) + (r % 4)]] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
+                lds[swz(pout + b.lds_off[8 * (r / 4) + (r % 4)])] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
         }
     }
 }
 
 // v_mfma_f32_16x16x4_f32: A[i][k] lane i + 16k, B[k][j] lane j + 16k,
 // D[i][j] lane j + 16(i/4), register i%4.
-__device__ __forceinline__ void region_mfma4(float2* lds, const BatchBlock& b, const float* ar, const float* ai,
-                                             const float* as)
+__device__ __forceinline__ void region_mfma4(float2* lds, const BatchBlock& b, const float4* amat)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 15, q = lane >> 4;
+    const float4 vr = amat[0 * 64 + lane], vi = amat[1 * 64 + lane], vs = amat[2 * 64 + lane];
+    const float ar[4] = {vr.x, vr.y, vr.z, vr.w};
+    const float ai[4] = {vi.x, vi.y, vi.z, vi.w};
+    const float as[4] = {vs.x, vs.y, vs.z, vs.w};
     const int groups = 1 << (b.L - b.n_lo);
     const int lin = ((q & 1) ? b.lds_off[1] : 0) + ((q & 2) ? b.lds_off[2] : 0);
     const int lout = ((q & 1) ? b.lds_off[4] : 0) + ((q & 2) ? b.lds_off[8] : 0);
@@ -81,7 +104,7 @@ __device__ __forceinline__ void region_mfma4(float2* lds, const BatchBlock& b, c
         const int pb = valid ? int(insert_zeros(uint64_t(gl), b.lo_pos, b.n_lo)) : 0;
         float2 x[4];
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) x[s4] = valid ? lds[pb + lin + b.lds_off[4 * s4]] : float2{0.f, 0.f};
+        for (int s4 = 0; s4 < 4; ++s4) x[s4] = valid ? lds[swz(pb + lin + b.lds_off[4 * s4])] : float2{0.f, 0.f};
         f32x4 p1 = {0}, p2 = {0}, p3 = {0};
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
@@ -91,7 +114,7 @@ __device__ __forceinline__ void region_mfma4(float2* lds, const BatchBlock& b, c
         }
         if (valid) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) lds[pb + lout + b.lds_off[r]] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
+            for (int r = 0; r < 4; ++r) lds[swz(pb + lout + b.lds_off[r])] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
         }
     }
 }
@@ -110,7 +133,7 @@ __device__ __forceinline__ void region_valu(float2* lds, const BatchBlock& b, co
         const int pb = int(insert_zeros(uint64_t(gl), b.lo_pos, b.n_lo));
         float2 v[D];
 #pragma unroll
-        for (int c = 0; c < D; ++c) v[c] = lds[pb + b.lds_off[c]];
+        for (int c = 0; c < D; ++c) v[c] = lds[swz(pb + b.lds_off[c])];
 #pragma unroll
         for (int r = 0; r < D; ++r) {
             float re = 0.f, im = 0.f;
@@ -122,44 +145,28 @@ __device__ __forceinline__ void region_valu(float2* lds, const BatchBlock& b, co
                 im = fmaf(e.x, v[c].y, im);
                 im = fmaf(e.y, v[c].x, im);
             }
-            lds[pb + b.lds_off[r]] = float2{re, im};
+            lds[swz(pb + b.lds_off[r])] = float2{re, im};
         }
     }
 }
 
-__device__ __forceinline__ void load_a(const float* __restrict__ mats, const BatchBlock& b, float* ar, float* ai,
-                                       float* as)
+// Copies block b's packed A operands to LDS (k = 4, 5); the caller
+// synchronises before they are read.
+__device__ __forceinline__ void stage_a(const float* __restrict__ mats, const BatchBlock& b, float4* amat)
 {
-    const int lane = threadIdx.x & 63;
     const float4* m4 = reinterpret_cast<const float4*>(mats + b.mat_off);
-    if (b.k == 5) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            float4 v = m4[(0 * 64 + lane) * 4 + q];
-            ar[4 * q] = v.x; ar[4 * q + 1] = v.y; ar[4 * q + 2] = v.z; ar[4 * q + 3] = v.w;
-            v = m4[(1 * 64 + lane) * 4 + q];
-            ai[4 * q] = v.x; ai[4 * q + 1] = v.y; ai[4 * q + 2] = v.z; ai[4 * q + 3] = v.w;
-            v = m4[(2 * 64 + lane) * 4 + q];
-            as[4 * q] = v.x; as[4 * q + 1] = v.y; as[4 * q + 2] = v.z; as[4 * q + 3] = v.w;
-        }
-    } else if (b.k == 4) {
-        float4 v = m4[0 * 64 + lane];
-        ar[0] = v.x; ar[1] = v.y; ar[2] = v.z; ar[3] = v.w;
-        v = m4[1 * 64 + lane];
-        ai[0] = v.x; ai[1] = v.y; ai[2] = v.z; ai[3] = v.w;
-        v = m4[2 * 64 + lane];
-        as[0] = v.x; as[1] = v.y; as[2] = v.z; as[3] = v.w;
-    }
+    const int n4 = b.k == 5 ? kAmat : b.k == 4 ? 3 * 64 : 0;
+    for (int e = threadIdx.x; e < n4; e += kThreads) amat[e] = m4[e];
 }
 
-// Applies block b to the region in LDS (A operands already in registers
+// Applies block b to the region in LDS (A operands already staged in LDS
 // for k = 4, 5).  Callers synchronise before and after.
 __device__ __forceinline__ void apply_region(float2* lds, const BatchBlock& b, const float* __restrict__ mats,
-                                             const float* ar, const float* ai, const float* as)
+                                             const float4* amat)
 {
     switch (b.k) {
-        case 5: region_mfma5(lds, b, ar, ai, as); break;
-        case 4: region_mfma4(lds, b, ar, ai, as); break;
+        case 5: region_mfma5(lds, b, amat); break;
+        case 4: region_mfma4(lds, b, amat); break;
         case 3: region_valu<3>(lds, b, reinterpret_cast<const float2*>(mats + b.mat_off)); break;
         case 2: region_valu<2>(lds, b, reinterpret_cast<const float2*>(mats + b.mat_off)); break;
         default: region_valu<1>(lds, b, reinterpret_cast<const float2*>(mats + b.mat_off)); break;
@@ -192,6 +199,7 @@ __device__ __forceinline__ double prob(const float2 a)
 // by it.
 constexpr int kTermsPerPass = 8;
 
+template <bool kInLds>
 __device__ __forceinline__ void expectations(const float2* src, uint64_t dim, const uint64_t* __restrict__ zm,
                                              int n_terms, double* red, double* __restrict__ out)
 {
@@ -200,7 +208,7 @@ __device__ __forceinline__ void expectations(const float2* src, uint64_t dim, co
 #pragma unroll
         for (int t = 0; t <= kTermsPerPass; ++t) acc[t] = 0.0;
         for (uint64_t i = threadIdx.x; i < dim; i += kThreads) {
-            const double p = prob(src[i]);
+            const double p = prob(src[kInLds ? uint64_t(swz(int(i))) : i]);
             acc[kTermsPerPass] = __dadd_rn(acc[kTermsPerPass], p);
 #pragma unroll
             for (int t = 0; t < kTermsPerPass; ++t)
@@ -217,83 +225,121 @@ __device__ __forceinline__ void expectations(const float2* src, uint64_t dim, co
     }
 }
 
+// complex64 pairs (i, i + 1), i even, move as one 16-byte slot; the slot's
+// two halves are swapped when bit 0 of the XOR is set
+__device__ __forceinline__ int pair_slot(int i) { return i ^ ((i >> 5) & 30); }
+__device__ __forceinline__ float4 swap_pair(const float4 v, int i)
+{
+    return ((i >> 5) & 1) ? float4{v.z, v.w, v.x, v.y} : v;
+}
+
+#define SV_REP8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
+
 __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A)
 {
     __shared__ float2 lds[kRegion];
+    __shared__ float4 amat[kAmat];
     __shared__ double red[kThreads];
     __shared__ uint32_t next;
     float2* states = static_cast<float2*>(A.states);
-    float4* l4 = reinterpret_cast<float4*>(lds);
-    if (threadIdx.x == 0) atomicMin(reinterpret_cast<unsigned long long*>(A.t_start),
-                                    static_cast<unsigned long long>(wall_clock64()));
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(A.queue, 1u);
-        __syncthreads();
-        // uniform across the workgroup: descriptors below load as scalars
-        const uint32_t slot = __builtin_amdgcn_readfirstlane(next);
-        __syncthreads();
-        if (slot >= A.n_circuits) break;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        atomicMin(reinterpret_cast<unsigned long long*>(A.t_start), static_cast<unsigned long long>(wall_clock64()));
+        next = atomicAdd(A.queue, 1u);
+    }
+    __syncthreads();
+    // uniform across the workgroup: descriptors below load as scalars.  The
+    // queue is read again only at the bottom of the loop, so the loop's one
+    // exit is this uniform test (a thread-0 branch at the top of the loop
+    // let the compiler give thread 0 a loop of its own around the barriers)
+    uint32_t slot = __builtin_amdgcn_readfirstlane(next);
+    __syncthreads();
+    while (slot < A.n_circuits) {
         const uint32_t ci = A.order[slot];
         const BatchCircuit c = A.circuits[ci];
         float2* psi = states + c.state_off;
         const uint64_t dim = uint64_t(1) << c.n;
         const bool resident = c.n <= 12;
+        // |0..0> (slot 0 is amplitude 0 under the swizzle)
         if (resident) {
-            for (int i = threadIdx.x; i < int(dim); i += kThreads) lds[i] = float2{i == 0 ? 1.f : 0.f, 0.f};
+            for (int i = tid; i < int(dim); i += kThreads) lds[i] = float2{i == 0 ? 1.f : 0.f, 0.f};
         } else {
             float4* p4 = reinterpret_cast<float4*>(psi);
-            for (uint64_t i = threadIdx.x; i < dim / 2; i += kThreads)
-                p4[i] = float4{i == 0 ? 1.f : 0.f, 0.f, 0.f, 0.f};
+            for (uint64_t i = tid; i < dim / 2; i += kThreads) p4[i] = float4{i == 0 ? 1.f : 0.f, 0.f, 0.f, 0.f};
         }
         // resident: one region (the state, kept in LDS); streaming: the
-        // state's 4096-amplitude tiles, loaded and stored around each block
+        // state's 4096-amplitude tiles, loaded and stored around each block,
+        // the next tile's loads in flight while one is transformed
         const uint64_t n_regions = resident ? 1 : (dim >> 12);
-        float ar[16], ai[16], as[16];
         for (uint32_t bi = 0; bi < c.n_blocks; ++bi) {
             __threadfence();
             __syncthreads();
             const BatchBlock& b = A.blocks[c.block0 + bi];
-            load_a(A.mats, b, ar, ai, as);
+            stage_a(A.mats, b, amat);
+            if (resident) {
+                __syncthreads();
+                apply_region(lds, b, A.mats, amat);
+            } else {
             const int mask = (1 << b.L) - 1;
             uint64_t goff[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int i = (u * kThreads + int(threadIdx.x)) * 2;
+                const int i = (u * kThreads + tid) * 2;
                 const uint32_t r = uint32_t(i >> b.L);
                 uint64_t o = 0;
                 for (int j = 0; j < b.n_hi; ++j) o |= uint64_t((r >> j) & 1u) << b.hi_pos[j];
                 goff[u] = o + uint64_t(i & mask);
             }
+#define SV_DECL(u) float4 buf##u;
+            SV_REP8(SV_DECL)
+#undef SV_DECL
+            uint64_t base = insert_zeros(0, b.hi_pos, b.n_hi);
+#define SV_LOAD(u) buf##u = *reinterpret_cast<const float4*>(psi + base + goff[u]);
+            SV_REP8(SV_LOAD)
             for (uint64_t t = 0; t < n_regions; ++t) {
-                uint64_t base = 0;
-                if (!resident) {
-                    base = insert_zeros(t << b.L, b.hi_pos, b.n_hi);
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        l4[u * kThreads + threadIdx.x] = *reinterpret_cast<const float4*>(psi + base + goff[u]);
-                    __syncthreads();
-                }
-                apply_region(lds, b, A.mats, ar, ai, as);
+#define SV_STAGE(u)                                                                       \
+    {                                                                                     \
+        const int i = (u * kThreads + tid) * 2;                                           \
+        *reinterpret_cast<float4*>(lds + pair_slot(i)) = swap_pair(buf##u, i);            \
+    }
+                SV_REP8(SV_STAGE)
+#undef SV_STAGE
                 __syncthreads();
-                if (!resident) {
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        *reinterpret_cast<float4*>(psi + base + goff[u]) = l4[u * kThreads + threadIdx.x];
-                    __syncthreads();
+                const uint64_t cur = base;
+                if (t + 1 < n_regions) {
+                    base = insert_zeros((t + 1) << b.L, b.hi_pos, b.n_hi);
+                    SV_REP8(SV_LOAD)
                 }
+                apply_region(lds, b, A.mats, amat);
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int i = (u * kThreads + tid) * 2;
+                    *reinterpret_cast<float4*>(psi + cur + goff[u]) =
+                        swap_pair(*reinterpret_cast<const float4*>(lds + pair_slot(i)), i);
+                }
+                __syncthreads();
+            }
+#undef SV_LOAD
             }
         }
         __threadfence();
         __syncthreads();
         if (resident) {
-            for (int i = threadIdx.x; i < int(dim); i += kThreads) psi[i] = lds[i];
-            expectations(lds, dim, A.z_masks + c.term0, int(c.n_terms), red, A.expect + c.term0);
+            for (int i = tid; i < int(dim); i += kThreads) psi[i] = lds[swz(i)];
+            expectations<true>(lds, dim, A.z_masks + c.term0, int(c.n_terms), red, A.expect + c.term0);
         } else {
-            expectations(psi, dim, A.z_masks + c.term0, int(c.n_terms), red, A.expect + c.term0);
+            expectations<false>(psi, dim, A.z_masks + c.term0, int(c.n_terms), red, A.expect + c.term0);
         }
         __threadfence();
         __syncthreads();
-        if (threadIdx.x == 0) A.t_done[ci] = wall_clock64();
+        if (tid == 0) {
+            A.t_done[ci] = wall_clock64();
+            next = atomicAdd(A.queue, 1u);
+        }
+        __syncthreads();
+        slot = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();
     }
 }
 
@@ -313,8 +359,12 @@ void launch_batch_reset(hipStream_t stream, const BatchArgs& a)
 
 void launch_batch(hipStream_t stream, int cu_count, const BatchArgs& a)
 {
-    // enough workgroups to fill the device; each exits when the queue is empty
-    const unsigned blocks = unsigned(cu_count) * 4;
+    // as many workgroups as fit on the device at once; each exits when the
+    // queue is empty
+    int per_cu = 0;
+    SV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, kThreads, 0));
+    if (per_cu < 1) per_cu = 1;
+    const unsigned blocks = unsigned(cu_count) * unsigned(per_cu);
     hipLaunchKernelGGL(k_batch, dim3(blocks), dim3(kThreads), 0, stream, a);
     SV_HIP(hipGetLastError());
 }

@@ -3,6 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <unordered_map>
+#include <vector>
+
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -45,6 +48,29 @@ constexpr size_t kMinWorkspace = 12u << 20;
 
 }  // namespace sv
 
+// Online choice between the two complex64 k = 5 tile shapes: per key
+// (dtype, n, target mask), up to kTileTrials timings of each shape, then the
+// faster one.
+namespace sv {
+constexpr int kTileShapes = 2;
+constexpr int kTileTrials = 2;
+struct TileTuneEntry {
+    float best_ms[kTileShapes] = {0.f, 0.f};
+    int measured[kTileShapes] = {0, 0};
+    int in_flight[kTileShapes] = {0, 0};
+};
+struct TileTrial {
+    uint64_t key;
+    int shape;
+    hipEvent_t e0, e1;
+};
+struct TileTuner {
+    std::unordered_map<uint64_t, TileTuneEntry> entries;
+    std::vector<TileTrial> pending;
+    std::vector<hipEvent_t> pool;
+};
+}  // namespace sv
+
 struct sv_handle_s {
     hipStream_t stream = nullptr;
     int device = 0;
@@ -59,6 +85,8 @@ struct sv_handle_s {
     bool seg_event_live[sv::kMatRingSegments] = {};
     char* aux = nullptr;            // device scratch that grows with the state (sampler prefixes)
     size_t aux_bytes = 0;
+    int tile_mode = 0;              // sv_tile_mode_t
+    sv::TileTuner* tuner = nullptr;
 };
 
 struct sv_state_s {

@@ -418,3 +418,40 @@ def test_copy_ranges(P, H):
     with pytest.raises(P.SVError):
         P.sv_copy_to_host(st.s, np.zeros(200, dtype=np.complex64), 900, 200)
     st.close()
+
+
+# ----------------------------------------------------- k = 5 tile shapes
+
+@pytest.mark.parametrize("targets", [(0, 1, 2, 3, 4), (3, 7, 9, 12, 15), (11, 12, 13, 14, 15), (2, 6, 10, 13, 16)])
+def test_k5_tile_shapes_agree_bitwise(P, targets):
+    # the narrow (32 KiB, 256 threads) and wide (64 KiB, 512 threads) shapes
+    # of the complex64 k = 5 sweep do the same arithmetic per group, so the
+    # states agree bit for bit, and both match the oracle; AUTO (which times
+    # both on the first sweeps) gives the same bits too
+    n = 17
+    rng = np.random.default_rng(sum(targets))
+    mats = [W.haar_unitary(5, rng) for _ in range(6)]
+    layer = W.brickwork(n, 1, 9)  # every amplitude non-zero
+    ref = oracle.run(n, layer)
+    for m in mats:
+        oracle.apply(ref, m, targets)
+    outs = {}
+    for mode in (P.SV_TILE_NARROW, P.SV_TILE_WIDE, P.SV_TILE_AUTO):
+        h = P.Handle()
+        h.set_tile_mode(mode)
+        st = P.State(h, n, "c64")
+        st.run(layer)
+        for m in mats:
+            st.apply_matrix(m, targets)
+        outs[mode] = st.to_numpy()
+        st.close()
+        h.close()
+    assert oracle.fidelity(ref, outs[P.SV_TILE_NARROW].astype(np.complex128)) >= C64_FID
+    np.testing.assert_array_equal(outs[P.SV_TILE_NARROW], outs[P.SV_TILE_WIDE])
+    np.testing.assert_array_equal(outs[P.SV_TILE_NARROW], outs[P.SV_TILE_AUTO])
+
+
+def test_tile_mode_rejects_unknown(P, H):
+    with pytest.raises(P.SVError):
+        H.set_tile_mode(3)
+    H.set_tile_mode(P.SV_TILE_AUTO)
