@@ -74,7 +74,9 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    # untimed steps; they also let the handle time its k = 5 tile variants
+    # on every target set of the circuit and settle on the fastest
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--depth", type=int, default=20)
     ap.add_argument("--kmax", type=int, default=5)

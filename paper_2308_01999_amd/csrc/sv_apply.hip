@@ -250,6 +250,7 @@ struct TileArgs {
     int32_t n_lo;
     int32_t lo_pos[SV_MAX_TARGETS];
     int32_t lds_off[64];  // matrix index -> LDS offset from the group's base
+    int32_t rot;          // tile-group order: group index rotated left by rot bits (0: in order)
 };
 
 __device__ __forceinline__ uint64_t insert_zero_bits(uint64_t v, const int32_t* pos, int n)
@@ -355,10 +356,18 @@ __device__ __forceinline__ uint64_t tile_base(uint64_t t, const TileArgs& a)
 #endif
 constexpr uint32_t kXcds = 8;
 
-__device__ __forceinline__ uint64_t tile_group()
+// The order in which workgroups take tile groups changes which DRAM pages
+// are open together, and for some target sets the sweep is much faster with
+// consecutive workgroups far apart: a.rot rotates the group index left by
+// that many bits (the grid is a power of two then; 0 keeps the order).
+__device__ __forceinline__ uint64_t tile_group(const TileArgs& a)
 {
     const uint32_t b = blockIdx.x, g = gridDim.x;
     if (SV_TILE_XCD && g % kXcds == 0) return uint64_t(b % kXcds) * (g / kXcds) + b / kXcds;
+    if (a.rot > 0 && (g & (g - 1)) == 0 && g > (1u << a.rot)) {
+        const int lg = 31 - __clz(g);
+        return ((b << a.rot) | (b >> (lg - a.rot))) & (g - 1);
+    }
     return b;
 }
 
@@ -405,7 +414,7 @@ __global__ __launch_bounds__(NT, NT == 512 ? SV_K5_WIDE_WAVES : 1) void k_tile_c
     // the packed A operands (same for every wave): 3 x 64 lanes x 4 float4,
     // read back four k-steps at a time so only 12 of them are live at once
     __shared__ float4 amat[kK5AParts * 64 * 4];
-    const uint64_t t0 = tile_group() * a.tiles_per_wg;
+    const uint64_t t0 = tile_group(a) * a.tiles_per_wg;
     if (t0 >= a.n_tiles) return;
     const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 31, half = lane >> 5;
@@ -480,7 +489,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict
                                                              const float4* __restrict__ mats, TileArgs a)
 {
     __shared__ float4 lds[kTileThreads * kTileVecs];
-    const uint64_t t0 = tile_group() * a.tiles_per_wg;
+    const uint64_t t0 = tile_group(a) * a.tiles_per_wg;
     if (t0 >= a.n_tiles) return;
     const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, q = lane >> 4;
@@ -549,7 +558,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restri
                                                               const double2* __restrict__ mats, TileArgs a)
 {
     __shared__ double2 lds[kTileThreads * kTileVecs];
-    const uint64_t t0 = tile_group() * a.tiles_per_wg;
+    const uint64_t t0 = tile_group(a) * a.tiles_per_wg;
     if (t0 >= a.n_tiles) return;
     const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, q = lane >> 4;
@@ -810,8 +819,16 @@ void tuner_poll(TileTuner& T)
     }
 }
 
-// Shape for a complex64 k = 5 sweep: 0 narrow, 1 wide.  *trial is set when
-// this launch is to be timed.
+// Variants of the complex64 k = 5 sweep the handle chooses among:
+// shape (narrow 32 KiB / wide 64 KiB tiles) and tile-group order.
+struct TileVariant {
+    bool wide;
+    int rot;
+};
+constexpr TileVariant kTileVariants[kTileShapes] = {{false, 0}, {true, 0}, {false, 9}};
+
+// Variant for a complex64 k = 5 sweep (index into kTileVariants).  *trial is
+// set when this launch is to be timed.
 int tile_shape(sv_handle_s* h, const GateDesc& d, bool* trial)
 {
     *trial = false;
@@ -838,25 +855,29 @@ int tile_shape(sv_handle_s* h, const GateDesc& d, bool* trial)
             return s;
         }
     }
-    if (e.measured[0] && e.measured[1]) return e.best_ms[1] < e.best_ms[0] ? 1 : 0;
-    return 0;
+    int best = 0;
+    for (int c = 1; c < kTileShapes; ++c)
+        if (e.measured[c] && (!e.measured[best] || e.best_ms[c] < e.best_ms[best])) best = c;
+    return e.measured[best] ? best : 0;
 }
 
 void launch_tile(sv_handle_s* h, Path p, void* psi, const void* mats, const GateDesc& d)
 {
     bool trial = false;
-    const bool wide = p == Path::kTileC64K5 && tile_shape(h, d, &trial) == 1;
+    const int variant = p == Path::kTileC64K5 ? tile_shape(h, d, &trial) : 0;
+    const bool wide = p == Path::kTileC64K5 && kTileVariants[variant].wide;
     TileTrial tr{};
     if (trial) {
         tr.key = uint64_t(d.n) << 40;
         for (int a = 0; a < d.k; ++a) tr.key |= d.tbit[a];
-        tr.shape = wide ? 1 : 0;
+        tr.shape = variant;
         tr.e0 = tuner_event(*h->tuner);
         tr.e1 = tuner_event(*h->tuner);
         SV_HIP(hipEventRecord(tr.e0, h->stream));
     }
     const int tb = (p == Path::kTileC128K5) ? 11 : wide ? kK5TileBits : 12;
-    const TileArgs t = make_tile_args(d, d.n, tb, h->cu_count);
+    TileArgs t = make_tile_args(d, d.n, tb, h->cu_count);
+    t.rot = p == Path::kTileC64K5 ? kTileVariants[variant].rot : 0;
     const uint64_t blocks = (t.n_tiles + t.tiles_per_wg - 1) / t.tiles_per_wg;
     switch (p) {
         case Path::kTileC64K5:

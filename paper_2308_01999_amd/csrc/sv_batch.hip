@@ -48,7 +48,20 @@ constexpr int kAmat = 3 * 64 * 4;
 
 // v_mfma_f32_32x32x2_f32: A[i][k] lane i + 32k, B[k][j] lane j + 32k,
 // D[i][j] lane j + 32((i/4)%2), register 4(i/8) + i%4.
-__device__ __forceinline__ void region_mfma5(float2* lds, const BatchBlock& b, const float4* amat)
+#ifndef SV_BATCH_A_LDS
+#define SV_BATCH_A_LDS 1
+#endif
+#ifndef SV_BATCH_PREFETCH
+#define SV_BATCH_PREFETCH 1
+#endif
+
+// A operands of a k = 5 block for this lane: from LDS at every use
+// (SV_BATCH_A_LDS) or held in registers for the whole block.
+struct AOps5 {
+    float r[16], i[16], s[16];
+};
+
+__device__ __forceinline__ void region_mfma5(float2* lds, const BatchBlock& b, const float4* amat, const AOps5& areg)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 31, half = lane >> 5;
     const int groups = 1 << (b.L - b.n_lo);
@@ -64,12 +77,22 @@ __device__ __forceinline__ void region_mfma5(float2* lds, const BatchBlock& b, c
         f32x16 p1 = {0}, p2 = {0}, p3 = {0};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float4 vr = amat[(0 * 64 + lane) * 4 + q];
-            const float4 vi = amat[(1 * 64 + lane) * 4 + q];
-            const float4 vs = amat[(2 * 64 + lane) * 4 + q];
-            const float ar[4] = {vr.x, vr.y, vr.z, vr.w};
-            const float ai[4] = {vi.x, vi.y, vi.z, vi.w};
-            const float as[4] = {vs.x, vs.y, vs.z, vs.w};
+            float ar[4], ai[4], as[4];
+            if (SV_BATCH_A_LDS) {
+                const float4 vr = amat[(0 * 64 + lane) * 4 + q];
+                const float4 vi = amat[(1 * 64 + lane) * 4 + q];
+                const float4 vs = amat[(2 * 64 + lane) * 4 + q];
+                ar[0] = vr.x; ar[1] = vr.y; ar[2] = vr.z; ar[3] = vr.w;
+                ai[0] = vi.x; ai[1] = vi.y; ai[2] = vi.z; ai[3] = vi.w;
+                as[0] = vs.x; as[1] = vs.y; as[2] = vs.z; as[3] = vs.w;
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    ar[jj] = areg.r[4 * q + jj];
+                    ai[jj] = areg.i[4 * q + jj];
+                    as[jj] = areg.s[4 * q + jj];
+                }
+            }
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
                 const float2 xv = x[4 * q + jj];
@@ -162,10 +185,10 @@ __device__ __forceinline__ void stage_a(const float* __restrict__ mats, const Ba
 // Applies block b to the region in LDS (A operands already staged in LDS
 // for k = 4, 5).  Callers synchronise before and after.
 __device__ __forceinline__ void apply_region(float2* lds, const BatchBlock& b, const float* __restrict__ mats,
-                                             const float4* amat)
+                                             const float4* amat, const AOps5& areg)
 {
     switch (b.k) {
-        case 5: region_mfma5(lds, b, amat); break;
+        case 5: region_mfma5(lds, b, amat, areg); break;
         case 4: region_mfma4(lds, b, amat); break;
         case 3: region_valu<3>(lds, b, reinterpret_cast<const float2*>(mats + b.mat_off)); break;
         case 2: region_valu<2>(lds, b, reinterpret_cast<const float2*>(mats + b.mat_off)); break;
@@ -276,9 +299,23 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A)
             __syncthreads();
             const BatchBlock& b = A.blocks[c.block0 + bi];
             stage_a(A.mats, b, amat);
+            AOps5 areg;
+            if (!SV_BATCH_A_LDS && b.k == 5) {
+                // straight from global memory: the same packed layout
+                const float4* m4 = reinterpret_cast<const float4*>(A.mats + b.mat_off);
+                const int lane = tid & 63;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float4 vr = m4[(0 * 64 + lane) * 4 + q], vi = m4[(1 * 64 + lane) * 4 + q];
+                    const float4 vs = m4[(2 * 64 + lane) * 4 + q];
+                    areg.r[4 * q] = vr.x; areg.r[4 * q + 1] = vr.y; areg.r[4 * q + 2] = vr.z; areg.r[4 * q + 3] = vr.w;
+                    areg.i[4 * q] = vi.x; areg.i[4 * q + 1] = vi.y; areg.i[4 * q + 2] = vi.z; areg.i[4 * q + 3] = vi.w;
+                    areg.s[4 * q] = vs.x; areg.s[4 * q + 1] = vs.y; areg.s[4 * q + 2] = vs.z; areg.s[4 * q + 3] = vs.w;
+                }
+            }
             if (resident) {
                 __syncthreads();
-                apply_region(lds, b, A.mats, amat);
+                apply_region(lds, b, A.mats, amat, areg);
             } else {
             const int mask = (1 << b.L) - 1;
             uint64_t goff[8];
@@ -306,11 +343,11 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A)
 #undef SV_STAGE
                 __syncthreads();
                 const uint64_t cur = base;
-                if (t + 1 < n_regions) {
+                if (SV_BATCH_PREFETCH && t + 1 < n_regions) {
                     base = insert_zeros((t + 1) << b.L, b.hi_pos, b.n_hi);
                     SV_REP8(SV_LOAD)
                 }
-                apply_region(lds, b, A.mats, amat);
+                apply_region(lds, b, A.mats, amat, areg);
                 __syncthreads();
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
@@ -319,6 +356,10 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A)
                         swap_pair(*reinterpret_cast<const float4*>(lds + pair_slot(i)), i);
                 }
                 __syncthreads();
+                if (!SV_BATCH_PREFETCH && t + 1 < n_regions) {
+                    base = insert_zeros((t + 1) << b.L, b.hi_pos, b.n_hi);
+                    SV_REP8(SV_LOAD)
+                }
             }
 #undef SV_LOAD
             }

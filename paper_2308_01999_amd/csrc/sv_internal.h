@@ -48,16 +48,16 @@ constexpr size_t kMinWorkspace = 12u << 20;
 
 }  // namespace sv
 
-// Online choice between the two complex64 k = 5 tile shapes: per key
-// (dtype, n, target mask), up to kTileTrials timings of each shape, then the
-// faster one.
+// Online choice among the complex64 k = 5 tile variants (shape and tile
+// order): per key (n, target mask), kTileTrials timings of each variant,
+// then the fastest.
 namespace sv {
-constexpr int kTileShapes = 2;
-constexpr int kTileTrials = 2;
+constexpr int kTileShapes = 3;
+constexpr int kTileTrials = 1;
 struct TileTuneEntry {
-    float best_ms[kTileShapes] = {0.f, 0.f};
-    int measured[kTileShapes] = {0, 0};
-    int in_flight[kTileShapes] = {0, 0};
+    float best_ms[kTileShapes] = {};
+    int measured[kTileShapes] = {};
+    int in_flight[kTileShapes] = {};
 };
 struct TileTrial {
     uint64_t key;
