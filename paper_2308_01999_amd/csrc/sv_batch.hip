@@ -40,6 +40,37 @@ __device__ __forceinline__ uint64_t insert_zeros(uint64_t v, const int8_t* pos, 
 // size stays inside its own 2^n slots.
 __device__ __forceinline__ int swz(int a) { return a ^ ((a >> 5) & 31); }
 
+// Block descriptor fields as wave-uniform scalars, read once per region
+// (re-reading them from memory inside the lanes' loops would put a memory
+// wait in front of every gather).
+struct RegionGeom {
+    int n_lo;
+    int lo_pos[kBatchMaxK];
+    int off[32];
+};
+
+__device__ __forceinline__ void region_geom(const BatchBlock& b, int n_off, RegionGeom& g)
+{
+    g.n_lo = __builtin_amdgcn_readfirstlane(b.n_lo);
+#pragma unroll
+    for (int j = 0; j < kBatchMaxK; ++j) g.lo_pos[j] = __builtin_amdgcn_readfirstlane(b.lo_pos[j]);
+#pragma unroll
+    for (int j = 0; j < 32; ++j) g.off[j] = j < n_off ? __builtin_amdgcn_readfirstlane(int(b.lds_off[j])) : 0;
+}
+
+// v with zeros inserted at the region's low target positions
+__device__ __forceinline__ int spread_lo(int v, const RegionGeom& g)
+{
+#pragma unroll
+    for (int j = 0; j < kBatchMaxK; ++j) {
+        if (j < g.n_lo) {
+            const int p = g.lo_pos[j];
+            v = ((v >> p) << (p + 1)) | (v & ((1 << p) - 1));
+        }
+    }
+    return v;
+}
+
 // LDS operand block for k = 4, 5: Re M, Im M, Re M + Im M in the per-lane
 // order of the MFMA A operand (k = 5: 4 float4 per lane each; k = 4: 1).
 constexpr int kAmat = 3 * 64 * 4;
@@ -48,51 +79,34 @@ constexpr int kAmat = 3 * 64 * 4;
 
 // v_mfma_f32_32x32x2_f32: A[i][k] lane i + 32k, B[k][j] lane j + 32k,
 // D[i][j] lane j + 32((i/4)%2), register 4(i/8) + i%4.
-#ifndef SV_BATCH_A_LDS
-#define SV_BATCH_A_LDS 1
-#endif
-#ifndef SV_BATCH_PREFETCH
-#define SV_BATCH_PREFETCH 1
-#endif
-
-// A operands of a k = 5 block for this lane: from LDS at every use
-// (SV_BATCH_A_LDS) or held in registers for the whole block.
-struct AOps5 {
-    float r[16], i[16], s[16];
-};
-
-__device__ __forceinline__ void region_mfma5(float2* lds, const BatchBlock& b, const float4* amat, const AOps5& areg)
+__device__ __forceinline__ void region_mfma5(float2* lds, const BatchBlock& b, const float4* amat)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, col = lane & 31, half = lane >> 5;
-    const int groups = 1 << (b.L - b.n_lo);
+    RegionGeom g;
+    region_geom(b, 32, g);
+    const int groups = 1 << (__builtin_amdgcn_readfirstlane(b.L) - g.n_lo);
     for (int ct = wave; ct * 32 < groups; ct += kThreads / 64) {
         const int gl = ct * 32 + col;
         const bool valid = gl < groups;
-        const int pb = valid ? int(insert_zeros(uint64_t(gl), b.lo_pos, b.n_lo)) : 0;
-        const int pin = pb + (half ? b.lds_off[1] : 0);
-        const int pout = pb + (half ? b.lds_off[4] : 0);
+        // lanes past the last group read group 0 and feed zeros
+        const int pb = spread_lo(valid ? gl : 0, g);
+        const int pin = pb + (half ? g.off[1] : 0);
+        const int pout = pb + (half ? g.off[4] : 0);
         float2 x[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) x[j] = valid ? lds[swz(pin + b.lds_off[2 * j])] : float2{0.f, 0.f};
+        for (int j = 0; j < 16; ++j) {
+            const float2 v = lds[swz(pin + g.off[2 * j])];
+            x[j] = valid ? v : float2{0.f, 0.f};
+        }
         f32x16 p1 = {0}, p2 = {0}, p3 = {0};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            float ar[4], ai[4], as[4];
-            if (SV_BATCH_A_LDS) {
-                const float4 vr = amat[(0 * 64 + lane) * 4 + q];
-                const float4 vi = amat[(1 * 64 + lane) * 4 + q];
-                const float4 vs = amat[(2 * 64 + lane) * 4 + q];
-                ar[0] = vr.x; ar[1] = vr.y; ar[2] = vr.z; ar[3] = vr.w;
-                ai[0] = vi.x; ai[1] = vi.y; ai[2] = vi.z; ai[3] = vi.w;
-                as[0] = vs.x; as[1] = vs.y; as[2] = vs.z; as[3] = vs.w;
-            } else {
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    ar[jj] = areg.r[4 * q + jj];
-                    ai[jj] = areg.i[4 * q + jj];
-                    as[jj] = areg.s[4 * q + jj];
-                }
-            }
+            const float4 vr = amat[(0 * 64 + lane) * 4 + q];
+            const float4 vi = amat[(1 * 64 + lane) * 4 + q];
+            const float4 vs = amat[(2 * 64 + lane) * 4 + q];
+            const float ar[4] = {vr.x, vr.y, vr.z, vr.w};
+            const float ai[4] = {vi.x, vi.y, vi.z, vi.w};
+            const float as[4] = {vs.x, vs.y, vs.z, vs.w};
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
                 const float2 xv = x[4 * q + jj];
@@ -104,7 +118,7 @@ __device__ __forceinline__ void region_mfma5(float2* lds, const BatchBlock& b, c
         if (valid) {
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                lds[swz(pout + b.lds_off[8 * (r / 4) + (r % 4)])] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
+                lds[swz(pout + g.off[8 * (r / 4) + (r % 4)])] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
         }
     }
 }
@@ -118,16 +132,21 @@ __device__ __forceinline__ void region_mfma4(float2* lds, const BatchBlock& b, c
     const float ar[4] = {vr.x, vr.y, vr.z, vr.w};
     const float ai[4] = {vi.x, vi.y, vi.z, vi.w};
     const float as[4] = {vs.x, vs.y, vs.z, vs.w};
-    const int groups = 1 << (b.L - b.n_lo);
-    const int lin = ((q & 1) ? b.lds_off[1] : 0) + ((q & 2) ? b.lds_off[2] : 0);
-    const int lout = ((q & 1) ? b.lds_off[4] : 0) + ((q & 2) ? b.lds_off[8] : 0);
+    RegionGeom g;
+    region_geom(b, 16, g);
+    const int groups = 1 << (__builtin_amdgcn_readfirstlane(b.L) - g.n_lo);
+    const int lin = ((q & 1) ? g.off[1] : 0) + ((q & 2) ? g.off[2] : 0);
+    const int lout = ((q & 1) ? g.off[4] : 0) + ((q & 2) ? g.off[8] : 0);
     for (int ct = wave; ct * 16 < groups; ct += kThreads / 64) {
         const int gl = ct * 16 + col;
         const bool valid = gl < groups;
-        const int pb = valid ? int(insert_zeros(uint64_t(gl), b.lo_pos, b.n_lo)) : 0;
+        const int pb = spread_lo(valid ? gl : 0, g);
         float2 x[4];
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) x[s4] = valid ? lds[swz(pb + lin + b.lds_off[4 * s4])] : float2{0.f, 0.f};
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const float2 v = lds[swz(pb + lin + g.off[4 * s4])];
+            x[s4] = valid ? v : float2{0.f, 0.f};
+        }
         f32x4 p1 = {0}, p2 = {0}, p3 = {0};
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
@@ -137,7 +156,7 @@ __device__ __forceinline__ void region_mfma4(float2* lds, const BatchBlock& b, c
         }
         if (valid) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) lds[swz(pb + lout + b.lds_off[r])] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
+            for (int r = 0; r < 4; ++r) lds[swz(pb + lout + g.off[r])] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
         }
     }
 }
@@ -148,15 +167,17 @@ template <int K>
 __device__ __forceinline__ void region_valu(float2* lds, const BatchBlock& b, const float2* __restrict__ m)
 {
     constexpr int D = 1 << K;
-    const int groups = 1 << (b.L - b.n_lo);
+    RegionGeom g;
+    region_geom(b, D, g);
+    const int groups = 1 << (__builtin_amdgcn_readfirstlane(b.L) - g.n_lo);
     for (int gl = threadIdx.x; gl < groups; gl += kThreads) {
         // keeps the matrix loads inside the loop (hoisting all 2^(2K) entries
         // out of it would exhaust the scalar registers)
         asm volatile("" ::: "memory");
-        const int pb = int(insert_zeros(uint64_t(gl), b.lo_pos, b.n_lo));
+        const int pb = spread_lo(gl, g);
         float2 v[D];
 #pragma unroll
-        for (int c = 0; c < D; ++c) v[c] = lds[swz(pb + b.lds_off[c])];
+        for (int c = 0; c < D; ++c) v[c] = lds[swz(pb + g.off[c])];
 #pragma unroll
         for (int r = 0; r < D; ++r) {
             float re = 0.f, im = 0.f;
@@ -168,7 +189,7 @@ __device__ __forceinline__ void region_valu(float2* lds, const BatchBlock& b, co
                 im = fmaf(e.x, v[c].y, im);
                 im = fmaf(e.y, v[c].x, im);
             }
-            lds[swz(pb + b.lds_off[r])] = float2{re, im};
+            lds[swz(pb + g.off[r])] = float2{re, im};
         }
     }
 }
@@ -185,10 +206,10 @@ __device__ __forceinline__ void stage_a(const float* __restrict__ mats, const Ba
 // Applies block b to the region in LDS (A operands already staged in LDS
 // for k = 4, 5).  Callers synchronise before and after.
 __device__ __forceinline__ void apply_region(float2* lds, const BatchBlock& b, const float* __restrict__ mats,
-                                             const float4* amat, const AOps5& areg)
+                                             const float4* amat)
 {
     switch (b.k) {
-        case 5: region_mfma5(lds, b, amat, areg); break;
+        case 5: region_mfma5(lds, b, amat); break;
         case 4: region_mfma4(lds, b, amat); break;
         case 3: region_valu<3>(lds, b, reinterpret_cast<const float2*>(mats + b.mat_off)); break;
         case 2: region_valu<2>(lds, b, reinterpret_cast<const float2*>(mats + b.mat_off)); break;
@@ -299,26 +320,10 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A)
             __syncthreads();
             const BatchBlock& b = A.blocks[c.block0 + bi];
             stage_a(A.mats, b, amat);
-            AOps5 areg;
-            if (!SV_BATCH_A_LDS && b.k == 5) {
-                // straight from global memory: the same packed layout
-                const float4* m4 = reinterpret_cast<const float4*>(A.mats + b.mat_off);
-                const int lane = tid & 63;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float4 vr = m4[(0 * 64 + lane) * 4 + q], vi = m4[(1 * 64 + lane) * 4 + q];
-                    const float4 vs = m4[(2 * 64 + lane) * 4 + q];
-                    areg.r[4 * q] = vr.x; areg.r[4 * q + 1] = vr.y; areg.r[4 * q + 2] = vr.z; areg.r[4 * q + 3] = vr.w;
-                    areg.i[4 * q] = vi.x; areg.i[4 * q + 1] = vi.y; areg.i[4 * q + 2] = vi.z; areg.i[4 * q + 3] = vi.w;
-                    areg.s[4 * q] = vs.x; areg.s[4 * q + 1] = vs.y; areg.s[4 * q + 2] = vs.z; areg.s[4 * q + 3] = vs.w;
-                }
-            }
-            if (resident) {
-                __syncthreads();
-                apply_region(lds, b, A.mats, amat, areg);
-            } else {
-            const int mask = (1 << b.L) - 1;
+            // streaming tiles: run index i >> L of the thread's vector u and
+            // the offset inside the run (unused for a resident state)
             uint64_t goff[8];
+            const int mask = (1 << b.L) - 1;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int i = (u * kThreads + tid) * 2;
@@ -327,42 +332,45 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A)
                 for (int j = 0; j < b.n_hi; ++j) o |= uint64_t((r >> j) & 1u) << b.hi_pos[j];
                 goff[u] = o + uint64_t(i & mask);
             }
-#define SV_DECL(u) float4 buf##u;
+#define SV_DECL(u) float4 buf##u = {};
             SV_REP8(SV_DECL)
 #undef SV_DECL
-            uint64_t base = insert_zeros(0, b.hi_pos, b.n_hi);
 #define SV_LOAD(u) buf##u = *reinterpret_cast<const float4*>(psi + base + goff[u]);
-            SV_REP8(SV_LOAD)
+            uint64_t base = 0;
+            if (!resident) {
+                base = insert_zeros(0, b.hi_pos, b.n_hi);
+                SV_REP8(SV_LOAD)
+            }
+            // one apply site for both kinds of state
             for (uint64_t t = 0; t < n_regions; ++t) {
+                const uint64_t cur = base;
+                if (!resident) {
 #define SV_STAGE(u)                                                                       \
     {                                                                                     \
         const int i = (u * kThreads + tid) * 2;                                           \
         *reinterpret_cast<float4*>(lds + pair_slot(i)) = swap_pair(buf##u, i);            \
     }
-                SV_REP8(SV_STAGE)
+                    SV_REP8(SV_STAGE)
 #undef SV_STAGE
+                }
                 __syncthreads();
-                const uint64_t cur = base;
-                if (SV_BATCH_PREFETCH && t + 1 < n_regions) {
+                if (!resident && t + 1 < n_regions) {
                     base = insert_zeros((t + 1) << b.L, b.hi_pos, b.n_hi);
                     SV_REP8(SV_LOAD)
                 }
-                apply_region(lds, b, A.mats, amat, areg);
+                apply_region(lds, b, A.mats, amat);
                 __syncthreads();
+                if (!resident) {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int i = (u * kThreads + tid) * 2;
-                    *reinterpret_cast<float4*>(psi + cur + goff[u]) =
-                        swap_pair(*reinterpret_cast<const float4*>(lds + pair_slot(i)), i);
-                }
-                __syncthreads();
-                if (!SV_BATCH_PREFETCH && t + 1 < n_regions) {
-                    base = insert_zeros((t + 1) << b.L, b.hi_pos, b.n_hi);
-                    SV_REP8(SV_LOAD)
+                    for (int u = 0; u < 8; ++u) {
+                        const int i = (u * kThreads + tid) * 2;
+                        *reinterpret_cast<float4*>(psi + cur + goff[u]) =
+                            swap_pair(*reinterpret_cast<const float4*>(lds + pair_slot(i)), i);
+                    }
+                    __syncthreads();
                 }
             }
 #undef SV_LOAD
-            }
         }
         __threadfence();
         __syncthreads();
