@@ -247,6 +247,37 @@ def kmax_leg(P, W, torch, H, gates, n):
     return out
 
 
+def graph_leg(P, W, torch, H, n=14, depth=20, reps=200):
+    """A small fused program (the brickwork circuit at n qubits, complex64,
+    k <= 5 blocks) run repeatedly: eager (one launch per block) against a
+    recorded HIP graph replay.  Host wall time per run, averaged over reps,
+    after a few untimed runs (which also settle the k = 5 tile variants)."""
+    gates = W.brickwork(n, depth, 0)
+    st = P.State(H, n, "c64")
+    f = P.fuse(gates, 5)
+
+    def timed(run):
+        for _ in range(5):
+            run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            run()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e6
+
+    eager_us = timed(lambda: P.sv_apply_fused(st.s, f.f))
+    g = P.Graph(st, gates, 5)
+    graph_us = timed(g.launch)
+    out = {"workload": f"{n}-qubit brickwork depth {depth}, complex64, {f.count} fused blocks, run {reps} times",
+           "eager_us_per_run": round(eager_us, 1), "graph_us_per_run": round(graph_us, 1),
+           "speedup": round(eager_us / graph_us, 2)}
+    g.close()
+    f.free()
+    st.close()
+    return out
+
+
 def cpu_baseline(W, P, gates, n, kmax, seconds):
     """The oracle (as it stands) applying the same fused blocks to a 2^n
     complex128 state on the host, until about `seconds` of work is done."""
@@ -291,11 +322,14 @@ def copy_ceiling(torch, n):
     return 2 * (1 << n) * 8 / (ms * 1e-3) / 1e9
 
 
-def gate_sweep(P, W, torch, H, n, sets, reps=3):
+def gate_sweep(P, W, torch, H, n, sets, reps=3, warm=3):
     """Single dense k-qubit gates (Haar random) on `sets` random target sets
     per k, after the paper's gate-application measurement (Sec. II-B, Fig. 2:
-    bandwidth from many random target sets).  Median GB/s per k and dtype,
-    timed with HIP events on the handle's stream."""
+    bandwidth from many random target sets).  Each set is applied `warm`
+    times untimed (the handle settles its k = 5 tile variant), then `reps`
+    times timed with HIP events on the handle's stream.  Median, p10 and p90
+    GB/s per k and dtype, and medians per target class: all targets below
+    n/2 ("low"), all at or above ("high"), or both ("mixed")."""
     import numpy as np
     out = {}
     for dt, ab in (("c64", 8), ("c128", 16)):
@@ -303,11 +337,12 @@ def gate_sweep(P, W, torch, H, n, sets, reps=3):
         rng = np.random.default_rng(1000)
         res = {}
         for k in range(1, 7):
-            bws = []
+            bws, cls = [], []
             for j in range(sets):
                 ts = W.random_targets(n, k, np.random.default_rng(1000 * k + j))
                 m = W.haar_unitary(k, rng)
-                st.apply_matrix(m, ts)
+                for _ in range(warm):
+                    st.apply_matrix(m, ts)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(H.stream)
                 for _ in range(reps):
@@ -316,9 +351,15 @@ def gate_sweep(P, W, torch, H, n, sets, reps=3):
                 e1.synchronize()
                 ms = e0.elapsed_time(e1) / reps
                 bws.append(2 * (1 << n) * ab / (ms * 1e-3) / 1e9)
-            res[str(k)] = {"median_GBps": round(float(np.median(bws)), 1),
-                           "p10_GBps": round(float(np.percentile(bws, 10)), 1),
-                           "p90_GBps": round(float(np.percentile(bws, 90)), 1)}
+                cls.append("low" if max(ts) < n // 2 else "high" if min(ts) >= n // 2 else "mixed")
+            r = {"median_GBps": round(float(np.median(bws)), 1),
+                 "p10_GBps": round(float(np.percentile(bws, 10)), 1),
+                 "p90_GBps": round(float(np.percentile(bws, 90)), 1)}
+            for c in ("low", "mixed", "high"):
+                v = [x for x, y in zip(bws, cls) if y == c]
+                if v:
+                    r[c] = {"sets": len(v), "median_GBps": round(float(np.median(v)), 1)}
+            res[str(k)] = r
         out[dt] = res
         st.close()
         torch.cuda.synchronize()
@@ -524,6 +565,10 @@ def main():
         H4 = P.Handle()
         line["fusion_widths"] = kmax_leg(P, W, torch, H4, gates, n)
         H4.close()
+    print("[bench] graph leg", file=sys.stderr, flush=True)
+    H5 = P.Handle()
+    line["graph_replay"] = graph_leg(P, W, torch, H5)
+    H5.close()
     if not args.no_batched:
         print("[bench] batched leg", file=sys.stderr, flush=True)
         H2 = P.Handle()

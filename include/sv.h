@@ -222,6 +222,26 @@ sv_status_t sv_apply_fused(sv_state_t s, sv_fused_t f);
  * Requires 0 <= first and first + count <= the block count. */
 sv_status_t sv_apply_fused_range(sv_state_t s, sv_fused_t f, int32_t first, int32_t count);
 
+/* A fused program recorded once into a HIP graph for repeated runs (Sec.
+ * II-B: fusion leaves few, large sweeps; for small states each sweep is far
+ * shorter than a kernel launch, so replaying a recorded graph removes the
+ * per-launch host cost).  sv_graph_create packs and uploads all block
+ * matrices of f into device memory owned by the graph (synchronously), then
+ * records the block sweeps for state s into a graph on a private stream;
+ * the k = 5 tile variants are the handle's current choices.  f may be freed
+ * afterwards.  The graph contains kernels only (no memory set or copy
+ * nodes).
+ * sv_graph_launch runs the recorded sweeps on s in place on the handle's
+ * current stream (async), exactly like sv_apply_fused(s, f) would; s must
+ * still exist and keep its device memory.  sv_graph_destroy waits for the
+ * handle's stream and frees the graph and its matrices.
+ * Errors: SV_ERR_INVALID_VALUE for NULL arguments; SV_ERR_OUT_OF_MEMORY if
+ * the matrices do not fit; SV_ERR_DEVICE for HIP failures. */
+typedef struct sv_graph_s* sv_graph_t;
+sv_status_t sv_graph_create(sv_state_t s, sv_fused_t f, sv_graph_t* out);
+sv_status_t sv_graph_launch(sv_graph_t g);
+sv_status_t sv_graph_destroy(sv_graph_t g);
+
 /* ------------------------------------------------------------- reductions */
 
 /* *out = sum_i |psi_i|^2 accumulated in FP64 in a fixed order (bitwise
@@ -294,13 +314,16 @@ sv_status_t sv_batch_state_layout(sv_batch_t b, uint64_t* state_bytes, uint64_t*
 sv_status_t sv_batch_info(sv_batch_t b, int32_t n_qubits, int32_t* max_fused_qubits, int32_t* blocks_per_circuit);
 
 /*
- * Runs the whole batch in one launch on the handle's stream and blocks.
+ * Runs the whole batch in one launch on the handle's stream and blocks.  The
+ * run (queue reset plus the persistent kernel) is recorded into a HIP graph
+ * on the first call for a given states buffer and replayed by later calls
+ * with the same buffer.
  * states: device buffer of sv_batch_state_layout bytes, 256-byte aligned; on
  * return it holds every circuit's final state.  expect_out (host, may be
  * NULL): all term results in term order.  latency_s (host, may be NULL):
  * per circuit, the device wall-clock time from the first workgroup's start
- * to that circuit's completion.  kernel_s (may be NULL): the launch's event
- * time.
+ * to that circuit's completion.  kernel_s (may be NULL): the event time of
+ * the graph launch.
  */
 sv_status_t sv_batch_run(sv_batch_t b, void* states, double* expect_out, double* latency_s, double* kernel_s);
 

@@ -62,6 +62,9 @@ _SIGS = {
     "sv_handle_destroy": [_vp],
     "sv_handle_set_stream": [_vp, _vp],
     "sv_handle_set_tile_mode": [_vp, _i32],
+    "sv_graph_create": [_vp, _vp, ctypes.POINTER(_vp)],
+    "sv_graph_launch": [_vp],
+    "sv_graph_destroy": [_vp],
     "sv_sync": [_vp],
     "sv_create": [_vp, _i32, ctypes.c_int, _vp, ctypes.POINTER(_vp)],
     "sv_destroy": [_vp],
@@ -155,6 +158,20 @@ SV_TILE_AUTO, SV_TILE_NARROW, SV_TILE_WIDE = 0, 1, 2
 
 def sv_handle_set_tile_mode(h: int, mode: int) -> None:
     _check(_L.sv_handle_set_tile_mode(_vp(h), _i32(mode)))
+
+
+def sv_graph_create(s: int, f: int) -> int:
+    out = _vp()
+    _check(_L.sv_graph_create(_vp(s), _vp(f), ctypes.byref(out)))
+    return out.value
+
+
+def sv_graph_launch(g: int) -> None:
+    _check(_L.sv_graph_launch(_vp(g)))
+
+
+def sv_graph_destroy(g: int) -> None:
+    _check(_L.sv_graph_destroy(_vp(g)))
 
 
 def sv_sync(h: int) -> None:
@@ -459,6 +476,33 @@ class Fused:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A fused program recorded into a HIP graph for one state; launch()
+    replays it on the state (async, on the handle's stream)."""
+
+    def __init__(self, state, gates, max_fused_qubits: int = 5):
+        f = fuse(gates, max_fused_qubits)
+        try:
+            self.blocks = f.count
+            self.g = sv_graph_create(state.s, f.f)
+        finally:
+            f.free()
+
+    def launch(self) -> None:
+        sv_graph_launch(self.g)
+
+    def close(self) -> None:
+        if self.g:
+            sv_graph_destroy(self.g)
+            self.g = 0
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass
 

@@ -478,6 +478,98 @@ sv_status_t sv_apply_fused_range(sv_state_t s, sv_fused_t f, int32_t first, int3
     return guarded([&] { apply_fused_blocks(s, f, first, count); });
 }
 
+struct sv_graph_s {
+    sv_state_s* s = nullptr;
+    char* mats = nullptr;  // packed block matrices, device
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+sv_status_t sv_graph_create(sv_state_t s, sv_fused_t f, sv_graph_t* out)
+{
+    return guarded([&] {
+        SV_CHECK(out != nullptr, "out is NULL");
+        *out = nullptr;
+        check_state(s);
+        SV_CHECK(f != nullptr, "fused gates are NULL");
+        sv_handle_s* h = s->h;
+        std::vector<GateDesc> descs(f->n_blocks);
+        std::vector<size_t> offs(f->n_blocks);
+        size_t bytes = 0;
+        for (int b = 0; b < f->n_blocks; ++b) {
+            const FusedBlock& blk = f->blocks[b];
+            descs[b] = make_desc(s->n, blk.targets, blk.k, nullptr, nullptr, 0);
+            offs[b] = bytes;
+            bytes += (packed_matrix_bytes(s->dt, s->n, blk.k, 0) + 255) & ~size_t(255);
+        }
+        std::vector<char> host(bytes ? bytes : 1);
+        for (int b = 0; b < f->n_blocks; ++b)
+            pack_matrix(s->dt, s->n, f->blocks[b].k, 0, f->blocks[b].m, 0, host.data() + offs[b]);
+        auto* g = new sv_graph_s;
+        g->s = s;
+        hipStream_t cap = nullptr;
+        hipStream_t saved = h->stream;
+        try {
+            const hipError_t e = hipMalloc(&g->mats, host.size());
+            if (e != hipSuccess) {
+                g->mats = nullptr;
+                (void)hipGetLastError();
+                throw Error{SV_ERR_OUT_OF_MEMORY, "hipMalloc of the graph's matrices failed"};
+            }
+            SV_HIP(hipMemcpy(g->mats, host.data(), host.size(), hipMemcpyHostToDevice));
+            // record on a private stream: the handle's own stream may be the
+            // null stream, which cannot be captured
+            SV_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            h->stream = cap;
+            SV_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+            try {
+                for (int b = 0; b < f->n_blocks; ++b) launch_apply(h, s->dt, s->d, g->mats + offs[b], descs[b]);
+            } catch (...) {
+                hipGraph_t dropped = nullptr;
+                (void)hipStreamEndCapture(cap, &dropped);
+                if (dropped) (void)hipGraphDestroy(dropped);
+                throw;
+            }
+            SV_HIP(hipStreamEndCapture(cap, &g->graph));
+            h->stream = saved;
+            SV_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+            SV_HIP(hipStreamDestroy(cap));
+            cap = nullptr;
+        } catch (...) {
+            h->stream = saved;
+            if (cap) (void)hipStreamDestroy(cap);
+            if (g->exec) (void)hipGraphExecDestroy(g->exec);
+            if (g->graph) (void)hipGraphDestroy(g->graph);
+            if (g->mats) (void)hipFree(g->mats);
+            delete g;
+            throw;
+        }
+        *out = g;
+    });
+}
+
+sv_status_t sv_graph_launch(sv_graph_t g)
+{
+    return guarded([&] {
+        SV_CHECK(g != nullptr, "graph is NULL");
+        check_state(g->s);
+        SV_HIP(hipGraphLaunch(g->exec, g->s->h->stream));
+    });
+}
+
+sv_status_t sv_graph_destroy(sv_graph_t g)
+{
+    return guarded([&] {
+        SV_CHECK(g != nullptr, "graph is NULL");
+        const hipError_t e = hipStreamSynchronize(g->s->h->stream);
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        if (g->mats) (void)hipFree(g->mats);
+        delete g;
+        SV_HIP(e);
+    });
+}
+
 sv_status_t sv_norm(sv_state_t s, double* out)
 {
     return guarded([&] {

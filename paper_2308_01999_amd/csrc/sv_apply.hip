@@ -838,11 +838,13 @@ int tile_shape(sv_handle_s* h, const GateDesc& d, bool* trial)
     TileTuner& T = *h->tuner;
     uint64_t key = uint64_t(d.n) << 40;
     for (int a = 0; a < d.k; ++a) key |= d.tbit[a];
-    tuner_poll(T);
-    TileTuneEntry& e = T.entries[key];
+    // while the stream is being recorded into a graph: no event queries and
+    // no timed trials, only the choice made so far
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     const bool capturing = hipStreamIsCapturing(h->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
     if (capturing) (void)hipGetLastError();
+    if (!capturing) tuner_poll(T);
+    TileTuneEntry& e = T.entries[key];
     if (!capturing) {
         // the shape with fewer timings started, narrow first
         int s = -1;

@@ -46,6 +46,11 @@ struct sv_batch_s {
     char* dev = nullptr;  // one arena for all device-side descriptors
     sv::BatchArgs args{};
     double tick_hz = 1e8;
+    // the run (queue reset + persistent kernel), recorded once per states
+    // buffer into a HIP graph and replayed by every later run
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* graph_states = nullptr;
 };
 
 namespace sv {
@@ -434,6 +439,47 @@ sv_batch_s* batch_create(sv_handle_s* h, int n_circuits, const int32_t* n_qubits
     return b;
 }
 
+static void drop_graph(sv_batch_s* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_states = nullptr;
+}
+
+// Records the queue reset and the persistent kernel for b->args.states on a
+// private stream (the handle's may be the null stream, which cannot be
+// captured).  Kernel nodes only.
+static void record_run(sv_batch_s* b)
+{
+    sv_handle_s* h = b->h;
+    SV_HIP(hipStreamSynchronize(h->stream));
+    drop_graph(b);
+    hipStream_t cap = nullptr;
+    SV_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    try {
+        SV_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+        try {
+            launch_batch_reset(cap, b->args);
+            launch_batch(cap, h->cu_count, b->args);
+        } catch (...) {
+            hipGraph_t dropped = nullptr;
+            (void)hipStreamEndCapture(cap, &dropped);
+            if (dropped) (void)hipGraphDestroy(dropped);
+            throw;
+        }
+        SV_HIP(hipStreamEndCapture(cap, &b->graph));
+        SV_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->graph_states = b->args.states;
+    } catch (...) {
+        (void)hipStreamDestroy(cap);
+        drop_graph(b);
+        throw;
+    }
+    SV_HIP(hipStreamDestroy(cap));
+}
+
 void batch_run(sv_batch_s* b, void* states, double* expect_out, double* latency_s, double* kernel_s)
 {
     SV_CHECK(b != nullptr, "batch is NULL");
@@ -448,9 +494,9 @@ void batch_run(sv_batch_s* b, void* states, double* expect_out, double* latency_
     std::vector<uint64_t> done(b->n_circuits);
     uint64_t t0 = 0;
     try {
-        launch_batch_reset(h->stream, b->args);
+        if (!b->exec || b->graph_states != states) record_run(b);
         SV_HIP(hipEventRecord(e0, h->stream));
-        launch_batch(h->stream, h->cu_count, b->args);
+        SV_HIP(hipGraphLaunch(b->exec, h->stream));
         SV_HIP(hipEventRecord(e1, h->stream));
         if (expect_out && b->total_terms > 0)
             SV_HIP(hipMemcpyAsync(expect_out, b->args.expect, sizeof(double) * b->total_terms,
@@ -490,10 +536,9 @@ void batch_info(sv_batch_s* b, int n_qubits, int32_t* kmax, int32_t* blocks)
 void batch_destroy(sv_batch_s* b)
 {
     if (!b) return;
-    if (b->dev) {
-        (void)hipStreamSynchronize(b->h->stream);
-        (void)hipFree(b->dev);
-    }
+    (void)hipStreamSynchronize(b->h->stream);
+    drop_graph(b);
+    if (b->dev) (void)hipFree(b->dev);
     delete b;
 }
 

@@ -455,3 +455,33 @@ def test_tile_mode_rejects_unknown(P, H):
     with pytest.raises(P.SVError):
         H.set_tile_mode(3)
     H.set_tile_mode(P.SV_TILE_AUTO)
+
+
+# ------------------------------------------------------ recorded programs
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n", [6, 12, 16])
+def test_graph_replays_match_eager_and_oracle(P, H, dt, n):
+    # a fused program recorded into a HIP graph, replayed three times with
+    # the program's own eager work (state reset, an eager sweep, a read-back)
+    # between replays: every replay equals the eager fused run bit for bit
+    gates = W.brickwork(n, 6, 70 + n)
+    ref = oracle.run(n, gates)
+    st = _state(P, H, n, dt)
+    st.run(gates, max_fused_qubits=5)
+    eager = st.to_numpy()
+    if dt == "c128":
+        assert np.max(np.abs(eager - ref)) <= 1e-10
+    else:
+        assert oracle.fidelity(ref, eager.astype(np.complex128)) >= C64_FID
+    g = P.Graph(st, gates, 5)
+    for rep in range(3):
+        P.sv_set_basis_state(st.s, 0)
+        g.launch()
+        got = st.to_numpy()
+        np.testing.assert_array_equal(got, eager, err_msg=f"replay {rep}")
+        # eager work between replays on the same handle
+        st.apply_matrix(np.array([[0, 1], [1, 0]]), (n - 1,))
+        P.sv_sync(H.h)
+    g.close()
+    st.close()
