@@ -621,6 +621,176 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restri
     }
 }
 
+// ----------------------------------------------------------- k = 6 tiles
+//
+// Six-qubit blocks on the matrix cores: a 64 x 64 complex matrix per group,
+// three real GEMMs (Gauss).  64 KiB tiles in 512-thread workgroups (eight
+// waves); the A operands are staged once per workgroup in LDS.  Every wave
+// reads all inputs of its groups, so the outputs are written back only after
+// a barrier.  One workgroup fits a CU (LDS), so the next tile's loads are in
+// flight while a tile is transformed, as in the k = 5 sweep.
+constexpr int kK6Threads = 512;
+
+// complex64: v_mfma_f32_32x32x2_f32.  Wave w takes 32 groups (column tile
+// w & 3) and 32 output rows (row tile w >> 2), K = 64 in 32 steps of 2.
+// A_g (g = Re, Im, Re + Im) per lane l = i + 32 half, row tile rt:
+// amat[((g * 2 + rt) * 64 + l) * 8 + s4] = A_g[32 rt + i][2 (4 s4 + j) + half], j = 0..3.
+__global__ __launch_bounds__(kK6Threads, 2) void k_tile_c64_k6(float2* __restrict__ psi,
+                                                              const float4* __restrict__ mats, TileArgs a)
+{
+    constexpr int NT = kK6Threads;
+    __shared__ float4 lds[NT * kTileVecs];
+    __shared__ float4 amat[3 * 2 * 64 * 8];
+    const uint64_t t0 = tile_group(a) * a.tiles_per_wg;
+    if (t0 >= a.n_tiles) return;
+    const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 31, half = lane >> 5;
+    const int ct = wave & 3, rt = wave >> 2;
+    for (int e = tid; e < 3 * 2 * 64 * 8; e += NT) amat[e] = mats[e];
+    uint64_t roff[kTileVecs];
+    uint32_t poff[kTileVecs];
+    tile_offsets<2, NT>(a, roff, poff);
+    const int pb = int(insert_zero_bits(uint64_t(ct * 32 + col), a.lo_pos, a.n_lo));
+    const int pin = pb + (half ? a.lds_off[1] : 0);
+    const int pout = pb + (half ? a.lds_off[4] : 0) + (rt ? a.lds_off[32] : 0);
+    float2* lds2 = reinterpret_cast<float2*>(lds);
+#define SV_DECL(u) float4 buf##u;
+    SV_REP8(SV_DECL)
+#undef SV_DECL
+    uint64_t base = tile_base(t0, a);
+#define SV_LOAD(u) buf##u = gload(reinterpret_cast<const float4*>(psi + base + roff[u] + poff[u]));
+    SV_REP8(SV_LOAD)
+#undef SV_LOAD
+    for (uint64_t t = t0; t < t1; ++t) {
+#define SV_STAGE(u)                                                                        \
+    {                                                                                      \
+        const int i = (u * NT + tid) * 2;                                                  \
+        *reinterpret_cast<float4*>(lds2 + pair_slot(i)) = swap_pair(buf##u, pair_swapped(i)); \
+    }
+        SV_REP8(SV_STAGE)
+#undef SV_STAGE
+        __syncthreads();
+        uint64_t nbase = 0;
+        if (t + 1 < t1) {
+            nbase = tile_base(t + 1, a);
+#define SV_PREFETCH(u) buf##u = gload(reinterpret_cast<const float4*>(psi + nbase + roff[u] + poff[u]));
+            SV_REP8(SV_PREFETCH)
+#undef SV_PREFETCH
+        }
+        float2 x[32];
+#pragma unroll
+        for (int s2 = 0; s2 < 32; ++s2) x[s2] = lds2[lds_swz(pin + a.lds_off[2 * s2])];
+        f32x16 p1 = {0}, p2 = {0}, p3 = {0};
+#pragma unroll
+        for (int s4 = 0; s4 < 8; ++s4) {
+            const float4 vr = amat[((0 * 2 + rt) * 64 + lane) * 8 + s4];
+            const float4 vi = amat[((1 * 2 + rt) * 64 + lane) * 8 + s4];
+            const float4 vs = amat[((2 * 2 + rt) * 64 + lane) * 8 + s4];
+            const float ar[4] = {vr.x, vr.y, vr.z, vr.w};
+            const float ai[4] = {vi.x, vi.y, vi.z, vi.w};
+            const float as[4] = {vs.x, vs.y, vs.z, vs.w};
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const float2 xv = x[4 * s4 + jj];
+                p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[jj], xv.x, p1, 0, 0, 0);
+                p2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[jj], xv.y, p2, 0, 0, 0);
+                p3 = __builtin_amdgcn_mfma_f32_32x32x2f32(as[jj], xv.x + xv.y, p3, 0, 0, 0);
+            }
+        }
+        __syncthreads();  // every wave has read its inputs
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            lds2[lds_swz(pout + a.lds_off[8 * (r / 4) + (r % 4)])] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kTileVecs; ++u) {
+            const int i = (u * NT + tid) * 2;
+            gstore(reinterpret_cast<float4*>(psi + base + roff[u] + poff[u]),
+                   swap_pair(*reinterpret_cast<const float4*>(lds2 + pair_slot(i)), pair_swapped(i)));
+        }
+        base = nbase;
+        __syncthreads();
+    }
+}
+
+// complex128: v_mfma_f64_16x16x4_f64.  Wave w takes 16 groups (column tile
+// w & 3) and 32 output rows (row tiles 2 (w >> 2) and 2 (w >> 2) + 1), K = 64
+// in 16 steps of 4.  A_g (g = Re, Im; Re + Im is summed here) per lane
+// l = i + 16 q, row tile rt: amat[((g * 4 + rt) * 16 + s) * 64 + l] = A_g[16 rt + i][4 s + q].
+__global__ __launch_bounds__(kK6Threads, 2) void k_tile_c128_k6(double2* __restrict__ psi,
+                                                               const double* __restrict__ mats, TileArgs a)
+{
+    constexpr int NT = kK6Threads;
+    __shared__ double2 lds[NT * kTileVecs];
+    __shared__ double amat[2 * 4 * 16 * 64];
+    const uint64_t t0 = tile_group(a) * a.tiles_per_wg;
+    if (t0 >= a.n_tiles) return;
+    const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, q = lane >> 4;
+    const int ct = wave & 3, rh = wave >> 2;
+    for (int e = tid; e < 2 * 4 * 16 * 64; e += NT) amat[e] = mats[e];
+    uint64_t roff[kTileVecs];
+    uint32_t poff[kTileVecs];
+    tile_offsets<1, NT>(a, roff, poff);
+    const int pb = int(insert_zero_bits(uint64_t(ct * 16 + col), a.lo_pos, a.n_lo));
+    // inputs: matrix index 4 s + q; outputs: row 16 rt + 4 v + q: bits 0-1 = q
+    const int pq = pb + ((q & 1) ? a.lds_off[1] : 0) + ((q & 2) ? a.lds_off[2] : 0);
+#define SV_DECL(u) double2 buf##u;
+    SV_REP8(SV_DECL)
+#undef SV_DECL
+    uint64_t base = tile_base(t0, a);
+#define SV_LOAD(u) buf##u = gload(psi + base + roff[u] + poff[u]);
+    SV_REP8(SV_LOAD)
+#undef SV_LOAD
+    for (uint64_t t = t0; t < t1; ++t) {
+#define SV_STAGE(u) lds[lds_swz(u * NT + tid)] = buf##u;
+        SV_REP8(SV_STAGE)
+#undef SV_STAGE
+        __syncthreads();
+        uint64_t nbase = 0;
+        if (t + 1 < t1) {
+            nbase = tile_base(t + 1, a);
+#define SV_PREFETCH(u) buf##u = gload(psi + nbase + roff[u] + poff[u]);
+            SV_REP8(SV_PREFETCH)
+#undef SV_PREFETCH
+        }
+        double2 x[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) x[s] = lds[lds_swz(pq + a.lds_off[4 * s])];
+        f64x4 p1[2], p2[2], p3[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int rt = 2 * rh + h;
+            p1[h] = f64x4{0, 0, 0, 0};
+            p2[h] = f64x4{0, 0, 0, 0};
+            p3[h] = f64x4{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const double ar = amat[((0 * 4 + rt) * 16 + s) * 64 + lane];
+                const double ai = amat[((1 * 4 + rt) * 16 + s) * 64 + lane];
+                p1[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, x[s].x, p1[h], 0, 0, 0);
+                p2[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, x[s].y, p2[h], 0, 0, 0);
+                p3[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar + ai, x[s].x + x[s].y, p3[h], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // every wave has read its inputs
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int rt = 2 * rh + h;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                lds[lds_swz(pq + a.lds_off[16 * rt + 4 * v])] =
+                    double2{p1[h][v] - p2[h][v], p3[h][v] - p1[h][v] - p2[h][v]};
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kTileVecs; ++u)
+            gstore(psi + base + roff[u] + poff[u], lds[lds_swz(u * NT + tid)]);
+        base = nbase;
+        __syncthreads();
+    }
+}
+
 // Large gates (k = 7..10, compute-bound): one workgroup per group.  The
 // group's 2^k amplitudes are staged in LDS; each thread forms whole rows.
 struct ApplyArgsLarge {
@@ -674,7 +844,7 @@ __global__ __launch_bounds__(256) void k_apply_large(typename Cx<R>::T* __restri
     }
 }
 
-enum class Path { kValu, kLarge, kMfmaC64K5, kMfmaC64K4, kTileC64K5, kTileC64K4, kTileC128K5 };
+enum class Path { kValu, kLarge, kMfmaC64K5, kMfmaC64K4, kTileC64K5, kTileC64K4, kTileC128K5, kTileC64K6, kTileC128K6 };
 
 Path choose(sv_dtype_t dt, int n, int k, int n_controls)
 {
@@ -683,6 +853,8 @@ Path choose(sv_dtype_t dt, int n, int k, int n_controls)
     if (dt == SV_C64 && k == 5) return (tile_ok && n >= 12) ? Path::kTileC64K5 : Path::kMfmaC64K5;
     if (dt == SV_C64 && k == 4) return (tile_ok && n >= 12) ? Path::kTileC64K4 : Path::kMfmaC64K4;
     if (dt == SV_C128 && k == 5 && tile_ok && n >= 11) return Path::kTileC128K5;
+    if (dt == SV_C64 && k == 6 && tile_ok && n >= 13) return Path::kTileC64K6;
+    if (dt == SV_C128 && k == 6 && tile_ok && n >= 12) return Path::kTileC128K6;
     return Path::kValu;
 }
 
@@ -877,7 +1049,11 @@ void launch_tile(sv_handle_s* h, Path p, void* psi, const void* mats, const Gate
         tr.e1 = tuner_event(*h->tuner);
         SV_HIP(hipEventRecord(tr.e0, h->stream));
     }
-    const int tb = (p == Path::kTileC128K5) ? 11 : wide ? kK5TileBits : 12;
+    const int tb = (p == Path::kTileC128K5)   ? 11
+                   : (p == Path::kTileC64K6) ? 13
+                   : (p == Path::kTileC128K6) ? 12
+                   : wide                     ? kK5TileBits
+                                              : 12;
     TileArgs t = make_tile_args(d, d.n, tb, h->cu_count);
     t.rot = p == Path::kTileC64K5 ? kTileVariants[variant].rot : 0;
     const uint64_t blocks = (t.n_tiles + t.tiles_per_wg - 1) / t.tiles_per_wg;
@@ -897,6 +1073,14 @@ void launch_tile(sv_handle_s* h, Path p, void* psi, const void* mats, const Gate
         case Path::kTileC128K5:
             hipLaunchKernelGGL(k_tile_c128_k5, dim3(unsigned(blocks)), dim3(kTileThreads), 0, h->stream,
                                static_cast<double2*>(psi), static_cast<const double2*>(mats), t);
+            break;
+        case Path::kTileC64K6:
+            hipLaunchKernelGGL(k_tile_c64_k6, dim3(unsigned(blocks)), dim3(kK6Threads), 0, h->stream,
+                               static_cast<float2*>(psi), static_cast<const float4*>(mats), t);
+            break;
+        case Path::kTileC128K6:
+            hipLaunchKernelGGL(k_tile_c128_k6, dim3(unsigned(blocks)), dim3(kK6Threads), 0, h->stream,
+                               static_cast<double2*>(psi), static_cast<const double*>(mats), t);
             break;
         default:
             throw Error{SV_ERR_INTERNAL, "not a tile path"};
@@ -971,6 +1155,10 @@ size_t packed_matrix_bytes(sv_dtype_t dt, int n, int k, int n_controls)
             return 3 * d2 * sizeof(float);
         case Path::kTileC128K5:
             return 3 * d2 * sizeof(double);
+        case Path::kTileC64K6:
+            return 3 * d2 * sizeof(float);
+        case Path::kTileC128K6:
+            return 2 * d2 * sizeof(double);
         default:
             return d2 * (dt == SV_C64 ? 8 : 16);
     }
@@ -1013,6 +1201,26 @@ void pack_matrix(sv_dtype_t dt, int n, int k, int n_controls, const double* m, i
                         o[(g * 64 + l) * 16 + rt * 8 + s8] = A(g, (l & 15) + 16 * rt, 4 * s8 + (l >> 4));
         return;
     }
+    if (p == Path::kTileC64K6) {
+        // lane l = i + 32 half, row tile rt: 32 floats A_g[32 rt + i][2 s + half], s = 0..31
+        float* o = static_cast<float*>(dst);
+        for (int g = 0; g < 3; ++g)
+            for (int rt = 0; rt < 2; ++rt)
+                for (int l = 0; l < 64; ++l)
+                    for (int s2 = 0; s2 < 32; ++s2)
+                        o[((g * 2 + rt) * 64 + l) * 32 + s2] = float(A(g, 32 * rt + (l & 31), 2 * s2 + (l >> 5)));
+        return;
+    }
+    if (p == Path::kTileC128K6) {
+        // [g][rt][s][lane]: A_g[16 rt + i][4 s + q] at lane i + 16 q (g = Re, Im)
+        double* o = static_cast<double*>(dst);
+        for (int g = 0; g < 2; ++g)
+            for (int rt = 0; rt < 4; ++rt)
+                for (int s4 = 0; s4 < 16; ++s4)
+                    for (int l = 0; l < 64; ++l)
+                        o[((g * 4 + rt) * 16 + s4) * 64 + l] = A(g, 16 * rt + (l & 15), 4 * s4 + (l >> 4));
+        return;
+    }
     for (int r = 0; r < d; ++r)
         for (int c = 0; c < d; ++c) {
             const double re = A(0, r, c), im = A(1, r, c);
@@ -1039,6 +1247,8 @@ void launch_apply(sv_handle_s* h, sv_dtype_t dt, void* psi, const void* mat, con
         case Path::kTileC64K4:
         case Path::kTileC64K5:
         case Path::kTileC128K5:
+        case Path::kTileC64K6:
+        case Path::kTileC128K6:
             launch_tile(h, p, psi, mat, d);
             break;
         default:

@@ -167,6 +167,20 @@ def test_fused_brickwork_matches_oracle(P, H, dt, kmax):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_fused_kmax6_on_tiles_matches_oracle(P, H, dt):
+    # six-qubit blocks through the k = 6 MFMA tiles (64 KiB tiles, several per
+    # state), low, mixed and high windows
+    n, depth = 16, 12
+    gates = W.brickwork(n, depth, 13)
+    ref = oracle.run(n, gates)
+    st = _state(P, H, n, dt)
+    nb = st.run(gates, max_fused_qubits=6)
+    assert nb >= 1
+    _check_state(st.to_numpy(), ref, dt)
+    st.close()
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
 def test_brickwork_20q_unfused_and_fused(P, H, dt):
     n, depth = 20, 20
     gates = W.brickwork(n, depth, 11)
