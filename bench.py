@@ -37,11 +37,17 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE reads them all, x1.0).  Valid only for the kernel source the
 # counters were taken on: its SHA-256 is recorded and checked at run time.
 PMC_TRAFFIC = {
-    # dispatch-weighted over both tile shapes (112 narrow, 72 wide launches)
-    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194402.5, "write_kib": 8389907.3,
+    # 30-qubit brickwork sweep, dispatch-weighted over both tile shapes
+    # (c64: 112 narrow + 72 wide fetch, 127 + 57 write launches;
+    #  c128: 122 narrow + 62 wide fetch, 122 + 62 write launches)
+    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194405.1, "write_kib": 8390015.9,
                       "fetch_scale": 2.0, "write_scale": 1.0,
                       "source": "paper_2308_01999_amd/csrc/sv_apply.hip",
-                      "source_sha256": "161a74fd369c475610aa52a17948e1c437d931d1444a30281a4176eba82e6ace"},
+                      "source_sha256": "dfbe3156601a4b472b81a6ffa5fb25bb724e49a7b4136bb122010dcbabef0ef8"},
+    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388722.6, "write_kib": 16781369.2,
+                       "fetch_scale": 2.0, "write_scale": 1.0,
+                       "source": "paper_2308_01999_amd/csrc/sv_apply.hip",
+                       "source_sha256": "dfbe3156601a4b472b81a6ffa5fb25bb724e49a7b4136bb122010dcbabef0ef8"},
 }
 
 
@@ -66,6 +72,10 @@ def dominant_kernel_name(dt, k, n):
         return f"k_tile_c64_k{k}"
     if dt == "c128" and k == 5 and n >= 11:
         return "k_tile_c128_k5"
+    if dt == "c64" and k == 6 and n >= 13:
+        return "k_tile_c64_k6"
+    if dt == "c128" and k == 6 and n >= 12:
+        return "k_tile_c128_k6"
     if dt == "c64" and k in (4, 5):
         return f"k_apply_mfma_c64_k{k}"
     return f"k_apply_dense<{'float' if dt == 'c64' else 'double'}, {k}>"
@@ -560,6 +570,14 @@ def main():
         "c64": r64,
         **extra,
     }
+    if "c128" in extra:
+        # the same figure for the complex128 leg's dominant kernel
+        dk2 = extra["c128"]["dominant_kernel"]
+        k2 = dominant_kernel_name("c128", dk2["k"], n)
+        line["roofline_c128"] = {"bound": "hbm", "achieved": round(dk2["GBps"], 1), "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": round(dk2["GBps"] / HBM_PEAK_GBS, 4),
+                                 "traffic": pmc_traffic(k2, n), "kernel": k2,
+                                 "bytes_per_launch": dk2["bytes_per_launch"], "avg_launch_ms": round(dk2["avg_ms"], 4)}
     if not args.no_kmax_sweep:
         print("[bench] unfused / kmax sweep", file=sys.stderr, flush=True)
         H4 = P.Handle()

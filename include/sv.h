@@ -95,19 +95,20 @@ sv_status_t sv_handle_destroy(sv_handle_t h);
 /* Rebinds the handle to another stream (the caller synchronises the switch). */
 sv_status_t sv_handle_set_stream(sv_handle_t h, void* hip_stream);
 
-/* Tile variant of the complex64 five-qubit sweep (the fused-gate hot path,
- * Sec. II-B: gate fusion makes k = 5 the common case).  All variants do the
- * same arithmetic on every amplitude group, so results are bitwise the same
- * whichever runs; they differ in tile shape (32 KiB tiles in 256-thread
- * workgroups, or 64 KiB tiles in 512-thread workgroups with twice as long
- * contiguous runs) and in the order workgroups take tiles.  Which one moves
- * HBM fastest depends on the target bits.
+/* Tile variant of the five-qubit sweeps (the fused-gate hot path, Sec.
+ * II-B: gate fusion makes k = 5 the common case), complex64 and complex128.
+ * All variants do the same arithmetic on every amplitude group, so results
+ * are bitwise the same whichever runs; they differ in tile shape (256-thread
+ * workgroups on 32 KiB tiles, or 512-thread workgroups on 64 KiB tiles with
+ * twice as long contiguous runs) and in the order workgroups take tiles.
+ * Which one moves HBM fastest depends on the target bits.
  *   SV_TILE_AUTO (default): the handle times each variant once on the first
  *     sweeps of every (state size, target set) it sees, with HIP events on
  *     its stream, then keeps the fastest (no timing while the stream is
  *     being captured);
  *   SV_TILE_NARROW / SV_TILE_WIDE: always that shape in tile order (wide
- *     needs n >= 13; smaller states use the narrow one).
+ *     needs n >= 13 for complex64 and n >= 12 for complex128; smaller states
+ *     use the narrow one).
  * Returns SV_ERR_INVALID_VALUE for any other mode. */
 typedef enum { SV_TILE_AUTO = 0, SV_TILE_NARROW = 1, SV_TILE_WIDE = 2 } sv_tile_mode_t;
 sv_status_t sv_handle_set_tile_mode(sv_handle_t h, int32_t mode);

@@ -554,26 +554,43 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict
 // complex128, k = 5 on v_mfma_f64_16x16x4_f64: 64 groups per tile, one
 // 16-column tile per wave; two 16-row tiles cover the 32 output amplitudes.
 // A_g slices per lane: 2 row tiles x 8 k-steps = 16 doubles.
-__global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restrict__ psi,
+#ifndef SV_C128_A_LDS
+#define SV_C128_A_LDS 1
+#endif
+// NT = 256: 32 KiB tiles (2048 amplitudes); NT = 512: 64 KiB tiles (the
+// wide shape), eight waves.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_tile_c128_k5(double2* __restrict__ psi,
                                                               const double2* __restrict__ mats, TileArgs a)
 {
-    __shared__ double2 lds[kTileThreads * kTileVecs];
+    __shared__ double2 lds[NT * kTileVecs];
+    // SV_C128_A_LDS: Re M and Im M staged in LDS lane-contiguous (16 KiB;
+    // Re M + Im M summed at use) instead of 48 doubles per lane in registers
+    __shared__ double amat[SV_C128_A_LDS ? 2 * 16 * 64 : 1];
     const uint64_t t0 = tile_group(a) * a.tiles_per_wg;
     if (t0 >= a.n_tiles) return;
     const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, q = lane >> 4;
     double A[3][16];
-#pragma unroll
-    for (int g = 0; g < 3; ++g)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const double2 v = mats[(g * 64 + lane) * 8 + e];
-            A[g][2 * e] = v.x;
-            A[g][2 * e + 1] = v.y;
+    if (SV_C128_A_LDS) {
+        const double* m1 = reinterpret_cast<const double*>(mats);
+        for (int e = tid; e < 2 * 16 * 64; e += NT) {
+            const int g = e >> 10, j = (e >> 6) & 15, l = e & 63;
+            amat[e] = m1[(g * 64 + l) * 16 + j];
         }
+    } else {
+#pragma unroll
+        for (int g = 0; g < 3; ++g)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const double2 v = mats[(g * 64 + lane) * 8 + e];
+                A[g][2 * e] = v.x;
+                A[g][2 * e + 1] = v.y;
+            }
+    }
     uint64_t roff[kTileVecs];
     uint32_t poff[kTileVecs];
-    tile_offsets<1>(a, roff, poff);
+    tile_offsets<1, NT>(a, roff, poff);
     const int pb = int(insert_zero_bits(uint64_t(wave * 16 + col), a.lo_pos, a.n_lo));
     // loads: matrix index 4s + q; stores: row 16 rt + 4 v + q: bits 0-1 = q
     const int pq = pb + ((q & 1) ? a.lds_off[1] : 0) + ((q & 2) ? a.lds_off[2] : 0);
@@ -585,7 +602,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restri
     SV_REP8(SV_LOAD)
 #undef SV_LOAD
     for (uint64_t t = t0; t < t1; ++t) {
-#define SV_STAGE(u) lds[lds_swz(u * kTileThreads + tid)] = buf##u;
+#define SV_STAGE(u) lds[lds_swz(u * NT + tid)] = buf##u;
         SV_REP8(SV_STAGE)
 #undef SV_STAGE
         __syncthreads();
@@ -604,9 +621,19 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restri
             f64x4 p1 = {0}, p2 = {0}, p3 = {0};
 #pragma unroll
             for (int s8 = 0; s8 < 8; ++s8) {
-                p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[0][rt * 8 + s8], x[s8].x, p1, 0, 0, 0);
-                p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[1][rt * 8 + s8], x[s8].y, p2, 0, 0, 0);
-                p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[2][rt * 8 + s8], x[s8].x + x[s8].y, p3, 0, 0, 0);
+                double a0, a1, a2;
+                if (SV_C128_A_LDS) {
+                    a0 = amat[(0 * 16 + rt * 8 + s8) * 64 + lane];
+                    a1 = amat[(1 * 16 + rt * 8 + s8) * 64 + lane];
+                    a2 = a0 + a1;
+                } else {
+                    a0 = A[0][rt * 8 + s8];
+                    a1 = A[1][rt * 8 + s8];
+                    a2 = A[2][rt * 8 + s8];
+                }
+                p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x[s8].x, p1, 0, 0, 0);
+                p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x[s8].y, p2, 0, 0, 0);
+                p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, x[s8].x + x[s8].y, p3, 0, 0, 0);
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v)
@@ -615,7 +642,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c128_k5(double2* __restri
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kTileVecs; ++u)
-            gstore(psi + base + roff[u] + poff[u], lds[lds_swz(u * kTileThreads + tid)]);
+            gstore(psi + base + roff[u] + poff[u], lds[lds_swz(u * NT + tid)]);
         base = nbase;
         __syncthreads();
     }
@@ -991,7 +1018,7 @@ void tuner_poll(TileTuner& T)
     }
 }
 
-// Variants of the complex64 k = 5 sweep the handle chooses among:
+// Variants of the k = 5 sweeps (complex64 and complex128) the handle chooses among:
 // shape (narrow 32 KiB / wide 64 KiB tiles) and tile-group order.
 struct TileVariant {
     bool wide;
@@ -1001,15 +1028,25 @@ constexpr TileVariant kTileVariants[kTileShapes] = {{false, 0}, {true, 0}, {fals
 
 // Variant for a complex64 k = 5 sweep (index into kTileVariants).  *trial is
 // set when this launch is to be timed.
-int tile_shape(sv_handle_s* h, const GateDesc& d, bool* trial)
+uint64_t tune_key(Path p, const GateDesc& d)
+{
+    uint64_t key = (uint64_t(d.n) << 40) | (uint64_t(p == Path::kTileC128K5) << 48);
+    for (int a = 0; a < d.k; ++a) key |= d.tbit[a];
+    return key;
+}
+
+// Tile bits of the wide shape: complex64 64 KiB = 2^13 amplitudes,
+// complex128 64 KiB = 2^12.
+int wide_tile_bits(Path p) { return p == Path::kTileC128K5 ? 12 : kK5TileBits; }
+
+int tile_shape(sv_handle_s* h, Path p, const GateDesc& d, bool* trial)
 {
     *trial = false;
-    if (d.n < kK5TileBits) return 0;
+    if (d.n < wide_tile_bits(p)) return 0;
     if (h->tile_mode == SV_TILE_NARROW) return 0;
     if (h->tile_mode == SV_TILE_WIDE) return 1;
     TileTuner& T = *h->tuner;
-    uint64_t key = uint64_t(d.n) << 40;
-    for (int a = 0; a < d.k; ++a) key |= d.tbit[a];
+    const uint64_t key = tune_key(p, d);
     // while the stream is being recorded into a graph: no event queries and
     // no timed trials, only the choice made so far
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -1038,24 +1075,24 @@ int tile_shape(sv_handle_s* h, const GateDesc& d, bool* trial)
 void launch_tile(sv_handle_s* h, Path p, void* psi, const void* mats, const GateDesc& d)
 {
     bool trial = false;
-    const int variant = p == Path::kTileC64K5 ? tile_shape(h, d, &trial) : 0;
-    const bool wide = p == Path::kTileC64K5 && kTileVariants[variant].wide;
+    const bool tuned = p == Path::kTileC64K5 || p == Path::kTileC128K5;
+    const int variant = tuned ? tile_shape(h, p, d, &trial) : 0;
+    const bool wide = tuned && kTileVariants[variant].wide;
     TileTrial tr{};
     if (trial) {
-        tr.key = uint64_t(d.n) << 40;
-        for (int a = 0; a < d.k; ++a) tr.key |= d.tbit[a];
+        tr.key = tune_key(p, d);
         tr.shape = variant;
         tr.e0 = tuner_event(*h->tuner);
         tr.e1 = tuner_event(*h->tuner);
         SV_HIP(hipEventRecord(tr.e0, h->stream));
     }
-    const int tb = (p == Path::kTileC128K5)   ? 11
+    const int tb = (p == Path::kTileC128K5)   ? (wide ? 12 : 11)
                    : (p == Path::kTileC64K6) ? 13
                    : (p == Path::kTileC128K6) ? 12
                    : wide                     ? kK5TileBits
                                               : 12;
     TileArgs t = make_tile_args(d, d.n, tb, h->cu_count);
-    t.rot = p == Path::kTileC64K5 ? kTileVariants[variant].rot : 0;
+    t.rot = tuned ? kTileVariants[variant].rot : 0;
     const uint64_t blocks = (t.n_tiles + t.tiles_per_wg - 1) / t.tiles_per_wg;
     switch (p) {
         case Path::kTileC64K5:
@@ -1071,8 +1108,12 @@ void launch_tile(sv_handle_s* h, Path p, void* psi, const void* mats, const Gate
                                static_cast<float2*>(psi), static_cast<const float4*>(mats), t);
             break;
         case Path::kTileC128K5:
-            hipLaunchKernelGGL(k_tile_c128_k5, dim3(unsigned(blocks)), dim3(kTileThreads), 0, h->stream,
-                               static_cast<double2*>(psi), static_cast<const double2*>(mats), t);
+            if (wide)
+                hipLaunchKernelGGL(k_tile_c128_k5<512>, dim3(unsigned(blocks)), dim3(512), 0, h->stream,
+                                   static_cast<double2*>(psi), static_cast<const double2*>(mats), t);
+            else
+                hipLaunchKernelGGL(k_tile_c128_k5<kTileThreads>, dim3(unsigned(blocks)), dim3(kTileThreads), 0,
+                                   h->stream, static_cast<double2*>(psi), static_cast<const double2*>(mats), t);
             break;
         case Path::kTileC64K6:
             hipLaunchKernelGGL(k_tile_c64_k6, dim3(unsigned(blocks)), dim3(kK6Threads), 0, h->stream,

@@ -436,10 +436,11 @@ def test_copy_ranges(P, H):
 
 # ----------------------------------------------------- k = 5 tile shapes
 
+@pytest.mark.parametrize("dt", ["c64", "c128"])
 @pytest.mark.parametrize("targets", [(0, 1, 2, 3, 4), (3, 7, 9, 12, 15), (11, 12, 13, 14, 15), (2, 6, 10, 13, 16)])
-def test_k5_tile_shapes_agree_bitwise(P, targets):
-    # the narrow (32 KiB, 256 threads) and wide (64 KiB, 512 threads) shapes
-    # of the complex64 k = 5 sweep do the same arithmetic per group, so the
+def test_k5_tile_shapes_agree_bitwise(P, dt, targets):
+    # the narrow (256 threads) and wide (512 threads, 64 KiB) shapes of the
+    # k = 5 sweep do the same arithmetic per group, so the
     # states agree bit for bit, and both match the oracle; AUTO (which times
     # both on the first sweeps) gives the same bits too
     n = 17
@@ -453,14 +454,17 @@ def test_k5_tile_shapes_agree_bitwise(P, targets):
     for mode in (P.SV_TILE_NARROW, P.SV_TILE_WIDE, P.SV_TILE_AUTO):
         h = P.Handle()
         h.set_tile_mode(mode)
-        st = P.State(h, n, "c64")
+        st = P.State(h, n, dt)
         st.run(layer)
         for m in mats:
             st.apply_matrix(m, targets)
         outs[mode] = st.to_numpy()
         st.close()
         h.close()
-    assert oracle.fidelity(ref, outs[P.SV_TILE_NARROW].astype(np.complex128)) >= C64_FID
+    if dt == "c128":
+        assert np.max(np.abs(outs[P.SV_TILE_NARROW] - ref)) <= 1e-10
+    else:
+        assert oracle.fidelity(ref, outs[P.SV_TILE_NARROW].astype(np.complex128)) >= C64_FID
     np.testing.assert_array_equal(outs[P.SV_TILE_NARROW], outs[P.SV_TILE_WIDE])
     np.testing.assert_array_equal(outs[P.SV_TILE_NARROW], outs[P.SV_TILE_AUTO])
 
