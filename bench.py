@@ -14,8 +14,8 @@ fused-block sweeps (each block reads and writes the whole state once,
 measured with HIP events on the handle's stream around every block of every
 timed step.  ``ms_per_step`` is the wall time of a whole step.
 
-Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one
-GPU.
+Prints one JSON line.  ``--gpus`` above 1 is refused: the library keeps a
+whole state on one GPU and has no multi-GPU sharding.
 """
 from __future__ import annotations
 
@@ -38,16 +38,15 @@ HBM_PEAK_GBS = 8000.0
 # counters were taken on: its SHA-256 is recorded and checked at run time.
 PMC_TRAFFIC = {
     # 30-qubit brickwork sweep, dispatch-weighted over both tile shapes
-    # (c64: 112 narrow + 72 wide fetch, 127 + 57 write launches;
-    #  c128: 122 narrow + 62 wide fetch, 122 + 62 write launches)
-    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194405.1, "write_kib": 8390015.9,
+    # (c64: 518 narrow + 80 wide launches per pass; c128: 540 + 58)
+    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194404.1, "write_kib": 8389796.9,
                       "fetch_scale": 2.0, "write_scale": 1.0,
                       "source": "paper_2308_01999_amd/csrc/sv_apply.hip",
-                      "source_sha256": "dfbe3156601a4b472b81a6ffa5fb25bb724e49a7b4136bb122010dcbabef0ef8"},
-    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388722.6, "write_kib": 16781369.2,
+                      "source_sha256": "101ccacca555b7f4c72b33306d06e04d69cf4d50d0ed8126a1394f86263308b8"},
+    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388721.3, "write_kib": 16779646.7,
                        "fetch_scale": 2.0, "write_scale": 1.0,
                        "source": "paper_2308_01999_amd/csrc/sv_apply.hip",
-                       "source_sha256": "dfbe3156601a4b472b81a6ffa5fb25bb724e49a7b4136bb122010dcbabef0ef8"},
+                       "source_sha256": "101ccacca555b7f4c72b33306d06e04d69cf4d50d0ed8126a1394f86263308b8"},
 }
 
 
@@ -87,7 +86,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     # untimed steps; they also let the handle time its k = 5 tile variants
     # on every target set of the circuit and settle on the fastest
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=12)
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--depth", type=int, default=20)
     ap.add_argument("--kmax", type=int, default=5)
@@ -261,13 +260,13 @@ def graph_leg(P, W, torch, H, n=14, depth=20, reps=200):
     """A small fused program (the brickwork circuit at n qubits, complex64,
     k <= 5 blocks) run repeatedly: eager (one launch per block) against a
     recorded HIP graph replay.  Host wall time per run, averaged over reps,
-    after a few untimed runs (which also settle the k = 5 tile variants)."""
+    after 20 untimed runs (which also settle the k = 5 tile variants)."""
     gates = W.brickwork(n, depth, 0)
     st = P.State(H, n, "c64")
     f = P.fuse(gates, 5)
 
     def timed(run):
-        for _ in range(5):
+        for _ in range(20):
             run()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -316,8 +315,12 @@ def cpu_baseline(W, P, gates, n, kmax, seconds):
 
 def copy_ceiling(torch, n):
     """In-place read+write bandwidth of torch's elementwise kernel on a
-    2^n complex64-sized buffer: the achievable ceiling for in-place sweeps."""
-    a = torch.ones(1 << (n + 1), dtype=torch.float32, device="cuda")
+    2^n complex64-sized buffer of uniform random floats (HBM transfer time
+    depends on the data: a mostly-zero buffer streams faster than a dense
+    state does): the achievable ceiling for in-place sweeps."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    a = torch.rand(1 << (n + 1), dtype=torch.float32, device="cuda", generator=g)
     a.mul_(1.0)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -332,26 +335,35 @@ def copy_ceiling(torch, n):
     return 2 * (1 << n) * 8 / (ms * 1e-3) / 1e9
 
 
-def gate_sweep(P, W, torch, H, n, sets, reps=3, warm=3):
+def gate_sweep(P, W, torch, H, n, sets, reps=3, warm=3, warm_k5=10):
     """Single dense k-qubit gates (Haar random) on `sets` random target sets
     per k, after the paper's gate-application measurement (Sec. II-B, Fig. 2:
     bandwidth from many random target sets).  Each set is applied `warm`
     times untimed (the handle settles its k = 5 tile variant), then `reps`
     times timed with HIP events on the handle's stream.  Median, p10 and p90
     GB/s per k and dtype, and medians per target class: all targets below
-    n/2 ("low"), all at or above ("high"), or both ("mixed")."""
+    n/2 ("low"), all at or above ("high"), or both ("mixed").  The state is
+    dense (a brickwork layer first: every amplitude non-zero), since sweep
+    time depends on the data.  For k = 5 the handle first passes its
+    untimed warm-up sweeps, and each set gets warm_k5 untimed applications
+    (three timings of each of the three tile variants, then the choice)."""
     import numpy as np
     out = {}
     for dt, ab in (("c64", 8), ("c128", 16)):
         st = P.State(H, n, dt)
+        st.run(W.brickwork(n, 1, 11))
         rng = np.random.default_rng(1000)
         res = {}
         for k in range(1, 7):
             bws, cls = [], []
+            if k == 5:
+                m0 = W.haar_unitary(5, np.random.default_rng(1))
+                for _ in range(P.TILE_WARM_SWEEPS):
+                    st.apply_matrix(m0, (0, 1, 2, 3, 4))
             for j in range(sets):
                 ts = W.random_targets(n, k, np.random.default_rng(1000 * k + j))
                 m = W.haar_unitary(k, rng)
-                for _ in range(warm):
+                for _ in range(warm_k5 if k == 5 else warm):
                     st.apply_matrix(m, ts)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(H.stream)
@@ -501,8 +513,8 @@ def serving_leg(P, W, torch, n_requests, slots):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is "
-              f"described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library keeps a whole "
+              f"state on one device and has no multi-GPU sharding", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2308_01999_amd as P
@@ -540,7 +552,6 @@ def main():
         st128.close()
         extra["c128"] = r128
     st64.close()
-    H.close()
     torch.cuda.synchronize()
     dk = r64["dominant_kernel"]
     achieved = dk["GBps"]
@@ -580,9 +591,9 @@ def main():
                                  "bytes_per_launch": dk2["bytes_per_launch"], "avg_launch_ms": round(dk2["avg_ms"], 4)}
     if not args.no_kmax_sweep:
         print("[bench] unfused / kmax sweep", file=sys.stderr, flush=True)
-        H4 = P.Handle()
-        line["fusion_widths"] = kmax_leg(P, W, torch, H4, gates, n)
-        H4.close()
+        # on the main handle, whose k = 5 tile choices for this circuit are settled
+        line["fusion_widths"] = kmax_leg(P, W, torch, H, gates, n)
+    H.close()
     print("[bench] graph leg", file=sys.stderr, flush=True)
     H5 = P.Handle()
     line["graph_replay"] = graph_leg(P, W, torch, H5)

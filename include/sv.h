@@ -99,18 +99,29 @@ sv_status_t sv_handle_set_stream(sv_handle_t h, void* hip_stream);
  * II-B: gate fusion makes k = 5 the common case), complex64 and complex128.
  * All variants do the same arithmetic on every amplitude group, so results
  * are bitwise the same whichever runs; they differ in tile shape (256-thread
- * workgroups on 32 KiB tiles, or 512-thread workgroups on 64 KiB tiles with
- * twice as long contiguous runs) and in the order workgroups take tiles.
- * Which one moves HBM fastest depends on the target bits.
- *   SV_TILE_AUTO (default): the handle times each variant once on the first
- *     sweeps of every (state size, target set) it sees, with HIP events on
- *     its stream, then keeps the fastest (no timing while the stream is
- *     being captured);
- *   SV_TILE_NARROW / SV_TILE_WIDE: always that shape in tile order (wide
- *     needs n >= 13 for complex64 and n >= 12 for complex128; smaller states
- *     use the narrow one).
+ * workgroups on 32 KiB tiles of 1 KiB runs, or 512-thread workgroups on
+ * 64 KiB tiles with twice as long runs), in which index bits besides the
+ * targets a tile spans, and in the order workgroups take tiles.  Which one
+ * moves HBM fastest depends on the target bits.
+ *   SV_TILE_AUTO (default): after the handle's first SV_TILE_WARM_SWEEPS
+ *     five-qubit sweeps (untimed, narrow), it times each variant three
+ *     times, in rotating order, on the sweeps of every (dtype, state size,
+ *     target set) it sees, with HIP events on its stream, then keeps the
+ *     variant with the lowest mean (no timing while the stream is being
+ *     captured);
+ *   SV_TILE_NARROW / SV_TILE_WIDE: always that shape, each workgroup on
+ *     consecutive tiles (wide needs n >= 13 for complex64 and n >= 12 for
+ *     complex128; smaller states use the narrow one);
+ *   SV_TILE_SPREAD: narrow tiles whose runs are always 1 KiB, with each
+ *     target below the run boundary swapped for a free index bit from 12
+ *     up, and workgroups taking tiles far apart (needs n >= 13 for
+ *     complex64 and n >= 12 for complex128, and enough free bits; otherwise
+ *     the narrow shape).
  * Returns SV_ERR_INVALID_VALUE for any other mode. */
-typedef enum { SV_TILE_AUTO = 0, SV_TILE_NARROW = 1, SV_TILE_WIDE = 2 } sv_tile_mode_t;
+typedef enum { SV_TILE_AUTO = 0, SV_TILE_NARROW = 1, SV_TILE_WIDE = 2, SV_TILE_SPREAD = 3 } sv_tile_mode_t;
+/* Untimed five-qubit sweeps an SV_TILE_AUTO handle runs before its first
+ * timed trial. */
+#define SV_TILE_WARM_SWEEPS 64
 sv_status_t sv_handle_set_tile_mode(sv_handle_t h, int32_t mode);
 
 /* Blocks until all work issued on the handle's stream has finished. */

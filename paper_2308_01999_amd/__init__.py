@@ -153,7 +153,8 @@ def sv_handle_set_stream(h: int, stream_ptr: int) -> None:
     _check(_L.sv_handle_set_stream(_vp(h), _vp(stream_ptr or None)))
 
 
-SV_TILE_AUTO, SV_TILE_NARROW, SV_TILE_WIDE = 0, 1, 2
+SV_TILE_AUTO, SV_TILE_NARROW, SV_TILE_WIDE, SV_TILE_SPREAD = 0, 1, 2, 3
+TILE_WARM_SWEEPS = 64  # SV_TILE_WARM_SWEEPS
 
 
 def sv_handle_set_tile_mode(h: int, mode: int) -> None:

@@ -248,8 +248,8 @@ sv_status_t sv_handle_set_tile_mode(sv_handle_t h, int32_t mode)
 {
     return guarded([&] {
         SV_CHECK(h != nullptr, "handle is NULL");
-        SV_CHECK(mode == SV_TILE_AUTO || mode == SV_TILE_NARROW || mode == SV_TILE_WIDE,
-                 "tile mode must be SV_TILE_AUTO, SV_TILE_NARROW or SV_TILE_WIDE");
+        SV_CHECK(mode == SV_TILE_AUTO || mode == SV_TILE_NARROW || mode == SV_TILE_WIDE || mode == SV_TILE_SPREAD,
+                 "tile mode must be SV_TILE_AUTO, SV_TILE_NARROW, SV_TILE_WIDE or SV_TILE_SPREAD");
         h->tile_mode = mode;
     });
 }

@@ -250,7 +250,8 @@ struct TileArgs {
     int32_t n_lo;
     int32_t lo_pos[SV_MAX_TARGETS];
     int32_t lds_off[64];  // matrix index -> LDS offset from the group's base
-    int32_t rot;          // tile-group order: group index rotated left by rot bits (0: in order)
+    int32_t trot;         // tile order: tile index rotated right by trot bits over lg_tiles bits
+    int32_t lg_tiles;     // log2 n_tiles
 };
 
 __device__ __forceinline__ uint64_t insert_zero_bits(uint64_t v, const int32_t* pos, int n)
@@ -285,6 +286,7 @@ constexpr int kTileVecs = 8;  // 16-byte vectors per thread per tile (32 KiB / 2
 #ifndef SV_TILES_PER_WG_MAX_K5
 #define SV_TILES_PER_WG_MAX_K5 4
 #endif
+
 
 typedef float nf4 __attribute__((ext_vector_type(4)));
 typedef double nd2 __attribute__((ext_vector_type(2)));
@@ -342,33 +344,15 @@ __device__ __forceinline__ void tile_offsets(const TileArgs& a, uint64_t* roff, 
     }
 }
 
+// Global index of tile t's first amplitude.  With a.trot > 0 the tile index
+// is first rotated right by trot bits: workgroup w, which sweeps its
+// tiles_per_wg = 2^trot tiles t = w * 2^trot + j, then touches tiles
+// w + j * (n_tiles / 2^trot), so at any moment the workgroups in flight work
+// on neighbouring tiles instead of tiles 2^trot apart.
 __device__ __forceinline__ uint64_t tile_base(uint64_t t, const TileArgs& a)
 {
+    if (a.trot > 0) t = ((t & ((uint64_t(1) << a.trot) - 1)) << (a.lg_tiles - a.trot)) | (t >> a.trot);
     return insert_zero_bits(t << a.L, a.hi_pos, a.n_hi);
-}
-
-// Workgroup ids are handed round-robin to the chip's 8 XCDs (each with its
-// own L2 and address-translation cache).  With SV_TILE_XCD, workgroup b takes
-// tile group (b % 8) * (G / 8) + b / 8, so each XCD sweeps one contiguous
-// eighth of the state instead of every eighth tile group.
-#ifndef SV_TILE_XCD
-#define SV_TILE_XCD 0
-#endif
-constexpr uint32_t kXcds = 8;
-
-// The order in which workgroups take tile groups changes which DRAM pages
-// are open together, and for some target sets the sweep is much faster with
-// consecutive workgroups far apart: a.rot rotates the group index left by
-// that many bits (the grid is a power of two then; 0 keeps the order).
-__device__ __forceinline__ uint64_t tile_group(const TileArgs& a)
-{
-    const uint32_t b = blockIdx.x, g = gridDim.x;
-    if (SV_TILE_XCD && g % kXcds == 0) return uint64_t(b % kXcds) * (g / kXcds) + b / kXcds;
-    if (a.rot > 0 && (g & (g - 1)) == 0 && g > (1u << a.rot)) {
-        const int lg = 31 - __clz(g);
-        return ((b << a.rot) | (b >> (lg - a.rot))) & (g - 1);
-    }
-    return b;
 }
 
 // LDS slot of tile-local amplitude a: its low five bits are XORed with bits
@@ -414,7 +398,7 @@ __global__ __launch_bounds__(NT, NT == 512 ? SV_K5_WIDE_WAVES : 1) void k_tile_c
     // the packed A operands (same for every wave): 3 x 64 lanes x 4 float4,
     // read back four k-steps at a time so only 12 of them are live at once
     __shared__ float4 amat[kK5AParts * 64 * 4];
-    const uint64_t t0 = tile_group(a) * a.tiles_per_wg;
+    const uint64_t t0 = uint64_t(blockIdx.x) * a.tiles_per_wg;
     if (t0 >= a.n_tiles) return;
     const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 31, half = lane >> 5;
@@ -489,7 +473,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict
                                                              const float4* __restrict__ mats, TileArgs a)
 {
     __shared__ float4 lds[kTileThreads * kTileVecs];
-    const uint64_t t0 = tile_group(a) * a.tiles_per_wg;
+    const uint64_t t0 = uint64_t(blockIdx.x) * a.tiles_per_wg;
     if (t0 >= a.n_tiles) return;
     const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, q = lane >> 4;
@@ -567,7 +551,7 @@ __global__ __launch_bounds__(NT) void k_tile_c128_k5(double2* __restrict__ psi,
     // SV_C128_A_LDS: Re M and Im M staged in LDS lane-contiguous (16 KiB;
     // Re M + Im M summed at use) instead of 48 doubles per lane in registers
     __shared__ double amat[SV_C128_A_LDS ? 2 * 16 * 64 : 1];
-    const uint64_t t0 = tile_group(a) * a.tiles_per_wg;
+    const uint64_t t0 = uint64_t(blockIdx.x) * a.tiles_per_wg;
     if (t0 >= a.n_tiles) return;
     const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, q = lane >> 4;
@@ -668,7 +652,7 @@ __global__ __launch_bounds__(kK6Threads, 2) void k_tile_c64_k6(float2* __restric
     constexpr int NT = kK6Threads;
     __shared__ float4 lds[NT * kTileVecs];
     __shared__ float4 amat[3 * 2 * 64 * 8];
-    const uint64_t t0 = tile_group(a) * a.tiles_per_wg;
+    const uint64_t t0 = uint64_t(blockIdx.x) * a.tiles_per_wg;
     if (t0 >= a.n_tiles) return;
     const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 31, half = lane >> 5;
@@ -750,7 +734,7 @@ __global__ __launch_bounds__(kK6Threads, 2) void k_tile_c128_k6(double2* __restr
     constexpr int NT = kK6Threads;
     __shared__ double2 lds[NT * kTileVecs];
     __shared__ double amat[2 * 4 * 16 * 64];
-    const uint64_t t0 = tile_group(a) * a.tiles_per_wg;
+    const uint64_t t0 = uint64_t(blockIdx.x) * a.tiles_per_wg;
     if (t0 >= a.n_tiles) return;
     const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, q = lane >> 4;
@@ -919,14 +903,24 @@ void launch_mfma_c64(sv_handle_s* h, float2* psi, const float4* mats, const Gate
 }
 
 // Tile geometry for a gate with targets d.tbit (matrix order) on n qubits;
-// tb = log2 of the tile's amplitude count.
-TileArgs make_tile_args(const GateDesc& d, int n, int tb, int cu_count)
+// tb = log2 of the tile's amplitude count.  The tile is the low L index
+// bits plus the bit set H (hi_pos): by default L is the smallest width that
+// leaves 2^(tb-k) groups in the tile and H the targets >= L.  With
+// spread_lo > 0 (and a target below tb - k) the runs are 2^(tb-k)
+// amplitudes and each target below them is matched by a free bit at or
+// above spread_lo in H, so the tile's runs are spread out in memory.
+// lo_pos lists the targets' positions inside the tile (bits < L as is, H's
+// bits at L + their rank in H).  strided: workgroups take their tiles
+// n_tiles / tiles_per_wg apart (tile_base) instead of consecutively.
+TileArgs make_tile_args(const GateDesc& d, int n, int tb, int cu_count, int spread_lo, bool strided)
 {
     int tq[SV_MAX_TARGETS];
+    bool is_target[64] = {};
     for (int a = 0; a < d.k; ++a) {
         int q = 0;
         while ((uint64_t(1) << q) != d.tbit[a]) ++q;
         tq[a] = q;
+        is_target[q] = true;
     }
     const int gbits = tb - d.k;  // log2 groups per tile
     int L = gbits;
@@ -936,34 +930,48 @@ TileArgs make_tile_args(const GateDesc& d, int n, int tb, int cu_count)
         if (L - klo >= gbits) break;
         ++L;
     }
+    bool extra[64] = {};
+    if (spread_lo > 0) {
+        int klo = 0;
+        for (int a = 0; a < d.k; ++a) klo += tq[a] < gbits;
+        int found = 0;
+        bool pick[64] = {};
+        for (int q = std::max(gbits, spread_lo); q < n && found < klo; ++q)
+            if (!is_target[q]) {
+                pick[q] = true;
+                ++found;
+            }
+        if (klo > 0 && found == klo) {
+            L = gbits;
+            for (int q = 0; q < 64; ++q) extra[q] = pick[q];
+        }
+    }
     TileArgs t{};
     t.L = L;
-    int hi[SV_MAX_TARGETS], lo[SV_MAX_TARGETS], nh = 0, nl = 0;
-    for (int q = 0; q < n; ++q)
-        for (int a = 0; a < d.k; ++a)
-            if (tq[a] == q) {
-                if (q < L)
-                    lo[nl++] = q;
-                else
-                    hi[nh++] = q;
-            }
+    int nh = 0;
+    for (int q = L; q < n; ++q)
+        if (is_target[q] || extra[q]) t.hi_pos[nh++] = q;
     t.n_hi = nh;
-    t.n_lo = nl;
-    for (int j = 0; j < nh; ++j) t.hi_pos[j] = hi[j];
-    for (int j = 0; j < nl; ++j) t.lo_pos[j] = lo[j];
-    for (int c = 0; c < (1 << d.k); ++c) {
-        int run = 0, low = 0;
-        for (int a = 0; a < d.k; ++a) {
-            if (!((c >> a) & 1)) continue;
-            if (tq[a] < L) {
-                low |= 1 << tq[a];
-            } else {
-                int rank = 0;
-                while (hi[rank] != tq[a]) ++rank;
-                run |= 1 << rank;
-            }
+    int local[SV_MAX_TARGETS];
+    for (int a = 0; a < d.k; ++a) {
+        if (tq[a] < L) {
+            local[a] = tq[a];
+        } else {
+            int rank = 0;
+            while (t.hi_pos[rank] != tq[a]) ++rank;
+            local[a] = L + rank;
         }
-        t.lds_off[c] = (run << L) + low;
+    }
+    int nl = 0;
+    for (int p = 0; p < tb; ++p)
+        for (int a = 0; a < d.k; ++a)
+            if (local[a] == p) t.lo_pos[nl++] = p;
+    t.n_lo = nl;
+    for (int c = 0; c < (1 << d.k); ++c) {
+        int off = 0;
+        for (int a = 0; a < d.k; ++a)
+            if ((c >> a) & 1) off |= 1 << local[a];
+        t.lds_off[c] = off;
     }
     t.n_tiles = uint64_t(1) << (n - tb);
     // about 32 workgroups per CU over the sweep, each on consecutive tiles
@@ -973,6 +981,9 @@ TileArgs make_tile_args(const GateDesc& d, int n, int tb, int cu_count)
     const uint64_t cap = d.k >= 5 ? SV_TILES_PER_WG_MAX_K5 : SV_TILES_PER_WG_MAX;
     if (per > cap) per = cap;
     t.tiles_per_wg = per;
+    t.lg_tiles = n - tb;
+    if (strided && (per & (per - 1)) == 0)
+        while ((uint64_t(1) << t.trot) < per) ++t.trot;
     return t;
 }
 
@@ -1003,12 +1014,11 @@ void tuner_poll(TileTuner& T)
         TileTuneEntry& e = T.entries[tr.key];
         float ms = 0.f;
         if (q == hipSuccess && hipEventElapsedTime(&ms, tr.e0, tr.e1) == hipSuccess) {
-            e.best_ms[tr.shape] = e.measured[tr.shape] ? std::min(e.best_ms[tr.shape], ms) : ms;
+            e.sum_ms[tr.shape] += ms;
             ++e.measured[tr.shape];
         } else {
             (void)hipGetLastError();
-            e.measured[tr.shape] = kTileTrials;  // unusable: stop trying it
-            e.best_ms[tr.shape] = 1e30f;
+            e.unusable[tr.shape] = true;  // no timing: never chosen, not tried again
         }
         --e.in_flight[tr.shape];
         T.pool.push_back(tr.e0);
@@ -1018,16 +1028,20 @@ void tuner_poll(TileTuner& T)
     }
 }
 
-// Variants of the k = 5 sweeps (complex64 and complex128) the handle chooses among:
-// shape (narrow 32 KiB / wide 64 KiB tiles) and tile-group order.
+// Variants of the k = 5 sweeps (complex64 and complex128) the handle chooses
+// among: narrow 32 KiB tiles, wide 64 KiB tiles, and narrow tiles with the
+// spread layout (free bits from 12 up in place of the low targets) taken in
+// strided order.  Which is fastest depends on the target set: in-circuit on
+// 30 qubits, the spread variant wins for windows of low or high targets, the
+// plain narrow one for targets around bits 10-13, the wide one where the
+// targets sit right above the 1 KiB runs.
 struct TileVariant {
     bool wide;
-    int rot;
+    int spread_lo;
+    bool strided;
 };
-constexpr TileVariant kTileVariants[kTileShapes] = {{false, 0}, {true, 0}, {false, 9}};
+constexpr TileVariant kTileVariants[kTileShapes] = {{false, 0, false}, {true, 0, false}, {false, 12, true}};
 
-// Variant for a complex64 k = 5 sweep (index into kTileVariants).  *trial is
-// set when this launch is to be timed.
 uint64_t tune_key(Path p, const GateDesc& d)
 {
     uint64_t key = (uint64_t(d.n) << 40) | (uint64_t(p == Path::kTileC128K5) << 48);
@@ -1039,12 +1053,15 @@ uint64_t tune_key(Path p, const GateDesc& d)
 // complex128 64 KiB = 2^12.
 int wide_tile_bits(Path p) { return p == Path::kTileC128K5 ? 12 : kK5TileBits; }
 
+// Variant for a k = 5 tile sweep (index into kTileVariants).  *trial is set
+// when this launch is to be timed.
 int tile_shape(sv_handle_s* h, Path p, const GateDesc& d, bool* trial)
 {
     *trial = false;
     if (d.n < wide_tile_bits(p)) return 0;
     if (h->tile_mode == SV_TILE_NARROW) return 0;
     if (h->tile_mode == SV_TILE_WIDE) return 1;
+    if (h->tile_mode == SV_TILE_SPREAD) return 2;
     TileTuner& T = *h->tuner;
     const uint64_t key = tune_key(p, d);
     // while the stream is being recorded into a graph: no event queries and
@@ -1054,22 +1071,29 @@ int tile_shape(sv_handle_s* h, Path p, const GateDesc& d, bool* trial)
     if (capturing) (void)hipGetLastError();
     if (!capturing) tuner_poll(T);
     TileTuneEntry& e = T.entries[key];
-    if (!capturing) {
-        // the shape with fewer timings started, narrow first
+    auto done = [&](int c) { return e.unusable[c] || e.measured[c] + e.in_flight[c] >= kTileTrials; };
+    if (!capturing && T.sweeps++ >= uint64_t(kTileWarmSweeps)) {
+        // trial j (counted over all variants) of this key belongs to round
+        // j / kTileShapes, which visits the variants starting from the
+        // round's number, so each variant takes every place in the order
+        int j = 0;
+        for (int c = 0; c < kTileShapes; ++c) j += e.measured[c] + e.in_flight[c];
         int s = -1;
-        for (int c = 0; c < kTileShapes; ++c)
-            if (e.measured[c] + e.in_flight[c] < kTileTrials &&
-                (s < 0 || e.measured[c] + e.in_flight[c] < e.measured[s] + e.in_flight[s]))
-                s = c;
+        for (int i = 0; i < kTileShapes && s < 0; ++i) {
+            const int c = (j / kTileShapes + j % kTileShapes + i) % kTileShapes;
+            if (!done(c)) s = c;
+        }
         if (s >= 0) {
             *trial = true;
             return s;
         }
     }
-    int best = 0;
-    for (int c = 1; c < kTileShapes; ++c)
-        if (e.measured[c] && (!e.measured[best] || e.best_ms[c] < e.best_ms[best])) best = c;
-    return e.measured[best] ? best : 0;
+    int best = -1;
+    for (int c = 0; c < kTileShapes; ++c) {
+        if (e.unusable[c] || e.measured[c] == 0) continue;
+        if (best < 0 || e.sum_ms[c] * e.measured[best] < e.sum_ms[best] * e.measured[c]) best = c;
+    }
+    return best < 0 ? 0 : best;
 }
 
 void launch_tile(sv_handle_s* h, Path p, void* psi, const void* mats, const GateDesc& d)
@@ -1091,8 +1115,8 @@ void launch_tile(sv_handle_s* h, Path p, void* psi, const void* mats, const Gate
                    : (p == Path::kTileC128K6) ? 12
                    : wide                     ? kK5TileBits
                                               : 12;
-    TileArgs t = make_tile_args(d, d.n, tb, h->cu_count);
-    t.rot = tuned ? kTileVariants[variant].rot : 0;
+    const TileVariant& v = kTileVariants[tuned ? variant : 0];
+    const TileArgs t = make_tile_args(d, d.n, tb, h->cu_count, v.spread_lo, v.strided);
     const uint64_t blocks = (t.n_tiles + t.tiles_per_wg - 1) / t.tiles_per_wg;
     switch (p) {
         case Path::kTileC64K5:

@@ -48,16 +48,21 @@ constexpr size_t kMinWorkspace = 12u << 20;
 
 }  // namespace sv
 
-// Online choice among the complex64 k = 5 tile variants (shape and tile
-// order): per key (n, target mask), kTileTrials timings of each variant,
-// then the fastest.
+// Online choice among the k = 5 tile variants (complex64 and complex128):
+// after the handle's first kTileWarmSweeps tuned sweeps (untimed, while
+// clocks and caches settle), per key (dtype, n, target mask) kTileTrials
+// timings of each variant, taken in rotating round-robin order so that every
+// variant meets the same mix of neighbouring work, then the variant with
+// the lowest mean.
 namespace sv {
 constexpr int kTileShapes = 3;
-constexpr int kTileTrials = 1;
+constexpr int kTileTrials = 3;
+constexpr int kTileWarmSweeps = SV_TILE_WARM_SWEEPS;
 struct TileTuneEntry {
-    float best_ms[kTileShapes] = {};
+    float sum_ms[kTileShapes] = {};
     int measured[kTileShapes] = {};
     int in_flight[kTileShapes] = {};
+    bool unusable[kTileShapes] = {};
 };
 struct TileTrial {
     uint64_t key;
@@ -68,6 +73,7 @@ struct TileTuner {
     std::unordered_map<uint64_t, TileTuneEntry> entries;
     std::vector<TileTrial> pending;
     std::vector<hipEvent_t> pool;
+    uint64_t sweeps = 0;  // tuned sweeps launched (warm-up count)
 };
 }  // namespace sv
 

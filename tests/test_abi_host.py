@@ -39,6 +39,18 @@ def test_library_exports_every_declared_symbol(P):
     assert sorted(P.EXPORTED) == names
 
 
+def test_binding_constants_match_the_header(P):
+    # the Python names of the header's enum values and defines carry the
+    # header's numbers
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "sv.h")).read(), flags=re.S)
+    enums = dict((k, int(v)) for k, v in re.findall(r"\b(SV_TILE_[A-Z]+)\s*=\s*(\d+)", src))
+    assert set(enums) == {"SV_TILE_AUTO", "SV_TILE_NARROW", "SV_TILE_WIDE", "SV_TILE_SPREAD"}
+    for name, v in enums.items():
+        assert getattr(P, name) == v, name
+    warm = re.search(r"#define\s+SV_TILE_WARM_SWEEPS\s+(\d+)", src)
+    assert warm and P.TILE_WARM_SWEEPS == int(warm.group(1))
+
+
 def test_version_string(P):
     assert "gfx950" in P.sv_version()
 

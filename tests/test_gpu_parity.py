@@ -436,13 +436,33 @@ def test_copy_ranges(P, H):
 
 # ----------------------------------------------------- k = 5 tile shapes
 
+TILE_MODES = ("SV_TILE_NARROW", "SV_TILE_WIDE", "SV_TILE_SPREAD", "SV_TILE_AUTO")
+
+
+def _tile_mode_states(P, dt, n, layer, mats, targets):
+    outs = {}
+    for name in TILE_MODES:
+        h = P.Handle()
+        h.set_tile_mode(getattr(P, name))
+        st = P.State(h, n, dt)
+        st.run(layer)
+        for m in mats:
+            st.apply_matrix(m, targets)
+        outs[name] = st.to_numpy()
+        st.close()
+        h.close()
+    return outs
+
+
 @pytest.mark.parametrize("dt", ["c64", "c128"])
-@pytest.mark.parametrize("targets", [(0, 1, 2, 3, 4), (3, 7, 9, 12, 15), (11, 12, 13, 14, 15), (2, 6, 10, 13, 16)])
+@pytest.mark.parametrize("targets", [(0, 1, 2, 3, 4), (3, 7, 9, 12, 15), (11, 12, 13, 14, 15), (2, 6, 10, 13, 16),
+                                     (14, 1, 8, 5, 12)])
 def test_k5_tile_shapes_agree_bitwise(P, dt, targets):
-    # the narrow (256 threads) and wide (512 threads, 64 KiB) shapes of the
-    # k = 5 sweep do the same arithmetic per group, so the
-    # states agree bit for bit, and both match the oracle; AUTO (which times
-    # both on the first sweeps) gives the same bits too
+    # the narrow (256 threads), wide (512 threads, 64 KiB) and spread (1 KiB
+    # runs, low targets swapped for free bits from 12 up, strided tile
+    # order) variants of the k = 5 sweep do the same arithmetic per group,
+    # so the states agree bit for bit, and match the oracle; AUTO (which
+    # times every variant on the first sweeps) gives the same bits too
     n = 17
     rng = np.random.default_rng(sum(targets))
     mats = [W.haar_unitary(5, rng) for _ in range(6)]
@@ -450,28 +470,67 @@ def test_k5_tile_shapes_agree_bitwise(P, dt, targets):
     ref = oracle.run(n, layer)
     for m in mats:
         oracle.apply(ref, m, targets)
+    outs = _tile_mode_states(P, dt, n, layer, mats, targets)
+    if dt == "c128":
+        assert np.max(np.abs(outs["SV_TILE_NARROW"] - ref)) <= 1e-10
+    else:
+        assert oracle.fidelity(ref, outs["SV_TILE_NARROW"].astype(np.complex128)) >= C64_FID
+    for name in TILE_MODES[1:]:
+        np.testing.assert_array_equal(outs["SV_TILE_NARROW"], outs[name], err_msg=name)
+
+
+@pytest.mark.parametrize("dt,n", [("c64", 13), ("c128", 12), ("c64", 16)])
+def test_k5_spread_on_small_states(P, dt, n):
+    # at 13 (complex64) and 12 (complex128) qubits there are too few free
+    # index bits from 12 up to stand in for the low targets, and the spread
+    # mode runs the narrow layout; at 16 it swaps four of them for bits
+    # 12-15; the bits agree with the other modes either way
+    targets = (0, 2, 4, 6, 8)
+    rng = np.random.default_rng(n)
+    mats = [W.haar_unitary(5, rng) for _ in range(3)]
+    layer = W.brickwork(n, 1, 4)
+    ref = oracle.run(n, layer)
+    for m in mats:
+        oracle.apply(ref, m, targets)
+    outs = _tile_mode_states(P, dt, n, layer, mats, targets)
+    if dt == "c128":
+        assert np.max(np.abs(outs["SV_TILE_SPREAD"] - ref)) <= 1e-10
+    else:
+        assert oracle.fidelity(ref, outs["SV_TILE_SPREAD"].astype(np.complex128)) >= C64_FID
+    for name in TILE_MODES[1:]:
+        np.testing.assert_array_equal(outs["SV_TILE_NARROW"], outs[name], err_msg=name)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_k5_autotuner_trials_give_the_same_bits(P, dt):
+    # enough sweeps on two target sets for the AUTO handle to pass its 64
+    # untimed sweeps, time every variant three times per set and settle:
+    # whichever variants ran, the state is bit for bit the NARROW one
+    n = 17
+    sets = [(0, 1, 2, 3, 4), (13, 2, 9, 15, 6)]
+    rng = np.random.default_rng(5)
+    mats = [W.haar_unitary(5, rng) for _ in range(4)]
+    layer = W.brickwork(n, 1, 3)
     outs = {}
-    for mode in (P.SV_TILE_NARROW, P.SV_TILE_WIDE, P.SV_TILE_AUTO):
+    for mode in (P.SV_TILE_NARROW, P.SV_TILE_AUTO):
         h = P.Handle()
         h.set_tile_mode(mode)
         st = P.State(h, n, dt)
         st.run(layer)
-        for m in mats:
-            st.apply_matrix(m, targets)
+        for i in range(64 + 2 * 9 + 8):
+            st.apply_matrix(mats[i % 4], sets[(i // 4) % 2])
         outs[mode] = st.to_numpy()
         st.close()
         h.close()
-    if dt == "c128":
-        assert np.max(np.abs(outs[P.SV_TILE_NARROW] - ref)) <= 1e-10
-    else:
-        assert oracle.fidelity(ref, outs[P.SV_TILE_NARROW].astype(np.complex128)) >= C64_FID
-    np.testing.assert_array_equal(outs[P.SV_TILE_NARROW], outs[P.SV_TILE_WIDE])
     np.testing.assert_array_equal(outs[P.SV_TILE_NARROW], outs[P.SV_TILE_AUTO])
+    assert abs(np.linalg.norm(outs[P.SV_TILE_AUTO].astype(np.complex128)) - 1.0) < 1e-4
 
 
 def test_tile_mode_rejects_unknown(P, H):
     with pytest.raises(P.SVError):
-        H.set_tile_mode(3)
+        H.set_tile_mode(4)
+    with pytest.raises(P.SVError):
+        H.set_tile_mode(-1)
     H.set_tile_mode(P.SV_TILE_AUTO)
 
 
