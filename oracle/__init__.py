@@ -47,6 +47,8 @@ def lib():
         L.orc_gate_matrix.restype = ctypes.c_int
         L.orc_apply.argtypes = [vp, ctypes.c_int, vp, ip, ctypes.c_int, ip, ip, ctypes.c_int]
         L.orc_apply.restype = ctypes.c_int
+        L.orc_apply_gperm.argtypes = [vp, ctypes.c_int, vp, vp, ip, ctypes.c_int, ip, ip, ctypes.c_int]
+        L.orc_apply_gperm.restype = ctypes.c_int
         L.orc_norm.argtypes = [vp, ctypes.c_int]
         L.orc_norm.restype = ctypes.c_double
         L.orc_expect_pauli.argtypes = [vp, ctypes.c_int, ip, ctypes.c_char_p, ctypes.c_int, dp]
@@ -100,6 +102,52 @@ def apply(psi: np.ndarray, matrix, targets, controls=(), cvals=None) -> None:
                          len(controls))
     if rc != 0:
         raise ValueError("invalid gate arguments")
+
+
+def gperm_matrix(perm, diag) -> np.ndarray:
+    """The dense 2^k x 2^k form of the generalized permutation matrix G = D P:
+    row r has diag[r] in column perm[r] (perm None: the diagonal matrix)."""
+    dg = np.asarray(diag, dtype=np.complex128)
+    d = dg.shape[0]
+    g = np.zeros((d, d), dtype=np.complex128)
+    for r in range(d):
+        g[r, r if perm is None else int(perm[r])] = dg[r]
+    return g
+
+
+def gperm_adjoint(perm, diag) -> tuple:
+    """(perm', diag') with G' = D' P' equal to G^dagger: G^dagger maps the
+    amplitude at row r of G's input column perm[r] back, so output q reads
+    input r = perm^-1[q] with factor conj(diag[r])."""
+    dg = np.asarray(diag, dtype=np.complex128)
+    d = dg.shape[0]
+    if perm is None:
+        return None, np.conj(dg)
+    inv = np.empty(d, dtype=np.int64)
+    for r in range(d):
+        inv[int(perm[r])] = r
+    return inv, np.conj(dg[inv])
+
+
+def apply_gperm(psi: np.ndarray, perm, diag, targets, controls=(), cvals=None, adjoint: bool = False) -> None:
+    """In-place generalized permutation gate G = D P on `targets` (perm None:
+    the diagonal gate diag): the amplitude at group offset r becomes
+    diag[r] times the one at offset perm[r]."""
+    n = _nqubits(psi)
+    if adjoint:
+        perm, diag = gperm_adjoint(perm, diag)
+    dg = np.ascontiguousarray(diag, dtype=np.complex128)
+    k = len(targets)
+    if dg.shape != (1 << k,):
+        raise ValueError("diagonal length does not match the number of targets")
+    pm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
+    if pm is not None and pm.shape != (1 << k,):
+        raise ValueError("permutation length does not match the number of targets")
+    cv = None if cvals is None else _ints(cvals)
+    rc = lib().orc_apply_gperm(psi.ctypes.data, n, None if pm is None else pm.ctypes.data, dg.ctypes.data,
+                               _ints(targets), k, _ints(controls), cv, len(controls))
+    if rc != 0:
+        raise ValueError("invalid generalized permutation gate arguments")
 
 
 def apply_gate(psi: np.ndarray, gate) -> None:

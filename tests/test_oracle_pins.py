@@ -352,3 +352,84 @@ def test_fidelity_helper():
     a = np.array([1, 1j]) / math.sqrt(2)
     assert oracle.fidelity(a, a * np.exp(0.3j)) == pytest.approx(1.0, abs=1e-15)
     assert oracle.fidelity(a, np.array([1, -1j])) == pytest.approx(0.0, abs=1e-15)
+
+
+# ------------------------------------------- generalized permutation gates
+
+def _rand_state(n, rng):
+    v = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    return v / np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("case", ["x", "y", "z", "cz", "cx", "swap", "cp"])
+def test_gperm_named_gates_match_pauli_operators(case):
+    # each gate written by hand as (perm, diag) in the matrix-index
+    # convention (bit a of the row index = state of targets[a]), against
+    # its full operator built from Pauli matrices by Kronecker products
+    n, rng = 4, np.random.default_rng(3)
+    cp = 0.7
+    table = {
+        "x": ([1, 0], [1, 1], (2,), embed(PAULI["X"], (2,), n)),
+        "y": ([1, 0], [-1j, 1j], (1,), embed(PAULI["Y"], (1,), n)),
+        "z": (None, [1, -1], (3,), embed(PAULI["Z"], (3,), n)),
+        # targets (a, b) = (0, 3): row r = a + 2 b
+        "cz": (None, [1, 1, 1, -1], (0, 3), embed(PAULI["Z"], (3,), n, (0,))),
+        # control a = qubit 1 (matrix bit 0) flips b = qubit 2 (bit 1): rows 1 and 3 trade
+        "cx": ([0, 3, 2, 1], [1, 1, 1, 1], (1, 2), embed(PAULI["X"], (2,), n, (1,))),
+        "swap": ([0, 2, 1, 3], [1, 1, 1, 1], (0, 2),
+                 embed(PAULI["X"], (0,), n, (2,)) @ embed(PAULI["X"], (2,), n, (0,)) @ embed(PAULI["X"], (0,), n, (2,))),
+        "cp": (None, [1, 1, 1, np.exp(1j * cp)], (3, 1), embed(np.diag([1, np.exp(1j * cp)]), (1,), n, (3,))),
+    }
+    perm, diag, targets, full = table[case]
+    psi = _rand_state(n, rng)
+    ref = full @ psi
+    oracle.apply_gperm(psi, perm, diag, targets)
+    np.testing.assert_allclose(psi, ref, atol=1e-13)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_gperm_matches_kronecker_operator(seed):
+    # random permutation, arbitrary (non-unitary) complex diagonal, random
+    # targets and controls with values, against the full operator of the
+    # dense G = D P (row r: diag[r] in column perm[r]) embedded by Kronecker
+    # products; the adjoint against the conjugate transpose
+    rng = np.random.default_rng(seed)
+    n = 6
+    k = int(rng.integers(1, 5))
+    nc = int(rng.integers(0, 3))
+    qs = [int(q) for q in rng.permutation(n)]
+    targets, controls = tuple(qs[:k]), tuple(qs[k:k + nc])
+    cvals = [int(v) for v in rng.integers(0, 2, nc)]
+    perm = None if seed % 3 == 0 else [int(p) for p in rng.permutation(1 << k)]
+    diag = rng.normal(size=1 << k) + 1j * rng.normal(size=1 << k)
+    g = np.zeros((1 << k, 1 << k), dtype=np.complex128)
+    for r in range(1 << k):
+        g[r, r if perm is None else perm[r]] = diag[r]
+    full = embed(g, targets, n, controls, cvals)
+    psi = _rand_state(n, rng)
+    a = psi.copy()
+    oracle.apply_gperm(a, perm, diag, targets, controls, cvals)
+    np.testing.assert_allclose(a, full @ psi, atol=1e-12)
+    b = psi.copy()
+    oracle.apply_gperm(b, perm, diag, targets, controls, cvals, adjoint=True)
+    np.testing.assert_allclose(b, full.conj().T @ psi, atol=1e-12)
+    # and the dense form of the oracle agrees with the dense apply
+    np.testing.assert_array_equal(oracle.gperm_matrix(perm, diag), g)
+
+
+def test_gperm_unitary_round_trip_and_rejects_bad_input():
+    rng = np.random.default_rng(9)
+    n, targets = 5, (4, 0, 2)
+    perm = [int(p) for p in rng.permutation(8)]
+    diag = np.exp(1j * rng.uniform(0, 2 * np.pi, 8))
+    psi = _rand_state(n, rng)
+    a = psi.copy()
+    oracle.apply_gperm(a, perm, diag, targets)
+    oracle.apply_gperm(a, perm, diag, targets, adjoint=True)
+    np.testing.assert_allclose(a, psi, atol=1e-13)
+    with pytest.raises(ValueError):
+        oracle.apply_gperm(psi, [0, 0, 1, 2, 3, 4, 5, 6], diag, targets)
+    with pytest.raises(ValueError):
+        oracle.apply_gperm(psi, None, diag[:4], targets)
+    with pytest.raises(ValueError):
+        oracle.apply_gperm(psi, None, diag, (1, 1, 2))
