@@ -106,6 +106,9 @@ def parse():
     ap.add_argument("--gate-sweep", action="store_true",
                     help="also time single k-qubit gates (k = 1..6) on random target sets, both dtypes")
     ap.add_argument("--sweep-sets", type=int, default=100)
+    ap.add_argument("--large", action="store_true",
+                    help="also time the fused depth-12 random CNOT/CP circuit on 34 qubits (complex64) and "
+                         "33 qubits (complex128): 128 GiB states")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain device copies of known size (for HBM counter calibration)")
     return ap.parse_args()
@@ -389,6 +392,51 @@ def gate_sweep(P, W, torch, H, n, sets, reps=3, warm=3, warm_k5=10):
     return out
 
 
+def large_leg(P, W, torch, H):
+    """The depth-12 random CNOT/CP circuit (U3 on every qubit, then a random
+    matching into far-apart CNOT or CP pairs, per layer) fused to k <= 5
+    blocks on 34 qubits (complex64) and 33 qubits (complex128), 128 GiB
+    each, from a random basis state: one untimed pass, then one pass timed
+    with HIP events on the handle's stream around every block."""
+    out = {}
+    for n, dt, ab in ((34, "c64", 8), (33, "c128", 16)):
+        free, _ = torch.cuda.mem_get_info()
+        need = (1 << n) * ab + (2 << 30)
+        if free < need:
+            out[dt] = {"skipped": f"needs {need >> 30} GiB of free device memory, {free >> 30} GiB free"}
+            continue
+        gates = W.random_cx_cp(n, 12, 0)
+        f = P.fuse(gates, 5)
+        ks = [len(t) for t, _ in f.blocks()]
+        st = P.State(H, n, dt)
+        P.sv_set_basis_state(st.s, W.random_basis_state(n, 0))
+        P.sv_apply_fused(st.s, f.f)
+        torch.cuda.synchronize()
+        P.sv_set_basis_state(st.s, W.random_basis_state(n, 0))
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(f.count + 1)]
+        for i in range(f.count):
+            evs[i].record(H.stream)
+            P.sv_apply_fused_range(st.s, f.f, i, 1)
+        evs[f.count].record(H.stream)
+        evs[f.count].synchronize()
+        times = [evs[i].elapsed_time(evs[i + 1]) for i in range(f.count)]
+        nrm = st.norm()
+        sweep = 2 * (1 << n) * ab
+        by_k = {}
+        for k in sorted(set(ks)):
+            t = [x for x, kk in zip(times, ks) if kk == k]
+            by_k[str(k)] = {"blocks": len(t), "avg_ms": round(sum(t) / len(t), 3),
+                            "GBps": round(sweep / (sum(t) / len(t) * 1e-3) / 1e9, 1)}
+        out[dt] = {"n_qubits": n, "gates": len(gates), "fused_blocks": f.count, "apply_ms": round(sum(times), 1),
+                   "fused_gate_GBps": round(f.count * sweep / (sum(times) * 1e-3) / 1e9, 1),
+                   "block_sizes": by_k, "norm_after": nrm}
+        f.free()
+        st.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
+
+
 def batched_leg(P, W, torch, H, count, steps, warmup, sample):
     """4096 independent complex64 brickwork circuits (qubits uniform in
     8..20, depth uniform in 10..40), each returning <Z_i Z_i+1> for all i, in
@@ -609,6 +657,11 @@ def main():
         line["serving"] = serving_leg(P, W, torch, args.serve_requests, args.serve_slots)
     line["copy_ceiling_GBps"] = round(copy_ceiling(torch, n), 1)
     line["frac_of_copy_ceiling"] = round(r64["fused_gate_GBps"] / line["copy_ceiling_GBps"], 4)
+    if args.large:
+        print("[bench] large-state leg", file=sys.stderr, flush=True)
+        HL = P.Handle()
+        line["large"] = large_leg(P, W, torch, HL)
+        HL.close()
     if args.gate_sweep:
         print("[bench] gate sweep", file=sys.stderr, flush=True)
         H3 = P.Handle()

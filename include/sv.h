@@ -104,11 +104,11 @@ sv_status_t sv_handle_set_stream(sv_handle_t h, void* hip_stream);
  * targets a tile spans, and in the order workgroups take tiles.  Which one
  * moves HBM fastest depends on the target bits.
  *   SV_TILE_AUTO (default): after the handle's first SV_TILE_WARM_SWEEPS
- *     five-qubit sweeps (untimed, narrow), it times each variant three
+ *     five-qubit sweeps (untimed, spread), it times each variant three
  *     times, in rotating order, on the sweeps of every (dtype, state size,
  *     target set) it sees, with HIP events on its stream, then keeps the
  *     variant with the lowest mean (no timing while the stream is being
- *     captured);
+ *     captured; the spread variant until a target set has timings);
  *   SV_TILE_NARROW / SV_TILE_WIDE: always that shape, each workgroup on
  *     consecutive tiles (wide needs n >= 13 for complex64 and n >= 12 for
  *     complex128; smaller states use the narrow one);

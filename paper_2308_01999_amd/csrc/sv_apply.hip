@@ -1040,7 +1040,11 @@ struct TileVariant {
     int spread_lo;
     bool strided;
 };
-constexpr TileVariant kTileVariants[kTileShapes] = {{false, 0, false}, {true, 0, false}, {false, 12, true}};
+// Index 0 is the default: the variant that runs before any timing (and for
+// target sets seen too rarely to be timed), the best single variant in-circuit.
+constexpr TileVariant kTileVariants[kTileShapes] = {{false, 12, true}, {false, 0, false}, {true, 0, false}};
+constexpr int kVariantSpread = 0, kVariantNarrow = 1, kVariantWide = 2;
+constexpr TileVariant kPlainTiles = {false, 0, false};  // the sweeps without variants (k = 4, 6)
 
 uint64_t tune_key(Path p, const GateDesc& d)
 {
@@ -1058,10 +1062,10 @@ int wide_tile_bits(Path p) { return p == Path::kTileC128K5 ? 12 : kK5TileBits; }
 int tile_shape(sv_handle_s* h, Path p, const GateDesc& d, bool* trial)
 {
     *trial = false;
-    if (d.n < wide_tile_bits(p)) return 0;
-    if (h->tile_mode == SV_TILE_NARROW) return 0;
-    if (h->tile_mode == SV_TILE_WIDE) return 1;
-    if (h->tile_mode == SV_TILE_SPREAD) return 2;
+    if (d.n < wide_tile_bits(p)) return kVariantNarrow;
+    if (h->tile_mode == SV_TILE_NARROW) return kVariantNarrow;
+    if (h->tile_mode == SV_TILE_WIDE) return kVariantWide;
+    if (h->tile_mode == SV_TILE_SPREAD) return kVariantSpread;
     TileTuner& T = *h->tuner;
     const uint64_t key = tune_key(p, d);
     // while the stream is being recorded into a graph: no event queries and
@@ -1093,7 +1097,7 @@ int tile_shape(sv_handle_s* h, Path p, const GateDesc& d, bool* trial)
         if (e.unusable[c] || e.measured[c] == 0) continue;
         if (best < 0 || e.sum_ms[c] * e.measured[best] < e.sum_ms[best] * e.measured[c]) best = c;
     }
-    return best < 0 ? 0 : best;
+    return best < 0 ? kVariantSpread : best;
 }
 
 void launch_tile(sv_handle_s* h, Path p, void* psi, const void* mats, const GateDesc& d)
@@ -1115,7 +1119,7 @@ void launch_tile(sv_handle_s* h, Path p, void* psi, const void* mats, const Gate
                    : (p == Path::kTileC128K6) ? 12
                    : wide                     ? kK5TileBits
                                               : 12;
-    const TileVariant& v = kTileVariants[tuned ? variant : 0];
+    const TileVariant& v = tuned ? kTileVariants[variant] : kPlainTiles;
     const TileArgs t = make_tile_args(d, d.n, tb, h->cu_count, v.spread_lo, v.strided);
     const uint64_t blocks = (t.n_tiles + t.tiles_per_wg - 1) / t.tiles_per_wg;
     switch (p) {

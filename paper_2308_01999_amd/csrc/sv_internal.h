@@ -49,8 +49,8 @@ constexpr size_t kMinWorkspace = 12u << 20;
 }  // namespace sv
 
 // Online choice among the k = 5 tile variants (complex64 and complex128):
-// after the handle's first kTileWarmSweeps tuned sweeps (untimed, while
-// clocks and caches settle), per key (dtype, n, target mask) kTileTrials
+// after the handle's first kTileWarmSweeps tuned sweeps (untimed, on the
+// default variant, while clocks and caches settle), per key (dtype, n, target mask) kTileTrials
 // timings of each variant, taken in rotating round-robin order so that every
 // variant meets the same mix of neighbouring work, then the variant with
 // the lowest mean.
