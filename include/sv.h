@@ -165,6 +165,29 @@ sv_status_t sv_apply_matrix(sv_state_t s, const double* matrix, const int32_t* t
                             int32_t n_controls, int32_t adjoint);
 
 /*
+ * Generalized permutation gate (Table I: gate application with a
+ * generalized permutation matrix; Sec. II-D: diagonal gates, e.g. CZ, cost
+ * one sweep whatever their size): G = D P on k targets, where row r of G
+ * has its only non-zero entry diag[r] in column perm[r].  In every group
+ * (as for sv_apply_matrix, targets[0] = bit 0 of r, controls as there) the
+ * amplitude at offset r becomes diag[r] times the one at offset perm[r].
+ *   perm: 2^k int64, a permutation of 0 .. 2^k - 1, host memory, or NULL
+ *     for the identity (G is then the diagonal matrix diag);
+ *   diag: 2^k complex128 (re, im interleaved), host memory, finite;
+ *   adjoint != 0 applies G^dagger.
+ * A diagonal gate takes 1 <= k <= min(n, SV_MAX_TARGETS) and any controls,
+ * and moves only the 2^(n - n_controls) amplitudes its controls select (one
+ * read and one write each).  A gate with a permutation takes
+ * k + n_controls <= 6.  Host arrays are copied before return.
+ * SV_ERR_INVALID_VALUE for bad sizes, repeated or out-of-range qubits, a
+ * perm that is not a permutation, or non-finite entries.  Asynchronous on
+ * the handle's stream.
+ */
+sv_status_t sv_apply_gen_permutation(sv_state_t s, const int64_t* perm, const double* diag, const int32_t* targets,
+                                     int32_t k, const int32_t* controls, const int32_t* control_values,
+                                     int32_t n_controls, int32_t adjoint);
+
+/*
  * Named standard gates (host only).  Writes the target matrix of `name`
  * into matrix_out (room for 16 complex128), its number of targets into
  * *n_targets and its number of leading control qubits into *n_controls.
@@ -215,13 +238,36 @@ typedef enum {
 sv_status_t sv_fuse_gate_list(const int32_t* codes, const int32_t* qubits, const double* params,
                               int32_t n_gates, int32_t max_fused_qubits, sv_fused_t* out);
 
+/*
+ * Dense and diagonal gate fusion (Sec. II-D: diagonal gates such as CZ and
+ * CP cost one sweep whatever their size, so they are fused into diagonal
+ * blocks of up to max_fused_diagonal_qubits qubits, beside the dense blocks
+ * of up to max_fused_qubits).  A gate counts as diagonal when every
+ * off-diagonal entry of its target matrix is exactly zero (controls keep
+ * it diagonal).  Diagonal gates commute with each other, so a diagonal
+ * block may gather diagonal gates from across the circuit as long as no
+ * non-diagonal gate on a shared qubit lies between them; a dense block may
+ * still absorb diagonal gates.  max_fused_diagonal_qubits in
+ * [0, SV_MAX_TARGETS]; 0 gives exactly sv_fuse_gates / sv_fuse_gate_list.
+ * Applying the blocks in order equals applying the gates in order.  Host
+ * only; FP64 products.
+ */
+sv_status_t sv_fuse_gates_diag(const sv_gate_t* gates, int32_t n_gates, int32_t max_fused_qubits,
+                               int32_t max_fused_diagonal_qubits, sv_fused_t* out);
+sv_status_t sv_fuse_gate_list_diag(const int32_t* codes, const int32_t* qubits, const double* params,
+                                   int32_t n_gates, int32_t max_fused_qubits, int32_t max_fused_diagonal_qubits,
+                                   sv_fused_t* out);
+
 /* Number of blocks. */
 sv_status_t sv_fused_count(sv_fused_t f, int32_t* n_blocks);
 
 /* Block i: its qubit count into *k, its ascending targets into targets
  * (room for SV_MAX_TARGETS), and, if matrix != NULL, its 2^k x 2^k
- * complex128 matrix. */
+ * complex128 matrix, or for a diagonal block its 2^k diagonal entries. */
 sv_status_t sv_fused_block(sv_fused_t f, int32_t i, int32_t* k, int32_t* targets, double* matrix);
+
+/* *diagonal = 1 if block i is a diagonal block, else 0. */
+sv_status_t sv_fused_block_is_diagonal(sv_fused_t f, int32_t i, int32_t* diagonal);
 
 sv_status_t sv_fused_free(sv_fused_t f);
 

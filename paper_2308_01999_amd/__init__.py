@@ -71,9 +71,13 @@ _SIGS = {
     "sv_state_device_ptr": [_vp, ctypes.POINTER(_vp)],
     "sv_set_basis_state": [_vp, _u64],
     "sv_apply_matrix": [_vp, _pd, _pi32, _i32, _pi32, _pi32, _i32, _i32],
+    "sv_apply_gen_permutation": [_vp, ctypes.POINTER(ctypes.c_int64), _pd, _pi32, _i32, _pi32, _pi32, _i32, _i32],
     "sv_gate_matrix": [ctypes.c_char_p, _pd, _i32, _pd, _pi32, _pi32],
     "sv_fuse_gates": [ctypes.POINTER(sv_gate_t), _i32, _i32, ctypes.POINTER(_vp)],
     "sv_fuse_gate_list": [_pi32, _pi32, _pd, _i32, _i32, ctypes.POINTER(_vp)],
+    "sv_fuse_gates_diag": [ctypes.POINTER(sv_gate_t), _i32, _i32, _i32, ctypes.POINTER(_vp)],
+    "sv_fuse_gate_list_diag": [_pi32, _pi32, _pd, _i32, _i32, _i32, ctypes.POINTER(_vp)],
+    "sv_fused_block_is_diagonal": [_vp, _i32, _pi32],
     "sv_fused_count": [_vp, _pi32],
     "sv_fused_block": [_vp, _i32, _pi32, _pi32, _pd],
     "sv_fused_free": [_vp],
@@ -206,6 +210,18 @@ def sv_apply_matrix(s: int, matrix, targets, controls=(), control_values=None, a
                               _i32arr(controls), cv, len(controls), int(bool(adjoint))))
 
 
+def sv_apply_gen_permutation(s: int, perm, diag, targets, controls=(), control_values=None,
+                             adjoint: bool = False) -> None:
+    """G = D P on targets: the amplitude at group offset r becomes diag[r]
+    times the one at offset perm[r] (perm None: the diagonal gate diag)."""
+    dg = np.ascontiguousarray(diag, dtype=np.complex128)
+    pm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
+    cv = None if control_values is None else _i32arr(control_values)
+    _check(_L.sv_apply_gen_permutation(_vp(s), None if pm is None else pm.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       dg.ctypes.data_as(_pd), _i32arr(targets), len(targets), _i32arr(controls), cv,
+                                       len(controls), int(bool(adjoint))))
+
+
 def sv_gate_matrix(name: str, params=()) -> tuple:
     """(matrix [2^k, 2^k] complex128, n_targets, n_controls) of a named gate."""
     p = (ctypes.c_double * 3)(*[float(v) for v in params])
@@ -237,6 +253,17 @@ def sv_fuse_gates(gates, max_fused_qubits: int) -> int:
     return f.value
 
 
+def sv_fuse_gates_diag(gates, max_fused_qubits: int, max_fused_diagonal_qubits: int) -> int:
+    """As sv_fuse_gates, with diagonal blocks of up to max_fused_diagonal_qubits."""
+    keep = []
+    arr = (sv_gate_t * max(1, len(gates)))()
+    for i, (t, m, c, cv) in enumerate(gates):
+        arr[i] = _gate_struct(t, m, c, cv, keep)
+    f = _vp()
+    _check(_L.sv_fuse_gates_diag(arr, len(gates), max_fused_qubits, max_fused_diagonal_qubits, ctypes.byref(f)))
+    return f.value
+
+
 GATE_CODES = {"u3": 0, "h": 1, "x": 2, "y": 3, "z": 4, "cx": 5, "cz": 6, "cp": 7, "swap": 8}
 SV_GATE_ADJOINT = 256
 
@@ -251,6 +278,18 @@ def sv_fuse_gate_list(codes, qubits, params, max_fused_qubits: int) -> int:
     f = _vp()
     _check(_L.sv_fuse_gate_list(c.ctypes.data_as(_pi32), q.ctypes.data_as(_pi32), _dptr(p), c.size,
                                 max_fused_qubits, ctypes.byref(f)))
+    return f.value
+
+
+def sv_fuse_gate_list_diag(codes, qubits, params, max_fused_qubits: int, max_fused_diagonal_qubits: int) -> int:
+    c = np.ascontiguousarray(codes, dtype=np.int32)
+    q = np.ascontiguousarray(qubits, dtype=np.int32)
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    if q.shape != (c.size, 2) or p.shape != (c.size, 3):
+        raise ValueError("qubits must be [G, 2] and params [G, 3]")
+    f = _vp()
+    _check(_L.sv_fuse_gate_list_diag(c.ctypes.data_as(_pi32), q.ctypes.data_as(_pi32), _dptr(p), c.size,
+                                     max_fused_qubits, max_fused_diagonal_qubits, ctypes.byref(f)))
     return f.value
 
 
@@ -275,13 +314,25 @@ def sv_fused_count(f: int) -> int:
     return n.value
 
 
+def sv_fused_block_is_diagonal(f: int, i: int) -> bool:
+    d = _i32()
+    _check(_L.sv_fused_block_is_diagonal(_vp(f), i, ctypes.byref(d)))
+    return bool(d.value)
+
+
 def sv_fused_block(f: int, i: int) -> tuple:
+    """(targets, matrix [2^k, 2^k]) of a dense block, (targets, diagonal
+    [2^k]) of a diagonal one."""
     k = _i32()
     t = (ctypes.c_int32 * SV_MAX_TARGETS)()
     _check(_L.sv_fused_block(_vp(f), i, ctypes.byref(k), t, None))
-    m = np.zeros((1 << k.value) ** 2, dtype=np.complex128)
-    _check(_L.sv_fused_block(_vp(f), i, ctypes.byref(k), t, _dptr(m)))
     d = 1 << k.value
+    if sv_fused_block_is_diagonal(f, i):
+        v = np.zeros(d, dtype=np.complex128)
+        _check(_L.sv_fused_block(_vp(f), i, ctypes.byref(k), t, _dptr(v)))
+        return tuple(t[: k.value]), v
+    m = np.zeros(d * d, dtype=np.complex128)
+    _check(_L.sv_fused_block(_vp(f), i, ctypes.byref(k), t, _dptr(m)))
     return tuple(t[: k.value]), m.reshape(d, d)
 
 
@@ -400,6 +451,9 @@ class State:
     def apply_matrix(self, matrix, targets, controls=(), control_values=None, adjoint=False):
         sv_apply_matrix(self.s, matrix, targets, controls, control_values, adjoint)
 
+    def apply_gen_permutation(self, perm, diag, targets, controls=(), control_values=None, adjoint=False):
+        sv_apply_gen_permutation(self.s, perm, diag, targets, controls, control_values, adjoint)
+
     def apply_gate(self, gate):
         """One workload gate (name, qubits, params) via the library's gate table."""
         name, qubits, params = gate
@@ -485,8 +539,8 @@ class Graph:
     """A fused program recorded into a HIP graph for one state; launch()
     replays it on the state (async, on the handle's stream)."""
 
-    def __init__(self, state, gates, max_fused_qubits: int = 5):
-        f = fuse(gates, max_fused_qubits)
+    def __init__(self, state, gates, max_fused_qubits: int = 5, max_fused_diagonal_qubits: int = 0):
+        f = fuse(gates, max_fused_qubits, max_fused_diagonal_qubits)
         try:
             self.blocks = f.count
             self.g = sv_graph_create(state.s, f.f)
@@ -508,9 +562,15 @@ class Graph:
             pass
 
 
-def fuse(gates, max_fused_qubits: int) -> Fused:
+def fuse(gates, max_fused_qubits: int, max_fused_diagonal_qubits: int = 0) -> Fused:
+    """Fused blocks of a workload circuit; with max_fused_diagonal_qubits > 0
+    diagonal gates also form diagonal blocks of up to that many qubits."""
     if any(g[0] in ("mat", "mat_dg") for g in gates):
+        if max_fused_diagonal_qubits:
+            return Fused(sv_fuse_gates_diag(gate_entries(gates), max_fused_qubits, max_fused_diagonal_qubits))
         return Fused(sv_fuse_gates(gate_entries(gates), max_fused_qubits))
+    if max_fused_diagonal_qubits:
+        return Fused(sv_fuse_gate_list_diag(*gate_list_arrays(gates), max_fused_qubits, max_fused_diagonal_qubits))
     return Fused(sv_fuse_gate_list(*gate_list_arrays(gates), max_fused_qubits))
 
 

@@ -27,9 +27,9 @@ void batch_run(sv_batch_s* b, void* states, double* expect_out, double* latency_
 void batch_destroy(sv_batch_s* b);
 void batch_layout(sv_batch_s* b, uint64_t* state_bytes, uint64_t* byte_offsets);
 void batch_info(sv_batch_s* b, int n_qubits, int32_t* kmax, int32_t* blocks);
-sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax);
+sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag);
 sv_fused_s* fuse_gate_list(const int32_t* codes, const int32_t* qubits, const double* params, int n_gates,
-                           int kmax);
+                           int kmax, int kdiag);
 void gate_matrix(const char* name, const double* params, int n_params, double* out, int* n_targets,
                  int* n_controls);
 
@@ -349,6 +349,74 @@ sv_status_t sv_apply_matrix(sv_state_t s, const double* matrix, const int32_t* t
     });
 }
 
+sv_status_t sv_apply_gen_permutation(sv_state_t s, const int64_t* perm, const double* diag, const int32_t* targets,
+                                     int32_t k, const int32_t* controls, const int32_t* control_values,
+                                     int32_t n_controls, int32_t adjoint)
+{
+    return guarded([&] {
+        check_state(s);
+        GateDesc d = make_desc(s->n, targets, k, controls, control_values, n_controls);
+        SV_CHECK(diag != nullptr, "diag is NULL");
+        const int dim = 1 << k;
+        for (int i = 0; i < 2 * dim; ++i) SV_CHECK(std::isfinite(diag[i]), "diag entry is not finite");
+        bool identity = true;
+        if (perm != nullptr) {
+            std::vector<char> seen(dim, 0);
+            for (int r = 0; r < dim; ++r) {
+                SV_CHECK(perm[r] >= 0 && perm[r] < dim && !seen[perm[r]], "perm is not a permutation of 0..2^k-1");
+                seen[perm[r]] = 1;
+                identity &= perm[r] == r;
+            }
+        }
+        if (identity) {
+            // a diagonal gate: one streaming pass over the control-satisfying amplitudes
+            std::vector<char> tmp(gperm_table_bytes(s->dt, k, false));
+            pack_gperm(s->dt, k, nullptr, diag, adjoint, tmp.data());
+            const void* dt_ = stage_matrix(s->h, tmp.data(), tmp.size());
+            launch_gperm(s->h, s->dt, s->d, dt_, d, false);
+            return;
+        }
+        SV_CHECK(k + n_controls <= 6, "a permutation gate takes at most 6 qubits, controls included");
+        // controls become the top matrix bits of an uncontrolled permutation
+        // that leaves the rows with other control values alone
+        const int kk = k + n_controls;
+        const int dd = 1 << kk;
+        std::vector<int64_t> p(dd);
+        std::vector<double> dg(2 * dd);
+        std::vector<int32_t> tg(kk);
+        int want = 0;
+        for (int a = 0; a < k; ++a) tg[a] = targets[a];
+        for (int a = 0; a < n_controls; ++a) {
+            tg[k + a] = controls[a];
+            if (!control_values || control_values[a]) want |= 1 << a;
+        }
+        for (int r = 0; r < dd; ++r) {
+            const int cb = r >> k, lo = r & (dim - 1);
+            const bool on = cb == want;
+            p[r] = on ? ((int64_t(cb) << k) | perm[lo]) : r;
+            dg[2 * r] = on ? diag[2 * lo] : 1.0;
+            dg[2 * r + 1] = on ? diag[2 * lo + 1] : 0.0;
+        }
+        d = make_desc(s->n, tg.data(), kk, nullptr, nullptr, 0);
+        if (s->n < (s->dt == SV_C64 ? 12 : 11)) {
+            // small states: the dense sweep with G written out
+            std::vector<double> m(size_t(2) * dd * dd, 0.0);
+            for (int r = 0; r < dd; ++r) {
+                m[2 * (size_t(r) * dd + p[r])] = dg[2 * r];
+                m[2 * (size_t(r) * dd + p[r]) + 1] = dg[2 * r + 1];
+            }
+            const size_t bytes = packed_matrix_bytes(s->dt, s->n, kk, 0);
+            std::vector<char> tmp(bytes);
+            pack_matrix(s->dt, s->n, kk, 0, m.data(), adjoint, tmp.data());
+            launch_apply(s->h, s->dt, s->d, stage_matrix(s->h, tmp.data(), bytes), d);
+            return;
+        }
+        std::vector<char> tmp(gperm_table_bytes(s->dt, kk, true));
+        pack_gperm(s->dt, kk, p.data(), dg.data(), adjoint, tmp.data());
+        launch_gperm(s->h, s->dt, s->d, stage_matrix(s->h, tmp.data(), tmp.size()), d, true);
+    });
+}
+
 sv_status_t sv_gate_matrix(const char* name, const double* params, int32_t n_params, double* matrix_out,
                            int32_t* n_targets, int32_t* n_controls)
 {
@@ -365,7 +433,17 @@ sv_status_t sv_fuse_gates(const sv_gate_t* gates, int32_t n_gates, int32_t max_f
     return guarded([&] {
         SV_CHECK(out != nullptr, "out is NULL");
         *out = nullptr;
-        *out = fuse(gates, n_gates, max_fused_qubits);
+        *out = fuse(gates, n_gates, max_fused_qubits, 0);
+    });
+}
+
+sv_status_t sv_fuse_gates_diag(const sv_gate_t* gates, int32_t n_gates, int32_t max_fused_qubits,
+                               int32_t max_fused_diagonal_qubits, sv_fused_t* out)
+{
+    return guarded([&] {
+        SV_CHECK(out != nullptr, "out is NULL");
+        *out = nullptr;
+        *out = fuse(gates, n_gates, max_fused_qubits, max_fused_diagonal_qubits);
     });
 }
 
@@ -375,7 +453,18 @@ sv_status_t sv_fuse_gate_list(const int32_t* codes, const int32_t* qubits, const
     return guarded([&] {
         SV_CHECK(out != nullptr, "out is NULL");
         *out = nullptr;
-        *out = fuse_gate_list(codes, qubits, params, n_gates, max_fused_qubits);
+        *out = fuse_gate_list(codes, qubits, params, n_gates, max_fused_qubits, 0);
+    });
+}
+
+sv_status_t sv_fuse_gate_list_diag(const int32_t* codes, const int32_t* qubits, const double* params,
+                                   int32_t n_gates, int32_t max_fused_qubits, int32_t max_fused_diagonal_qubits,
+                                   sv_fused_t* out)
+{
+    return guarded([&] {
+        SV_CHECK(out != nullptr, "out is NULL");
+        *out = nullptr;
+        *out = fuse_gate_list(codes, qubits, params, n_gates, max_fused_qubits, max_fused_diagonal_qubits);
     });
 }
 
@@ -395,7 +484,16 @@ sv_status_t sv_fused_block(sv_fused_t f, int32_t i, int32_t* k, int32_t* targets
         const FusedBlock& b = f->blocks[i];
         *k = b.k;
         for (int a = 0; a < b.k; ++a) targets[a] = b.targets[a];
-        if (matrix) std::memcpy(matrix, b.m, sizeof(double) * (size_t(2) << (2 * b.k)));
+        if (matrix) std::memcpy(matrix, b.m, sizeof(double) * (size_t(2) << (b.diagonal ? b.k : 2 * b.k)));
+    });
+}
+
+sv_status_t sv_fused_block_is_diagonal(sv_fused_t f, int32_t i, int32_t* diagonal)
+{
+    return guarded([&] {
+        SV_CHECK(f != nullptr && diagonal != nullptr, "NULL argument");
+        SV_CHECK(i >= 0 && i < f->n_blocks, "block index out of range");
+        *diagonal = f->blocks[i].diagonal ? 1 : 0;
     });
 }
 
@@ -413,6 +511,29 @@ sv_status_t sv_fused_free(sv_fused_t f)
 
 namespace sv {
 namespace {
+
+// A fused block's device form and sweep: the dense sweep, or for a diagonal
+// block the diagonal sweep.
+size_t block_bytes(const sv_state_s* s, const FusedBlock& b)
+{
+    return b.diagonal ? gperm_table_bytes(s->dt, b.k, false) : packed_matrix_bytes(s->dt, s->n, b.k, 0);
+}
+
+void pack_block(const sv_state_s* s, const FusedBlock& b, void* dst)
+{
+    if (b.diagonal)
+        pack_gperm(s->dt, b.k, nullptr, b.m, 0, dst);
+    else
+        pack_matrix(s->dt, s->n, b.k, 0, b.m, 0, dst);
+}
+
+void launch_block(sv_handle_s* h, const sv_state_s* s, const FusedBlock& b, const void* dm, const GateDesc& d)
+{
+    if (b.diagonal)
+        launch_gperm(h, s->dt, s->d, dm, d, false);
+    else
+        launch_apply(h, s->dt, s->d, dm, d);
+}
 
 void apply_fused_blocks(sv_state_s* s, sv_fused_s* f, int first, int count)
 {
@@ -435,7 +556,7 @@ void apply_fused_blocks(sv_state_s* s, sv_fused_s* f, int first, int count)
             size_t bytes = 0;
             int e = b;
             while (e < end) {
-                const size_t mb = (packed_matrix_bytes(s->dt, s->n, f->blocks[e].k, 0) + 255) & ~size_t(255);
+                const size_t mb = (block_bytes(s, f->blocks[e]) + 255) & ~size_t(255);
                 if (bytes + mb > seg) break;
                 offs.push_back(bytes);
                 bytes += mb;
@@ -443,18 +564,17 @@ void apply_fused_blocks(sv_state_s* s, sv_fused_s* f, int first, int count)
             }
             if (e == b) {
                 // one block larger than a ring segment: stage it on its own
-                const size_t mb = packed_matrix_bytes(s->dt, s->n, f->blocks[b].k, 0);
+                const size_t mb = block_bytes(s, f->blocks[b]);
                 std::vector<char> one(mb);
-                pack_matrix(s->dt, s->n, f->blocks[b].k, 0, f->blocks[b].m, 0, one.data());
-                launch_apply(s->h, s->dt, s->d, stage_matrix(s->h, one.data(), mb), descs[b]);
+                pack_block(s, f->blocks[b], one.data());
+                launch_block(s->h, s, f->blocks[b], stage_matrix(s->h, one.data(), mb), descs[b]);
                 ++b;
                 continue;
             }
             std::vector<char> tmp(bytes);
-            for (int j = b; j < e; ++j)
-                pack_matrix(s->dt, s->n, f->blocks[j].k, 0, f->blocks[j].m, 0, tmp.data() + offs[j - b]);
+            for (int j = b; j < e; ++j) pack_block(s, f->blocks[j], tmp.data() + offs[j - b]);
             const char* dm = static_cast<const char*>(stage_matrix(s->h, tmp.data(), bytes));
-            for (int j = b; j < e; ++j) launch_apply(s->h, s->dt, s->d, dm + offs[j - b], descs[j]);
+            for (int j = b; j < e; ++j) launch_block(s->h, s, f->blocks[j], dm + offs[j - b], descs[j]);
             b = e;
         }
     }
@@ -500,11 +620,10 @@ sv_status_t sv_graph_create(sv_state_t s, sv_fused_t f, sv_graph_t* out)
             const FusedBlock& blk = f->blocks[b];
             descs[b] = make_desc(s->n, blk.targets, blk.k, nullptr, nullptr, 0);
             offs[b] = bytes;
-            bytes += (packed_matrix_bytes(s->dt, s->n, blk.k, 0) + 255) & ~size_t(255);
+            bytes += (block_bytes(s, blk) + 255) & ~size_t(255);
         }
         std::vector<char> host(bytes ? bytes : 1);
-        for (int b = 0; b < f->n_blocks; ++b)
-            pack_matrix(s->dt, s->n, f->blocks[b].k, 0, f->blocks[b].m, 0, host.data() + offs[b]);
+        for (int b = 0; b < f->n_blocks; ++b) pack_block(s, f->blocks[b], host.data() + offs[b]);
         auto* g = new sv_graph_s;
         g->s = s;
         hipStream_t cap = nullptr;
@@ -523,7 +642,7 @@ sv_status_t sv_graph_create(sv_state_t s, sv_fused_t f, sv_graph_t* out)
             h->stream = cap;
             SV_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
             try {
-                for (int b = 0; b < f->n_blocks; ++b) launch_apply(h, s->dt, s->d, g->mats + offs[b], descs[b]);
+                for (int b = 0; b < f->n_blocks; ++b) launch_block(h, s, f->blocks[b], g->mats + offs[b], descs[b]);
             } catch (...) {
                 hipGraph_t dropped = nullptr;
                 (void)hipStreamEndCapture(cap, &dropped);

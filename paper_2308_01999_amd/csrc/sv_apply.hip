@@ -1211,6 +1211,118 @@ void launch_apply_t(sv_handle_s* h, void* psi_v, const void* mat_v, const GateDe
     SV_HIP(hipGetLastError());
 }
 
+// ------------------------------------------- generalized permutation gates
+//
+// G = D P on k targets (Table I: gate application with a generalized
+// permutation matrix; Sec. II-D: diagonal gates and diagonal gate fusion):
+// in every group, the amplitude at offset r becomes diag[r] times the one
+// at offset perm[r].  A diagonal (no permutation) touches each amplitude on
+// its own: one coalesced streaming pass with the 2^k-entry table in LDS,
+// over the control-satisfying amplitudes only.  A true permutation moves
+// amplitudes inside their group: the tile geometry of the dense sweeps
+// (whole groups per 32 KiB tile) with the permutation done in LDS.
+
+struct DiagArgs {
+    uint64_t n_vecs;                   // vectors in the control-compressed index space
+    int32_t k;
+    int32_t tpos[SV_MAX_TARGETS];      // index bit of matrix bit a
+    int32_t n_ctrl;
+    int32_t cpos[SV_MAX_QUBITS];       // control bits, ascending
+    uint64_t cval;
+};
+
+constexpr int kDiagThreads = 256;
+constexpr int kDiagVecs = 8;
+
+template <typename T>
+__device__ __forceinline__ T cmul(const T a, const T b)
+{
+    return T{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+__device__ __forceinline__ int diag_row(uint64_t i, const DiagArgs& a)
+{
+    int r = 0;
+    for (int b = 0; b < a.k; ++b) r |= int((i >> a.tpos[b]) & 1) << b;
+    return r;
+}
+
+// APV complex amplitudes per 16-byte vector: 2 for complex64 (pairs i, i+1
+// with bit 0 free), 1 for complex128.  NARROW: complex64 one amplitude per
+// 8-byte access (bit 0 is a control).
+template <typename R, bool NARROW>
+__global__ __launch_bounds__(kDiagThreads) void k_apply_diag(typename Cx<R>::T* __restrict__ psi,
+                                                             const typename Cx<R>::T* __restrict__ table, DiagArgs a)
+{
+    using T = typename Cx<R>::T;
+    constexpr int APV = (sizeof(T) == 8 && !NARROW) ? 2 : 1;
+    __shared__ T tab[1 << SV_MAX_TARGETS];
+    for (int e = threadIdx.x; e < (1 << a.k); e += kDiagThreads) tab[e] = table[e];
+    __syncthreads();
+    const uint64_t v0 = uint64_t(blockIdx.x) * (kDiagThreads * kDiagVecs) + threadIdx.x;
+    T x[kDiagVecs][APV];
+    uint64_t at[kDiagVecs];
+#pragma unroll
+    for (int u = 0; u < kDiagVecs; ++u) {
+        const uint64_t v = v0 + uint64_t(u) * kDiagThreads;
+        at[u] = v < a.n_vecs ? (insert_zero_bits(v * APV, a.cpos, a.n_ctrl) | a.cval) : ~uint64_t(0);
+        if (at[u] != ~uint64_t(0)) {
+            if constexpr (APV == 2) {
+                const float4 w = gload(reinterpret_cast<const float4*>(psi + at[u]));
+                x[u][0] = T{w.x, w.y};
+                x[u][APV - 1] = T{w.z, w.w};
+            } else {
+                x[u][0] = psi[at[u]];
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kDiagVecs; ++u) {
+        if (at[u] == ~uint64_t(0)) continue;
+#pragma unroll
+        for (int e = 0; e < APV; ++e) x[u][e] = cmul(tab[diag_row(at[u] + e, a)], x[u][e]);
+        if constexpr (APV == 2) {
+            gstore(reinterpret_cast<float4*>(psi + at[u]), float4{x[u][0].x, x[u][0].y, x[u][APV - 1].x, x[u][APV - 1].y});
+        } else {
+            psi[at[u]] = x[u][0];
+        }
+    }
+}
+
+// One 32 KiB tile per workgroup (whole groups: 2^tb amplitudes), loaded to
+// LDS, then every output read from its permuted source in LDS.  diag: 2^k
+// entries in the state's precision, perm: 2^k ints (k <= 6).
+template <typename R>
+__global__ __launch_bounds__(kTileThreads) void k_tile_gperm(typename Cx<R>::T* __restrict__ psi,
+                                                             const typename Cx<R>::T* __restrict__ diag,
+                                                             const int32_t* __restrict__ perm, TileArgs a, int k)
+{
+    using T = typename Cx<R>::T;
+    constexpr int kAmps = 32768 / int(sizeof(T));
+    __shared__ T lds[kAmps];
+    __shared__ T dtab[64];
+    __shared__ int32_t ptab[64];
+    __shared__ int32_t lpos[SV_MAX_TARGETS];
+    const int tid = threadIdx.x;
+    if (tid < (1 << k)) {
+        dtab[tid] = diag[tid];
+        ptab[tid] = perm[tid];
+    }
+    if (tid < k) lpos[tid] = 31 - __clz(a.lds_off[1 << tid]);
+    const uint64_t base = tile_base(blockIdx.x, a);
+    const uint64_t mask = (uint64_t(1) << a.L) - 1;
+    for (int e = tid; e < kAmps; e += kTileThreads)
+        lds[e] = psi[base + deposit_bits(uint32_t(e >> a.L), a.hi_pos, a.n_hi) + (uint64_t(e) & mask)];
+    __syncthreads();
+    const int full = a.lds_off[(1 << k) - 1];
+    for (int e = tid; e < kAmps; e += kTileThreads) {
+        int r = 0;
+        for (int b = 0; b < k; ++b) r |= ((e >> lpos[b]) & 1) << b;
+        const int src = (e & ~full) + a.lds_off[ptab[r]];
+        psi[base + deposit_bits(uint32_t(e >> a.L), a.hi_pos, a.n_hi) + (uint64_t(e) & mask)] = cmul(dtab[r], lds[src]);
+    }
+}
+
 }  // namespace
 
 size_t packed_matrix_bytes(sv_dtype_t dt, int n, int k, int n_controls)
@@ -1326,6 +1438,103 @@ void launch_apply(sv_handle_s* h, sv_dtype_t dt, void* psi, const void* mat, con
             else
                 launch_apply_t<double>(h, psi, mat, d);
     }
+}
+
+
+// ------------------------------------------- generalized permutation gates
+
+size_t gperm_table_bytes(sv_dtype_t dt, int k, bool has_perm)
+{
+    return (size_t(1) << k) * (dt == SV_C64 ? 8 : 16) + (has_perm ? (size_t(1) << k) * 4 : 0);
+}
+
+// Device table: diag' (2^k complex in the state's precision), then perm' (2^k
+// int32) if has_perm, where (perm', diag') is G or, for adjoint, G^dagger =
+// P^T D^*: output q of G^dagger takes input r = perm^-1(q) times conj(diag[r]).
+void pack_gperm(sv_dtype_t dt, int k, const int64_t* perm, const double* diag, int adjoint, void* dst)
+{
+    const int d = 1 << k;
+    std::vector<int32_t> p(d), src(d);
+    for (int r = 0; r < d; ++r) p[r] = perm ? int32_t(perm[r]) : r;
+    for (int r = 0; r < d; ++r) src[r] = r;
+    if (adjoint)
+        for (int r = 0; r < d; ++r) src[p[r]] = r;  // src = perm^-1
+    char* o = static_cast<char*>(dst);
+    for (int q = 0; q < d; ++q) {
+        const int r = src[q];
+        const double re = diag[2 * r], im = adjoint ? -diag[2 * r + 1] : diag[2 * r + 1];
+        if (dt == SV_C64) {
+            reinterpret_cast<float*>(o)[2 * q] = float(re);
+            reinterpret_cast<float*>(o)[2 * q + 1] = float(im);
+        } else {
+            reinterpret_cast<double*>(o)[2 * q] = re;
+            reinterpret_cast<double*>(o)[2 * q + 1] = im;
+        }
+    }
+    if (perm) {
+        int32_t* po = reinterpret_cast<int32_t*>(o + size_t(d) * (dt == SV_C64 ? 8 : 16));
+        for (int q = 0; q < d; ++q) po[q] = adjoint ? src[q] : p[q];
+    }
+}
+
+void launch_gperm(sv_handle_s* h, sv_dtype_t dt, void* psi, const void* table, const GateDesc& d, bool has_perm)
+{
+    const size_t tab_bytes = (size_t(1) << d.k) * (dt == SV_C64 ? 8 : 16);
+    if (!has_perm) {
+        DiagArgs a{};
+        a.k = d.k;
+        for (int b = 0; b < d.k; ++b) {
+            int q = 0;
+            while ((uint64_t(1) << q) != d.tbit[b]) ++q;
+            a.tpos[b] = q;
+        }
+        uint64_t cmask = 0;
+        for (int j = 0; j < d.n_fixed; ++j) {
+            const uint64_t bit = uint64_t(1) << d.fixed_sorted[j];
+            bool is_t = false;
+            for (int b = 0; b < d.k; ++b) is_t |= d.tbit[b] == bit;
+            if (!is_t) {
+                a.cpos[a.n_ctrl++] = d.fixed_sorted[j];
+                cmask |= bit;
+            }
+        }
+        a.cval = d.cval;
+        const uint64_t amps = uint64_t(1) << (d.n - a.n_ctrl);
+        const bool narrow = dt == SV_C64 && ((cmask & 1) || d.n - a.n_ctrl < 1);
+        const int apv = (dt == SV_C64 && !narrow) ? 2 : 1;
+        a.n_vecs = amps / apv;
+        const uint64_t per_block = uint64_t(kDiagThreads) * kDiagVecs;
+        const uint64_t blocks = (a.n_vecs + per_block - 1) / per_block;
+        SV_CHECK(blocks <= 0x7fffffffu, "state too large for one launch");
+        if (dt == SV_C64) {
+            if (narrow)
+                hipLaunchKernelGGL((k_apply_diag<float, true>), dim3(unsigned(blocks)), dim3(kDiagThreads), 0, h->stream,
+                                   static_cast<float2*>(psi), static_cast<const float2*>(table), a);
+            else
+                hipLaunchKernelGGL((k_apply_diag<float, false>), dim3(unsigned(blocks)), dim3(kDiagThreads), 0,
+                                   h->stream, static_cast<float2*>(psi), static_cast<const float2*>(table), a);
+        } else {
+            hipLaunchKernelGGL((k_apply_diag<double, false>), dim3(unsigned(blocks)), dim3(kDiagThreads), 0, h->stream,
+                               static_cast<double2*>(psi), static_cast<const double2*>(table), a);
+        }
+        SV_HIP(hipGetLastError());
+        return;
+    }
+    SV_CHECK(d.n_controls == 0 && d.k <= 6, "a permutation takes at most 6 qubits, controls included");
+    const int tb = dt == SV_C64 ? 12 : 11;
+    SV_CHECK(d.n >= tb, "internal: small states take the dense path");
+    TileArgs t = make_tile_args(d, d.n, tb, h->cu_count, 0, false);
+    t.tiles_per_wg = 1;
+    const char* tab = static_cast<const char*>(table);
+    if (dt == SV_C64)
+        hipLaunchKernelGGL(k_tile_gperm<float>, dim3(unsigned(t.n_tiles)), dim3(kTileThreads), 0, h->stream,
+                           static_cast<float2*>(psi), reinterpret_cast<const float2*>(tab),
+                           reinterpret_cast<const int32_t*>(tab + tab_bytes), t, d.k);
+    else
+        hipLaunchKernelGGL(k_tile_gperm<double>, dim3(unsigned(t.n_tiles)), dim3(kTileThreads), 0, h->stream,
+                           static_cast<double2*>(psi), reinterpret_cast<const double2*>(tab),
+                           reinterpret_cast<const int32_t*>(tab + tab_bytes), t, d.k);
+    SV_HIP(hipGetLastError());
 }
 
 }  // namespace sv

@@ -21,7 +21,7 @@
 namespace sv {
 
 sv_fused_s* fuse_gate_list(const int32_t* codes, const int32_t* qubits, const double* params, int n_gates,
-                           int kmax);
+                           int kmax, int kdiag);
 
 struct BatchHost {
     std::vector<BatchCircuit> circuits;
@@ -162,7 +162,7 @@ std::vector<sv_fused_s*> fuse_all(const std::vector<CircuitInput>& in, const std
             const size_t i = next.fetch_add(1);
             if (i >= in.size()) return;
             try {
-                out[i] = fuse_gate_list(in[i].codes, in[i].qubits, in[i].params, in[i].n_gates, kmax[i]);
+                out[i] = fuse_gate_list(in[i].codes, in[i].qubits, in[i].params, in[i].n_gates, kmax[i], 0);
             } catch (const Error& e) {
                 std::lock_guard<std::mutex> g(err_mu);
                 if (err.empty()) {

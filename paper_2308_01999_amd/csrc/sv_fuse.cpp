@@ -104,6 +104,14 @@ struct HostGate {
     std::vector<int> targets, controls, cvals;
     std::vector<cd> m;
     uint64_t qmask = 0;  // targets | controls
+    bool diagonal = false;  // every off-diagonal entry of m is exactly 0
+};
+
+// A selected block: its gates (circuit order) and whether it is a diagonal
+// block (all its gates diagonal, applied as one diagonal sweep).
+struct Selected {
+    std::vector<int> gates;
+    bool diagonal = false;
 };
 
 // U <- G * U where G acts on positions pos_t (matrix bit order) with
@@ -176,15 +184,25 @@ int popcount64(uint64_t v) { return __builtin_popcountll(v); }
 // that touch the set, and the one whose addition lets the most gates be
 // absorbed wins (lowest qubit on ties).  The seed whose grown set absorbs
 // the most gates becomes the next block.
-std::vector<std::vector<int>> select_blocks(const std::vector<HostGate>& gates, int kmax)
+//
+// With kdiag > 0, diagonal blocks compete as well: absorbing into a
+// diagonal set takes diagonal gates only, and since diagonal gates commute
+// with one another, a skipped diagonal gate does not block later ones; only
+// skipped non-diagonal gates block their qubits.  A diagonal set grows up to
+// kdiag qubits from the qubits of near-future diagonal gates.  Every round
+// takes the dense or diagonal block that absorbs the most gates (dense on
+// ties).
+std::vector<Selected> select_blocks(const std::vector<HostGate>& gates, int kmax, int kdiag)
 {
     std::vector<int> live(gates.size());
     std::vector<uint64_t> mask(gates.size());
+    std::vector<char> diag(gates.size());
     for (size_t i = 0; i < gates.size(); ++i) {
         live[i] = int(i);
         mask[i] = gates[i].qmask;
+        diag[i] = gates[i].diagonal;
     }
-    std::vector<std::vector<int>> blocks;
+    std::vector<Selected> blocks;
     std::vector<int> ready;
     std::vector<char> take;
     constexpr size_t kWindow = 256;  // gates looked at for candidate qubits
@@ -202,6 +220,43 @@ std::vector<std::vector<int>> select_blocks(const std::vector<HostGate>& gates, 
             if ((S & ~blocked) == 0) break;  // every qubit of S is blocked
         }
         return count;
+    };
+    auto absorb_diag = [&](uint64_t S, bool mark) {
+        uint64_t blocked = 0;
+        int count = 0;
+        for (size_t j = 0; j < live.size(); ++j) {
+            const uint64_t Q = mask[j];
+            if (diag[j] && (Q & blocked) == 0 && (Q & ~S) == 0) {
+                ++count;
+                if (mark) take[j] = 1;
+            } else if (!diag[j]) {
+                blocked |= Q;
+            }
+            if ((S & ~blocked) == 0) break;
+        }
+        return count;
+    };
+    auto grow_diag = [&](uint64_t S) {
+        while (popcount64(S) < kdiag) {
+            uint64_t cand = 0, blocked = 0;
+            const size_t lim = std::min(live.size(), kWindow);
+            for (size_t j = 0; j < lim; ++j) {
+                if (diag[j] && (mask[j] & S) && !(mask[j] & blocked)) cand |= mask[j] & ~S;
+                if (!diag[j]) blocked |= mask[j];
+            }
+            if (!cand) break;
+            int best_q = -1, best_c = -1;
+            for (int q = 0; q < 64; ++q) {
+                if (!((cand >> q) & 1)) continue;
+                const int c = absorb_diag(S | (uint64_t(1) << q), false);
+                if (c > best_c) {
+                    best_c = c;
+                    best_q = q;
+                }
+            }
+            S |= uint64_t(1) << best_q;
+        }
+        return S;
     };
     auto grow = [&](uint64_t S) {
         while (popcount64(S) < kmax) {
@@ -232,6 +287,7 @@ std::vector<std::vector<int>> select_blocks(const std::vector<HostGate>& gates, 
         }
         uint64_t best_S = 0;
         int best_count = -1;
+        bool best_diag = false;
         for (int pos : ready) {
             const uint64_t S = grow(mask[size_t(pos)]);
             const int c = absorb(S, false);
@@ -240,8 +296,29 @@ std::vector<std::vector<int>> select_blocks(const std::vector<HostGate>& gates, 
                 best_S = S;
             }
         }
+        if (kdiag > 0) {
+            // seeds: the diagonal gates not blocked by an earlier non-diagonal one
+            uint64_t blocked = 0;
+            const size_t lim = std::min(live.size(), kWindow);
+            for (size_t j = 0; j < lim; ++j) {
+                if (diag[j] && !(mask[j] & blocked) && popcount64(mask[j]) <= kdiag) {
+                    const uint64_t S = grow_diag(mask[j]);
+                    const int c = absorb_diag(S, false);
+                    if (c > best_count) {
+                        best_count = c;
+                        best_S = S;
+                        best_diag = true;
+                    }
+                }
+                if (!diag[j]) blocked |= mask[j];
+            }
+        }
+        SV_CHECK(best_count > 0, "internal: fusion found no block");
         take.assign(live.size(), 0);
-        absorb(best_S, true);
+        if (best_diag)
+            absorb_diag(best_S, true);
+        else
+            absorb(best_S, true);
         std::vector<int> blk;
         size_t w = 0;
         for (size_t j = 0; j < live.size(); ++j) {
@@ -255,17 +332,24 @@ std::vector<std::vector<int>> select_blocks(const std::vector<HostGate>& gates, 
         }
         live.resize(w);
         mask.resize(w);
-        blocks.push_back(std::move(blk));
+        size_t w2 = 0;
+        for (size_t j = 0; j < take.size(); ++j)
+            if (!take[j]) diag[w2++] = diag[j];
+        diag.resize(w2);
+        Selected sel;
+        sel.gates = std::move(blk);
+        sel.diagonal = best_diag;
+        blocks.push_back(std::move(sel));
     }
     return blocks;
 }
 
 }  // namespace
 
-sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax);
+sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag);
 
 sv_fused_s* fuse_gate_list(const int32_t* codes, const int32_t* qubits, const double* params, int n_gates,
-                           int kmax)
+                           int kmax, int kdiag)
 {
     SV_CHECK(n_gates >= 0, "n_gates is negative");
     SV_CHECK(n_gates == 0 || (codes && qubits && params), "NULL gate arrays");
@@ -293,14 +377,15 @@ sv_fused_s* fuse_gate_list(const int32_t* codes, const int32_t* qubits, const do
         e.targets = &qs[2 * g + nc];
         e.matrix = &mats[size_t(g) * 32];
     }
-    return fuse(gates.data(), n_gates, kmax);
+    return fuse(gates.data(), n_gates, kmax, kdiag);
 }
 
-sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax)
+sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag)
 {
     SV_CHECK(n_gates >= 0, "n_gates is negative");
     SV_CHECK(n_gates == 0 || gates != nullptr, "gates is NULL");
     SV_CHECK(kmax >= 1 && kmax <= SV_MAX_TARGETS, "max_fused_qubits must be in [1, 10]");
+    SV_CHECK(kdiag >= 0 && kdiag <= SV_MAX_TARGETS, "max_fused_diagonal_qubits must be in [0, 10]");
     std::vector<HostGate> hg(n_gates);
     for (int i = 0; i < n_gates; ++i) {
         const sv_gate_t& g = gates[i];
@@ -327,23 +412,25 @@ sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax)
         }
         const int d = 1 << g.n_targets;
         h.m.resize(size_t(d) * d);
+        h.diagonal = true;
         for (int e = 0; e < d * d; ++e) {
             h.m[e] = cd(g.matrix[2 * e], g.matrix[2 * e + 1]);
             SV_CHECK(std::isfinite(g.matrix[2 * e]) && std::isfinite(g.matrix[2 * e + 1]),
                      "gate " + std::to_string(i) + ": matrix entry is not finite");
+            if (e / d != e % d && h.m[e] != cd(0.0, 0.0)) h.diagonal = false;
         }
     }
-    const auto sel = select_blocks(hg, kmax);
+    const auto sel = select_blocks(hg, kmax, kdiag);
     // build matrices
     std::vector<std::vector<int>> qs(sel.size());
     size_t total = 0;
     for (size_t b = 0; b < sel.size(); ++b) {
         uint64_t S = 0;
-        for (int i : sel[b]) S |= hg[i].qmask;
+        for (int i : sel[b].gates) S |= hg[i].qmask;
         for (int q = 0; q < 64; ++q)
             if ((S >> q) & 1) qs[b].push_back(q);
         const size_t d = size_t(1) << qs[b].size();
-        total += d * d;
+        total += sel[b].diagonal ? d : d * d;
     }
     auto* f = new sv_fused_s;
     f->n_blocks = int(sel.size());
@@ -353,20 +440,48 @@ sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax)
     for (size_t b = 0; b < sel.size(); ++b) {
         const int m = int(qs[b].size());
         const uint64_t dim = uint64_t(1) << m;
+        auto pos = [&](int q) { return int(std::lower_bound(qs[b].begin(), qs[b].end(), q) - qs[b].begin()); };
+        FusedBlock& blk = f->blocks[b];
+        blk.k = m;
+        for (int a = 0; a < m; ++a) blk.targets[a] = qs[b][a];
+        blk.m = f->storage + 2 * at;
+        if (sel[b].diagonal) {
+            // the product of the gates' diagonals: entry i gets, from every
+            // gate whose control bits in i match, the diagonal element of the
+            // row that i's bits at the gate's targets select
+            blk.diagonal = true;
+            std::vector<cd> D(dim, cd(1.0, 0.0));
+            for (int gi : sel[b].gates) {
+                const HostGate& g = hg[gi];
+                const int d = 1 << g.targets.size();
+                for (uint64_t i = 0; i < dim; ++i) {
+                    bool on = true;
+                    for (size_t a = 0; a < g.controls.size(); ++a)
+                        on &= int((i >> pos(g.controls[a])) & 1) == g.cvals[a];
+                    if (!on) continue;
+                    int r = 0;
+                    for (size_t a = 0; a < g.targets.size(); ++a) r |= int((i >> pos(g.targets[a])) & 1) << a;
+                    const cd e = g.m[size_t(r) * d + r];
+                    D[i] = cd(D[i].real() * e.real() - D[i].imag() * e.imag(),
+                              D[i].real() * e.imag() + D[i].imag() * e.real());
+                }
+            }
+            for (uint64_t i = 0; i < dim; ++i) {
+                blk.m[2 * i] = D[i].real();
+                blk.m[2 * i + 1] = D[i].imag();
+            }
+            at += dim;
+            continue;
+        }
         std::vector<double> U(2 * dim * dim, 0.0);
         for (uint64_t i = 0; i < dim; ++i) U[2 * (i * dim + i)] = 1.0;
-        for (int gi : sel[b]) {
+        for (int gi : sel[b].gates) {
             const HostGate& g = hg[gi];
-            auto pos = [&](int q) { return int(std::lower_bound(qs[b].begin(), qs[b].end(), q) - qs[b].begin()); };
             std::vector<int> pt, pc;
             for (int q : g.targets) pt.push_back(pos(q));
             for (int q : g.controls) pc.push_back(pos(q));
             left_multiply(U, m, g, pt, pc);
         }
-        FusedBlock& blk = f->blocks[b];
-        blk.k = m;
-        for (int a = 0; a < m; ++a) blk.targets[a] = qs[b][a];
-        blk.m = f->storage + 2 * at;
         std::memcpy(blk.m, U.data(), sizeof(double) * 2 * dim * dim);
         at += dim * dim;
     }

@@ -106,8 +106,10 @@ struct sv_state_s {
 struct FusedBlock {
     int k = 0;
     int targets[SV_MAX_TARGETS] = {};
-    // 2^k x 2^k complex128, row-major, interleaved
+    // dense: 2^k x 2^k complex128, row-major, interleaved; diagonal: the 2^k
+    // diagonal entries
     double* m = nullptr;
+    bool diagonal = false;
 };
 
 struct sv_fused_s {
@@ -142,6 +144,12 @@ void pack_matrix(sv_dtype_t dt, int n, int k, int n_controls, const double* m, i
 
 // psi: amplitudes; mat: device copy of the packed matrix; desc: the sweep.
 void launch_apply(sv_handle_s* h, sv_dtype_t dt, void* psi, const void* mat, const GateDesc& desc);
+
+// Generalized permutation gate G = D P (diagonal when has_perm is false):
+// device table size and packing (adjoint folded in), and the sweep.
+size_t gperm_table_bytes(sv_dtype_t dt, int k, bool has_perm);
+void pack_gperm(sv_dtype_t dt, int k, const int64_t* perm, const double* diag, int adjoint, void* dst);
+void launch_gperm(sv_handle_s* h, sv_dtype_t dt, void* psi, const void* table, const GateDesc& desc, bool has_perm);
 
 void launch_set_basis(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, uint64_t x);
 void launch_scale(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, double factor);

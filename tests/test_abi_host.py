@@ -94,7 +94,10 @@ def test_gate_table_rejects_bad_input(P):
 def _apply_blocks_with_oracle(n, blocks, basis=0):
     psi = oracle.basis_state(n, basis)
     for targets, m in blocks:
-        oracle.apply(psi, m, targets)
+        if m.ndim == 1:  # a diagonal block
+            oracle.apply_gperm(psi, None, m, targets)
+        else:
+            oracle.apply(psi, m, targets)
     return psi
 
 
@@ -135,6 +138,60 @@ def test_fusion_with_controls_and_values(P):
     P.sv_fused_free(f)
     got = _apply_blocks_with_oracle(n, blocks, basis=3)
     np.testing.assert_allclose(got, ref, atol=1e-12)
+
+
+@pytest.mark.parametrize("kmax,kdiag", [(2, 3), (3, 6), (5, 10), (4, 1), (5, 0)])
+@pytest.mark.parametrize("circuit", ["qft", "diagheavy", "cxcp", "brickwork"])
+def test_diagonal_fusion_equals_unfused(P, kmax, kdiag, circuit):
+    # dense and diagonal blocks applied in order (diagonal ones by the
+    # oracle's diagonal gate) equal the unfused circuit; dense blocks are
+    # unitary and within kmax, diagonal ones unit-modulus and within kdiag
+    n = 9
+    gates = {"qft": lambda: W.qft(n), "diagheavy": lambda: W.diagonal_heavy(n, 80, kmax + 10 * kdiag),
+             "cxcp": lambda: W.random_cx_cp(n, 5, kdiag), "brickwork": lambda: W.brickwork(n, 5, kmax)}[circuit]()
+    x = W.random_basis_state(n, kdiag)
+    ref = oracle.run(n, gates, basis=x)
+    f = P.fuse(gates, kmax, kdiag)
+    blocks = f.blocks()
+    n_diag = sum(P.sv_fused_block_is_diagonal(f.f, i) for i in range(f.count))
+    f.free()
+    for targets, m in blocks:
+        assert list(targets) == sorted(targets)
+        if m.ndim == 1:
+            assert len(targets) <= kdiag
+            np.testing.assert_allclose(np.abs(m), 1.0, atol=1e-13)
+        else:
+            assert len(targets) <= max(kmax, 3 if circuit == "diagheavy" else 2)
+            np.testing.assert_allclose(m @ m.conj().T, np.eye(m.shape[0]), atol=1e-13)
+    assert n_diag == sum(1 for _, m in blocks if m.ndim == 1)
+    if kdiag == 0:
+        assert n_diag == 0
+    got = _apply_blocks_with_oracle(n, blocks, basis=x)
+    np.testing.assert_allclose(got, ref, atol=1e-12)
+
+
+def test_diagonal_fusion_off_is_the_plain_fuser(P):
+    gates = W.qft(10)
+    a, b = P.fuse(gates, 4), P.fuse(gates, 4, 0)
+    assert a.count == b.count
+    for (ta, ma), (tb, mb) in zip(a.blocks(), b.blocks()):
+        assert ta == tb
+        np.testing.assert_array_equal(ma, mb)
+
+
+def test_diagonal_fusion_cuts_qft_sweeps(P):
+    # the QFT's controlled phases are diagonal: with diagonal blocks the
+    # 30-qubit QFT needs far fewer sweeps than with dense blocks alone
+    gates = W.qft(30)
+    dense, both = P.fuse(gates, 5).count, P.fuse(gates, 5, 10).count
+    assert both < 0.6 * dense
+
+
+def test_diagonal_fusion_rejects_bad_sizes(P):
+    gates = W.qft(4)
+    for kd in (-1, 11):
+        with pytest.raises(P.SVError):
+            P.fuse(gates, 4, kd)
 
 
 def test_fusion_reduces_sweeps_on_brickwork(P):

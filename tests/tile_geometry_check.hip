@@ -115,7 +115,9 @@ int main()
     struct Shape {
         int tb, k, min_L;
     };
-    const Shape shapes[] = {{12, 4, 7}, {12, 5, 7}, {13, 5, 7}, {11, 5, 6}, {12, 5, 6}, {13, 6, 7}, {12, 6, 6}};
+    const Shape shapes[] = {{12, 4, 7}, {12, 5, 7}, {13, 5, 7}, {11, 5, 6}, {12, 5, 6}, {13, 6, 7}, {12, 6, 6},
+                            // the permutation-gate tiles (per-lane addresses: any run width)
+                            {12, 1, 0}, {12, 2, 0}, {12, 3, 0}, {12, 6, 0}, {11, 1, 0}, {11, 3, 0}, {11, 6, 0}};
     std::mt19937 rng(7);
     int cases = 0;
     for (const Shape& sh : shapes)

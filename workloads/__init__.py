@@ -170,6 +170,31 @@ def random_dense_circuit(n: int, n_gates: int, kmax: int, seed: int, with_contro
     return ops
 
 
+def diagonal_heavy(n: int, count: int, seed: int) -> list:
+    """`count` random gates, two thirds of them diagonal: U3, CZ, CP, Z, CX
+    and random diagonal unitaries on 1-3 qubits (as "mat" gates), each kind
+    equally likely, on random qubits."""
+    rng = np.random.default_rng(seed)
+    gates = []
+    for _ in range(count):
+        kind = rng.integers(0, 6)
+        qs = [int(q) for q in rng.permutation(n)]
+        if kind == 0:
+            gates.append(Gate("u3", (qs[0],), tuple(float(a) for a in rng.uniform(0, 2 * np.pi, 3))))
+        elif kind == 1:
+            gates.append(Gate("cz", (qs[0], qs[1]), ()))
+        elif kind == 2:
+            gates.append(Gate("cp", (qs[0], qs[1]), (float(rng.uniform(0, 2 * np.pi)),)))
+        elif kind == 3:
+            gates.append(Gate("z", (qs[0],), ()))
+        elif kind == 4:
+            gates.append(Gate("cx", (qs[0], qs[1]), ()))
+        else:
+            k = int(rng.integers(1, 4))
+            gates.append(Gate("mat", tuple(qs[:k]), np.diag(np.exp(1j * rng.uniform(0, 2 * np.pi, 1 << k)))))
+    return gates
+
+
 def random_basis_state(n: int, seed: int) -> int:
     rng = np.random.default_rng(seed)
     return int(rng.integers(0, 1 << n, dtype=np.uint64)) if n < 64 else 0
