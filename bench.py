@@ -106,6 +106,8 @@ def parse():
     ap.add_argument("--gate-sweep", action="store_true",
                     help="also time single k-qubit gates (k = 1..6) on random target sets, both dtypes")
     ap.add_argument("--sweep-sets", type=int, default=100)
+    ap.add_argument("--no-diagonal", action="store_true",
+                    help="skip the diagonal / permutation gate leg (and the QFT with diagonal fusion)")
     ap.add_argument("--large", action="store_true",
                     help="also time the fused depth-12 random CNOT/CP circuit on 34 qubits (complex64) and "
                          "33 qubits (complex128): 128 GiB states")
@@ -392,6 +394,56 @@ def gate_sweep(P, W, torch, H, n, sets, reps=3, warm=3, warm_k5=10):
     return out
 
 
+def diagonal_leg(P, W, torch, H, n, reps=10):
+    """Generalized permutation gates at n qubits on a dense state: diagonal
+    gates on 2 and 10 targets (random phases) and a permutation on 3 targets,
+    HBM GB/s over `reps` back-to-back sweeps each (HIP events on the handle's
+    stream); then the n-qubit QFT fused with dense blocks only (k <= 5)
+    against dense plus diagonal blocks (k <= 5, diagonal k <= 10): sweeps and
+    apply time of one timed pass after one untimed pass."""
+    import numpy as np
+    out = {}
+    rng = np.random.default_rng(17)
+    for dt, ab in (("c64", 8), ("c128", 16)):
+        st = P.State(H, n, dt)
+        st.run(W.brickwork(n, 1, 13))
+        sweep = 2 * (1 << n) * ab
+        res = {}
+        for label, perm, targets in (("diag_k2", None, (3, 17)), ("diag_k10", None, tuple(range(0, 30, 3))[:10]),
+                                     ("perm_k3", [int(p) for p in rng.permutation(8)], (2, 11, 25))):
+            diag = np.exp(1j * rng.uniform(0, 2 * np.pi, 1 << len(targets)))
+            for _ in range(2):
+                st.apply_gen_permutation(perm, diag, targets)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(H.stream)
+            for _ in range(reps):
+                st.apply_gen_permutation(perm, diag, targets)
+            e1.record(H.stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            res[label] = {"avg_ms": round(ms, 3), "GBps": round(sweep / (ms * 1e-3) / 1e9, 1)}
+        gates = W.qft(n)
+        for label, kd in (("qft_dense_only", 0), ("qft_dense_and_diagonal", 10)):
+            f = P.fuse(gates, 5, kd)
+            ndiag = sum(1 for _, m in f.blocks() if m.ndim == 1)
+            P.sv_apply_fused(st.s, f.f)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(H.stream)
+            P.sv_apply_fused(st.s, f.f)
+            e1.record(H.stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            res[label] = {"sweeps": f.count, "diagonal_sweeps": ndiag, "apply_ms": round(ms, 2),
+                          "GBps": round(f.count * sweep / (ms * 1e-3) / 1e9, 1)}
+            f.free()
+        res["qft_speedup"] = round(res["qft_dense_only"]["apply_ms"] / res["qft_dense_and_diagonal"]["apply_ms"], 2)
+        out[dt] = res
+        st.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
+
+
 def large_leg(P, W, torch, H):
     """The depth-12 random CNOT/CP circuit (U3 on every qubit, then a random
     matching into far-apart CNOT or CP pairs, per layer) fused to k <= 5
@@ -657,6 +709,11 @@ def main():
         line["serving"] = serving_leg(P, W, torch, args.serve_requests, args.serve_slots)
     line["copy_ceiling_GBps"] = round(copy_ceiling(torch, n), 1)
     line["frac_of_copy_ceiling"] = round(r64["fused_gate_GBps"] / line["copy_ceiling_GBps"], 4)
+    if not args.no_diagonal:
+        print("[bench] diagonal / permutation leg", file=sys.stderr, flush=True)
+        HD = P.Handle()
+        line["diagonal_gates"] = diagonal_leg(P, W, torch, HD, n)
+        HD.close()
     if args.large:
         print("[bench] large-state leg", file=sys.stderr, flush=True)
         HL = P.Handle()

@@ -1271,6 +1271,8 @@ __global__ __launch_bounds__(kDiagThreads) void k_apply_diag(typename Cx<R>::T* 
                 const float4 w = gload(reinterpret_cast<const float4*>(psi + at[u]));
                 x[u][0] = T{w.x, w.y};
                 x[u][APV - 1] = T{w.z, w.w};
+            } else if constexpr (sizeof(T) == 16) {
+                x[u][0] = gload(psi + at[u]);
             } else {
                 x[u][0] = psi[at[u]];
             }
@@ -1283,6 +1285,8 @@ __global__ __launch_bounds__(kDiagThreads) void k_apply_diag(typename Cx<R>::T* 
         for (int e = 0; e < APV; ++e) x[u][e] = cmul(tab[diag_row(at[u] + e, a)], x[u][e]);
         if constexpr (APV == 2) {
             gstore(reinterpret_cast<float4*>(psi + at[u]), float4{x[u][0].x, x[u][0].y, x[u][APV - 1].x, x[u][APV - 1].y});
+        } else if constexpr (sizeof(T) == 16) {
+            gstore(psi + at[u], x[u][0]);
         } else {
             psi[at[u]] = x[u][0];
         }
@@ -1311,16 +1315,38 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_gperm(typename Cx<R>::T* 
     if (tid < k) lpos[tid] = 31 - __clz(a.lds_off[1 << tid]);
     const uint64_t base = tile_base(blockIdx.x, a);
     const uint64_t mask = (uint64_t(1) << a.L) - 1;
-    for (int e = tid; e < kAmps; e += kTileThreads)
-        lds[e] = psi[base + deposit_bits(uint32_t(e >> a.L), a.hi_pos, a.n_hi) + (uint64_t(e) & mask)];
+    // 16-byte accesses: amplitude pairs (e, e + 1), e even, for complex64
+    // (the runs are at least 2^6 amplitudes long, so a pair never straddles
+    // two runs), single amplitudes for complex128
+    constexpr int APV = sizeof(T) == 8 ? 2 : 1;
+    constexpr int kVecs = kAmps / APV / kTileThreads;
+    auto glob = [&](int e) { return base + deposit_bits(uint32_t(e >> a.L), a.hi_pos, a.n_hi) + (uint64_t(e) & mask); };
+    using V = typename std::conditional<APV == 2, float4, double2>::type;
+    V v[kVecs];
+#pragma unroll
+    for (int u = 0; u < kVecs; ++u) v[u] = gload(reinterpret_cast<const V*>(psi + glob((u * kTileThreads + tid) * APV)));
+#pragma unroll
+    for (int u = 0; u < kVecs; ++u) reinterpret_cast<V*>(lds)[u * kTileThreads + tid] = v[u];
     __syncthreads();
     const int full = a.lds_off[(1 << k) - 1];
-    for (int e = tid; e < kAmps; e += kTileThreads) {
+    auto out = [&](int e) {
         int r = 0;
         for (int b = 0; b < k; ++b) r |= ((e >> lpos[b]) & 1) << b;
-        const int src = (e & ~full) + a.lds_off[ptab[r]];
-        psi[base + deposit_bits(uint32_t(e >> a.L), a.hi_pos, a.n_hi) + (uint64_t(e) & mask)] = cmul(dtab[r], lds[src]);
+        return cmul(dtab[r], lds[(e & ~full) + a.lds_off[ptab[r]]]);
+    };
+#pragma unroll
+    for (int u = 0; u < kVecs; ++u) {
+        const int e = (u * kTileThreads + tid) * APV;
+        if constexpr (APV == 2) {
+            const T lo = out(e), hi = out(e + 1);
+            v[u] = V{lo.x, lo.y, hi.x, hi.y};
+        } else {
+            v[u] = out(e);
+        }
     }
+#pragma unroll
+    for (int u = 0; u < kVecs; ++u)
+        gstore(reinterpret_cast<V*>(psi + glob((u * kTileThreads + tid) * APV)), v[u]);
 }
 
 }  // namespace
