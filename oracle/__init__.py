@@ -49,6 +49,15 @@ def lib():
         L.orc_apply.restype = ctypes.c_int
         L.orc_apply_gperm.argtypes = [vp, ctypes.c_int, vp, vp, ip, ctypes.c_int, ip, ip, ctypes.c_int]
         L.orc_apply_gperm.restype = ctypes.c_int
+        L.orc_apply_pauli_rotation.argtypes = [vp, ctypes.c_int, ctypes.c_double, ip, ctypes.c_char_p, ctypes.c_int,
+                                               ip, ip, ctypes.c_int]
+        L.orc_apply_pauli_rotation.restype = ctypes.c_int
+        L.orc_measure_probs.argtypes = [vp, ctypes.c_int, ip, ctypes.c_int, dp]
+        L.orc_measure_probs.restype = ctypes.c_int
+        L.orc_collapse.argtypes = [vp, ctypes.c_int, ip, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_double]
+        L.orc_collapse.restype = ctypes.c_int
+        L.orc_expect_matrix.argtypes = [vp, ctypes.c_int, vp, ip, ctypes.c_int, dp]
+        L.orc_expect_matrix.restype = ctypes.c_int
         L.orc_norm.argtypes = [vp, ctypes.c_int]
         L.orc_norm.restype = ctypes.c_double
         L.orc_expect_pauli.argtypes = [vp, ctypes.c_int, ip, ctypes.c_char_p, ctypes.c_int, dp]
@@ -148,6 +157,86 @@ def apply_gperm(psi: np.ndarray, perm, diag, targets, controls=(), cvals=None, a
                                _ints(targets), k, _ints(controls), cv, len(controls))
     if rc != 0:
         raise ValueError("invalid generalized permutation gate arguments")
+
+
+def apply_pauli_rotation(psi: np.ndarray, theta: float, term, controls=(), cvals=None) -> None:
+    """psi <- exp(i theta P) psi for the Pauli string term = [(qubit, op)],
+    on the indices whose controls hold their values (default 1)."""
+    n = _nqubits(psi)
+    qs = [q for q, _ in term]
+    ops = "".join(o for _, o in term).encode()
+    cv = None if cvals is None else _ints(cvals)
+    rc = lib().orc_apply_pauli_rotation(psi.ctypes.data, n, float(theta), _ints(qs), ops, len(qs), _ints(controls), cv,
+                                        len(controls))
+    if rc != 0:
+        raise ValueError("invalid Pauli rotation arguments")
+
+
+def measure_probs(psi: np.ndarray, qubits) -> np.ndarray:
+    """Unnormalised probabilities of the 2^m outcomes of measuring qubits
+    (bit a of an outcome = the value of qubits[a])."""
+    n = _nqubits(psi)
+    out = np.zeros(1 << len(qubits), dtype=np.float64)
+    rc = lib().orc_measure_probs(psi.ctypes.data, n, _ints(qubits), len(qubits),
+                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != 0:
+        raise ValueError("invalid measurement arguments")
+    return out
+
+
+def zbasis_probs(psi: np.ndarray, qubits) -> tuple:
+    """(even, odd): unnormalised probabilities of the two eigenvalues +1
+    (even parity of the measured bits) and -1 of the Z-product on qubits."""
+    p = measure_probs(psi, qubits)
+    par = np.array([bin(b).count("1") & 1 for b in range(p.size)])
+    return float(p[par == 0].sum()), float(p[par == 1].sum())
+
+
+def collapse(psi: np.ndarray, qubits, outcome: int = 0, norm: float = 1.0, parity: int | None = None) -> None:
+    """Keep the amplitudes whose bits at qubits spell outcome (or, with
+    parity 0/1, whose bits at qubits have that parity), divided by
+    sqrt(norm); zero all others."""
+    n = _nqubits(psi)
+    rc = lib().orc_collapse(psi.ctypes.data, n, _ints(qubits), len(qubits), int(outcome),
+                            -1 if parity is None else int(parity), float(norm))
+    if rc != 0:
+        raise ValueError("invalid collapse arguments")
+
+
+def measure_zbasis(psi: np.ndarray, qubits, randnum: float, collapse_state: bool = True) -> int:
+    """Parity outcome of measuring the Z-product on qubits with the uniform
+    randnum in [0, 1): 0 (eigenvalue +1) if randnum * N < P_even, else 1;
+    with collapse_state the state is projected and renormalised."""
+    pe, po = zbasis_probs(psi, qubits)
+    parity = 0 if randnum * (pe + po) < pe else 1
+    if collapse_state:
+        collapse(psi, qubits, norm=pe if parity == 0 else po, parity=parity)
+    return parity
+
+
+def batch_measure(psi: np.ndarray, qubits, randnum: float, collapse_state: bool = True) -> int:
+    """Joint outcome of measuring qubits with the uniform randnum in [0, 1):
+    the smallest b with randnum * N < C_b, C_b the running sum of the
+    outcome probabilities in outcome order; with collapse_state the state is
+    projected onto b and renormalised."""
+    p = measure_probs(psi, qubits)
+    c = np.cumsum(p)
+    r = randnum * c[-1]
+    b = int(np.searchsorted(c, r, side="right"))
+    if collapse_state:
+        collapse(psi, qubits, outcome=b, norm=float(p[b]))
+    return b
+
+
+def expect_matrix(psi: np.ndarray, matrix, targets) -> complex:
+    """<psi| M |psi> / <psi|psi> for the dense observable M on targets."""
+    n = _nqubits(psi)
+    m = np.ascontiguousarray(matrix, dtype=np.complex128)
+    out = (ctypes.c_double * 3)()
+    rc = lib().orc_expect_matrix(psi.ctypes.data, n, m.ctypes.data, _ints(targets), len(targets), out)
+    if rc != 0:
+        raise ValueError("invalid expectation arguments")
+    return complex(out[0], out[1])
 
 
 def apply_gate(psi: np.ndarray, gate) -> None:

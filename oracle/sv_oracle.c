@@ -314,6 +314,142 @@ int orc_expect_pauli(const double* psi_ri, int n, const int* qubits, const char*
  * bit_ordering == NULL returns the full index.  `cdf_out`, if not NULL,
  * receives C (2^n doubles).
  */
+/* ------------------------------------------------------------------------ */
+/* Pauli rotation (Table I: rotation of the state vector by a Pauli string): */
+/* psi <- exp(i theta P) psi = cos(theta) psi + i sin(theta) P psi, with P   */
+/* the product of the single-qubit Paulis of the string (the identity on    */
+/* every other qubit), applied to the indices whose control bits equal the  */
+/* control values; every other amplitude is unchanged.                      */
+/* ------------------------------------------------------------------------ */
+
+int orc_apply_pauli_rotation(double* psi_ri, int n, double theta, const int* qubits, const char* ops, int nops,
+                             const int* controls, const int* cvals, int nc)
+{
+    static const double X[8] = {0, 0, 1, 0, 1, 0, 0, 0};
+    static const double Y[8] = {0, 0, 0, -1, 0, 1, 0, 0};
+    static const double Z[8] = {1, 0, 0, 0, 0, 0, -1, 0};
+    if (n < 1 || n > 40 || nops < 0 || nc < 0) return ORC_BAD;
+    uint64_t used = 0, cmask = 0, cval = 0;
+    for (int a = 0; a < nops; ++a) {
+        if (qubits[a] < 0 || qubits[a] >= n || (used >> qubits[a] & 1)) return ORC_BAD;
+        used |= (uint64_t)1 << qubits[a];
+    }
+    for (int a = 0; a < nc; ++a) {
+        uint64_t b = (uint64_t)1 << controls[a];
+        if (controls[a] < 0 || controls[a] >= n || (used & b)) return ORC_BAD;
+        used |= b;
+        cmask |= b;
+        if (cvals == NULL || cvals[a]) cval |= b;
+    }
+    int64_t dim = (int64_t)1 << n;
+    cplx* psi = (cplx*)psi_ri;
+    cplx* phi = (cplx*)malloc(sizeof(cplx) * (size_t)dim);
+    if (!phi) return ORC_BAD;
+    memcpy(phi, psi, sizeof(cplx) * (size_t)dim);
+    for (int a = 0; a < nops; ++a) {
+        const double* m = NULL;
+        if (ops[a] == 'X') m = X;
+        else if (ops[a] == 'Y') m = Y;
+        else if (ops[a] == 'Z') m = Z;
+        else if (ops[a] == 'I') continue;
+        else { free(phi); return ORC_BAD; }
+        orc_apply((double*)phi, n, m, &qubits[a], 1, NULL, NULL, 0);
+    }
+    const double c = cos(theta), sn = sin(theta);
+    for (int64_t i = 0; i < dim; ++i) {
+        if (((uint64_t)i & cmask) != cval) continue;
+        psi[i] = c * psi[i] + (I * sn) * phi[i];
+    }
+    free(phi);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Measurement (Table I: measurement on a Z-product basis and batched        */
+/* single-qubit measurement, with probability and collapse as separate     */
+/* steps).  probs[b] = sum of |psi_i|^2 over the indices i whose bits at    */
+/* qubits[0..m-1] spell b (bit a of b = bit qubits[a] of i), unnormalised,  */
+/* each bin a compensated sum in index order.                               */
+/* ------------------------------------------------------------------------ */
+
+int orc_measure_probs(const double* psi_ri, int n, const int* qubits, int m, double* probs)
+{
+    if (n < 1 || n > 40 || m < 1 || m > 20 || m > n) return ORC_BAD;
+    uint64_t used = 0;
+    for (int a = 0; a < m; ++a) {
+        if (qubits[a] < 0 || qubits[a] >= n || (used >> qubits[a] & 1)) return ORC_BAD;
+        used |= (uint64_t)1 << qubits[a];
+    }
+    const cplx* psi = (const cplx*)psi_ri;
+    int64_t dim = (int64_t)1 << n;
+    int64_t bins = (int64_t)1 << m;
+    ksum* acc = (ksum*)calloc((size_t)bins, sizeof(ksum));
+    if (!acc) return ORC_BAD;
+    for (int64_t i = 0; i < dim; ++i) {
+        int64_t b = 0;
+        for (int a = 0; a < m; ++a) b |= (int64_t)((i >> qubits[a]) & 1) << a;
+        const double re = creal(psi[i]), im = cimag(psi[i]);
+        ks_add(&acc[b], re * re + im * im);
+    }
+    for (int64_t b = 0; b < bins; ++b) probs[b] = ks_val(&acc[b]);
+    free(acc);
+    return ORC_OK;
+}
+
+/* Collapse onto one outcome: amplitudes whose bits at qubits spell outcome  */
+/* (parity < 0), or whose bits at qubits have that parity (parity 0 or 1),  */
+/* are divided by sqrt(norm); all others become 0.                          */
+int orc_collapse(double* psi_ri, int n, const int* qubits, int m, uint64_t outcome, int parity, double norm)
+{
+    if (n < 1 || n > 40 || m < 1 || m > n || !(norm > 0.0)) return ORC_BAD;
+    uint64_t used = 0;
+    for (int a = 0; a < m; ++a) {
+        if (qubits[a] < 0 || qubits[a] >= n || (used >> qubits[a] & 1)) return ORC_BAD;
+        used |= (uint64_t)1 << qubits[a];
+    }
+    cplx* psi = (cplx*)psi_ri;
+    int64_t dim = (int64_t)1 << n;
+    const double s = 1.0 / sqrt(norm);
+    for (int64_t i = 0; i < dim; ++i) {
+        uint64_t b = 0;
+        int par = 0;
+        for (int a = 0; a < m; ++a) {
+            const int bit = (int)((i >> qubits[a]) & 1);
+            b |= (uint64_t)bit << a;
+            par ^= bit;
+        }
+        const int keep = parity < 0 ? (b == outcome) : (par == parity);
+        psi[i] = keep ? s * psi[i] : 0.0;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Expectation of a dense k-qubit observable M (Table I: expectation with a  */
+/* dense matrix observable): <psi| M |psi> / <psi|psi>, complex, with M on  */
+/* targets (targets[0] = matrix LSB).  out = (re, im, <psi|psi>).           */
+/* ------------------------------------------------------------------------ */
+
+int orc_expect_matrix(const double* psi_ri, int n, const double* m_ri, const int* targets, int k, double* out)
+{
+    int64_t dim = (int64_t)1 << n;
+    double* phi = (double*)malloc(sizeof(cplx) * (size_t)dim);
+    if (!phi) return ORC_BAD;
+    memcpy(phi, psi_ri, sizeof(cplx) * (size_t)dim);
+    if (orc_apply(phi, n, m_ri, targets, k, NULL, NULL, 0) != ORC_OK) {
+        free(phi);
+        return ORC_BAD;
+    }
+    double re, im;
+    inner((const cplx*)psi_ri, (const cplx*)phi, dim, &re, &im);
+    double nrm = orc_norm(psi_ri, n);
+    free(phi);
+    out[0] = re / nrm;
+    out[1] = im / nrm;
+    out[2] = nrm;
+    return ORC_OK;
+}
+
 int orc_sample(const double* psi_ri, int n, const double* u, int64_t nshots,
                const int* bit_ordering, int nbits, uint64_t* out, double* cdf_out)
 {

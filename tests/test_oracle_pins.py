@@ -433,3 +433,129 @@ def test_gperm_unitary_round_trip_and_rejects_bad_input():
         oracle.apply_gperm(psi, None, diag[:4], targets)
     with pytest.raises(ValueError):
         oracle.apply_gperm(psi, None, diag, (1, 1, 2))
+
+
+# --------------------------------------------------------- Pauli rotation
+
+@pytest.mark.parametrize("seed", range(6))
+def test_pauli_rotation_matches_matrix_exponential(seed):
+    # exp(i theta P) against scipy's expm of the Kronecker-built Pauli string,
+    # with controls embedded by Kronecker projectors
+    rng = np.random.default_rng(seed)
+    n = 5
+    qs = [int(q) for q in rng.permutation(n)]
+    k = int(rng.integers(1, 4))
+    term = [(qs[a], "IXYZ"[int(rng.integers(0, 4))]) for a in range(k)]
+    nc = int(rng.integers(0, 2))
+    controls = tuple(qs[k:k + nc])
+    cvals = [int(v) for v in rng.integers(0, 2, nc)]
+    theta = float(rng.uniform(-3, 3))
+    psi = _rand_state(n, rng)
+    if nc:
+        local = expm(1j * theta * pauli_operator([(a, o) for a, (_, o) in enumerate(term)], k))
+        full = embed(local, tuple(q for q, _ in term), n, controls, cvals)
+    else:
+        full = expm(1j * theta * pauli_operator(term, n))
+    ref = full @ psi
+    oracle.apply_pauli_rotation(psi, theta, term, controls, cvals if nc else None)
+    np.testing.assert_allclose(psi, ref, atol=1e-12)
+
+
+def test_pauli_rotation_closed_forms():
+    # exp(i t Z)|0> = e^{it}|0>; exp(i t X)|0> = cos t|0> + i sin t|1>;
+    # exp(i t Y)|0> = cos t|0> - sin t|1>
+    t = 0.3
+    for op, a1 in (("Z", 0.0), ("X", 1j * math.sin(t)), ("Y", -math.sin(t))):
+        psi = oracle.basis_state(1)
+        oracle.apply_pauli_rotation(psi, t, [(0, op)])
+        a0 = np.exp(1j * t) if op == "Z" else math.cos(t)
+        np.testing.assert_allclose(psi, [a0, a1], atol=1e-15)
+
+
+# -------------------------------------------------------------- measurement
+
+def test_measure_probs_ghz_product_and_ordering():
+    n = 4
+    ghz = oracle.run(n, W.ghz(n))
+    np.testing.assert_allclose(oracle.measure_probs(ghz, [0, 2]), [0.5, 0, 0, 0.5], atol=1e-15)
+    # one U3 layer: P(q = 1) = sin^2(theta_q / 2), independent across qubits
+    th = [0.4, 1.1, 2.0]
+    psi = oracle.run(3, [W.Gate("u3", (q,), (th[q], 0.3, 0.2)) for q in range(3)])
+    p = oracle.measure_probs(psi, [2, 0])
+    s2 = [math.sin(t / 2) ** 2 for t in th]
+    np.testing.assert_allclose(p, [(1 - s2[2]) * (1 - s2[0]), s2[2] * (1 - s2[0]), (1 - s2[2]) * s2[0], s2[2] * s2[0]],
+                               atol=1e-15)
+    # bit a of the outcome is qubits[a]: |100> measured on (2, 0) is outcome 1
+    np.testing.assert_allclose(oracle.measure_probs(oracle.basis_state(3, 4), [2, 0]), [0, 1, 0, 0])
+    rng = np.random.default_rng(2)
+    v = _rand_state(6, rng) * 1.7
+    assert abs(oracle.measure_probs(v, [5, 1, 3]).sum() - np.vdot(v, v).real) < 1e-13
+
+
+def _projector(qubits, bits, n):
+    # Kronecker product of |b><b| on the measured qubits
+    ops = [np.eye(2)] * n
+    for q, b in zip(qubits, bits):
+        ops[q] = np.diag([1.0 - b, float(b)])
+    full = np.array([[1.0 + 0j]])
+    for q in range(n - 1, -1, -1):
+        full = np.kron(full, ops[q])
+    return full
+
+
+def test_collapse_matches_projectors():
+    rng = np.random.default_rng(4)
+    n = 5
+    psi = _rand_state(n, rng)
+    qubits = (3, 0, 4)
+    p = oracle.measure_probs(psi, qubits)
+    for b in (0, 5, 6):
+        bits = [(b >> a) & 1 for a in range(3)]
+        ref = _projector(qubits, bits, n) @ psi / math.sqrt(p[b])
+        a = psi.copy()
+        oracle.collapse(a, qubits, outcome=b, norm=p[b])
+        np.testing.assert_allclose(a, ref, atol=1e-14)
+        assert abs(np.vdot(a, a).real - 1.0) < 1e-13
+    # parity collapse = (I + (-1)^par Z.Z.Z)/2 psi / sqrt(p_par)
+    pe, po = oracle.zbasis_probs(psi, qubits)
+    zzz = pauli_operator([(q, "Z") for q in qubits], n)
+    for par, pp in ((0, pe), (1, po)):
+        ref = 0.5 * (np.eye(1 << n) + (-1) ** par * zzz) @ psi / math.sqrt(pp)
+        a = psi.copy()
+        oracle.collapse(a, qubits, norm=pp, parity=par)
+        np.testing.assert_allclose(a, ref, atol=1e-14)
+
+
+def test_measurement_outcome_rules():
+    # Z parity on GHZ is always even; on |+> the split is at randnum = 1/2
+    ghz = oracle.run(4, W.ghz(4))
+    for r in (0.0, 0.5, 0.999):
+        assert oracle.measure_zbasis(ghz.copy(), [1, 3], r) == 0
+    plus = oracle.run(1, [W.Gate("h", (0,), ())])
+    assert oracle.measure_zbasis(plus.copy(), [0], 0.49) == 0
+    assert oracle.measure_zbasis(plus.copy(), [0], 0.51) == 1
+    # batched: probabilities (0.1, 0, 0.2, 0.7) -> upper-bound rule, never
+    # the zero-probability outcome
+    amp = np.sqrt(np.array([0.1, 0.0, 0.2, 0.7])).astype(np.complex128)
+    for r, want in ((0.05, 0), (0.1, 2), (0.29, 2), (0.3, 3), (0.999, 3)):
+        a = amp.copy()
+        assert oracle.batch_measure(a, [0, 1], r) == want
+        np.testing.assert_allclose(np.abs(a) ** 2, np.eye(4)[want], atol=1e-15)
+
+
+# ----------------------------------------------- dense observable expectation
+
+@pytest.mark.parametrize("seed", range(4))
+def test_expect_matrix_matches_kronecker(seed):
+    rng = np.random.default_rng(seed)
+    n = 5
+    k = int(rng.integers(1, 4))
+    targets = tuple(int(q) for q in rng.permutation(n)[:k])
+    m = rng.normal(size=(1 << k, 1 << k)) + 1j * rng.normal(size=(1 << k, 1 << k))
+    psi = _rand_state(n, rng) * 0.8
+    ref = np.vdot(psi, embed(m, targets, n) @ psi) / np.vdot(psi, psi)
+    got = oracle.expect_matrix(psi, m, targets)
+    assert abs(got - ref) < 1e-13
+    # a Pauli product as a matrix equals the Pauli expectation
+    term = [(targets[0], "Y")]
+    assert abs(oracle.expect_matrix(psi, PAULI["Y"], targets[:1]) - oracle.expect_pauli(psi, term)) < 1e-14
