@@ -300,11 +300,70 @@ sv_status_t sv_graph_create(sv_state_t s, sv_fused_t f, sv_graph_t* out);
 sv_status_t sv_graph_launch(sv_graph_t g);
 sv_status_t sv_graph_destroy(sv_graph_t g);
 
+/* --------------------------------------------------------- Pauli rotation */
+
+/*
+ * Rotation by a Pauli string (Table I): psi <- exp(i theta P) psi
+ * = cos(theta) psi + i sin(theta) P psi, P the product of the term's
+ * single-qubit Paulis ('I', 'X', 'Y', 'Z'; identity elsewhere), applied to
+ * the amplitudes whose controls (distinct, disjoint from the term's qubits)
+ * hold their values (NULL: all 1); all other amplitudes are unchanged.  One
+ * sweep: X/Y factors pair amplitude i with i XOR x, a Z-only string is a
+ * phase per amplitude.  Asynchronous.  SV_ERR_INVALID_VALUE for bad qubits,
+ * operators or controls, or a non-finite theta.
+ */
+sv_status_t sv_apply_pauli_rotation(sv_state_t s, double theta, const sv_pauli_term_t* term, const int32_t* controls,
+                                    const int32_t* control_values, int32_t n_controls);
+
+/* ------------------------------------------------------------ measurement */
+
+/*
+ * Measurement (Table I: on a Z-product basis and batched single-qubit
+ * measurement, with probability computation and collapse as separate
+ * steps).  Outcome b of measuring qubits[0..m-1] has bit a equal to the
+ * value of qubits[a].  Probabilities are unnormalised sums of |psi_i|^2 in
+ * FP64, in a fixed order (bitwise reproducible); the calls that return them
+ * block.
+ *   sv_measure_probabilities: probs[b] for the 2^m outcomes,
+ *     1 <= m <= SV_MAX_TARGETS;
+ *   sv_zbasis_probabilities: the sums over indices whose measured bits have
+ *     even / odd parity (eigenvalue +1 / -1 of the Z-product), any m <= n;
+ *   sv_collapse: keeps the amplitudes of outcome `outcome`, divided by
+ *     sqrt(norm), sets every other to 0 (norm > 0: the outcome's
+ *     probability makes the result a unit vector);
+ *   sv_collapse_zbasis: the same for the amplitudes of parity `parity`;
+ *   sv_measure_zbasis: parity 0 if randnum * (p_even + p_odd) < p_even,
+ *     else 1, into *parity; collapses onto it if collapse != 0;
+ *   sv_batch_measure: the first outcome b (in outcome order) whose running
+ *     sum of probabilities exceeds randnum times their total, into
+ *     *outcome (never a zero-probability outcome); collapses onto it if
+ *     collapse != 0.
+ * randnum in [0, 1).  Collapse is one write sweep that reads only vectors
+ * holding a kept amplitude (asynchronous on its own).
+ */
+sv_status_t sv_measure_probabilities(sv_state_t s, const int32_t* qubits, int32_t m, double* probs);
+sv_status_t sv_zbasis_probabilities(sv_state_t s, const int32_t* qubits, int32_t m, double* p_even, double* p_odd);
+sv_status_t sv_collapse(sv_state_t s, const int32_t* qubits, int32_t m, uint64_t outcome, double norm);
+sv_status_t sv_collapse_zbasis(sv_state_t s, const int32_t* qubits, int32_t m, int32_t parity, double norm);
+sv_status_t sv_measure_zbasis(sv_state_t s, const int32_t* qubits, int32_t m, double randnum, int32_t collapse,
+                              int32_t* parity);
+sv_status_t sv_batch_measure(sv_state_t s, const int32_t* qubits, int32_t m, double randnum, int32_t collapse,
+                             uint64_t* outcome);
+
 /* ------------------------------------------------------------- reductions */
 
 /* *out = sum_i |psi_i|^2 accumulated in FP64 in a fixed order (bitwise
  * reproducible for a given state).  Blocks. */
 sv_status_t sv_norm(sv_state_t s, double* out);
+
+/*
+ * Expectation of a dense observable (Table I: expectation with a dense matrix
+ * observable): out[0] + i out[1] = <psi| M |psi> / <psi|psi> for the
+ * 2^k x 2^k complex128 row-major M on targets (targets[0] = matrix LSB),
+ * 1 <= k <= 5.  One read sweep, FP64 arithmetic and sums in a fixed order.
+ * Blocks.
+ */
+sv_status_t sv_expect_matrix(sv_state_t s, const double* matrix, const int32_t* targets, int32_t k, double* out);
 
 /* Scales the state by 1/sqrt(norm) (FP64 norm, scale applied in the state's
  * precision).  *norm_out (may be NULL) receives the norm before scaling. */

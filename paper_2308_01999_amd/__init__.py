@@ -87,6 +87,14 @@ _SIGS = {
     "sv_renormalize": [_vp, _pd],
     "sv_expect_pauli": [_vp, ctypes.POINTER(sv_pauli_term_t), _i32, _pd],
     "sv_sample": [_vp, _pd, _i64, _pi32, _i32, _pu64],
+    "sv_apply_pauli_rotation": [_vp, ctypes.c_double, ctypes.POINTER(sv_pauli_term_t), _pi32, _pi32, _i32],
+    "sv_measure_probabilities": [_vp, _pi32, _i32, _pd],
+    "sv_zbasis_probabilities": [_vp, _pi32, _i32, _pd, _pd],
+    "sv_collapse": [_vp, _pi32, _i32, _u64, ctypes.c_double],
+    "sv_collapse_zbasis": [_vp, _pi32, _i32, _i32, ctypes.c_double],
+    "sv_measure_zbasis": [_vp, _pi32, _i32, ctypes.c_double, _i32, _pi32],
+    "sv_batch_measure": [_vp, _pi32, _i32, ctypes.c_double, _i32, _pu64],
+    "sv_expect_matrix": [_vp, _pd, _pi32, _i32, _pd],
     "sv_copy_to_host": [_vp, _vp, _u64, _u64],
     "sv_copy_from_host": [_vp, _vp, _u64, _u64],
     "sv_batch_create": [_vp, _i32, _pi32, _pi32, _pi32, _pi32, _pd, _pi32, _pu64, _i32, ctypes.POINTER(_vp)],
@@ -372,6 +380,56 @@ def sv_expect_pauli(s: int, terms) -> np.ndarray:
     out = np.zeros(max(1, len(terms)), dtype=np.float64)
     _check(_L.sv_expect_pauli(_vp(s), arr, len(terms), _dptr(out)))
     return out[: len(terms)]
+
+
+def sv_apply_pauli_rotation(s: int, theta: float, term, controls=(), control_values=None) -> None:
+    """psi <- exp(i theta P) psi, term = [(qubit, 'I'|'X'|'Y'|'Z'), ...]."""
+    q = _i32arr([qq for qq, _ in term])
+    ops = "".join(o for _, o in term).encode()
+    t = sv_pauli_term_t(len(term), q, ops)
+    cv = None if control_values is None else _i32arr(control_values)
+    _check(_L.sv_apply_pauli_rotation(_vp(s), float(theta), ctypes.byref(t), _i32arr(controls), cv, len(controls)))
+
+
+def sv_measure_probabilities(s: int, qubits) -> np.ndarray:
+    out = np.zeros(1 << len(qubits), dtype=np.float64)
+    _check(_L.sv_measure_probabilities(_vp(s), _i32arr(qubits), len(qubits), _dptr(out)))
+    return out
+
+
+def sv_zbasis_probabilities(s: int, qubits) -> tuple:
+    e, o = ctypes.c_double(), ctypes.c_double()
+    _check(_L.sv_zbasis_probabilities(_vp(s), _i32arr(qubits), len(qubits), ctypes.byref(e), ctypes.byref(o)))
+    return e.value, o.value
+
+
+def sv_collapse(s: int, qubits, outcome: int, norm: float) -> None:
+    _check(_L.sv_collapse(_vp(s), _i32arr(qubits), len(qubits), int(outcome), float(norm)))
+
+
+def sv_collapse_zbasis(s: int, qubits, parity: int, norm: float) -> None:
+    _check(_L.sv_collapse_zbasis(_vp(s), _i32arr(qubits), len(qubits), int(parity), float(norm)))
+
+
+def sv_measure_zbasis(s: int, qubits, randnum: float, collapse: bool = True) -> int:
+    p = _i32()
+    _check(_L.sv_measure_zbasis(_vp(s), _i32arr(qubits), len(qubits), float(randnum), int(bool(collapse)),
+                                ctypes.byref(p)))
+    return p.value
+
+
+def sv_batch_measure(s: int, qubits, randnum: float, collapse: bool = True) -> int:
+    o = _u64()
+    _check(_L.sv_batch_measure(_vp(s), _i32arr(qubits), len(qubits), float(randnum), int(bool(collapse)),
+                               ctypes.byref(o)))
+    return o.value
+
+
+def sv_expect_matrix(s: int, matrix, targets) -> complex:
+    m = _mat(matrix)
+    out = np.zeros(2, dtype=np.float64)
+    _check(_L.sv_expect_matrix(_vp(s), m.ctypes.data_as(_pd), _i32arr(targets), len(targets), _dptr(out)))
+    return complex(out[0], out[1])
 
 
 def sv_sample(s: int, uniforms, bit_ordering=None) -> np.ndarray:

@@ -740,6 +740,186 @@ sv_status_t sv_expect_pauli(sv_state_t s, const sv_pauli_term_t* terms, int32_t 
     });
 }
 
+}  // extern "C"
+
+namespace sv {
+namespace {
+
+// Distinct measured qubits of a state: their mask.
+uint64_t measured_mask(const sv_state_s* s, const int32_t* qubits, int m, int max_m)
+{
+    SV_CHECK(m >= 1 && m <= max_m && m <= s->n, "bad number of measured qubits");
+    SV_CHECK(qubits != nullptr, "qubits is NULL");
+    uint64_t mask = 0;
+    for (int a = 0; a < m; ++a) {
+        SV_CHECK(qubits[a] >= 0 && qubits[a] < s->n, "measured qubit out of range");
+        SV_CHECK(!((mask >> qubits[a]) & 1), "measured qubit repeated");
+        mask |= uint64_t(1) << qubits[a];
+    }
+    return mask;
+}
+
+uint64_t outcome_bits(const int32_t* qubits, int m, uint64_t outcome)
+{
+    uint64_t o = 0;
+    for (int a = 0; a < m; ++a)
+        if ((outcome >> a) & 1) o |= uint64_t(1) << qubits[a];
+    return o;
+}
+
+PauliMasks pauli_masks(const sv_state_s* s, const sv_pauli_term_t& T, uint64_t* used)
+{
+    PauliMasks pm;
+    SV_CHECK(T.n_ops >= 0 && T.n_ops <= s->n, "term has a bad number of operators");
+    SV_CHECK(T.n_ops == 0 || (T.qubits && T.ops), "term has NULL arrays");
+    for (int a = 0; a < T.n_ops; ++a) {
+        const int q = T.qubits[a];
+        SV_CHECK(q >= 0 && q < s->n, "Pauli qubit out of range");
+        SV_CHECK(!((*used >> q) & 1), "Pauli term names a qubit twice");
+        *used |= uint64_t(1) << q;
+        const uint64_t b = uint64_t(1) << q;
+        switch (T.ops[a]) {
+            case 'I': break;
+            case 'X': pm.x |= b; break;
+            case 'Y': pm.x |= b; pm.z |= b; pm.ny++; break;
+            case 'Z': pm.z |= b; break;
+            default: SV_CHECK(false, "Pauli operator must be one of I, X, Y, Z");
+        }
+    }
+    return pm;
+}
+
+}  // namespace
+}  // namespace sv
+
+extern "C" {
+
+sv_status_t sv_apply_pauli_rotation(sv_state_t s, double theta, const sv_pauli_term_t* term, const int32_t* controls,
+                                    const int32_t* control_values, int32_t n_controls)
+{
+    return guarded([&] {
+        check_state(s);
+        SV_CHECK(term != nullptr, "term is NULL");
+        SV_CHECK(std::isfinite(theta), "theta is not finite");
+        uint64_t used = 0;
+        const PauliMasks pm = pauli_masks(s, *term, &used);
+        SV_CHECK(n_controls >= 0 && (n_controls == 0 || controls != nullptr), "bad controls");
+        for (int a = 0; a < n_controls; ++a) {
+            const int q = controls[a];
+            SV_CHECK(q >= 0 && q < s->n, "control out of range");
+            SV_CHECK(!((used >> q) & 1), "control repeats a Pauli qubit or another control");
+            used |= uint64_t(1) << q;
+            const int v = control_values ? control_values[a] : 1;
+            SV_CHECK(v == 0 || v == 1, "control values must be 0 or 1");
+        }
+        launch_pauli_rotation(s->h, s->dt, s->d, s->n, pm, theta, controls, control_values, n_controls);
+    });
+}
+
+sv_status_t sv_measure_probabilities(sv_state_t s, const int32_t* qubits, int32_t m, double* probs)
+{
+    return guarded([&] {
+        check_state(s);
+        measured_mask(s, qubits, m, SV_MAX_TARGETS);
+        SV_CHECK(probs != nullptr, "probs is NULL");
+        run_measure_probs(s->h, s->dt, s->d, s->n, qubits, m, probs);
+    });
+}
+
+sv_status_t sv_zbasis_probabilities(sv_state_t s, const int32_t* qubits, int32_t m, double* p_even, double* p_odd)
+{
+    return guarded([&] {
+        check_state(s);
+        const uint64_t mask = measured_mask(s, qubits, m, s->n);
+        SV_CHECK(p_even != nullptr && p_odd != nullptr, "NULL output");
+        double r[2];
+        run_parity_probs(s->h, s->dt, s->d, s->n, mask, r);
+        *p_even = r[0];
+        *p_odd = r[1];
+    });
+}
+
+sv_status_t sv_collapse(sv_state_t s, const int32_t* qubits, int32_t m, uint64_t outcome, double norm)
+{
+    return guarded([&] {
+        check_state(s);
+        const uint64_t mask = measured_mask(s, qubits, m, s->n);
+        SV_CHECK(m >= 64 || outcome < (uint64_t(1) << m), "outcome has bits beyond the measured qubits");
+        SV_CHECK(norm > 0.0 && std::isfinite(norm), "norm must be positive and finite");
+        launch_collapse(s->h, s->dt, s->d, s->n, mask, outcome_bits(qubits, m, outcome), 0, -1, 1.0 / std::sqrt(norm));
+    });
+}
+
+sv_status_t sv_collapse_zbasis(sv_state_t s, const int32_t* qubits, int32_t m, int32_t parity, double norm)
+{
+    return guarded([&] {
+        check_state(s);
+        const uint64_t mask = measured_mask(s, qubits, m, s->n);
+        SV_CHECK(parity == 0 || parity == 1, "parity must be 0 or 1");
+        SV_CHECK(norm > 0.0 && std::isfinite(norm), "norm must be positive and finite");
+        launch_collapse(s->h, s->dt, s->d, s->n, 0, 0, mask, parity, 1.0 / std::sqrt(norm));
+    });
+}
+
+sv_status_t sv_measure_zbasis(sv_state_t s, const int32_t* qubits, int32_t m, double randnum, int32_t collapse,
+                              int32_t* parity)
+{
+    return guarded([&] {
+        check_state(s);
+        const uint64_t mask = measured_mask(s, qubits, m, s->n);
+        SV_CHECK(parity != nullptr, "parity is NULL");
+        SV_CHECK(randnum >= 0.0 && randnum < 1.0, "randnum must lie in [0, 1)");
+        double r[2];
+        run_parity_probs(s->h, s->dt, s->d, s->n, mask, r);
+        const double total = r[0] + r[1];
+        SV_CHECK(total > 0.0 && std::isfinite(total), "state norm is zero or not finite");
+        const int par = randnum * total < r[0] ? 0 : 1;
+        *parity = par;
+        if (collapse) launch_collapse(s->h, s->dt, s->d, s->n, 0, 0, mask, par, 1.0 / std::sqrt(r[par]));
+    });
+}
+
+sv_status_t sv_batch_measure(sv_state_t s, const int32_t* qubits, int32_t m, double randnum, int32_t collapse,
+                             uint64_t* outcome)
+{
+    return guarded([&] {
+        check_state(s);
+        const uint64_t mask = measured_mask(s, qubits, m, SV_MAX_TARGETS);
+        SV_CHECK(outcome != nullptr, "outcome is NULL");
+        SV_CHECK(randnum >= 0.0 && randnum < 1.0, "randnum must lie in [0, 1)");
+        std::vector<double> p(size_t(1) << m);
+        run_measure_probs(s->h, s->dt, s->d, s->n, qubits, m, p.data());
+        // running sums in outcome order; the outcome is the first whose
+        // running sum exceeds randnum times the total
+        std::vector<double> c(p.size());
+        double acc = 0.0;
+        for (size_t b = 0; b < p.size(); ++b) c[b] = acc = acc + p[b];
+        SV_CHECK(acc > 0.0 && std::isfinite(acc), "state norm is zero or not finite");
+        const double r = randnum * acc;
+        size_t b = 0;
+        while (b + 1 < c.size() && !(r < c[b])) ++b;
+        *outcome = b;
+        if (collapse) launch_collapse(s->h, s->dt, s->d, s->n, mask, outcome_bits(qubits, m, b), 0, -1, 1.0 / std::sqrt(p[b]));
+    });
+}
+
+sv_status_t sv_expect_matrix(sv_state_t s, const double* matrix, const int32_t* targets, int32_t k, double* out)
+{
+    return guarded([&] {
+        check_state(s);
+        SV_CHECK(k >= 1 && k <= 5, "a dense observable takes 1 to 5 qubits");
+        const GateDesc d = make_desc(s->n, targets, k, nullptr, nullptr, 0);
+        (void)d;
+        check_matrix_finite(matrix, k);
+        SV_CHECK(out != nullptr, "out is NULL");
+        double r[3];
+        run_expect_matrix(s->h, s->dt, s->d, s->n, matrix, targets, k, r);
+        SV_CHECK(r[2] > 0.0 && std::isfinite(r[2]), "state norm is zero or not finite");
+        out[0] = r[0] / r[2];
+        out[1] = r[1] / r[2];
+    });
+}
+
 sv_status_t sv_sample(sv_state_t s, const double* uniforms, int64_t n_shots, const int32_t* bit_ordering,
                       int32_t n_bits, uint64_t* out)
 {

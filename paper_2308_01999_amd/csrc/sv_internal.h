@@ -171,6 +171,24 @@ void run_expect(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const Pau
 void run_sample(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const double* u,
                 int64_t n_shots, const int32_t* bit_ordering, int n_bits, uint64_t* out);
 
+// Measurement: unnormalised probabilities of the 2^m outcomes of qubits
+// (m <= SV_MAX_TARGETS) or of the two parities of the bits in mask; collapse
+// (keep (i & qmask) == obits, or parity(i & parity_mask) == parity when
+// parity >= 0, times scale; zero the rest).
+void run_measure_probs(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const int32_t* qubits, int m,
+                       double* out);
+void run_parity_probs(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, uint64_t mask, double* out);
+void launch_collapse(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, uint64_t qmask, uint64_t obits,
+                     uint64_t parity_mask, int parity, double scale);
+
+// psi <- exp(i theta P) psi on the indices whose controls hold their values.
+void launch_pauli_rotation(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, const PauliMasks& pm, double theta,
+                           const int32_t* controls, const int32_t* cvals, int n_controls);
+
+// out = (Re, Im of sum conj(psi) M psi, sum |psi|^2) for M on targets (k <= 5).
+void run_expect_matrix(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const double* m,
+                       const int32_t* targets, int k, double* out);
+
 // Copies `bytes` of host data into the matrix ring and returns the device
 // address (stream-ordered before any later launch on the handle).
 const void* stage_matrix(sv_handle_s* h, const void* host, size_t bytes);

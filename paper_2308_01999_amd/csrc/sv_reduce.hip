@@ -1,7 +1,8 @@
-// Read-only sweeps over the state: norm, Pauli-string expectations and the
-// sampler (Table I: expectation, sampler; Sec. II: outcomes from the
-// numerically computed probability distribution, without collapse), plus the
-// two write sweeps set-basis and scale.
+// Read-only sweeps over the state: norm, Pauli-string and dense-observable
+// expectations, measurement probabilities and the sampler (Table I:
+// expectation, measurement, sampler; Sec. II: outcomes from the numerically
+// computed probability distribution), plus the write sweeps set-basis,
+// scale, collapse and Pauli rotation.
 //
 // Every reduction accumulates in FP64 in an order that depends only on n
 // (never on the grid size or on other work on the device): a fixed partition
@@ -12,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "sv_internal.h"
@@ -31,6 +33,16 @@ struct Cx<double> {
 };
 
 constexpr int kThreads = 256;
+
+// v with a zero bit inserted at each of the n ascending positions pos.
+__device__ __forceinline__ uint64_t insert_bits0(uint64_t v, const int32_t* pos, int n)
+{
+    for (int j = 0; j < n; ++j) {
+        const int p = pos[j];
+        v = ((v >> p) << (p + 1)) | (v & ((uint64_t(1) << p) - 1));
+    }
+    return v;
+}
 
 // |a|^2 in FP64 with a fixed rounding sequence (no contraction freedom):
 // complex64 components square exactly in FP64.
@@ -734,6 +746,318 @@ void run_sample_t(sv_handle_s* h, const void* psi_v, int n, const double* u, int
     }
 }
 
+// --------------------------------------------------------- measurement
+//
+// Probabilities (Table I: measurement; probability computation and collapse
+// as separate steps).  Outcome bins of m measured qubits: bin b holds the
+// indices whose bits at the measured qubits spell b.  Its sum runs over the
+// 2^(n-m) indices of that bin (the measured bits inserted as b), split into
+// a fixed partition of blocks, so every bin's sum has a fixed order; one
+// launch covers all bins (grid = bins x blocks per bin).  Z-product parity:
+// two accumulators per thread (even, odd) over a fixed partition of the
+// whole state.
+
+struct BinArgs {
+    uint64_t per;                  // compressed items per block
+    uint64_t nbp;                  // blocks per bin
+    int32_t m;
+    int32_t qpos[SV_MAX_TARGETS];  // measured qubit of outcome bit a
+    int32_t qsorted[SV_MAX_TARGETS];
+};
+
+__device__ __forceinline__ double block_wave_sum(double v, double* wsum)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double w = wave_sum(v);
+    if (lane == 0) wsum[wave] = w;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kThreads / 64; ++i) s = __dadd_rn(s, wsum[i]);
+    __syncthreads();
+    return s;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_bin_probs(const typename Cx<R>::T* __restrict__ psi, BinArgs a,
+                                                        double* __restrict__ part)
+{
+    __shared__ double wsum[kThreads / 64];
+    const uint64_t bin = blockIdx.x / a.nbp, blk = blockIdx.x % a.nbp;
+    uint64_t obits = 0;
+    for (int b = 0; b < a.m; ++b) obits |= ((bin >> b) & 1) << a.qpos[b];
+    const uint64_t j0 = blk * a.per;
+    double acc = 0.0;
+    for (uint64_t j = threadIdx.x; j < a.per; j += kThreads)
+        acc = __dadd_rn(acc, prob(psi[insert_bits0(j0 + j, a.qsorted, a.m) | obits]));
+    const double s = block_wave_sum(acc, wsum);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_parity_probs(const typename Cx<R>::T* __restrict__ psi, uint64_t per,
+                                                           uint64_t mask, double* __restrict__ part)
+{
+    __shared__ double wsum[kThreads / 64];
+    const uint64_t i0 = uint64_t(blockIdx.x) * per;
+    double acc[2] = {0.0, 0.0};
+    for (uint64_t j = threadIdx.x; j < per; j += kThreads) {
+        const uint64_t i = i0 + j;
+        const int par = __popcll(i & mask) & 1;
+        const double p = prob(psi[i]);
+        acc[0] = __dadd_rn(acc[0], par ? 0.0 : p);
+        acc[1] = __dadd_rn(acc[1], par ? p : 0.0);
+    }
+    const double e = block_wave_sum(acc[0], wsum);
+    const double o = block_wave_sum(acc[1], wsum);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = e;
+        part[gridDim.x + blockIdx.x] = o;
+    }
+}
+
+// Collapse: kept amplitudes (bits at the measured qubits == obits, or the
+// parity of i & mask == parity when parity >= 0) times scale, all others 0.
+// A vector with nothing kept is written without being read.
+struct CollapseArgs {
+    uint64_t n_vecs;
+    uint64_t qmask, obits, mask;
+    int32_t parity;
+    double scale;
+};
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_collapse(typename Cx<R>::T* __restrict__ psi, CollapseArgs a)
+{
+    using T = typename Cx<R>::T;
+    constexpr int APV = sizeof(T) == 8 ? 2 : 1;  // amplitudes per 16-byte vector
+    using V = typename std::conditional<APV == 2, float4, double2>::type;
+    const R sc = R(a.scale);
+    for (uint64_t v = uint64_t(blockIdx.x) * kThreads + threadIdx.x; v < a.n_vecs; v += uint64_t(gridDim.x) * kThreads) {
+        const uint64_t i = v * APV;
+        bool keep[APV];
+        bool any = false;
+#pragma unroll
+        for (int e = 0; e < APV; ++e) {
+            const uint64_t ie = i + e;
+            keep[e] = a.parity >= 0 ? int(__popcll(ie & a.mask) & 1) == a.parity : (ie & a.qmask) == a.obits;
+            any |= keep[e];
+        }
+        V* p = reinterpret_cast<V*>(psi + i);
+        if (!any) {
+            *p = V{};
+            continue;
+        }
+        V x = *p;
+        R* f = reinterpret_cast<R*>(&x);
+#pragma unroll
+        for (int e = 0; e < APV; ++e) {
+            f[2 * e] = keep[e] ? f[2 * e] * sc : R(0);
+            f[2 * e + 1] = keep[e] ? f[2 * e + 1] * sc : R(0);
+        }
+        *p = x;
+    }
+}
+
+// --------------------------------------------------------- Pauli rotation
+//
+// psi <- exp(i theta P) psi = cos(theta) psi + i sin(theta) P psi (Table I:
+// rotation by a Pauli string), P|k> = i^ny (-1)^popcount(k & z) |k ^ x>.
+// x == 0: a phase per amplitude.  x != 0: amplitudes i and j = i ^ x form a
+// pair (i has bit h = highest bit of x clear) updated together:
+//   new[i] = c psi[i] + i s i^ny (-1)^popcount(j & z) psi[j], and likewise
+// for j.  Items run over the control-satisfying pairs (bit h and the
+// controls inserted).
+
+struct RotArgs {
+    uint64_t items;
+    uint64_t x, z, cval;
+    int32_t ny;                       // number of Y factors, mod 4
+    int32_t n_ins;                    // inserted bits (h if x != 0, then the controls), ascending
+    int32_t ins[SV_MAX_QUBITS + 1];
+    double c, s;
+};
+
+template <typename T, typename R>
+__device__ __forceinline__ T mul_i_pow(const T v, int e)
+{
+    switch (e & 3) {
+        case 0: return v;
+        case 1: return T{-v.y, v.x};
+        case 2: return T{-v.x, -v.y};
+        default: return T{v.y, -v.x};
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_pauli_rotation(typename Cx<R>::T* __restrict__ psi, RotArgs a)
+{
+    using T = typename Cx<R>::T;
+    const R c = R(a.c), s = R(a.s);
+    for (uint64_t t = uint64_t(blockIdx.x) * kThreads + threadIdx.x; t < a.items; t += uint64_t(gridDim.x) * kThreads) {
+        const uint64_t i = insert_bits0(t, a.ins, a.n_ins) | a.cval;
+        if (a.x == 0) {
+            // exp(i theta (+-1)) = c +- i s
+            const T v = psi[i];
+            const R sg = (__popcll(i & a.z) & 1) ? -s : s;
+            psi[i] = T{c * v.x - sg * v.y, c * v.y + sg * v.x};
+            continue;
+        }
+        const uint64_t j = i ^ a.x;
+        const T vi = psi[i], vj = psi[j];
+        // i s (P psi)[i] = i^(ny+1) s (-1)^popcount(j & z) psi[j]
+        const R si = (__popcll(j & a.z) & 1) ? -s : s;
+        const R sj = (__popcll(i & a.z) & 1) ? -s : s;
+        const T pi = mul_i_pow<T, R>(T{si * vj.x, si * vj.y}, a.ny + 1);
+        const T pj = mul_i_pow<T, R>(T{sj * vi.x, sj * vi.y}, a.ny + 1);
+        psi[i] = T{c * vi.x + pi.x, c * vi.y + pi.y};
+        psi[j] = T{c * vj.x + pj.x, c * vj.y + pj.y};
+    }
+}
+
+// ------------------------------------------- dense-observable expectation
+//
+// <psi|M|psi> = sum over groups g of sum_r conj(x_r) (M x)_r, x the group's
+// 2^K amplitudes (Table I: expectation with a dense matrix observable).
+// One thread per group, M (complex128) in LDS, FP64 arithmetic for both
+// precisions, per-thread sums over a fixed partition of the groups; block
+// partials of (re, im, norm).
+
+struct ObsArgs {
+    uint64_t per;                 // groups per block
+    int32_t k;
+    uint64_t off[1 << 5];         // group offset of matrix index r
+    int32_t tsorted[5];
+};
+
+template <typename R, int K>
+__global__ __launch_bounds__(kThreads) void k_expect_matrix(const typename Cx<R>::T* __restrict__ psi,
+                                                            const double2* __restrict__ mat, ObsArgs a,
+                                                            double* __restrict__ part)
+{
+    constexpr int D = 1 << K;
+    __shared__ double2 M[D * D];
+    __shared__ double wsum[kThreads / 64];
+    for (int e = threadIdx.x; e < D * D; e += kThreads) M[e] = mat[e];
+    __syncthreads();
+    const uint64_t g0 = uint64_t(blockIdx.x) * a.per;
+    double re = 0.0, im = 0.0, nrm = 0.0;
+    using T = typename Cx<R>::T;
+    for (uint64_t g = threadIdx.x; g < a.per; g += kThreads) {
+        const uint64_t b = insert_bits0(g0 + g, a.tsorted, K);
+        T x[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) x[c] = psi[b + a.off[c]];
+        // rows one at a time (x_r read again: a cache hit), columns unrolled
+#pragma unroll 1
+        for (int r = 0; r < D; ++r) {
+            double yr = 0.0, yi = 0.0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const double2 m = M[r * D + c];
+                yr = fma(m.x, double(x[c].x), fma(-m.y, double(x[c].y), yr));
+                yi = fma(m.x, double(x[c].y), fma(m.y, double(x[c].x), yi));
+            }
+            const T v = psi[b + a.off[r]];
+            const double vr = double(v.x), vi = double(v.y);
+            // conj(x_r) y
+            re = fma(vr, yr, fma(vi, yi, re));
+            im = fma(vr, yi, fma(-vi, yr, im));
+            nrm = fma(vr, vr, fma(vi, vi, nrm));
+        }
+    }
+    const double s0 = block_wave_sum(re, wsum);
+    const double s1 = block_wave_sum(im, wsum);
+    const double s2 = block_wave_sum(nrm, wsum);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = s0;
+        part[gridDim.x + blockIdx.x] = s1;
+        part[2 * gridDim.x + blockIdx.x] = s2;
+    }
+}
+
+template <typename R>
+void run_bin_probs_t(sv_handle_s* h, const void* psi_v, int n, const int32_t* qubits, int m, double* out)
+{
+    using T2 = typename Cx<R>::T;
+    BinArgs a{};
+    a.m = m;
+    for (int b = 0; b < m; ++b) a.qpos[b] = a.qsorted[b] = qubits[b];
+    std::sort(a.qsorted, a.qsorted + m);
+    const uint64_t items = uint64_t(1) << (n - m);
+    const uint64_t bins = uint64_t(1) << m;
+    uint64_t nbp = std::max<uint64_t>(1, std::min<uint64_t>(items / 2048, std::max<uint64_t>(1, 8192 / bins)));
+    a.nbp = nbp;
+    a.per = items / nbp;
+    double* part = reinterpret_cast<double*>(h->ws + kMatRingBytes);
+    double* res = part + bins * nbp;
+    hipLaunchKernelGGL((k_bin_probs<R>), dim3(unsigned(bins * nbp)), dim3(kThreads), 0, h->stream,
+                       static_cast<const T2*>(psi_v), a, part);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_finish_sums, dim3(unsigned(bins)), dim3(kThreads), 0, h->stream, part, nbp, res);
+    SV_HIP(hipGetLastError());
+    SV_HIP(hipMemcpyAsync(out, res, sizeof(double) * bins, hipMemcpyDeviceToHost, h->stream));
+    SV_HIP(hipStreamSynchronize(h->stream));
+}
+
+template <typename R>
+void run_parity_probs_t(sv_handle_s* h, const void* psi_v, int n, uint64_t mask, double* out)
+{
+    using T2 = typename Cx<R>::T;
+    const Partition P = partition(uint64_t(1) << n);
+    double* part = reinterpret_cast<double*>(h->ws + kMatRingBytes);
+    double* res = part + 2 * P.nb;
+    hipLaunchKernelGGL((k_parity_probs<R>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream,
+                       static_cast<const T2*>(psi_v), P.per, mask, part);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_finish_sums, dim3(2), dim3(kThreads), 0, h->stream, part, P.nb, res);
+    SV_HIP(hipGetLastError());
+    SV_HIP(hipMemcpyAsync(out, res, sizeof(double) * 2, hipMemcpyDeviceToHost, h->stream));
+    SV_HIP(hipStreamSynchronize(h->stream));
+}
+
+template <typename R, int K>
+void launch_expect_matrix_k(sv_handle_s* h, const void* psi_v, const double2* mat, const ObsArgs& a, unsigned nb,
+                            double* part)
+{
+    hipLaunchKernelGGL((k_expect_matrix<R, K>), dim3(nb), dim3(kThreads), 0, h->stream,
+                       static_cast<const typename Cx<R>::T*>(psi_v), mat, a, part);
+}
+
+template <typename R>
+void run_expect_matrix_t(sv_handle_s* h, const void* psi_v, int n, const double* m, const int32_t* targets, int k,
+                         double* out)
+{
+    ObsArgs a{};
+    a.k = k;
+    for (int r = 0; r < (1 << k); ++r) {
+        uint64_t o = 0;
+        for (int b = 0; b < k; ++b)
+            if ((r >> b) & 1) o |= uint64_t(1) << targets[b];
+        a.off[r] = o;
+    }
+    for (int b = 0; b < k; ++b) a.tsorted[b] = targets[b];
+    std::sort(a.tsorted, a.tsorted + k);
+    const Partition P = partition(uint64_t(1) << (n - k));
+    const double2* dm = static_cast<const double2*>(stage_matrix(h, m, sizeof(double2) << (2 * k)));
+    double* part = reinterpret_cast<double*>(h->ws + kMatRingBytes);
+    double* res = part + 3 * P.nb;
+    a.per = P.per;
+    const unsigned nb = unsigned(P.nb);
+    switch (k) {
+        case 1: launch_expect_matrix_k<R, 1>(h, psi_v, dm, a, nb, part); break;
+        case 2: launch_expect_matrix_k<R, 2>(h, psi_v, dm, a, nb, part); break;
+        case 3: launch_expect_matrix_k<R, 3>(h, psi_v, dm, a, nb, part); break;
+        case 4: launch_expect_matrix_k<R, 4>(h, psi_v, dm, a, nb, part); break;
+        default: launch_expect_matrix_k<R, 5>(h, psi_v, dm, a, nb, part); break;
+    }
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_finish_sums, dim3(3), dim3(kThreads), 0, h->stream, part, P.nb, res);
+    SV_HIP(hipGetLastError());
+    SV_HIP(hipMemcpyAsync(out, res, sizeof(double) * 3, hipMemcpyDeviceToHost, h->stream));
+    SV_HIP(hipStreamSynchronize(h->stream));
+}
+
 }  // namespace
 
 void launch_set_basis(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, uint64_t x)
@@ -781,6 +1105,83 @@ void run_sample(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const dou
         run_sample_t<float>(h, psi, n, u, n_shots, bit_ordering, n_bits, out);
     else
         run_sample_t<double>(h, psi, n, u, n_shots, bit_ordering, n_bits, out);
+}
+
+
+void run_measure_probs(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const int32_t* qubits, int m,
+                       double* out)
+{
+    if (dt == SV_C64)
+        run_bin_probs_t<float>(h, psi, n, qubits, m, out);
+    else
+        run_bin_probs_t<double>(h, psi, n, qubits, m, out);
+}
+
+void run_parity_probs(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, uint64_t mask, double* out)
+{
+    if (dt == SV_C64)
+        run_parity_probs_t<float>(h, psi, n, mask, out);
+    else
+        run_parity_probs_t<double>(h, psi, n, mask, out);
+}
+
+void launch_collapse(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, uint64_t qmask, uint64_t obits,
+                     uint64_t parity_mask, int parity, double scale)
+{
+    CollapseArgs a{};
+    const uint64_t dim = uint64_t(1) << n;
+    a.qmask = qmask;
+    a.obits = obits;
+    a.mask = parity_mask;
+    a.parity = parity;
+    a.scale = scale;
+    if (dt == SV_C64) {
+        a.n_vecs = dim / 2;
+        hipLaunchKernelGGL(k_collapse<float>, dim3(grid_for(h, a.n_vecs)), dim3(kThreads), 0, h->stream,
+                           static_cast<float2*>(psi), a);
+    } else {
+        a.n_vecs = dim;
+        hipLaunchKernelGGL(k_collapse<double>, dim3(grid_for(h, a.n_vecs)), dim3(kThreads), 0, h->stream,
+                           static_cast<double2*>(psi), a);
+    }
+    SV_HIP(hipGetLastError());
+}
+
+void launch_pauli_rotation(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, const PauliMasks& pm, double theta,
+                           const int32_t* controls, const int32_t* cvals, int n_controls)
+{
+    RotArgs a{};
+    a.x = pm.x;
+    a.z = pm.z;
+    a.ny = pm.ny & 3;
+    a.c = std::cos(theta);
+    a.s = std::sin(theta);
+    std::vector<int32_t> ins;
+    if (pm.x) ins.push_back(63 - __builtin_clzll(pm.x));
+    for (int b = 0; b < n_controls; ++b) {
+        ins.push_back(controls[b]);
+        if (!cvals || cvals[b]) a.cval |= uint64_t(1) << controls[b];
+    }
+    std::sort(ins.begin(), ins.end());
+    a.n_ins = int(ins.size());
+    for (size_t b = 0; b < ins.size(); ++b) a.ins[b] = ins[b];
+    a.items = uint64_t(1) << (n - a.n_ins);
+    if (dt == SV_C64)
+        hipLaunchKernelGGL(k_pauli_rotation<float>, dim3(grid_for(h, a.items)), dim3(kThreads), 0, h->stream,
+                           static_cast<float2*>(psi), a);
+    else
+        hipLaunchKernelGGL(k_pauli_rotation<double>, dim3(grid_for(h, a.items)), dim3(kThreads), 0, h->stream,
+                           static_cast<double2*>(psi), a);
+    SV_HIP(hipGetLastError());
+}
+
+void run_expect_matrix(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const double* m,
+                       const int32_t* targets, int k, double* out)
+{
+    if (dt == SV_C64)
+        run_expect_matrix_t<float>(h, psi, n, m, targets, k, out);
+    else
+        run_expect_matrix_t<double>(h, psi, n, m, targets, k, out);
 }
 
 }  // namespace sv
