@@ -58,6 +58,11 @@ def lib():
         L.orc_collapse.restype = ctypes.c_int
         L.orc_expect_matrix.argtypes = [vp, ctypes.c_int, vp, ip, ctypes.c_int, dp]
         L.orc_expect_matrix.restype = ctypes.c_int
+        L.orc_swap_index_bits.argtypes = [vp, ctypes.c_int, ip, ctypes.c_int, ip, ip, ctypes.c_int]
+        L.orc_swap_index_bits.restype = ctypes.c_int
+        L.orc_accessor.argtypes = [vp, ctypes.c_int, ip, ctypes.c_int, ip, ip, ctypes.c_int, vp, ctypes.c_int64,
+                                   ctypes.c_int64, ctypes.c_int]
+        L.orc_accessor.restype = ctypes.c_int
         L.orc_norm.argtypes = [vp, ctypes.c_int]
         L.orc_norm.restype = ctypes.c_double
         L.orc_expect_pauli.argtypes = [vp, ctypes.c_int, ip, ctypes.c_char_p, ctypes.c_int, dp]
@@ -237,6 +242,42 @@ def expect_matrix(psi: np.ndarray, matrix, targets) -> complex:
     if rc != 0:
         raise ValueError("invalid expectation arguments")
     return complex(out[0], out[1])
+
+
+def swap_index_bits(psi: np.ndarray, pairs, mask_bits=(), mask_values=()) -> None:
+    """Exchange index bits a and b for every pair (a, b) (all distinct), on
+    the indices whose mask bits hold the mask values."""
+    n = _nqubits(psi)
+    flat = [q for p in pairs for q in p]
+    rc = lib().orc_swap_index_bits(psi.ctypes.data, n, _ints(flat), len(pairs), _ints(mask_bits), _ints(mask_values),
+                                   len(mask_bits))
+    if rc != 0:
+        raise ValueError("invalid index bit swap arguments")
+
+
+def accessor_get(psi: np.ndarray, ordering, mask_bits=(), mask_values=(), begin: int = 0, end: int | None = None):
+    """Amplitudes in the qubit order `ordering` (bit a of the output index is
+    state bit ordering[a]) on the slice whose mask bits hold mask_values,
+    output indices [begin, end)."""
+    n = _nqubits(psi)
+    if end is None:
+        end = 1 << len(ordering)
+    buf = np.zeros(max(0, end - begin), dtype=np.complex128)
+    rc = lib().orc_accessor(psi.ctypes.data, n, _ints(ordering), len(ordering), _ints(mask_bits), _ints(mask_values),
+                            len(mask_bits), buf.ctypes.data, begin, end, 0)
+    if rc != 0:
+        raise ValueError("invalid accessor arguments")
+    return buf
+
+
+def accessor_set(psi: np.ndarray, values, ordering, mask_bits=(), mask_values=(), begin: int = 0) -> None:
+    """The inverse of accessor_get: writes values into those amplitudes."""
+    n = _nqubits(psi)
+    buf = np.ascontiguousarray(values, dtype=np.complex128)
+    rc = lib().orc_accessor(psi.ctypes.data, n, _ints(ordering), len(ordering), _ints(mask_bits), _ints(mask_values),
+                            len(mask_bits), buf.ctypes.data, begin, begin + buf.size, 1)
+    if rc != 0:
+        raise ValueError("invalid accessor arguments")
 
 
 def apply_gate(psi: np.ndarray, gate) -> None:

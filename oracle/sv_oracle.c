@@ -219,6 +219,82 @@ int orc_apply_gperm(double* psi_ri, int n, const int64_t* perm, const double* di
 }
 
 /* ------------------------------------------------------------------------ */
+/* Index bit swap (Table I: swap index bit pairs of the state vector).  For  */
+/* every index i whose mask bits equal the mask values, the amplitude moves  */
+/* to the index with bits a_p and b_p exchanged for every pair p (all bits  */
+/* of all pairs distinct, none a mask bit); other amplitudes stay.           */
+/* ------------------------------------------------------------------------ */
+
+int orc_swap_index_bits(double* psi_ri, int n, const int* pairs, int npairs, const int* mbits, const int* mvals,
+                        int nmask)
+{
+    if (n < 1 || n > 40 || npairs < 0 || nmask < 0) return ORC_BAD;
+    uint64_t used = 0, mmask = 0, mval = 0;
+    for (int a = 0; a < 2 * npairs; ++a) {
+        if (pairs[a] < 0 || pairs[a] >= n || (used >> pairs[a] & 1)) return ORC_BAD;
+        used |= (uint64_t)1 << pairs[a];
+    }
+    for (int a = 0; a < nmask; ++a) {
+        uint64_t b = (uint64_t)1 << mbits[a];
+        if (mbits[a] < 0 || mbits[a] >= n || (used & b)) return ORC_BAD;
+        used |= b;
+        mmask |= b;
+        if (mvals[a]) mval |= b;
+    }
+    int64_t dim = (int64_t)1 << n;
+    cplx* psi = (cplx*)psi_ri;
+    cplx* out = (cplx*)malloc(sizeof(cplx) * (size_t)dim);
+    if (!out) return ORC_BAD;
+    memcpy(out, psi, sizeof(cplx) * (size_t)dim);
+    for (int64_t i = 0; i < dim; ++i) {
+        if (((uint64_t)i & mmask) != mval) continue;
+        uint64_t j = (uint64_t)i;
+        for (int p = 0; p < npairs; ++p) {
+            const uint64_t ba = ((uint64_t)i >> pairs[2 * p]) & 1, bb = ((uint64_t)i >> pairs[2 * p + 1]) & 1;
+            j &= ~(((uint64_t)1 << pairs[2 * p]) | ((uint64_t)1 << pairs[2 * p + 1]));
+            j |= (bb << pairs[2 * p]) | (ba << pairs[2 * p + 1]);
+        }
+        out[j] = psi[i];
+    }
+    memcpy(psi, out, sizeof(cplx) * (size_t)dim);
+    free(out);
+    return ORC_OK;
+}
+
+/* Accessor with reordering (Table I: copy the state between host and device */
+/* while changing the qubit order): element k - begin of buf is the          */
+/* amplitude whose bit ordering[a] is bit a of k (a < nbits) and whose mask  */
+/* bits hold the mask values; nbits + nmask == n, all bits distinct.         */
+/* set != 0 writes buf into the state instead of reading.                    */
+int orc_accessor(double* psi_ri, int n, const int* ordering, int nbits, const int* mbits, const int* mvals,
+                 int nmask, double* buf_ri, int64_t begin, int64_t end, int set)
+{
+    if (n < 1 || n > 40 || nbits < 0 || nmask < 0 || nbits + nmask != n) return ORC_BAD;
+    uint64_t used = 0, mval = 0;
+    for (int a = 0; a < nbits; ++a) {
+        if (ordering[a] < 0 || ordering[a] >= n || (used >> ordering[a] & 1)) return ORC_BAD;
+        used |= (uint64_t)1 << ordering[a];
+    }
+    for (int a = 0; a < nmask; ++a) {
+        if (mbits[a] < 0 || mbits[a] >= n || (used >> mbits[a] & 1)) return ORC_BAD;
+        used |= (uint64_t)1 << mbits[a];
+        if (mvals[a]) mval |= (uint64_t)1 << mbits[a];
+    }
+    if (begin < 0 || end < begin || end > ((int64_t)1 << nbits)) return ORC_BAD;
+    cplx* psi = (cplx*)psi_ri;
+    cplx* buf = (cplx*)buf_ri;
+    for (int64_t k = begin; k < end; ++k) {
+        uint64_t i = mval;
+        for (int a = 0; a < nbits; ++a) i |= (((uint64_t)k >> a) & 1) << ordering[a];
+        if (set)
+            psi[i] = buf[k - begin];
+        else
+            buf[k - begin] = psi[i];
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Reductions.  Sums are Neumaier-compensated and run in index order, so the */
 /* result is the exact sum rounded to within a few ulps.                     */
 /* ------------------------------------------------------------------------ */

@@ -559,3 +559,54 @@ def test_expect_matrix_matches_kronecker(seed):
     # a Pauli product as a matrix equals the Pauli expectation
     term = [(targets[0], "Y")]
     assert abs(oracle.expect_matrix(psi, PAULI["Y"], targets[:1]) - oracle.expect_pauli(psi, term)) < 1e-14
+
+
+# ---------------------------------------------- index bit swap and accessor
+
+@pytest.mark.parametrize("seed", range(5))
+def test_swap_index_bits_equals_swap_gates(seed):
+    # exchanging bit pairs is a product of SWAP gates; with mask bits, of
+    # SWAPs controlled on the mask values (Kronecker operators)
+    rng = np.random.default_rng(seed)
+    n = 6
+    qs = [int(q) for q in rng.permutation(n)]
+    npairs = int(rng.integers(1, 3))
+    pairs = [(qs[2 * p], qs[2 * p + 1]) for p in range(npairs)]
+    nm = int(rng.integers(0, n - 2 * npairs + 1))
+    nm = min(nm, 2)
+    mbits = qs[2 * npairs:2 * npairs + nm]
+    mvals = [int(v) for v in rng.integers(0, 2, nm)]
+    psi = _rand_state(n, rng)
+    ref = psi.copy()
+    swap = np.eye(4)[[0, 2, 1, 3]]
+    for a, b in pairs:
+        ref = embed(swap, (a, b), n, tuple(mbits), mvals if nm else None) @ ref
+    oracle.swap_index_bits(psi, pairs, mbits, mvals)
+    np.testing.assert_allclose(psi, ref, atol=1e-15)
+
+
+def test_accessor_reorders_like_a_tensor_transpose():
+    # with every bit listed, the reordered copy equals numpy's axis
+    # permutation of the state viewed as a 2 x ... x 2 tensor; with mask
+    # bits, a slice of it; set inverts get
+    rng = np.random.default_rng(8)
+    n = 5
+    psi = _rand_state(n, rng)
+    order = [3, 0, 4, 1, 2]
+    # tensor axis t corresponds to qubit n - 1 - t (C order, qubit 0 last)
+    t = psi.reshape([2] * n)
+    # output bit a = state bit order[a]; output axis n-1-a <- state axis n-1-order[a]
+    perm = [n - 1 - order[n - 1 - ax] for ax in range(n)]
+    want = np.transpose(t, perm).reshape(-1)
+    np.testing.assert_array_equal(oracle.accessor_get(psi, order), want)
+    np.testing.assert_array_equal(oracle.accessor_get(psi, order, begin=5, end=19), want[5:19])
+    sl = oracle.accessor_get(psi, [4, 0, 2], mask_bits=[1, 3], mask_values=[1, 0])
+    idx = [(1 << 1) | (((k >> 0) & 1) << 4) | (((k >> 1) & 1) << 0) | (((k >> 2) & 1) << 2) for k in range(8)]
+    np.testing.assert_array_equal(sl, psi[idx])
+    phi = np.zeros_like(psi)
+    oracle.accessor_set(phi, want, order)
+    np.testing.assert_array_equal(phi, psi)
+    with pytest.raises(ValueError):
+        oracle.accessor_get(psi, [0, 1, 2])          # bits missing
+    with pytest.raises(ValueError):
+        oracle.swap_index_bits(psi, [(0, 1), (1, 2)])  # bit 1 twice
