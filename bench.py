@@ -444,6 +444,67 @@ def diagonal_leg(P, W, torch, H, n, reps=10):
     return out
 
 
+def table1_leg(P, W, torch, H, n, reps=5):
+    """The other single-GPU operations of the paper's Table I at n qubits on
+    a dense state, each timed over `reps` calls with HIP events on the
+    handle's stream (blocking calls: host wall time): Pauli rotations (an
+    X/Y/Z string, a Z-only string), measurement probabilities of 3 qubits,
+    Z-product parity probabilities, collapse, batched measurement with
+    collapse, and a 3-qubit dense-observable expectation.  GB/s counts the
+    algorithmic bytes: reads of 2^n amplitudes for the reductions, read and
+    write for the rotation, the write plus the kept reads for a collapse."""
+    import numpy as np
+    out = {}
+    rng = np.random.default_rng(23)
+    for dt, ab in (("c64", 8), ("c128", 16)):
+        st = P.State(H, n, dt)
+        st.run(W.brickwork(n, 1, 29))
+        state = (1 << n) * ab
+        res = {}
+
+        def timed_async(fn):
+            fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(H.stream)
+            for _ in range(reps):
+                fn()
+            e1.record(H.stream)
+            e1.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        def timed_blocking(fn):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            return (time.perf_counter() - t0) / reps * 1e3
+
+        term = [(1, "X"), (7, "Y"), (19, "Z"), (26, "X")]
+        ms = timed_async(lambda: P.sv_apply_pauli_rotation(st.s, 0.3, term))
+        res["pauli_rotation_xyz"] = {"avg_ms": round(ms, 3), "GBps": round(2 * state / (ms * 1e-3) / 1e9, 1)}
+        ms = timed_async(lambda: P.sv_apply_pauli_rotation(st.s, 0.3, [(q, "Z") for q in range(0, n, 2)]))
+        res["pauli_rotation_z"] = {"avg_ms": round(ms, 3), "GBps": round(2 * state / (ms * 1e-3) / 1e9, 1)}
+        q3 = [2, 14, 27]
+        ms = timed_blocking(lambda: P.sv_measure_probabilities(st.s, q3))
+        res["measure_probabilities_3q"] = {"avg_ms": round(ms, 3), "GBps": round(state / (ms * 1e-3) / 1e9, 1)}
+        ms = timed_blocking(lambda: P.sv_zbasis_probabilities(st.s, list(range(0, n, 3))))
+        res["zbasis_probabilities"] = {"avg_ms": round(ms, 3), "GBps": round(state / (ms * 1e-3) / 1e9, 1)}
+        p = P.sv_measure_probabilities(st.s, [29])
+        ms = timed_async(lambda: P.sv_collapse(st.s, [29], 0, 1.0))
+        res["collapse_1q"] = {"avg_ms": round(ms, 3), "GBps": round(1.5 * state / (ms * 1e-3) / 1e9, 1),
+                              "note": "bytes: the whole state written, the kept half read"}
+        m = rng.normal(size=(8, 8)) + 1j * rng.normal(size=(8, 8))
+        ms = timed_blocking(lambda: P.sv_expect_matrix(st.s, m, [3, 12, 21]))
+        res["expect_matrix_3q"] = {"avg_ms": round(ms, 3), "GBps": round(state / (ms * 1e-3) / 1e9, 1)}
+        del p
+        out[dt] = res
+        st.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
+
+
 def large_leg(P, W, torch, H):
     """The depth-12 random CNOT/CP circuit (U3 on every qubit, then a random
     matching into far-apart CNOT or CP pairs, per layer) fused to k <= 5
@@ -714,6 +775,11 @@ def main():
         HD = P.Handle()
         line["diagonal_gates"] = diagonal_leg(P, W, torch, HD, n)
         HD.close()
+    if not args.no_diagonal:
+        print("[bench] Table I operations leg", file=sys.stderr, flush=True)
+        HT = P.Handle()
+        line["table1_ops"] = table1_leg(P, W, torch, HT, n)
+        HT.close()
     if args.large:
         print("[bench] large-state leg", file=sys.stderr, flush=True)
         HL = P.Handle()

@@ -350,6 +350,34 @@ sv_status_t sv_measure_zbasis(sv_state_t s, const int32_t* qubits, int32_t m, do
 sv_status_t sv_batch_measure(sv_state_t s, const int32_t* qubits, int32_t m, double randnum, int32_t collapse,
                              uint64_t* outcome);
 
+/* ---------------------------------------------- index bit swap, accessor */
+
+/*
+ * Index bit swap (Table I; the single-GPU building block of the paper's
+ * qubit reordering, Sec. II-C): for every index whose mask bits equal
+ * mask_values, the amplitude moves to the index with bits pairs[2p] and
+ * pairs[2p + 1] exchanged for every pair p.  All bits of the pairs and the
+ * mask must be distinct.  Each moved amplitude is read and written once;
+ * amplitudes the swap leaves in place are not touched.  Asynchronous.
+ */
+sv_status_t sv_swap_index_bits(sv_state_t s, const int32_t* pairs, int32_t n_pairs, const int32_t* mask_bits,
+                               const int32_t* mask_values, int32_t n_mask);
+
+/*
+ * Accessor (Table I: copy between host and device while changing the qubit
+ * order): host element k - begin, k in [begin, end), is the amplitude whose
+ * bit ordering[a] equals bit a of k (a < n_bits) and whose mask bits hold
+ * mask_values; n_bits + n_mask must equal n, all bits distinct; end <=
+ * 2^n_bits.  Host buffers hold amplitudes in the state's dtype (interleaved
+ * re, im; complex64 or complex128).  get reads the state, set writes it.
+ * Gathered / scattered on the device through the handle's workspace in
+ * chunks of up to 32 MiB, one host copy per chunk.  Both block.
+ */
+sv_status_t sv_accessor_get(sv_state_t s, const int32_t* ordering, int32_t n_bits, const int32_t* mask_bits,
+                            const int32_t* mask_values, int32_t n_mask, void* dst, int64_t begin, int64_t end);
+sv_status_t sv_accessor_set(sv_state_t s, const int32_t* ordering, int32_t n_bits, const int32_t* mask_bits,
+                            const int32_t* mask_values, int32_t n_mask, const void* src, int64_t begin, int64_t end);
+
 /* ------------------------------------------------------------- reductions */
 
 /* *out = sum_i |psi_i|^2 accumulated in FP64 in a fixed order (bitwise

@@ -95,6 +95,9 @@ _SIGS = {
     "sv_measure_zbasis": [_vp, _pi32, _i32, ctypes.c_double, _i32, _pi32],
     "sv_batch_measure": [_vp, _pi32, _i32, ctypes.c_double, _i32, _pu64],
     "sv_expect_matrix": [_vp, _pd, _pi32, _i32, _pd],
+    "sv_swap_index_bits": [_vp, _pi32, _i32, _pi32, _pi32, _i32],
+    "sv_accessor_get": [_vp, _pi32, _i32, _pi32, _pi32, _i32, _vp, _i64, _i64],
+    "sv_accessor_set": [_vp, _pi32, _i32, _pi32, _pi32, _i32, _vp, _i64, _i64],
     "sv_copy_to_host": [_vp, _vp, _u64, _u64],
     "sv_copy_from_host": [_vp, _vp, _u64, _u64],
     "sv_batch_create": [_vp, _i32, _pi32, _pi32, _pi32, _pi32, _pd, _pi32, _pu64, _i32, ctypes.POINTER(_vp)],
@@ -430,6 +433,28 @@ def sv_expect_matrix(s: int, matrix, targets) -> complex:
     out = np.zeros(2, dtype=np.float64)
     _check(_L.sv_expect_matrix(_vp(s), m.ctypes.data_as(_pd), _i32arr(targets), len(targets), _dptr(out)))
     return complex(out[0], out[1])
+
+
+def sv_swap_index_bits(s: int, pairs, mask_bits=(), mask_values=()) -> None:
+    flat = [int(q) for p in pairs for q in p]
+    _check(_L.sv_swap_index_bits(_vp(s), _i32arr(flat), len(pairs), _i32arr(mask_bits), _i32arr(mask_values),
+                                 len(mask_bits)))
+
+
+def sv_accessor_get(s: int, dtype: int, ordering, mask_bits=(), mask_values=(), begin: int = 0,
+                    end: int | None = None) -> np.ndarray:
+    if end is None:
+        end = 1 << len(ordering)
+    out = np.zeros(max(0, end - begin), dtype=np.complex64 if dtype == SV_C64 else np.complex128)
+    _check(_L.sv_accessor_get(_vp(s), _i32arr(ordering), len(ordering), _i32arr(mask_bits), _i32arr(mask_values),
+                              len(mask_bits), out.ctypes.data, begin, end))
+    return out
+
+
+def sv_accessor_set(s: int, dtype: int, values, ordering, mask_bits=(), mask_values=(), begin: int = 0) -> None:
+    v = np.ascontiguousarray(values, dtype=np.complex64 if dtype == SV_C64 else np.complex128)
+    _check(_L.sv_accessor_set(_vp(s), _i32arr(ordering), len(ordering), _i32arr(mask_bits), _i32arr(mask_values),
+                              len(mask_bits), v.ctypes.data, begin, begin + v.size))
 
 
 def sv_sample(s: int, uniforms, bit_ordering=None) -> np.ndarray:

@@ -903,6 +903,80 @@ sv_status_t sv_batch_measure(sv_state_t s, const int32_t* qubits, int32_t m, dou
     });
 }
 
+sv_status_t sv_swap_index_bits(sv_state_t s, const int32_t* pairs, int32_t n_pairs, const int32_t* mask_bits,
+                               const int32_t* mask_values, int32_t n_mask)
+{
+    return guarded([&] {
+        check_state(s);
+        SV_CHECK(n_pairs >= 0 && n_mask >= 0, "negative count");
+        SV_CHECK(n_pairs == 0 || pairs != nullptr, "pairs is NULL");
+        SV_CHECK(n_mask == 0 || (mask_bits != nullptr && mask_values != nullptr), "mask arrays are NULL");
+        SV_CHECK(2 * n_pairs + n_mask <= s->n, "more bits than qubits");
+        uint64_t used = 0;
+        for (int a = 0; a < 2 * n_pairs; ++a) {
+            SV_CHECK(pairs[a] >= 0 && pairs[a] < s->n, "swapped bit out of range");
+            SV_CHECK(!((used >> pairs[a]) & 1), "a bit appears twice among the pairs");
+            used |= uint64_t(1) << pairs[a];
+        }
+        for (int a = 0; a < n_mask; ++a) {
+            SV_CHECK(mask_bits[a] >= 0 && mask_bits[a] < s->n, "mask bit out of range");
+            SV_CHECK(!((used >> mask_bits[a]) & 1), "mask bit repeats a swapped or mask bit");
+            used |= uint64_t(1) << mask_bits[a];
+            SV_CHECK(mask_values[a] == 0 || mask_values[a] == 1, "mask values must be 0 or 1");
+        }
+        if (n_pairs == 0) return;
+        launch_swap_bits(s->h, s->dt, s->d, s->n, pairs, n_pairs, mask_bits, mask_values, n_mask);
+    });
+}
+
+namespace {
+void check_access(const sv_state_s* s, const int32_t* ordering, int32_t n_bits, const int32_t* mask_bits,
+                  const int32_t* mask_values, int32_t n_mask, const void* host, int64_t begin, int64_t end)
+{
+    SV_CHECK(n_bits >= 0 && n_mask >= 0 && n_bits + n_mask == s->n, "ordering plus mask bits must cover every qubit");
+    SV_CHECK(n_bits == 0 || ordering != nullptr, "ordering is NULL");
+    SV_CHECK(n_mask == 0 || (mask_bits != nullptr && mask_values != nullptr), "mask arrays are NULL");
+    uint64_t used = 0;
+    for (int a = 0; a < n_bits; ++a) {
+        SV_CHECK(ordering[a] >= 0 && ordering[a] < s->n, "ordering bit out of range");
+        SV_CHECK(!((used >> ordering[a]) & 1), "ordering repeats a bit");
+        used |= uint64_t(1) << ordering[a];
+    }
+    for (int a = 0; a < n_mask; ++a) {
+        SV_CHECK(mask_bits[a] >= 0 && mask_bits[a] < s->n, "mask bit out of range");
+        SV_CHECK(!((used >> mask_bits[a]) & 1), "mask bit repeats a bit");
+        used |= uint64_t(1) << mask_bits[a];
+        SV_CHECK(mask_values[a] == 0 || mask_values[a] == 1, "mask values must be 0 or 1");
+    }
+    SV_CHECK(begin >= 0 && begin <= end && uint64_t(end) <= (uint64_t(1) << n_bits), "range out of bounds");
+    SV_CHECK(begin == end || host != nullptr, "host buffer is NULL");
+}
+}  // namespace
+
+sv_status_t sv_accessor_get(sv_state_t s, const int32_t* ordering, int32_t n_bits, const int32_t* mask_bits,
+                            const int32_t* mask_values, int32_t n_mask, void* dst, int64_t begin, int64_t end)
+{
+    return guarded([&] {
+        check_state(s);
+        check_access(s, ordering, n_bits, mask_bits, mask_values, n_mask, dst, begin, end);
+        if (begin < end)
+            run_accessor(s->h, s->dt, s->d, s->n, ordering, n_bits, mask_bits, mask_values, n_mask, dst, begin, end,
+                         false);
+    });
+}
+
+sv_status_t sv_accessor_set(sv_state_t s, const int32_t* ordering, int32_t n_bits, const int32_t* mask_bits,
+                            const int32_t* mask_values, int32_t n_mask, const void* src, int64_t begin, int64_t end)
+{
+    return guarded([&] {
+        check_state(s);
+        check_access(s, ordering, n_bits, mask_bits, mask_values, n_mask, src, begin, end);
+        if (begin < end)
+            run_accessor(s->h, s->dt, s->d, s->n, ordering, n_bits, mask_bits, mask_values, n_mask,
+                         const_cast<void*>(src), begin, end, true);
+    });
+}
+
 sv_status_t sv_expect_matrix(sv_state_t s, const double* matrix, const int32_t* targets, int32_t k, double* out)
 {
     return guarded([&] {

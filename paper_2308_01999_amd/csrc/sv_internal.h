@@ -185,6 +185,14 @@ void launch_collapse(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, uint64_t q
 void launch_pauli_rotation(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, const PauliMasks& pm, double theta,
                            const int32_t* controls, const int32_t* cvals, int n_controls);
 
+// Index bit swap of disjoint bit pairs on the mask-selected indices (async),
+// and the reordering accessor (blocking; host memory in the state's dtype).
+void launch_swap_bits(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, const int32_t* pairs, int n_pairs,
+                      const int32_t* mask_bits, const int32_t* mask_values, int n_mask);
+void run_accessor(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, const int32_t* ordering, int n_bits,
+                  const int32_t* mask_bits, const int32_t* mask_values, int n_mask, void* host, int64_t begin,
+                  int64_t end, bool set);
+
 // out = (Re, Im of sum conj(psi) M psi, sum |psi|^2) for M on targets (k <= 5).
 void run_expect_matrix(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const double* m,
                        const int32_t* targets, int k, double* out);

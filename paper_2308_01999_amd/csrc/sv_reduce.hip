@@ -1058,6 +1058,71 @@ void run_expect_matrix_t(sv_handle_s* h, const void* psi_v, int n, const double*
     SV_HIP(hipStreamSynchronize(h->stream));
 }
 
+// -------------------------------------------- index bit swap, accessor
+//
+// Index bit swap (Table I): the amplitude at i moves to pi(i), pi exchanging
+// bits a_p and b_p of every pair (all distinct), for the indices whose mask
+// bits hold the mask values.  pi is an involution, so each moved pair (i,
+// pi(i)) is swapped once, by the thread of the smaller index; fixed points
+// are not touched.
+
+struct SwapArgs {
+    uint64_t items;                  // mask-compressed indices
+    uint64_t mval;
+    int32_t n_pairs;
+    int32_t a[SV_MAX_QUBITS / 2], b[SV_MAX_QUBITS / 2];
+    int32_t n_mask;
+    int32_t msorted[SV_MAX_QUBITS];
+};
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_swap_bits(typename Cx<R>::T* __restrict__ psi, SwapArgs a)
+{
+    for (uint64_t t = uint64_t(blockIdx.x) * kThreads + threadIdx.x; t < a.items; t += uint64_t(gridDim.x) * kThreads) {
+        const uint64_t i = insert_bits0(t, a.msorted, a.n_mask) | a.mval;
+        uint64_t j = i;
+        for (int p = 0; p < a.n_pairs; ++p) {
+            const uint64_t d = ((i >> a.a[p]) ^ (i >> a.b[p])) & 1;
+            j ^= (d << a.a[p]) | (d << a.b[p]);
+        }
+        if (j > i) {
+            const auto x = psi[i], y = psi[j];
+            psi[i] = y;
+            psi[j] = x;
+        }
+    }
+}
+
+// Accessor (Table I: copy between host and device while reordering the
+// qubits): element k of a chunk is the amplitude whose bit ordering[a] is bit
+// a of (first + k) and whose mask bits hold the mask values.  Gather into a
+// contiguous device buffer (then one copy to the host), or scatter from one.
+struct AccessArgs {
+    uint64_t first, count, mval;
+    int32_t n_bits;
+    int32_t ordering[SV_MAX_QUBITS];
+};
+
+__device__ __forceinline__ uint64_t access_index(uint64_t k, const AccessArgs& a)
+{
+    uint64_t i = a.mval;
+    for (int b = 0; b < a.n_bits; ++b) i |= ((k >> b) & 1) << a.ordering[b];
+    return i;
+}
+
+template <typename R, bool SET>
+__global__ __launch_bounds__(kThreads) void k_access(typename Cx<R>::T* __restrict__ psi,
+                                                     typename Cx<R>::T* __restrict__ buf, AccessArgs a)
+{
+    for (uint64_t k = uint64_t(blockIdx.x) * kThreads + threadIdx.x; k < a.count; k += uint64_t(gridDim.x) * kThreads) {
+        const uint64_t i = access_index(a.first + k, a);
+        if (SET)
+            psi[i] = buf[k];
+        else
+            buf[k] = psi[i];
+    }
+}
+
 }  // namespace
 
 void launch_set_basis(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, uint64_t x)
@@ -1182,6 +1247,74 @@ void run_expect_matrix(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, co
         run_expect_matrix_t<float>(h, psi, n, m, targets, k, out);
     else
         run_expect_matrix_t<double>(h, psi, n, m, targets, k, out);
+}
+
+
+void launch_swap_bits(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, const int32_t* pairs, int n_pairs,
+                      const int32_t* mask_bits, const int32_t* mask_values, int n_mask)
+{
+    SwapArgs a{};
+    a.n_pairs = n_pairs;
+    for (int p = 0; p < n_pairs; ++p) {
+        a.a[p] = pairs[2 * p];
+        a.b[p] = pairs[2 * p + 1];
+    }
+    a.n_mask = n_mask;
+    for (int m = 0; m < n_mask; ++m) {
+        a.msorted[m] = mask_bits[m];
+        if (mask_values[m]) a.mval |= uint64_t(1) << mask_bits[m];
+    }
+    std::sort(a.msorted, a.msorted + n_mask);
+    a.items = uint64_t(1) << (n - n_mask);
+    if (dt == SV_C64)
+        hipLaunchKernelGGL(k_swap_bits<float>, dim3(grid_for(h, a.items)), dim3(kThreads), 0, h->stream,
+                           static_cast<float2*>(psi), a);
+    else
+        hipLaunchKernelGGL(k_swap_bits<double>, dim3(grid_for(h, a.items)), dim3(kThreads), 0, h->stream,
+                           static_cast<double2*>(psi), a);
+    SV_HIP(hipGetLastError());
+}
+
+void run_accessor(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, const int32_t* ordering, int n_bits,
+                  const int32_t* mask_bits, const int32_t* mask_values, int n_mask, void* host, int64_t begin,
+                  int64_t end, bool set)
+{
+    (void)n;
+    AccessArgs a{};
+    a.n_bits = n_bits;
+    for (int b = 0; b < n_bits; ++b) a.ordering[b] = ordering[b];
+    for (int m = 0; m < n_mask; ++m)
+        if (mask_values[m]) a.mval |= uint64_t(1) << mask_bits[m];
+    const size_t amp = dt == SV_C64 ? 8 : 16;
+    // staged through the workspace after the matrix ring, one chunk at a time
+    const size_t stage_bytes = std::min<size_t>(h->ws_bytes - kMatRingBytes, size_t(32) << 20);
+    const uint64_t chunk = stage_bytes / amp;
+    char* stage = h->ws + kMatRingBytes;
+    char* hb = static_cast<char*>(host);
+    for (int64_t k0 = begin; k0 < end; k0 += int64_t(chunk)) {
+        a.first = uint64_t(k0);
+        a.count = std::min<uint64_t>(chunk, uint64_t(end - k0));
+        char* hp = hb + size_t(k0 - begin) * amp;
+        if (set) SV_HIP(hipMemcpyAsync(stage, hp, a.count * amp, hipMemcpyHostToDevice, h->stream));
+        if (dt == SV_C64) {
+            if (set)
+                hipLaunchKernelGGL((k_access<float, true>), dim3(grid_for(h, a.count)), dim3(kThreads), 0, h->stream,
+                                   static_cast<float2*>(psi), reinterpret_cast<float2*>(stage), a);
+            else
+                hipLaunchKernelGGL((k_access<float, false>), dim3(grid_for(h, a.count)), dim3(kThreads), 0,
+                                   h->stream, static_cast<float2*>(psi), reinterpret_cast<float2*>(stage), a);
+        } else {
+            if (set)
+                hipLaunchKernelGGL((k_access<double, true>), dim3(grid_for(h, a.count)), dim3(kThreads), 0,
+                                   h->stream, static_cast<double2*>(psi), reinterpret_cast<double2*>(stage), a);
+            else
+                hipLaunchKernelGGL((k_access<double, false>), dim3(grid_for(h, a.count)), dim3(kThreads), 0,
+                                   h->stream, static_cast<double2*>(psi), reinterpret_cast<double2*>(stage), a);
+        }
+        SV_HIP(hipGetLastError());
+        if (!set) SV_HIP(hipMemcpyAsync(hp, stage, a.count * amp, hipMemcpyDeviceToHost, h->stream));
+        SV_HIP(hipStreamSynchronize(h->stream));
+    }
 }
 
 }  // namespace sv
