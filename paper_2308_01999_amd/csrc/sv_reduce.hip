@@ -794,6 +794,35 @@ __global__ __launch_bounds__(kThreads) void k_bin_probs(const typename Cx<R>::T*
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// Outcome probabilities of M <= 3 qubits: a fixed partition of the whole
+// state, one accumulator per outcome in registers (every item adds to all of
+// them, 0 to all but its own: exact), then a fixed block reduction per
+// outcome into part[b * gridDim.x + block].
+template <typename R, int M>
+__global__ __launch_bounds__(kThreads) void k_bin_probs_small(const typename Cx<R>::T* __restrict__ psi, uint64_t per,
+                                                              BinArgs a, double* __restrict__ part)
+{
+    __shared__ double wsum[kThreads / 64];
+    const uint64_t i0 = uint64_t(blockIdx.x) * per;
+    double acc[1 << M];
+#pragma unroll
+    for (int b = 0; b < (1 << M); ++b) acc[b] = 0.0;
+    for (uint64_t j = threadIdx.x; j < per; j += kThreads) {
+        const uint64_t i = i0 + j;
+        int bin = 0;
+#pragma unroll
+        for (int q = 0; q < M; ++q) bin |= int((i >> a.qpos[q]) & 1) << q;
+        const double p = prob(psi[i]);
+#pragma unroll
+        for (int b = 0; b < (1 << M); ++b) acc[b] = __dadd_rn(acc[b], bin == b ? p : 0.0);
+    }
+#pragma unroll
+    for (int b = 0; b < (1 << M); ++b) {
+        const double v = block_wave_sum(acc[b], wsum);
+        if (threadIdx.x == 0) part[uint64_t(b) * gridDim.x + blockIdx.x] = v;
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_parity_probs(const typename Cx<R>::T* __restrict__ psi, uint64_t per,
                                                            uint64_t mask, double* __restrict__ part)
@@ -826,6 +855,8 @@ struct CollapseArgs {
     double scale;
 };
 
+constexpr int kColUnits = 8;
+
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_collapse(typename Cx<R>::T* __restrict__ psi, CollapseArgs a)
 {
@@ -833,29 +864,36 @@ __global__ __launch_bounds__(kThreads) void k_collapse(typename Cx<R>::T* __rest
     constexpr int APV = sizeof(T) == 8 ? 2 : 1;  // amplitudes per 16-byte vector
     using V = typename std::conditional<APV == 2, float4, double2>::type;
     const R sc = R(a.scale);
-    for (uint64_t v = uint64_t(blockIdx.x) * kThreads + threadIdx.x; v < a.n_vecs; v += uint64_t(gridDim.x) * kThreads) {
-        const uint64_t i = v * APV;
-        bool keep[APV];
-        bool any = false;
+    const uint64_t v0 = uint64_t(blockIdx.x) * (kThreads * kColUnits) + threadIdx.x;
+    V x[kColUnits];
+    int keep[kColUnits];  // bit e: amplitude e of the vector is kept
+#pragma unroll
+    for (int u = 0; u < kColUnits; ++u) {
+        const uint64_t v = v0 + uint64_t(u) * kThreads;
+        keep[u] = 0;
+        if (v >= a.n_vecs) continue;
 #pragma unroll
         for (int e = 0; e < APV; ++e) {
-            const uint64_t ie = i + e;
-            keep[e] = a.parity >= 0 ? int(__popcll(ie & a.mask) & 1) == a.parity : (ie & a.qmask) == a.obits;
-            any |= keep[e];
+            const uint64_t ie = v * APV + e;
+            const bool k = a.parity >= 0 ? int(__popcll(ie & a.mask) & 1) == a.parity : (ie & a.qmask) == a.obits;
+            keep[u] |= int(k) << e;
         }
-        V* p = reinterpret_cast<V*>(psi + i);
-        if (!any) {
-            *p = V{};
-            continue;
-        }
-        V x = *p;
-        R* f = reinterpret_cast<R*>(&x);
+        if (keep[u]) x[u] = *reinterpret_cast<const V*>(psi + v * APV);
+    }
 #pragma unroll
-        for (int e = 0; e < APV; ++e) {
-            f[2 * e] = keep[e] ? f[2 * e] * sc : R(0);
-            f[2 * e + 1] = keep[e] ? f[2 * e + 1] * sc : R(0);
+    for (int u = 0; u < kColUnits; ++u) {
+        const uint64_t v = v0 + uint64_t(u) * kThreads;
+        if (v >= a.n_vecs) continue;
+        V y{};
+        if (keep[u]) {
+            if constexpr (APV == 2) {
+                y = float4{(keep[u] & 1) ? x[u].x * sc : 0.f, (keep[u] & 1) ? x[u].y * sc : 0.f,
+                           (keep[u] & 2) ? x[u].z * sc : 0.f, (keep[u] & 2) ? x[u].w * sc : 0.f};
+            } else {
+                y = V{x[u].x * sc, x[u].y * sc};
+            }
         }
-        *p = x;
+        *reinterpret_cast<V*>(psi + v * APV) = y;
     }
 }
 
@@ -889,29 +927,79 @@ __device__ __forceinline__ T mul_i_pow(const T v, int e)
     }
 }
 
-template <typename R>
+// exp(i theta (+-1)) v = (c +- i s) v, the sign from the parity of i & z
+template <typename T, typename R>
+__device__ __forceinline__ T rot_phase(const T v, uint64_t i, const RotArgs& a, R c, R s)
+{
+    const R sg = (__popcll(i & a.z) & 1) ? -s : s;
+    return T{c * v.x - sg * v.y, c * v.y + sg * v.x};
+}
+
+// the pair (i, j = i ^ x): new[i] = c v_i + i^(ny+1) s (-1)^popcount(j & z) v_j, and likewise for j
+template <typename T, typename R>
+__device__ __forceinline__ void rot_pair(T& vi, T& vj, uint64_t i, uint64_t j, const RotArgs& a, R c, R s)
+{
+    const R si = (__popcll(j & a.z) & 1) ? -s : s;
+    const R sj = (__popcll(i & a.z) & 1) ? -s : s;
+    const T pi = mul_i_pow<T, R>(T{si * vj.x, si * vj.y}, a.ny + 1);
+    const T pj = mul_i_pow<T, R>(T{sj * vi.x, sj * vi.y}, a.ny + 1);
+    vi = T{c * vi.x + pi.x, c * vi.y + pi.y};
+    vj = T{c * vj.x + pj.x, c * vj.y + pj.y};
+}
+
+// PAIRED (complex64 with bit 0 neither in x nor a control): items 2u and
+// 2u + 1 are the neighbours i, i + 1 and their partners j, j + 1, so both
+// move as 16-byte vectors.
+// One-shot grid: each thread takes kRotUnits units kThreads apart and
+// issues all their loads before any arithmetic.
+constexpr int kRotUnits = 4;
+
+template <typename R, bool PAIRED>
 __global__ __launch_bounds__(kThreads) void k_pauli_rotation(typename Cx<R>::T* __restrict__ psi, RotArgs a)
 {
     using T = typename Cx<R>::T;
+    using V = typename std::conditional<PAIRED, float4, T>::type;  // one or two amplitudes
     const R c = R(a.c), s = R(a.s);
-    for (uint64_t t = uint64_t(blockIdx.x) * kThreads + threadIdx.x; t < a.items; t += uint64_t(gridDim.x) * kThreads) {
-        const uint64_t i = insert_bits0(t, a.ins, a.n_ins) | a.cval;
-        if (a.x == 0) {
-            // exp(i theta (+-1)) = c +- i s
-            const T v = psi[i];
-            const R sg = (__popcll(i & a.z) & 1) ? -s : s;
-            psi[i] = T{c * v.x - sg * v.y, c * v.y + sg * v.x};
-            continue;
+    const uint64_t units = PAIRED ? a.items / 2 : a.items;
+    const uint64_t t0 = uint64_t(blockIdx.x) * (kThreads * kRotUnits) + threadIdx.x;
+    uint64_t ii[kRotUnits];
+    V vi[kRotUnits], vj[kRotUnits];
+#pragma unroll
+    for (int u = 0; u < kRotUnits; ++u) {
+        const uint64_t t = t0 + uint64_t(u) * kThreads;
+        ii[u] = t < units ? (insert_bits0(PAIRED ? 2 * t : t, a.ins, a.n_ins) | a.cval) : ~uint64_t(0);
+        if (ii[u] == ~uint64_t(0)) continue;
+        vi[u] = *reinterpret_cast<const V*>(psi + ii[u]);
+        if (a.x != 0) vj[u] = *reinterpret_cast<const V*>(psi + (ii[u] ^ a.x));
+    }
+#pragma unroll
+    for (int u = 0; u < kRotUnits; ++u) {
+        const uint64_t i = ii[u];
+        if (i == ~uint64_t(0)) continue;
+        if constexpr (PAIRED) {
+            T v0{vi[u].x, vi[u].y}, v1{vi[u].z, vi[u].w};
+            if (a.x == 0) {
+                v0 = rot_phase(v0, i, a, c, s);
+                v1 = rot_phase(v1, i + 1, a, c, s);
+            } else {
+                const uint64_t j = i ^ a.x;
+                T u0{vj[u].x, vj[u].y}, u1{vj[u].z, vj[u].w};
+                rot_pair(v0, u0, i, j, a, c, s);
+                rot_pair(v1, u1, i + 1, j + 1, a, c, s);
+                *reinterpret_cast<float4*>(psi + j) = float4{u0.x, u0.y, u1.x, u1.y};
+            }
+            *reinterpret_cast<float4*>(psi + i) = float4{v0.x, v0.y, v1.x, v1.y};
+        } else {
+            if (a.x == 0) {
+                psi[i] = rot_phase(vi[u], i, a, c, s);
+                continue;
+            }
+            const uint64_t j = i ^ a.x;
+            T x = vi[u], y = vj[u];
+            rot_pair(x, y, i, j, a, c, s);
+            psi[i] = x;
+            psi[j] = y;
         }
-        const uint64_t j = i ^ a.x;
-        const T vi = psi[i], vj = psi[j];
-        // i s (P psi)[i] = i^(ny+1) s (-1)^popcount(j & z) psi[j]
-        const R si = (__popcll(j & a.z) & 1) ? -s : s;
-        const R sj = (__popcll(i & a.z) & 1) ? -s : s;
-        const T pi = mul_i_pow<T, R>(T{si * vj.x, si * vj.y}, a.ny + 1);
-        const T pj = mul_i_pow<T, R>(T{sj * vi.x, sj * vi.y}, a.ny + 1);
-        psi[i] = T{c * vi.x + pi.x, c * vi.y + pi.y};
-        psi[j] = T{c * vj.x + pj.x, c * vj.y + pj.y};
     }
 }
 
@@ -984,8 +1072,27 @@ void run_bin_probs_t(sv_handle_s* h, const void* psi_v, int n, const int32_t* qu
     a.m = m;
     for (int b = 0; b < m; ++b) a.qpos[b] = a.qsorted[b] = qubits[b];
     std::sort(a.qsorted, a.qsorted + m);
-    const uint64_t items = uint64_t(1) << (n - m);
     const uint64_t bins = uint64_t(1) << m;
+    if (m <= 3) {
+        // few outcomes: per-thread accumulators over one contiguous sweep
+        const Partition P = partition(uint64_t(1) << n);
+        double* part = reinterpret_cast<double*>(h->ws + kMatRingBytes);
+        double* res = part + bins * P.nb;
+        const T2* psi = static_cast<const T2*>(psi_v);
+        if (m == 1)
+            hipLaunchKernelGGL((k_bin_probs_small<R, 1>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, P.per, a, part);
+        else if (m == 2)
+            hipLaunchKernelGGL((k_bin_probs_small<R, 2>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, P.per, a, part);
+        else
+            hipLaunchKernelGGL((k_bin_probs_small<R, 3>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, P.per, a, part);
+        SV_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_finish_sums, dim3(unsigned(bins)), dim3(kThreads), 0, h->stream, part, P.nb, res);
+        SV_HIP(hipGetLastError());
+        SV_HIP(hipMemcpyAsync(out, res, sizeof(double) * bins, hipMemcpyDeviceToHost, h->stream));
+        SV_HIP(hipStreamSynchronize(h->stream));
+        return;
+    }
+    const uint64_t items = uint64_t(1) << (n - m);
     uint64_t nbp = std::max<uint64_t>(1, std::min<uint64_t>(items / 2048, std::max<uint64_t>(1, 8192 / bins)));
     a.nbp = nbp;
     a.per = items / nbp;
@@ -1200,15 +1307,15 @@ void launch_collapse(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, uint64_t q
     a.mask = parity_mask;
     a.parity = parity;
     a.scale = scale;
-    if (dt == SV_C64) {
-        a.n_vecs = dim / 2;
-        hipLaunchKernelGGL(k_collapse<float>, dim3(grid_for(h, a.n_vecs)), dim3(kThreads), 0, h->stream,
+    a.n_vecs = dt == SV_C64 ? dim / 2 : dim;
+    const uint64_t blocks = (a.n_vecs + kThreads * kColUnits - 1) / (kThreads * kColUnits);
+    SV_CHECK(blocks <= 0x7fffffffu, "state too large for one launch");
+    if (dt == SV_C64)
+        hipLaunchKernelGGL(k_collapse<float>, dim3(unsigned(blocks)), dim3(kThreads), 0, h->stream,
                            static_cast<float2*>(psi), a);
-    } else {
-        a.n_vecs = dim;
-        hipLaunchKernelGGL(k_collapse<double>, dim3(grid_for(h, a.n_vecs)), dim3(kThreads), 0, h->stream,
+    else
+        hipLaunchKernelGGL(k_collapse<double>, dim3(unsigned(blocks)), dim3(kThreads), 0, h->stream,
                            static_cast<double2*>(psi), a);
-    }
     SV_HIP(hipGetLastError());
 }
 
@@ -1231,12 +1338,21 @@ void launch_pauli_rotation(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, cons
     a.n_ins = int(ins.size());
     for (size_t b = 0; b < ins.size(); ++b) a.ins[b] = ins[b];
     a.items = uint64_t(1) << (n - a.n_ins);
-    if (dt == SV_C64)
-        hipLaunchKernelGGL(k_pauli_rotation<float>, dim3(grid_for(h, a.items)), dim3(kThreads), 0, h->stream,
-                           static_cast<float2*>(psi), a);
+    const bool bit0_free = (a.n_ins == 0 || a.ins[0] != 0) && !(pm.x & 1);
+    auto blocks = [](uint64_t units) {
+        const uint64_t b = (units + kThreads * kRotUnits - 1) / (kThreads * kRotUnits);
+        SV_CHECK(b <= 0x7fffffffu, "state too large for one launch");
+        return unsigned(b);
+    };
+    if (dt == SV_C64 && bit0_free)
+        hipLaunchKernelGGL((k_pauli_rotation<float, true>), dim3(blocks(a.items / 2)), dim3(kThreads), 0,
+                           h->stream, static_cast<float2*>(psi), a);
+    else if (dt == SV_C64)
+        hipLaunchKernelGGL((k_pauli_rotation<float, false>), dim3(blocks(a.items)), dim3(kThreads), 0,
+                           h->stream, static_cast<float2*>(psi), a);
     else
-        hipLaunchKernelGGL(k_pauli_rotation<double>, dim3(grid_for(h, a.items)), dim3(kThreads), 0, h->stream,
-                           static_cast<double2*>(psi), a);
+        hipLaunchKernelGGL((k_pauli_rotation<double, false>), dim3(blocks(a.items)), dim3(kThreads), 0,
+                           h->stream, static_cast<double2*>(psi), a);
     SV_HIP(hipGetLastError());
 }
 
