@@ -37,16 +37,17 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE reads them all, x1.0).  Valid only for the kernel source the
 # counters were taken on: its SHA-256 is recorded and checked at run time.
 PMC_TRAFFIC = {
-    # 30-qubit brickwork sweep, dispatch-weighted over both tile shapes
-    # (c64: 518 narrow + 80 wide launches per pass; c128: 540 + 58)
-    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194404.1, "write_kib": 8389796.9,
+    # 30-qubit brickwork sweep, dispatch-weighted over all tile variants
+    # (c64: 675 narrow-shape + 83 wide launches per pass; c128: 697 + 61
+    # fetch, 680 + 78 write)
+    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194404.8, "write_kib": 8389775.5,
                       "fetch_scale": 2.0, "write_scale": 1.0,
                       "source": "paper_2308_01999_amd/csrc/sv_apply.hip",
-                      "source_sha256": "101ccacca555b7f4c72b33306d06e04d69cf4d50d0ed8126a1394f86263308b8"},
-    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388721.3, "write_kib": 16779646.7,
+                      "source_sha256": "2b960ba471b366b2b81692c595722df9218f1b87a672e5e9ca569b449a123012"},
+    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388721.2, "write_kib": 16780932.6,
                        "fetch_scale": 2.0, "write_scale": 1.0,
                        "source": "paper_2308_01999_amd/csrc/sv_apply.hip",
-                       "source_sha256": "101ccacca555b7f4c72b33306d06e04d69cf4d50d0ed8126a1394f86263308b8"},
+                       "source_sha256": "2b960ba471b366b2b81692c595722df9218f1b87a672e5e9ca569b449a123012"},
 }
 
 

@@ -1036,17 +1036,25 @@ __global__ __launch_bounds__(kThreads) void k_expect_matrix(const typename Cx<R>
         T x[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) x[c] = psi[b + a.off[c]];
-        // rows one at a time (x_r read again: a cache hit), columns unrolled
+        // K <= 3: rows and columns unrolled, x_r straight from the
+        // registers (a compiler barrier per row keeps M's entries from being
+        // hoisted into registers all at once).  K > 3: rows one at a time;
+        // x_r is read again (a cache hit), since indexing the register
+        // array with a run-time row would put it in scratch memory.
+#pragma unroll
+        for (int rr = 0; rr < (K <= 3 ? D : 1); ++rr)
 #pragma unroll 1
-        for (int r = 0; r < D; ++r) {
+        for (int r2 = 0; r2 < (K <= 3 ? 1 : D); ++r2) {
+            const int r = K <= 3 ? rr : r2;
+            asm volatile("" ::: "memory");
             double yr = 0.0, yi = 0.0;
 #pragma unroll
             for (int c = 0; c < D; ++c) {
-                const double2 m = M[r * D + c];
-                yr = fma(m.x, double(x[c].x), fma(-m.y, double(x[c].y), yr));
-                yi = fma(m.x, double(x[c].y), fma(m.y, double(x[c].x), yi));
+                const double mx = M[r * D + c].x, my = M[r * D + c].y;
+                yr = fma(mx, double(x[c].x), fma(-my, double(x[c].y), yr));
+                yi = fma(mx, double(x[c].y), fma(my, double(x[c].x), yi));
             }
-            const T v = psi[b + a.off[r]];
+            const T v = K <= 3 ? x[rr] : psi[b + a.off[r]];
             const double vr = double(v.x), vi = double(v.y);
             // conj(x_r) y
             re = fma(vr, yr, fma(vi, yi, re));
