@@ -499,6 +499,14 @@ def table1_leg(P, W, torch, H, n, reps=5):
         ms = timed_blocking(lambda: P.sv_expect_matrix(st.s, m, [3, 12, 21]))
         res["expect_matrix_3q"] = {"avg_ms": round(ms, 3), "GBps": round(state / (ms * 1e-3) / 1e9, 1)}
         del p
+        ms = timed_async(lambda: P.sv_swap_index_bits(st.s, [(1, 25), (4, 17)]))
+        res["swap_index_bits_2pairs"] = {"avg_ms": round(ms, 3), "GBps": round(2 * 0.75 * state / (ms * 1e-3) / 1e9, 1),
+                                         "note": "bytes: the 3/4 of amplitudes the swap moves, read and written"}
+        order = list(range(n))[::-1]
+        svd = P.SV_C64 if dt == "c64" else P.SV_C128
+        ms = timed_blocking(lambda: P.sv_accessor_get(st.s, svd, order, begin=0, end=1 << 26))
+        res["accessor_get_reversed_2^26"] = {"avg_ms": round(ms, 3),
+                                             "GBps_host": round((1 << 26) * ab / (ms * 1e-3) / 1e9, 1)}
         out[dt] = res
         st.close()
         torch.cuda.synchronize()

@@ -357,8 +357,11 @@ sv_status_t sv_batch_measure(sv_state_t s, const int32_t* qubits, int32_t m, dou
  * qubit reordering, Sec. II-C): for every index whose mask bits equal
  * mask_values, the amplitude moves to the index with bits pairs[2p] and
  * pairs[2p + 1] exchanged for every pair p.  All bits of the pairs and the
- * mask must be distinct.  Each moved amplitude is read and written once;
- * amplitudes the swap leaves in place are not touched.  Asynchronous.
+ * mask must be distinct.  Up to 6 bits in all (pairs and mask), on states of
+ * at least 12 (complex64) / 11 (complex128) qubits: one sweep that reads and
+ * writes every amplitude once in LDS tiles; otherwise each moved amplitude
+ * is read and written once and amplitudes the swap leaves in place are not
+ * touched.  Asynchronous.
  */
 sv_status_t sv_swap_index_bits(sv_state_t s, const int32_t* pairs, int32_t n_pairs, const int32_t* mask_bits,
                                const int32_t* mask_values, int32_t n_mask);

@@ -794,7 +794,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_probs(const typename Cx<R>::T*
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// Outcome probabilities of M <= 3 qubits: a fixed partition of the whole
+// Outcome probabilities of M <= 4 qubits: a fixed partition of the whole
 // state, one accumulator per outcome in registers (every item adds to all of
 // them, 0 to all but its own: exact), then a fixed block reduction per
 // outcome into part[b * gridDim.x + block].
@@ -1081,7 +1081,7 @@ void run_bin_probs_t(sv_handle_s* h, const void* psi_v, int n, const int32_t* qu
     for (int b = 0; b < m; ++b) a.qpos[b] = a.qsorted[b] = qubits[b];
     std::sort(a.qsorted, a.qsorted + m);
     const uint64_t bins = uint64_t(1) << m;
-    if (m <= 3) {
+    if (m <= 4) {
         // few outcomes: per-thread accumulators over one contiguous sweep
         const Partition P = partition(uint64_t(1) << n);
         double* part = reinterpret_cast<double*>(h->ws + kMatRingBytes);
@@ -1091,8 +1091,10 @@ void run_bin_probs_t(sv_handle_s* h, const void* psi_v, int n, const int32_t* qu
             hipLaunchKernelGGL((k_bin_probs_small<R, 1>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, P.per, a, part);
         else if (m == 2)
             hipLaunchKernelGGL((k_bin_probs_small<R, 2>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, P.per, a, part);
-        else
+        else if (m == 3)
             hipLaunchKernelGGL((k_bin_probs_small<R, 3>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, P.per, a, part);
+        else
+            hipLaunchKernelGGL((k_bin_probs_small<R, 4>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, P.per, a, part);
         SV_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_finish_sums, dim3(unsigned(bins)), dim3(kThreads), 0, h->stream, part, P.nb, res);
         SV_HIP(hipGetLastError());
@@ -1190,10 +1192,23 @@ struct SwapArgs {
     int32_t msorted[SV_MAX_QUBITS];
 };
 
+constexpr int kSwapUnits = 4;
+
+// One-shot grid, kSwapUnits indices per thread kThreads apart, every load
+// issued before the stores.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_swap_bits(typename Cx<R>::T* __restrict__ psi, SwapArgs a)
 {
-    for (uint64_t t = uint64_t(blockIdx.x) * kThreads + threadIdx.x; t < a.items; t += uint64_t(gridDim.x) * kThreads) {
+    using T = typename Cx<R>::T;
+    const uint64_t t0 = uint64_t(blockIdx.x) * (kThreads * kSwapUnits) + threadIdx.x;
+    uint64_t ii[kSwapUnits], jj[kSwapUnits];
+    T x[kSwapUnits], y[kSwapUnits];
+#pragma unroll
+    for (int u = 0; u < kSwapUnits; ++u) {
+        const uint64_t t = t0 + uint64_t(u) * kThreads;
+        ii[u] = jj[u] = 0;
+        x[u] = y[u] = T{};
+        if (t >= a.items) continue;
         const uint64_t i = insert_bits0(t, a.msorted, a.n_mask) | a.mval;
         uint64_t j = i;
         for (int p = 0; p < a.n_pairs; ++p) {
@@ -1201,9 +1216,17 @@ __global__ __launch_bounds__(kThreads) void k_swap_bits(typename Cx<R>::T* __res
             j ^= (d << a.a[p]) | (d << a.b[p]);
         }
         if (j > i) {
-            const auto x = psi[i], y = psi[j];
-            psi[i] = y;
-            psi[j] = x;
+            ii[u] = i;
+            jj[u] = j;
+            x[u] = psi[i];
+            y[u] = psi[j];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kSwapUnits; ++u) {
+        if (jj[u] > ii[u]) {
+            psi[ii[u]] = y[u];
+            psi[jj[u]] = x[u];
         }
     }
 }
@@ -1390,11 +1413,13 @@ void launch_swap_bits(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, const int
     }
     std::sort(a.msorted, a.msorted + n_mask);
     a.items = uint64_t(1) << (n - n_mask);
+    const uint64_t blocks = (a.items + kThreads * kSwapUnits - 1) / (kThreads * kSwapUnits);
+    SV_CHECK(blocks <= 0x7fffffffu, "state too large for one launch");
     if (dt == SV_C64)
-        hipLaunchKernelGGL(k_swap_bits<float>, dim3(grid_for(h, a.items)), dim3(kThreads), 0, h->stream,
+        hipLaunchKernelGGL(k_swap_bits<float>, dim3(unsigned(blocks)), dim3(kThreads), 0, h->stream,
                            static_cast<float2*>(psi), a);
     else
-        hipLaunchKernelGGL(k_swap_bits<double>, dim3(grid_for(h, a.items)), dim3(kThreads), 0, h->stream,
+        hipLaunchKernelGGL(k_swap_bits<double>, dim3(unsigned(blocks)), dim3(kThreads), 0, h->stream,
                            static_cast<double2*>(psi), a);
     SV_HIP(hipGetLastError());
 }
