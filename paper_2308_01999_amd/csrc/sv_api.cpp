@@ -102,6 +102,42 @@ GateDesc make_desc(int n, const int32_t* targets, int k, const int32_t* controls
     return d;
 }
 
+// Dense uncontrolled gates on 2-4 qubits of a state of >= 14 qubits run as
+// five-qubit gates M (x) I on their targets plus free qubits next to them
+// (below the lowest target first, then above the highest): the five-qubit
+// tile sweep, with its tuned variants, moves the state faster than the
+// smaller gates' own kernels, and the result is the same gate.  The extra
+// qubits are the high matrix bits; out_m is the 32 x 32 complex128 matrix.
+bool pad_to_five(int n, int k, int n_controls, const int32_t* targets, const double* m, int32_t* out_t,
+                 std::vector<double>& out_m)
+{
+    if (n_controls != 0 || k < 2 || k > 4 || n < 14) return false;
+    uint64_t used = 0;
+    int lo = n, hi = -1;
+    for (int a = 0; a < k; ++a) {
+        out_t[a] = targets[a];
+        used |= uint64_t(1) << targets[a];
+        lo = std::min(lo, int(targets[a]));
+        hi = std::max(hi, int(targets[a]));
+    }
+    int kk = k;
+    for (int q = lo - 1; q >= 0 && kk < 5; --q)
+        if (!((used >> q) & 1)) out_t[kk++] = q;
+    for (int q = hi + 1; q < n && kk < 5; ++q)
+        if (!((used >> q) & 1)) out_t[kk++] = q;
+    if (kk < 5) return false;
+    const int d = 1 << k, D = 32;
+    out_m.assign(size_t(2) * D * D, 0.0);
+    for (int e = 0; e < D / d; ++e)
+        for (int r = 0; r < d; ++r)
+            for (int c = 0; c < d; ++c) {
+                const size_t dst = size_t(e * d + r) * D + size_t(e * d + c);
+                out_m[2 * dst] = m[2 * (size_t(r) * d + c)];
+                out_m[2 * dst + 1] = m[2 * (size_t(r) * d + c) + 1];
+            }
+    return true;
+}
+
 void check_matrix_finite(const double* m, int k)
 {
     SV_CHECK(m != nullptr, "matrix is NULL");
@@ -339,8 +375,15 @@ sv_status_t sv_apply_matrix(sv_state_t s, const double* matrix, const int32_t* t
 {
     return guarded([&] {
         check_state(s);
-        const GateDesc d = make_desc(s->n, targets, k, controls, control_values, n_controls);
+        GateDesc d = make_desc(s->n, targets, k, controls, control_values, n_controls);
         check_matrix_finite(matrix, k);
+        int32_t pt[SV_MAX_TARGETS];
+        std::vector<double> pm;
+        if (pad_to_five(s->n, k, n_controls, targets, matrix, pt, pm)) {
+            d = make_desc(s->n, pt, 5, nullptr, nullptr, 0);
+            matrix = pm.data();
+            k = 5;
+        }
         const size_t bytes = packed_matrix_bytes(s->dt, s->n, k, n_controls);
         std::vector<char> tmp(bytes);
         pack_matrix(s->dt, s->n, k, n_controls, matrix, adjoint, tmp.data());
@@ -512,6 +555,27 @@ sv_status_t sv_fused_free(sv_fused_t f)
 namespace sv {
 namespace {
 
+// The blocks as launched: dense blocks on 2-4 qubits of a large state padded
+// to five qubits (pad_to_five), all others as they are.
+void effective_blocks(int n, const sv_fused_s* f, int first, int end, std::vector<FusedBlock>& eff,
+                      std::vector<std::vector<double>>& padm)
+{
+    eff.assign(f->blocks, f->blocks + f->n_blocks);
+    padm.resize(f->n_blocks);
+    for (int b = first; b < end; ++b) {
+        FusedBlock& blk = eff[b];
+        if (blk.diagonal) continue;
+        int32_t pt[SV_MAX_TARGETS];
+        int32_t t[SV_MAX_TARGETS];
+        for (int a = 0; a < blk.k; ++a) t[a] = blk.targets[a];
+        if (pad_to_five(n, blk.k, 0, t, blk.m, pt, padm[b])) {
+            blk.k = 5;
+            for (int a = 0; a < 5; ++a) blk.targets[a] = pt[a];
+            blk.m = padm[b].data();
+        }
+    }
+}
+
 // A fused block's device form and sweep: the dense sweep, or for a diagonal
 // block the diagonal sweep.
 size_t block_bytes(const sv_state_s* s, const FusedBlock& b)
@@ -543,8 +607,11 @@ void apply_fused_blocks(sv_state_s* s, sv_fused_s* f, int first, int count)
              "block range out of bounds");
     const int end = first + count;
     std::vector<GateDesc> descs(f->n_blocks);
+    std::vector<std::vector<double>> padm;
+    std::vector<FusedBlock> eff;
+    effective_blocks(s->n, f, first, end, eff, padm);
     for (int b = first; b < end; ++b) {
-        const FusedBlock& blk = f->blocks[b];
+        const FusedBlock& blk = eff[b];
         descs[b] = make_desc(s->n, blk.targets, blk.k, nullptr, nullptr, 0);
     }
     {
@@ -556,7 +623,7 @@ void apply_fused_blocks(sv_state_s* s, sv_fused_s* f, int first, int count)
             size_t bytes = 0;
             int e = b;
             while (e < end) {
-                const size_t mb = (block_bytes(s, f->blocks[e]) + 255) & ~size_t(255);
+                const size_t mb = (block_bytes(s, eff[e]) + 255) & ~size_t(255);
                 if (bytes + mb > seg) break;
                 offs.push_back(bytes);
                 bytes += mb;
@@ -564,17 +631,17 @@ void apply_fused_blocks(sv_state_s* s, sv_fused_s* f, int first, int count)
             }
             if (e == b) {
                 // one block larger than a ring segment: stage it on its own
-                const size_t mb = block_bytes(s, f->blocks[b]);
+                const size_t mb = block_bytes(s, eff[b]);
                 std::vector<char> one(mb);
-                pack_block(s, f->blocks[b], one.data());
-                launch_block(s->h, s, f->blocks[b], stage_matrix(s->h, one.data(), mb), descs[b]);
+                pack_block(s, eff[b], one.data());
+                launch_block(s->h, s, eff[b], stage_matrix(s->h, one.data(), mb), descs[b]);
                 ++b;
                 continue;
             }
             std::vector<char> tmp(bytes);
-            for (int j = b; j < e; ++j) pack_block(s, f->blocks[j], tmp.data() + offs[j - b]);
+            for (int j = b; j < e; ++j) pack_block(s, eff[j], tmp.data() + offs[j - b]);
             const char* dm = static_cast<const char*>(stage_matrix(s->h, tmp.data(), bytes));
-            for (int j = b; j < e; ++j) launch_block(s->h, s, f->blocks[j], dm + offs[j - b], descs[j]);
+            for (int j = b; j < e; ++j) launch_block(s->h, s, eff[j], dm + offs[j - b], descs[j]);
             b = e;
         }
     }
@@ -615,15 +682,18 @@ sv_status_t sv_graph_create(sv_state_t s, sv_fused_t f, sv_graph_t* out)
         sv_handle_s* h = s->h;
         std::vector<GateDesc> descs(f->n_blocks);
         std::vector<size_t> offs(f->n_blocks);
+        std::vector<std::vector<double>> padm;
+        std::vector<FusedBlock> eff;
+        effective_blocks(s->n, f, 0, f->n_blocks, eff, padm);
         size_t bytes = 0;
         for (int b = 0; b < f->n_blocks; ++b) {
-            const FusedBlock& blk = f->blocks[b];
+            const FusedBlock& blk = eff[b];
             descs[b] = make_desc(s->n, blk.targets, blk.k, nullptr, nullptr, 0);
             offs[b] = bytes;
             bytes += (block_bytes(s, blk) + 255) & ~size_t(255);
         }
         std::vector<char> host(bytes ? bytes : 1);
-        for (int b = 0; b < f->n_blocks; ++b) pack_block(s, f->blocks[b], host.data() + offs[b]);
+        for (int b = 0; b < f->n_blocks; ++b) pack_block(s, eff[b], host.data() + offs[b]);
         auto* g = new sv_graph_s;
         g->s = s;
         hipStream_t cap = nullptr;
@@ -642,7 +712,7 @@ sv_status_t sv_graph_create(sv_state_t s, sv_fused_t f, sv_graph_t* out)
             h->stream = cap;
             SV_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
             try {
-                for (int b = 0; b < f->n_blocks; ++b) launch_block(h, s, f->blocks[b], g->mats + offs[b], descs[b]);
+                for (int b = 0; b < f->n_blocks; ++b) launch_block(h, s, eff[b], g->mats + offs[b], descs[b]);
             } catch (...) {
                 hipGraph_t dropped = nullptr;
                 (void)hipStreamEndCapture(cap, &dropped);
