@@ -371,13 +371,9 @@ __device__ __forceinline__ float4 swap_pair(const float4 v, bool sw)
     return sw ? float4{v.z, v.w, v.x, v.y} : v;
 }
 
-// With SV_K5_A2_FLY the third operand Re M + Im M is summed in registers
-// instead of kept in LDS: 40 KiB of LDS per workgroup instead of 44, so four
-// workgroups fit a CU's 160 KiB instead of three.
-#ifndef SV_K5_A2_FLY
-#define SV_K5_A2_FLY 0
-#endif
-constexpr int kK5AParts = SV_K5_A2_FLY ? 2 : 3;
+// The three A operands (Re M, Im M, Re M + Im M) of the complex64 k = 5
+// sweep, kept in LDS (44 KiB per workgroup with the tile: three per CU).
+constexpr int kK5AParts = 3;
 
 // The wide shape of the complex64 k = 5 sweep: 64 KiB tiles in 512-thread
 // workgroups (8 waves, 256 groups), so every run of a tile is 2 KiB long
@@ -441,8 +437,7 @@ __global__ __launch_bounds__(NT, NT == 512 ? SV_K5_WIDE_WAVES : 1) void k_tile_c
         for (int q = 0; q < 4; ++q) {
             const float4 vr = amat[(0 * 64 + lane) * 4 + q];
             const float4 vi = amat[(1 * 64 + lane) * 4 + q];
-            const float4 vs = (kK5AParts == 3) ? amat[((kK5AParts - 1) * 64 + lane) * 4 + q]
-                                               : float4{vr.x + vi.x, vr.y + vi.y, vr.z + vi.z, vr.w + vi.w};
+            const float4 vs = amat[(2 * 64 + lane) * 4 + q];
             const float ar[4] = {vr.x, vr.y, vr.z, vr.w};
             const float ai[4] = {vi.x, vi.y, vi.z, vi.w};
             const float as[4] = {vs.x, vs.y, vs.z, vs.w};
@@ -537,10 +532,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict
 
 // complex128, k = 5 on v_mfma_f64_16x16x4_f64: 64 groups per tile, one
 // 16-column tile per wave; two 16-row tiles cover the 32 output amplitudes.
-// A_g slices per lane: 2 row tiles x 8 k-steps = 16 doubles.
-#ifndef SV_C128_A_LDS
-#define SV_C128_A_LDS 1
-#endif
+// Re M and Im M are staged in LDS, lane-contiguous (16 KiB), and summed at
+// use for the third product, which keeps 48 doubles per lane out of the
+// registers: three workgroups per CU instead of two.
 // NT = 256: 32 KiB tiles (2048 amplitudes); NT = 512: 64 KiB tiles (the
 // wide shape), eight waves.
 template <int NT>
@@ -548,29 +542,18 @@ __global__ __launch_bounds__(NT) void k_tile_c128_k5(double2* __restrict__ psi,
                                                               const double2* __restrict__ mats, TileArgs a)
 {
     __shared__ double2 lds[NT * kTileVecs];
-    // SV_C128_A_LDS: Re M and Im M staged in LDS lane-contiguous (16 KiB;
-    // Re M + Im M summed at use) instead of 48 doubles per lane in registers
-    __shared__ double amat[SV_C128_A_LDS ? 2 * 16 * 64 : 1];
+    __shared__ double amat[2 * 16 * 64];
     const uint64_t t0 = uint64_t(blockIdx.x) * a.tiles_per_wg;
     if (t0 >= a.n_tiles) return;
     const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15, q = lane >> 4;
-    double A[3][16];
-    if (SV_C128_A_LDS) {
+    {
+        // packed A_g: lane l holds its 16 doubles contiguously; LDS: [g][j][l]
         const double* m1 = reinterpret_cast<const double*>(mats);
         for (int e = tid; e < 2 * 16 * 64; e += NT) {
             const int g = e >> 10, j = (e >> 6) & 15, l = e & 63;
             amat[e] = m1[(g * 64 + l) * 16 + j];
         }
-    } else {
-#pragma unroll
-        for (int g = 0; g < 3; ++g)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const double2 v = mats[(g * 64 + lane) * 8 + e];
-                A[g][2 * e] = v.x;
-                A[g][2 * e + 1] = v.y;
-            }
     }
     uint64_t roff[kTileVecs];
     uint32_t poff[kTileVecs];
@@ -605,16 +588,9 @@ __global__ __launch_bounds__(NT) void k_tile_c128_k5(double2* __restrict__ psi,
             f64x4 p1 = {0}, p2 = {0}, p3 = {0};
 #pragma unroll
             for (int s8 = 0; s8 < 8; ++s8) {
-                double a0, a1, a2;
-                if (SV_C128_A_LDS) {
-                    a0 = amat[(0 * 16 + rt * 8 + s8) * 64 + lane];
-                    a1 = amat[(1 * 16 + rt * 8 + s8) * 64 + lane];
-                    a2 = a0 + a1;
-                } else {
-                    a0 = A[0][rt * 8 + s8];
-                    a1 = A[1][rt * 8 + s8];
-                    a2 = A[2][rt * 8 + s8];
-                }
+                const double a0 = amat[(0 * 16 + rt * 8 + s8) * 64 + lane];
+                const double a1 = amat[(1 * 16 + rt * 8 + s8) * 64 + lane];
+                const double a2 = a0 + a1;
                 p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x[s8].x, p1, 0, 0, 0);
                 p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x[s8].y, p2, 0, 0, 0);
                 p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, x[s8].x + x[s8].y, p3, 0, 0, 0);
