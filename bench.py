@@ -38,16 +38,15 @@ HBM_PEAK_GBS = 8000.0
 # counters were taken on: its SHA-256 is recorded and checked at run time.
 PMC_TRAFFIC = {
     # 30-qubit brickwork sweep, dispatch-weighted over all tile variants
-    # (c64: 675 narrow-shape + 83 wide launches per pass; c128: 697 + 61
-    # fetch, 680 + 78 write)
-    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194404.8, "write_kib": 8389775.5,
+    # (c64: 778 launches of the 256-thread shapes + 102 wide; c128: 770 + 110)
+    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194404.7, "write_kib": 8389961.0,
                       "fetch_scale": 2.0, "write_scale": 1.0,
                       "source": "paper_2308_01999_amd/csrc/sv_apply.hip",
-                      "source_sha256": "2b960ba471b366b2b81692c595722df9218f1b87a672e5e9ca569b449a123012"},
-    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388721.2, "write_kib": 16780932.6,
+                      "source_sha256": "7bd9f80ec412a33a8306ce9324964b3757d1df764799a3a619ae54f536cabf2e"},
+    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388720.7, "write_kib": 16781059.1,
                        "fetch_scale": 2.0, "write_scale": 1.0,
                        "source": "paper_2308_01999_amd/csrc/sv_apply.hip",
-                       "source_sha256": "2b960ba471b366b2b81692c595722df9218f1b87a672e5e9ca569b449a123012"},
+                       "source_sha256": "7bd9f80ec412a33a8306ce9324964b3757d1df764799a3a619ae54f536cabf2e"},
 }
 
 
