@@ -10,6 +10,13 @@
 // product), k <= 3 on the vector ALUs.  The workgroup records its
 // circuit's completion on the device wall clock.  Every workgroup exits
 // once the queue is empty; no workgroup waits on another.
+//
+// A workgroup reads back only what it wrote itself (its circuit's state),
+// so the workgroup-scope fences of its barriers order all of its memory
+// traffic; a device-scope fence would also write back and invalidate the
+// L2 at every block.  Block descriptors and matrices are staged in LDS once
+// per block, so that the tile loop's only vector-memory waits are those on
+// the state's own tiles.
 #include <hip/hip_runtime.h>
 
 #include "sv_batch.h"
@@ -92,15 +99,18 @@ __device__ __forceinline__ void region_mfma5(float2* lds, const BatchBlock& b, c
         const int pb = spread_lo(valid ? gl : 0, g);
         const int pin = pb + (half ? g.off[1] : 0);
         const int pout = pb + (half ? g.off[4] : 0);
-        float2 x[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const float2 v = lds[swz(pin + g.off[2 * j])];
-            x[j] = valid ? v : float2{0.f, 0.f};
-        }
         f32x16 p1 = {0}, p2 = {0}, p3 = {0};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
+            // one quarter of the B operands live at a time (the compiler
+            // would otherwise load all 16 up front, 32 more registers)
+            asm volatile("" ::: "memory");
+            float2 x[4];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const float2 v = lds[swz(pin + g.off[2 * (4 * q + jj)])];
+                x[jj] = valid ? v : float2{0.f, 0.f};
+            }
             const float4 vr = amat[(0 * 64 + lane) * 4 + q];
             const float4 vi = amat[(1 * 64 + lane) * 4 + q];
             const float4 vs = amat[(2 * 64 + lane) * 4 + q];
@@ -109,7 +119,7 @@ __device__ __forceinline__ void region_mfma5(float2* lds, const BatchBlock& b, c
             const float as[4] = {vs.x, vs.y, vs.z, vs.w};
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
-                const float2 xv = x[4 * q + jj];
+                const float2 xv = x[jj];
                 p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[jj], xv.x, p1, 0, 0, 0);
                 p2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[jj], xv.y, p2, 0, 0, 0);
                 p3 = __builtin_amdgcn_mfma_f32_32x32x2f32(as[jj], xv.x + xv.y, p3, 0, 0, 0);
@@ -194,26 +204,33 @@ __device__ __forceinline__ void region_valu(float2* lds, const BatchBlock& b, co
     }
 }
 
-// Copies block b's packed A operands to LDS (k = 4, 5); the caller
-// synchronises before they are read.
-__device__ __forceinline__ void stage_a(const float* __restrict__ mats, const BatchBlock& b, float4* amat)
+// Copies block b's matrix to LDS: the packed A operands for k = 4, 5, the
+// complex64 matrix for k <= 3.  The caller synchronises before it is read.
+__device__ __forceinline__ void stage_matrix(const float* __restrict__ mats, const BatchBlock& b, float4* amat)
 {
-    const float4* m4 = reinterpret_cast<const float4*>(mats + b.mat_off);
-    const int n4 = b.k == 5 ? kAmat : b.k == 4 ? 3 * 64 : 0;
-    for (int e = threadIdx.x; e < n4; e += kThreads) amat[e] = m4[e];
+    const int k = __builtin_amdgcn_readfirstlane(b.k);
+    if (k >= 4) {
+        const float4* m4 = reinterpret_cast<const float4*>(mats + b.mat_off);
+        const int n4 = k == 5 ? kAmat : 3 * 64;
+        for (int e = threadIdx.x; e < n4; e += kThreads) amat[e] = m4[e];
+    } else {
+        const float2* m2 = reinterpret_cast<const float2*>(mats + b.mat_off);
+        float2* d2 = reinterpret_cast<float2*>(amat);
+        for (int e = threadIdx.x; e < (1 << (2 * k)); e += kThreads) d2[e] = m2[e];
+    }
 }
 
-// Applies block b to the region in LDS (A operands already staged in LDS
-// for k = 4, 5).  Callers synchronise before and after.
-__device__ __forceinline__ void apply_region(float2* lds, const BatchBlock& b, const float* __restrict__ mats,
-                                             const float4* amat)
+// Applies block b to the region in LDS (descriptor and matrix already
+// staged in LDS).  Callers synchronise before and after.
+__device__ __forceinline__ void apply_region(float2* lds, const BatchBlock& b, const float4* amat)
 {
-    switch (b.k) {
+    const float2* m2 = reinterpret_cast<const float2*>(amat);
+    switch (__builtin_amdgcn_readfirstlane(b.k)) {
         case 5: region_mfma5(lds, b, amat); break;
         case 4: region_mfma4(lds, b, amat); break;
-        case 3: region_valu<3>(lds, b, reinterpret_cast<const float2*>(mats + b.mat_off)); break;
-        case 2: region_valu<2>(lds, b, reinterpret_cast<const float2*>(mats + b.mat_off)); break;
-        default: region_valu<1>(lds, b, reinterpret_cast<const float2*>(mats + b.mat_off)); break;
+        case 3: region_valu<3>(lds, b, m2); break;
+        case 2: region_valu<2>(lds, b, m2); break;
+        default: region_valu<1>(lds, b, m2); break;
     }
 }
 
@@ -286,6 +303,8 @@ __global__ __launch_bounds__(kThreads, SV_BATCH_WAVES) void k_batch(BatchArgs A)
 {
     __shared__ float2 lds[kRegion];
     __shared__ float4 amat[kAmat];
+    __shared__ BatchBlock blk;
+    static_assert(sizeof(BatchBlock) % 4 == 0, "the block descriptor is copied as words");
     __shared__ double red[kThreads];
     __shared__ uint32_t next;
     float2* states = static_cast<float2*>(A.states);
@@ -319,21 +338,28 @@ __global__ __launch_bounds__(kThreads, SV_BATCH_WAVES) void k_batch(BatchArgs A)
         // the next tile's loads in flight while one is transformed
         const uint64_t n_regions = resident ? 1 : (dim >> 12);
         for (uint32_t bi = 0; bi < c.n_blocks; ++bi) {
-            __threadfence();
             __syncthreads();
-            const BatchBlock& b = A.blocks[c.block0 + bi];
-            stage_a(A.mats, b, amat);
+            // the block's descriptor and matrix are staged in LDS once: the
+            // tile loop then reads no global memory but the state, and a wait
+            // for a descriptor load (vector loads complete in order) cannot
+            // also wait for the tiles prefetched before it
+            if (tid < int(sizeof(BatchBlock) / 4))
+                reinterpret_cast<uint32_t*>(&blk)[tid] =
+                    reinterpret_cast<const uint32_t*>(A.blocks + c.block0 + bi)[tid];
+            __syncthreads();
+            const BatchBlock& b = blk;
+            stage_matrix(A.mats, b, amat);
             // streaming tiles: run index i >> L of the thread's vector u and
             // the offset inside the run (unused for a resident state)
-            uint64_t goff[8];
+            uint32_t goff[8];
             const int mask = (1 << b.L) - 1;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int i = (u * kThreads + tid) * 2;
                 const uint32_t r = uint32_t(i >> b.L);
-                uint64_t o = 0;
-                for (int j = 0; j < b.n_hi; ++j) o |= uint64_t((r >> j) & 1u) << b.hi_pos[j];
-                goff[u] = o + uint64_t(i & mask);
+                uint32_t o = 0;
+                for (int j = 0; j < b.n_hi; ++j) o |= ((r >> j) & 1u) << b.hi_pos[j];
+                goff[u] = o + uint32_t(i & mask);
             }
 #define SV_DECL(u) float4 buf##u = {};
             SV_REP8(SV_DECL)
@@ -361,7 +387,7 @@ __global__ __launch_bounds__(kThreads, SV_BATCH_WAVES) void k_batch(BatchArgs A)
                     base = insert_zeros((t + 1) << b.L, b.hi_pos, b.n_hi);
                     SV_REP8(SV_LOAD)
                 }
-                apply_region(lds, b, A.mats, amat);
+                apply_region(lds, b, amat);
                 __syncthreads();
                 if (!resident) {
 #pragma unroll
@@ -375,7 +401,6 @@ __global__ __launch_bounds__(kThreads, SV_BATCH_WAVES) void k_batch(BatchArgs A)
             }
 #undef SV_LOAD
         }
-        __threadfence();
         __syncthreads();
         if (resident) {
             for (int i = tid; i < int(dim); i += kThreads) psi[i] = lds[swz(i)];
@@ -383,7 +408,6 @@ __global__ __launch_bounds__(kThreads, SV_BATCH_WAVES) void k_batch(BatchArgs A)
         } else {
             expectations<false>(psi, dim, A.z_masks + c.term0, int(c.n_terms), red, A.expect + c.term0);
         }
-        __threadfence();
         __syncthreads();
         if (tid == 0) {
             A.t_done[ci] = wall_clock64();
