@@ -794,6 +794,42 @@ __global__ __launch_bounds__(kThreads) void k_bin_probs(const typename Cx<R>::T*
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// Streams a block's items [first, first + per) in rounds of kExpectUnroll
+// items per thread, two register buffers in turn (one round's loads in
+// flight while the other is summed), calling f(item, amplitude) for each
+// item in the order of a plain per-thread loop (it = tid, tid + 256, ...).
+// Past the end a round re-reads the block's last amplitude and skips it, so
+// every load is unconditional and the compiler waits for the older round
+// only.
+template <typename T2, typename F>
+__device__ __forceinline__ void stream_items(const T2* __restrict__ psi, uint64_t first, uint64_t per, F&& f)
+{
+    constexpr uint64_t kRound = uint64_t(kExpectUnroll) * kThreads;
+    T2 va[kExpectUnroll] = {}, vb[kExpectUnroll] = {};
+    auto load = [&](T2 (&v)[kExpectUnroll], uint64_t it0) {
+#pragma unroll
+        for (int u = 0; u < kExpectUnroll; ++u) {
+            const uint64_t it = it0 + uint64_t(u) * kThreads + threadIdx.x;
+            v[u] = psi[first + (it < per ? it : per - 1)];
+        }
+    };
+    auto visit = [&](const T2 (&v)[kExpectUnroll], uint64_t it0) {
+#pragma unroll
+        for (int u = 0; u < kExpectUnroll; ++u) {
+            const uint64_t it = it0 + uint64_t(u) * kThreads + threadIdx.x;
+            if (it < per) f(first + it, v[u]);
+        }
+    };
+    load(va, 0);
+    for (uint64_t it0 = 0; it0 < per; it0 += 2 * kRound) {
+        load(vb, it0 + kRound);
+        visit(va, it0);
+        if (it0 + kRound >= per) break;
+        load(va, it0 + 2 * kRound);
+        visit(vb, it0 + kRound);
+    }
+}
+
 // Outcome probabilities of M <= 4 qubits: a fixed partition of the whole
 // state, one accumulator per outcome in registers (every item adds to all of
 // them, 0 to all but its own: exact), then a fixed block reduction per
@@ -803,19 +839,17 @@ __global__ __launch_bounds__(kThreads) void k_bin_probs_small(const typename Cx<
                                                               BinArgs a, double* __restrict__ part)
 {
     __shared__ double wsum[kThreads / 64];
-    const uint64_t i0 = uint64_t(blockIdx.x) * per;
     double acc[1 << M];
 #pragma unroll
     for (int b = 0; b < (1 << M); ++b) acc[b] = 0.0;
-    for (uint64_t j = threadIdx.x; j < per; j += kThreads) {
-        const uint64_t i = i0 + j;
+    stream_items(psi, uint64_t(blockIdx.x) * per, per, [&](uint64_t i, const typename Cx<R>::T& v) {
         int bin = 0;
 #pragma unroll
         for (int q = 0; q < M; ++q) bin |= int((i >> a.qpos[q]) & 1) << q;
-        const double p = prob(psi[i]);
+        const double p = prob(v);
 #pragma unroll
         for (int b = 0; b < (1 << M); ++b) acc[b] = __dadd_rn(acc[b], bin == b ? p : 0.0);
-    }
+    });
 #pragma unroll
     for (int b = 0; b < (1 << M); ++b) {
         const double v = block_wave_sum(acc[b], wsum);
@@ -828,15 +862,13 @@ __global__ __launch_bounds__(kThreads) void k_parity_probs(const typename Cx<R>:
                                                            uint64_t mask, double* __restrict__ part)
 {
     __shared__ double wsum[kThreads / 64];
-    const uint64_t i0 = uint64_t(blockIdx.x) * per;
     double acc[2] = {0.0, 0.0};
-    for (uint64_t j = threadIdx.x; j < per; j += kThreads) {
-        const uint64_t i = i0 + j;
+    stream_items(psi, uint64_t(blockIdx.x) * per, per, [&](uint64_t i, const typename Cx<R>::T& v) {
         const int par = __popcll(i & mask) & 1;
-        const double p = prob(psi[i]);
+        const double p = prob(v);
         acc[0] = __dadd_rn(acc[0], par ? 0.0 : p);
         acc[1] = __dadd_rn(acc[1], par ? p : 0.0);
-    }
+    });
     const double e = block_wave_sum(acc[0], wsum);
     const double o = block_wave_sum(acc[1], wsum);
     if (threadIdx.x == 0) {
@@ -1031,11 +1063,9 @@ __global__ __launch_bounds__(kThreads) void k_expect_matrix(const typename Cx<R>
     const uint64_t g0 = uint64_t(blockIdx.x) * a.per;
     double re = 0.0, im = 0.0, nrm = 0.0;
     using T = typename Cx<R>::T;
-    for (uint64_t g = threadIdx.x; g < a.per; g += kThreads) {
+    // adds group g's conj(x_r) (M x)_r and |x_r|^2 over the rows r
+    auto group = [&](const T (&x)[D], uint64_t g) {
         const uint64_t b = insert_bits0(g0 + g, a.tsorted, K);
-        T x[D];
-#pragma unroll
-        for (int c = 0; c < D; ++c) x[c] = psi[b + a.off[c]];
         // K <= 3: rows and columns unrolled, x_r straight from the
         // registers (a compiler barrier per row keeps M's entries from being
         // hoisted into registers all at once).  K > 3: rows one at a time;
@@ -1060,6 +1090,32 @@ __global__ __launch_bounds__(kThreads) void k_expect_matrix(const typename Cx<R>
             re = fma(vr, yr, fma(vi, yi, re));
             im = fma(vr, yi, fma(-vi, yr, im));
             nrm = fma(vr, vr, fma(vi, vi, nrm));
+        }
+    };
+    // group g's amplitudes; past the block's end the last group is read
+    // again (and not summed), so every load is unconditional
+    auto load = [&](T (&x)[D], uint64_t g) {
+        const uint64_t b = insert_bits0(g0 + (g < a.per ? g : a.per - 1), a.tsorted, K);
+#pragma unroll
+        for (int c = 0; c < D; ++c) x[c] = psi[b + a.off[c]];
+    };
+    if constexpr (K <= 3) {
+        // two register buffers in turn: one group's loads in flight while
+        // the other is summed (groups in the order of a plain loop)
+        T xa[D] = {}, xb[D] = {};
+        load(xa, threadIdx.x);
+        for (uint64_t g = threadIdx.x; g < a.per; g += 2 * kThreads) {
+            load(xb, g + kThreads);
+            group(xa, g);
+            if (g + kThreads >= a.per) break;
+            load(xa, g + 2 * kThreads);
+            group(xb, g + kThreads);
+        }
+    } else {
+        for (uint64_t g = threadIdx.x; g < a.per; g += kThreads) {
+            T x[D];
+            load(x, g);
+            group(x, g);
         }
     }
     const double s0 = block_wave_sum(re, wsum);
