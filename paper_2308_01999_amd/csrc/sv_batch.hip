@@ -296,10 +296,7 @@ __device__ __forceinline__ float4 swap_pair(const float4 v, int i)
 
 #define SV_REP8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
-#ifndef SV_BATCH_WAVES
-#define SV_BATCH_WAVES 1
-#endif
-__global__ __launch_bounds__(kThreads, SV_BATCH_WAVES) void k_batch(BatchArgs A)
+__global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A)
 {
     __shared__ float2 lds[kRegion];
     __shared__ float4 amat[kAmat];
