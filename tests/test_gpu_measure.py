@@ -73,7 +73,7 @@ def test_pauli_rotation_matches_oracle(P, H, dt, n, seed):
 
 
 @pytest.mark.parametrize("dt", ["c64", "c128"])
-@pytest.mark.parametrize("n,m", [(4, 1), (9, 4), (14, 10), (20, 3)])
+@pytest.mark.parametrize("n,m", [(1, 1), (2, 2), (3, 2), (4, 1), (9, 4), (11, 4), (14, 10), (20, 3)])
 def test_measure_probabilities_match_oracle(P, H, dt, n, m):
     rng = np.random.default_rng(n * 10 + m)
     qubits = [int(q) for q in rng.permutation(n)[:m]]
