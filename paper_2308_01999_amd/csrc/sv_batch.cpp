@@ -234,14 +234,24 @@ BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>
     }
     H.state_amps = off;
     for (auto* f : fused) free_fused(f);
-    // largest work first
+    // Queue order.  The cheapest circuits, up to kShortShare of the batch's
+    // work, go first (smallest first): they are done within that share of
+    // the launch instead of after every large state.  The rest follow
+    // largest first, so the long circuits start early and none starts late.
+    // A circuit's work is its state size times its sweeps.
+    constexpr double kShortShare = 0.05;
     H.order.resize(sel.size());
     std::iota(H.order.begin(), H.order.end(), 0u);
-    std::stable_sort(H.order.begin(), H.order.end(), [&](uint32_t a, uint32_t b) {
-        const double wa = double(uint64_t(1) << H.circuits[a].n) * (H.circuits[a].n_blocks + 1);
-        const double wb = double(uint64_t(1) << H.circuits[b].n) * (H.circuits[b].n_blocks + 1);
-        return wa > wb;
-    });
+    auto work = [&](uint32_t c) { return double(uint64_t(1) << H.circuits[c].n) * (H.circuits[c].n_blocks + 1); };
+    std::stable_sort(H.order.begin(), H.order.end(), [&](uint32_t a, uint32_t b) { return work(a) < work(b); });
+    double total = 0.0;
+    for (uint32_t c : H.order) total += work(c);
+    size_t n_short = 0;
+    for (double cum = 0.0; n_short < H.order.size(); ++n_short) {
+        cum += work(H.order[n_short]);
+        if (cum > kShortShare * total) break;
+    }
+    std::reverse(H.order.begin() + std::ptrdiff_t(n_short), H.order.end());
     return H;
 }
 

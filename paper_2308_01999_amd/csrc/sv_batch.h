@@ -41,7 +41,7 @@ struct BatchCircuit {
 struct BatchArgs {
     void* states;
     const BatchCircuit* circuits;
-    const uint32_t* order;  // circuit indices, largest first
+    const uint32_t* order;  // circuit indices in queue order (short first, then largest first)
     const BatchBlock* blocks;
     const float* mats;
     const uint64_t* z_masks;
