@@ -1,8 +1,7 @@
 // Batched execution of many independent small circuits in one persistent
 // launch (complex64).  Each workgroup takes circuits from a device queue
 // (in the order the host chose) and runs a circuit's whole fused program,
-// then its
-// Z-type Pauli expectations:
+// then its Z-type Pauli expectations:
 //   - states of <= 12 qubits stay in LDS from |0..0> to the end, and are
 //     written to HBM once;
 //   - larger states are swept block by block through 4096-amplitude tiles
