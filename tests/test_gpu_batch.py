@@ -105,3 +105,22 @@ def test_batch_rejects_bad_input(P, H):
         P.Batch(H, [4], [W.brickwork(5, 1, 0)], [[1]], 5)
     with pytest.raises(P.SVError):
         P.Batch(H, [4], [W.brickwork(4, 1, 0)], [[1]], 6)
+
+
+def test_batch_short_circuits_finish_first(P, H):
+    # more large circuits than workgroups: the cheap circuits (the first 5%
+    # of the work) are queued first, so every one of them completes before
+    # most large ones; in largest-first order they would wait for a full
+    # wave of large circuits
+    rng = np.random.default_rng(9)
+    small = [W.brickwork(8, int(rng.integers(4, 9)), 10_000 + i) for i in range(1200)]
+    large = [W.brickwork(14, int(rng.integers(10, 17)), 20_000 + i) for i in range(600)]
+    circuits = small + large
+    ns = [8] * len(small) + [14] * len(large)
+    terms = [[1] for _ in circuits]
+    b = P.Batch(H, ns, circuits, terms, max_fused_qubits=5)
+    b.run()
+    _, lat, ks = b.run()
+    b.close()
+    lat_small, lat_large = lat[: len(small)], lat[len(small):]
+    assert lat_small.max() < np.median(lat_large), (lat_small.max(), np.median(lat_large), ks)
