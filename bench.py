@@ -227,12 +227,12 @@ def kmax_leg(P, W, torch, H, gates, n):
         for kmax in (0, 4, 5, 6):
             if kmax == 0:
                 entries = P.gate_entries(gates)
-                nbytes = sum(2 * (1 << (n - len(c))) * s for _, _, c, _ in entries)
+                nbytes = sum(2 * (1 << (n - len(e[2]))) * s for e in entries)
                 sweeps = len(entries)
 
                 def go():
-                    for t, m, c, cv in entries:
-                        st.apply_matrix(m, t, c, cv)
+                    for t, m, c, cv, adj in entries:
+                        st.apply_matrix(m, t, c, cv, adjoint=adj)
             else:
                 f = P.fuse(gates, kmax)
                 sweeps = f.count

@@ -63,7 +63,9 @@ typedef struct sv_state_s* sv_state_t;
 typedef struct sv_fused_s* sv_fused_t;
 
 /* One gate of a circuit, as input to gate fusion.  `matrix` is
- * 2^n_targets x 2^n_targets complex128 (see conventions). */
+ * 2^n_targets x 2^n_targets complex128 (see conventions); with adjoint != 0
+ * the gate is its conjugate transpose (as the adjoint flag of
+ * sv_apply_matrix), so a circuit and its inverse share their matrices. */
 typedef struct {
     int32_t n_targets;
     const int32_t* targets;
@@ -71,6 +73,7 @@ typedef struct {
     int32_t n_controls;
     const int32_t* controls;
     const int32_t* control_values; /* NULL: all 1 */
+    int32_t adjoint;               /* 0: matrix; else its conjugate transpose */
 } sv_gate_t;
 
 /* A Pauli string: ops[a] in {'I','X','Y','Z'} acts on qubits[a]. */
@@ -383,8 +386,11 @@ sv_status_t sv_accessor_set(sv_state_t s, const int32_t* ordering, int32_t n_bit
 
 /* ------------------------------------------------------------- reductions */
 
-/* *out = sum_i |psi_i|^2 accumulated in FP64 in a fixed order (bitwise
- * reproducible for a given state).  Blocks. */
+/* The total of the probability distribution that measurement outcomes are
+ * drawn from (Sec. II: the probability distribution is computed
+ * numerically): *out = sum_i |psi_i|^2 accumulated in FP64 in a fixed order
+ * (bitwise reproducible for a given state).  Blocks.  SV_ERR_INVALID_VALUE
+ * for a NULL state or out. */
 sv_status_t sv_norm(sv_state_t s, double* out);
 
 /*
@@ -396,8 +402,14 @@ sv_status_t sv_norm(sv_state_t s, double* out);
  */
 sv_status_t sv_expect_matrix(sv_state_t s, const double* matrix, const int32_t* targets, int32_t k, double* out);
 
-/* Scales the state by 1/sqrt(norm) (FP64 norm, scale applied in the state's
- * precision).  *norm_out (may be NULL) receives the norm before scaling. */
+/* Renormalisation of the state whose probability distribution (Sec. II)
+ * no longer sums to one (for example after rounding in complex64 or a
+ * collapse by the caller): scales the state by 1/sqrt(norm), the norm as
+ * sv_norm computes it and the scale applied in the state's precision.
+ * *norm_out (may be NULL) receives the norm before scaling.  Blocks until
+ * the norm is known; the scaling sweep is asynchronous.
+ * SV_ERR_INVALID_VALUE when the norm is zero or not finite (the state is
+ * then left as it is). */
 sv_status_t sv_renormalize(sv_state_t s, double* norm_out);
 
 /*
@@ -476,6 +488,24 @@ sv_status_t sv_batch_info(sv_batch_t b, int32_t n_qubits, int32_t* max_fused_qub
 sv_status_t sv_batch_run(sv_batch_t b, void* states, double* expect_out, double* latency_s, double* kernel_s);
 
 sv_status_t sv_batch_destroy(sv_batch_t b);
+
+/* ---------------------------------------------------- device memory budget */
+
+/*
+ * Cap on the device memory libsv allocates itself (Table I: resource
+ * management; Sec. II-A: the caller may keep states in memory of its own, so
+ * only libsv's own allocations count: handle workspaces and scratch, states
+ * created without a device pointer, recorded programs and batch
+ * descriptors).  The cap starts as the environment variable
+ * SV_HBM_BUDGET_BYTES (a decimal byte count, read at the first allocation;
+ * unset or unparsable: no cap).  sv_set_hbm_budget replaces it (0: no cap).
+ * An allocation that would take the total past the cap fails with
+ * SV_ERR_OUT_OF_MEMORY before any device work, and the call that needed it
+ * has no effect.  sv_hbm_usage reports the bytes in use and the cap (0: no
+ * cap); either pointer may be NULL.  Both are host-only.
+ */
+sv_status_t sv_set_hbm_budget(uint64_t bytes);
+sv_status_t sv_hbm_usage(uint64_t* used_bytes, uint64_t* budget_bytes);
 
 /* ------------------------------------------------------------------ errors */
 

@@ -48,7 +48,7 @@ _pu64 = ctypes.POINTER(ctypes.c_uint64)
 
 class sv_gate_t(ctypes.Structure):
     _fields_ = [("n_targets", _i32), ("targets", _pi32), ("matrix", _pd), ("n_controls", _i32),
-                ("controls", _pi32), ("control_values", _pi32)]
+                ("controls", _pi32), ("control_values", _pi32), ("adjoint", _i32)]
 
 
 class sv_pauli_term_t(ctypes.Structure):
@@ -105,6 +105,8 @@ _SIGS = {
     "sv_batch_info": [_vp, _i32, _pi32, _pi32],
     "sv_batch_run": [_vp, _vp, _pd, _pd, _pd],
     "sv_batch_destroy": [_vp],
+    "sv_set_hbm_budget": [_u64],
+    "sv_hbm_usage": [_pu64, _pu64],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_L, _name)
@@ -152,6 +154,19 @@ def sv_version() -> str:
 
 def sv_last_error() -> str:
     return _L.sv_last_error().decode(errors="replace")
+
+
+def sv_set_hbm_budget(budget_bytes: int) -> None:
+    """Cap on the device memory libsv allocates itself (0: no cap)."""
+    _check(_L.sv_set_hbm_budget(int(budget_bytes)))
+
+
+def sv_hbm_usage() -> tuple:
+    """(bytes libsv has allocated, cap or 0)."""
+    used = ctypes.c_uint64()
+    cap = ctypes.c_uint64()
+    _check(_L.sv_hbm_usage(ctypes.byref(used), ctypes.byref(cap)))
+    return used.value, cap.value
 
 
 def sv_handle_create(stream_ptr: int = 0, workspace_bytes: int = 0) -> int:
@@ -244,21 +259,29 @@ def sv_gate_matrix(name: str, params=()) -> tuple:
     return out[: d * d].reshape(d, d).copy(), nt.value, nc.value
 
 
-def _gate_struct(targets, matrix, controls=(), control_values=None, keep=None):
+def _gate_struct(targets, matrix, controls=(), control_values=None, adjoint=False, keep=None):
     m = _mat(matrix)
     t = _i32arr(targets)
     c = _i32arr(controls)
     cv = None if control_values is None else _i32arr(control_values)
     keep.extend([m, t, c, cv])
-    return sv_gate_t(len(targets), t, m.ctypes.data_as(_pd), len(controls), c, cv)
+    return sv_gate_t(len(targets), t, m.ctypes.data_as(_pd), len(controls), c, cv, int(bool(adjoint)))
+
+
+def _gate_array(gates, keep):
+    """Entries (targets, matrix, controls, control_values[, adjoint]) as a
+    sv_gate_t array."""
+    arr = (sv_gate_t * max(1, len(gates)))()
+    for i, e in enumerate(gates):
+        t, m, c, cv = e[:4]
+        arr[i] = _gate_struct(t, m, c, cv, e[4] if len(e) > 4 else False, keep)
+    return arr
 
 
 def sv_fuse_gates(gates, max_fused_qubits: int) -> int:
-    """gates: list of (targets, matrix, controls, control_values)."""
+    """gates: list of (targets, matrix, controls, control_values[, adjoint])."""
     keep = []
-    arr = (sv_gate_t * max(1, len(gates)))()
-    for i, (t, m, c, cv) in enumerate(gates):
-        arr[i] = _gate_struct(t, m, c, cv, keep)
+    arr = _gate_array(gates, keep)
     f = _vp()
     _check(_L.sv_fuse_gates(arr, len(gates), max_fused_qubits, ctypes.byref(f)))
     return f.value
@@ -267,9 +290,7 @@ def sv_fuse_gates(gates, max_fused_qubits: int) -> int:
 def sv_fuse_gates_diag(gates, max_fused_qubits: int, max_fused_diagonal_qubits: int) -> int:
     """As sv_fuse_gates, with diagonal blocks of up to max_fused_diagonal_qubits."""
     keep = []
-    arr = (sv_gate_t * max(1, len(gates)))()
-    for i, (t, m, c, cv) in enumerate(gates):
-        arr[i] = _gate_struct(t, m, c, cv, keep)
+    arr = _gate_array(gates, keep)
     f = _vp()
     _check(_L.sv_fuse_gates_diag(arr, len(gates), max_fused_qubits, max_fused_diagonal_qubits, ctypes.byref(f)))
     return f.value
@@ -585,16 +606,16 @@ class State:
 
 
 def gate_entries(gates):
-    """Workload gates -> (targets, matrix, controls, control_values) via the
-    library's gate table."""
+    """Workload gates -> (targets, matrix, controls, control_values, adjoint)
+    via the library's gate table; a "mat_dg" gate passes its matrix with the
+    adjoint flag set."""
     out = []
     for name, qubits, params in gates:
         if name in ("mat", "mat_dg"):
-            m = _mat(params)
-            out.append((tuple(qubits), np.conj(m).T if name == "mat_dg" else m, (), None))
+            out.append((tuple(qubits), _mat(params), (), None, name == "mat_dg"))
         else:
             m, nt, nc = sv_gate_matrix(name, params)
-            out.append((tuple(qubits[nc:]), m, tuple(qubits[:nc]), None))
+            out.append((tuple(qubits[nc:]), m, tuple(qubits[:nc]), None, False))
     return out
 
 

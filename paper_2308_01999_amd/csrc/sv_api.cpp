@@ -5,8 +5,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -19,6 +22,65 @@ namespace sv {
 static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+// ------------------------------------------------- device memory budget
+
+namespace {
+
+std::atomic<uint64_t> g_hbm_used{0};
+std::atomic<uint64_t> g_hbm_budget{0};  // 0: no cap
+std::once_flag g_budget_env_once;
+
+void read_budget_env()
+{
+    std::call_once(g_budget_env_once, [] {
+        const char* v = std::getenv("SV_HBM_BUDGET_BYTES");
+        if (v == nullptr || *v == 0) return;
+        char* end = nullptr;
+        const unsigned long long b = std::strtoull(v, &end, 10);
+        if (end != nullptr && *end == 0) g_hbm_budget.store(b);
+    });
+}
+
+}  // namespace
+
+void budget_reserve(size_t bytes, const char* what)
+{
+    read_budget_env();
+    const uint64_t cap = g_hbm_budget.load();
+    uint64_t used = g_hbm_used.load();
+    for (;;) {
+        if (cap != 0 && (bytes > cap || used > cap - bytes))
+            throw Error{SV_ERR_OUT_OF_MEMORY, std::string(what) + ": " + std::to_string(bytes) +
+                                                  " B would exceed the HBM budget of " + std::to_string(cap) +
+                                                  " B (" + std::to_string(used) + " B in use)"};
+        if (g_hbm_used.compare_exchange_weak(used, used + bytes)) return;
+    }
+}
+
+void budget_release(size_t bytes) { g_hbm_used.fetch_sub(bytes); }
+
+void* dev_alloc(size_t bytes, const char* what)
+{
+    budget_reserve(bytes, what);
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        budget_release(bytes);
+        (void)hipGetLastError();
+        throw Error{e == hipErrorOutOfMemory ? SV_ERR_OUT_OF_MEMORY : SV_ERR_DEVICE,
+                    std::string(what) + ": hipMalloc of " + std::to_string(bytes) + " B failed: " +
+                        hipGetErrorString(e)};
+    }
+    return p;
+}
+
+void dev_free(void* p, size_t bytes)
+{
+    if (p == nullptr) return;
+    (void)hipFree(p);
+    budget_release(bytes);
+}
 
 sv_batch_s* batch_create(sv_handle_s* h, int n_circuits, const int32_t* n_qubits, const int32_t* gate_offsets,
                          const int32_t* codes, const int32_t* qubits, const double* params,
@@ -193,16 +255,11 @@ char* ensure_aux(sv_handle_s* h, size_t bytes)
     if (bytes <= h->aux_bytes) return h->aux;
     SV_HIP(hipStreamSynchronize(h->stream));
     if (h->aux) {
-        SV_HIP(hipFree(h->aux));
+        dev_free(h->aux, h->aux_bytes);
         h->aux = nullptr;
         h->aux_bytes = 0;
     }
-    const hipError_t e = hipMalloc(&h->aux, bytes);
-    if (e != hipSuccess) {
-        h->aux = nullptr;
-        (void)hipGetLastError();
-        throw Error{SV_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " B of scratch failed"};
-    }
+    h->aux = static_cast<char*>(dev_alloc(bytes, "sampler scratch"));
     h->aux_bytes = bytes;
     return h->aux;
 }
@@ -215,6 +272,23 @@ extern "C" {
 
 const char* sv_last_error(void) { return g_last_error.c_str(); }
 
+sv_status_t sv_set_hbm_budget(uint64_t bytes)
+{
+    return guarded([&] {
+        read_budget_env();
+        g_hbm_budget.store(bytes);
+    });
+}
+
+sv_status_t sv_hbm_usage(uint64_t* used_bytes, uint64_t* budget_bytes)
+{
+    return guarded([&] {
+        read_budget_env();
+        if (used_bytes) *used_bytes = g_hbm_used.load();
+        if (budget_bytes) *budget_bytes = g_hbm_budget.load();
+    });
+}
+
 const char* sv_version(void) { return "libsv 0.1 (gfx950)"; }
 
 sv_status_t sv_handle_create(sv_handle_t* out, void* hip_stream, size_t workspace_bytes)
@@ -224,12 +298,15 @@ sv_status_t sv_handle_create(sv_handle_t* out, void* hip_stream, size_t workspac
         *out = nullptr;
         if (workspace_bytes == 0) workspace_bytes = kDefaultWorkspace;
         SV_CHECK(workspace_bytes >= kMinWorkspace, "workspace must be at least 12 MiB");
+        // the budget is a host-side limit: checked before any device work
+        budget_reserve(workspace_bytes, "handle workspace");
+        budget_release(workspace_bytes);
         auto* h = new sv_handle_s;
         try {
             h->stream = static_cast<hipStream_t>(hip_stream);
             SV_HIP(hipGetDevice(&h->device));
             SV_HIP(hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, h->device));
-            SV_HIP(hipMalloc(&h->ws, workspace_bytes));
+            h->ws = static_cast<char*>(dev_alloc(workspace_bytes, "handle workspace"));
             h->ws_bytes = workspace_bytes;
             SV_HIP(hipHostMalloc(&h->pinned, kMatRingBytes, hipHostMallocDefault));
             h->pinned_bytes = kMatRingBytes;
@@ -241,7 +318,7 @@ sv_status_t sv_handle_create(sv_handle_t* out, void* hip_stream, size_t workspac
             for (int i = 0; i < kMatRingSegments; ++i)
                 if (h->seg_event[i]) (void)hipEventDestroy(h->seg_event[i]);
             if (h->pinned) (void)hipHostFree(h->pinned);
-            if (h->ws) (void)hipFree(h->ws);
+            dev_free(h->ws, h->ws_bytes);
             delete h;
             throw;
         }
@@ -257,8 +334,8 @@ sv_status_t sv_handle_destroy(sv_handle_t h)
         for (int i = 0; i < kMatRingSegments; ++i)
             if (h->seg_event[i]) (void)hipEventDestroy(h->seg_event[i]);
         if (h->pinned) (void)hipHostFree(h->pinned);
-        if (h->ws) (void)hipFree(h->ws);
-        if (h->aux) (void)hipFree(h->aux);
+        dev_free(h->ws, h->ws_bytes);
+        dev_free(h->aux, h->aux_bytes);
         if (h->tuner) {
             for (auto& t : h->tuner->pending) {
                 (void)hipEventDestroy(t.e0);
@@ -317,17 +394,17 @@ sv_status_t sv_create(sv_handle_t h, int32_t n_qubits, sv_dtype_t dtype, void* d
             s->owned = false;
         } else {
             const size_t bytes = amp_bytes(dtype) << n_qubits;
-            const hipError_t e = hipMalloc(&s->d, bytes);
-            if (e != hipSuccess) {
+            try {
+                s->d = dev_alloc(bytes, "state");
+            } catch (...) {
                 delete s;
-                (void)hipGetLastError();
-                throw Error{SV_ERR_OUT_OF_MEMORY, "hipMalloc of the state failed: " + std::string(hipGetErrorString(e))};
+                throw;
             }
             s->owned = true;
             try {
                 launch_set_basis(h, dtype, s->d, n_qubits, 0);
             } catch (...) {
-                (void)hipFree(s->d);
+                dev_free(s->d, bytes);
                 delete s;
                 throw;
             }
@@ -343,8 +420,7 @@ sv_status_t sv_destroy(sv_state_t s)
         hipError_t e = hipSuccess;
         if (s->owned) {
             e = hipStreamSynchronize(s->h->stream);
-            const hipError_t e2 = hipFree(s->d);
-            if (e == hipSuccess) e = e2;
+            dev_free(s->d, amp_bytes(s->dt) << s->n);
         }
         delete s;
         SV_HIP(e);
@@ -668,6 +744,7 @@ sv_status_t sv_apply_fused_range(sv_state_t s, sv_fused_t f, int32_t first, int3
 struct sv_graph_s {
     sv_state_s* s = nullptr;
     char* mats = nullptr;  // packed block matrices, device
+    size_t mats_bytes = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -699,12 +776,8 @@ sv_status_t sv_graph_create(sv_state_t s, sv_fused_t f, sv_graph_t* out)
         hipStream_t cap = nullptr;
         hipStream_t saved = h->stream;
         try {
-            const hipError_t e = hipMalloc(&g->mats, host.size());
-            if (e != hipSuccess) {
-                g->mats = nullptr;
-                (void)hipGetLastError();
-                throw Error{SV_ERR_OUT_OF_MEMORY, "hipMalloc of the graph's matrices failed"};
-            }
+            g->mats = static_cast<char*>(dev_alloc(host.size(), "recorded program matrices"));
+            g->mats_bytes = host.size();
             SV_HIP(hipMemcpy(g->mats, host.data(), host.size(), hipMemcpyHostToDevice));
             // record on a private stream: the handle's own stream may be the
             // null stream, which cannot be captured
@@ -729,7 +802,7 @@ sv_status_t sv_graph_create(sv_state_t s, sv_fused_t f, sv_graph_t* out)
             if (cap) (void)hipStreamDestroy(cap);
             if (g->exec) (void)hipGraphExecDestroy(g->exec);
             if (g->graph) (void)hipGraphDestroy(g->graph);
-            if (g->mats) (void)hipFree(g->mats);
+            dev_free(g->mats, g->mats_bytes);
             delete g;
             throw;
         }
@@ -753,7 +826,7 @@ sv_status_t sv_graph_destroy(sv_graph_t g)
         const hipError_t e = hipStreamSynchronize(g->s->h->stream);
         if (g->exec) (void)hipGraphExecDestroy(g->exec);
         if (g->graph) (void)hipGraphDestroy(g->graph);
-        if (g->mats) (void)hipFree(g->mats);
+        dev_free(g->mats, g->mats_bytes);
         delete g;
         SV_HIP(e);
     });

@@ -44,6 +44,7 @@ struct sv_batch_s {
     std::map<int, int> kmax_for_n;
     std::vector<int> blocks_per_circuit;
     char* dev = nullptr;  // one arena for all device-side descriptors
+    size_t dev_bytes = 0;
     sv::BatchArgs args{};
     double tick_hz = 1e8;
     // the run (queue reset + persistent kernel), recorded once per states
@@ -262,7 +263,7 @@ size_t align_up(size_t v)
 }
 
 // Uploads H into one device arena and fills args (states excluded).
-char* upload(const BatchHost& H, BatchArgs& a, hipStream_t stream)
+char* upload(const BatchHost& H, BatchArgs& a, hipStream_t stream, size_t* dev_bytes)
 {
     const size_t s_c = align_up<int>(H.circuits.size() * sizeof(BatchCircuit));
     const size_t s_o = align_up<int>(H.order.size() * sizeof(uint32_t));
@@ -272,15 +273,15 @@ char* upload(const BatchHost& H, BatchArgs& a, hipStream_t stream)
     const size_t s_e = align_up<int>(std::max<size_t>(1, H.z_masks.size()) * sizeof(double));
     const size_t s_t = align_up<int>(H.circuits.size() * sizeof(uint64_t));
     const size_t total = s_c + s_o + s_b + s_m + s_z + s_e + s_t + 256 + 256;
-    char* dev = nullptr;
-    SV_HIP(hipMalloc(&dev, total));
+    char* dev = static_cast<char*>(dev_alloc(total, "batch descriptors"));
+    if (dev_bytes) *dev_bytes = total;
     char* p = dev;
     auto put = [&](const void* src, size_t bytes, size_t room) {
         char* d = p;
         if (bytes) {
             const hipError_t e = hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, stream);
             if (e != hipSuccess) {
-                (void)hipFree(dev);
+                dev_free(dev, total);
                 throw Error{SV_ERR_DEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e)};
             }
         }
@@ -299,7 +300,7 @@ char* upload(const BatchHost& H, BatchArgs& a, hipStream_t stream)
     a.n_circuits = uint32_t(H.circuits.size());
     const hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
-        (void)hipFree(dev);
+        dev_free(dev, total);
         throw Error{SV_ERR_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e)};
     }
     return dev;
@@ -335,11 +336,14 @@ int tune_width(sv_handle_s* h, const std::vector<CircuitInput>& in, const std::v
         std::vector<int> km(in.size(), k);
         BatchHost H = build_host(in, sample, km, term0, nterms, z_masks, nullptr);
         BatchArgs a{};
-        char* dev = upload(H, a, h->stream);
+        size_t dev_bytes = 0;
+        char* dev = upload(H, a, h->stream, &dev_bytes);
+        const size_t st_bytes = H.state_amps * sizeof(float) * 2;
         void* states = nullptr;
-        hipError_t e = hipMalloc(&states, H.state_amps * sizeof(float) * 2);
-        if (e != hipSuccess) {
-            (void)hipFree(dev);
+        try {
+            states = dev_alloc(st_bytes, "autotuner states");
+        } catch (...) {
+            dev_free(dev, dev_bytes);
             break;
         }
         a.states = states;
@@ -354,12 +358,12 @@ int tune_width(sv_handle_s* h, const std::vector<CircuitInput>& in, const std::v
             SV_HIP(hipEventSynchronize(e1));
             SV_HIP(hipEventElapsedTime(&ms, e0, e1));
         } catch (...) {
-            (void)hipFree(states);
-            (void)hipFree(dev);
+            dev_free(states, st_bytes);
+            dev_free(dev, dev_bytes);
             throw;
         }
-        (void)hipFree(states);
-        (void)hipFree(dev);
+        dev_free(states, st_bytes);
+        dev_free(dev, dev_bytes);
         if (ms < best_ms) {
             best_ms = ms;
             best_k = k;
@@ -438,7 +442,7 @@ sv_batch_s* batch_create(sv_handle_s* h, int n_circuits, const int32_t* n_qubits
         b->state_off.resize(n_circuits);
         for (int i = 0; i < n_circuits; ++i) b->state_off[i] = H.circuits[i].state_off;
         b->state_amps = H.state_amps;
-        b->dev = upload(H, b->args, h->stream);
+        b->dev = upload(H, b->args, h->stream, &b->dev_bytes);
         int khz = 0;
         SV_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device));
         b->tick_hz = khz > 0 ? double(khz) * 1e3 : 1e8;
@@ -548,7 +552,7 @@ void batch_destroy(sv_batch_s* b)
     if (!b) return;
     (void)hipStreamSynchronize(b->h->stream);
     drop_graph(b);
-    if (b->dev) (void)hipFree(b->dev);
+    dev_free(b->dev, b->dev_bytes);
     delete b;
 }
 

@@ -376,6 +376,7 @@ sv_fused_s* fuse_gate_list(const int32_t* codes, const int32_t* qubits, const do
         e.n_targets = nt;
         e.targets = &qs[2 * g + nc];
         e.matrix = &mats[size_t(g) * 32];
+        e.adjoint = 0;  // the adjoint code is already in the matrix
     }
     return fuse(gates.data(), n_gates, kmax, kdiag);
 }
@@ -414,9 +415,12 @@ sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag)
         h.m.resize(size_t(d) * d);
         h.diagonal = true;
         for (int e = 0; e < d * d; ++e) {
-            h.m[e] = cd(g.matrix[2 * e], g.matrix[2 * e + 1]);
             SV_CHECK(std::isfinite(g.matrix[2 * e]) && std::isfinite(g.matrix[2 * e + 1]),
                      "gate " + std::to_string(i) + ": matrix entry is not finite");
+            // the adjoint's entry (r, c) is the conjugate of entry (c, r)
+            const int src = g.adjoint ? (e % d) * d + e / d : e;
+            const double im = g.matrix[2 * src + 1];
+            h.m[e] = cd(g.matrix[2 * src], g.adjoint ? -im : im);
             if (e / d != e % d && h.m[e] != cd(0.0, 0.0)) h.diagonal = false;
         }
     }

@@ -36,6 +36,20 @@ struct Error {
         if (!(cond)) throw ::sv::Error{SV_ERR_INVALID_VALUE, (msg)};                     \
     } while (0)
 
+// ------------------------------------------------------ device memory
+
+// Every device allocation libsv makes for itself (handle workspaces,
+// scratch, states it owns, recorded programs, batch descriptors) goes
+// through dev_alloc / dev_free, which keep a process-wide count against an
+// optional cap: the environment variable SV_HBM_BUDGET_BYTES (a decimal byte
+// count, read at the first allocation) or sv_set_hbm_budget.  A request
+// beyond the cap throws SV_ERR_OUT_OF_MEMORY before any HIP call; memory the
+// caller lends (borrowed state pointers) is not counted.
+void budget_reserve(size_t bytes, const char* what);
+void budget_release(size_t bytes);
+void* dev_alloc(size_t bytes, const char* what);
+void dev_free(void* p, size_t bytes);
+
 // ------------------------------------------------------------- workspace
 
 // Layout of the handle's device workspace (bytes from its start).  The

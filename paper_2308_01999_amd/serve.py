@@ -18,6 +18,7 @@ alone or among others.
 from __future__ import annotations
 
 import collections
+import os
 import threading
 import time
 from dataclasses import dataclass
@@ -27,6 +28,42 @@ import numpy as np
 from . import Handle, State, fuse, sv_apply_fused, sv_expect_pauli, sv_sample
 
 STATE_BYTES = {"c64": 8, "c128": 16}
+WORKSPACE_BYTES = 64 << 20    # libsv's default handle workspace (one per slot)
+
+
+def state_bytes(n: int, dtype: str) -> int:
+    """Device bytes of an n-qubit state."""
+    return (1 << n) * STATE_BYTES[dtype]
+
+
+def sampler_scratch_bytes(n: int) -> int:
+    """The sampler's per-handle prefix buffer for an n-qubit state: one
+    double per 64 amplitudes, rounded up to 256 B.  libsv grows it to the
+    largest state a handle has sampled and keeps it until the handle is
+    destroyed."""
+    return (((1 << n) // 64) * 8 + 255) & ~255
+
+
+def slot_reserve(max_qubits: int) -> int:
+    """Device bytes a slot holds whatever it serves: its handle workspace and
+    its sampler buffer grown to the largest admissible state."""
+    return WORKSPACE_BYTES + sampler_scratch_bytes(max_qubits)
+
+
+def request_budget(total_bytes: int, slots: int, max_qubits: int) -> int:
+    """What is left of a device-memory budget for request states once every
+    slot's reserve is set aside."""
+    left = total_bytes - slots * slot_reserve(max_qubits)
+    if left <= 0:
+        raise ValueError(f"a budget of {total_bytes} B does not cover {slots} slots of {slot_reserve(max_qubits)} B")
+    return left
+
+
+def default_budget() -> int:
+    """SV_HBM_BUDGET_BYTES if set (the same cap libsv applies to its own
+    allocations), else 64 GiB."""
+    v = os.environ.get("SV_HBM_BUDGET_BYTES", "")
+    return int(v) if v.isdigit() else 64 << 30
 
 
 @dataclass
@@ -104,15 +141,20 @@ class Admission:
 
 class Server:
     """Serves requests on `slots` concurrent streams within `budget_bytes`
-    of state memory, complex64 (or complex128) states, fusion width kmax
-    (0: no fusion, one sweep per gate)."""
+    of device memory (default: SV_HBM_BUDGET_BYTES, else 64 GiB), complex64
+    (or complex128) states, fusion width kmax (0: no fusion, one sweep per
+    gate).  Each slot's handle workspace and sampler buffer (sized for
+    max_qubits) are set aside first; requests are admitted by their state
+    size against the rest.  Requests above max_qubits are rejected."""
 
-    def __init__(self, slots: int = 4, budget_bytes: int = 64 << 30, dtype: str = "c64", kmax: int = 5,
-                 max_bypass: int = 8):
+    def __init__(self, slots: int = 4, budget_bytes: int | None = None, dtype: str = "c64", kmax: int = 5,
+                 max_bypass: int = 8, max_qubits: int = 28):
         import torch
         self.dtype = dtype
         self.kmax = kmax
-        self.adm = Admission(budget_bytes, slots, max_bypass)
+        self.max_qubits = max_qubits
+        total = default_budget() if budget_bytes is None else budget_bytes
+        self.adm = Admission(request_budget(total, slots, max_qubits), slots, max_bypass)
         self.cv = threading.Condition()
         self.pending = {}        # rid -> Request
         self.results = {}        # rid -> Result
@@ -126,13 +168,17 @@ class Server:
         self.dispatcher.start()
 
     def footprint(self, n: int) -> int:
-        return (1 << n) * STATE_BYTES[self.dtype]
+        return state_bytes(n, self.dtype)
 
     def submit(self, req: Request) -> None:
+        """Queues a request; raises ValueError (and keeps nothing of it) if it
+        can never be admitted."""
+        if req.n > self.max_qubits:
+            raise ValueError(f"request {req.rid} has {req.n} qubits, more than the server's {self.max_qubits}")
         req.arrival = time.monotonic()
         with self.cv:
-            self.pending[req.rid] = req
             self.adm.add(req.rid, self.footprint(req.n))
+            self.pending[req.rid] = req
             self.cv.notify_all()
 
     def _dispatch(self) -> None:

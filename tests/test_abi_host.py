@@ -126,6 +126,33 @@ def test_fusion_equals_unfused(P, kmax, circuit):
     np.testing.assert_allclose(got, ref, atol=1e-12)
 
 
+@pytest.mark.parametrize("kmax", [2, 5])
+def test_fusion_of_adjoint_gates(P, kmax):
+    # "mat_dg" gates reach the fuser as their matrix with the adjoint flag
+    # set; the fused program equals the unfused oracle run, and a dense
+    # circuit followed by its inverse fuses to the identity
+    n = 7
+    dense = [W.Gate("mat", t, m) for t, c, cv, m in W.random_dense_circuit(n, 10, 3, 5 + kmax, with_controls=False)]
+    gates = dense + W.inverse(dense)
+    assert any(g.name == "mat_dg" for g in gates)
+    entries = P.gate_entries(gates)
+    assert all(e[1] is not None and (e[4] == (g.name == "mat_dg")) for e, g in zip(entries, gates))
+    x = W.random_basis_state(n, kmax)
+    f = P.fuse(gates, kmax)
+    blocks = f.blocks()
+    f.free()
+    got = _apply_blocks_with_oracle(n, blocks, basis=x)
+    np.testing.assert_allclose(got, oracle.run(n, gates, basis=x), atol=1e-12)
+    np.testing.assert_allclose(got, oracle.basis_state(n, x), atol=1e-12)
+    # the flag gives exactly the block of the conjugate-transposed matrix
+    t, c, cv, m = W.random_dense_circuit(n, 1, 3, 11, with_controls=False)[0]
+    fa = P.sv_fuse_gates([(t, m, (), None, True)], 5)
+    fb = P.sv_fuse_gates([(t, np.conj(m).T.copy(), (), None, False)], 5)
+    np.testing.assert_array_equal(P.sv_fused_block(fa, 0)[1], P.sv_fused_block(fb, 0)[1])
+    P.sv_fused_free(fa)
+    P.sv_fused_free(fb)
+
+
 def test_fusion_with_controls_and_values(P):
     n = 7
     ops = W.random_dense_circuit(n, 30, 2, 77)
@@ -243,3 +270,45 @@ def test_package_binds_one_hip_runtime():
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, check=True)
     assert out.stdout.split() == ["1", "1"], out.stdout
+
+
+def test_hbm_budget_caps_allocations_before_device_work():
+    """SV_HBM_BUDGET_BYTES caps what libsv allocates; a handle whose
+    workspace does not fit fails with SV_ERR_OUT_OF_MEMORY before any HIP
+    call (so the same status comes back with or without a GPU), and an
+    unparsable value means no cap.  Run in a child process: the cap is read
+    once per process."""
+    import subprocess
+    import sys
+    code = ("import paper_2308_01999_amd as P\n"
+            "print(P.sv_hbm_usage())\n"
+            "try:\n"
+            "    P.sv_handle_create(0, 32 << 20)\n"
+            "    print('created')\n"
+            "except P.SVError as e:\n"
+            "    print(e.status, 'budget' in str(e))\n"
+            "P.sv_set_hbm_budget(0)\n"
+            "print(P.sv_hbm_usage())\n")
+    env = dict(os.environ, SV_HBM_BUDGET_BYTES=str(16 << 20))
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, check=True,
+                         env=env)
+    lines = out.stdout.split("\n")
+    assert lines[0] == f"(0, {16 << 20})"
+    assert lines[1] == "2 True"            # SV_ERR_OUT_OF_MEMORY, message names the budget
+    assert lines[2] == "(0, 0)"
+    env["SV_HBM_BUDGET_BYTES"] = "lots"
+    out = subprocess.run([sys.executable, "-c", "import paper_2308_01999_amd as P; print(P.sv_hbm_usage())"],
+                         cwd=ROOT, capture_output=True, text=True, check=True, env=env)
+    assert out.stdout.strip() == "(0, 0)"
+
+
+def test_hbm_budget_setter(P):
+    used, cap = P.sv_hbm_usage()
+    try:
+        P.sv_set_hbm_budget(1 << 20)
+        assert P.sv_hbm_usage()[1] == 1 << 20
+        with pytest.raises(P.SVError) as e:
+            P.sv_handle_create(0, 12 << 20)
+        assert e.value.status == P.SV_ERR_OUT_OF_MEMORY
+    finally:
+        P.sv_set_hbm_budget(cap)

@@ -31,24 +31,37 @@ def _eps_ok(psi_gpu_p, psi_ref, u, got):
 
 
 def test_serving_mix_matches_alone_and_oracle(P):
-    from paper_2308_01999_amd.serve import Server, replay
+    from paper_2308_01999_amd.serve import Server, replay, slot_reserve
     reqs = W.serving_requests(14, rate_per_s=400.0, seed=3, n_lo=6, n_hi=16, d_lo=4, d_hi=20,
                               n_terms=6, n_shots=256)
-    budget = 3 * (1 << 16) * 8        # a few of the largest states at once
-    srv = Server(slots=3, budget_bytes=budget, dtype="c64", kmax=5)
+    # a few of the largest states at once, beside each slot's reserve
+    states = 3 * (1 << 16) * 8
+    srv = Server(slots=3, budget_bytes=states + 3 * slot_reserve(16), dtype="c64", kmax=5, max_qubits=16)
     mixed = replay(srv, reqs)
     srv.close()
-    alone_srv = Server(slots=1, budget_bytes=budget, dtype="c64", kmax=5)
+    assert all(not m.error for m in mixed.values()), [m.error for m in mixed.values()]
+    alone_srv = Server(slots=1, budget_bytes=states + slot_reserve(16), dtype="c64", kmax=5, max_qubits=16)
     for r in reqs:
         one = replay(alone_srv, [r])[r.rid]
         m = mixed[r.rid]
         np.testing.assert_array_equal(one.expectations, m.expectations)
         np.testing.assert_array_equal(one.samples, m.samples)
     alone_srv.close()
+    h = P.Handle()
     for r in reqs:
         ref = oracle.run(r.n, r.gates)
         er = np.array([oracle.expect_pauli(ref, t) for t in r.terms])
         assert np.max(np.abs(mixed[r.rid].expectations - er)) <= 1e-4
         assert mixed[r.rid].latency > 0
+        # the served samples against the oracle's CDF by the epsilon rule,
+        # with epsilon from the served state: the same fused program rebuilt
+        # on a fresh state, which samples bitwise the same outcomes
+        st = P.State(h, r.n, "c64")
+        st.run(r.gates, max_fused_qubits=5)
+        psi = st.to_numpy().astype(np.complex128)
+        np.testing.assert_array_equal(st.sample(np.asarray(r.uniforms)), mixed[r.rid].samples)
+        st.close()
+        assert _eps_ok(np.abs(psi) ** 2, ref, np.asarray(r.uniforms), mixed[r.rid].samples), r.rid
+    h.close()
     # results arrive for every request; latency covers queueing
     assert all(m.done >= m.admitted >= m.arrival for m in mixed.values())

@@ -3,6 +3,7 @@ budget, slot limits, bounded bypass of a blocked head, and rejection of
 requests that can never fit."""
 import pytest
 
+from paper_2308_01999_amd import serve
 from paper_2308_01999_amd.serve import Admission
 
 
@@ -50,3 +51,52 @@ def test_oversized_request_rejected():
     a = Admission(budget_bytes=100, slots=1)
     with pytest.raises(ValueError):
         a.add(0, 101)
+
+
+def test_footprint_counts_slot_scratch():
+    # a slot keeps its handle workspace and a sampler prefix buffer of one
+    # double per 64 amplitudes of the largest state it may sample
+    assert serve.sampler_scratch_bytes(28) == (1 << 28) // 8
+    assert serve.sampler_scratch_bytes(10) == 256           # 16 doubles, rounded up to 256 B
+    assert serve.slot_reserve(28) == (64 << 20) + (32 << 20)
+    assert serve.state_bytes(28, "c64") == 2 << 30 and serve.state_bytes(10, "c128") == 16 << 10
+    total = 3 << 30
+    left = serve.request_budget(total, 4, 28)
+    assert left == total - 4 * ((64 << 20) + (32 << 20))
+    # with the reserve set aside, a 28-qubit complex64 state (2 GiB) and a
+    # 27-qubit one (1 GiB) no longer fit together in 3 GiB
+    a = Admission(left, 4)
+    a.add(0, serve.state_bytes(28, "c64"))
+    a.add(1, serve.state_bytes(27, "c64"))
+    assert a.pick() == (0, 2 << 30)
+    assert a.pick() is None
+    with pytest.raises(ValueError):
+        serve.request_budget(256 << 20, 4, 28)
+
+
+def test_budget_from_environment(monkeypatch):
+    monkeypatch.setenv("SV_HBM_BUDGET_BYTES", str(3 << 30))
+    assert serve.default_budget() == 3 << 30
+    monkeypatch.setenv("SV_HBM_BUDGET_BYTES", "x")
+    assert serve.default_budget() == 64 << 30
+    monkeypatch.delenv("SV_HBM_BUDGET_BYTES")
+    assert serve.default_budget() == 64 << 30
+
+
+def test_rejected_request_leaves_no_state():
+    # submit() registers a request only once admission has accepted it
+    srv = serve.Server.__new__(serve.Server)
+    import threading
+    srv.cv = threading.Condition()
+    srv.pending = {}
+    srv.dtype = "c64"
+    srv.max_qubits = 28
+    srv.adm = Admission(1 << 20, 1)
+    with pytest.raises(ValueError):
+        srv.submit(serve.Request(7, 20, [], [], None))     # 8 MiB > 1 MiB
+    assert srv.pending == {} and not srv.adm.queue
+    with pytest.raises(ValueError):
+        srv.submit(serve.Request(8, 29, [], [], None))     # above max_qubits
+    assert srv.pending == {}
+    srv.submit(serve.Request(9, 10, [], [], None))
+    assert list(srv.pending) == [9] and list(srv.adm.queue) == [(9, 8 << 10)]
