@@ -433,6 +433,27 @@ sv_status_t sv_expect_pauli(sv_state_t s, const sv_pauli_term_t* terms, int32_t 
 sv_status_t sv_sample(sv_state_t s, const double* uniforms, int64_t n_shots,
                       const int32_t* bit_ordering, int32_t n_bits, uint64_t* out);
 
+/*
+ * The sampler of sv_sample for callers that cannot allocate device memory
+ * (code that must not call hipMalloc: tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, outputs and errors as sv_sample, and
+ * the same kernels, so the outcomes are identical.  sv_sample keeps its block
+ * prefixes in a handle buffer that grows with the state (a device
+ * allocation on first use); this call allocates nothing: all of its device
+ * scratch lives in one fixed array of SV_SAMPLE_NOALLOC_SCRATCH_BYTES per
+ * GPU, part of libsv's code object and held until the process ends, and it
+ * does not touch the handle's workspace.  States of more than
+ * SV_SAMPLE_NOALLOC_MAX_QUBITS qubits are rejected with
+ * SV_ERR_INVALID_VALUE before any device work.  Every call on one GPU shares
+ * that GPU's array (each call rewrites what it reads), so calls that overlap
+ * on one GPU, from different handles or threads, race: the caller must
+ * serialise them.  Blocks.
+ */
+#define SV_SAMPLE_NOALLOC_MAX_QUBITS 28
+#define SV_SAMPLE_NOALLOC_SCRATCH_BYTES (37u << 20)
+sv_status_t sv_sample_noalloc(sv_state_t s, const double* uniforms, int64_t n_shots,
+                              const int32_t* bit_ordering, int32_t n_bits, uint64_t* out);
+
 /* ------------------------------------------------------------------ copies */
 
 /* Copies amplitudes [first, first + count) to / from host memory (Table I:

@@ -36,6 +36,7 @@ SV_OK, SV_ERR_INVALID_VALUE, SV_ERR_OUT_OF_MEMORY, SV_ERR_NOT_SUPPORTED, SV_ERR_
 SV_C64, SV_C128 = 0, 1
 SV_MAX_QUBITS = 36
 SV_MAX_TARGETS = 10
+SV_SAMPLE_NOALLOC_MAX_QUBITS = 28
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -87,6 +88,7 @@ _SIGS = {
     "sv_renormalize": [_vp, _pd],
     "sv_expect_pauli": [_vp, ctypes.POINTER(sv_pauli_term_t), _i32, _pd],
     "sv_sample": [_vp, _pd, _i64, _pi32, _i32, _pu64],
+    "sv_sample_noalloc": [_vp, _pd, _i64, _pi32, _i32, _pu64],
     "sv_apply_pauli_rotation": [_vp, ctypes.c_double, ctypes.POINTER(sv_pauli_term_t), _pi32, _pi32, _i32],
     "sv_measure_probabilities": [_vp, _pi32, _i32, _pd],
     "sv_zbasis_probabilities": [_vp, _pi32, _i32, _pd, _pd],
@@ -484,6 +486,15 @@ def sv_sample(s: int, uniforms, bit_ordering=None) -> np.ndarray:
     bo = None if bit_ordering is None else _i32arr(bit_ordering)
     nb = 0 if bit_ordering is None else len(bit_ordering)
     _check(_L.sv_sample(_vp(s), _dptr(u), u.size, bo, nb, out.ctypes.data_as(_pu64)))
+    return out[: u.size]
+
+
+def sv_sample_noalloc(s: int, uniforms, bit_ordering=None) -> np.ndarray:
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    out = np.zeros(max(1, u.size), dtype=np.uint64)
+    bo = None if bit_ordering is None else _i32arr(bit_ordering)
+    nb = 0 if bit_ordering is None else len(bit_ordering)
+    _check(_L.sv_sample_noalloc(_vp(s), _dptr(u), u.size, bo, nb, out.ctypes.data_as(_pu64)))
     return out[: u.size]
 
 

@@ -1170,29 +1170,54 @@ sv_status_t sv_expect_matrix(sv_state_t s, const double* matrix, const int32_t* 
     });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Arguments of a sampling call; returns false when there is nothing to do.
+bool check_sample_args(const sv_state_s* s, const double* uniforms, int64_t n_shots, const int32_t* bit_ordering,
+                       int32_t* n_bits, uint64_t* out)
+{
+    check_state(s);
+    SV_CHECK(n_shots >= 0, "n_shots is negative");
+    if (n_shots == 0) return false;
+    SV_CHECK(uniforms != nullptr && out != nullptr, "NULL argument");
+    for (int64_t i = 0; i < n_shots; ++i)
+        SV_CHECK(uniforms[i] >= 0.0 && uniforms[i] < 1.0, "uniforms must lie in [0, 1)");
+    if (bit_ordering) {
+        SV_CHECK(*n_bits >= 1 && *n_bits <= s->n, "n_bits must be in [1, n]");
+        uint64_t seen = 0;
+        for (int b = 0; b < *n_bits; ++b) {
+            const int q = bit_ordering[b];
+            SV_CHECK(q >= 0 && q < s->n, "bit_ordering entry out of range");
+            SV_CHECK(!((seen >> q) & 1), "bit_ordering repeats a qubit");
+            seen |= uint64_t(1) << q;
+        }
+    } else {
+        *n_bits = 0;
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
 sv_status_t sv_sample(sv_state_t s, const double* uniforms, int64_t n_shots, const int32_t* bit_ordering,
                       int32_t n_bits, uint64_t* out)
 {
     return guarded([&] {
-        check_state(s);
-        SV_CHECK(n_shots >= 0, "n_shots is negative");
-        if (n_shots == 0) return;
-        SV_CHECK(uniforms != nullptr && out != nullptr, "NULL argument");
-        for (int64_t i = 0; i < n_shots; ++i)
-            SV_CHECK(uniforms[i] >= 0.0 && uniforms[i] < 1.0, "uniforms must lie in [0, 1)");
-        if (bit_ordering) {
-            SV_CHECK(n_bits >= 1 && n_bits <= s->n, "n_bits must be in [1, n]");
-            uint64_t seen = 0;
-            for (int b = 0; b < n_bits; ++b) {
-                const int q = bit_ordering[b];
-                SV_CHECK(q >= 0 && q < s->n, "bit_ordering entry out of range");
-                SV_CHECK(!((seen >> q) & 1), "bit_ordering repeats a qubit");
-                seen |= uint64_t(1) << q;
-            }
-        } else {
-            n_bits = 0;
-        }
+        if (!check_sample_args(s, uniforms, n_shots, bit_ordering, &n_bits, out)) return;
         run_sample(s->h, s->dt, s->d, s->n, uniforms, n_shots, bit_ordering, n_bits, out);
+    });
+}
+
+sv_status_t sv_sample_noalloc(sv_state_t s, const double* uniforms, int64_t n_shots, const int32_t* bit_ordering,
+                              int32_t n_bits, uint64_t* out)
+{
+    return guarded([&] {
+        if (!check_sample_args(s, uniforms, n_shots, bit_ordering, &n_bits, out)) return;
+        run_sample_noalloc(s->h, s->dt, s->d, s->n, uniforms, n_shots, bit_ordering, n_bits, out);
     });
 }
 

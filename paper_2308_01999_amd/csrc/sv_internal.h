@@ -184,6 +184,10 @@ void run_expect(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const Pau
 
 void run_sample(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const double* u,
                 int64_t n_shots, const int32_t* bit_ordering, int n_bits, uint64_t* out);
+// The same sampler with every device buffer in a fixed per-GPU array of
+// SV_SAMPLE_NOALLOC_SCRATCH_BYTES (no allocation; n <= SV_SAMPLE_NOALLOC_MAX_QUBITS).
+void run_sample_noalloc(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const double* u,
+                        int64_t n_shots, const int32_t* bit_ordering, int n_bits, uint64_t* out);
 
 // Measurement: unnormalised probabilities of the 2^m outcomes of qubits
 // (m <= SV_MAX_TARGETS) or of the two parities of the bits in mask; collapse

@@ -13,6 +13,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -692,58 +694,149 @@ void run_expect_t(sv_handle_s* h, const void* psi_v, int n, const PauliMasks* te
     for (int t = 0; t < n_terms; ++t) out[t] = sums[t] / norm;
 }
 
+// Device buffers of one sampling call: block prefixes C (nc * nbk doubles),
+// chunk totals S (nc), chunk boundaries B (nc + 1), and a shot batch of
+// `batch` uniforms and indices.
+struct SampleBuffers {
+    double* C;
+    double* S;
+    double* B;
+    double* du;
+    uint64_t* didx;
+    int64_t batch;
+};
+
 template <typename R>
-void run_sample_t(sv_handle_s* h, const void* psi_v, int n, const double* u, int64_t n_shots,
-                  const int32_t* bit_ordering, int n_bits, uint64_t* out)
+void sample_core(hipStream_t stream, int cu_count, const void* psi_v, int n, const double* u, int64_t n_shots,
+                 const int32_t* bit_ordering, int n_bits, uint64_t* out, const SampleBuffers& sb)
 {
     using T2 = typename Cx<R>::T;
     const T2* psi = static_cast<const T2*>(psi_v);
     const SampleLayout L = sample_layout(n);
-    double* C = reinterpret_cast<double*>(ensure_aux(h, sizeof(double) * L.nc * L.nbk));
+    hipLaunchKernelGGL((k_block_prefix<R>), dim3(unsigned(std::min<uint64_t>(L.nc, uint64_t(cu_count) * 8))),
+                       dim3(kThreads), 0, stream, psi, L, sb.C, sb.S);
+    SV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(kScanThreads), 0, stream, sb.S, L.nc, sb.B);
+    SV_HIP(hipGetLastError());
+    double total = 0.0;
+    SV_HIP(hipMemcpyAsync(&total, sb.B + L.nc, sizeof(double), hipMemcpyDeviceToHost, stream));
+    SV_HIP(hipStreamSynchronize(stream));
+    if (!(total > 0.0)) throw Error{SV_ERR_INVALID_VALUE, "state has zero norm"};
+
+    BitArgs ba{};
+    ba.n_bits = n_bits;
+    for (int b = 0; b < n_bits; ++b) ba.bits[b] = bit_ordering[b];
+    for (int64_t s0 = 0; s0 < n_shots; s0 += sb.batch) {
+        const uint64_t ns = uint64_t(std::min<int64_t>(sb.batch, n_shots - s0));
+        SV_HIP(hipMemcpyAsync(sb.du, u + s0, sizeof(double) * ns, hipMemcpyHostToDevice, stream));
+        const unsigned sg = unsigned((ns + kThreads - 1) / kThreads);
+        hipLaunchKernelGGL((k_resolve<R>), dim3(sg), dim3(kThreads), 0, stream, psi, L, sb.B, sb.C, sb.du, ns,
+                           sb.didx);
+        SV_HIP(hipGetLastError());
+        if (n_bits > 0) {
+            hipLaunchKernelGGL(k_extract_bits, dim3(sg), dim3(kThreads), 0, stream, sb.didx, ns, ba);
+            SV_HIP(hipGetLastError());
+        }
+        SV_HIP(hipMemcpyAsync(out + s0, sb.didx, sizeof(uint64_t) * ns, hipMemcpyDeviceToHost, stream));
+        SV_HIP(hipStreamSynchronize(stream));
+    }
+}
+
+// The handle's sampler: block prefixes in the handle's growable scratch,
+// everything else in its workspace.
+template <typename R>
+void run_sample_t(sv_handle_s* h, const void* psi_v, int n, const double* u, int64_t n_shots,
+                  const int32_t* bit_ordering, int n_bits, uint64_t* out)
+{
+    const SampleLayout L = sample_layout(n);
+    SampleBuffers sb{};
+    sb.C = reinterpret_cast<double*>(ensure_aux(h, sizeof(double) * L.nc * L.nbk));
     char* w = h->ws + kMatRingBytes;
     auto take = [&](size_t bytes) {
         char* p = w;
         w += (bytes + 255) & ~size_t(255);
         return p;
     };
-    double* S = reinterpret_cast<double*>(take(sizeof(double) * L.nc));
-    double* B = reinterpret_cast<double*>(take(sizeof(double) * (L.nc + 1)));
+    sb.S = reinterpret_cast<double*>(take(sizeof(double) * L.nc));
+    sb.B = reinterpret_cast<double*>(take(sizeof(double) * (L.nc + 1)));
     const size_t used = size_t(w - h->ws);
     if (used >= h->ws_bytes) throw Error{SV_ERR_OUT_OF_MEMORY, "workspace too small for the sampler"};
     const size_t per_shot = sizeof(double) + sizeof(uint64_t);
     int64_t batch = int64_t((h->ws_bytes - used) / per_shot) - 1024;
     if (batch > (int64_t(1) << 22)) batch = int64_t(1) << 22;
     if (batch < 1) throw Error{SV_ERR_OUT_OF_MEMORY, "workspace too small for the sampler"};
-    double* du = reinterpret_cast<double*>(take(sizeof(double) * batch));
-    uint64_t* didx = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * batch));
+    sb.batch = batch;
+    sb.du = reinterpret_cast<double*>(take(sizeof(double) * batch));
+    sb.didx = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * batch));
     if (size_t(w - h->ws) > h->ws_bytes) throw Error{SV_ERR_INTERNAL, "sampler workspace layout"};
+    sample_core<R>(h->stream, h->cu_count, psi_v, n, u, n_shots, bit_ordering, n_bits, out, sb);
+}
 
-    hipLaunchKernelGGL((k_block_prefix<R>), dim3(unsigned(std::min<uint64_t>(L.nc, uint64_t(h->cu_count) * 8))),
-                       dim3(kThreads), 0, h->stream, psi, L, C, S);
-    SV_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(kScanThreads), 0, h->stream, S, L.nc, B);
-    SV_HIP(hipGetLastError());
-    double total = 0.0;
-    SV_HIP(hipMemcpyAsync(&total, B + L.nc, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    SV_HIP(hipStreamSynchronize(h->stream));
-    if (!(total > 0.0)) throw Error{SV_ERR_INVALID_VALUE, "state has zero norm"};
+// ------------------------------------------- allocation-free sampler scratch
+//
+// The sampler variant for callers that cannot allocate device memory keeps
+// all of its scratch in this fixed array (one copy per GPU, held until the
+// process ends): block prefixes for states of up to SV_SAMPLE_NOALLOC_MAX_QUBITS
+// qubits, chunk totals and boundaries, and one shot batch.  In host code the
+// array's name is not a device address: its address on each device comes
+// from hipGetSymbolAddress, looked up once per device and kept.
 
-    BitArgs ba{};
-    ba.n_bits = n_bits;
-    for (int b = 0; b < n_bits; ++b) ba.bits[b] = bit_ordering[b];
-    for (int64_t s0 = 0; s0 < n_shots; s0 += batch) {
-        const uint64_t ns = uint64_t(std::min<int64_t>(batch, n_shots - s0));
-        SV_HIP(hipMemcpyAsync(du, u + s0, sizeof(double) * ns, hipMemcpyHostToDevice, h->stream));
-        const unsigned sg = unsigned((ns + kThreads - 1) / kThreads);
-        hipLaunchKernelGGL((k_resolve<R>), dim3(sg), dim3(kThreads), 0, h->stream, psi, L, B, C, du, ns, didx);
-        SV_HIP(hipGetLastError());
-        if (n_bits > 0) {
-            hipLaunchKernelGGL(k_extract_bits, dim3(sg), dim3(kThreads), 0, h->stream, didx, ns, ba);
-            SV_HIP(hipGetLastError());
-        }
-        SV_HIP(hipMemcpyAsync(out + s0, didx, sizeof(uint64_t) * ns, hipMemcpyDeviceToHost, h->stream));
-        SV_HIP(hipStreamSynchronize(h->stream));
+constexpr size_t kNoAllocPrefixBytes = (size_t(1) << SV_SAMPLE_NOALLOC_MAX_QUBITS) / kBlk * sizeof(double);
+constexpr uint64_t kNoAllocMaxChunks = (uint64_t(1) << SV_SAMPLE_NOALLOC_MAX_QUBITS) / (4 * kSub);
+constexpr size_t kNoAllocChunkBytes = (kNoAllocMaxChunks + 1) * sizeof(double) + 256;
+constexpr int kMaxScratchDevices = 64;
+constexpr int64_t kNoAllocShotBatch = int64_t(1) << 18;
+constexpr size_t kNoAllocShotBytes = size_t(kNoAllocShotBatch) * sizeof(double);
+static_assert(kNoAllocPrefixBytes + 2 * kNoAllocChunkBytes + 2 * kNoAllocShotBytes <= SV_SAMPLE_NOALLOC_SCRATCH_BYTES,
+              "allocation-free sampler scratch too small");
+
+}  // namespace
+}  // namespace sv
+
+static __device__ __align__(256) char scratch[SV_SAMPLE_NOALLOC_SCRATCH_BYTES];
+
+namespace sv {
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on `device` (looked up once, with that
+// device current).
+char* noalloc_scratch(int device)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    SV_CHECK(device >= 0 && device < kMaxScratchDevices, "device index out of range");
+    if (!g_scratch_ptr[device]) {
+        int cur = 0;
+        SV_HIP(hipGetDevice(&cur));
+        if (cur != device) SV_HIP(hipSetDevice(device));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        SV_HIP(e);
+        SV_CHECK(p != nullptr, "hipGetSymbolAddress returned no address for the sampler scratch");
+        g_scratch_ptr[device] = p;
     }
+    return static_cast<char*>(g_scratch_ptr[device]);
+}
+
+template <typename R>
+void run_sample_noalloc_t(sv_handle_s* h, const void* psi_v, int n, const double* u, int64_t n_shots,
+                          const int32_t* bit_ordering, int n_bits, uint64_t* out)
+{
+    const SampleLayout L = sample_layout(n);
+    char* w = noalloc_scratch(h->device);
+    SampleBuffers sb{};
+    sb.C = reinterpret_cast<double*>(w);
+    sb.S = reinterpret_cast<double*>(w + kNoAllocPrefixBytes);
+    sb.B = reinterpret_cast<double*>(w + kNoAllocPrefixBytes + kNoAllocChunkBytes);
+    sb.du = reinterpret_cast<double*>(w + kNoAllocPrefixBytes + 2 * kNoAllocChunkBytes);
+    sb.didx = reinterpret_cast<uint64_t*>(w + kNoAllocPrefixBytes + 2 * kNoAllocChunkBytes + kNoAllocShotBytes);
+    sb.batch = kNoAllocShotBatch;
+    if (sizeof(double) * L.nc * L.nbk > kNoAllocPrefixBytes || L.nc > kNoAllocMaxChunks)
+        throw Error{SV_ERR_INTERNAL, "allocation-free sampler layout"};
+    sample_core<R>(h->stream, h->cu_count, psi_v, n, u, n_shots, bit_ordering, n_bits, out, sb);
 }
 
 // --------------------------------------------------------- measurement
@@ -1364,6 +1457,18 @@ void run_sample(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const dou
         run_sample_t<float>(h, psi, n, u, n_shots, bit_ordering, n_bits, out);
     else
         run_sample_t<double>(h, psi, n, u, n_shots, bit_ordering, n_bits, out);
+}
+
+void run_sample_noalloc(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const double* u, int64_t n_shots,
+                        const int32_t* bit_ordering, int n_bits, uint64_t* out)
+{
+    if (n > SV_SAMPLE_NOALLOC_MAX_QUBITS)
+        throw Error{SV_ERR_INVALID_VALUE, "state too large for sv_sample_noalloc (at most " +
+                                              std::to_string(SV_SAMPLE_NOALLOC_MAX_QUBITS) + " qubits)"};
+    if (dt == SV_C64)
+        run_sample_noalloc_t<float>(h, psi, n, u, n_shots, bit_ordering, n_bits, out);
+    else
+        run_sample_noalloc_t<double>(h, psi, n, u, n_shots, bit_ordering, n_bits, out);
 }
 
 
