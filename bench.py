@@ -561,8 +561,9 @@ def large_leg(P, W, torch, H):
 def batched_leg(P, W, torch, H, count, steps, warmup, sample):
     """4096 independent complex64 brickwork circuits (qubits uniform in
     8..20, depth uniform in 10..40), each returning <Z_i Z_i+1> for all i, in
-    one persistent launch with autotuned fusion widths; per-circuit latency
-    from the device wall clock.  Baseline: a sample of the same circuits run
+    one recorded run: circuits below 15 qubits on the persistent kernel with
+    autotuned fusion widths, larger ones on the level path; per-circuit
+    latency from the device wall clock.  Baseline: a sample of the same circuits run
     one at a time through the plain complex128 path (one sv_apply_matrix per
     gate, then sv_expect_pauli), timed on the host."""
     import numpy as np
@@ -607,7 +608,7 @@ def batched_leg(P, W, torch, H, count, steps, warmup, sample):
     base_lat = np.array(base_lat)
     return {
         "workload": f"{count} complex64 brickwork circuits, qubits uniform 8-20, depth uniform 10-40, "
-                    f"<Z_i Z_i+1> for all i, one persistent launch",
+                    f"<Z_i Z_i+1> for all i, one recorded run (persistent kernel below 15 qubits, level path above)",
         "circuits": count,
         "states_GB": round(state_gb, 3),
         "kernel_ms": round(1e3 * float(np.median(kts)), 3),

@@ -466,25 +466,41 @@ sv_status_t sv_copy_from_host(sv_state_t s, const void* src, uint64_t first, uin
 typedef struct sv_batch_s* sv_batch_t;
 
 /*
- * A batch of independent complex64 circuits run together by one persistent
- * kernel launch (the batched execution of many small states; the paper's
- * fused-gate path of Sec. II-B applied to each).  Circuit i has n_qubits[i]
+ * A batch of independent complex64 circuits run together in one recorded
+ * run (the batched execution of many small states; the paper's fused-gate
+ * path of Sec. II-B applied to each).  Circuit i has n_qubits[i]
  * in [1, 30] qubits, starts from |0..0>, and is the named-gate list
  * [gate_offsets[i], gate_offsets[i+1]) of the flat arrays codes, qubits
  * (2 per gate) and params (3 per gate), coded as for sv_fuse_gate_list.
  * Its observables are the Z-type Pauli strings z_masks[term_offsets[i] ..
  * term_offsets[i+1]) (bit q set = Z on qubit q), at most 32 per circuit;
  * each result is <psi|Z..Z|psi> / <psi|psi> accumulated in FP64.
- * max_fused_qubits in [1, 5] fixes the fusion width; 0 lets the autotuner
- * pick it per qubit count by timing the batch kernel at widths 3..5 on the
- * batch's own circuits (cached for the process).  Circuits are fused on host
- * threads and their descriptors uploaded once.  Host arrays may be freed on
- * return.
+ * Circuits below the handle's level-path qubit count
+ * (sv_handle_set_batch_level_qubits) run in one persistent kernel launch,
+ * one workgroup per circuit at a time; max_fused_qubits in [1, 5] fixes
+ * their fusion width, 0 lets the autotuner pick it per qubit count by timing
+ * the batch kernel at widths 3..5 on the batch's own circuits (cached for
+ * the process).  Circuits of at least that many qubits run on the level
+ * path: fused into blocks of up to five qubits, each block swept as a
+ * five-qubit gate by the single-state tile sweep, block l of all of them in
+ * launch l.  A circuit's results depend only on the circuit itself and the
+ * handle's settings, never on the rest of the batch.  Circuits are fused on
+ * host threads and their descriptors uploaded once.  Host arrays may be
+ * freed on return.
  */
 sv_status_t sv_batch_create(sv_handle_t h, int32_t n_circuits, const int32_t* n_qubits,
                             const int32_t* gate_offsets, const int32_t* codes, const int32_t* qubits,
                             const double* params, const int32_t* term_offsets, const uint64_t* z_masks,
                             int32_t max_fused_qubits, sv_batch_t* out);
+
+/* Qubit count from which circuits of batches created later on handle h run on
+ * the level path (default SV_BATCH_LEVEL_DEFAULT); SV_BATCH_LEVEL_NONE keeps
+ * every circuit on the persistent kernel.  Range [SV_BATCH_LEVEL_MIN_QUBITS,
+ * SV_BATCH_LEVEL_NONE]; SV_ERR_INVALID_VALUE otherwise. */
+#define SV_BATCH_LEVEL_MIN_QUBITS 13
+#define SV_BATCH_LEVEL_DEFAULT 15
+#define SV_BATCH_LEVEL_NONE 31
+sv_status_t sv_handle_set_batch_level_qubits(sv_handle_t h, int32_t n_qubits);
 
 /* Bytes of device memory the batch's states need (*state_bytes) and, if
  * byte_offsets is not NULL, the byte offset of each circuit's state. */
@@ -495,16 +511,16 @@ sv_status_t sv_batch_state_layout(sv_batch_t b, uint64_t* state_bytes, uint64_t*
 sv_status_t sv_batch_info(sv_batch_t b, int32_t n_qubits, int32_t* max_fused_qubits, int32_t* blocks_per_circuit);
 
 /*
- * Runs the whole batch in one launch on the handle's stream and blocks.  The
- * run (queue reset plus the persistent kernel) is recorded into a HIP graph
- * on the first call for a given states buffer and replayed by later calls
- * with the same buffer.
+ * Runs the whole batch on the handle's stream and blocks.  The run (queue
+ * reset, the persistent kernel, the level path's launches) is recorded into
+ * a HIP graph on the first call for a given states buffer and replayed by
+ * later calls with the same buffer.
  * states: device buffer of sv_batch_state_layout bytes, 256-byte aligned; on
  * return it holds every circuit's final state.  expect_out (host, may be
  * NULL): all term results in term order.  latency_s (host, may be NULL):
- * per circuit, the device wall-clock time from the first workgroup's start
- * to that circuit's completion.  kernel_s (may be NULL): the event time of
- * the graph launch.
+ * per circuit, the device wall-clock time from the run's start to that
+ * circuit's completion (its state and expectations written).  kernel_s
+ * (may be NULL): the event time of the graph launch.
  */
 sv_status_t sv_batch_run(sv_batch_t b, void* states, double* expect_out, double* latency_s, double* kernel_s);
 

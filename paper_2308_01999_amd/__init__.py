@@ -63,6 +63,7 @@ _SIGS = {
     "sv_handle_destroy": [_vp],
     "sv_handle_set_stream": [_vp, _vp],
     "sv_handle_set_tile_mode": [_vp, _i32],
+    "sv_handle_set_batch_level_qubits": [_vp, _i32],
     "sv_graph_create": [_vp, _vp, ctypes.POINTER(_vp)],
     "sv_graph_launch": [_vp],
     "sv_graph_destroy": [_vp],
@@ -191,6 +192,13 @@ TILE_WARM_SWEEPS = 64  # SV_TILE_WARM_SWEEPS
 
 def sv_handle_set_tile_mode(h: int, mode: int) -> None:
     _check(_L.sv_handle_set_tile_mode(_vp(h), _i32(mode)))
+
+
+SV_BATCH_LEVEL_MIN_QUBITS, SV_BATCH_LEVEL_DEFAULT, SV_BATCH_LEVEL_NONE = 13, 15, 31
+
+
+def sv_handle_set_batch_level_qubits(h: int, n_qubits: int) -> None:
+    _check(_L.sv_handle_set_batch_level_qubits(_vp(h), _i32(n_qubits)))
 
 
 def sv_graph_create(s: int, f: int) -> int:
@@ -531,6 +539,9 @@ class Handle:
 
     def set_tile_mode(self, mode: int) -> None:
         sv_handle_set_tile_mode(self.h, mode)
+
+    def set_batch_level_qubits(self, n_qubits: int) -> None:
+        sv_handle_set_batch_level_qubits(self.h, n_qubits)
 
     def close(self):
         if self.h:

@@ -367,6 +367,16 @@ sv_status_t sv_handle_set_tile_mode(sv_handle_t h, int32_t mode)
     });
 }
 
+sv_status_t sv_handle_set_batch_level_qubits(sv_handle_t h, int32_t n_qubits)
+{
+    return guarded([&] {
+        SV_CHECK(h != nullptr, "handle is NULL");
+        SV_CHECK(n_qubits >= SV_BATCH_LEVEL_MIN_QUBITS && n_qubits <= SV_BATCH_LEVEL_NONE,
+                 "level-path qubit count must be in [SV_BATCH_LEVEL_MIN_QUBITS, SV_BATCH_LEVEL_NONE]");
+        h->batch_level_qubits = n_qubits;
+    });
+}
+
 sv_status_t sv_sync(sv_handle_t h)
 {
     return guarded([&] {

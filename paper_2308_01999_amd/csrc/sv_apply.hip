@@ -12,10 +12,12 @@
 
 #include <type_traits>
 
-#include "sv_internal.h"
+#include "sv_tile.h"
 
 namespace sv {
 namespace {
+
+using namespace tile;
 
 template <typename R>
 struct Cx;
@@ -241,140 +243,6 @@ __global__ __launch_bounds__(256) void k_apply_mfma_c64_k4(float2* __restrict__ 
 // tile t is in LDS.  Each wave owns whole groups, so the in-place update in
 // LDS needs no synchronisation beyond the three barriers per tile.
 
-struct TileArgs {
-    uint64_t n_tiles;
-    uint64_t tiles_per_wg;
-    int32_t L;
-    int32_t n_hi;
-    int32_t hi_pos[SV_MAX_TARGETS];
-    int32_t n_lo;
-    int32_t lo_pos[SV_MAX_TARGETS];
-    int32_t lds_off[64];  // matrix index -> LDS offset from the group's base
-    int32_t trot;         // tile order: tile index rotated right by trot bits over lg_tiles bits
-    int32_t lg_tiles;     // log2 n_tiles
-};
-
-__device__ __forceinline__ uint64_t insert_zero_bits(uint64_t v, const int32_t* pos, int n)
-{
-    for (int j = 0; j < n; ++j) {
-        const int p = pos[j];
-        const uint64_t lo = v & ((uint64_t(1) << p) - 1);
-        v = ((v >> p) << (p + 1)) | lo;
-    }
-    return v;
-}
-
-__device__ __forceinline__ uint64_t deposit_bits(uint32_t r, const int32_t* pos, int n)
-{
-    uint64_t o = 0;
-    for (int b = 0; b < n; ++b) o |= uint64_t((r >> b) & 1u) << pos[b];
-    return o;
-}
-
-constexpr int kTileThreads = 256;
-constexpr int kTileVecs = 8;  // 16-byte vectors per thread per tile (32 KiB / 256 / 16)
-
-#ifndef SV_TILE_NT
-#define SV_TILE_NT 1
-#endif
-#ifndef SV_TILE_WGS_PER_CU
-#define SV_TILE_WGS_PER_CU 32
-#endif
-#ifndef SV_TILES_PER_WG_MAX
-#define SV_TILES_PER_WG_MAX 64
-#endif
-#ifndef SV_TILES_PER_WG_MAX_K5
-#define SV_TILES_PER_WG_MAX_K5 4
-#endif
-
-
-typedef float nf4 __attribute__((ext_vector_type(4)));
-typedef double nd2 __attribute__((ext_vector_type(2)));
-
-template <typename V>
-__device__ __forceinline__ V gload(const V* p)
-{
-    if (SV_TILE_NT) {
-        if constexpr (sizeof(V) == 16 && std::is_same<V, float4>::value) {
-            const nf4 v = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(p));
-            return V{v.x, v.y, v.z, v.w};
-        } else {
-            const nd2 v = __builtin_nontemporal_load(reinterpret_cast<const nd2*>(p));
-            return V{v.x, v.y};
-        }
-    }
-    return *p;
-}
-
-template <typename V>
-__device__ __forceinline__ void gstore(V* p, const V v)
-{
-    if (SV_TILE_NT) {
-        if constexpr (std::is_same<V, float4>::value) {
-            __builtin_nontemporal_store(nf4{v.x, v.y, v.z, v.w}, reinterpret_cast<nf4*>(p));
-        } else {
-            __builtin_nontemporal_store(nd2{v.x, v.y}, reinterpret_cast<nd2*>(p));
-        }
-        return;
-    }
-    *p = v;
-}
-
-// The 8 per-thread vectors live in named registers (an array carried across
-// the tile loop would be placed in scratch memory by the compiler).
-#define SV_REP8(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
-
-// Offsets (relative to a tile's base) of the thread's 8 vectors; vector u
-// of thread tid holds tile-local amplitudes starting at
-// i = (u * 256 + tid) * amps_per_vec, which is also its LDS position.  Its
-// run index i >> L is the same for the whole wave (L >= 6 for complex128 and
-// >= 7 for complex64, so the lane bits of tid stay below L), so the 64-bit
-// run offset is a scalar and only the 32-bit offset inside the run is
-// per lane.
-template <int APV, int NT = kTileThreads>
-__device__ __forceinline__ void tile_offsets(const TileArgs& a, uint64_t* roff, uint32_t* poff)
-{
-    const int mask = (1 << a.L) - 1;
-#pragma unroll
-    for (int u = 0; u < kTileVecs; ++u) {
-        const int i = (u * NT + int(threadIdx.x)) * APV;
-        const uint32_t r = uint32_t(__builtin_amdgcn_readfirstlane(i >> a.L));
-        roff[u] = deposit_bits(r, a.hi_pos, a.n_hi);
-        poff[u] = uint32_t(i & mask);
-    }
-}
-
-// Global index of tile t's first amplitude.  With a.trot > 0 the tile index
-// is first rotated right by trot bits: workgroup w, which sweeps its
-// tiles_per_wg = 2^trot tiles t = w * 2^trot + j, then touches tiles
-// w + j * (n_tiles / 2^trot), so at any moment the workgroups in flight work
-// on neighbouring tiles instead of tiles 2^trot apart.
-__device__ __forceinline__ uint64_t tile_base(uint64_t t, const TileArgs& a)
-{
-    if (a.trot > 0) t = ((t & ((uint64_t(1) << a.trot) - 1)) << (a.lg_tiles - a.trot)) | (t >> a.trot);
-    return insert_zero_bits(t << a.L, a.hi_pos, a.n_hi);
-}
-
-// LDS slot of tile-local amplitude a: its low five bits are XORed with bits
-// 5-9.  The gathers read, per instruction, the amplitudes of consecutive
-// groups; when the low target bits spread those groups 2^m amplitudes apart
-// (m <= 5), they would all map to one LDS bank without this.  Bijective on
-// every aligned block of 1024 amplitudes, so it only permutes a tile.
-__device__ __forceinline__ int lds_swz(int a) { return a ^ ((a >> 5) & 31); }
-
-// complex64 staging moves pairs (i, i + 1), i even: both land in one aligned
-// 16-byte slot, in swapped order when bit 0 of the XOR is set.
-__device__ __forceinline__ int pair_slot(int i) { return i ^ ((i >> 5) & 30); }
-__device__ __forceinline__ bool pair_swapped(int i) { return ((i >> 5) & 1) != 0; }
-__device__ __forceinline__ float4 swap_pair(const float4 v, bool sw)
-{
-    return sw ? float4{v.z, v.w, v.x, v.y} : v;
-}
-
-// The three A operands (Re M, Im M, Re M + Im M) of the complex64 k = 5
-// sweep, kept in LDS (44 KiB per workgroup with the tile: three per CU).
-constexpr int kK5AParts = 3;
-
 // The wide shape of the complex64 k = 5 sweep: 64 KiB tiles in 512-thread
 // workgroups (8 waves, 256 groups), so every run of a tile is 2 KiB long
 // instead of 1 KiB.  Which shape runs is chosen per handle (tile_shape).
@@ -394,74 +262,7 @@ __global__ __launch_bounds__(NT, NT == 512 ? SV_K5_WIDE_WAVES : 1) void k_tile_c
     // the packed A operands (same for every wave): 3 x 64 lanes x 4 float4,
     // read back four k-steps at a time so only 12 of them are live at once
     __shared__ float4 amat[kK5AParts * 64 * 4];
-    const uint64_t t0 = uint64_t(blockIdx.x) * a.tiles_per_wg;
-    if (t0 >= a.n_tiles) return;
-    const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 31, half = lane >> 5;
-    for (int e = tid; e < kK5AParts * 64 * 4; e += NT) amat[e] = mats[e];
-    uint64_t roff[kTileVecs];
-    uint32_t poff[kTileVecs];
-    tile_offsets<2, NT>(a, roff, poff);
-    const int pb = int(insert_zero_bits(uint64_t(wave * 32 + col), a.lo_pos, a.n_lo));
-    const int pin = pb + (half ? a.lds_off[1] : 0);
-    const int pout = pb + (half ? a.lds_off[4] : 0);
-    float2* lds2 = reinterpret_cast<float2*>(lds);
-#define SV_DECL(u) float4 buf##u;
-    SV_REP8(SV_DECL)
-#undef SV_DECL
-    uint64_t base = tile_base(t0, a);
-#define SV_LOAD(u) buf##u = gload(reinterpret_cast<const float4*>(psi + base + roff[u] + poff[u]));
-    SV_REP8(SV_LOAD)
-#undef SV_LOAD
-    for (uint64_t t = t0; t < t1; ++t) {
-#define SV_STAGE(u)                                                                        \
-    {                                                                                      \
-        const int i = (u * NT + tid) * 2;                                        \
-        *reinterpret_cast<float4*>(lds2 + pair_slot(i)) = swap_pair(buf##u, pair_swapped(i)); \
-    }
-        SV_REP8(SV_STAGE)
-#undef SV_STAGE
-        __syncthreads();
-        uint64_t nbase = 0;
-        if (t + 1 < t1) {
-            nbase = tile_base(t + 1, a);
-#define SV_PREFETCH(u) buf##u = gload(reinterpret_cast<const float4*>(psi + nbase + roff[u] + poff[u]));
-            SV_REP8(SV_PREFETCH)
-#undef SV_PREFETCH
-        }
-        float2 x[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) x[j] = lds2[lds_swz(pin + a.lds_off[2 * j])];
-        f32x16 p1 = {0}, p2 = {0}, p3 = {0};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float4 vr = amat[(0 * 64 + lane) * 4 + q];
-            const float4 vi = amat[(1 * 64 + lane) * 4 + q];
-            const float4 vs = amat[(2 * 64 + lane) * 4 + q];
-            const float ar[4] = {vr.x, vr.y, vr.z, vr.w};
-            const float ai[4] = {vi.x, vi.y, vi.z, vi.w};
-            const float as[4] = {vs.x, vs.y, vs.z, vs.w};
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const float2 xv = x[4 * q + jj];
-                p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[jj], xv.x, p1, 0, 0, 0);
-                p2 = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[jj], xv.y, p2, 0, 0, 0);
-                p3 = __builtin_amdgcn_mfma_f32_32x32x2f32(as[jj], xv.x + xv.y, p3, 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-            lds2[lds_swz(pout + a.lds_off[8 * (r / 4) + (r % 4)])] = float2{p1[r] - p2[r], p3[r] - p1[r] - p2[r]};
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kTileVecs; ++u) {
-            const int i = (u * NT + tid) * 2;
-            gstore(reinterpret_cast<float4*>(psi + base + roff[u] + poff[u]),
-                   swap_pair(*reinterpret_cast<const float4*>(lds2 + pair_slot(i)), pair_swapped(i)));
-        }
-        base = nbase;
-        __syncthreads();
-    }
+    tile_c64_k5_sweep<NT, false>(psi, mats, a, blockIdx.x, lds, amat, ZSums{nullptr, -1, nullptr, nullptr});
 }
 
 __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict__ psi,
@@ -888,6 +689,8 @@ void launch_mfma_c64(sv_handle_s* h, float2* psi, const float4* mats, const Gate
 // lo_pos lists the targets' positions inside the tile (bits < L as is, H's
 // bits at L + their rank in H).  strided: workgroups take their tiles
 // n_tiles / tiles_per_wg apart (tile_base) instead of consecutively.
+}  // namespace
+
 TileArgs make_tile_args(const GateDesc& d, int n, int tb, int cu_count, int spread_lo, bool strided)
 {
     int tq[SV_MAX_TARGETS];
@@ -962,6 +765,8 @@ TileArgs make_tile_args(const GateDesc& d, int n, int tb, int cu_count, int spre
         while ((uint64_t(1) << t.trot) < per) ++t.trot;
     return t;
 }
+
+namespace {
 
 // ------------------------------------------------- tile shape autotuning
 

@@ -23,13 +23,29 @@ namespace sv {
 sv_fused_s* fuse_gate_list(const int32_t* codes, const int32_t* qubits, const double* params, int n_gates,
                            int kmax, int kdiag);
 
+// One level of the level path: its workgroup entries and the circuits whose
+// expectations follow it.
+struct BatchLevel {
+    uint64_t entry0 = 0;
+    uint32_t n_entries = 0;
+    uint64_t finish0 = 0;
+    uint32_t n_finish = 0;
+};
+
 struct BatchHost {
     std::vector<BatchCircuit> circuits;
-    std::vector<uint32_t> order;
+    std::vector<uint32_t> order;  // the persistent kernel's queue
     std::vector<BatchBlock> blocks;
     std::vector<float> mats;
     std::vector<uint64_t> z_masks;
     uint64_t state_amps = 0;
+    // level path
+    std::vector<BatchTileDesc> tdescs;
+    std::vector<float4> tmats;
+    std::vector<BatchLevelEntry> entries;
+    std::vector<BatchFinish> finish;
+    std::vector<BatchLevel> levels;
+    uint64_t n_partials = 0;
 };
 
 }  // namespace sv
@@ -42,6 +58,8 @@ struct sv_batch_s {
     std::vector<uint64_t> state_off;  // amplitudes
     uint64_t state_amps = 0;
     std::map<int, int> kmax_for_n;
+    int level_qubits = SV_BATCH_LEVEL_DEFAULT;  // circuits of >= this many qubits take the level path
+    std::vector<sv::BatchLevel> levels;
     std::vector<int> blocks_per_circuit;
     char* dev = nullptr;  // one arena for all device-side descriptors
     size_t dev_bytes = 0;
@@ -198,9 +216,87 @@ void free_fused(sv_fused_s* f)
 }
 
 // Builds the device-side descriptors for circuits `sel` with widths kmax.
+// Block b (k targets tq, 2^k x 2^k complex128 m) as a five-qubit gate: the
+// targets, then free qubits below the lowest target and above the highest as
+// the high matrix bits, the matrix M (x) I (32 x 32 complex128).
+void pad_block_to_five(int n, int k, const int* tq, const double* m, int32_t* out_t, std::vector<double>& out_m)
+{
+    uint64_t used = 0;
+    int lo = n, hi = -1;
+    for (int a = 0; a < k; ++a) {
+        out_t[a] = tq[a];
+        used |= uint64_t(1) << tq[a];
+        lo = std::min(lo, tq[a]);
+        hi = std::max(hi, tq[a]);
+    }
+    int kk = k;
+    for (int q = lo - 1; q >= 0 && kk < 5; --q)
+        if (!((used >> q) & 1)) out_t[kk++] = q;
+    for (int q = hi + 1; q < n && kk < 5; ++q)
+        if (!((used >> q) & 1)) out_t[kk++] = q;
+    if (kk < 5) throw Error{SV_ERR_INTERNAL, "level path: no free qubits to pad a block"};
+    const int d = 1 << k, D = 32;
+    out_m.assign(size_t(2) * D * D, 0.0);
+    for (int e = 0; e < D / d; ++e)
+        for (int r = 0; r < d; ++r)
+            for (int c = 0; c < d; ++c) {
+                const size_t dst = size_t(e * d + r) * D + size_t(e * d + c);
+                out_m[2 * dst] = m[2 * (size_t(r) * d + c)];
+                out_m[2 * dst + 1] = m[2 * (size_t(r) * d + c) + 1];
+            }
+}
+
+constexpr uint64_t kLevelTilesPerWg = 4;
+
+// Level-path descriptors of circuit j (state at c.state_off, fused blocks f):
+// one tile-sweep descriptor and packed matrix per block.  Returns the index
+// of its first descriptor.
+uint32_t add_level_circuit(BatchHost& H, const BatchCircuit& c, const sv_fused_s* f, int cu_count)
+{
+    const uint32_t first = uint32_t(H.tdescs.size());
+    const size_t mat_bytes = packed_matrix_bytes(SV_C64, c.n, 5, 0);
+    std::vector<double> pm;
+    for (int bi = 0; bi < f->n_blocks; ++bi) {
+        const FusedBlock& fb = f->blocks[bi];
+        int32_t t5[5];
+        const double* m5 = fb.m;
+        if (fb.k < 5) {
+            pad_block_to_five(c.n, fb.k, fb.targets, fb.m, t5, pm);
+            m5 = pm.data();
+        } else {
+            for (int a = 0; a < 5; ++a) t5[a] = fb.targets[a];
+        }
+        GateDesc d{};
+        d.n = c.n;
+        d.k = 5;
+        for (int a = 0; a < 5; ++a) d.tbit[a] = uint64_t(1) << t5[a];
+        BatchTileDesc td{};
+        // the single-state sweep's default variant: spread layout, strided order
+        td.t = make_tile_args(d, c.n, 12, cu_count, 12, false);
+        td.t.tiles_per_wg = std::min<uint64_t>(kLevelTilesPerWg, td.t.n_tiles);
+        td.t.trot = 0;
+        while ((uint64_t(1) << td.t.trot) < td.t.tiles_per_wg) ++td.t.trot;
+        td.state_off = c.state_off;
+        td.term0 = c.term0;
+        td.n_terms = -1;
+        td.red_off = 0;
+        if (bi + 1 == f->n_blocks) {
+            td.n_terms = int32_t(c.n_terms);
+            td.red_off = H.n_partials;
+            const uint64_t n_wg = (td.t.n_tiles + td.t.tiles_per_wg - 1) / td.t.tiles_per_wg;
+            H.n_partials += n_wg * (c.n_terms + 1);
+        }
+        td.mat_off = H.tmats.size();
+        H.tmats.resize(H.tmats.size() + mat_bytes / sizeof(float4));
+        pack_matrix(SV_C64, c.n, 5, 0, m5, 0, H.tmats.data() + td.mat_off);
+        H.tdescs.push_back(td);
+    }
+    return first;
+}
+
 BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>& sel,
                      const std::vector<int>& kmax, const std::vector<int>& term0, const std::vector<int>& nterms,
-                     const uint64_t* z_masks, std::vector<int>* blocks_out)
+                     const uint64_t* z_masks, std::vector<int>* blocks_out, int level_qubits, int cu_count)
 {
     std::vector<CircuitInput> sub;
     std::vector<int> ks;
@@ -211,6 +307,7 @@ BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>
     auto fused = fuse_all(sub, ks);
     BatchHost H;
     H.circuits.resize(sel.size());
+    std::vector<uint32_t> level_circuits, level_first;
     uint64_t off = 0;
     for (size_t j = 0; j < sel.size(); ++j) {
         const int i = sel[j];
@@ -223,6 +320,12 @@ BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>
         for (int t = 0; t < nterms[i]; ++t) H.z_masks.push_back(z_masks[term0[i] + t]);
         c.state_off = off;
         off += std::max<uint64_t>(uint64_t(1) << c.n, 32);  // 256-byte aligned starts
+        if (c.n >= level_qubits && fused[j]->n_blocks > 0) {
+            level_circuits.push_back(uint32_t(j));
+            level_first.push_back(add_level_circuit(H, c, fused[j], cu_count));
+            if (blocks_out) (*blocks_out)[i] = fused[j]->n_blocks;
+            continue;
+        }
         for (int bidx = 0; bidx < fused[j]->n_blocks; ++bidx) {
             const FusedBlock& fb = fused[j]->blocks[bidx];
             BatchBlock b{};
@@ -241,8 +344,8 @@ BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>
     // largest first, so the long circuits start early and none starts late.
     // A circuit's work is its state size times its sweeps.
     constexpr double kShortShare = 0.05;
-    H.order.resize(sel.size());
-    std::iota(H.order.begin(), H.order.end(), 0u);
+    for (uint32_t j = 0; j < uint32_t(sel.size()); ++j)
+        if (std::find(level_circuits.begin(), level_circuits.end(), j) == level_circuits.end()) H.order.push_back(j);
     auto work = [&](uint32_t c) { return double(uint64_t(1) << H.circuits[c].n) * (H.circuits[c].n_blocks + 1); };
     std::stable_sort(H.order.begin(), H.order.end(), [&](uint32_t a, uint32_t b) { return work(a) < work(b); });
     double total = 0.0;
@@ -253,6 +356,33 @@ BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>
         if (cum > kShortShare * total) break;
     }
     std::reverse(H.order.begin() + std::ptrdiff_t(n_short), H.order.end());
+    // Level path: launch l sweeps block l of every circuit that has one, the
+    // circuits with the most blocks first; after it, the circuits whose last
+    // block it was are reduced.
+    std::vector<size_t> lorder(level_circuits.size());
+    std::iota(lorder.begin(), lorder.end(), size_t(0));
+    std::stable_sort(lorder.begin(), lorder.end(), [&](size_t a, size_t b) {
+        return H.circuits[level_circuits[a]].n_blocks > H.circuits[level_circuits[b]].n_blocks;
+    });
+    uint32_t depth = 0;
+    for (uint32_t j : level_circuits) depth = std::max(depth, H.circuits[j].n_blocks);
+    for (uint32_t l = 0; l < depth; ++l) {
+        BatchLevel L;
+        L.entry0 = H.entries.size();
+        L.finish0 = H.finish.size();
+        for (size_t q : lorder) {
+            const BatchCircuit& c = H.circuits[level_circuits[q]];
+            if (c.n_blocks <= l) continue;
+            const uint32_t di = level_first[q] + l;
+            const TileArgs& t = H.tdescs[di].t;
+            const uint64_t n_wg = (t.n_tiles + t.tiles_per_wg - 1) / t.tiles_per_wg;
+            for (uint64_t w = 0; w < n_wg; ++w) H.entries.push_back({di, uint32_t(w)});
+            if (c.n_blocks == l + 1) H.finish.push_back({level_circuits[q], uint32_t(n_wg), H.tdescs[di].red_off});
+        }
+        L.n_entries = uint32_t(H.entries.size() - L.entry0);
+        L.n_finish = uint32_t(H.finish.size() - L.finish0);
+        H.levels.push_back(L);
+    }
     return H;
 }
 
@@ -265,39 +395,62 @@ size_t align_up(size_t v)
 // Uploads H into one device arena and fills args (states excluded).
 char* upload(const BatchHost& H, BatchArgs& a, hipStream_t stream, size_t* dev_bytes)
 {
-    const size_t s_c = align_up<int>(H.circuits.size() * sizeof(BatchCircuit));
-    const size_t s_o = align_up<int>(H.order.size() * sizeof(uint32_t));
-    const size_t s_b = align_up<int>(std::max<size_t>(1, H.blocks.size()) * sizeof(BatchBlock));
-    const size_t s_m = align_up<int>(std::max<size_t>(1, H.mats.size()) * sizeof(float));
-    const size_t s_z = align_up<int>(std::max<size_t>(1, H.z_masks.size()) * sizeof(uint64_t));
-    const size_t s_e = align_up<int>(std::max<size_t>(1, H.z_masks.size()) * sizeof(double));
-    const size_t s_t = align_up<int>(H.circuits.size() * sizeof(uint64_t));
-    const size_t total = s_c + s_o + s_b + s_m + s_z + s_e + s_t + 256 + 256;
+    struct Part {
+        const void* src;
+        size_t bytes;
+        size_t room;
+    };
+    auto part = [](const void* src, size_t bytes) { return Part{src, bytes, align_up<int>(std::max<size_t>(bytes, 1))}; };
+    const size_t n_terms = std::max<size_t>(1, H.z_masks.size());
+    Part parts[] = {
+        part(H.circuits.data(), H.circuits.size() * sizeof(BatchCircuit)),
+        part(H.order.data(), H.order.size() * sizeof(uint32_t)),
+        part(H.blocks.data(), H.blocks.size() * sizeof(BatchBlock)),
+        part(H.mats.data(), H.mats.size() * sizeof(float)),
+        part(H.z_masks.data(), H.z_masks.size() * sizeof(uint64_t)),
+        part(nullptr, n_terms * sizeof(double)),                   // expectations
+        part(nullptr, H.circuits.size() * sizeof(uint64_t)),       // completion times
+        part(nullptr, 256),                                        // run start
+        part(nullptr, 256),                                        // queue
+        part(H.tdescs.data(), H.tdescs.size() * sizeof(BatchTileDesc)),
+        part(H.tmats.data(), H.tmats.size() * sizeof(float4)),
+        part(H.entries.data(), H.entries.size() * sizeof(BatchLevelEntry)),
+        part(H.finish.data(), H.finish.size() * sizeof(BatchFinish)),
+        part(nullptr, H.n_partials * sizeof(double)),             // last levels' sums
+    };
+    size_t total = 0;
+    for (const Part& q : parts) total += q.room;
     char* dev = static_cast<char*>(dev_alloc(total, "batch descriptors"));
     if (dev_bytes) *dev_bytes = total;
+    char* where[sizeof(parts) / sizeof(parts[0])];
     char* p = dev;
-    auto put = [&](const void* src, size_t bytes, size_t room) {
-        char* d = p;
-        if (bytes) {
-            const hipError_t e = hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, stream);
+    for (size_t i = 0; i < sizeof(parts) / sizeof(parts[0]); ++i) {
+        where[i] = p;
+        if (parts[i].src && parts[i].bytes) {
+            const hipError_t e = hipMemcpyAsync(p, parts[i].src, parts[i].bytes, hipMemcpyHostToDevice, stream);
             if (e != hipSuccess) {
+                (void)hipStreamSynchronize(stream);
                 dev_free(dev, total);
                 throw Error{SV_ERR_DEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e)};
             }
         }
-        p += room;
-        return d;
-    };
-    a.circuits = reinterpret_cast<const BatchCircuit*>(put(H.circuits.data(), H.circuits.size() * sizeof(BatchCircuit), s_c));
-    a.order = reinterpret_cast<const uint32_t*>(put(H.order.data(), H.order.size() * sizeof(uint32_t), s_o));
-    a.blocks = reinterpret_cast<const BatchBlock*>(put(H.blocks.data(), H.blocks.size() * sizeof(BatchBlock), s_b));
-    a.mats = reinterpret_cast<const float*>(put(H.mats.data(), H.mats.size() * sizeof(float), s_m));
-    a.z_masks = reinterpret_cast<const uint64_t*>(put(H.z_masks.data(), H.z_masks.size() * sizeof(uint64_t), s_z));
-    a.expect = reinterpret_cast<double*>(put(nullptr, 0, s_e));
-    a.t_done = reinterpret_cast<uint64_t*>(put(nullptr, 0, s_t));
-    a.t_start = reinterpret_cast<uint64_t*>(put(nullptr, 0, 256));
-    a.queue = reinterpret_cast<uint32_t*>(put(nullptr, 0, 256));
-    a.n_circuits = uint32_t(H.circuits.size());
+        p += parts[i].room;
+    }
+    a.circuits = reinterpret_cast<const BatchCircuit*>(where[0]);
+    a.order = reinterpret_cast<const uint32_t*>(where[1]);
+    a.blocks = reinterpret_cast<const BatchBlock*>(where[2]);
+    a.mats = reinterpret_cast<const float*>(where[3]);
+    a.z_masks = reinterpret_cast<const uint64_t*>(where[4]);
+    a.expect = reinterpret_cast<double*>(where[5]);
+    a.t_done = reinterpret_cast<uint64_t*>(where[6]);
+    a.t_start = reinterpret_cast<uint64_t*>(where[7]);
+    a.queue = reinterpret_cast<uint32_t*>(where[8]);
+    a.tdescs = reinterpret_cast<const BatchTileDesc*>(where[9]);
+    a.tmats = reinterpret_cast<const float4*>(where[10]);
+    a.entries = reinterpret_cast<const BatchLevelEntry*>(where[11]);
+    a.finish = reinterpret_cast<const BatchFinish*>(where[12]);
+    a.partials = reinterpret_cast<double*>(where[13]);
+    a.n_queue = uint32_t(H.order.size());
     const hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         dev_free(dev, total);
@@ -334,7 +487,7 @@ int tune_width(sv_handle_s* h, const std::vector<CircuitInput>& in, const std::v
     SV_HIP(hipEventCreate(&e1));
     for (int k = 3; k <= std::min(5, n); ++k) {
         std::vector<int> km(in.size(), k);
-        BatchHost H = build_host(in, sample, km, term0, nterms, z_masks, nullptr);
+        BatchHost H = build_host(in, sample, km, term0, nterms, z_masks, nullptr, kBatchMaxQubits + 1, h->cu_count);
         BatchArgs a{};
         size_t dev_bytes = 0;
         char* dev = upload(H, a, h->stream, &dev_bytes);
@@ -428,17 +581,23 @@ sv_batch_s* batch_create(sv_handle_s* h, int n_circuits, const int32_t* n_qubits
         b->n_circuits = n_circuits;
         b->total_terms = total_terms;
         b->n.assign(n_qubits, n_qubits + n_circuits);
+        b->level_qubits = h->batch_level_qubits;
         std::vector<int> kmax(n_circuits);
         for (auto& kv : by_n) {
-            const int k = max_fused_qubits > 0 ? std::min(max_fused_qubits, kv.first)
-                                               : tune_width(h, in, kv.second, kv.first, term0, nterms, z_masks);
+            // the level path sweeps every block as a five-qubit gate, so it
+            // fuses at the widest width
+            const int k = kv.first >= b->level_qubits ? std::min(kBatchMaxK, kv.first)
+                          : max_fused_qubits > 0     ? std::min(max_fused_qubits, kv.first)
+                                                     : tune_width(h, in, kv.second, kv.first, term0, nterms, z_masks);
             b->kmax_for_n[kv.first] = k;
             for (int i : kv.second) kmax[i] = k;
         }
         std::vector<int> all(n_circuits);
         std::iota(all.begin(), all.end(), 0);
         b->blocks_per_circuit.assign(n_circuits, 0);
-        BatchHost H = build_host(in, all, kmax, term0, nterms, z_masks, &b->blocks_per_circuit);
+        BatchHost H = build_host(in, all, kmax, term0, nterms, z_masks, &b->blocks_per_circuit, b->level_qubits,
+                                 h->cu_count);
+        b->levels = H.levels;
         b->state_off.resize(n_circuits);
         for (int i = 0; i < n_circuits; ++i) b->state_off[i] = H.circuits[i].state_off;
         b->state_amps = H.state_amps;
@@ -462,9 +621,11 @@ static void drop_graph(sv_batch_s* b)
     b->graph_states = nullptr;
 }
 
-// Records the queue reset and the persistent kernel for b->args.states on a
-// private stream (the handle's may be the null stream, which cannot be
-// captured).  Kernel nodes only.
+// Records the run for b->args.states on a private stream (the handle's may
+// be the null stream, which cannot be captured): the queue reset, the
+// persistent kernel (if any circuit takes it), then every level of the
+// level path, each followed by the expectations of the circuits it
+// finishes.  Kernel nodes only.
 static void record_run(sv_batch_s* b)
 {
     sv_handle_s* h = b->h;
@@ -476,7 +637,12 @@ static void record_run(sv_batch_s* b)
         SV_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
         try {
             launch_batch_reset(cap, b->args);
-            launch_batch(cap, h->cu_count, b->args);
+            if (b->args.n_queue > 0) launch_batch(cap, h->cu_count, b->args);
+            for (size_t l = 0; l < b->levels.size(); ++l) {
+                const BatchLevel& L = b->levels[l];
+                launch_batch_level(cap, b->args, L.entry0, L.n_entries, l == 0);
+                if (L.n_finish > 0) launch_batch_finish(cap, b->args, L.finish0, L.n_finish);
+            }
         } catch (...) {
             hipGraph_t dropped = nullptr;
             (void)hipStreamEndCapture(cap, &dropped);

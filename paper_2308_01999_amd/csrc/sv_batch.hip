@@ -1,11 +1,17 @@
-// Batched execution of many independent small circuits in one persistent
-// launch (complex64).  Each workgroup takes circuits from a device queue
-// (in the order the host chose) and runs a circuit's whole fused program,
-// then its Z-type Pauli expectations:
+// Batched execution of many independent circuits (complex64) in one
+// recorded run.  Circuits below the level path's qubit count go to one
+// persistent launch: each workgroup takes circuits from a device queue (in
+// the order the host chose) and runs a circuit's whole fused program, then
+// its Z-type Pauli expectations:
 //   - states of <= 12 qubits stay in LDS from |0..0> to the end, and are
 //     written to HBM once;
 //   - larger states are swept block by block through 4096-amplitude tiles
 //     staged in LDS, the same tiling as the single-state sweep.
+// Larger circuits run on the level path: launch l applies block l of every
+// such circuit that has one, each block through the single-state
+// five-qubit tile sweep (many workgroups per state, so the streamed states
+// move at the single-state sweep's rate), and a circuit's expectations are
+// taken on a side stream right after its last level.
 // k = 4, 5 blocks run as three real GEMMs on the matrix cores (Gauss's
 // product), k <= 3 on the vector ALUs.  The workgroup records its
 // circuit's completion on the device wall clock.  Every workgroup exits
@@ -307,7 +313,6 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A)
     float2* states = static_cast<float2*>(A.states);
     const int tid = threadIdx.x;
     if (tid == 0) {
-        atomicMin(reinterpret_cast<unsigned long long*>(A.t_start), static_cast<unsigned long long>(wall_clock64()));
         next = atomicAdd(A.queue, 1u);
     }
     __syncthreads();
@@ -317,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A)
     // let the compiler give thread 0 a loop of its own around the barriers)
     uint32_t slot = __builtin_amdgcn_readfirstlane(next);
     __syncthreads();
-    while (slot < A.n_circuits) {
+    while (slot < A.n_queue) {
         const uint32_t ci = A.order[slot];
         const BatchCircuit c = A.circuits[ci];
         float2* psi = states + c.state_off;
@@ -419,7 +424,46 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs A)
 __global__ void k_batch_reset(uint32_t* queue, uint64_t* t_start)
 {
     *queue = 0;
-    *t_start = ~uint64_t(0);
+    *t_start = wall_clock64();
+}
+
+// Level path: workgroup w sweeps its tiles of one block of one circuit; on a
+// circuit's last block it also leaves the Z-type sums of its tiles.
+template <bool FIRST>
+__global__ __launch_bounds__(tile::kTileThreads, 3) void k_batch_level(float2* __restrict__ states,
+                                                                    const BatchTileDesc* __restrict__ descs,
+                                                                    const BatchLevelEntry* __restrict__ entries,
+                                                                    const float4* __restrict__ mats,
+                                                                    const uint64_t* __restrict__ z_masks,
+                                                                    double* __restrict__ partials)
+{
+    __shared__ float4 lds[tile::kTileThreads * tile::kTileVecs];
+    __shared__ float4 amat[tile::kK5AParts * 64 * 4];
+    __shared__ double zacc[(tile::kTileThreads / 64) * (tile::kZSumsMax + 1)];
+    const BatchLevelEntry e = entries[blockIdx.x];
+    const BatchTileDesc& d = descs[e.desc];
+    const tile::ZSums zs{z_masks + d.term0, d.n_terms,
+                         partials + d.red_off + uint64_t(e.wg) * uint64_t(d.n_terms + 1), zacc};
+    tile::tile_c64_k5_sweep<tile::kTileThreads, FIRST>(states + d.state_off, mats + d.mat_off, d.t, e.wg, lds,
+                                                       amat, zs);
+}
+
+// Level path: a finished circuit's expectations from its workgroups' sums
+// (in workgroup order), then its completion time.
+__global__ __launch_bounds__(kThreads) void k_batch_finish(BatchArgs A, const BatchFinish* __restrict__ fin)
+{
+    __shared__ double nrm;
+    const BatchFinish f = fin[blockIdx.x];
+    const BatchCircuit c = A.circuits[f.circuit];
+    const int nt = int(c.n_terms);
+    double v = 0.0;
+    if (int(threadIdx.x) <= nt)
+        for (uint32_t w = 0; w < f.n_wg; ++w) v = __dadd_rn(v, A.partials[f.red_off + uint64_t(w) * (nt + 1) + threadIdx.x]);
+    if (int(threadIdx.x) == nt) nrm = v;
+    __syncthreads();
+    if (int(threadIdx.x) < nt) A.expect[c.term0 + threadIdx.x] = v / nrm;
+    __syncthreads();
+    if (threadIdx.x == 0) A.t_done[f.circuit] = wall_clock64();
 }
 
 }  // namespace
@@ -427,6 +471,24 @@ __global__ void k_batch_reset(uint32_t* queue, uint64_t* t_start)
 void launch_batch_reset(hipStream_t stream, const BatchArgs& a)
 {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, stream, a.queue, a.t_start);
+    SV_HIP(hipGetLastError());
+}
+
+void launch_batch_level(hipStream_t stream, const BatchArgs& a, uint64_t first, uint32_t n_entries, bool first_level)
+{
+    float2* states = static_cast<float2*>(a.states);
+    if (first_level)
+        hipLaunchKernelGGL(k_batch_level<true>, dim3(n_entries), dim3(tile::kTileThreads), 0, stream, states, a.tdescs,
+                           a.entries + first, a.tmats, a.z_masks, a.partials);
+    else
+        hipLaunchKernelGGL(k_batch_level<false>, dim3(n_entries), dim3(tile::kTileThreads), 0, stream, states,
+                           a.tdescs, a.entries + first, a.tmats, a.z_masks, a.partials);
+    SV_HIP(hipGetLastError());
+}
+
+void launch_batch_finish(hipStream_t stream, const BatchArgs& a, uint64_t first, uint32_t n)
+{
+    hipLaunchKernelGGL(k_batch_finish, dim3(n), dim3(kThreads), 0, stream, a, a.finish + first);
     SV_HIP(hipGetLastError());
 }
 

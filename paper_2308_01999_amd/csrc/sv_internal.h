@@ -106,6 +106,7 @@ struct sv_handle_s {
     char* aux = nullptr;            // device scratch that grows with the state (sampler prefixes)
     size_t aux_bytes = 0;
     int tile_mode = 0;              // sv_tile_mode_t
+    int batch_level_qubits = SV_BATCH_LEVEL_DEFAULT;  // batches: circuits of >= this many qubits take the level path
     sv::TileTuner* tuner = nullptr;
 };
 
