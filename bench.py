@@ -99,8 +99,13 @@ def parse():
     ap.add_argument("--baseline-sample", type=int, default=48,
                     help="circuits of the batch run through the plain complex128 per-circuit path")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-small-slots", type=int, default=2,
+                    help="extra serving slots for requests of up to 16 qubits")
+    ap.add_argument("--serving-sweep", action="store_true",
+                    help="also serve at 0.25/0.5/0.75/0.9 of capacity and compare capacity with 1 slot")
+    ap.add_argument("--sweep-requests", type=int, default=500)
     ap.add_argument("--no-kmax-sweep", action="store_true",
                     help="skip the unfused / kmax 4, 5, 6 comparison on the same circuit")
     ap.add_argument("--gate-sweep", action="store_true",
@@ -292,10 +297,29 @@ def graph_leg(P, W, torch, H, n=14, depth=20, reps=200):
     return out
 
 
-def cpu_baseline(W, P, gates, n, kmax, seconds):
-    """The oracle (as it stands) applying the same fused blocks to a 2^n
-    complex128 state on the host, until about `seconds` of work is done."""
-    import numpy as np
+def host_facts():
+    """nproc, CPU model and RAM of the host the oracle runs on."""
+    model, ram = "", 0.0
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    ram = int(line.split()[1]) * 1024 / 1e9
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model, "ram_GB": round(ram, 1)}
+
+
+def oracle_blocks_rate(P, gates, n, kmax, seconds):
+    """The oracle applying the fused blocks of `gates` to a 2^n complex128
+    state in host memory until about `seconds` of work: (GB/s counting
+    2 * 2^n * 16 B per block, blocks done, blocks, seconds)."""
     import oracle
     f = P.fuse(gates, kmax)
     blocks = f.blocks()
@@ -309,13 +333,85 @@ def cpu_baseline(W, P, gates, n, kmax, seconds):
         if time.perf_counter() - t0 >= seconds:
             break
     el = time.perf_counter() - t0
-    bytes_ = done * 2 * (1 << n) * 16
-    threads = oracle.threads()
     del psi
-    return {"value": round(bytes_ / el / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {done} of {len(blocks)} fused blocks (k<={kmax}) of the {n}-qubit brickwork "
-                      f"depth-20 circuit applied by the complex128 oracle to a 2^{n} state in host memory; "
-                      f"{el:.1f} s; bytes counted as 2*2^{n}*16 per block"}
+    return done * 2 * (1 << n) * 16 / el / 1e9, done, len(blocks), el
+
+
+def cpu_baseline(W, P, gates, n, depth, kmax, seconds, per_circuit):
+    """The oracle (as it stands) applying the same fused blocks to a 2^n
+    complex128 state on the host, on all of its threads until about
+    `seconds` of work is done; then on one thread, on the same circuit at
+    n - 4 qubits (a 30-qubit block takes minutes on one core).  Also the
+    oracle's whole-circuit times measured by the error legs."""
+    import oracle
+    threads = oracle.threads()
+    gbs, done, nb, el = oracle_blocks_rate(P, gates, n, kmax, seconds)
+    n1 = n - 4
+    oracle.set_threads(1)
+    try:
+        gbs1, done1, nb1, el1 = oracle_blocks_rate(P, W.brickwork(n1, depth, 0), n1, kmax, seconds / 2)
+    finally:
+        oracle.set_threads(threads)
+    return {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {done} of {nb} fused blocks (k<={kmax}) of the {n}-qubit brickwork "
+                      f"depth-{depth} circuit applied by the complex128 oracle to a 2^{n} state in host memory; "
+                      f"{el:.1f} s; bytes counted as 2*2^{n}*16 per block",
+            "one_core": {"value": round(gbs1, 3), "unit": "GB/s", "cores": 1,
+                         "sample": f"first {done1} of {nb1} fused blocks of the {n1}-qubit brickwork depth-{depth} "
+                                   f"circuit on one thread; {el1:.1f} s"},
+            "host": host_facts(),
+            "per_circuit_s": per_circuit}
+
+
+def config1_errors(P, W, H):
+    """The 12-qubit brickwork circuit (depth 20, seed 0) unfused and fused to
+    <= 5-qubit blocks, complex128 and complex64, against the oracle: the
+    largest amplitude difference, the state fidelity and the largest <Z_i>
+    difference; and the oracle's time for the whole circuit."""
+    import numpy as np
+    import oracle
+    n, depth = 12, 20
+    gates = W.brickwork(n, depth, 0)
+    t0 = time.perf_counter()
+    ref = oracle.run(n, gates)
+    zref = np.array([oracle.expect_pauli(ref, t) for t in W.z_terms(n)])
+    t_oracle = time.perf_counter() - t0
+    out = {"workload": f"{n}-qubit brickwork, depth {depth}, seed 0", "oracle_s": round(t_oracle, 4)}
+    for dt in ("c128", "c64"):
+        for kmax in (0, 5):
+            st = P.State(H, n, dt)
+            st.run(gates, max_fused_qubits=kmax or None)
+            got = st.to_numpy().astype(np.complex128)
+            z = P.sv_expect_pauli(st.s, W.z_terms(n))
+            st.close()
+            out[f"{dt}_{'fused5' if kmax else 'unfused'}"] = {
+                "max_abs_damp": float(np.max(np.abs(got - ref))),
+                "fidelity": oracle.fidelity(ref, got),
+                "max_abs_dz": float(np.max(np.abs(z - zref)))}
+    return out
+
+
+def config2_errors(P, W, torch, st, n, depth):
+    """The timed leg's final state against the oracle's values for the same
+    30-qubit circuit (tests/golden/config2_30q_d20_seed0.npz, written by the
+    oracle alone): the amplitudes at 65540 seeded indices (largest
+    difference; ||d psi||^2 estimated from them, whose complement bounds the
+    fidelity from below) and all <Z_i>."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "config2_30q_d20_seed0.npz")
+    if n != 30 or depth != 20 or not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        g = {k: z[k] for k in ("idx", "amp", "z", "norm")}
+    idx = torch.from_numpy(g["idx"].astype(np.int64)).to(st.tensor.device)
+    got = st.tensor[idx].cpu().numpy().astype(np.complex128)
+    d = got - g["amp"]
+    dpsi2 = float(np.sum(np.abs(d) ** 2)) * float(1 << n) / idx.numel()
+    e = P.sv_expect_pauli(st.s, W.z_terms(n))
+    return {"sampled_amplitudes": int(idx.numel()), "max_abs_damp": float(np.max(np.abs(d))),
+            "est_dpsi2": dpsi2, "est_fidelity_lower_bound": 1.0 - dpsi2,
+            "max_abs_dz": float(np.max(np.abs(e - g["z"]))),
+            "norm_diff": float(P.sv_norm(st.s) - float(g["norm"]))}
 
 
 def copy_ceiling(torch, n):
@@ -558,15 +654,18 @@ def large_leg(P, W, torch, H):
     return out
 
 
-def batched_leg(P, W, torch, H, count, steps, warmup, sample):
+def batched_leg(P, W, torch, H, count, steps, warmup, sample, check_per_n=4):
     """4096 independent complex64 brickwork circuits (qubits uniform in
     8..20, depth uniform in 10..40), each returning <Z_i Z_i+1> for all i, in
     one recorded run: circuits below 15 qubits on the persistent kernel with
     autotuned fusion widths, larger ones on the level path; per-circuit
-    latency from the device wall clock.  Baseline: a sample of the same circuits run
-    one at a time through the plain complex128 path (one sv_apply_matrix per
-    gate, then sv_expect_pauli), timed on the host."""
+    latency from the device wall clock.  Baseline: a sample of the same
+    circuits run one at a time through the plain complex128 path (one
+    sv_apply_matrix per gate, then sv_expect_pauli), timed on the host.
+    Errors: the first `check_per_n` circuits of every qubit count against
+    the oracle (state fidelity, <Z_i Z_i+1>)."""
     import numpy as np
+    import oracle
     items = W.batched(count, seed=0)
     ns = [it.n for it in items]
     circuits = [it.gates for it in items]
@@ -590,6 +689,19 @@ def batched_leg(P, W, torch, H, count, steps, warmup, sample):
     state_gb = sum((1 << n) * 8 for n in ns) / 1e9
     # every fused block reads and writes its state once
     sweep_bytes = sum(int(nb) * 2 * (1 << n) * 8 for nb, n in zip(blocks, ns))
+    # errors against the oracle on a sample spread over every qubit count
+    check = []
+    for n in sorted(set(ns)):
+        check += [i for i in range(count) if ns[i] == n][:check_per_n]
+    fids, dzz, t_or = [], [], {}
+    for i in check:
+        n = ns[i]
+        t1 = time.perf_counter()
+        ref = oracle.run(n, circuits[i])
+        zr = np.array([oracle.expect_pauli(ref, [(q, "Z"), (q + 1, "Z")]) for q in range(n - 1)])
+        t_or.setdefault(n, []).append(time.perf_counter() - t1)
+        fids.append(oracle.fidelity(ref, b.state(i).astype(np.complex128)))
+        dzz.append(float(np.max(np.abs(exps[i] - zr))))
     b.close()
     # baseline: plain complex128 per-circuit path on a sample
     rng = np.random.default_rng(1)
@@ -615,69 +727,156 @@ def batched_leg(P, W, torch, H, count, steps, warmup, sample):
         "wall_ms_per_batch": round(1e3 * wall, 3),
         "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
         "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+        "latency_clock": "device wall clock, from the run's start to each circuit's state and expectations written",
         "circuits_per_s": round(count / float(np.median(kts)), 1),
         "sweep_GB": round(sweep_bytes / 1e9, 2),
         "effective_GBps": round(sweep_bytes / float(np.median(kts)) / 1e9, 1),
         "fusion_widths": widths,
         "fused_blocks_total": int(blocks.sum()),
         "host_prep_s": round(prep, 3),
+        "vs_oracle": {"circuits": len(check), "qubits": f"{min(ns)}-{max(ns)}", "min_fidelity": min(fids),
+                      "max_abs_dzz": max(dzz)},
+        "oracle_s_per_circuit": {str(n): round(float(np.mean(v)), 4) for n, v in sorted(t_or.items())},
         "baseline_c128_per_circuit": {
             "sample": len(pick),
             "p50_ms": round(1e3 * float(np.percentile(base_lat, 50)), 3),
             "p99_ms": round(1e3 * float(np.percentile(base_lat, 99)), 3),
             "circuits_per_s": round(len(pick) / float(base_lat.sum()), 1),
-            "path": "one circuit at a time, unfused sv_apply_matrix per gate, then sv_expect_pauli; host wall time",
+            "latency_clock": "host wall clock of each circuit alone (no queueing)",
+            "path": "one circuit at a time, unfused sv_apply_matrix per gate, then sv_expect_pauli",
         },
     }
 
 
-def serving_leg(P, W, torch, n_requests, slots):
+def _serve_stats(res, reqs, span):
+    import numpy as np
+    lat = np.array([res[r.rid].latency for r in reqs])
+    svc = np.array([res[r.rid].done - res[r.rid].admitted for r in reqs])
+    return {"requests": len(reqs),
+            "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
+            "service_p50_ms": round(1e3 * float(np.percentile(svc, 50)), 2),
+            "circuits_per_s": round(len(reqs) / span, 2)}
+
+
+def serving_capacity(Server, replay, W, slots, small_slots, dtype="c64", kmax=5, count=32, seed=11):
+    """Requests per second a server sustains when a calibration set of the
+    stream's requests is submitted at once."""
+    srv = Server(slots=slots, small_slots=small_slots, budget_bytes=96 << 30, dtype=dtype, kmax=kmax)
+    cal = W.serving_requests(count, rate_per_s=1e9, seed=seed)
+    replay(srv, cal[: max(4, slots)], time_scale=0.0)  # warm the slots
+    t0 = time.monotonic()
+    replay(srv, cal, time_scale=0.0)
+    cap = len(cal) / (time.monotonic() - t0)
+    srv.close()
+    return cap
+
+
+def serving_leg(P, W, torch, n_requests, slots, small_slots, check=16):
     """Poisson stream of circuit requests (qubits log-uniform 10..28, depth
     10..100, random U3 + CZ/CNOT pairs; 16 random Pauli strings and 1024
     samples each) through the continuous-batching server (complex64 states,
-    FP64 reductions).  The offered load is 0.75 of the capacity measured by
-    submitting a calibration set at once.  Baseline: a complex128 FIFO that
-    serves one request at a time, on the first requests of the same stream."""
+    FP64 reductions; `slots` general slots plus `small_slots` for requests
+    of up to 16 qubits).  The offered load is 0.75 of the capacity measured
+    by submitting a calibration set at once.  Latency: host monotonic time
+    from a request's arrival to its results.  Baseline: a complex128 FIFO
+    that serves one request at a time, offered 0.75 of its own capacity.
+    Errors: the first `check` requests of up to 20 qubits against the oracle
+    (expectations; samples by the epsilon-interval rule with the served
+    state's probabilities, rebuilt by the same fused program)."""
     import numpy as np
+    import oracle
     from paper_2308_01999_amd.serve import Server, replay
-    cal = W.serving_requests(max(8, slots * 4), rate_per_s=1e9, seed=11)
-    srv = Server(slots=slots, budget_bytes=96 << 30, dtype="c64", kmax=5)
-    t0 = time.monotonic()
-    replay(srv, cal, time_scale=0.0)
-    capacity = len(cal) / (time.monotonic() - t0)
+    capacity = serving_capacity(Server, replay, W, slots, small_slots)
     rate = 0.75 * capacity
     reqs = W.serving_requests(n_requests, rate_per_s=rate, seed=0)
+    srv = Server(slots=slots, small_slots=small_slots, budget_bytes=96 << 30, dtype="c64", kmax=5)
     t0 = time.monotonic()
     res = replay(srv, reqs)
     span = time.monotonic() - t0
     srv.close()
-    lat = np.array([res[r.rid].latency for r in reqs])
+    main = _serve_stats(res, reqs, span)
+    # baseline: complex128, one request at a time, unfused, below its capacity
     base_n = min(16, n_requests)
+    bcap = serving_capacity(Server, replay, W, 1, 0, dtype="c128", kmax=0, count=8)
+    breqs = W.serving_requests(base_n, rate_per_s=0.75 * bcap, seed=0)
     bsrv = Server(slots=1, budget_bytes=96 << 30, dtype="c128", kmax=0)
     t0 = time.monotonic()
-    bres = replay(bsrv, reqs[:base_n])
+    bres = replay(bsrv, breqs)
     bspan = time.monotonic() - t0
     bsrv.close()
-    blat = np.array([bres[r.rid].latency for r in reqs[:base_n]])
+    # errors against the oracle
+    h = P.Handle()
+    dexp, eps_ok, t_or, checked = [], [], [], 0
+    for r in reqs:
+        if checked >= check:
+            break
+        if r.n > 20:
+            continue
+        checked += 1
+        t1 = time.perf_counter()
+        ref = oracle.run(r.n, r.gates)
+        er = np.array([oracle.expect_pauli(ref, t) for t in r.terms])
+        t_or.append(time.perf_counter() - t1)
+        dexp.append(float(np.max(np.abs(res[r.rid].expectations - er))))
+        st = P.State(h, r.n, "c64")
+        st.run(r.gates, max_fused_qubits=5)
+        p_g = np.abs(st.to_numpy().astype(np.complex128)) ** 2
+        same = np.array_equal(st.sample(np.asarray(r.uniforms)), res[r.rid].samples)
+        st.close()
+        u = np.asarray(r.uniforms)
+        _, cdf = oracle.sample(ref, u[:1], return_cdf=True)
+        eps = float(np.sum(np.abs(p_g - np.abs(ref) ** 2))) + 1e-12
+        got = res[r.rid].samples.astype(np.int64)
+        lo = np.where(got > 0, cdf[np.maximum(got - 1, 0)], 0.0)
+        x = u * cdf[-1]
+        eps_ok.append(bool(same and ((lo - eps <= x) & (x < cdf[got] + eps)).all()))
+    h.close()
     return {
         "workload": "Poisson requests: qubits log-uniform 10-28, depth 10-100, U3 + CZ/CNOT on random pairs, "
                     "16 Pauli strings + 1024 samples each; complex64, fused k<=5, FP64 reductions",
-        "requests": n_requests,
         "slots": slots,
+        "small_slots": small_slots,
         "capacity_req_per_s": round(capacity, 2),
         "offered_req_per_s": round(rate, 2),
-        "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
-        "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
-        "circuits_per_s": round(n_requests / span, 2),
+        **main,
+        "latency_clock": "host monotonic, arrival to results; service = admission to results",
         "qubits_mean": round(float(np.mean([r.n for r in reqs])), 2),
+        "vs_oracle": {"requests": checked, "max_qubits": 20, "max_abs_dexpect": max(dexp),
+                      "eps_rule_pass_rate": sum(eps_ok) / max(1, len(eps_ok))},
+        "oracle_s_per_request_mean": round(float(np.mean(t_or)), 4),
         "baseline_c128_fifo": {
-            "requests": base_n,
-            "p50_ms": round(1e3 * float(np.percentile(blat, 50)), 2),
-            "p99_ms": round(1e3 * float(np.percentile(blat, 99)), 2),
-            "circuits_per_s": round(base_n / bspan, 2),
-            "path": "same stream, one request at a time, complex128 states, one sv_apply_matrix sweep per gate",
+            "capacity_req_per_s": round(bcap, 2),
+            "offered_req_per_s": round(0.75 * bcap, 2),
+            **_serve_stats(bres, breqs, bspan),
+            "path": "one request at a time, complex128 states, one sv_apply_matrix sweep per gate",
         },
     }
+
+
+def serving_sweep(P, W, torch, n_requests, slots, small_slots):
+    """Serving at offered loads of 0.25, 0.5, 0.75 and 0.9 of the measured
+    capacity, and the capacity with one slot against `slots` (the same
+    complex64, kmax 5 stream): more slots only raise capacity if the slots'
+    work overlaps on the device."""
+    from paper_2308_01999_amd.serve import Server, replay
+    capacity = serving_capacity(Server, replay, W, slots, small_slots)
+    points = []
+    for frac in (0.25, 0.5, 0.75, 0.9):
+        reqs = W.serving_requests(n_requests, rate_per_s=frac * capacity, seed=0)
+        srv = Server(slots=slots, small_slots=small_slots, budget_bytes=96 << 30, dtype="c64", kmax=5)
+        t0 = time.monotonic()
+        res = replay(srv, reqs)
+        span = time.monotonic() - t0
+        srv.close()
+        points.append({"load": frac, "offered_req_per_s": round(frac * capacity, 2), **_serve_stats(res, reqs, span)})
+        print(f"[bench] serving sweep load {frac}: {points[-1]}", file=sys.stderr, flush=True)
+    caps = {}
+    for sl, sm in ((1, 0), (slots, 0), (slots, small_slots)):
+        caps[f"{sl}+{sm}"] = round(serving_capacity(Server, replay, W, sl, sm, count=48), 2)
+    return {"capacity_req_per_s": round(capacity, 2), "points": points,
+            "capacity_by_slots": caps,
+            "capacity_note": "general+small slots; calibration set of 48 requests submitted at once"}
 
 
 def main():
@@ -699,10 +898,13 @@ def main():
     H = P.Handle()
     print(f"[bench] c64 leg: n={n} depth={depth} kmax={kmax}", file=sys.stderr, flush=True)
     r64, st64 = run_leg(P, W, torch, H, gates, n, "c64", kmax, args.shots, args.steps, args.warmup)
+    # errors of the results against the oracle (outside every timed region)
+    errors = {"config2_c64": config2_errors(P, W, torch, st64, n, depth)}
     extra = {}
     if not args.no_c128:
         print("[bench] c128 leg", file=sys.stderr, flush=True)
         r128, st128 = run_leg(P, W, torch, H, gates, n, "c128", kmax, args.shots, args.steps, args.warmup)
+        errors["config2_c128"] = config2_errors(P, W, torch, st128, n, depth)
         # fidelity of the complex64 result against the complex128 GPU result,
         # streamed in chunks through host memory
         import numpy as np
@@ -759,6 +961,9 @@ def main():
                                  "unit": "GB/s", "frac": round(dk2["GBps"] / HBM_PEAK_GBS, 4),
                                  "traffic": pmc_traffic(k2, n), "kernel": k2,
                                  "bytes_per_launch": dk2["bytes_per_launch"], "avg_launch_ms": round(dk2["avg_ms"], 4)}
+    print("[bench] 12-qubit configuration against the oracle", file=sys.stderr, flush=True)
+    errors["config1"] = config1_errors(P, W, H)
+    line["oracle_errors"] = errors
     if not args.no_kmax_sweep:
         print("[bench] unfused / kmax sweep", file=sys.stderr, flush=True)
         # on the main handle, whose k = 5 tile choices for this circuit are settled
@@ -776,7 +981,11 @@ def main():
         H2.close()
     if not args.no_serving:
         print("[bench] serving leg", file=sys.stderr, flush=True)
-        line["serving"] = serving_leg(P, W, torch, args.serve_requests, args.serve_slots)
+        line["serving"] = serving_leg(P, W, torch, args.serve_requests, args.serve_slots, args.serve_small_slots)
+    if args.serving_sweep:
+        print("[bench] serving sweep", file=sys.stderr, flush=True)
+        line["serving_sweep"] = serving_sweep(P, W, torch, args.sweep_requests, args.serve_slots,
+                                              args.serve_small_slots)
     line["copy_ceiling_GBps"] = round(copy_ceiling(torch, n), 1)
     line["frac_of_copy_ceiling"] = round(r64["fused_gate_GBps"] / line["copy_ceiling_GBps"], 4)
     if not args.no_diagonal:
@@ -803,7 +1012,12 @@ def main():
         line["copy_calibration"] = calibrate_copy(torch)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(W, P, gates, n, kmax, args.cpu_seconds)
+        per_circuit = {"config1_12q_c128": errors["config1"]["oracle_s"]}
+        if "batched" in line:
+            per_circuit["batched_by_qubits"] = line["batched"]["oracle_s_per_circuit"]
+        if "serving" in line:
+            per_circuit["serving_mean_up_to_20q"] = line["serving"]["oracle_s_per_request_mean"]
+        line["cpu_baseline"] = cpu_baseline(W, P, gates, n, depth, kmax, args.cpu_seconds, per_circuit)
     print(json.dumps(line), flush=True)
 
 

@@ -74,6 +74,8 @@ def lib():
         L.orc_set_basis.restype = None
         L.orc_threads.argtypes = []
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -357,6 +359,11 @@ def sample(psi: np.ndarray, u, bit_ordering=None, return_cdf: bool = False):
 def threads() -> int:
     """OpenMP threads used by the oracle's parallel loops."""
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads for the oracle's parallel loops (n >= 1)."""
+    lib().orc_set_threads(int(n))
 
 
 def fidelity(a: np.ndarray, b: np.ndarray) -> float:

@@ -575,6 +575,16 @@ int orc_threads(void)
 #endif
 }
 
+/* Sets the number of OpenMP threads of the parallel loops (n >= 1). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* |0..0> or |x> */
 void orc_set_basis(double* psi_ri, int n, uint64_t x)
 {

@@ -4,9 +4,11 @@ Requests (a named-gate circuit on n qubits, Pauli strings to evaluate, and
 uniforms to sample with) arrive over time.  A dispatcher admits them in
 arrival order as soon as a slot is free and the request's state fits the
 HBM budget; later requests may pass a blocked head only a bounded number of
-times, so large requests do not starve.  Each slot is a worker thread with
-its own torch stream and libsv handle, so the work of admitted requests
-overlaps on the device.  A request's state stays resident in HBM from
+times, so large requests do not starve.  Some slots may be kept for small
+requests (a few qubits' worth of memory and milliseconds of work), which
+then never wait behind large states for a slot.  Each slot is a worker
+thread with its own torch stream and libsv handle, so the work of admitted
+requests overlaps on the device.  A request's state stays resident in HBM from
 admission until its results are read back, then its memory is returned to
 the budget and the next request is admitted.
 
@@ -94,74 +96,112 @@ class Result:
 
 class Admission:
     """Pure admission policy (no GPU): FIFO with bounded bypass under a
-    byte budget and a slot count.  Unit-tested on the CPU."""
+    byte budget and slot counts.  `slots` general slots take any request;
+    `small_slots` more take only requests marked small, so small requests
+    never wait behind large ones for a slot.  A request that cannot start
+    may be passed by later ones at most max_bypass times while it waits for
+    memory or for a general slot (a small request taking a small slot the
+    head could not use does not count).  Unit-tested on the CPU."""
 
-    def __init__(self, budget_bytes: int, slots: int, max_bypass: int = 8):
+    def __init__(self, budget_bytes: int, slots: int, max_bypass: int = 8, small_slots: int = 0):
         self.budget = budget_bytes
         self.slots = slots
+        self.small_slots = small_slots
         self.max_bypass = max_bypass
         self.used = 0
-        self.busy = 0
-        self.queue = collections.deque()  # (rid, footprint)
+        self.busy = 0          # general slots in use
+        self.busy_small = 0    # small slots in use
+        self.queue = collections.deque()  # (rid, footprint, small)
         self.head_bypassed = 0
 
-    def add(self, rid: int, footprint: int) -> None:
+    def add(self, rid: int, footprint: int, small: bool = False) -> None:
         if footprint > self.budget:
             raise ValueError(f"request {rid} needs {footprint} B, more than the budget {self.budget} B")
-        self.queue.append((rid, footprint))
+        self.queue.append((rid, footprint, bool(small)))
 
-    def pick(self):
-        """Next request to admit, or None.  Reserves its slot and bytes."""
-        if self.busy >= self.slots or not self.queue:
-            return None
-        rid, fp = self.queue[0]
-        if self.used + fp <= self.budget:
-            self.queue.popleft()
-            self.head_bypassed = 0
-            return self._take(rid, fp)
-        if self.head_bypassed >= self.max_bypass:
-            return None
-        for i in range(1, len(self.queue)):
-            r2, f2 = self.queue[i]
-            if self.used + f2 <= self.budget:
-                del self.queue[i]
-                self.head_bypassed += 1
-                return self._take(r2, f2)
+    def _slot_for(self, small: bool):
+        """'small', 'general' or None: the free slot a request would take."""
+        if small and self.busy_small < self.small_slots:
+            return "small"
+        if self.busy < self.slots:
+            return "general"
         return None
 
-    def _take(self, rid, fp):
-        self.used += fp
-        self.busy += 1
-        return rid, fp
+    def pick(self):
+        """Next request to admit as (rid, footprint, small_slot), or None.
+        Reserves its slot and bytes."""
+        if not self.queue:
+            return None
+        rid, fp, small = self.queue[0]
+        cls = self._slot_for(small)
+        if cls is not None and self.used + fp <= self.budget:
+            self.queue.popleft()
+            self.head_bypassed = 0
+            return self._take(rid, fp, cls)
+        for i in range(1, len(self.queue)):
+            r2, f2, s2 = self.queue[i]
+            c2 = self._slot_for(s2)
+            if c2 is None or self.used + f2 > self.budget:
+                continue
+            # passing the head costs it a turn only if the head could have
+            # used what this request takes: memory, or a general slot
+            counts = cls is not None or c2 == "general"
+            if counts and self.head_bypassed >= self.max_bypass:
+                continue
+            del self.queue[i]
+            if counts:
+                self.head_bypassed += 1
+            return self._take(r2, f2, c2)
+        return None
 
-    def release(self, footprint: int) -> None:
+    def _take(self, rid, fp, cls):
+        self.used += fp
+        if cls == "small":
+            self.busy_small += 1
+        else:
+            self.busy += 1
+        return rid, fp, cls == "small"
+
+    def release(self, footprint: int, small_slot: bool = False) -> None:
         self.used -= footprint
-        self.busy -= 1
+        if small_slot:
+            self.busy_small -= 1
+        else:
+            self.busy -= 1
 
 
 class Server:
     """Serves requests on `slots` concurrent streams within `budget_bytes`
     of device memory (default: SV_HBM_BUDGET_BYTES, else 64 GiB), complex64
     (or complex128) states, fusion width kmax (0: no fusion, one sweep per
-    gate).  Each slot's handle workspace and sampler buffer (sized for
-    max_qubits) are set aside first; requests are admitted by their state
-    size against the rest.  Requests above max_qubits are rejected."""
+    gate).  `small_slots` more streams serve only requests of at most
+    small_qubits qubits, so those never queue behind large states for a
+    slot.  Each slot's handle workspace and sampler buffer (sized for the
+    largest state it may serve) are set aside first; requests are admitted
+    by their state size against the rest.  Requests above max_qubits are
+    rejected."""
 
     def __init__(self, slots: int = 4, budget_bytes: int | None = None, dtype: str = "c64", kmax: int = 5,
-                 max_bypass: int = 8, max_qubits: int = 28):
+                 max_bypass: int = 8, max_qubits: int = 28, small_slots: int = 0, small_qubits: int = 16):
         import torch
         self.dtype = dtype
         self.kmax = kmax
         self.max_qubits = max_qubits
+        self.small_qubits = min(small_qubits, max_qubits)
         total = default_budget() if budget_bytes is None else budget_bytes
-        self.adm = Admission(request_budget(total, slots, max_qubits), slots, max_bypass)
+        left = request_budget(total, slots, max_qubits)
+        if small_slots:
+            left = request_budget(left, small_slots, self.small_qubits)
+        self.adm = Admission(left, slots, max_bypass, small_slots)
         self.cv = threading.Condition()
         self.pending = {}        # rid -> Request
         self.results = {}        # rid -> Result
-        self.ready = collections.deque()  # admitted, waiting for a worker
+        self.ready = {False: collections.deque(), True: collections.deque()}  # admitted, per slot class
         self.stop = False
-        self.handles = [Handle(stream=torch.cuda.Stream()) for _ in range(slots)]
-        self.workers = [threading.Thread(target=self._worker, args=(i,), daemon=True) for i in range(slots)]
+        n_workers = slots + small_slots
+        self.handles = [Handle(stream=torch.cuda.Stream()) for _ in range(n_workers)]
+        self.workers = [threading.Thread(target=self._worker, args=(i, i >= slots), daemon=True)
+                        for i in range(n_workers)]
         self.dispatcher = threading.Thread(target=self._dispatch, daemon=True)
         for w in self.workers:
             w.start()
@@ -177,7 +217,7 @@ class Server:
             raise ValueError(f"request {req.rid} has {req.n} qubits, more than the server's {self.max_qubits}")
         req.arrival = time.monotonic()
         with self.cv:
-            self.adm.add(req.rid, self.footprint(req.n))
+            self.adm.add(req.rid, self.footprint(req.n), req.n <= self.small_qubits)
             self.pending[req.rid] = req
             self.cv.notify_all()
 
@@ -188,20 +228,21 @@ class Server:
                 if picked is None:
                     self.cv.wait(timeout=0.05)
                     continue
-                rid, _ = picked
-                self.ready.append((rid, time.monotonic()))
+                rid, _, small_slot = picked
+                self.ready[small_slot].append((rid, time.monotonic()))
                 self.cv.notify_all()
 
-    def _worker(self, slot: int) -> None:
+    def _worker(self, slot: int, small_slot: bool) -> None:
         import torch
         h = self.handles[slot]
+        ready = self.ready[small_slot]
         while True:
             with self.cv:
-                while not self.ready and not self.stop:
+                while not ready and not self.stop:
                     self.cv.wait(timeout=0.05)
-                if self.stop and not self.ready:
+                if self.stop and not ready:
                     return
-                rid, admitted = self.ready.popleft()
+                rid, admitted = ready.popleft()
                 req = self.pending.pop(rid)
             try:
                 with torch.cuda.stream(h.stream):
@@ -211,7 +252,7 @@ class Server:
                              time.monotonic(), error=str(e))
             with self.cv:
                 self.results[rid] = res
-                self.adm.release(self.footprint(req.n))
+                self.adm.release(self.footprint(req.n), small_slot)
                 self.cv.notify_all()
 
     def _run(self, h: Handle, req: Request, admitted: float) -> Result:

@@ -135,6 +135,38 @@ def test_adjoint_flag(P, H):
     st.close()
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("k,n_ctrl,targets", [
+    (5, 0, (0, 1, 2, 3, 4)), (5, 0, (14, 3, 9, 11, 6)),  # five-qubit tiles
+    (6, 0, (2, 13, 5, 8, 0, 10)),                       # six-qubit tiles
+    (4, 0, (12, 1, 7, 4)), (2, 0, (9, 3)),              # padded to five qubits
+    (4, 1, (2, 11, 5, 0)), (5, 1, (6, 1, 13, 9, 3)),    # controlled: direct matrix-core path
+    (3, 2, (10, 4, 7)),                                 # controlled, vector path
+])
+def test_adjoint_flag_on_every_sweep(P, H, dt, k, n_ctrl, targets):
+    # a non-unitary matrix, so M^dagger differs from M^-1: the result must be
+    # the oracle's application of the conjugate transpose
+    n = 15
+    rng = np.random.default_rng(100 * k + n_ctrl)
+    d = 1 << k
+    m = (rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))) / math.sqrt(2.0 * d)
+    free = [q for q in range(n) if q not in targets]
+    controls = tuple(int(v) for v in rng.choice(free, n_ctrl, replace=False))
+    cvals = [int(v) for v in rng.integers(0, 2, size=n_ctrl)]
+    psi0 = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    st = _state(P, H, n, dt, basis=None)
+    st_np = psi0.astype(P.NP_DTYPES[st.dt])
+    P.sv_copy_from_host(st.s, st_np)
+    ref = st_np.astype(np.complex128)
+    oracle.apply(ref, np.conj(m).T, targets, controls, cvals)
+    st.apply_matrix(m, targets, controls, cvals, adjoint=True)
+    out = st.to_numpy().astype(np.complex128)
+    tol = 1e-12 if dt == "c128" else 2e-6
+    assert np.max(np.abs(out - ref)) <= tol
+    st.close()
+
+
 # ------------------------------------------------------------- whole circuits
 
 @pytest.mark.parametrize("seed", [0, 1])

@@ -36,7 +36,10 @@ def test_serving_mix_matches_alone_and_oracle(P):
                               n_terms=6, n_shots=256)
     # a few of the largest states at once, beside each slot's reserve
     states = 3 * (1 << 16) * 8
-    srv = Server(slots=3, budget_bytes=states + 3 * slot_reserve(16), dtype="c64", kmax=5, max_qubits=16)
+    # two general slots and two kept for requests of up to 12 qubits
+    srv = Server(slots=2, small_slots=2, small_qubits=12,
+                 budget_bytes=states + 2 * slot_reserve(16) + 2 * slot_reserve(12), dtype="c64", kmax=5,
+                 max_qubits=16)
     mixed = replay(srv, reqs)
     srv.close()
     assert all(not m.error for m in mixed.values()), [m.error for m in mixed.values()]

@@ -1,6 +1,6 @@
 """CPU tests of the serving admission policy (no GPU): FIFO order, the HBM
-budget, slot limits, bounded bypass of a blocked head, and rejection of
-requests that can never fit."""
+budget, slot limits, bounded bypass of a blocked head, slots reserved for
+small requests, and rejection of requests that can never fit."""
 import pytest
 
 from paper_2308_01999_amd import serve
@@ -11,11 +11,11 @@ def test_fifo_within_budget_and_slots():
     a = Admission(budget_bytes=100, slots=2)
     for rid, fp in [(0, 30), (1, 30), (2, 30)]:
         a.add(rid, fp)
-    assert a.pick() == (0, 30)
-    assert a.pick() == (1, 30)
+    assert a.pick() == (0, 30, False)
+    assert a.pick() == (1, 30, False)
     assert a.pick() is None          # both slots busy
     a.release(30)
-    assert a.pick() == (2, 30)
+    assert a.pick() == (2, 30, False)
     assert a.used == 60 and a.busy == 2
 
 
@@ -23,28 +23,73 @@ def test_budget_blocks_until_release():
     a = Admission(budget_bytes=100, slots=8)
     a.add(0, 70)
     a.add(1, 70)
-    assert a.pick() == (0, 70)
+    assert a.pick() == (0, 70, False)
     assert a.pick() is None          # 140 > 100
     a.release(70)
-    assert a.pick() == (1, 70)
+    assert a.pick() == (1, 70, False)
 
 
 def test_bounded_bypass_of_blocked_head():
     a = Admission(budget_bytes=100, slots=16, max_bypass=2)
     a.add(0, 60)
-    assert a.pick() == (0, 60)
+    assert a.pick() == (0, 60, False)
     a.add(1, 80)                     # head: does not fit while 0 runs
     for rid in range(2, 6):
         a.add(rid, 10)
-    assert a.pick() == (2, 10)       # bypass 1
-    assert a.pick() == (3, 10)       # bypass 2
+    assert a.pick() == (2, 10, False)       # bypass 1
+    assert a.pick() == (3, 10, False)       # bypass 2
     assert a.pick() is None          # no more bypass while the head waits
     a.release(60)
     a.release(10)
     a.release(10)
-    assert a.pick() == (1, 80)       # head admitted first
-    assert a.pick() == (4, 10)
-    assert a.pick() == (5, 10)
+    assert a.pick() == (1, 80, False)       # head admitted first
+    assert a.pick() == (4, 10, False)
+    assert a.pick() == (5, 10, False)
+
+
+def test_small_slots_serve_small_requests_past_large_ones():
+    a = Admission(budget_bytes=1000, slots=1, small_slots=2)
+    a.add(0, 100)                    # large: takes the general slot
+    a.add(1, 100)                    # large: waits for the general slot
+    for rid in (2, 3, 4):
+        a.add(rid, 10, small=True)
+    assert a.pick() == (0, 100, False)
+    # the head (1) waits for a general slot; small requests take the small
+    # slots without using up its bypass allowance
+    assert a.pick() == (2, 10, True)
+    assert a.pick() == (3, 10, True)
+    assert a.pick() is None          # small slots full, general slot busy
+    assert a.head_bypassed == 0
+    a.release(10, small_slot=True)
+    assert a.pick() == (4, 10, True)
+    a.release(100)
+    assert a.pick() == (1, 100, False)
+    assert a.busy == 1 and a.busy_small == 2
+
+
+def test_small_request_may_use_a_general_slot():
+    a = Admission(budget_bytes=1000, slots=2, small_slots=1)
+    for rid in (0, 1, 2):
+        a.add(rid, 10, small=True)
+    assert a.pick() == (0, 10, True)
+    assert a.pick() == (1, 10, False)
+    assert a.pick() == (2, 10, False)
+    a.add(3, 500)
+    assert a.pick() is None          # no general slot left for the large request
+
+
+def test_small_requests_passing_a_head_blocked_by_memory_count():
+    a = Admission(budget_bytes=100, slots=2, small_slots=2, max_bypass=1)
+    a.add(0, 60)
+    assert a.pick() == (0, 60, False)
+    a.add(1, 60)                     # head: a general slot is free, memory is not
+    a.add(2, 10, small=True)
+    a.add(3, 10, small=True)
+    assert a.pick() == (2, 10, True)  # passes the head: counts
+    assert a.pick() is None          # allowance used up
+    a.release(60)
+    assert a.pick() == (1, 60, False)
+    assert a.pick() == (3, 10, True)
 
 
 def test_oversized_request_rejected():
@@ -68,7 +113,7 @@ def test_footprint_counts_slot_scratch():
     a = Admission(left, 4)
     a.add(0, serve.state_bytes(28, "c64"))
     a.add(1, serve.state_bytes(27, "c64"))
-    assert a.pick() == (0, 2 << 30)
+    assert a.pick() == (0, 2 << 30, False)
     assert a.pick() is None
     with pytest.raises(ValueError):
         serve.request_budget(256 << 20, 4, 28)
@@ -91,6 +136,7 @@ def test_rejected_request_leaves_no_state():
     srv.pending = {}
     srv.dtype = "c64"
     srv.max_qubits = 28
+    srv.small_qubits = 0
     srv.adm = Admission(1 << 20, 1)
     with pytest.raises(ValueError):
         srv.submit(serve.Request(7, 20, [], [], None))     # 8 MiB > 1 MiB
@@ -99,4 +145,4 @@ def test_rejected_request_leaves_no_state():
         srv.submit(serve.Request(8, 29, [], [], None))     # above max_qubits
     assert srv.pending == {}
     srv.submit(serve.Request(9, 10, [], [], None))
-    assert list(srv.pending) == [9] and list(srv.adm.queue) == [(9, 8 << 10)]
+    assert list(srv.pending) == [9] and list(srv.adm.queue) == [(9, 8 << 10, False)]
