@@ -308,6 +308,7 @@ def sv_fuse_gates_diag(gates, max_fused_qubits: int, max_fused_diagonal_qubits: 
 
 GATE_CODES = {"u3": 0, "h": 1, "x": 2, "y": 3, "z": 4, "cx": 5, "cz": 6, "cp": 7, "swap": 8}
 SV_GATE_ADJOINT = 256
+_GATE_CODE_OF = {**GATE_CODES, **{k + "_dg": v | SV_GATE_ADJOINT for k, v in GATE_CODES.items()}}
 
 
 def sv_fuse_gate_list(codes, qubits, params, max_fused_qubits: int) -> int:
@@ -337,17 +338,17 @@ def sv_fuse_gate_list_diag(codes, qubits, params, max_fused_qubits: int, max_fus
 
 def gate_list_arrays(gates):
     """Workload gates (named gates only) -> (codes, qubits, params) arrays."""
-    G = len(gates)
-    codes = np.zeros(G, dtype=np.int32)
-    qubits = np.zeros((G, 2), dtype=np.int32)
-    params = np.zeros((G, 3), dtype=np.float64)
-    for g, (name, qs, ps) in enumerate(gates):
-        adj = name.endswith("_dg")
-        base = name[:-3] if adj else name
-        codes[g] = GATE_CODES[base] | (SV_GATE_ADJOINT if adj else 0)
-        qubits[g, : len(qs)] = qs
-        params[g, : len(ps)] = ps
-    return codes, qubits, params
+    codes, qubits, params = [], [], []
+    for name, qs, ps in gates:
+        code = _GATE_CODE_OF.get(name)
+        if code is None:
+            raise KeyError(f"unknown gate {name!r}")
+        codes.append(code)
+        qubits.append((qs[0], qs[1] if len(qs) > 1 else 0))
+        params.append((tuple(ps) + (0.0, 0.0, 0.0))[:3])
+    G = len(codes)
+    return (np.array(codes, dtype=np.int32).reshape(G), np.array(qubits, dtype=np.int32).reshape(G, 2),
+            np.array(params, dtype=np.float64).reshape(G, 3))
 
 
 def sv_fused_count(f: int) -> int:
