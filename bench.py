@@ -32,35 +32,37 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc passes
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged over the 30-qubit
-# complex64 launches), each scaled by what the same counter reads for a plain
-# copy of known size (FETCH_SIZE reads half the bytes a copy fetches, so x2.0;
-# WRITE_SIZE reads them all, x1.0).  Valid only for the kernel source the
-# counters were taken on: its SHA-256 is recorded and checked at run time.
+# launches of the headline circuit), each scaled by what the same counter
+# reads for a plain copy of known size (FETCH_SIZE reads half the bytes a
+# copy fetches, so x2.0; WRITE_SIZE reads them all, x1.0).  Valid only for the
+# kernel sources the counters were taken on: their SHA-256 are recorded and
+# checked at run time.
+_K5_SOURCES = {"paper_2308_01999_amd/csrc/sv_apply.hip":
+               "31752cb4dd14dd894918d04e5e6636006dbbac8044e080c6f9418307c2fa7e15",
+               "paper_2308_01999_amd/csrc/sv_tile.h":
+               "4c8938bc4f6b7336ce9610a1a44a224479c8fd1c848c2706ee43b296858d1f81"}
 PMC_TRAFFIC = {
-    # 30-qubit brickwork sweep, dispatch-weighted over all tile variants
-    # (c64: 778 launches of the 256-thread shapes + 102 wide; c128: 770 + 110)
-    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194404.7, "write_kib": 8389961.0,
-                      "fetch_scale": 2.0, "write_scale": 1.0,
-                      "source": "paper_2308_01999_amd/csrc/sv_apply.hip",
-                      "source_sha256": "7bd9f80ec412a33a8306ce9324964b3757d1df764799a3a619ae54f536cabf2e"},
-    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388720.7, "write_kib": 16781059.1,
-                       "fetch_scale": 2.0, "write_scale": 1.0,
-                       "source": "paper_2308_01999_amd/csrc/sv_apply.hip",
-                       "source_sha256": "7bd9f80ec412a33a8306ce9324964b3757d1df764799a3a619ae54f536cabf2e"},
+    # 30-qubit brickwork sweep, dispatch-weighted over all tile variants (676
+    # launches of each dtype in one pass: 13 steps of 52 blocks)
+    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194404.5, "write_kib": 8389726.6,
+                      "fetch_scale": 2.0, "write_scale": 1.0, "sources": _K5_SOURCES},
+    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388721.0, "write_kib": 16780431.4,
+                       "fetch_scale": 2.0, "write_scale": 1.0, "sources": _K5_SOURCES},
 }
 
 
 def pmc_traffic(kernel, n):
     """Calibrated HBM bytes per launch of `kernel` at n qubits from the
-    recorded counters, or None if none were taken for it or its source has
+    recorded counters, or None if none were taken for it or its sources have
     changed since."""
     import hashlib
     rec = PMC_TRAFFIC.get(kernel)
-    if rec is None or rec["n"] != n or rec["source_sha256"] is None:
+    if rec is None or rec["n"] != n:
         return None
-    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
-            return None
+    for path, digest in rec["sources"].items():
+        with open(os.path.join(ROOT, path), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
     return int(rec["fetch_kib"] * 1024 * rec["fetch_scale"] + rec["write_kib"] * 1024 * rec["write_scale"])
 
 

@@ -1,6 +1,6 @@
 """CPU checks of bench.py's host logic: the multi-GPU refusal and the
-recorded HBM counters (used only while the kernel source they were taken on
-is unchanged)."""
+recorded HBM counters (used only while the kernel sources they were taken
+on are unchanged)."""
 import hashlib
 import os
 import subprocess
@@ -21,8 +21,10 @@ def test_more_than_one_gpu_is_refused():
 
 def test_traffic_record_follows_the_kernel_source():
     for kernel, rec in bench.PMC_TRAFFIC.items():
-        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-            current = hashlib.sha256(f.read()).hexdigest() == rec["source_sha256"]
+        current = True
+        for path, digest in rec["sources"].items():
+            with open(os.path.join(ROOT, path), "rb") as f:
+                current &= hashlib.sha256(f.read()).hexdigest() == digest
         t = bench.pmc_traffic(kernel, rec["n"])
         if current:
             # 2 x FETCH_SIZE + WRITE_SIZE, within 0.1% of the algorithmic
