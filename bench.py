@@ -118,6 +118,9 @@ def parse():
     ap.add_argument("--large", action="store_true",
                     help="also time the fused depth-12 random CNOT/CP circuit on 34 qubits (complex64) and "
                          "33 qubits (complex128): 128 GiB states")
+    ap.add_argument("--full-oracle", action="store_true",
+                    help="also compare the whole 30-qubit states (fused and unfused, both dtypes) with the "
+                         "oracle's, streamed through host memory (the oracle takes minutes on the host)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain device copies of known size (for HBM counter calibration)")
     return ap.parse_args()
@@ -390,6 +393,39 @@ def config1_errors(P, W, H):
                 "max_abs_damp": float(np.max(np.abs(got - ref))),
                 "fidelity": oracle.fidelity(ref, got),
                 "max_abs_dz": float(np.max(np.abs(z - zref)))}
+    return out
+
+
+def full_oracle_errors(P, W, H, gates, n, states):
+    """The oracle's whole state for `gates` (its gates applied one by one on
+    the host, progress printed) against each GPU state in `states` (label ->
+    libsv state), streamed in chunks: max |d amp| and the fidelity."""
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    ref = oracle.basis_state(n, 0)
+    for g, gate in enumerate(gates):
+        oracle.apply_gate(ref, gate)
+        if g % 50 == 0:
+            print(f"[bench] oracle gate {g}/{len(gates)} {time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+    t_or = time.perf_counter() - t0
+    out = {"workload": f"{n}-qubit brickwork depth 20 seed 0, whole states", "oracle_s": round(t_or, 1),
+           "oracle_threads": oracle.threads()}
+    chunk = 1 << 24
+    for label, (st, dt) in states.items():
+        buf = np.empty(chunk, dtype=np.complex64 if dt == "c64" else np.complex128)
+        ov, ng, nr, dmax = 0.0 + 0.0j, 0.0, 0.0, 0.0
+        for first in range(0, 1 << n, chunk):
+            P.sv_copy_to_host(st.s, buf, first, chunk)
+            a = buf.astype(np.complex128)
+            r = ref[first: first + chunk]
+            ov += np.vdot(r, a)
+            ng += np.vdot(a, a).real
+            nr += np.vdot(r, r).real
+            dmax = max(dmax, float(np.max(np.abs(a - r))))
+        out[label] = {"max_abs_damp": dmax, "fidelity": float(abs(ov) ** 2 / (ng * nr))}
+        print(f"[bench] full-state comparison {label}: {out[label]}", file=sys.stderr, flush=True)
+    del ref
     return out
 
 
@@ -923,9 +959,14 @@ def main():
             n64 += np.vdot(a128, a128).real
             n128 += np.vdot(b, b).real
         r128["fidelity_c64_vs_c128"] = float(abs(ov) ** 2 / (n64 * n128))
-        st128.close()
         extra["c128"] = r128
-    st64.close()
+    # the fused states stay for the full-state comparison, if asked for
+    st64_keep = st64 if args.full_oracle else None
+    st128_keep = st128 if (args.full_oracle and not args.no_c128) else None
+    if st64_keep is None:
+        st64.close()
+    if not args.no_c128 and st128_keep is None:
+        st128.close()
     torch.cuda.synchronize()
     dk = r64["dominant_kernel"]
     achieved = dk["GBps"]
@@ -963,6 +1004,20 @@ def main():
                                  "unit": "GB/s", "frac": round(dk2["GBps"] / HBM_PEAK_GBS, 4),
                                  "traffic": pmc_traffic(k2, n), "kernel": k2,
                                  "bytes_per_launch": dk2["bytes_per_launch"], "avg_launch_ms": round(dk2["avg_ms"], 4)}
+    if args.full_oracle:
+        # the timed legs' states (fused) and unfused runs of the same circuit
+        print("[bench] full-state comparison with the oracle", file=sys.stderr, flush=True)
+        states = {}
+        for dt in ("c64", "c128"):
+            su = P.State(H, n, dt)
+            su.run(gates)
+            states[f"{dt}_unfused"] = (su, dt)
+        states["c64_fused5"] = (st64_keep, "c64")
+        if st128_keep is not None:
+            states["c128_fused5"] = (st128_keep, "c128")
+        errors["config2_full"] = full_oracle_errors(P, W, H, gates, n, states)
+        for su, _ in states.values():
+            su.close()
     print("[bench] 12-qubit configuration against the oracle", file=sys.stderr, flush=True)
     errors["config1"] = config1_errors(P, W, H)
     line["oracle_errors"] = errors
