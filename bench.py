@@ -533,8 +533,10 @@ def diagonal_leg(P, W, torch, H, n, reps=10):
     gates on 2 and 10 targets (random phases) and a permutation on 3 targets,
     HBM GB/s over `reps` back-to-back sweeps each (HIP events on the handle's
     stream); then the n-qubit QFT fused with dense blocks only (k <= 5)
-    against dense plus diagonal blocks (k <= 5, diagonal k <= 10): sweeps and
-    apply time of one timed pass after one untimed pass."""
+    against dense plus diagonal blocks (k <= 5, diagonal k <= 10) and against
+    coupled fusion (k <= 5, the controlled phases carried as couplings of
+    the dense blocks): sweeps and apply time of one timed pass after one
+    untimed pass."""
     import numpy as np
     out = {}
     rng = np.random.default_rng(17)
@@ -557,8 +559,9 @@ def diagonal_leg(P, W, torch, H, n, reps=10):
             ms = e0.elapsed_time(e1) / reps
             res[label] = {"avg_ms": round(ms, 3), "GBps": round(sweep / (ms * 1e-3) / 1e9, 1)}
         gates = W.qft(n)
-        for label, kd in (("qft_dense_only", 0), ("qft_dense_and_diagonal", 10)):
-            f = P.fuse(gates, 5, kd)
+        for label, kd, coupled in (("qft_dense_only", 0, False), ("qft_dense_and_diagonal", 10, False),
+                                   ("qft_coupled", 0, True)):
+            f = P.fuse(gates, 5, kd, coupled)
             ndiag = sum(1 for _, m in f.blocks() if m.ndim == 1)
             P.sv_apply_fused(st.s, f.f)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -571,6 +574,7 @@ def diagonal_leg(P, W, torch, H, n, reps=10):
                           "GBps": round(f.count * sweep / (ms * 1e-3) / 1e9, 1)}
             f.free()
         res["qft_speedup"] = round(res["qft_dense_only"]["apply_ms"] / res["qft_dense_and_diagonal"]["apply_ms"], 2)
+        res["qft_coupled_speedup"] = round(res["qft_dense_only"]["apply_ms"] / res["qft_coupled"]["apply_ms"], 2)
         out[dt] = res
         st.close()
         torch.cuda.synchronize()

@@ -261,6 +261,39 @@ sv_status_t sv_fuse_gate_list_diag(const int32_t* codes, const int32_t* qubits, 
                                    int32_t n_gates, int32_t max_fused_qubits, int32_t max_fused_diagonal_qubits,
                                    sv_fused_t* out);
 
+/*
+ * Coupled fusion: dense fusion (blocks of up to max_fused_qubits qubits)
+ * that also lets diagonal phase gates pass (Sec. II-D: diagonal gates are
+ * cheap to fuse; Table II fuses the QFT's 577 gates into 18).  A diagonal
+ * gate on at most two qubits whose entries all have modulus one (CZ, CP, Z,
+ * phase gates) touching a block's qubits and a qubit outside it is not
+ * forced into a block of its own: it commutes with everything up to the
+ * next non-diagonal gate on its qubits, so it is deferred and applied at
+ * the start of the next block that contains one of its qubits.  There its
+ * parts inside the block join the block's matrix, and a part coupling a
+ * block qubit a to an outside qubit b becomes a phase coupling of the
+ * block: before the matrix, the amplitude at index i is multiplied by
+ * exp(i phi) when bits a and b of i are both set (sv_fused_block_coupling).
+ * Phases still deferred at the end form blocks without gates.  Blocks are
+ * dense (never diagonal blocks).  Applying the blocks in order (each:
+ * coupling, then matrix) equals applying the gates in order.  Host only;
+ * FP64 products.
+ */
+sv_status_t sv_fuse_gates_coupled(const sv_gate_t* gates, int32_t n_gates, int32_t max_fused_qubits,
+                                  sv_fused_t* out);
+sv_status_t sv_fuse_gate_list_coupled(const int32_t* codes, const int32_t* qubits, const double* params,
+                                      int32_t n_gates, int32_t max_fused_qubits, sv_fused_t* out);
+
+/* Phase coupling of block i: *n_coupled qubits outside the block (ascending
+ * into coupled_qubits, room for SV_MAX_QUBITS, may be NULL) and, if phases
+ * is not NULL, phases[a * n_coupled + c] (k x n_coupled doubles): the
+ * amplitude at index i is multiplied by exp(i sum of phases[a * n_coupled +
+ * c] over the a with bit targets[a] of i set and the c with bit
+ * coupled_qubits[c] of i set) before the block's matrix.  0 coupled qubits
+ * for blocks of the other fusion modes. */
+sv_status_t sv_fused_block_coupling(sv_fused_t f, int32_t i, int32_t* n_coupled, int32_t* coupled_qubits,
+                                    double* phases);
+
 /* Number of blocks. */
 sv_status_t sv_fused_count(sv_fused_t f, int32_t* n_blocks);
 

@@ -80,6 +80,9 @@ _SIGS = {
     "sv_fuse_gates_diag": [ctypes.POINTER(sv_gate_t), _i32, _i32, _i32, ctypes.POINTER(_vp)],
     "sv_fuse_gate_list_diag": [_pi32, _pi32, _pd, _i32, _i32, _i32, ctypes.POINTER(_vp)],
     "sv_fused_block_is_diagonal": [_vp, _i32, _pi32],
+    "sv_fuse_gates_coupled": [ctypes.POINTER(sv_gate_t), _i32, _i32, ctypes.POINTER(_vp)],
+    "sv_fuse_gate_list_coupled": [_pi32, _pi32, _pd, _i32, _i32, ctypes.POINTER(_vp)],
+    "sv_fused_block_coupling": [_vp, _i32, _pi32, _pi32, _pd],
     "sv_fused_count": [_vp, _pi32],
     "sv_fused_block": [_vp, _i32, _pi32, _pi32, _pd],
     "sv_fused_free": [_vp],
@@ -306,6 +309,15 @@ def sv_fuse_gates_diag(gates, max_fused_qubits: int, max_fused_diagonal_qubits: 
     return f.value
 
 
+def sv_fuse_gates_coupled(gates, max_fused_qubits: int) -> int:
+    """Coupled fusion of sv_gate_t-style gates (see sv.h)."""
+    keep = []
+    arr = _gate_array(gates, keep)
+    f = _vp()
+    _check(_L.sv_fuse_gates_coupled(arr, len(gates), max_fused_qubits, ctypes.byref(f)))
+    return f.value
+
+
 GATE_CODES = {"u3": 0, "h": 1, "x": 2, "y": 3, "z": 4, "cx": 5, "cz": 6, "cp": 7, "swap": 8}
 SV_GATE_ADJOINT = 256
 _GATE_CODE_OF = {**GATE_CODES, **{k + "_dg": v | SV_GATE_ADJOINT for k, v in GATE_CODES.items()}}
@@ -334,6 +346,29 @@ def sv_fuse_gate_list_diag(codes, qubits, params, max_fused_qubits: int, max_fus
     _check(_L.sv_fuse_gate_list_diag(c.ctypes.data_as(_pi32), q.ctypes.data_as(_pi32), _dptr(p), c.size,
                                      max_fused_qubits, max_fused_diagonal_qubits, ctypes.byref(f)))
     return f.value
+
+
+def sv_fuse_gate_list_coupled(codes, qubits, params, max_fused_qubits: int) -> int:
+    c = np.ascontiguousarray(codes, dtype=np.int32)
+    q = np.ascontiguousarray(qubits, dtype=np.int32)
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    if q.shape != (c.size, 2) or p.shape != (c.size, 3):
+        raise ValueError("qubits must be [G, 2] and params [G, 3]")
+    f = _vp()
+    _check(_L.sv_fuse_gate_list_coupled(c.ctypes.data_as(_pi32), q.ctypes.data_as(_pi32), _dptr(p), c.size,
+                                        max_fused_qubits, ctypes.byref(f)))
+    return f.value
+
+
+def sv_fused_block_coupling(f: int, i: int, k: int):
+    """(coupled qubits, phases [k, n_coupled]) of block i (k its qubit count)."""
+    nc = _i32()
+    q = (ctypes.c_int32 * SV_MAX_QUBITS)()
+    _check(_L.sv_fused_block_coupling(_vp(f), i, ctypes.byref(nc), q, None))
+    ph = np.zeros((k, nc.value), dtype=np.float64)
+    if nc.value:
+        _check(_L.sv_fused_block_coupling(_vp(f), i, ctypes.byref(nc), q, _dptr(ph)))
+    return [int(q[c]) for c in range(nc.value)], ph
 
 
 def gate_list_arrays(gates):
@@ -590,12 +625,12 @@ class State:
         m, nt, nc = sv_gate_matrix(name, params)
         sv_apply_matrix(self.s, m, qubits[nc:], qubits[:nc])
 
-    def run(self, gates, max_fused_qubits: int | None = None):
+    def run(self, gates, max_fused_qubits: int | None = None, coupled: bool = False):
         if not max_fused_qubits:
             for g in gates:
                 self.apply_gate(g)
             return None
-        f = fuse(gates, max_fused_qubits)
+        f = fuse(gates, max_fused_qubits, coupled=coupled)
         try:
             sv_apply_fused(self.s, f.f)
             return f.count
@@ -650,6 +685,14 @@ class Fused:
     def blocks(self):
         return [sv_fused_block(self.f, i) for i in range(self.count)]
 
+    def couplings(self):
+        """Per block: (coupled qubits, phases [k, n_coupled])."""
+        out = []
+        for i in range(self.count):
+            t, _ = sv_fused_block(self.f, i)
+            out.append(sv_fused_block_coupling(self.f, i, len(t)))
+        return out
+
     def free(self):
         if self.f:
             sv_fused_free(self.f)
@@ -666,8 +709,9 @@ class Graph:
     """A fused program recorded into a HIP graph for one state; launch()
     replays it on the state (async, on the handle's stream)."""
 
-    def __init__(self, state, gates, max_fused_qubits: int = 5, max_fused_diagonal_qubits: int = 0):
-        f = fuse(gates, max_fused_qubits, max_fused_diagonal_qubits)
+    def __init__(self, state, gates, max_fused_qubits: int = 5, max_fused_diagonal_qubits: int = 0,
+                 coupled: bool = False):
+        f = fuse(gates, max_fused_qubits, max_fused_diagonal_qubits, coupled)
         try:
             self.blocks = f.count
             self.g = sv_graph_create(state.s, f.f)
@@ -689,10 +733,17 @@ class Graph:
             pass
 
 
-def fuse(gates, max_fused_qubits: int, max_fused_diagonal_qubits: int = 0) -> Fused:
+def fuse(gates, max_fused_qubits: int, max_fused_diagonal_qubits: int = 0, coupled: bool = False) -> Fused:
     """Fused blocks of a workload circuit; with max_fused_diagonal_qubits > 0
-    diagonal gates also form diagonal blocks of up to that many qubits."""
-    if any(g[0] in ("mat", "mat_dg") for g in gates):
+    diagonal gates also form diagonal blocks of up to that many qubits; with
+    coupled, phase gates are deferred into the phase couplings of later
+    blocks (sv_fuse_gate_list_coupled)."""
+    named = not any(g[0] in ("mat", "mat_dg") for g in gates)
+    if coupled:
+        if named:
+            return Fused(sv_fuse_gate_list_coupled(*gate_list_arrays(gates), max_fused_qubits))
+        return Fused(sv_fuse_gates_coupled(gate_entries(gates), max_fused_qubits))
+    if not named:
         if max_fused_diagonal_qubits:
             return Fused(sv_fuse_gates_diag(gate_entries(gates), max_fused_qubits, max_fused_diagonal_qubits))
         return Fused(sv_fuse_gates(gate_entries(gates), max_fused_qubits))

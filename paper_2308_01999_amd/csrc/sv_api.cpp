@@ -16,6 +16,7 @@
 
 #include "sv_batch.h"
 #include "sv_internal.h"
+#include "sv_tile.h"
 
 namespace sv {
 
@@ -89,9 +90,9 @@ void batch_run(sv_batch_s* b, void* states, double* expect_out, double* latency_
 void batch_destroy(sv_batch_s* b);
 void batch_layout(sv_batch_s* b, uint64_t* state_bytes, uint64_t* byte_offsets);
 void batch_info(sv_batch_s* b, int n_qubits, int32_t* kmax, int32_t* blocks);
-sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag);
+sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag, bool coupled = false);
 sv_fused_s* fuse_gate_list(const int32_t* codes, const int32_t* qubits, const double* params, int n_gates,
-                           int kmax, int kdiag);
+                           int kmax, int kdiag, bool coupled = false);
 void gate_matrix(const char* name, const double* params, int n_params, double* out, int* n_targets,
                  int* n_controls);
 
@@ -597,6 +598,39 @@ sv_status_t sv_fuse_gate_list_diag(const int32_t* codes, const int32_t* qubits, 
     });
 }
 
+sv_status_t sv_fuse_gates_coupled(const sv_gate_t* gates, int32_t n_gates, int32_t max_fused_qubits, sv_fused_t* out)
+{
+    return guarded([&] {
+        SV_CHECK(out != nullptr, "out is NULL");
+        *out = nullptr;
+        *out = fuse(gates, n_gates, max_fused_qubits, 0, true);
+    });
+}
+
+sv_status_t sv_fuse_gate_list_coupled(const int32_t* codes, const int32_t* qubits, const double* params,
+                                      int32_t n_gates, int32_t max_fused_qubits, sv_fused_t* out)
+{
+    return guarded([&] {
+        SV_CHECK(out != nullptr, "out is NULL");
+        *out = nullptr;
+        *out = fuse_gate_list(codes, qubits, params, n_gates, max_fused_qubits, 0, true);
+    });
+}
+
+sv_status_t sv_fused_block_coupling(sv_fused_t f, int32_t i, int32_t* n_coupled, int32_t* coupled_qubits,
+                                    double* phases)
+{
+    return guarded([&] {
+        SV_CHECK(f != nullptr && n_coupled != nullptr, "NULL argument");
+        SV_CHECK(i >= 0 && i < f->n_blocks, "block index out of range");
+        const FusedBlock& b = f->blocks[i];
+        *n_coupled = b.n_couple;
+        if (coupled_qubits)
+            for (int c = 0; c < b.n_couple; ++c) coupled_qubits[c] = b.couple_q[c];
+        if (phases && b.n_couple > 0) std::memcpy(phases, b.couple, sizeof(double) * size_t(b.k) * b.n_couple);
+    });
+}
+
 sv_status_t sv_fused_count(sv_fused_t f, int32_t* n_blocks)
 {
     return guarded([&] {
@@ -641,16 +675,94 @@ sv_status_t sv_fused_free(sv_fused_t f)
 namespace sv {
 namespace {
 
+// A block of coupled fusion on 1-4 qubits of a state of >= 14 qubits as a
+// five-qubit block: pad qubits as pad_to_five takes them, the matrix
+// M (x) I, and a coupling term of a block qubit with a pad qubit becomes a
+// phase inside the block (its columns with both bits set scaled, since the
+// coupling acts before M); the other coupled qubits stay coupled.
+bool pad_coupled_to_five(int n, const FusedBlock& b, FusedBlock& out, std::vector<double>& mstore,
+                         std::vector<double>& cstore)
+{
+    if (b.k < 1 || b.k >= 5 || n < 14) return false;
+    uint64_t used = 0;
+    int lo = n, hi = -1;
+    int t[5];
+    for (int a = 0; a < b.k; ++a) {
+        t[a] = b.targets[a];
+        used |= uint64_t(1) << t[a];
+        lo = std::min(lo, t[a]);
+        hi = std::max(hi, t[a]);
+    }
+    int kk = b.k;
+    for (int q = lo - 1; q >= 0 && kk < 5; --q)
+        if (!((used >> q) & 1)) t[kk++] = q;
+    for (int q = hi + 1; q < n && kk < 5; ++q)
+        if (!((used >> q) & 1)) t[kk++] = q;
+    if (kk < 5) return false;
+    const int d = 1 << b.k, D = 32;
+    mstore.assign(size_t(2) * D * D, 0.0);
+    for (int e = 0; e < D / d; ++e)
+        for (int r = 0; r < d; ++r)
+            for (int c = 0; c < d; ++c) {
+                const size_t dst = size_t(e * d + r) * D + size_t(e * d + c);
+                mstore[2 * dst] = b.m[2 * (size_t(r) * d + c)];
+                mstore[2 * dst + 1] = b.m[2 * (size_t(r) * d + c) + 1];
+            }
+    out = b;
+    out.k = 5;
+    for (int a = 0; a < 5; ++a) out.targets[a] = t[a];
+    out.m = mstore.data();
+    std::vector<int> keep;
+    for (int c = 0; c < b.n_couple; ++c) {
+        int pad = -1;
+        for (int a = b.k; a < 5; ++a)
+            if (t[a] == b.couple_q[c]) pad = a;
+        if (pad < 0) {
+            keep.push_back(c);
+            continue;
+        }
+        for (int a = 0; a < b.k; ++a) {
+            const double ph = b.couple[size_t(a) * b.n_couple + c];
+            if (ph == 0.0) continue;
+            const double er = std::cos(ph), ei = std::sin(ph);
+            for (int col = 0; col < D; ++col) {
+                if (!((col >> a) & 1) || !((col >> pad) & 1)) continue;
+                for (int row = 0; row < D; ++row) {
+                    double* u = &mstore[2 * (size_t(row) * D + col)];
+                    const double ur = u[0], ui = u[1];
+                    u[0] = ur * er - ui * ei;
+                    u[1] = ur * ei + ui * er;
+                }
+            }
+        }
+    }
+    out.n_couple = int(keep.size());
+    cstore.assign(size_t(5) * keep.size(), 0.0);
+    for (size_t j = 0; j < keep.size(); ++j) {
+        out.couple_q[j] = b.couple_q[keep[j]];
+        for (int a = 0; a < b.k; ++a) cstore[size_t(a) * keep.size() + j] = b.couple[size_t(a) * b.n_couple + keep[j]];
+    }
+    out.couple = cstore.data();
+    return true;
+}
+
 // The blocks as launched: dense blocks on 2-4 qubits of a large state padded
-// to five qubits (pad_to_five), all others as they are.
+// to five qubits (pad_to_five; blocks of coupled fusion from 1 qubit up,
+// pad_coupled_to_five), all others as they are.
 void effective_blocks(int n, const sv_fused_s* f, int first, int end, std::vector<FusedBlock>& eff,
-                      std::vector<std::vector<double>>& padm)
+                      std::vector<std::vector<double>>& padm, std::vector<std::vector<double>>& padc)
 {
     eff.assign(f->blocks, f->blocks + f->n_blocks);
     padm.resize(f->n_blocks);
+    padc.resize(f->n_blocks);
     for (int b = first; b < end; ++b) {
         FusedBlock& blk = eff[b];
         if (blk.diagonal) continue;
+        if (blk.n_couple > 0) {
+            FusedBlock out;
+            if (pad_coupled_to_five(n, blk, out, padm[b], padc[b])) blk = out;
+            continue;
+        }
         int32_t pt[SV_MAX_TARGETS];
         int32_t t[SV_MAX_TARGETS];
         for (int a = 0; a < blk.k; ++a) t[a] = blk.targets[a];
@@ -663,10 +775,17 @@ void effective_blocks(int n, const sv_fused_s* f, int first, int end, std::vecto
 }
 
 // A fused block's device form and sweep: the dense sweep, or for a diagonal
-// block the diagonal sweep.
-size_t block_bytes(const sv_state_s* s, const FusedBlock& b)
+// block the diagonal sweep; a block with a phase coupling carries it (a
+// CoupleDev) after its matrix, 256-byte aligned.
+size_t matrix_part_bytes(const sv_state_s* s, const FusedBlock& b)
 {
     return b.diagonal ? gperm_table_bytes(s->dt, b.k, false) : packed_matrix_bytes(s->dt, s->n, b.k, 0);
+}
+
+size_t block_bytes(const sv_state_s* s, const FusedBlock& b)
+{
+    const size_t m = matrix_part_bytes(s, b);
+    return b.n_couple > 0 ? ((m + 255) & ~size_t(255)) + sizeof(CoupleDev) : m;
 }
 
 void pack_block(const sv_state_s* s, const FusedBlock& b, void* dst)
@@ -675,12 +794,27 @@ void pack_block(const sv_state_s* s, const FusedBlock& b, void* dst)
         pack_gperm(s->dt, b.k, nullptr, b.m, 0, dst);
     else
         pack_matrix(s->dt, s->n, b.k, 0, b.m, 0, dst);
+    if (b.n_couple > 0) {
+        CoupleDev cd{};
+        cd.n = b.n_couple;
+        cd.k = b.k;
+        for (int c = 0; c < b.n_couple; ++c) cd.q[c] = b.couple_q[c];
+        for (int a = 0; a < b.k; ++a) cd.t[a] = b.targets[a];
+        for (int a = 0; a < b.k; ++a)
+            for (int c = 0; c < b.n_couple; ++c)
+                cd.phase[a * SV_MAX_QUBITS + c] = b.couple[size_t(a) * b.n_couple + c] / M_PI;
+        const size_t off = (matrix_part_bytes(s, b) + 255) & ~size_t(255);
+        std::memcpy(static_cast<char*>(dst) + off, &cd, sizeof(cd));
+    }
 }
 
 void launch_block(sv_handle_s* h, const sv_state_s* s, const FusedBlock& b, const void* dm, const GateDesc& d)
 {
     if (b.diagonal)
         launch_gperm(h, s->dt, s->d, dm, d, false);
+    else if (b.n_couple > 0)
+        launch_apply_coupled(h, s->dt, s->d, dm,
+                             static_cast<const char*>(dm) + ((matrix_part_bytes(s, b) + 255) & ~size_t(255)), d);
     else
         launch_apply(h, s->dt, s->d, dm, d);
 }
@@ -693,9 +827,9 @@ void apply_fused_blocks(sv_state_s* s, sv_fused_s* f, int first, int count)
              "block range out of bounds");
     const int end = first + count;
     std::vector<GateDesc> descs(f->n_blocks);
-    std::vector<std::vector<double>> padm;
+    std::vector<std::vector<double>> padm, padc;
     std::vector<FusedBlock> eff;
-    effective_blocks(s->n, f, first, end, eff, padm);
+    effective_blocks(s->n, f, first, end, eff, padm, padc);
     for (int b = first; b < end; ++b) {
         const FusedBlock& blk = eff[b];
         descs[b] = make_desc(s->n, blk.targets, blk.k, nullptr, nullptr, 0);
@@ -769,9 +903,9 @@ sv_status_t sv_graph_create(sv_state_t s, sv_fused_t f, sv_graph_t* out)
         sv_handle_s* h = s->h;
         std::vector<GateDesc> descs(f->n_blocks);
         std::vector<size_t> offs(f->n_blocks);
-        std::vector<std::vector<double>> padm;
+        std::vector<std::vector<double>> padm, padc;
         std::vector<FusedBlock> eff;
-        effective_blocks(s->n, f, 0, f->n_blocks, eff, padm);
+        effective_blocks(s->n, f, 0, f->n_blocks, eff, padm, padc);
         size_t bytes = 0;
         for (int b = 0; b < f->n_blocks; ++b) {
             const FusedBlock& blk = eff[b];

@@ -265,6 +265,18 @@ __global__ __launch_bounds__(NT, NT == 512 ? SV_K5_WIDE_WAVES : 1) void k_tile_c
     tile_c64_k5_sweep<NT, false>(psi, mats, a, blockIdx.x, lds, amat, ZSums{nullptr, -1, nullptr, nullptr});
 }
 
+// The same sweep for a block of coupled fusion: each group's inputs are first
+// multiplied by the block's phase coupling (CoupleDev).
+template <int NT>
+__global__ __launch_bounds__(NT, NT == 512 ? SV_K5_WIDE_WAVES : 3) void k_tile_c64_k5c(
+    float2* __restrict__ psi, const float4* __restrict__ mats, TileArgs a, const CoupleDev* __restrict__ cp)
+{
+    __shared__ float4 lds[NT * kTileVecs];
+    __shared__ float4 amat[kK5AParts * 64 * 4];
+    tile_c64_k5_sweep<NT, false, true>(psi, mats, a, blockIdx.x, lds, amat, ZSums{nullptr, -1, nullptr, nullptr},
+                                       cp);
+}
+
 __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict__ psi,
                                                              const float4* __restrict__ mats, TileArgs a)
 {
@@ -338,9 +350,10 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_c64_k4(float2* __restrict
 // registers: three workgroups per CU instead of two.
 // NT = 256: 32 KiB tiles (2048 amplitudes); NT = 512: 64 KiB tiles (the
 // wide shape), eight waves.
-template <int NT>
+template <int NT, bool COUPLED>
 __global__ __launch_bounds__(NT) void k_tile_c128_k5(double2* __restrict__ psi,
-                                                              const double2* __restrict__ mats, TileArgs a)
+                                                              const double2* __restrict__ mats, TileArgs a,
+                                                              const CoupleDev* __restrict__ cp)
 {
     __shared__ double2 lds[NT * kTileVecs];
     __shared__ double amat[2 * 16 * 64];
@@ -384,6 +397,38 @@ __global__ __launch_bounds__(NT) void k_tile_c128_k5(double2* __restrict__ psi,
         double2 x[8];
 #pragma unroll
         for (int s8 = 0; s8 < 8; ++s8) x[s8] = lds[lds_swz(pq + a.lds_off[4 * s8])];
+        if constexpr (COUPLED) {
+            // the block's phase coupling on this lane's group (tile-local base
+            // pb); its amplitude s8 is matrix column 4 s8 + q, walked in
+            // Gray-code order of s8
+            auto cmul = [](const double2 u, const double2 w) {
+                return double2{u.x * w.x - u.y * w.y, u.x * w.y + u.y * w.x};
+            };
+            auto cmulc = [](const double2 u, const double2 w) {
+                return double2{u.x * w.x + u.y * w.y, u.y * w.x - u.x * w.y};
+            };
+            const uint64_t g = base + deposit_bits(uint32_t(pb >> a.L), a.hi_pos, a.n_hi) +
+                               uint64_t(pb & ((1 << a.L) - 1));
+            double L[5];
+            couple_terms(cp, g, L);
+            double2 e[5];
+#pragma unroll
+            for (int b = 0; b < 5; ++b) {
+                double sn, cs;
+                sincospi(L[b], &sn, &cs);
+                e[b] = double2{cs, sn};
+            }
+            double2 v = double2{1.0, 0.0};
+            if (q & 1) v = e[0];
+            if (q & 2) v = cmul(v, e[1]);
+            x[0] = cmul(x[0], v);
+#pragma unroll
+            for (int st = 1; st < 8; ++st) {
+                const int j = st ^ (st >> 1), b = __builtin_ctz(st);
+                v = ((j >> b) & 1) ? cmul(v, e[b + 2]) : cmulc(v, e[b + 2]);
+                x[j] = cmul(x[j], v);
+            }
+        }
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
             f64x4 p1 = {0}, p2 = {0}, p3 = {0};
@@ -840,7 +885,7 @@ int wide_tile_bits(Path p) { return p == Path::kTileC128K5 ? 12 : kK5TileBits; }
 
 // Variant for a k = 5 tile sweep (index into kTileVariants).  *trial is set
 // when this launch is to be timed.
-int tile_shape(sv_handle_s* h, Path p, const GateDesc& d, bool* trial)
+int tile_shape(sv_handle_s* h, Path p, const GateDesc& d, bool* trial, bool allow_trial)
 {
     *trial = false;
     if (d.n < wide_tile_bits(p)) return kVariantNarrow;
@@ -857,7 +902,7 @@ int tile_shape(sv_handle_s* h, Path p, const GateDesc& d, bool* trial)
     if (!capturing) tuner_poll(T);
     TileTuneEntry& e = T.entries[key];
     auto done = [&](int c) { return e.unusable[c] || e.measured[c] + e.in_flight[c] >= kTileTrials; };
-    if (!capturing && T.sweeps++ >= uint64_t(kTileWarmSweeps)) {
+    if (!capturing && allow_trial && T.sweeps++ >= uint64_t(kTileWarmSweeps)) {
         // trial j (counted over all variants) of this key belongs to round
         // j / kTileShapes, which visits the variants starting from the
         // round's number, so each variant takes every place in the order
@@ -881,11 +926,14 @@ int tile_shape(sv_handle_s* h, Path p, const GateDesc& d, bool* trial)
     return best < 0 ? kVariantSpread : best;
 }
 
-void launch_tile(sv_handle_s* h, Path p, void* psi, const void* mats, const GateDesc& d)
+void launch_tile(sv_handle_s* h, Path p, void* psi, const void* mats, const GateDesc& d,
+                 const CoupleDev* cpl = nullptr)
 {
     bool trial = false;
     const bool tuned = p == Path::kTileC64K5 || p == Path::kTileC128K5;
-    const int variant = tuned ? tile_shape(h, p, d, &trial) : 0;
+    // coupled sweeps do more arithmetic per group than the plain ones:
+    // they take the variant the plain sweeps chose, without timed trials
+    const int variant = tuned ? tile_shape(h, p, d, &trial, cpl == nullptr) : 0;
     const bool wide = tuned && kTileVariants[variant].wide;
     TileTrial tr{};
     if (trial) {
@@ -905,7 +953,13 @@ void launch_tile(sv_handle_s* h, Path p, void* psi, const void* mats, const Gate
     const uint64_t blocks = (t.n_tiles + t.tiles_per_wg - 1) / t.tiles_per_wg;
     switch (p) {
         case Path::kTileC64K5:
-            if (wide)
+            if (cpl && wide)
+                hipLaunchKernelGGL(k_tile_c64_k5c<kK5Threads>, dim3(unsigned(blocks)), dim3(kK5Threads), 0,
+                                   h->stream, static_cast<float2*>(psi), static_cast<const float4*>(mats), t, cpl);
+            else if (cpl)
+                hipLaunchKernelGGL(k_tile_c64_k5c<kTileThreads>, dim3(unsigned(blocks)), dim3(kTileThreads), 0,
+                                   h->stream, static_cast<float2*>(psi), static_cast<const float4*>(mats), t, cpl);
+            else if (wide)
                 hipLaunchKernelGGL(k_tile_c64_k5<kK5Threads>, dim3(unsigned(blocks)), dim3(kK5Threads), 0,
                                    h->stream, static_cast<float2*>(psi), static_cast<const float4*>(mats), t);
             else
@@ -917,12 +971,19 @@ void launch_tile(sv_handle_s* h, Path p, void* psi, const void* mats, const Gate
                                static_cast<float2*>(psi), static_cast<const float4*>(mats), t);
             break;
         case Path::kTileC128K5:
-            if (wide)
-                hipLaunchKernelGGL(k_tile_c128_k5<512>, dim3(unsigned(blocks)), dim3(512), 0, h->stream,
-                                   static_cast<double2*>(psi), static_cast<const double2*>(mats), t);
+            if (cpl && wide)
+                hipLaunchKernelGGL((k_tile_c128_k5<512, true>), dim3(unsigned(blocks)), dim3(512), 0, h->stream,
+                                   static_cast<double2*>(psi), static_cast<const double2*>(mats), t, cpl);
+            else if (cpl)
+                hipLaunchKernelGGL((k_tile_c128_k5<kTileThreads, true>), dim3(unsigned(blocks)), dim3(kTileThreads),
+                                   0, h->stream, static_cast<double2*>(psi), static_cast<const double2*>(mats), t, cpl);
+            else if (wide)
+                hipLaunchKernelGGL((k_tile_c128_k5<512, false>), dim3(unsigned(blocks)), dim3(512), 0, h->stream,
+                                   static_cast<double2*>(psi), static_cast<const double2*>(mats), t, nullptr);
             else
-                hipLaunchKernelGGL(k_tile_c128_k5<kTileThreads>, dim3(unsigned(blocks)), dim3(kTileThreads), 0,
-                                   h->stream, static_cast<double2*>(psi), static_cast<const double2*>(mats), t);
+                hipLaunchKernelGGL((k_tile_c128_k5<kTileThreads, false>), dim3(unsigned(blocks)), dim3(kTileThreads),
+                                   0, h->stream, static_cast<double2*>(psi), static_cast<const double2*>(mats), t,
+                                   nullptr);
             break;
         case Path::kTileC64K6:
             hipLaunchKernelGGL(k_tile_c64_k6, dim3(unsigned(blocks)), dim3(kK6Threads), 0, h->stream,
@@ -1130,7 +1191,51 @@ __global__ __launch_bounds__(kTileThreads) void k_tile_gperm(typename Cx<R>::T* 
         gstore(reinterpret_cast<V*>(psi + glob((u * kTileThreads + tid) * APV)), v[u]);
 }
 
+// Phase coupling on its own (blocks of coupled fusion whose dense part does
+// not run on the five-qubit tiles): one thread per amplitude, which is
+// rewritten only if its phase is not zero.
+template <typename R>
+__global__ __launch_bounds__(256) void k_couple(typename Cx<R>::T* __restrict__ psi, uint64_t dim,
+                                                const CoupleDev* __restrict__ cp)
+{
+    using T = typename Cx<R>::T;
+    const uint64_t i = uint64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= dim) return;
+    double th = 0.0;
+    for (int a = 0; a < cp->k; ++a) {
+        if (!((i >> cp->t[a]) & 1)) continue;
+        for (int c = 0; c < cp->n; ++c) th = fma(double((i >> cp->q[c]) & 1), cp->phase[a * SV_MAX_QUBITS + c], th);
+    }
+    if (th == 0.0) return;
+    th -= 2.0 * rint(0.5 * th);
+    double sn, cs;
+    sincospi(th, &sn, &cs);
+    const T v = psi[i];
+    const double re = double(v.x), im = double(v.y);
+    psi[i] = T{R(re * cs - im * sn), R(re * sn + im * cs)};
+}
+
 }  // namespace
+
+void launch_apply_coupled(sv_handle_s* h, sv_dtype_t dt, void* psi, const void* mat, const void* couple,
+                          const GateDesc& d)
+{
+    const CoupleDev* cp = static_cast<const CoupleDev*>(couple);
+    const Path p = choose(dt, d.n, d.k, d.n_controls);
+    if (p == Path::kTileC64K5 || p == Path::kTileC128K5) {
+        launch_tile(h, p, psi, mat, d, cp);
+        return;
+    }
+    const uint64_t dim = uint64_t(1) << d.n;
+    const unsigned blocks = unsigned((dim + 255) / 256);
+    if (dt == SV_C64)
+        hipLaunchKernelGGL(k_couple<float>, dim3(blocks), dim3(256), 0, h->stream, static_cast<float2*>(psi), dim, cp);
+    else
+        hipLaunchKernelGGL(k_couple<double>, dim3(blocks), dim3(256), 0, h->stream, static_cast<double2*>(psi), dim,
+                           cp);
+    SV_HIP(hipGetLastError());
+    launch_apply(h, dt, psi, mat, d);
+}
 
 size_t packed_matrix_bytes(sv_dtype_t dt, int n, int k, int n_controls)
 {

@@ -21,7 +21,7 @@
 namespace sv {
 
 sv_fused_s* fuse_gate_list(const int32_t* codes, const int32_t* qubits, const double* params, int n_gates,
-                           int kmax, int kdiag);
+                           int kmax, int kdiag, bool coupled = false);
 
 // One level of the level path: its workgroup entries and the circuits whose
 // expectations follow it.

@@ -9,7 +9,9 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "sv_internal.h"
@@ -344,12 +346,291 @@ std::vector<Selected> select_blocks(const std::vector<HostGate>& gates, int kmax
     return blocks;
 }
 
+// ------------------------------------------------------- coupled fusion
+//
+// Diagonal gates whose entries all have modulus one and that act on at most
+// two qubits (CZ, CP, Z, phase gates) are phases: such a gate multiplies the
+// amplitude at index i by exp(i theta(i)) with theta = c + s_a b_a + s_b b_b
+// + p b_a b_b (b_q the bit of qubit q in i).  Coupled fusion does not force
+// them into blocks: a dense block on qubit set S takes the gates inside S as
+// usual, and a phase gate that touches S but also a qubit outside it is
+// deferred: it commutes with every later gate on its qubits up to the next
+// non-diagonal one, so it can be applied at the start of the next block
+// that contains one of its qubits.  There the deferred terms are flushed:
+// constant, singles and pairs inside the block's qubits are folded into the
+// block's matrix, and a pair (a, b) with a in the block and b outside
+// becomes a phase coupling: the block's input amplitude is multiplied by
+// exp(i phi_ab) when both bits are set, which depends on the amplitude's
+// index outside the block and so is applied in the sweep itself.  A
+// deferred gate blocks later non-diagonal gates on its qubits from joining
+// the block being built (they have to wait for the flush).
+
+struct PhasePoly {
+    double constant = 0.0;
+    double single[64] = {};
+    uint64_t single_mask = 0;
+    std::map<std::pair<int, int>, double> pair;  // (a, b), a < b
+};
+
+// The phase terms of gate g if it is a deferrable phase gate.
+bool phase_terms(const HostGate& g, PhasePoly& out)
+{
+    if (!g.diagonal || popcount64(g.qmask) > 2) return false;
+    int qs[2] = {-1, -1}, nq = 0;
+    for (int q = 0; q < 64; ++q)
+        if ((g.qmask >> q) & 1) qs[nq++] = q;
+    const int d = 1 << g.targets.size();
+    double th[4] = {};
+    for (int x = 0; x < (1 << nq); ++x) {
+        // the gate's diagonal entry for bits x of its (ascending) qubits
+        auto bit = [&](int q) {
+            for (int a = 0; a < nq; ++a)
+                if (qs[a] == q) return (x >> a) & 1;
+            return 0;
+        };
+        bool on = true;
+        for (size_t a = 0; a < g.controls.size(); ++a) on &= bit(g.controls[a]) == g.cvals[a];
+        cd e(1.0, 0.0);
+        if (on) {
+            int r = 0;
+            for (size_t a = 0; a < g.targets.size(); ++a) r |= bit(g.targets[a]) << a;
+            e = g.m[size_t(r) * d + r];
+        }
+        if (std::fabs(std::abs(e) - 1.0) > 1e-12) return false;
+        th[x] = std::arg(e);
+    }
+    // zero terms are left out (a CP has no single-qubit part)
+    auto single = [&](int q, double v) {
+        if (v == 0.0) return;
+        out.single[q] += v;
+        out.single_mask |= uint64_t(1) << q;
+    };
+    out.constant += th[0];
+    if (nq == 1) {
+        single(qs[0], th[1] - th[0]);
+    } else {
+        single(qs[0], th[1] - th[0]);
+        single(qs[1], th[2] - th[0]);
+        const double p = th[3] - th[2] - th[1] + th[0];
+        if (p != 0.0) out.pair[{qs[0], qs[1]}] += p;
+    }
+    return true;
+}
+
+void add_terms(PhasePoly& to, const PhasePoly& from)
+{
+    to.constant += from.constant;
+    for (int q = 0; q < 64; ++q)
+        if ((from.single_mask >> q) & 1) to.single[q] += from.single[q];
+    to.single_mask |= from.single_mask;
+    for (const auto& kv : from.pair) to.pair[kv.first] += kv.second;
+}
+
+// Moves the terms of `from` that touch S (and its constant) into `to`.
+void flush_terms(PhasePoly& from, uint64_t S, PhasePoly& to)
+{
+    to.constant += from.constant;
+    from.constant = 0.0;
+    for (int q = 0; q < 64; ++q) {
+        if (((from.single_mask & S) >> q) & 1) {
+            to.single[q] += from.single[q];
+            to.single_mask |= uint64_t(1) << q;
+            from.single[q] = 0.0;
+        }
+    }
+    from.single_mask &= ~S;
+    for (auto it = from.pair.begin(); it != from.pair.end();) {
+        const uint64_t m = (uint64_t(1) << it->first.first) | (uint64_t(1) << it->first.second);
+        if (m & S) {
+            to.pair[it->first] += it->second;
+            it = from.pair.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+struct CoupledSel {
+    std::vector<int> gates;  // taken, in circuit order
+    uint64_t S = 0;
+    PhasePoly flushed;       // applied before the gates
+};
+
+std::vector<CoupledSel> select_blocks_coupled(const std::vector<HostGate>& gates, int kmax)
+{
+    const size_t G = gates.size();
+    std::vector<int> live(G);
+    std::vector<uint64_t> mask(G);
+    std::vector<char> diag(G), deferrable(G);
+    std::vector<PhasePoly> terms(G);
+    for (size_t i = 0; i < G; ++i) {
+        live[i] = int(i);
+        mask[i] = gates[i].qmask;
+        diag[i] = gates[i].diagonal;
+        deferrable[i] = phase_terms(gates[i], terms[i]);
+    }
+    std::vector<CoupledSel> blocks;
+    PhasePoly pending;
+    std::vector<char> take;  // 1 taken, 2 deferred
+    constexpr size_t kWindow = 256;
+    // Gates S takes (inside S) and defers (phases touching S) in one scan.
+    auto absorb = [&](uint64_t S, bool mark) {
+        uint64_t blocked_all = 0, blocked_nd = 0;
+        int count = 0;
+        for (size_t j = 0; j < live.size(); ++j) {
+            const uint64_t Q = mask[j];
+            const int li = live[j];
+            if (Q & blocked_all) {
+                if (diag[li])
+                    blocked_nd |= Q;
+                else
+                    blocked_all |= Q;
+            } else if (!diag[li]) {
+                if ((Q & ~S) == 0 && (Q & blocked_nd) == 0) {
+                    ++count;
+                    if (mark) take[j] = 1;
+                } else {
+                    blocked_all |= Q;
+                }
+            } else if ((Q & ~S) == 0) {
+                ++count;
+                if (mark) take[j] = 1;
+            } else if ((Q & S) && deferrable[li]) {
+                ++count;
+                if (mark) take[j] = 2;
+                blocked_nd |= Q;
+            } else {
+                blocked_nd |= Q;
+            }
+            if ((S & ~blocked_all) == 0) break;
+        }
+        return count;
+    };
+    std::vector<int> ready;
+    // Grows S one qubit at a time from the qubits of near-future gates that
+    // touch it; when none is left, by all qubits of a ready gate disjoint
+    // from S that fits (independent gates side by side in one block), the
+    // one that lets the most gates be absorbed.
+    auto grow = [&](uint64_t S) {
+        while (popcount64(S) < kmax) {
+            uint64_t cand = 0;
+            const size_t lim = std::min(live.size(), kWindow);
+            for (size_t j = 0; j < lim; ++j)
+                if (mask[j] & S) cand |= mask[j] & ~S;
+            if (cand) {
+                int best_q = -1, best_c = -1;
+                for (int q = 0; q < 64; ++q) {
+                    if (!((cand >> q) & 1)) continue;
+                    const int c = absorb(S | (uint64_t(1) << q), false);
+                    if (c > best_c) {
+                        best_c = c;
+                        best_q = q;
+                    }
+                }
+                S |= uint64_t(1) << best_q;
+                continue;
+            }
+            const int here = absorb(S, false);
+            uint64_t best_m = 0;
+            int best_c = here;
+            for (int pos : ready) {
+                const uint64_t m = mask[size_t(pos)];
+                if ((m & S) || popcount64(S | m) > kmax) continue;
+                const int c = absorb(S | m, false);
+                if (c > best_c) {
+                    best_c = c;
+                    best_m = m;
+                }
+            }
+            if (!best_m) break;
+            S |= best_m;
+        }
+        return S;
+    };
+    while (!live.empty()) {
+        ready.clear();
+        uint64_t seen = 0;
+        for (size_t j = 0; j < live.size(); ++j) {
+            if ((mask[j] & seen) == 0) ready.push_back(int(j));
+            seen |= mask[j];
+        }
+        uint64_t best_S = 0;
+        int best_count = -1;
+        for (int pos : ready) {
+            const uint64_t S = grow(mask[size_t(pos)]);
+            const int c = absorb(S, false);
+            if (c > best_count) {
+                best_count = c;
+                best_S = S;
+            }
+        }
+        SV_CHECK(best_count > 0, "internal: coupled fusion found no block");
+        CoupledSel sel;
+        sel.S = best_S;
+        // the phases deferred so far that touch the block precede its gates
+        flush_terms(pending, best_S, sel.flushed);
+        take.assign(live.size(), 0);
+        absorb(best_S, true);
+        size_t w = 0;
+        for (size_t j = 0; j < live.size(); ++j) {
+            if (take[j] == 1) {
+                sel.gates.push_back(live[j]);
+            } else if (take[j] == 2) {
+                add_terms(pending, terms[size_t(live[j])]);
+            } else {
+                live[w] = live[j];
+                mask[w] = mask[j];
+                ++w;
+            }
+        }
+        live.resize(w);
+        mask.resize(w);
+        blocks.push_back(std::move(sel));
+    }
+    // phases still deferred at the end: blocks without gates, each on up to
+    // kmax qubits chosen greedily to cover the most remaining terms
+    while (pending.single_mask || !pending.pair.empty()) {
+        uint64_t S = 0;
+        while (popcount64(S) < kmax) {
+            int score[64] = {};
+            for (int q = 0; q < 64; ++q)
+                if (((pending.single_mask & ~S) >> q) & 1) ++score[q];
+            for (const auto& kv : pending.pair) {
+                const int a = kv.first.first, b = kv.first.second;
+                if (((S >> a) & 1) || ((S >> b) & 1)) continue;
+                ++score[a];
+                ++score[b];
+            }
+            int best = -1;
+            for (int q = 0; q < 64; ++q)
+                if (score[q] > 0 && (best < 0 || score[q] > score[best])) best = q;
+            if (best < 0) break;
+            S |= uint64_t(1) << best;
+        }
+        CoupledSel sel;
+        sel.S = S;
+        flush_terms(pending, S, sel.flushed);
+        blocks.push_back(std::move(sel));
+    }
+    if (pending.constant != 0.0) {
+        // a global phase left over: the last block carries it (or a block of
+        // its own on qubit 0 when there is none)
+        if (blocks.empty()) {
+            CoupledSel sel;
+            sel.S = 1;
+            blocks.push_back(std::move(sel));
+        }
+        blocks.back().flushed.constant += pending.constant;
+    }
+    return blocks;
+}
+
 }  // namespace
 
-sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag);
+sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag, bool coupled);
 
 sv_fused_s* fuse_gate_list(const int32_t* codes, const int32_t* qubits, const double* params, int n_gates,
-                           int kmax, int kdiag)
+                           int kmax, int kdiag, bool coupled)
 {
     SV_CHECK(n_gates >= 0, "n_gates is negative");
     SV_CHECK(n_gates == 0 || (codes && qubits && params), "NULL gate arrays");
@@ -378,10 +659,109 @@ sv_fused_s* fuse_gate_list(const int32_t* codes, const int32_t* qubits, const do
         e.matrix = &mats[size_t(g) * 32];
         e.adjoint = 0;  // the adjoint code is already in the matrix
     }
-    return fuse(gates.data(), n_gates, kmax, kdiag);
+    return fuse(gates.data(), n_gates, kmax, kdiag, coupled);
 }
 
-sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag)
+namespace {
+
+// Blocks of coupled fusion: each block's matrix is the product of its gates
+// times the diagonal of its flushed phases inside its qubits (applied
+// first), and its coupling holds the flushed pairs with one qubit outside.
+sv_fused_s* build_coupled(const std::vector<HostGate>& hg, const std::vector<CoupledSel>& sel)
+{
+    struct Plan {
+        std::vector<int> qs;      // targets, ascending
+        std::vector<int> cq;      // coupled qubits, ascending
+    };
+    std::vector<Plan> plan(sel.size());
+    size_t total = 0;
+    for (size_t b = 0; b < sel.size(); ++b) {
+        const CoupledSel& c = sel[b];
+        uint64_t T = 0;
+        for (int i : c.gates) T |= hg[i].qmask;
+        T |= c.flushed.single_mask & c.S;
+        uint64_t C = 0;
+        for (const auto& kv : c.flushed.pair) {
+            const uint64_t ma = uint64_t(1) << kv.first.first, mb = uint64_t(1) << kv.first.second;
+            T |= (ma | mb) & c.S;
+            C |= (ma | mb) & ~c.S;
+        }
+        if (T == 0) T = c.S & (~c.S + 1);  // a block holding only a global phase
+        for (int q = 0; q < 64; ++q) {
+            if ((T >> q) & 1) plan[b].qs.push_back(q);
+            if ((C >> q) & 1) plan[b].cq.push_back(q);
+        }
+        SV_CHECK(plan[b].qs.size() <= size_t(SV_MAX_TARGETS), "internal: coupled block too wide");
+        SV_CHECK(plan[b].cq.size() <= size_t(SV_MAX_QUBITS), "coupled fusion: too many coupled qubits");
+        const size_t d = size_t(1) << plan[b].qs.size();
+        total += 2 * d * d + plan[b].qs.size() * plan[b].cq.size();
+    }
+    auto* f = new sv_fused_s;
+    f->n_blocks = int(sel.size());
+    f->blocks = new FusedBlock[sel.size()];
+    f->storage = new double[std::max<size_t>(total, 1)];
+    size_t at = 0;
+    for (size_t b = 0; b < sel.size(); ++b) {
+        const CoupledSel& c = sel[b];
+        const std::vector<int>& qs = plan[b].qs;
+        const std::vector<int>& cq = plan[b].cq;
+        const int m = int(qs.size());
+        const uint64_t dim = uint64_t(1) << m;
+        auto pos = [&](int q) { return int(std::lower_bound(qs.begin(), qs.end(), q) - qs.begin()); };
+        FusedBlock& blk = f->blocks[b];
+        blk.k = m;
+        for (int a = 0; a < m; ++a) blk.targets[a] = qs[a];
+        std::vector<double> U(2 * dim * dim, 0.0);
+        for (uint64_t i = 0; i < dim; ++i) U[2 * (i * dim + i)] = 1.0;
+        for (int gi : c.gates) {
+            const HostGate& g = hg[gi];
+            std::vector<int> pt, pc;
+            for (int q : g.targets) pt.push_back(pos(q));
+            for (int q : g.controls) pc.push_back(pos(q));
+            left_multiply(U, m, g, pt, pc);
+        }
+        // flushed phases inside the block: U <- U diag(exp(i theta(col)))
+        for (uint64_t col = 0; col < dim; ++col) {
+            double th = c.flushed.constant;
+            for (int a = 0; a < m; ++a)
+                if (((col >> a) & 1) && ((c.flushed.single_mask >> qs[a]) & 1)) th += c.flushed.single[qs[a]];
+            for (const auto& kv : c.flushed.pair) {
+                const int x = kv.first.first, y = kv.first.second;
+                if (((c.S >> x) & 1) && ((c.S >> y) & 1) && ((col >> pos(x)) & 1) && ((col >> pos(y)) & 1))
+                    th += kv.second;
+            }
+            if (th == 0.0) continue;
+            const double er = std::cos(th), ei = std::sin(th);
+            for (uint64_t row = 0; row < dim; ++row) {
+                double* u = &U[2 * (row * dim + col)];
+                const double ur = u[0], ui = u[1];
+                u[0] = ur * er - ui * ei;
+                u[1] = ur * ei + ui * er;
+            }
+        }
+        blk.m = f->storage + at;
+        std::memcpy(blk.m, U.data(), sizeof(double) * 2 * dim * dim);
+        at += 2 * dim * dim;
+        blk.n_couple = int(cq.size());
+        for (size_t j = 0; j < cq.size(); ++j) blk.couple_q[j] = cq[j];
+        blk.couple = f->storage + at;
+        for (size_t e = 0; e < size_t(m) * cq.size(); ++e) blk.couple[e] = 0.0;
+        for (const auto& kv : c.flushed.pair) {
+            const int x = kv.first.first, y = kv.first.second;
+            const bool xin = (c.S >> x) & 1, yin = (c.S >> y) & 1;
+            if (xin == yin) continue;
+            const int a = pos(xin ? x : y), o = xin ? y : x;
+            const size_t ci = size_t(std::lower_bound(cq.begin(), cq.end(), o) - cq.begin());
+            blk.couple[size_t(a) * cq.size() + ci] += kv.second;
+        }
+        at += size_t(m) * cq.size();
+    }
+    return f;
+}
+
+}  // namespace
+
+sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag, bool coupled)
 {
     SV_CHECK(n_gates >= 0, "n_gates is negative");
     SV_CHECK(n_gates == 0 || gates != nullptr, "gates is NULL");
@@ -424,6 +804,7 @@ sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag)
             if (e / d != e % d && h.m[e] != cd(0.0, 0.0)) h.diagonal = false;
         }
     }
+    if (coupled) return build_coupled(hg, select_blocks_coupled(hg, kmax));
     const auto sel = select_blocks(hg, kmax, kdiag);
     // build matrices
     std::vector<std::vector<int>> qs(sel.size());

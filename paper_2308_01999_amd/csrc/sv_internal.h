@@ -125,6 +125,13 @@ struct FusedBlock {
     // diagonal entries
     double* m = nullptr;
     bool diagonal = false;
+    // Phase coupling applied before m (dense blocks of coupled fusion): the
+    // amplitude at index i is first multiplied by exp(i theta), theta = sum
+    // over targets a with bit targets[a] of i set, and coupled qubits c with
+    // bit couple_q[c] of i set, of couple[a * n_couple + c].
+    int n_couple = 0;
+    int couple_q[SV_MAX_QUBITS] = {};
+    double* couple = nullptr;
 };
 
 struct sv_fused_s {
@@ -159,6 +166,10 @@ void pack_matrix(sv_dtype_t dt, int n, int k, int n_controls, const double* m, i
 
 // psi: amplitudes; mat: device copy of the packed matrix; desc: the sweep.
 void launch_apply(sv_handle_s* h, sv_dtype_t dt, void* psi, const void* mat, const GateDesc& desc);
+// The same for a block of coupled fusion: couple is the device copy of its
+// phase coupling (a CoupleDev, sv_tile.h), applied before the matrix.
+void launch_apply_coupled(sv_handle_s* h, sv_dtype_t dt, void* psi, const void* mat, const void* couple,
+                          const GateDesc& desc);
 
 // Generalized permutation gate G = D P (diagonal when has_perm is false):
 // device table size and packing (adjoint folded in), and the sweep.

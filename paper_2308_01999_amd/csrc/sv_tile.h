@@ -35,6 +35,21 @@ struct TileArgs {
 // take tiles far apart.  Host only.
 TileArgs make_tile_args(const GateDesc& d, int n, int tb, int cu_count, int spread_lo, bool strided);
 
+// Phase coupling of a block (coupled fusion): before the block's
+// matrix, the amplitude at index i is multiplied by exp(i pi theta(i)),
+// theta(i) = sum over the block's matrix bits a set in i of
+// sum over the coupled qubits c set in i of phase[a][c] (in units of pi).
+// A group's amplitudes share every bit outside the block, so per group
+// theta is a sum of per-bit terms L_a: the amplitude at matrix column col
+// gets exp(i pi sum_{a in col} L_a).
+struct CoupleDev {
+    int32_t n;                                     // coupled qubits
+    int32_t k;                                     // the block's targets
+    int32_t q[SV_MAX_QUBITS];                      // coupled index bits
+    int32_t t[SV_MAX_TARGETS];                     // target index bits (matrix bit order)
+    double phase[SV_MAX_TARGETS * SV_MAX_QUBITS];  // [a * SV_MAX_QUBITS + c], units of pi
+};
+
 namespace tile {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -182,7 +197,33 @@ __device__ __forceinline__ double wave_sum_f64(double v)
     return v;
 }
 
-// complex64 pair (i, i + 1) of the state |0..0> starting at global index i
+// L_a (units of pi, reduced to [-1, 1]) of the group whose base index (block
+// bits zero) is g.  Sums in a fixed order, exact selection of terms.
+__device__ __forceinline__ void couple_terms(const CoupleDev* __restrict__ cp, uint64_t g, double* L)
+{
+#pragma unroll
+    for (int a = 0; a < 5; ++a) L[a] = 0.0;
+    const int n = cp->n;
+    for (int c = 0; c < n; ++c) {
+        const double b = double((g >> cp->q[c]) & 1);
+#pragma unroll
+        for (int a = 0; a < 5; ++a) L[a] = fma(b, cp->phase[a * SV_MAX_QUBITS + c], L[a]);
+    }
+#pragma unroll
+    for (int a = 0; a < 5; ++a) L[a] -= 2.0 * rint(0.5 * L[a]);
+}
+
+__device__ __forceinline__ float2 cmulf(const float2 x, const float2 y)
+{
+    return float2{x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x};
+}
+
+__device__ __forceinline__ float2 cmulf_conj(const float2 x, const float2 y)
+{
+    return float2{x.x * y.x + x.y * y.y, x.y * y.x - x.x * y.y};
+}
+
+// complex64 pair (i, i + 1) of the state |0..0> starting at global index i// complex64 pair (i, i + 1) of the state |0..0> starting at global index i
 __device__ __forceinline__ float4 basis0_pair(uint64_t i) { return i == 0 ? float4{1.f, 0.f, 0.f, 0.f} : float4{}; }
 
 // The complex64 five-qubit tile sweep of workgroup `wg` (its tiles_per_wg
@@ -193,11 +234,12 @@ __device__ __forceinline__ float4 basis0_pair(uint64_t i) { return i == 0 ? floa
 // Re M, A_1 = Im M, A_2 = Re M + Im M), the next tile's loads in flight
 // meanwhile.  mats: the packed A operands (3 x 64 lanes x 4 float4); lds:
 // NT * kTileVecs float4 of LDS; amat: kK5AParts * 64 * 4 float4 of LDS.
-// FIRST: the input is the basis state |0..0>, which is not read.
-template <int NT, bool FIRST>
+// FIRST: the input is the basis state |0..0>, which is not read.  COUPLED:
+// the block's phase coupling cp multiplies each group's inputs first.
+template <int NT, bool FIRST, bool COUPLED = false>
 __device__ __forceinline__ void tile_c64_k5_sweep(float2* __restrict__ psi, const float4* __restrict__ mats,
                                                   const TileArgs& a, uint64_t wg, float4* lds, float4* amat,
-                                                  const ZSums& zs)
+                                                  const ZSums& zs, const CoupleDev* __restrict__ cp = nullptr)
 {
     const uint64_t t0 = wg * a.tiles_per_wg;
     if (t0 >= a.n_tiles) return;
@@ -230,6 +272,34 @@ __device__ __forceinline__ void tile_c64_k5_sweep(float2* __restrict__ psi, cons
         SV_REP8(SV_STAGE)
 #undef SV_STAGE
         __syncthreads();
+        if constexpr (COUPLED) {
+            // the phase coupling, in LDS on the 16 amplitudes this lane will
+            // gather (so no barrier is needed), before the next tile's loads
+            // are issued (fewer live registers): lane (col, half) owns columns 2j + half of its
+            // group, whose tile-local base is pb.  The factors walk j in
+            // Gray-code order, one multiplication (or division) per step.
+            const uint64_t g = base + deposit_bits(uint32_t(pb >> a.L), a.hi_pos, a.n_hi) +
+                               uint64_t(pb & ((1 << a.L) - 1));
+            double L[5];
+            couple_terms(cp, g, L);
+            float2 e[5];
+#pragma unroll
+            for (int b = 0; b < 5; ++b) {
+                float sn, cs;
+                sincospif(float(L[b]), &sn, &cs);
+                e[b] = float2{cs, sn};
+            }
+            float2 v = half ? e[0] : float2{1.f, 0.f};
+            float2* y = &lds2[lds_swz(pin)];
+            *y = cmulf(*y, v);
+#pragma unroll
+            for (int s = 1; s < 16; ++s) {
+                const int j = s ^ (s >> 1), b = __builtin_ctz(s);
+                v = ((j >> b) & 1) ? cmulf(v, e[b + 1]) : cmulf_conj(v, e[b + 1]);
+                y = &lds2[lds_swz(pin + a.lds_off[2 * j])];
+                *y = cmulf(*y, v);
+            }
+        }
         uint64_t nbase = 0;
         if (t + 1 < t1) {
             nbase = tile_base(t + 1, a);

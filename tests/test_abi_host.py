@@ -1,6 +1,7 @@
 """CPU checks of libsv: the shared library loads and exports every entry
 point that include/sv.h declares, and its host logic (the gate table and gate
 fusion) is right.  No compute call touches a GPU here."""
+import json
 import math
 import os
 import re
@@ -212,6 +213,74 @@ def test_diagonal_fusion_cuts_qft_sweeps(P):
     gates = W.qft(30)
     dense, both = P.fuse(gates, 5).count, P.fuse(gates, 5, 10).count
     assert both < 0.6 * dense
+
+
+def _apply_coupled_with_oracle(n, blocks, couplings, basis=0):
+    # each block: its phase coupling (as two-qubit controlled phases between
+    # a block qubit and a coupled qubit, applied by the oracle), then its
+    # matrix
+    psi = oracle.basis_state(n, basis)
+    for (targets, m), (cq, ph) in zip(blocks, couplings):
+        for a, t in enumerate(targets):
+            for c, q in enumerate(cq):
+                if ph[a, c] != 0.0:
+                    oracle.apply(psi, np.diag([1.0, 1.0, 1.0, np.exp(1j * ph[a, c])]), (t, q))
+        oracle.apply(psi, m, targets)
+    return psi
+
+
+@pytest.mark.parametrize("kmax", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("circuit", ["qft", "diagheavy", "cxcp", "brickwork", "mirror"])
+def test_coupled_fusion_equals_unfused(P, kmax, circuit):
+    # blocks of coupled fusion applied in order (phase coupling, then
+    # matrix) equal the unfused circuit from a random basis state; every
+    # block is unitary on at most kmax qubits and couples only qubits outside
+    # it
+    n = 10
+    gates = {"qft": lambda: W.qft(n), "diagheavy": lambda: W.diagonal_heavy(n, 90, 7 * kmax),
+             "cxcp": lambda: W.random_cx_cp(n, 6, kmax), "brickwork": lambda: W.brickwork(n, 6, kmax),
+             "mirror": lambda: W.random_cx_cp(n, 4, 3) + W.inverse(W.random_cx_cp(n, 4, 3))}[circuit]()
+    x = W.random_basis_state(n, kmax)
+    ref = oracle.run(n, gates, basis=x)
+    f = P.fuse(gates, kmax, coupled=True)
+    blocks, couplings = f.blocks(), f.couplings()
+    f.free()
+    for (targets, m), (cq, ph) in zip(blocks, couplings):
+        assert list(targets) == sorted(targets)
+        assert len(targets) <= max(kmax, 3 if circuit == "diagheavy" else 2)
+        assert m.ndim == 2
+        np.testing.assert_allclose(m @ m.conj().T, np.eye(m.shape[0]), atol=1e-12)
+        assert list(cq) == sorted(cq) and not set(cq) & set(targets)
+        assert ph.shape == (len(targets), len(cq))
+    got = _apply_coupled_with_oracle(n, blocks, couplings, basis=x)
+    np.testing.assert_allclose(got, ref, atol=1e-12)
+
+
+def test_coupled_fusion_of_the_qft_is_as_tight_as_table_ii(P):
+    # Table II fuses the 33-qubit QFT (577 gates) into 18 gates with a fused
+    # size of 4 or 5; coupled fusion at 5 needs no more: seven dense blocks
+    # of five H with their phases (the phases to earlier qubits as
+    # couplings) and the final swaps two by two
+    counts = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_gate_counts.json")))
+    gates = W.qft(33)
+    assert len(gates) == counts["qft"]["gates"]
+    f = P.fuse(gates, 5, coupled=True)
+    assert f.count <= counts["qft"]["fused_1gpu"]
+    assert P.fuse(gates, 5).count > 2 * f.count
+    f.free()
+
+
+def test_coupled_fusion_keeps_non_phase_diagonals_in_blocks(P):
+    # a diagonal gate whose entries are not all of modulus one is not a
+    # phase and is never deferred: it stays a dense gate of its block
+    d = np.diag([1.0, 0.5])
+    gates = [("mat", (0,), np.diag(np.exp([0.3j, 1.1j]))), ("mat", (1,), d), ("h", (1,), ()),
+             ("cz", (0, 1), ()), ("mat", (0, 1), np.diag([1.0, 1.0, 0.2, 1.0]))]
+    ref = oracle.run(2, gates, basis=3)
+    f = P.fuse(gates, 1, coupled=True)
+    got = _apply_coupled_with_oracle(2, f.blocks(), f.couplings(), basis=3)
+    f.free()
+    np.testing.assert_allclose(got, ref, atol=1e-13)
 
 
 def test_diagonal_fusion_rejects_bad_sizes(P):
