@@ -690,6 +690,20 @@ def large_leg(P, W, torch, H):
                    "fused_gate_GBps": round(f.count * sweep / (sum(times) * 1e-3) / 1e9, 1),
                    "block_sizes": by_k, "norm_after": nrm}
         f.free()
+        # the same circuit and the QFT of a basis state with coupled fusion
+        # (controlled phases carried as couplings of the dense blocks)
+        for label, g in (("cxcp_coupled", gates), ("qft_coupled", W.qft(n))):
+            fc = P.fuse(g, 5, coupled=True)
+            P.sv_set_basis_state(st.s, W.random_basis_state(n, 0))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(H.stream)
+            P.sv_apply_fused(st.s, fc.f)
+            e1.record(H.stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            out[dt][label] = {"gates": len(g), "fused_blocks": fc.count, "apply_ms": round(ms, 1),
+                              "GBps": round(fc.count * sweep / (ms * 1e-3) / 1e9, 1)}
+            fc.free()
         st.close()
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
