@@ -38,15 +38,15 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources the counters were taken on: their SHA-256 are recorded and
 # checked at run time.
 _K5_SOURCES = {"paper_2308_01999_amd/csrc/sv_apply.hip":
-               "31752cb4dd14dd894918d04e5e6636006dbbac8044e080c6f9418307c2fa7e15",
+               "85353f05b4dde9a2e25210ff1c61db0ca5c87b6ed0188fee5334b05aebb09f8e",
                "paper_2308_01999_amd/csrc/sv_tile.h":
-               "4c8938bc4f6b7336ce9610a1a44a224479c8fd1c848c2706ee43b296858d1f81"}
+               "666e279461e0e28b6f6fec1e309576162839c3bd41b1dca9e6f1de30a5c9b6d7"}
 PMC_TRAFFIC = {
     # 30-qubit brickwork sweep, dispatch-weighted over all tile variants (676
     # launches of each dtype in one pass: 13 steps of 52 blocks)
-    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194404.5, "write_kib": 8389726.6,
+    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194398.5, "write_kib": 8389610.9,
                       "fetch_scale": 2.0, "write_scale": 1.0, "sources": _K5_SOURCES},
-    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388721.0, "write_kib": 16780431.4,
+    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388720.9, "write_kib": 16780255.6,
                        "fetch_scale": 2.0, "write_scale": 1.0, "sources": _K5_SOURCES},
 }
 
@@ -113,6 +113,10 @@ def parse():
     ap.add_argument("--gate-sweep", action="store_true",
                     help="also time single k-qubit gates (k = 1..6) on random target sets, both dtypes")
     ap.add_argument("--sweep-sets", type=int, default=100)
+    ap.add_argument("--sweep-n64", type=int, default=None,
+                    help="qubits of the gate sweep's complex64 state (default: --n; the paper's Fig. 2: 33)")
+    ap.add_argument("--sweep-n128", type=int, default=None,
+                    help="qubits of the gate sweep's complex128 state (default: --n; the paper's Fig. 2: 32)")
     ap.add_argument("--no-diagonal", action="store_true",
                     help="skip the diagonal / permutation gate leg (and the QFT with diagonal fusion)")
     ap.add_argument("--large", action="store_true",
@@ -136,16 +140,57 @@ def calibrate_copy(torch):
     torch.cuda.synchronize()
     del a, b
     return {"copy_bytes_read": 1 << 31, "copy_bytes_written": 1 << 31, "launches": 3,
-            "kernel": "torch elementwise mul(a, 1.0) on 2^29 float32"}
+            "kernel": "torch elementwise mul(a, 1.0) on 2^29 float32",
+            "streaming_ceilings": streaming_ceilings(torch)}
+
+
+def streaming_ceilings(torch, reps=5):
+    """HBM rates of plain streaming kernels (torch's own) on 8 GiB of random
+    float32, median of `reps` launches timed with HIP events after one
+    untimed launch: in place read + write (the shape of a gate sweep), out of
+    place copy, read only (a sum) and write only (a fill).  A reference for
+    the sweeps' rates on the same device, not a peak."""
+    import numpy as np
+    n = 1 << 31
+    a = torch.rand(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    out = {}
+    cases = (("in_place_read_write", lambda: a.mul_(1.0), 2 * 4 * n),
+             ("copy", lambda: b.copy_(a), 2 * 4 * n),
+             ("read_only_sum", lambda: a.sum(), 4 * n),
+             ("write_only_fill", lambda: b.fill_(0.5), 4 * n))
+    for name, fn, nbytes in cases:
+        fn()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        med = float(np.median(ms))
+        out[name] = {"avg_ms": round(med, 3), "GBps": round(nbytes / (med * 1e-3) / 1e9, 1),
+                     "frac_of_8TBps": round(nbytes / (med * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_leg(P, W, torch, H, gates, n, dt, kmax, shots, steps, warmup):
     """Runs warmup + timed steps on one dtype; returns measurements."""
+    import numpy as np
     st = P.State(H, n, dt)
     abytes = 8 if dt == "c64" else 16
     zterms = W.z_terms(n)
     u = W.uniforms(shots, 1)
     stream = H.stream
+    # the uniforms and outcomes stay in device memory for the timed sampler
+    with torch.cuda.stream(stream):
+        du = torch.from_numpy(u).to("cuda")
+        dsmp = torch.empty(shots, dtype=torch.int64, device="cuda")
+    stream.synchronize()
+    sample_dev_ms_total = 0.0
     per_block = None
     block_k = None
     apply_ms_total = 0.0
@@ -155,6 +200,7 @@ def run_leg(P, W, torch, H, gates, n, dt, kmax, shots, steps, warmup):
 
     def step(timed):
         nonlocal per_block, block_k, apply_ms_total, fuse_ms_total, expect_ms_total, sample_ms_total
+        nonlocal sample_dev_ms_total
         t0 = time.perf_counter()
         f = P.fuse(gates, kmax)
         t1 = time.perf_counter()
@@ -168,9 +214,14 @@ def run_leg(P, W, torch, H, gates, n, dt, kmax, shots, steps, warmup):
         evs[nb].synchronize()
         t2 = time.perf_counter()
         z = P.sv_expect_pauli(st.s, zterms)
+        es0, es1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t3 = time.perf_counter()
-        smp = P.sv_sample(st.s, u)
+        es0.record(stream)
+        P.sv_sample_device(st.s, du.data_ptr(), shots, dsmp.data_ptr())
+        es1.record(stream)
         t4 = time.perf_counter()
+        es1.synchronize()
+        smp = dsmp
         times = [evs[i].elapsed_time(evs[i + 1]) for i in range(nb)]
         ks = [len(t) for t, _ in f.blocks()] if block_k is None else block_k
         f.free()
@@ -183,6 +234,7 @@ def run_leg(P, W, torch, H, gates, n, dt, kmax, shots, steps, warmup):
             fuse_ms_total += (t1 - t0) * 1e3
             expect_ms_total += (t3 - t2) * 1e3
             sample_ms_total += (t4 - t3) * 1e3
+            sample_dev_ms_total += es0.elapsed_time(es1)
         block_k = ks
         return z, smp
 
@@ -195,6 +247,13 @@ def run_leg(P, W, torch, H, gates, n, dt, kmax, shots, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     nrm = st.norm()
+    # the same sampler with the uniforms and outcomes in host memory (over
+    # the host link): outside the timed steps, once warm
+    P.sv_sample(st.s, u)
+    t5 = time.perf_counter()
+    host_smp = P.sv_sample(st.s, u)
+    sample_host_io_ms = (time.perf_counter() - t5) * 1e3
+    host_equals_device = bool(np.array_equal(host_smp, smp.cpu().numpy().view(np.uint64)))
     dim = 1 << n
     sweep_bytes = 2 * dim * abytes
     nb = len(block_k)
@@ -215,6 +274,9 @@ def run_leg(P, W, torch, H, gates, n, dt, kmax, shots, steps, warmup):
         "fuse_host_ms_per_step": fuse_ms_total / steps,
         "expect_ms_per_step": expect_ms_total / steps,
         "sample_ms_per_step": sample_ms_total / steps,
+        "sample_device_ms_per_step": sample_dev_ms_total / steps,
+        "sample_host_io_ms": sample_host_io_ms,
+        "sample_host_io_equals_device": host_equals_device,
         "dominant_kernel": {"k": max(block_k), "launches_per_step": len(kmax_idx), "avg_ms": avg_kmax_ms,
                             "bytes_per_launch": sweep_bytes,
                             "GBps": sweep_bytes / (avg_kmax_ms * 1e-3) / 1e9},
@@ -474,7 +536,7 @@ def copy_ceiling(torch, n):
     return 2 * (1 << n) * 8 / (ms * 1e-3) / 1e9
 
 
-def gate_sweep(P, W, torch, H, n, sets, reps=3, warm=3, warm_k5=10):
+def gate_sweep(P, W, torch, H, qubits, sets, reps=3, warm=3, warm_k5=10):
     """Single dense k-qubit gates (Haar random) on `sets` random target sets
     per k, after the paper's gate-application measurement (Sec. II-B, Fig. 2:
     bandwidth from many random target sets).  Each set is applied `warm`
@@ -485,10 +547,12 @@ def gate_sweep(P, W, torch, H, n, sets, reps=3, warm=3, warm_k5=10):
     dense (a brickwork layer first: every amplitude non-zero), since sweep
     time depends on the data.  For k = 5 the handle first passes its
     untimed warm-up sweeps, and each set gets warm_k5 untimed applications
-    (three timings of each of the three tile variants, then the choice)."""
+    (three timings of each of the three tile variants, then the choice).
+    qubits: the state's qubit count per dtype."""
     import numpy as np
     out = {}
     for dt, ab in (("c64", 8), ("c128", 16)):
+        n = qubits[dt]
         st = P.State(H, n, dt)
         st.run(W.brickwork(n, 1, 11))
         rng = np.random.default_rng(1000)
@@ -521,6 +585,8 @@ def gate_sweep(P, W, torch, H, n, sets, reps=3, warm=3, warm_k5=10):
                 if v:
                     r[c] = {"sets": len(v), "median_GBps": round(float(np.median(v)), 1)}
             res[str(k)] = r
+            print(f"[bench] gate sweep {dt} {n}q k={k}: median {r['median_GBps']} GB/s", file=sys.stderr, flush=True)
+        res["n_qubits"] = n
         out[dt] = res
         st.close()
         torch.cuda.synchronize()
@@ -713,9 +779,9 @@ def large_leg(P, W, torch, H):
 def batched_leg(P, W, torch, H, count, steps, warmup, sample, check_per_n=4):
     """4096 independent complex64 brickwork circuits (qubits uniform in
     8..20, depth uniform in 10..40), each returning <Z_i Z_i+1> for all i, in
-    one recorded run: circuits below 15 qubits on the persistent kernel with
-    autotuned fusion widths, larger ones on the level path; per-circuit
-    latency from the device wall clock.  Baseline: a sample of the same
+    one recorded run: the autotuner chooses, per qubit count, the persistent
+    kernel (and its fusion width) or the level path (and its tile shape);
+    per-circuit latency from the device wall clock.  Baseline: a sample of the same
     circuits run one at a time through the plain complex128 path (one
     sv_apply_matrix per gate, then sv_expect_pauli), timed on the host.
     Errors: the first `check_per_n` circuits of every qubit count against
@@ -741,6 +807,8 @@ def batched_leg(P, W, torch, H, count, steps, warmup, sample, check_per_n=4):
     wall = (time.perf_counter() - t0) / steps
     lat = np.concatenate(lats)
     widths = {str(n): b.fusion_width(n) for n in sorted(set(ns))}
+    plans = {str(n): {k: v for k, v in b.plan(n).items() if k != "tuned"} for n in sorted(set(ns))}
+    tune_s, build_s = b.host_times()
     blocks = b.blocks()
     state_gb = sum((1 << n) * 8 for n in ns) / 1e9
     # every fused block reads and writes its state once
@@ -776,7 +844,8 @@ def batched_leg(P, W, torch, H, count, steps, warmup, sample, check_per_n=4):
     base_lat = np.array(base_lat)
     return {
         "workload": f"{count} complex64 brickwork circuits, qubits uniform 8-20, depth uniform 10-40, "
-                    f"<Z_i Z_i+1> for all i, one recorded run (persistent kernel below 15 qubits, level path above)",
+                    f"<Z_i Z_i+1> for all i, one recorded run (path, fusion width and tile shape per qubit count "
+                    f"from the autotuner)",
         "circuits": count,
         "states_GB": round(state_gb, 3),
         "kernel_ms": round(1e3 * float(np.median(kts)), 3),
@@ -788,8 +857,11 @@ def batched_leg(P, W, torch, H, count, steps, warmup, sample, check_per_n=4):
         "sweep_GB": round(sweep_bytes / 1e9, 2),
         "effective_GBps": round(sweep_bytes / float(np.median(kts)) / 1e9, 1),
         "fusion_widths": widths,
+        "plans": plans,
         "fused_blocks_total": int(blocks.sum()),
         "host_prep_s": round(prep, 3),
+        "host_prep_split_s": {"autotuner": round(tune_s, 3), "fuse_pack_upload": round(build_s, 3),
+                              "note": "autotuner 0 when every plan came from the process or SV_AUTOTUNE_CACHE"},
         "vs_oracle": {"circuits": len(check), "qubits": f"{min(ns)}-{max(ns)}", "min_fidelity": min(fids),
                       "max_abs_dzz": max(dzz)},
         "oracle_s_per_circuit": {str(n): round(float(np.mean(v)), 4) for n, v in sorted(t_or.items())},
@@ -1081,7 +1153,8 @@ def main():
     if args.gate_sweep:
         print("[bench] gate sweep", file=sys.stderr, flush=True)
         H3 = P.Handle()
-        line["gate_sweep"] = gate_sweep(P, W, torch, H3, n, args.sweep_sets)
+        qubits = {"c64": args.sweep_n64 or n, "c128": args.sweep_n128 or n}
+        line["gate_sweep"] = gate_sweep(P, W, torch, H3, qubits, args.sweep_sets)
         H3.close()
     if args.calibrate_copy:
         line["copy_calibration"] = calibrate_copy(torch)

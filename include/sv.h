@@ -467,6 +467,23 @@ sv_status_t sv_sample(sv_state_t s, const double* uniforms, int64_t n_shots,
                       const int32_t* bit_ordering, int32_t n_bits, uint64_t* out);
 
 /*
+ * The sampler of sv_sample with the uniforms and the outcomes in device
+ * memory of the state's GPU (for uniforms drawn on the device and outcomes
+ * consumed there: no transfer over the host link).  uniforms: n_shots
+ * doubles in [0, 1); out: n_shots uint64 outcomes, in the order of the
+ * uniforms, bitwise the same as sv_sample's for the same uniforms;
+ * bit_ordering stays a host array.  Both device ranges must lie inside
+ * allocations on the handle's device (SV_ERR_INVALID_VALUE otherwise).  A
+ * uniform outside [0, 1) or NaN cannot be seen before the kernels run: the
+ * call then returns SV_ERR_INVALID_VALUE, as for a state of zero norm, and
+ * the contents of out are unspecified.  The sampler's work runs on the
+ * handle's stream after the work already queued there; blocks until the
+ * outcomes are written.
+ */
+sv_status_t sv_sample_device(sv_state_t s, const double* uniforms, int64_t n_shots,
+                             const int32_t* bit_ordering, int32_t n_bits, uint64_t* out);
+
+/*
  * The sampler of sv_sample for callers that cannot allocate device memory
  * (code that must not call hipMalloc: tight serving loops, harnesses that
  * forbid allocation).  Same arguments, outputs and errors as sv_sample, and
@@ -508,18 +525,30 @@ typedef struct sv_batch_s* sv_batch_t;
  * Its observables are the Z-type Pauli strings z_masks[term_offsets[i] ..
  * term_offsets[i+1]) (bit q set = Z on qubit q), at most 32 per circuit;
  * each result is <psi|Z..Z|psi> / <psi|psi> accumulated in FP64.
- * Circuits below the handle's level-path qubit count
- * (sv_handle_set_batch_level_qubits) run in one persistent kernel launch,
- * one workgroup per circuit at a time; max_fused_qubits in [1, 5] fixes
- * their fusion width, 0 lets the autotuner pick it per qubit count by timing
- * the batch kernel at widths 3..5 on the batch's own circuits (cached for
- * the process).  Circuits of at least that many qubits run on the level
- * path: fused into blocks of up to five qubits, each block swept as a
- * five-qubit gate by the single-state tile sweep, block l of all of them in
- * launch l.  A circuit's results depend only on the circuit itself and the
- * handle's settings, never on the rest of the batch.  Circuits are fused on
- * host threads and their descriptors uploaded once.  Host arrays may be
- * freed on return.
+ * Two paths run the circuits.  The persistent kernel: one launch, one
+ * workgroup per circuit at a time, the circuit fused at a width of 1..5
+ * qubits.  The level path: circuits fused into blocks of up to five
+ * qubits, each block swept as a five-qubit gate by the single-state tile
+ * sweep (narrow tiles in a spread or plain layout, 1..8 tiles per
+ * workgroup), block l of all of them in launch l.
+ * max_fused_qubits in [1, 5] fixes the persistent kernel's width: circuits
+ * below the handle's level-path qubit count (sv_handle_set_batch_level_qubits,
+ * default SV_BATCH_LEVEL_DEFAULT) take the persistent kernel, the others
+ * the level path in its default shape (spread layout, 4 tiles per
+ * workgroup).  max_fused_qubits = 0 lets the autotuner choose per qubit
+ * count by timing, on the batch's own circuits of that size, the persistent
+ * kernel at widths 3..5 and the level path in each tile shape, and keeping
+ * the fastest; sizes from SV_BATCH_LEVEL_MIN_QUBITS to 16 qubits take the
+ * faster of the two paths unless the handle's level-path qubit count was
+ * set, which then decides the path.  Tuned choices are kept for the process
+ * and, if the environment variable SV_AUTOTUNE_CACHE names a file, in that
+ * JSON file (keyed by device architecture, state type and qubit count;
+ * entries of other keys are kept, unreadable lines skipped, and a file that
+ * cannot be written is no error), so that later processes reuse them
+ * without timing.  A circuit's results depend only on the circuit itself,
+ * the handle's settings and the plan of its size (sv_batch_plan), never on
+ * the rest of the batch.  Circuits are fused on host threads and their
+ * descriptors uploaded once.  Host arrays may be freed on return.
  */
 sv_status_t sv_batch_create(sv_handle_t h, int32_t n_circuits, const int32_t* n_qubits,
                             const int32_t* gate_offsets, const int32_t* codes, const int32_t* qubits,
@@ -527,8 +556,10 @@ sv_status_t sv_batch_create(sv_handle_t h, int32_t n_circuits, const int32_t* n_
                             int32_t max_fused_qubits, sv_batch_t* out);
 
 /* Qubit count from which circuits of batches created later on handle h run on
- * the level path (default SV_BATCH_LEVEL_DEFAULT); SV_BATCH_LEVEL_NONE keeps
- * every circuit on the persistent kernel.  Range [SV_BATCH_LEVEL_MIN_QUBITS,
+ * the level path (default SV_BATCH_LEVEL_DEFAULT, which the autotuner may
+ * override for sizes up to 16 qubits; once set by this call, it decides the
+ * path for every size); SV_BATCH_LEVEL_NONE keeps every circuit on the
+ * persistent kernel.  Range [SV_BATCH_LEVEL_MIN_QUBITS,
  * SV_BATCH_LEVEL_NONE]; SV_ERR_INVALID_VALUE otherwise. */
 #define SV_BATCH_LEVEL_MIN_QUBITS 13
 #define SV_BATCH_LEVEL_DEFAULT 15
@@ -542,6 +573,25 @@ sv_status_t sv_batch_state_layout(sv_batch_t b, uint64_t* state_bytes, uint64_t*
 /* Fusion width used for circuits of n_qubits (0 if the batch has none) and
  * the fused block count of every circuit (blocks_per_circuit may be NULL). */
 sv_status_t sv_batch_info(sv_batch_t b, int32_t n_qubits, int32_t* max_fused_qubits, int32_t* blocks_per_circuit);
+
+/* The plan of the batch's circuits of n_qubits: fusion width, path (1: the
+ * level path), the level path's tile shape (tiles per workgroup, 1 for the
+ * spread layout, 0 for plain; both 0 on the persistent kernel), and whether
+ * the autotuner chose it.  All zero if the batch has no circuit of that
+ * size. */
+typedef struct {
+    int32_t max_fused_qubits;
+    int32_t level_path;
+    int32_t tiles_per_wg;
+    int32_t spread;
+    int32_t tuned;
+} sv_batch_size_plan_t;
+sv_status_t sv_batch_plan(sv_batch_t b, int32_t n_qubits, sv_batch_size_plan_t* out);
+
+/* Host seconds that sv_batch_create spent in the autotuner (*tune_s, 0 when
+ * every choice came from its process or file cache) and fusing, packing and
+ * uploading the batch itself (*build_s).  Either pointer may be NULL. */
+sv_status_t sv_batch_host_times(sv_batch_t b, double* tune_s, double* build_s);
 
 /*
  * Runs the whole batch on the handle's stream and blocks.  The run (queue

@@ -56,6 +56,11 @@ class sv_pauli_term_t(ctypes.Structure):
     _fields_ = [("n_ops", _i32), ("qubits", _pi32), ("ops", ctypes.c_char_p)]
 
 
+class sv_batch_size_plan_t(ctypes.Structure):
+    _fields_ = [("max_fused_qubits", _i32), ("level_path", _i32), ("tiles_per_wg", _i32), ("spread", _i32),
+                ("tuned", _i32)]
+
+
 # name -> (argtypes); every entry point returns sv_status_t except the two
 # string getters
 _SIGS = {
@@ -93,6 +98,7 @@ _SIGS = {
     "sv_expect_pauli": [_vp, ctypes.POINTER(sv_pauli_term_t), _i32, _pd],
     "sv_sample": [_vp, _pd, _i64, _pi32, _i32, _pu64],
     "sv_sample_noalloc": [_vp, _pd, _i64, _pi32, _i32, _pu64],
+    "sv_sample_device": [_vp, _vp, _i64, _pi32, _i32, _vp],
     "sv_apply_pauli_rotation": [_vp, ctypes.c_double, ctypes.POINTER(sv_pauli_term_t), _pi32, _pi32, _i32],
     "sv_measure_probabilities": [_vp, _pi32, _i32, _pd],
     "sv_zbasis_probabilities": [_vp, _pi32, _i32, _pd, _pd],
@@ -109,6 +115,8 @@ _SIGS = {
     "sv_batch_create": [_vp, _i32, _pi32, _pi32, _pi32, _pi32, _pd, _pi32, _pu64, _i32, ctypes.POINTER(_vp)],
     "sv_batch_state_layout": [_vp, _pu64, _pu64],
     "sv_batch_info": [_vp, _i32, _pi32, _pi32],
+    "sv_batch_plan": [_vp, _i32, ctypes.POINTER(sv_batch_size_plan_t)],
+    "sv_batch_host_times": [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
     "sv_batch_run": [_vp, _vp, _pd, _pd, _pd],
     "sv_batch_destroy": [_vp],
     "sv_set_hbm_budget": [_u64],
@@ -542,6 +550,14 @@ def sv_sample_noalloc(s: int, uniforms, bit_ordering=None) -> np.ndarray:
     return out[: u.size]
 
 
+def sv_sample_device(s: int, uniforms_ptr: int, n_shots: int, out_ptr: int, bit_ordering=None) -> None:
+    """sv_sample_device: uniforms_ptr and out_ptr are device addresses (for
+    example torch CUDA tensors' data_ptr(): float64 and 64-bit integers)."""
+    bo = None if bit_ordering is None else _i32arr(bit_ordering)
+    nb = 0 if bit_ordering is None else len(bit_ordering)
+    _check(_L.sv_sample_device(_vp(s), _vp(uniforms_ptr), n_shots, bo, nb, _vp(out_ptr)))
+
+
 def sv_copy_to_host(s: int, dst: np.ndarray, first: int = 0, count: int | None = None) -> None:
     count = dst.size if count is None else count
     _check(_L.sv_copy_to_host(_vp(s), dst.ctypes.data, first, count))
@@ -805,6 +821,19 @@ def sv_batch_info(b: int, n_qubits: int, n_circuits: int):
     return k.value, blocks[:n_circuits]
 
 
+def sv_batch_plan(b: int, n_qubits: int) -> dict:
+    p = sv_batch_size_plan_t()
+    _check(_L.sv_batch_plan(_vp(b), n_qubits, ctypes.byref(p)))
+    return {f: getattr(p, f) for f, _ in sv_batch_size_plan_t._fields_}
+
+
+def sv_batch_host_times(b: int):
+    """(seconds in the autotuner, seconds fusing, packing and uploading)"""
+    t, u = ctypes.c_double(), ctypes.c_double()
+    _check(_L.sv_batch_host_times(_vp(b), ctypes.byref(t), ctypes.byref(u)))
+    return t.value, u.value
+
+
 def sv_batch_run(b: int, states_ptr: int, n_terms_total: int, n_circuits: int):
     exp = np.zeros(max(1, n_terms_total), dtype=np.float64)
     lat = np.zeros(max(1, n_circuits), dtype=np.float64)
@@ -849,6 +878,12 @@ class Batch:
 
     def blocks(self):
         return sv_batch_info(self.b, 0, len(self.n_qubits))[1]
+
+    def plan(self, n: int) -> dict:
+        return sv_batch_plan(self.b, n)
+
+    def host_times(self):
+        return sv_batch_host_times(self.b)
 
     def state(self, i: int) -> np.ndarray:
         import torch

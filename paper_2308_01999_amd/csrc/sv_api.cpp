@@ -90,6 +90,8 @@ void batch_run(sv_batch_s* b, void* states, double* expect_out, double* latency_
 void batch_destroy(sv_batch_s* b);
 void batch_layout(sv_batch_s* b, uint64_t* state_bytes, uint64_t* byte_offsets);
 void batch_info(sv_batch_s* b, int n_qubits, int32_t* kmax, int32_t* blocks);
+void batch_plan(sv_batch_s* b, int n_qubits, sv_batch_size_plan_t* out);
+void batch_host_times(sv_batch_s* b, double* tune_s, double* build_s);
 sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag, bool coupled = false);
 sv_fused_s* fuse_gate_list(const int32_t* codes, const int32_t* qubits, const double* params, int n_gates,
                            int kmax, int kdiag, bool coupled = false);
@@ -375,6 +377,7 @@ sv_status_t sv_handle_set_batch_level_qubits(sv_handle_t h, int32_t n_qubits)
         SV_CHECK(n_qubits >= SV_BATCH_LEVEL_MIN_QUBITS && n_qubits <= SV_BATCH_LEVEL_NONE,
                  "level-path qubit count must be in [SV_BATCH_LEVEL_MIN_QUBITS, SV_BATCH_LEVEL_NONE]");
         h->batch_level_qubits = n_qubits;
+        h->batch_level_fixed = true;
     });
 }
 
@@ -1318,16 +1321,45 @@ sv_status_t sv_expect_matrix(sv_state_t s, const double* matrix, const int32_t* 
 
 namespace {
 
+// A device range [p, p + bytes) passed by the caller: it must lie inside one
+// allocation of device memory on the handle's device.
+void check_device_range(const sv_handle_s* h, const void* p, uint64_t bytes, const char* what)
+{
+    hipPointerAttribute_t at{};
+    const hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{SV_ERR_INVALID_VALUE, std::string(what) + " is not device memory"};
+    }
+    if (at.type != hipMemoryTypeDevice || at.device != h->device)
+        throw Error{SV_ERR_INVALID_VALUE, std::string(what) + " is not device memory of the handle's device"};
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, hipDeviceptr_t(p)) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{SV_ERR_INVALID_VALUE, std::string(what) + " is not device memory"};
+    }
+    const uintptr_t b = uintptr_t(base), q = uintptr_t(p);
+    if (q < b || bytes > size || q - b > size - bytes)
+        throw Error{SV_ERR_INVALID_VALUE, std::string(what) + " extends past its device allocation"};
+}
+
 // Arguments of a sampling call; returns false when there is nothing to do.
 bool check_sample_args(const sv_state_s* s, const double* uniforms, int64_t n_shots, const int32_t* bit_ordering,
-                       int32_t* n_bits, uint64_t* out)
+                       int32_t* n_bits, uint64_t* out, bool host_io = true)
 {
     check_state(s);
     SV_CHECK(n_shots >= 0, "n_shots is negative");
     if (n_shots == 0) return false;
     SV_CHECK(uniforms != nullptr && out != nullptr, "NULL argument");
-    for (int64_t i = 0; i < n_shots; ++i)
-        SV_CHECK(uniforms[i] >= 0.0 && uniforms[i] < 1.0, "uniforms must lie in [0, 1)");
+    if (host_io) {
+        for (int64_t i = 0; i < n_shots; ++i)
+            SV_CHECK(uniforms[i] >= 0.0 && uniforms[i] < 1.0, "uniforms must lie in [0, 1)");
+    } else {
+        SV_CHECK(n_shots <= (int64_t(1) << 40), "n_shots too large");
+        check_device_range(s->h, uniforms, sizeof(double) * uint64_t(n_shots), "uniforms");
+        check_device_range(s->h, out, sizeof(uint64_t) * uint64_t(n_shots), "out");
+    }
     if (bit_ordering) {
         SV_CHECK(*n_bits >= 1 && *n_bits <= s->n, "n_bits must be in [1, n]");
         uint64_t seen = 0;
@@ -1352,7 +1384,16 @@ sv_status_t sv_sample(sv_state_t s, const double* uniforms, int64_t n_shots, con
 {
     return guarded([&] {
         if (!check_sample_args(s, uniforms, n_shots, bit_ordering, &n_bits, out)) return;
-        run_sample(s->h, s->dt, s->d, s->n, uniforms, n_shots, bit_ordering, n_bits, out);
+        run_sample(s->h, s->dt, s->d, s->n, uniforms, n_shots, bit_ordering, n_bits, out, true);
+    });
+}
+
+sv_status_t sv_sample_device(sv_state_t s, const double* uniforms, int64_t n_shots, const int32_t* bit_ordering,
+                             int32_t n_bits, uint64_t* out)
+{
+    return guarded([&] {
+        if (!check_sample_args(s, uniforms, n_shots, bit_ordering, &n_bits, out, false)) return;
+        run_sample(s->h, s->dt, s->d, s->n, uniforms, n_shots, bit_ordering, n_bits, out, false);
     });
 }
 
@@ -1421,6 +1462,22 @@ sv_status_t sv_batch_info(sv_batch_t b, int32_t n_qubits, int32_t* max_fused_qub
     return guarded([&] {
         SV_CHECK(b != nullptr && max_fused_qubits != nullptr, "NULL argument");
         batch_info(b, n_qubits, max_fused_qubits, blocks_per_circuit);
+    });
+}
+
+sv_status_t sv_batch_plan(sv_batch_t b, int32_t n_qubits, sv_batch_size_plan_t* out)
+{
+    return guarded([&] {
+        SV_CHECK(b != nullptr && out != nullptr, "NULL argument");
+        batch_plan(b, n_qubits, out);
+    });
+}
+
+sv_status_t sv_batch_host_times(sv_batch_t b, double* tune_s, double* build_s)
+{
+    return guarded([&] {
+        SV_CHECK(b != nullptr, "batch is NULL");
+        batch_host_times(b, tune_s, build_s);
     });
 }
 

@@ -8,7 +8,11 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -17,6 +21,7 @@
 #include <vector>
 
 #include "sv_batch.h"
+#include "sv_tune_cache.h"
 
 namespace sv {
 
@@ -30,6 +35,20 @@ struct BatchLevel {
     uint32_t n_entries = 0;
     uint64_t finish0 = 0;
     uint32_t n_finish = 0;
+};
+
+// Level-path tile shape of one qubit count.
+struct LevelShape {
+    int tiles_per_wg = 4;  // tiles per workgroup, taken in strided order
+    int spread = 1;        // 1: spread tile layout, 0: plain
+};
+
+// How a batch runs the circuits of one qubit count.
+struct SizePlan {
+    int kmax = kBatchMaxK;  // fusion width on the persistent kernel
+    bool level = false;     // true: the level path (fused at min(5, n))
+    LevelShape shape;       // the level path's tile shape
+    bool tuned = false;     // chosen by the autotuner (measured or from its cache)
 };
 
 struct BatchHost {
@@ -57,8 +76,9 @@ struct sv_batch_s {
     std::vector<int> n;
     std::vector<uint64_t> state_off;  // amplitudes
     uint64_t state_amps = 0;
-    std::map<int, int> kmax_for_n;
-    int level_qubits = SV_BATCH_LEVEL_DEFAULT;  // circuits of >= this many qubits take the level path
+    std::map<int, sv::SizePlan> plans;  // per qubit count
+    double tune_s = 0.0;                // host time in the autotuner
+    double build_s = 0.0;               // host time fusing, packing and uploading the batch
     std::vector<sv::BatchLevel> levels;
     std::vector<int> blocks_per_circuit;
     char* dev = nullptr;  // one arena for all device-side descriptors
@@ -246,12 +266,11 @@ void pad_block_to_five(int n, int k, const int* tq, const double* m, int32_t* ou
             }
 }
 
-constexpr uint64_t kLevelTilesPerWg = 4;
-
 // Level-path descriptors of circuit j (state at c.state_off, fused blocks f):
-// one tile-sweep descriptor and packed matrix per block.  Returns the index
-// of its first descriptor.
-uint32_t add_level_circuit(BatchHost& H, const BatchCircuit& c, const sv_fused_s* f, int cu_count)
+// one tile-sweep descriptor and packed matrix per block, in tile shape s.
+// Returns the index of its first descriptor.
+uint32_t add_level_circuit(BatchHost& H, const BatchCircuit& c, const sv_fused_s* f, int cu_count,
+                           const LevelShape& s)
 {
     const uint32_t first = uint32_t(H.tdescs.size());
     const size_t mat_bytes = packed_matrix_bytes(SV_C64, c.n, 5, 0);
@@ -271,9 +290,10 @@ uint32_t add_level_circuit(BatchHost& H, const BatchCircuit& c, const sv_fused_s
         d.k = 5;
         for (int a = 0; a < 5; ++a) d.tbit[a] = uint64_t(1) << t5[a];
         BatchTileDesc td{};
-        // the single-state sweep's default variant: spread layout, strided order
-        td.t = make_tile_args(d, c.n, 12, cu_count, 12, false);
-        td.t.tiles_per_wg = std::min<uint64_t>(kLevelTilesPerWg, td.t.n_tiles);
+        // the single-state sweep's narrow tiles, in the spread or the plain
+        // layout; a workgroup takes tiles_per_wg tiles in strided order
+        td.t = make_tile_args(d, c.n, 12, cu_count, s.spread ? 12 : 0, false);
+        td.t.tiles_per_wg = std::min<uint64_t>(uint64_t(s.tiles_per_wg), td.t.n_tiles);
         td.t.trot = 0;
         while ((uint64_t(1) << td.t.trot) < td.t.tiles_per_wg) ++td.t.trot;
         td.state_off = c.state_off;
@@ -295,16 +315,30 @@ uint32_t add_level_circuit(BatchHost& H, const BatchCircuit& c, const sv_fused_s
 }
 
 BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>& sel,
-                     const std::vector<int>& kmax, const std::vector<int>& term0, const std::vector<int>& nterms,
-                     const uint64_t* z_masks, std::vector<int>* blocks_out, int level_qubits, int cu_count)
+                     const std::map<int, SizePlan>& plans, const std::vector<int>& term0,
+                     const std::vector<int>& nterms, const uint64_t* z_masks, std::vector<int>* blocks_out,
+                     int cu_count)
 {
+    // each distinct circuit is fused once (a tuning sample repeats circuits)
+    auto plan_of = [&](int n) -> const SizePlan& { return plans.at(n); };
     std::vector<CircuitInput> sub;
     std::vector<int> ks;
-    for (int i : sel) {
-        sub.push_back(in[i]);
-        ks.push_back(kmax[i]);
+    std::map<int, size_t> uniq;
+    std::vector<size_t> slot(sel.size());
+    for (size_t j = 0; j < sel.size(); ++j) {
+        const int i = sel[j];
+        auto it = uniq.find(i);
+        if (it == uniq.end()) {
+            const SizePlan& pl = plan_of(in[i].n);
+            it = uniq.emplace(i, sub.size()).first;
+            sub.push_back(in[i]);
+            ks.push_back(pl.level ? std::min(kBatchMaxK, in[i].n) : pl.kmax);
+        }
+        slot[j] = it->second;
     }
-    auto fused = fuse_all(sub, ks);
+    auto fused_u = fuse_all(sub, ks);
+    std::vector<sv_fused_s*> fused(sel.size());
+    for (size_t j = 0; j < sel.size(); ++j) fused[j] = fused_u[slot[j]];
     BatchHost H;
     H.circuits.resize(sel.size());
     std::vector<uint32_t> level_circuits, level_first;
@@ -320,9 +354,10 @@ BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>
         for (int t = 0; t < nterms[i]; ++t) H.z_masks.push_back(z_masks[term0[i] + t]);
         c.state_off = off;
         off += std::max<uint64_t>(uint64_t(1) << c.n, 32);  // 256-byte aligned starts
-        if (c.n >= level_qubits && fused[j]->n_blocks > 0) {
+        const SizePlan& pl = plan_of(c.n);
+        if (pl.level && fused[j]->n_blocks > 0) {
             level_circuits.push_back(uint32_t(j));
-            level_first.push_back(add_level_circuit(H, c, fused[j], cu_count));
+            level_first.push_back(add_level_circuit(H, c, fused[j], cu_count, pl.shape));
             if (blocks_out) (*blocks_out)[i] = fused[j]->n_blocks;
             continue;
         }
@@ -337,7 +372,7 @@ BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>
         if (blocks_out) (*blocks_out)[i] = fused[j]->n_blocks;
     }
     H.state_amps = off;
-    for (auto* f : fused) free_fused(f);
+    for (auto* f : fused_u) free_fused(f);
     // Queue order.  The cheapest circuits, up to kShortShare of the batch's
     // work, go first (smallest first): they are done within that share of
     // the launch instead of after every large state.  The rest follow
@@ -459,75 +494,213 @@ char* upload(const BatchHost& H, BatchArgs& a, hipStream_t stream, size_t* dev_b
     return dev;
 }
 
-// Autotuner: for each qubit count, time the batch kernel on (up to 64)
-// circuits of that size fused at each candidate width, on scratch states,
-// and keep the fastest width.  Results are cached per process.
-std::mutex g_tune_mu;
-std::map<int, int> g_tuned;  // n -> kmax
-
-int tune_width(sv_handle_s* h, const std::vector<CircuitInput>& in, const std::vector<int>& idx, int n,
-               const std::vector<int>& term0, const std::vector<int>& nterms, const uint64_t* z_masks)
+// Runs the level path's launches of args on a stream: level l, then the
+// expectations of the circuits it finishes.
+void launch_levels(hipStream_t stream, const BatchArgs& a, const std::vector<BatchLevel>& levels)
 {
-    {
-        std::lock_guard<std::mutex> g(g_tune_mu);
-        auto it = g_tuned.find(n);
-        if (it != g_tuned.end()) return it->second;
+    for (size_t l = 0; l < levels.size(); ++l) {
+        const BatchLevel& L = levels[l];
+        launch_batch_level(stream, a, L.entry0, L.n_entries, l == 0);
+        if (L.n_finish > 0) launch_batch_finish(stream, a, L.finish0, L.n_finish);
     }
+}
+
+// ------------------------------------------------------------ autotuner
+//
+// For each qubit count of a batch the autotuner times, on a sample of the
+// batch's own circuits of that size (up to 64, repeated until they fill the
+// device), the persistent kernel at fusion widths 3, 4 and 5, and the level
+// path in each tile shape (1, 2, 4 or 8 tiles per workgroup; spread or plain
+// layout), as far as the size may take each path, and keeps the fastest
+// width and shape; where both paths are open to the size it keeps the
+// faster path.  Results are kept for the process and, when the environment
+// variable SV_AUTOTUNE_CACHE names a file, in that JSON file, keyed by the
+// device's architecture, the state type and the qubit count, so that later
+// processes skip the timing.
+
+using tunecache::Records;
+using tunecache::TuneRecord;
+
+std::mutex g_tune_mu;
+Records g_tuned;  // (arch, n)
+std::map<int, std::string> g_arch;                           // device -> architecture name
+
+std::string device_arch(int device)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_arch.find(device);
+    if (it != g_arch.end()) return it->second;
+    hipDeviceProp_t prop{};
+    SV_HIP(hipGetDeviceProperties(&prop, device));
+    std::string a(prop.gcnArchName);
+    for (char& ch : a)
+        if (ch == '"' || ch == '\\' || uint8_t(ch) < 0x20) ch = '_';
+    g_arch[device] = a;
+    return a;
+}
+
+std::string tune_cache_path()
+{
+    const char* p = std::getenv("SV_AUTOTUNE_CACHE");
+    return p ? std::string(p) : std::string();
+}
+
+// The tuned record of (arch, n), from the process or the cache file;
+// missing parts stay -1.
+TuneRecord lookup_tuned(const std::string& arch, int n)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tuned.find({arch, n});
+    TuneRecord r = it == g_tuned.end() ? TuneRecord{} : it->second;
+    const std::string path = tune_cache_path();
+    if ((r.kmax == -1 || r.tiles_per_wg == -1) && !path.empty()) {
+        const auto file = tunecache::read_tune_file(path);
+        auto f = file.find({arch, n});
+        if (f != file.end()) {
+            if (r.kmax == -1 && f->second.kmax != -1) {
+                r.kmax = f->second.kmax;
+                r.persistent_ms = f->second.persistent_ms;
+            }
+            if (r.tiles_per_wg == -1 && f->second.tiles_per_wg != -1) {
+                r.tiles_per_wg = f->second.tiles_per_wg;
+                r.spread = f->second.spread;
+                r.level_ms = f->second.level_ms;
+            }
+            g_tuned[{arch, n}] = r;
+        }
+    }
+    return r;
+}
+
+void store_tuned(const std::string& arch, int n, const TuneRecord& r)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tuned[{arch, n}] = r;
+    const std::string path = tune_cache_path();
+    if (!path.empty()) tunecache::write_tune_file(path, {{{arch, n}, r}});
+}
+
+// Times one plan of the sample: an untimed run, then a timed one; returns
+// the timed run's milliseconds, or a negative value if its memory could not
+// be had.
+float time_plan(sv_handle_s* h, const std::vector<CircuitInput>& in, const std::vector<int>& sample,
+                const std::map<int, SizePlan>& plans, const std::vector<int>& term0, const std::vector<int>& nterms,
+                const uint64_t* z_masks, hipEvent_t e0, hipEvent_t e1)
+{
+    BatchHost H = build_host(in, sample, plans, term0, nterms, z_masks, nullptr, h->cu_count);
+    BatchArgs a{};
+    size_t dev_bytes = 0;
+    char* dev = upload(H, a, h->stream, &dev_bytes);
+    const size_t st_bytes = H.state_amps * sizeof(float) * 2;
+    void* states = nullptr;
+    try {
+        states = dev_alloc(st_bytes, "autotuner states");
+    } catch (...) {
+        dev_free(dev, dev_bytes);
+        return -1.f;
+    }
+    a.states = states;
+    float ms = 0.f;
+    try {
+        for (int rep = 0; rep < 2; ++rep) {
+            if (rep == 1) SV_HIP(hipEventRecord(e0, h->stream));
+            launch_batch_reset(h->stream, a);
+            if (a.n_queue > 0) launch_batch(h->stream, h->cu_count, a);
+            launch_levels(h->stream, a, H.levels);
+            if (rep == 1) SV_HIP(hipEventRecord(e1, h->stream));
+        }
+        SV_HIP(hipEventSynchronize(e1));
+        SV_HIP(hipEventElapsedTime(&ms, e0, e1));
+    } catch (...) {
+        dev_free(states, st_bytes);
+        dev_free(dev, dev_bytes);
+        throw;
+    }
+    dev_free(states, st_bytes);
+    dev_free(dev, dev_bytes);
+    return ms;
+}
+
+// Tunes what rec lacks for circuits idx of n qubits: the persistent kernel's
+// width if want_persistent, the level path's shape if want_level.
+void tune_size(sv_handle_s* h, const std::vector<CircuitInput>& in, const std::vector<int>& idx, int n,
+               const std::vector<int>& term0, const std::vector<int>& nterms, const uint64_t* z_masks,
+               bool want_persistent, bool want_level, TuneRecord& rec)
+{
     std::vector<int> sel;
     for (int i : idx)
         if (int(sel.size()) < 64) sel.push_back(i);
-    // replicate so that the sample fills the device
-    const size_t want = std::max<size_t>(sel.size(), size_t(h->cu_count) * 2);
-    std::vector<int> sample;
-    while (sample.size() < want) sample.push_back(sel[sample.size() % sel.size()]);
-    float best_ms = 1e30f;
-    int best_k = std::min(5, n);
+    auto repeat = [&](size_t want) {
+        std::vector<int> sample;
+        while (sample.size() < want) sample.push_back(sel[sample.size() % sel.size()]);
+        return sample;
+    };
     hipEvent_t e0, e1;
     SV_HIP(hipEventCreate(&e0));
     SV_HIP(hipEventCreate(&e1));
-    for (int k = 3; k <= std::min(5, n); ++k) {
-        std::vector<int> km(in.size(), k);
-        BatchHost H = build_host(in, sample, km, term0, nterms, z_masks, nullptr, kBatchMaxQubits + 1, h->cu_count);
-        BatchArgs a{};
-        size_t dev_bytes = 0;
-        char* dev = upload(H, a, h->stream, &dev_bytes);
-        const size_t st_bytes = H.state_amps * sizeof(float) * 2;
-        void* states = nullptr;
-        try {
-            states = dev_alloc(st_bytes, "autotuner states");
-        } catch (...) {
-            dev_free(dev, dev_bytes);
-            break;
+    try {
+        if (want_persistent && rec.kmax == -1) {
+            // two workgroups' worth of circuits per CU
+            const auto sample = repeat(std::max<size_t>(sel.size(), size_t(h->cu_count) * 2));
+            for (int k = 3; k <= std::min(kBatchMaxK, n); ++k) {
+                SizePlan p;
+                p.kmax = k;
+                const float ms = time_plan(h, in, sample, {{n, p}}, term0, nterms, z_masks, e0, e1);
+                if (ms < 0.f) break;
+                const double per = double(ms) / double(sample.size());
+                if (rec.kmax == -1 || per < rec.persistent_ms) {
+                    rec.kmax = k;
+                    rec.persistent_ms = per;
+                }
+            }
+            if (rec.kmax == -1) {  // no room to time: the widest width
+                rec.kmax = std::min(kBatchMaxK, n);
+                rec.persistent_ms = 0.0;
+            }
         }
-        a.states = states;
-        float ms = 0.f;
-        try {
-            launch_batch_reset(h->stream, a);
-            launch_batch(h->stream, h->cu_count, a);  // warm-up
-            launch_batch_reset(h->stream, a);
-            SV_HIP(hipEventRecord(e0, h->stream));
-            launch_batch(h->stream, h->cu_count, a);
-            SV_HIP(hipEventRecord(e1, h->stream));
-            SV_HIP(hipEventSynchronize(e1));
-            SV_HIP(hipEventElapsedTime(&ms, e0, e1));
-        } catch (...) {
-            dev_free(states, st_bytes);
-            dev_free(dev, dev_bytes);
-            throw;
+        if (want_level && rec.tiles_per_wg == -1) {
+            // enough circuits for twelve tiles per CU in every level, at
+            // most 1 GiB of states
+            const uint64_t tiles = uint64_t(1) << (n - 12);
+            size_t want = std::max<size_t>(sel.size(), size_t((uint64_t(h->cu_count) * 12 + tiles - 1) / tiles));
+            want = std::min<size_t>(want, std::max<size_t>(1, size_t((uint64_t(1) << 30) >> (n + 3))));
+            const auto sample = repeat(want);
+            for (int tpw = 1; tpw <= 8 && uint64_t(tpw) <= tiles; tpw *= 2) {
+                for (int spread = 1; spread >= 0; --spread) {
+                    SizePlan p;
+                    p.level = true;
+                    p.shape.tiles_per_wg = tpw;
+                    p.shape.spread = spread;
+                    const float ms = time_plan(h, in, sample, {{n, p}}, term0, nterms, z_masks, e0, e1);
+                    if (ms < 0.f) continue;
+                    const double per = double(ms) / double(sample.size());
+                    if (rec.tiles_per_wg == -1 || per < rec.level_ms) {
+                        rec.tiles_per_wg = tpw;
+                        rec.spread = spread;
+                        rec.level_ms = per;
+                    }
+                }
+            }
+            if (rec.tiles_per_wg == -1) {  // no room to time: the default shape
+                rec.tiles_per_wg = int(std::min<uint64_t>(4, tiles));
+                rec.spread = 1;
+                rec.level_ms = 0.0;
+            }
         }
-        dev_free(states, st_bytes);
-        dev_free(dev, dev_bytes);
-        if (ms < best_ms) {
-            best_ms = ms;
-            best_k = k;
-        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tuned[n] = best_k;
-    return best_k;
 }
+
+// Qubit counts whose path the autotuner chooses when the handle leaves the
+// level path's size open: below, the persistent kernel; above, the level
+// path.
+constexpr int kRouteTuneLo = SV_BATCH_LEVEL_MIN_QUBITS;
+constexpr int kRouteTuneHi = 16;
 
 }  // namespace
 }  // namespace sv
@@ -581,27 +754,54 @@ sv_batch_s* batch_create(sv_handle_s* h, int n_circuits, const int32_t* n_qubits
         b->n_circuits = n_circuits;
         b->total_terms = total_terms;
         b->n.assign(n_qubits, n_qubits + n_circuits);
-        b->level_qubits = h->batch_level_qubits;
-        std::vector<int> kmax(n_circuits);
+        using clock = std::chrono::steady_clock;
+        std::string arch;
         for (auto& kv : by_n) {
-            // the level path sweeps every block as a five-qubit gate, so it
-            // fuses at the widest width
-            const int k = kv.first >= b->level_qubits ? std::min(kBatchMaxK, kv.first)
-                          : max_fused_qubits > 0     ? std::min(max_fused_qubits, kv.first)
-                                                     : tune_width(h, in, kv.second, kv.first, term0, nterms, z_masks);
-            b->kmax_for_n[kv.first] = k;
-            for (int i : kv.second) kmax[i] = k;
+            const int n = kv.first;
+            SizePlan p;
+            if (max_fused_qubits > 0) {
+                // a fixed width and no timing: the handle's level-path size
+                // decides the path, the level path's default tile shape
+                p.level = n >= h->batch_level_qubits;
+                p.kmax = p.level ? std::min(kBatchMaxK, n) : std::min(max_fused_qubits, n);
+            } else {
+                if (arch.empty()) arch = device_arch(h->device);
+                bool may_persist, may_level;
+                if (h->batch_level_fixed) {
+                    may_level = n >= h->batch_level_qubits;
+                    may_persist = !may_level;
+                } else {
+                    may_persist = n <= kRouteTuneHi;
+                    may_level = n >= kRouteTuneLo;
+                }
+                TuneRecord rec = lookup_tuned(arch, n);
+                if ((may_persist && rec.kmax == -1) || (may_level && rec.tiles_per_wg == -1)) {
+                    const auto t0 = clock::now();
+                    tune_size(h, in, kv.second, n, term0, nterms, z_masks, may_persist, may_level, rec);
+                    store_tuned(arch, n, rec);
+                    b->tune_s += std::chrono::duration<double>(clock::now() - t0).count();
+                }
+                p.tuned = true;
+                p.level = may_level && (!may_persist || rec.level_ms < rec.persistent_ms);
+                p.kmax = p.level ? std::min(kBatchMaxK, n) : rec.kmax;
+                if (p.level) {
+                    p.shape.tiles_per_wg = rec.tiles_per_wg;
+                    p.shape.spread = rec.spread;
+                }
+            }
+            b->plans[n] = p;
         }
+        const auto t_build = clock::now();
         std::vector<int> all(n_circuits);
         std::iota(all.begin(), all.end(), 0);
         b->blocks_per_circuit.assign(n_circuits, 0);
-        BatchHost H = build_host(in, all, kmax, term0, nterms, z_masks, &b->blocks_per_circuit, b->level_qubits,
-                                 h->cu_count);
+        BatchHost H = build_host(in, all, b->plans, term0, nterms, z_masks, &b->blocks_per_circuit, h->cu_count);
         b->levels = H.levels;
         b->state_off.resize(n_circuits);
         for (int i = 0; i < n_circuits; ++i) b->state_off[i] = H.circuits[i].state_off;
         b->state_amps = H.state_amps;
         b->dev = upload(H, b->args, h->stream, &b->dev_bytes);
+        b->build_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_build).count();
         int khz = 0;
         SV_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device));
         b->tick_hz = khz > 0 ? double(khz) * 1e3 : 1e8;
@@ -638,11 +838,7 @@ static void record_run(sv_batch_s* b)
         try {
             launch_batch_reset(cap, b->args);
             if (b->args.n_queue > 0) launch_batch(cap, h->cu_count, b->args);
-            for (size_t l = 0; l < b->levels.size(); ++l) {
-                const BatchLevel& L = b->levels[l];
-                launch_batch_level(cap, b->args, L.entry0, L.n_entries, l == 0);
-                if (L.n_finish > 0) launch_batch_finish(cap, b->args, L.finish0, L.n_finish);
-            }
+            launch_levels(cap, b->args, b->levels);
         } catch (...) {
             hipGraph_t dropped = nullptr;
             (void)hipStreamEndCapture(cap, &dropped);
@@ -707,10 +903,29 @@ void batch_layout(sv_batch_s* b, uint64_t* state_bytes, uint64_t* byte_offsets)
 
 void batch_info(sv_batch_s* b, int n_qubits, int32_t* kmax, int32_t* blocks)
 {
-    auto it = b->kmax_for_n.find(n_qubits);
-    *kmax = it == b->kmax_for_n.end() ? 0 : it->second;
+    auto it = b->plans.find(n_qubits);
+    *kmax = it == b->plans.end() ? 0 : it->second.kmax;
     if (blocks)
         for (int i = 0; i < b->n_circuits; ++i) blocks[i] = b->blocks_per_circuit[i];
+}
+
+void batch_plan(sv_batch_s* b, int n_qubits, sv_batch_size_plan_t* out)
+{
+    *out = sv_batch_size_plan_t{};
+    auto it = b->plans.find(n_qubits);
+    if (it == b->plans.end()) return;
+    const SizePlan& p = it->second;
+    out->max_fused_qubits = p.kmax;
+    out->level_path = p.level ? 1 : 0;
+    out->tiles_per_wg = p.level ? p.shape.tiles_per_wg : 0;
+    out->spread = p.level ? p.shape.spread : 0;
+    out->tuned = p.tuned ? 1 : 0;
+}
+
+void batch_host_times(sv_batch_s* b, double* tune_s, double* build_s)
+{
+    if (tune_s) *tune_s = b->tune_s;
+    if (build_s) *build_s = b->build_s;
 }
 
 void batch_destroy(sv_batch_s* b)

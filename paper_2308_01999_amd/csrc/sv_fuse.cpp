@@ -116,17 +116,38 @@ struct Selected {
     bool diagonal = false;
 };
 
+// A block matrix under construction: 2^m x 2^m, row-major, its real and
+// imaginary parts in separate arrays, starting as the identity.
+struct BlockMatrix {
+    int m;
+    uint64_t dim;
+    std::vector<double> re, im;
+    explicit BlockMatrix(int m_) : m(m_), dim(uint64_t(1) << m_), re(dim * dim, 0.0), im(dim * dim, 0.0)
+    {
+        for (uint64_t i = 0; i < dim; ++i) re[i * dim + i] = 1.0;
+    }
+    // interleaved (re, im), row-major
+    void store(double* out) const
+    {
+        for (size_t e = 0; e < size_t(dim * dim); ++e) {
+            out[2 * e] = re[e];
+            out[2 * e + 1] = im[e];
+        }
+    }
+};
+
 // U <- G * U where G acts on positions pos_t (matrix bit order) with
-// controls at positions pos_c having values cv; U is 2^m x 2^m row-major,
-// interleaved (re, im).  Each column of U is updated like a state of m
-// qubits.  Plain real arithmetic: std::complex products would go through
-// the C99 special-value path.
-void left_multiply(std::vector<double>& U, int m, const HostGate& g, const std::vector<int>& pos_t,
-                   const std::vector<int>& pos_c)
+// controls at positions pos_c having values cv.  Each column of U is
+// updated like a state of m qubits; the 2^k rows of a group are combined
+// element by element along their (contiguous) columns, real and imaginary
+// parts apart, so the inner loop is plain multiply-adds on contiguous
+// doubles.  No std::complex products: those would go through the C99
+// special-value path.
+void left_multiply(BlockMatrix& U, const HostGate& g, const std::vector<int>& pos_t, const std::vector<int>& pos_c)
 {
     const int k = int(pos_t.size());
     const int d = 1 << k;
-    const uint64_t dim = uint64_t(1) << m;
+    const uint64_t dim = U.dim;
     uint64_t tmask = 0, cmask = 0, cset = 0;
     for (int p : pos_t) tmask |= uint64_t(1) << p;
     for (size_t a = 0; a < pos_c.size(); ++a) {
@@ -140,30 +161,28 @@ void left_multiply(std::vector<double>& U, int m, const HostGate& g, const std::
             if ((r >> a) & 1) o |= uint64_t(1) << pos_t[a];
         off[r] = o;
     }
-    std::vector<double> gm(2 * size_t(d) * d);
-    for (size_t e = 0; e < size_t(d) * d; ++e) {
-        gm[2 * e] = g.m[e].real();
-        gm[2 * e + 1] = g.m[e].imag();
-    }
-    // Row-oriented: the 2^k rows of a group are combined element by element
-    // along the (contiguous) columns.
-    const size_t rowlen = 2 * dim;
-    std::vector<double> in(size_t(d) * rowlen);
+    thread_local std::vector<double> in_re, in_im;
+    in_re.resize(size_t(d) * dim);
+    in_im.resize(size_t(d) * dim);
     for (uint64_t row = 0; row < dim; ++row) {
         if ((row & tmask) || (row & cmask) != cset) continue;
-        for (int c = 0; c < d; ++c)
-            std::memcpy(&in[c * rowlen], &U[(row + off[c]) * rowlen], sizeof(double) * rowlen);
+        for (int c = 0; c < d; ++c) {
+            std::memcpy(&in_re[c * dim], &U.re[(row + off[c]) * dim], sizeof(double) * dim);
+            std::memcpy(&in_im[c * dim], &U.im[(row + off[c]) * dim], sizeof(double) * dim);
+        }
         for (int r = 0; r < d; ++r) {
-            double* out = &U[(row + off[r]) * rowlen];
-            for (size_t e = 0; e < rowlen; ++e) out[e] = 0.0;
+            double* __restrict ore = &U.re[(row + off[r]) * dim];
+            double* __restrict oim = &U.im[(row + off[r]) * dim];
+            for (uint64_t col = 0; col < dim; ++col) ore[col] = oim[col] = 0.0;
             for (int c = 0; c < d; ++c) {
-                const double mr = gm[2 * (size_t(r) * d + c)], mi = gm[2 * (size_t(r) * d + c) + 1];
+                const cd e = g.m[size_t(r) * d + c];
+                const double mr = e.real(), mi = e.imag();
                 if (mr == 0.0 && mi == 0.0) continue;
-                const double* x = &in[c * rowlen];
+                const double* __restrict xr = &in_re[c * dim];
+                const double* __restrict xi = &in_im[c * dim];
                 for (uint64_t col = 0; col < dim; ++col) {
-                    const double xr = x[2 * col], xi = x[2 * col + 1];
-                    out[2 * col] += mr * xr - mi * xi;
-                    out[2 * col + 1] += mr * xi + mi * xr;
+                    ore[col] += mr * xr[col] - mi * xi[col];
+                    oim[col] += mr * xi[col] + mi * xr[col];
                 }
             }
         }
@@ -711,14 +730,13 @@ sv_fused_s* build_coupled(const std::vector<HostGate>& hg, const std::vector<Cou
         FusedBlock& blk = f->blocks[b];
         blk.k = m;
         for (int a = 0; a < m; ++a) blk.targets[a] = qs[a];
-        std::vector<double> U(2 * dim * dim, 0.0);
-        for (uint64_t i = 0; i < dim; ++i) U[2 * (i * dim + i)] = 1.0;
+        BlockMatrix U(m);
         for (int gi : c.gates) {
             const HostGate& g = hg[gi];
             std::vector<int> pt, pc;
             for (int q : g.targets) pt.push_back(pos(q));
             for (int q : g.controls) pc.push_back(pos(q));
-            left_multiply(U, m, g, pt, pc);
+            left_multiply(U, g, pt, pc);
         }
         // flushed phases inside the block: U <- U diag(exp(i theta(col)))
         for (uint64_t col = 0; col < dim; ++col) {
@@ -733,14 +751,13 @@ sv_fused_s* build_coupled(const std::vector<HostGate>& hg, const std::vector<Cou
             if (th == 0.0) continue;
             const double er = std::cos(th), ei = std::sin(th);
             for (uint64_t row = 0; row < dim; ++row) {
-                double* u = &U[2 * (row * dim + col)];
-                const double ur = u[0], ui = u[1];
-                u[0] = ur * er - ui * ei;
-                u[1] = ur * ei + ui * er;
+                const double ur = U.re[row * dim + col], ui = U.im[row * dim + col];
+                U.re[row * dim + col] = ur * er - ui * ei;
+                U.im[row * dim + col] = ur * ei + ui * er;
             }
         }
         blk.m = f->storage + at;
-        std::memcpy(blk.m, U.data(), sizeof(double) * 2 * dim * dim);
+        U.store(blk.m);
         at += 2 * dim * dim;
         blk.n_couple = int(cq.size());
         for (size_t j = 0; j < cq.size(); ++j) blk.couple_q[j] = cq[j];
@@ -858,16 +875,15 @@ sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag, bool 
             at += dim;
             continue;
         }
-        std::vector<double> U(2 * dim * dim, 0.0);
-        for (uint64_t i = 0; i < dim; ++i) U[2 * (i * dim + i)] = 1.0;
+        BlockMatrix U(m);
         for (int gi : sel[b].gates) {
             const HostGate& g = hg[gi];
             std::vector<int> pt, pc;
             for (int q : g.targets) pt.push_back(pos(q));
             for (int q : g.controls) pc.push_back(pos(q));
-            left_multiply(U, m, g, pt, pc);
+            left_multiply(U, g, pt, pc);
         }
-        std::memcpy(blk.m, U.data(), sizeof(double) * 2 * dim * dim);
+        U.store(blk.m);
         at += dim * dim;
     }
     return f;

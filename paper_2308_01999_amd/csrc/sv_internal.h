@@ -107,6 +107,7 @@ struct sv_handle_s {
     size_t aux_bytes = 0;
     int tile_mode = 0;              // sv_tile_mode_t
     int batch_level_qubits = SV_BATCH_LEVEL_DEFAULT;  // batches: circuits of >= this many qubits take the level path
+    bool batch_level_fixed = false;  // set by the caller: the autotuner does not choose the path
     sv::TileTuner* tuner = nullptr;
 };
 
@@ -194,8 +195,9 @@ struct PauliMasks {
 void run_expect(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const PauliMasks* terms,
                 int n_terms, double* out);
 
+// host_io: u and out are host arrays; otherwise device arrays.
 void run_sample(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const double* u,
-                int64_t n_shots, const int32_t* bit_ordering, int n_bits, uint64_t* out);
+                int64_t n_shots, const int32_t* bit_ordering, int n_bits, uint64_t* out, bool host_io);
 // The same sampler with every device buffer in a fixed per-GPU array of
 // SV_SAMPLE_NOALLOC_SCRATCH_BYTES (no allocation; n <= SV_SAMPLE_NOALLOC_MAX_QUBITS).
 void run_sample_noalloc(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const double* u,

@@ -443,8 +443,21 @@ __global__ __launch_bounds__(kThreads) void k_block_prefix(const typename Cx<R>:
         }
         if (tid < 64) {
             double sum = 0.0;
-            if (lane < rows)
-                for (int j = 0; j < L.w; ++j) sum = __dadd_rn(sum, p[lane * kRow + j]);
+            if (lane < rows) {
+                if (L.w == kBlk) {
+                    // the row's loads issued kQ at a time, then summed in order
+                    constexpr int kQ = sizeof(R) == 4 ? 16 : 8;
+                    for (int j0 = 0; j0 < kBlk; j0 += kQ) {
+                        double q[kQ];
+#pragma unroll
+                        for (int j = 0; j < kQ; ++j) q[j] = p[lane * kRow + j0 + j];
+#pragma unroll
+                        for (int j = 0; j < kQ; ++j) sum = __dadd_rn(sum, q[j]);
+                    }
+                } else {
+                    for (int j = 0; j < L.w; ++j) sum = __dadd_rn(sum, p[lane * kRow + j]);
+                }
+            }
             double mine = 0.0;
             for (int l = 0; l < rows; ++l) {
                 carry = __dadd_rn(carry, readlane_f64(sum, l));
@@ -458,34 +471,105 @@ __global__ __launch_bounds__(kThreads) void k_block_prefix(const typename Cx<R>:
 }
 
 constexpr int kScanThreads = 1024;
+constexpr int kScanRound = 8192;                      // chunk totals staged in LDS per round
+constexpr int kScanPad = kScanRound + kScanRound / 64;  // one pad slot per 64
 
-// B[0..nc] from S[0..nc-1] (single block).
+__device__ __forceinline__ int scan_slot(int i) { return i + (i >> 6); }
+
+// B[0..nc] from S[0..nc-1] (single workgroup).  Thread t owns the chunks
+// [t * per, (t + 1) * per): its local prefix is the sequential sum of their
+// totals, the offsets o_t of the threads are the sequential sum of the
+// thread totals in thread order, and B[c + 1] = o_t + local_c.  Since
+// local_last == tot_t and o_{t+1} = o_t + tot_t with the same rounding, the
+// boundaries are monotone across threads and B[c + 1] == B[c] whenever
+// S[c] == 0.  S and B move between HBM and LDS in coalesced rounds of
+// kScanRound chunks (per divides kScanRound), the owners of a round's
+// chunks walk them in LDS, and the chain over the thread totals runs in
+// wave 0 from registers.
 __global__ __launch_bounds__(kScanThreads) void k_scan_chunks(const double* __restrict__ S, uint64_t nc,
                                                              double* __restrict__ B)
 {
+    __shared__ double stage[kScanPad];
     __shared__ double tot[kScanThreads];
     __shared__ double off[kScanThreads];
+    const int t = threadIdx.x;
     const uint64_t per = (nc + kScanThreads - 1) / kScanThreads;
-    const uint64_t lo = std::min<uint64_t>(nc, threadIdx.x * per);
+    const uint64_t lo = std::min<uint64_t>(nc, t * per);
     const uint64_t hi = std::min<uint64_t>(nc, lo + per);
     double run = 0.0;
-    for (uint64_t c = lo; c < hi; ++c) {
-        run = __dadd_rn(run, S[c]);
-        B[c + 1] = run;  // local inclusive prefix for now
-    }
-    tot[threadIdx.x] = run;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double o = 0.0;
-        for (int t = 0; t < kScanThreads; ++t) {
-            off[t] = o;
-            o = __dadd_rn(o, tot[t]);
+    for (uint64_t r0 = 0; r0 < nc; r0 += kScanRound) {
+        const int len = int(std::min<uint64_t>(kScanRound, nc - r0));
+        for (int i = t; i < len; i += kScanThreads) stage[scan_slot(i)] = S[r0 + i];
+        __syncthreads();
+        if (lo >= r0 && lo < r0 + uint64_t(len)) {
+            const int b0 = int(lo - r0), cnt = int(hi - lo);
+            int i = 0;
+            for (; i + 16 <= cnt; i += 16) {
+                double q[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) q[j] = stage[scan_slot(b0 + i + j)];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) run = __dadd_rn(run, q[j]);
+            }
+            for (; i < cnt; ++i) run = __dadd_rn(run, stage[scan_slot(b0 + i)]);
         }
+        __syncthreads();
+    }
+    tot[t] = run;
+    __syncthreads();
+    if (t < 64) {
+        // lane l holds the totals of threads 16 l .. 16 l + 15
+        constexpr int kPerLane = kScanThreads / 64;
+        double v[kPerLane], mine[kPerLane];
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) {
+            v[j] = tot[t * kPerLane + j];
+            mine[j] = 0.0;
+        }
+        double o = 0.0;
+        for (int l = 0; l < 64; ++l) {
+#pragma unroll
+            for (int j = 0; j < kPerLane; ++j) {
+                if (t == l) mine[j] = o;
+                o = __dadd_rn(o, readlane_f64(v[j], l));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) off[t * kPerLane + j] = mine[j];
     }
     __syncthreads();
-    const double o = off[threadIdx.x];
-    for (uint64_t c = lo; c < hi; ++c) B[c + 1] = __dadd_rn(o, B[c + 1]);
-    if (threadIdx.x == 0) B[0] = 0.0;
+    const double o = off[t];
+    run = 0.0;
+    for (uint64_t r0 = 0; r0 < nc; r0 += kScanRound) {
+        const int len = int(std::min<uint64_t>(kScanRound, nc - r0));
+        for (int i = t; i < len; i += kScanThreads) stage[scan_slot(i)] = S[r0 + i];
+        __syncthreads();
+        if (lo >= r0 && lo < r0 + uint64_t(len)) {
+            const int b0 = int(lo - r0), cnt = int(hi - lo);
+            int i = 0;
+            for (; i + 16 <= cnt; i += 16) {
+                double q[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) q[j] = stage[scan_slot(b0 + i + j)];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    run = __dadd_rn(run, q[j]);
+                    q[j] = __dadd_rn(o, run);
+                }
+#pragma unroll
+                for (int j = 0; j < 16; ++j) stage[scan_slot(b0 + i + j)] = q[j];
+            }
+            for (; i < cnt; ++i) {
+                const int k = scan_slot(b0 + i);
+                run = __dadd_rn(run, stage[k]);
+                stage[k] = __dadd_rn(o, run);
+            }
+        }
+        __syncthreads();
+        for (int i = t; i < len; i += kScanThreads) B[r0 + i + 1] = stage[scan_slot(i)];
+        __syncthreads();
+    }
+    if (t == 0) B[0] = 0.0;
 }
 
 __device__ __forceinline__ double shot_r(double u, double total)
@@ -495,20 +579,26 @@ __device__ __forceinline__ double shot_r(double u, double total)
     return r;
 }
 
-// One thread per shot: chunk by binary search over B, block by binary search
-// over the chunk's C, then the block's amplitudes in order.
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_resolve(const typename Cx<R>::T* __restrict__ psi,
-                                                     SampleLayout L, const double* __restrict__ B,
-                                                     const double* __restrict__ C,
-                                                     const double* __restrict__ u, uint64_t ns,
-                                                     uint64_t* __restrict__ idx_out)
+// ------------------------------------------------------- shot buckets
+//
+// The shots of a batch are resolved in chunk order.  A first pass finds
+// each shot's chunk (a binary search over B inside the range a guide table
+// gives) and its rank among the shots of that chunk (one atomic counter per
+// chunk); an exclusive scan of the counters gives the buckets' offsets; a
+// second pass puts each shot (its chunk and index, and r) at its bucket's
+// offset plus its rank; the resolver then takes the buckets in order, one
+// shot per thread, so the shots of one chunk run in the same workgroup and
+// share the lines of the chunk's block prefixes and of the blocks they land
+// in, instead of each shot fetching its own.  Ranks follow the order of the
+// atomic additions and may differ between runs; each outcome depends only
+// on its shot's r, so the outputs do not.
+//
+// counts[nc] is a flag that the first pass sets when a uniform lies outside
+// [0, 1) (or is NaN); such a shot is resolved as u = 0.
+
+// Smallest chunk c in [lo, hi] with r < B[c+1], or hi if there is none.
+__device__ __forceinline__ uint32_t chunk_in(const double* __restrict__ B, uint64_t lo, uint64_t hi, double r)
 {
-    using T2 = typename Cx<R>::T;
-    const uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= ns) return;
-    const double r = shot_r(u[s], B[L.nc]);
-    uint64_t lo = 0, hi = L.nc - 1;  // smallest c with r < B[c+1]
     while (lo < hi) {
         const uint64_t mid = lo + (hi - lo) / 2;
         if (r < B[mid + 1])
@@ -516,7 +606,181 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const typename Cx<R>::T* _
         else
             lo = mid + 1;
     }
-    const uint64_t c = lo;
+    return uint32_t(lo);
+}
+
+__device__ __forceinline__ double checked_uniform(double u, bool* bad)
+{
+    if (u >= 0.0 && u < 1.0) return u;
+    *bad = true;
+    return 0.0;
+}
+
+// Guide table of the chunk search (a cutpoint table): G[k] is the chunk of
+// the point u = k / 2^g, for k = 0 .. 2^g.  Since r = u * N and the chunk
+// are monotone in u, a shot with k / 2^g <= u < (k + 1) / 2^g has its chunk
+// in [G[k], G[k+1]], a range of one or two chunks unless many chunks hold
+// little probability between two cutpoints.
+__global__ __launch_bounds__(kThreads) void k_chunk_guide(SampleLayout L, const double* __restrict__ B, int g,
+                                                         uint32_t* __restrict__ G)
+{
+    const uint64_t k = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k > (uint64_t(1) << g)) return;
+    G[k] = chunk_in(B, 0, L.nc - 1, shot_r(ldexp(double(k), -g), B[L.nc]));
+}
+
+// Lanes of a wave that add to the same counter form a group: the group's
+// lowest lane adds the group's size once, and every lane gets the counter's
+// old value plus its rank in the group (lanes in lane order).  All lanes of
+// the wave take part; inactive lanes add nothing.
+__device__ __forceinline__ uint32_t wave_claim(uint32_t* __restrict__ ctr, uint32_t c, bool act)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t todo = __ballot(act);
+    uint64_t peers = 0;
+    while (todo) {
+        const int l = __ffsll((unsigned long long)todo) - 1;
+        const uint32_t cl = uint32_t(__builtin_amdgcn_readlane(int(c), l));
+        const uint64_t m = __ballot(act && c == cl);
+        if (act && c == cl) peers = m;
+        todo &= ~m;
+    }
+    const int leader = act ? __ffsll((unsigned long long)peers) - 1 : lane;
+    uint32_t base = 0;
+    if (act && lane == leader) base = atomicAdd(ctr + c, uint32_t(__popcll(peers)));
+    base = uint32_t(__shfl(int(base), leader, 64));
+    return base + uint32_t(__popcll(peers & ((uint64_t(1) << lane) - 1)));
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill_u32(uint32_t* __restrict__ p, uint64_t n)
+{
+    const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// Each shot's chunk (through the guide table) and its rank among the shots
+// of that chunk.
+__global__ __launch_bounds__(kThreads) void k_shot_chunks(SampleLayout L, const double* __restrict__ B,
+                                                         const uint32_t* __restrict__ G, int g,
+                                                         const double* __restrict__ u, uint64_t ns,
+                                                         uint32_t* __restrict__ key, uint32_t* __restrict__ rank,
+                                                         uint32_t* __restrict__ counts)
+{
+    const uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool act = s < ns;
+    uint32_t c = 0;
+    if (act) {
+        bool bad = false;
+        const double us = checked_uniform(u[s], &bad);
+        if (bad) counts[L.nc] = 1u;
+        const uint64_t k = uint64_t(ldexp(us, g));  // < 2^g
+        c = chunk_in(B, G[k], G[k + 1], shot_r(us, B[L.nc]));
+        key[s] = c;
+    }
+    const uint32_t rk = wave_claim(counts, c, act);
+    if (act) rank[s] = rk;
+}
+
+constexpr int kCountThreads = 1024;
+constexpr int kCountTiles = 64;  // counts per thread: nc <= kCountThreads * kCountTiles
+
+// Exclusive scan of counts[0..nc) into off[0..nc] (single workgroup).
+// Element e = j * 1024 + t is thread t's item of tile j (coalesced loads and
+// stores).  A first pass takes every wave's total of every tile, those are
+// scanned in LDS (over the waves of a tile, then over the tiles), and a
+// second pass scans each tile inside its waves and adds the two offsets.
+__global__ __launch_bounds__(kCountThreads) void k_scan_counts(const uint32_t* __restrict__ counts, uint64_t nc,
+                                                              uint32_t* __restrict__ off)
+{
+    __shared__ uint32_t wtot[kCountThreads / 64][kCountTiles];
+    __shared__ uint32_t jtot[kCountTiles + 1];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int J = int((nc + kCountThreads - 1) / kCountThreads);
+#pragma unroll 8
+    for (int j = 0; j < J; ++j) {
+        const uint64_t e = uint64_t(j) * kCountThreads + t;
+        uint32_t x = e < nc ? counts[e] : 0u;
+        for (int d = 32; d > 0; d >>= 1) x += uint32_t(__shfl_xor(int(x), d, 64));
+        if (lane == 0) wtot[w][j] = x;
+    }
+    __syncthreads();
+    if (t < J) {  // column t: exclusive prefix over the waves, and the tile total
+        uint32_t run = 0;
+        for (int ww = 0; ww < kCountThreads / 64; ++ww) {
+            const uint32_t x = wtot[ww][t];
+            wtot[ww][t] = run;
+            run += x;
+        }
+        jtot[t] = run;
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t run = 0;
+        for (int j = 0; j < J; ++j) {
+            const uint32_t x = jtot[j];
+            jtot[j] = run;
+            run += x;
+        }
+        jtot[kCountTiles] = run;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int j = 0; j < J; ++j) {
+        const uint64_t e = uint64_t(j) * kCountThreads + t;
+        const uint32_t x = e < nc ? counts[e] : 0u;
+        uint32_t incl = x;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = uint32_t(__shfl_up(int(incl), d, 64));
+            if (lane >= d) incl += y;
+        }
+        if (e < nc) off[e] = jtot[j] + wtot[w][j] + (incl - x);
+    }
+    if (t == 0) off[nc] = jtot[kCountTiles];
+}
+
+// Places each shot in its chunk's bucket: sorted[pos] = chunk << 32 | shot,
+// rs[pos] = r, pos = the bucket's offset plus the shot's rank in it.
+__global__ __launch_bounds__(kThreads) void k_shot_place(SampleLayout L, const double* __restrict__ B,
+                                                        const double* __restrict__ u, uint64_t ns,
+                                                        const uint32_t* __restrict__ key,
+                                                        const uint32_t* __restrict__ rank,
+                                                        const uint32_t* __restrict__ off,
+                                                        uint64_t* __restrict__ sorted, double* __restrict__ rs)
+{
+    const uint64_t s = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    const uint32_t c = key[s];
+    if (c >= L.nc) return;
+    bool bad = false;
+    const double us = checked_uniform(u[s], &bad);
+    const uint64_t pos = uint64_t(off[c]) + rank[s];
+    if (pos < ns) {
+        sorted[pos] = (uint64_t(c) << 32) | uint64_t(uint32_t(s));
+        rs[pos] = shot_r(us, B[L.nc]);
+    }
+}
+
+// One thread per placed shot, in bucket order: block by binary search over
+// the chunk's C, then the block's amplitudes in order.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_resolve(const typename Cx<R>::T* __restrict__ psi,
+                                                     SampleLayout L, const double* __restrict__ B,
+                                                     const double* __restrict__ C,
+                                                     const uint64_t* __restrict__ sorted,
+                                                     const double* __restrict__ rs, uint64_t ns,
+                                                     uint64_t* __restrict__ idx_out)
+{
+    using T2 = typename Cx<R>::T;
+    const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= ns) return;
+    const uint64_t e0 = sorted[i];
+    const uint64_t c = e0 >> 32, s = e0 & 0xffffffffu;
+    if (c >= L.nc || s >= ns) return;
+    if (!(B[L.nc] > 0.0)) {  // a zero state: the call reports the error
+        idx_out[s] = 0;
+        return;
+    }
+    const double r = rs[i];
     const double base = B[c];
     const double* cc = C + c * L.nbk;
     const T2* chunk = psi + c * L.cs;
@@ -554,9 +818,9 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const typename Cx<R>::T* _
         // non-zero probability (the chunk has one, since S[c] > 0 whenever
         // the chunk can be chosen)
         found = c * L.cs;
-        for (uint64_t i = L.cs; i-- > 0;) {
-            if (prob(chunk[i]) > 0.0) {
-                found = c * L.cs + i;
+        for (uint64_t k = L.cs; k-- > 0;) {
+            if (prob(chunk[k]) > 0.0) {
+                found = c * L.cs + k;
                 break;
             }
         }
@@ -694,21 +958,90 @@ void run_expect_t(sv_handle_s* h, const void* psi_v, int n, const PauliMasks* te
     for (int t = 0; t < n_terms; ++t) out[t] = sums[t] / norm;
 }
 
-// Device buffers of one sampling call: block prefixes C (nc * nbk doubles),
-// chunk totals S (nc), chunk boundaries B (nc + 1), and a shot batch of
-// `batch` uniforms and indices.
+// Device buffers of one sampling call: block prefixes C (nc * nbk
+// doubles), chunk totals S (nc), chunk boundaries B (nc + 1), bucket counts
+// (nc + 1: the last is the flag for uniforms outside [0, 1)) and offsets
+// (nc + 1), and per shot of a batch its chunk, its bucket entry and its r;
+// with host uniforms and outputs also a batch of uniforms and indices.
 struct SampleBuffers {
     double* C;
     double* S;
     double* B;
+    uint32_t* counts;
+    uint32_t* off;
+    uint32_t* guide;
+    uint32_t* key;
+    uint32_t* rank;
+    uint64_t* sorted;
+    double* rs;
     double* du;
     uint64_t* didx;
     int64_t batch;
 };
 
+constexpr int kGuideMaxBits = 16;
+constexpr size_t kShotBytes = 2 * sizeof(uint32_t) + sizeof(uint64_t) + sizeof(double);  // key, rank, sorted, rs
+constexpr size_t kHostShotBytes = sizeof(double) + sizeof(uint64_t);                    // du, didx
+constexpr size_t kCarveAlign = 256;
+
+constexpr size_t carve_size(size_t bytes) { return (bytes + kCarveAlign - 1) & ~(kCarveAlign - 1); }
+
+// Bytes of the per-call part of SampleBuffers (everything but C).
+constexpr size_t sample_fixed_bytes(uint64_t nc)
+{
+    return carve_size(sizeof(double) * nc) + carve_size(sizeof(double) * (nc + 1)) +
+           2 * carve_size(sizeof(uint32_t) * (nc + 1)) + carve_size(sizeof(uint32_t) * ((size_t(1) << kGuideMaxBits) + 1));
+}
+
+// Bytes of a shot batch.
+constexpr size_t sample_batch_bytes(int64_t batch, bool host_io)
+{
+    const size_t b = size_t(batch);
+    size_t t = 2 * carve_size(sizeof(uint32_t) * b) + carve_size(sizeof(uint64_t) * b) + carve_size(sizeof(double) * b);
+    if (host_io) t += carve_size(sizeof(double) * b) + carve_size(sizeof(uint64_t) * b);
+    return t;
+}
+
+// Lays SampleBuffers (all but C) out from w.
+void carve_sample_buffers(char* w, uint64_t nc, int64_t batch, bool host_io, SampleBuffers& sb)
+{
+    auto take = [&](size_t bytes) {
+        char* p = w;
+        w += carve_size(bytes);
+        return p;
+    };
+    sb.S = reinterpret_cast<double*>(take(sizeof(double) * nc));
+    sb.B = reinterpret_cast<double*>(take(sizeof(double) * (nc + 1)));
+    sb.counts = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * (nc + 1)));
+    sb.off = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * (nc + 1)));
+    sb.guide = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * ((size_t(1) << kGuideMaxBits) + 1)));
+    const size_t b = size_t(batch);
+    sb.key = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * b));
+    sb.rank = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * b));
+    sb.sorted = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * b));
+    sb.rs = reinterpret_cast<double*>(take(sizeof(double) * b));
+    sb.du = host_io ? reinterpret_cast<double*>(take(sizeof(double) * b)) : nullptr;
+    sb.didx = host_io ? reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * b)) : nullptr;
+    sb.batch = batch;
+}
+
+// Bits of the guide table for a batch of ns shots on nc chunks: about one
+// cutpoint per 16 shots, at most four per chunk and 2^16 in all.
+int guide_bits(uint64_t ns, uint64_t nc)
+{
+    int g = 0;
+    while (g < kGuideMaxBits && (uint64_t(16) << (g + 1)) <= ns && (uint64_t(1) << (g + 1)) <= 4 * nc) ++g;
+    return g;
+}
+
+// The sampler's launches.  With host_io, u and out are host arrays (each
+// batch's uniforms go to the device and its outcomes come back); otherwise
+// they are device arrays that the kernels read and write directly.  Blocks
+// until the outcomes are written; the norm and the uniforms are checked at
+// the end (on an error the outputs are unspecified).
 template <typename R>
 void sample_core(hipStream_t stream, int cu_count, const void* psi_v, int n, const double* u, int64_t n_shots,
-                 const int32_t* bit_ordering, int n_bits, uint64_t* out, const SampleBuffers& sb)
+                 const int32_t* bit_ordering, int n_bits, uint64_t* out, const SampleBuffers& sb, bool host_io)
 {
     using T2 = typename Cx<R>::T;
     const T2* psi = static_cast<const T2*>(psi_v);
@@ -718,58 +1051,83 @@ void sample_core(hipStream_t stream, int cu_count, const void* psi_v, int n, con
     SV_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(kScanThreads), 0, stream, sb.S, L.nc, sb.B);
     SV_HIP(hipGetLastError());
-    double total = 0.0;
-    SV_HIP(hipMemcpyAsync(&total, sb.B + L.nc, sizeof(double), hipMemcpyDeviceToHost, stream));
-    SV_HIP(hipStreamSynchronize(stream));
-    if (!(total > 0.0)) throw Error{SV_ERR_INVALID_VALUE, "state has zero norm"};
 
+    if (L.nc > uint64_t(kCountThreads) * kCountTiles) throw Error{SV_ERR_INTERNAL, "sampler chunk count"};
     BitArgs ba{};
     ba.n_bits = n_bits;
     for (int b = 0; b < n_bits; ++b) ba.bits[b] = bit_ordering[b];
+    int g_built = -1;  // bits of the guide table in sb.guide
     for (int64_t s0 = 0; s0 < n_shots; s0 += sb.batch) {
         const uint64_t ns = uint64_t(std::min<int64_t>(sb.batch, n_shots - s0));
-        SV_HIP(hipMemcpyAsync(sb.du, u + s0, sizeof(double) * ns, hipMemcpyHostToDevice, stream));
+        const double* du = u + s0;
+        uint64_t* dout = out + s0;
+        if (host_io) {
+            SV_HIP(hipMemcpyAsync(sb.du, u + s0, sizeof(double) * ns, hipMemcpyHostToDevice, stream));
+            du = sb.du;
+            dout = sb.didx;
+        }
+        // the first batch also clears the uniforms flag
+        const uint64_t nclear = s0 == 0 ? L.nc + 1 : L.nc;
+        hipLaunchKernelGGL(k_fill_u32, dim3(unsigned((nclear + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                           stream, sb.counts, nclear);
+        SV_HIP(hipGetLastError());
+        const int g = guide_bits(ns, L.nc);
+        if (g != g_built) {
+            const uint64_t ng = (uint64_t(1) << g) + 1;
+            hipLaunchKernelGGL(k_chunk_guide, dim3(unsigned((ng + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                               stream, L, sb.B, g, sb.guide);
+            SV_HIP(hipGetLastError());
+            g_built = g;
+        }
         const unsigned sg = unsigned((ns + kThreads - 1) / kThreads);
-        hipLaunchKernelGGL((k_resolve<R>), dim3(sg), dim3(kThreads), 0, stream, psi, L, sb.B, sb.C, sb.du, ns,
-                           sb.didx);
+        hipLaunchKernelGGL(k_shot_chunks, dim3(sg), dim3(kThreads), 0, stream, L, sb.B, sb.guide, g, du, ns, sb.key,
+                           sb.rank, sb.counts);
+        SV_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(kCountThreads), 0, stream, sb.counts, L.nc, sb.off);
+        SV_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_shot_place, dim3(sg), dim3(kThreads), 0, stream, L, sb.B, du, ns, sb.key, sb.rank,
+                           sb.off, sb.sorted, sb.rs);
+        SV_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_resolve<R>), dim3(sg), dim3(kThreads), 0, stream, psi, L, sb.B, sb.C, sb.sorted, sb.rs,
+                           ns, dout);
         SV_HIP(hipGetLastError());
         if (n_bits > 0) {
-            hipLaunchKernelGGL(k_extract_bits, dim3(sg), dim3(kThreads), 0, stream, sb.didx, ns, ba);
+            hipLaunchKernelGGL(k_extract_bits, dim3(sg), dim3(kThreads), 0, stream, dout, ns, ba);
             SV_HIP(hipGetLastError());
         }
-        SV_HIP(hipMemcpyAsync(out + s0, sb.didx, sizeof(uint64_t) * ns, hipMemcpyDeviceToHost, stream));
-        SV_HIP(hipStreamSynchronize(stream));
+        if (host_io) {
+            SV_HIP(hipMemcpyAsync(out + s0, sb.didx, sizeof(uint64_t) * ns, hipMemcpyDeviceToHost, stream));
+            SV_HIP(hipStreamSynchronize(stream));
+        }
     }
+    double total = 0.0;
+    uint32_t bad = 0;
+    SV_HIP(hipMemcpyAsync(&total, sb.B + L.nc, sizeof(double), hipMemcpyDeviceToHost, stream));
+    SV_HIP(hipMemcpyAsync(&bad, sb.counts + L.nc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+    SV_HIP(hipStreamSynchronize(stream));
+    if (!(total > 0.0)) throw Error{SV_ERR_INVALID_VALUE, "state has zero norm"};
+    if (bad) throw Error{SV_ERR_INVALID_VALUE, "uniforms must lie in [0, 1)"};
 }
 
 // The handle's sampler: block prefixes in the handle's growable scratch,
 // everything else in its workspace.
 template <typename R>
 void run_sample_t(sv_handle_s* h, const void* psi_v, int n, const double* u, int64_t n_shots,
-                  const int32_t* bit_ordering, int n_bits, uint64_t* out)
+                  const int32_t* bit_ordering, int n_bits, uint64_t* out, bool host_io)
 {
     const SampleLayout L = sample_layout(n);
     SampleBuffers sb{};
     sb.C = reinterpret_cast<double*>(ensure_aux(h, sizeof(double) * L.nc * L.nbk));
-    char* w = h->ws + kMatRingBytes;
-    auto take = [&](size_t bytes) {
-        char* p = w;
-        w += (bytes + 255) & ~size_t(255);
-        return p;
-    };
-    sb.S = reinterpret_cast<double*>(take(sizeof(double) * L.nc));
-    sb.B = reinterpret_cast<double*>(take(sizeof(double) * (L.nc + 1)));
-    const size_t used = size_t(w - h->ws);
+    const size_t used = kMatRingBytes + sample_fixed_bytes(L.nc);
     if (used >= h->ws_bytes) throw Error{SV_ERR_OUT_OF_MEMORY, "workspace too small for the sampler"};
-    const size_t per_shot = sizeof(double) + sizeof(uint64_t);
-    int64_t batch = int64_t((h->ws_bytes - used) / per_shot) - 1024;
+    const size_t per_shot = kShotBytes + (host_io ? kHostShotBytes : 0);
+    int64_t batch = int64_t((h->ws_bytes - used) / per_shot) - int64_t(kCarveAlign);
     if (batch > (int64_t(1) << 22)) batch = int64_t(1) << 22;
     if (batch < 1) throw Error{SV_ERR_OUT_OF_MEMORY, "workspace too small for the sampler"};
-    sb.batch = batch;
-    sb.du = reinterpret_cast<double*>(take(sizeof(double) * batch));
-    sb.didx = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * batch));
-    if (size_t(w - h->ws) > h->ws_bytes) throw Error{SV_ERR_INTERNAL, "sampler workspace layout"};
-    sample_core<R>(h->stream, h->cu_count, psi_v, n, u, n_shots, bit_ordering, n_bits, out, sb);
+    if (used + sample_batch_bytes(batch, host_io) > h->ws_bytes)
+        throw Error{SV_ERR_INTERNAL, "sampler workspace layout"};
+    carve_sample_buffers(h->ws + kMatRingBytes, L.nc, batch, host_io, sb);
+    sample_core<R>(h->stream, h->cu_count, psi_v, n, u, n_shots, bit_ordering, n_bits, out, sb, host_io);
 }
 
 // ------------------------------------------- allocation-free sampler scratch
@@ -783,11 +1141,10 @@ void run_sample_t(sv_handle_s* h, const void* psi_v, int n, const double* u, int
 
 constexpr size_t kNoAllocPrefixBytes = (size_t(1) << SV_SAMPLE_NOALLOC_MAX_QUBITS) / kBlk * sizeof(double);
 constexpr uint64_t kNoAllocMaxChunks = (uint64_t(1) << SV_SAMPLE_NOALLOC_MAX_QUBITS) / (4 * kSub);
-constexpr size_t kNoAllocChunkBytes = (kNoAllocMaxChunks + 1) * sizeof(double) + 256;
 constexpr int kMaxScratchDevices = 64;
-constexpr int64_t kNoAllocShotBatch = int64_t(1) << 18;
-constexpr size_t kNoAllocShotBytes = size_t(kNoAllocShotBatch) * sizeof(double);
-static_assert(kNoAllocPrefixBytes + 2 * kNoAllocChunkBytes + 2 * kNoAllocShotBytes <= SV_SAMPLE_NOALLOC_SCRATCH_BYTES,
+constexpr int64_t kNoAllocShotBatch = int64_t(1) << 16;
+static_assert(kNoAllocPrefixBytes + sample_fixed_bytes(kNoAllocMaxChunks) + sample_batch_bytes(kNoAllocShotBatch, true) <=
+                  SV_SAMPLE_NOALLOC_SCRATCH_BYTES,
               "allocation-free sampler scratch too small");
 
 }  // namespace
@@ -826,17 +1183,13 @@ void run_sample_noalloc_t(sv_handle_s* h, const void* psi_v, int n, const double
                           const int32_t* bit_ordering, int n_bits, uint64_t* out)
 {
     const SampleLayout L = sample_layout(n);
+    if (sizeof(double) * L.nc * L.nbk > kNoAllocPrefixBytes || L.nc > kNoAllocMaxChunks)
+        throw Error{SV_ERR_INTERNAL, "allocation-free sampler layout"};
     char* w = noalloc_scratch(h->device);
     SampleBuffers sb{};
     sb.C = reinterpret_cast<double*>(w);
-    sb.S = reinterpret_cast<double*>(w + kNoAllocPrefixBytes);
-    sb.B = reinterpret_cast<double*>(w + kNoAllocPrefixBytes + kNoAllocChunkBytes);
-    sb.du = reinterpret_cast<double*>(w + kNoAllocPrefixBytes + 2 * kNoAllocChunkBytes);
-    sb.didx = reinterpret_cast<uint64_t*>(w + kNoAllocPrefixBytes + 2 * kNoAllocChunkBytes + kNoAllocShotBytes);
-    sb.batch = kNoAllocShotBatch;
-    if (sizeof(double) * L.nc * L.nbk > kNoAllocPrefixBytes || L.nc > kNoAllocMaxChunks)
-        throw Error{SV_ERR_INTERNAL, "allocation-free sampler layout"};
-    sample_core<R>(h->stream, h->cu_count, psi_v, n, u, n_shots, bit_ordering, n_bits, out, sb);
+    carve_sample_buffers(w + kNoAllocPrefixBytes, L.nc, kNoAllocShotBatch, true, sb);
+    sample_core<R>(h->stream, h->cu_count, psi_v, n, u, n_shots, bit_ordering, n_bits, out, sb, true);
 }
 
 // --------------------------------------------------------- measurement
@@ -1451,12 +1804,12 @@ void run_expect(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const Pau
 }
 
 void run_sample(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const double* u, int64_t n_shots,
-                const int32_t* bit_ordering, int n_bits, uint64_t* out)
+                const int32_t* bit_ordering, int n_bits, uint64_t* out, bool host_io)
 {
     if (dt == SV_C64)
-        run_sample_t<float>(h, psi, n, u, n_shots, bit_ordering, n_bits, out);
+        run_sample_t<float>(h, psi, n, u, n_shots, bit_ordering, n_bits, out, host_io);
     else
-        run_sample_t<double>(h, psi, n, u, n_shots, bit_ordering, n_bits, out);
+        run_sample_t<double>(h, psi, n, u, n_shots, bit_ordering, n_bits, out, host_io);
 }
 
 void run_sample_noalloc(sv_handle_s* h, sv_dtype_t dt, const void* psi, int n, const double* u, int64_t n_shots,

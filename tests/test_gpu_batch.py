@@ -189,3 +189,115 @@ def test_batch_short_circuits_finish_first(P, H):
     b.close()
     lat_small, lat_large = lat[: len(small)], lat[len(small):]
     assert lat_small.max() < np.median(lat_large), (lat_small.max(), np.median(lat_large), ks)
+
+
+def test_batch_autotuner_plans(P):
+    # every size of a mixed batch gets a tuned plan: the persistent kernel's
+    # width below 13 qubits, the level path's tile shape above 16, either
+    # path in between (the faster one); the results match the oracle
+    sizes = [9, 12, 13, 14, 15, 16, 17, 19] * 2
+    ns, circuits, terms = _mixed(91, sizes, 6, 14)
+    h = P.Handle()
+    b = P.Batch(h, ns, circuits, terms, max_fused_qubits=0)
+    for n in set(sizes):
+        p = b.plan(n)
+        assert p["tuned"] == 1, (n, p)
+        if n < 13:
+            assert p["level_path"] == 0 and 3 <= p["max_fused_qubits"] <= 5, (n, p)
+        if n > 16:
+            assert p["level_path"] == 1, (n, p)
+        if p["level_path"]:
+            assert p["max_fused_qubits"] == 5 and p["tiles_per_wg"] in (1, 2, 4, 8) and p["spread"] in (0, 1), (n, p)
+            assert p["tiles_per_wg"] <= 1 << (n - 12)
+        else:
+            assert p["tiles_per_wg"] == 0 and p["spread"] == 0, (n, p)
+    assert b.plan(25) == {"max_fused_qubits": 0, "level_path": 0, "tiles_per_wg": 0, "spread": 0, "tuned": 0}
+    tune_s, build_s = b.host_times()
+    assert tune_s >= 0.0 and build_s > 0.0
+    exps, lat, ks = b.run()
+    _check(P, b, ns, circuits, terms, exps)
+    # a later batch with these sizes takes the same plans without timing
+    b2 = P.Batch(h, ns[:8], circuits[:8], terms[:8], max_fused_qubits=0)
+    assert b2.host_times()[0] == 0.0
+    for n in sizes[:8]:
+        assert b2.plan(n) == b.plan(n)
+    e2, _, _ = b2.run()
+    for i in range(8):
+        np.testing.assert_array_equal(e2[i], exps[i])
+    b2.close()
+    # a fixed width takes no timing and the default level shape
+    b3 = P.Batch(h, ns, circuits, terms, max_fused_qubits=4)
+    assert b3.host_times()[0] == 0.0
+    assert b3.plan(17) == {"max_fused_qubits": 5, "level_path": 1, "tiles_per_wg": 4, "spread": 1, "tuned": 0}
+    assert b3.plan(12) == {"max_fused_qubits": 4, "level_path": 0, "tiles_per_wg": 0, "spread": 0, "tuned": 0}
+    b3.close()
+    b.close()
+    h.close()
+
+
+_CACHE_SCRIPT = r"""
+import json, os, sys
+sys.path.insert(0, os.getcwd())
+import paper_2308_01999_amd as P
+import workloads as W
+h = P.Handle()
+ns = [10, 14, 17]
+circuits = [W.brickwork(n, 8, 100 + n) for n in ns]
+terms = [[1, 1 << (n - 1)] for n in ns]
+b = P.Batch(h, ns, circuits, terms, max_fused_qubits=0)
+exps, _, _ = b.run()
+print(json.dumps({"tune_s": b.host_times()[0], "plans": {str(n): b.plan(n) for n in ns},
+                  "exps": [[float(v) for v in e] for e in exps]}))
+b.close()
+h.close()
+"""
+
+
+def test_batch_tune_cache_file_across_processes(P, tmp_path):
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.json"
+    env = dict(os.environ, SV_AUTOTUNE_CACHE=str(cache))
+
+    def run():
+        r = subprocess.run([sys.executable, "-c", _CACHE_SCRIPT], cwd=root, env=env, capture_output=True,
+                           text=True, timeout=240)
+        assert r.returncode == 0, r.stderr[-3000:]
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    first = run()
+    assert first["tune_s"] > 0.0
+    doc = json.load(open(cache))
+    entries = {e["n"]: e for e in doc["entries"]}
+    assert {10, 14, 17} <= set(entries)
+    assert entries[10]["kmax"] in (3, 4, 5) and entries[17]["tiles_per_wg"] in (1, 2, 4, 8)
+    assert entries[14]["kmax"] != -1 and entries[14]["tiles_per_wg"] != -1  # both paths timed
+    arch = entries[10]["arch"]
+    # a second process reads the file: no timing, the same plans and results
+    second = run()
+    assert second["tune_s"] == 0.0
+    assert second["plans"] == first["plans"]
+    assert second["exps"] == first["exps"]
+    # choices written by hand are taken as they are
+    lines = [
+        {"arch": arch, "dtype": "c64", "n": 10, "kmax": 3, "persistent_ms": 1.0, "tiles_per_wg": -1, "spread": -1,
+         "level_ms": -1},
+        {"arch": arch, "dtype": "c64", "n": 14, "kmax": 4, "persistent_ms": 1.0, "tiles_per_wg": 1, "spread": 0,
+         "level_ms": 2.0},
+        {"arch": arch, "dtype": "c64", "n": 17, "kmax": -1, "persistent_ms": -1, "tiles_per_wg": 1, "spread": 0,
+         "level_ms": 1.0},
+    ]
+    cache.write_text('{"sv_autotune": 1, "entries": [\n' + ",\n".join(json.dumps(x) for x in lines) + "\n]}\n")
+    third = run()
+    assert third["tune_s"] == 0.0
+    p = third["plans"]
+    assert p["10"] == {"max_fused_qubits": 3, "level_path": 0, "tiles_per_wg": 0, "spread": 0, "tuned": 1}
+    assert p["14"] == {"max_fused_qubits": 4, "level_path": 0, "tiles_per_wg": 0, "spread": 0, "tuned": 1}
+    assert p["17"] == {"max_fused_qubits": 5, "level_path": 1, "tiles_per_wg": 1, "spread": 0, "tuned": 1}
+    for n, e in zip((10, 14, 17), third["exps"]):
+        ref = oracle.run(n, W.brickwork(n, 8, 100 + n))
+        want = [oracle.expect_pauli(ref, [(0, "Z")]), oracle.expect_pauli(ref, [(n - 1, "Z")])]
+        assert np.max(np.abs(np.array(e) - np.array(want))) <= 1e-4, (n, e, want)
