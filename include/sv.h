@@ -531,16 +531,16 @@ typedef struct sv_batch_s* sv_batch_t;
  * qubits, each block swept as a five-qubit gate by the single-state tile
  * sweep (narrow tiles in a spread or plain layout, 1..8 tiles per
  * workgroup), block l of all of them in launch l.
- * max_fused_qubits in [1, 5] fixes the persistent kernel's width: circuits
- * below the handle's level-path qubit count (sv_handle_set_batch_level_qubits,
- * default SV_BATCH_LEVEL_DEFAULT) take the persistent kernel, the others
- * the level path in its default shape (spread layout, 4 tiles per
- * workgroup).  max_fused_qubits = 0 lets the autotuner choose per qubit
- * count by timing, on the batch's own circuits of that size, the persistent
- * kernel at widths 3..5 and the level path in each tile shape, and keeping
- * the fastest; sizes from SV_BATCH_LEVEL_MIN_QUBITS to 16 qubits take the
- * faster of the two paths unless the handle's level-path qubit count was
- * set, which then decides the path.  Tuned choices are kept for the process
+ * Circuits below the handle's level-path qubit count
+ * (sv_handle_set_batch_level_qubits, default SV_BATCH_LEVEL_DEFAULT) take
+ * the persistent kernel, the others the level path.  max_fused_qubits in
+ * [1, 5] fixes the persistent kernel's width, and the level path runs in
+ * its default shape (spread layout, 4 tiles per workgroup).
+ * max_fused_qubits = 0 lets the autotuner choose: per qubit count of the
+ * persistent kernel, the fastest width of 3..5 on the batch's own circuits
+ * of that size; for the level path, whose circuits share its launches, the
+ * fastest tile shape on a mix of the batch's level-path circuits of the
+ * sizes not tuned yet.  Tuned choices are kept for the process
  * and, if the environment variable SV_AUTOTUNE_CACHE names a file, in that
  * JSON file (keyed by device architecture, state type and qubit count;
  * entries of other keys are kept, unreadable lines skipped, and a file that
@@ -556,10 +556,8 @@ sv_status_t sv_batch_create(sv_handle_t h, int32_t n_circuits, const int32_t* n_
                             int32_t max_fused_qubits, sv_batch_t* out);
 
 /* Qubit count from which circuits of batches created later on handle h run on
- * the level path (default SV_BATCH_LEVEL_DEFAULT, which the autotuner may
- * override for sizes up to 16 qubits; once set by this call, it decides the
- * path for every size); SV_BATCH_LEVEL_NONE keeps every circuit on the
- * persistent kernel.  Range [SV_BATCH_LEVEL_MIN_QUBITS,
+ * the level path (default SV_BATCH_LEVEL_DEFAULT); SV_BATCH_LEVEL_NONE keeps
+ * every circuit on the persistent kernel.  Range [SV_BATCH_LEVEL_MIN_QUBITS,
  * SV_BATCH_LEVEL_NONE]; SV_ERR_INVALID_VALUE otherwise. */
 #define SV_BATCH_LEVEL_MIN_QUBITS 13
 #define SV_BATCH_LEVEL_DEFAULT 15

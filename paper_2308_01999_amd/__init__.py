@@ -517,10 +517,17 @@ def sv_swap_index_bits(s: int, pairs, mask_bits=(), mask_values=()) -> None:
 
 
 def sv_accessor_get(s: int, dtype: int, ordering, mask_bits=(), mask_values=(), begin: int = 0,
-                    end: int | None = None) -> np.ndarray:
+                    end: int | None = None, out: np.ndarray | None = None) -> np.ndarray:
+    """out (optional): a C-contiguous array of end - begin elements of the
+    state's dtype to fill (reusing it spares the host the page faults of a
+    fresh array)."""
     if end is None:
         end = 1 << len(ordering)
-    out = np.zeros(max(0, end - begin), dtype=np.complex64 if dtype == SV_C64 else np.complex128)
+    want = np.complex64 if dtype == SV_C64 else np.complex128
+    if out is None:
+        out = np.zeros(max(0, end - begin), dtype=want)
+    elif out.dtype != want or out.size != max(0, end - begin) or not out.flags["C_CONTIGUOUS"]:
+        raise ValueError("out must be a C-contiguous array of end - begin elements of the state's dtype")
     _check(_L.sv_accessor_get(_vp(s), _i32arr(ordering), len(ordering), _i32arr(mask_bits), _i32arr(mask_values),
                               len(mask_bits), out.ctypes.data, begin, end))
     return out

@@ -337,6 +337,9 @@ sv_status_t sv_handle_destroy(sv_handle_t h)
         for (int i = 0; i < kMatRingSegments; ++i)
             if (h->seg_event[i]) (void)hipEventDestroy(h->seg_event[i]);
         if (h->pinned) (void)hipHostFree(h->pinned);
+        if (h->acc_pinned) (void)hipHostFree(h->acc_pinned);
+        for (hipEvent_t ev : h->acc_event)
+            if (ev) (void)hipEventDestroy(ev);
         dev_free(h->ws, h->ws_bytes);
         dev_free(h->aux, h->aux_bytes);
         if (h->tuner) {
@@ -377,7 +380,6 @@ sv_status_t sv_handle_set_batch_level_qubits(sv_handle_t h, int32_t n_qubits)
         SV_CHECK(n_qubits >= SV_BATCH_LEVEL_MIN_QUBITS && n_qubits <= SV_BATCH_LEVEL_NONE,
                  "level-path qubit count must be in [SV_BATCH_LEVEL_MIN_QUBITS, SV_BATCH_LEVEL_NONE]");
         h->batch_level_qubits = n_qubits;
-        h->batch_level_fixed = true;
     });
 }
 

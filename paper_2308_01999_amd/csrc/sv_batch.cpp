@@ -314,10 +314,14 @@ uint32_t add_level_circuit(BatchHost& H, const BatchCircuit& c, const sv_fused_s
     return first;
 }
 
+// Fused programs of circuits (input index -> program) that a caller keeps
+// across several builds; build_host neither fuses nor frees them.
+using Prefused = std::map<int, sv_fused_s*>;
+
 BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>& sel,
                      const std::map<int, SizePlan>& plans, const std::vector<int>& term0,
                      const std::vector<int>& nterms, const uint64_t* z_masks, std::vector<int>* blocks_out,
-                     int cu_count)
+                     int cu_count, const Prefused* prefused = nullptr)
 {
     // each distinct circuit is fused once (a tuning sample repeats circuits)
     auto plan_of = [&](int n) -> const SizePlan& { return plans.at(n); };
@@ -325,20 +329,25 @@ BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>
     std::vector<int> ks;
     std::map<int, size_t> uniq;
     std::vector<size_t> slot(sel.size());
-    for (size_t j = 0; j < sel.size(); ++j) {
-        const int i = sel[j];
-        auto it = uniq.find(i);
-        if (it == uniq.end()) {
-            const SizePlan& pl = plan_of(in[i].n);
-            it = uniq.emplace(i, sub.size()).first;
-            sub.push_back(in[i]);
-            ks.push_back(pl.level ? std::min(kBatchMaxK, in[i].n) : pl.kmax);
-        }
-        slot[j] = it->second;
-    }
-    auto fused_u = fuse_all(sub, ks);
     std::vector<sv_fused_s*> fused(sel.size());
-    for (size_t j = 0; j < sel.size(); ++j) fused[j] = fused_u[slot[j]];
+    std::vector<sv_fused_s*> fused_u;  // fused here, freed here
+    if (prefused) {
+        for (size_t j = 0; j < sel.size(); ++j) fused[j] = prefused->at(sel[j]);
+    } else {
+        for (size_t j = 0; j < sel.size(); ++j) {
+            const int i = sel[j];
+            auto it = uniq.find(i);
+            if (it == uniq.end()) {
+                const SizePlan& pl = plan_of(in[i].n);
+                it = uniq.emplace(i, sub.size()).first;
+                sub.push_back(in[i]);
+                ks.push_back(pl.level ? std::min(kBatchMaxK, in[i].n) : pl.kmax);
+            }
+            slot[j] = it->second;
+        }
+        fused_u = fuse_all(sub, ks);
+        for (size_t j = 0; j < sel.size(); ++j) fused[j] = fused_u[slot[j]];
+    }
     BatchHost H;
     H.circuits.resize(sel.size());
     std::vector<uint32_t> level_circuits, level_first;
@@ -585,9 +594,10 @@ void store_tuned(const std::string& arch, int n, const TuneRecord& r)
 // be had.
 float time_plan(sv_handle_s* h, const std::vector<CircuitInput>& in, const std::vector<int>& sample,
                 const std::map<int, SizePlan>& plans, const std::vector<int>& term0, const std::vector<int>& nterms,
-                const uint64_t* z_masks, hipEvent_t e0, hipEvent_t e1)
+                const uint64_t* z_masks, hipEvent_t e0, hipEvent_t e1, const Prefused* prefused = nullptr,
+                int timed_runs = 1)
 {
-    BatchHost H = build_host(in, sample, plans, term0, nterms, z_masks, nullptr, h->cu_count);
+    BatchHost H = build_host(in, sample, plans, term0, nterms, z_masks, nullptr, h->cu_count, prefused);
     BatchArgs a{};
     size_t dev_bytes = 0;
     char* dev = upload(H, a, h->stream, &dev_bytes);
@@ -602,15 +612,20 @@ float time_plan(sv_handle_s* h, const std::vector<CircuitInput>& in, const std::
     a.states = states;
     float ms = 0.f;
     try {
-        for (int rep = 0; rep < 2; ++rep) {
-            if (rep == 1) SV_HIP(hipEventRecord(e0, h->stream));
+        // an untimed run, then the fastest of timed_runs
+        for (int rep = 0; rep <= timed_runs; ++rep) {
+            if (rep > 0) SV_HIP(hipEventRecord(e0, h->stream));
             launch_batch_reset(h->stream, a);
             if (a.n_queue > 0) launch_batch(h->stream, h->cu_count, a);
             launch_levels(h->stream, a, H.levels);
-            if (rep == 1) SV_HIP(hipEventRecord(e1, h->stream));
+            if (rep > 0) {
+                SV_HIP(hipEventRecord(e1, h->stream));
+                SV_HIP(hipEventSynchronize(e1));
+                float t = 0.f;
+                SV_HIP(hipEventElapsedTime(&t, e0, e1));
+                ms = rep == 1 ? t : std::min(ms, t);
+            }
         }
-        SV_HIP(hipEventSynchronize(e1));
-        SV_HIP(hipEventElapsedTime(&ms, e0, e1));
     } catch (...) {
         dev_free(states, st_bytes);
         dev_free(dev, dev_bytes);
@@ -621,70 +636,32 @@ float time_plan(sv_handle_s* h, const std::vector<CircuitInput>& in, const std::
     return ms;
 }
 
-// Tunes what rec lacks for circuits idx of n qubits: the persistent kernel's
-// width if want_persistent, the level path's shape if want_level.
-void tune_size(sv_handle_s* h, const std::vector<CircuitInput>& in, const std::vector<int>& idx, int n,
-               const std::vector<int>& term0, const std::vector<int>& nterms, const uint64_t* z_masks,
-               bool want_persistent, bool want_level, TuneRecord& rec)
+// The persistent kernel's fusion width for circuits idx of n qubits: each
+// width 3..5 timed on up to 64 of them, repeated to two workgroups' worth
+// per CU.  Fills rec.kmax and rec.persistent_ms (per circuit).
+void tune_width(sv_handle_s* h, const std::vector<CircuitInput>& in, const std::vector<int>& idx, int n,
+                const std::vector<int>& term0, const std::vector<int>& nterms, const uint64_t* z_masks,
+                TuneRecord& rec)
 {
     std::vector<int> sel;
     for (int i : idx)
         if (int(sel.size()) < 64) sel.push_back(i);
-    auto repeat = [&](size_t want) {
-        std::vector<int> sample;
-        while (sample.size() < want) sample.push_back(sel[sample.size() % sel.size()]);
-        return sample;
-    };
+    std::vector<int> sample;
+    const size_t want = std::max<size_t>(sel.size(), size_t(h->cu_count) * 2);
+    while (sample.size() < want) sample.push_back(sel[sample.size() % sel.size()]);
     hipEvent_t e0, e1;
     SV_HIP(hipEventCreate(&e0));
     SV_HIP(hipEventCreate(&e1));
     try {
-        if (want_persistent && rec.kmax == -1) {
-            // two workgroups' worth of circuits per CU
-            const auto sample = repeat(std::max<size_t>(sel.size(), size_t(h->cu_count) * 2));
-            for (int k = 3; k <= std::min(kBatchMaxK, n); ++k) {
-                SizePlan p;
-                p.kmax = k;
-                const float ms = time_plan(h, in, sample, {{n, p}}, term0, nterms, z_masks, e0, e1);
-                if (ms < 0.f) break;
-                const double per = double(ms) / double(sample.size());
-                if (rec.kmax == -1 || per < rec.persistent_ms) {
-                    rec.kmax = k;
-                    rec.persistent_ms = per;
-                }
-            }
-            if (rec.kmax == -1) {  // no room to time: the widest width
-                rec.kmax = std::min(kBatchMaxK, n);
-                rec.persistent_ms = 0.0;
-            }
-        }
-        if (want_level && rec.tiles_per_wg == -1) {
-            // enough circuits for twelve tiles per CU in every level, at
-            // most 1 GiB of states
-            const uint64_t tiles = uint64_t(1) << (n - 12);
-            size_t want = std::max<size_t>(sel.size(), size_t((uint64_t(h->cu_count) * 12 + tiles - 1) / tiles));
-            want = std::min<size_t>(want, std::max<size_t>(1, size_t((uint64_t(1) << 30) >> (n + 3))));
-            const auto sample = repeat(want);
-            for (int tpw = 1; tpw <= 8 && uint64_t(tpw) <= tiles; tpw *= 2) {
-                for (int spread = 1; spread >= 0; --spread) {
-                    SizePlan p;
-                    p.level = true;
-                    p.shape.tiles_per_wg = tpw;
-                    p.shape.spread = spread;
-                    const float ms = time_plan(h, in, sample, {{n, p}}, term0, nterms, z_masks, e0, e1);
-                    if (ms < 0.f) continue;
-                    const double per = double(ms) / double(sample.size());
-                    if (rec.tiles_per_wg == -1 || per < rec.level_ms) {
-                        rec.tiles_per_wg = tpw;
-                        rec.spread = spread;
-                        rec.level_ms = per;
-                    }
-                }
-            }
-            if (rec.tiles_per_wg == -1) {  // no room to time: the default shape
-                rec.tiles_per_wg = int(std::min<uint64_t>(4, tiles));
-                rec.spread = 1;
-                rec.level_ms = 0.0;
+        for (int k = 3; k <= std::min(kBatchMaxK, n); ++k) {
+            SizePlan p;
+            p.kmax = k;
+            const float ms = time_plan(h, in, sample, {{n, p}}, term0, nterms, z_masks, e0, e1);
+            if (ms < 0.f) break;
+            const double per = double(ms) / double(sample.size());
+            if (rec.kmax == -1 || per < rec.persistent_ms) {
+                rec.kmax = k;
+                rec.persistent_ms = per;
             }
         }
     } catch (...) {
@@ -694,13 +671,100 @@ void tune_size(sv_handle_s* h, const std::vector<CircuitInput>& in, const std::v
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (rec.kmax == -1) {  // no room to time: the widest width
+        rec.kmax = std::min(kBatchMaxK, n);
+        rec.persistent_ms = 0.0;
+    }
 }
 
-// Qubit counts whose path the autotuner chooses when the handle leaves the
-// level path's size open: below, the persistent kernel; above, the level
-// path.
-constexpr int kRouteTuneLo = SV_BATCH_LEVEL_MIN_QUBITS;
-constexpr int kRouteTuneHi = 16;
+// The level path's tile shape for a batch whose level-path circuits are
+// by_n (qubit count -> circuits): every circuit of the level path shares
+// its launches, so the shapes are timed on one mixed sample, up to 256
+// circuits and 320 MiB of states of each size (fused once for all shapes),
+// repeated until every level holds twelve tiles per CU, at most 2 GiB of
+// states in all; the fastest of
+// two timed runs per shape.  The default shape (4 tiles per workgroup,
+// spread) stays unless another is at least kShapeMargin faster.  Returns the
+// chosen shape and its time per circuit of the sample.
+constexpr double kShapeMargin = 0.02;
+
+LevelShape tune_level_shape(sv_handle_s* h, const std::vector<CircuitInput>& in,
+                            const std::map<int, std::vector<int>>& by_n, const std::vector<int>& term0,
+                            const std::vector<int>& nterms, const uint64_t* z_masks, double* ms_per_circuit)
+{
+    std::vector<int> sel;
+    uint64_t tiles = 0, bytes = 0;
+    int min_n = kBatchMaxQubits;
+    for (const auto& kv : by_n) {
+        min_n = std::min(min_n, kv.first);
+        // at most 256 circuits and 320 MiB of states per size
+        const size_t cap = std::min<size_t>(256, std::max<size_t>(1, (size_t(320) << 20) >> (kv.first + 3)));
+        for (size_t j = 0; j < kv.second.size() && j < cap; ++j) {
+            sel.push_back(kv.second[j]);
+            tiles += uint64_t(1) << (kv.first - 12);
+            bytes += uint64_t(8) << kv.first;
+        }
+    }
+    std::vector<int> sample = sel;
+    while (tiles * (sample.size() / sel.size()) < uint64_t(h->cu_count) * 12 &&
+           bytes * (sample.size() / sel.size() + 1) <= (uint64_t(2) << 30))
+        sample.insert(sample.end(), sel.begin(), sel.end());
+    // fused once, at the level path's width
+    Prefused pre;
+    {
+        std::vector<CircuitInput> sub;
+        std::vector<int> ks;
+        for (int i : sel) {
+            sub.push_back(in[i]);
+            ks.push_back(std::min(kBatchMaxK, in[i].n));
+        }
+        auto f = fuse_all(sub, ks);
+        for (size_t j = 0; j < sel.size(); ++j) pre[sel[j]] = f[j];
+    }
+    const LevelShape dflt;
+    LevelShape best = dflt;
+    double best_ms = -1.0, dflt_ms = -1.0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    try {
+        SV_HIP(hipEventCreate(&e0));
+        SV_HIP(hipEventCreate(&e1));
+        for (int tpw = 1; tpw <= 8 && uint64_t(tpw) <= (uint64_t(1) << (min_n - 12)); tpw *= 2) {
+            for (int spread = 1; spread >= 0; --spread) {
+                std::map<int, SizePlan> plans;
+                for (const auto& kv : by_n) {
+                    SizePlan p;
+                    p.level = true;
+                    p.shape.tiles_per_wg = tpw;
+                    p.shape.spread = spread;
+                    plans[kv.first] = p;
+                }
+                const float ms = time_plan(h, in, sample, plans, term0, nterms, z_masks, e0, e1, &pre, 2);
+                if (ms < 0.f) continue;
+                const double per = double(ms) / double(sample.size());
+                if (tpw == dflt.tiles_per_wg && spread == dflt.spread) dflt_ms = per;
+                if (best_ms < 0.0 || per < best_ms) {
+                    best_ms = per;
+                    best.tiles_per_wg = tpw;
+                    best.spread = spread;
+                }
+            }
+        }
+    } catch (...) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        for (auto& kv : pre) free_fused(kv.second);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (auto& kv : pre) free_fused(kv.second);
+    if (dflt_ms > 0.0 && best_ms > dflt_ms * (1.0 - kShapeMargin)) {
+        best = dflt;
+        best_ms = dflt_ms;
+    }
+    *ms_per_circuit = best_ms < 0.0 ? 0.0 : best_ms;
+    return best;
+}
 
 }  // namespace
 }  // namespace sv
@@ -756,40 +820,56 @@ sv_batch_s* batch_create(sv_handle_s* h, int n_circuits, const int32_t* n_qubits
         b->n.assign(n_qubits, n_qubits + n_circuits);
         using clock = std::chrono::steady_clock;
         std::string arch;
+        std::map<int, std::vector<int>> level_untuned;  // level sizes without a tuned shape
         for (auto& kv : by_n) {
             const int n = kv.first;
             SizePlan p;
+            // the handle's level-path size decides the path
+            p.level = n >= h->batch_level_qubits;
             if (max_fused_qubits > 0) {
-                // a fixed width and no timing: the handle's level-path size
-                // decides the path, the level path's default tile shape
-                p.level = n >= h->batch_level_qubits;
+                // a fixed width and no timing: the level path's default shape
                 p.kmax = p.level ? std::min(kBatchMaxK, n) : std::min(max_fused_qubits, n);
             } else {
                 if (arch.empty()) arch = device_arch(h->device);
-                bool may_persist, may_level;
-                if (h->batch_level_fixed) {
-                    may_level = n >= h->batch_level_qubits;
-                    may_persist = !may_level;
-                } else {
-                    may_persist = n <= kRouteTuneHi;
-                    may_level = n >= kRouteTuneLo;
-                }
                 TuneRecord rec = lookup_tuned(arch, n);
-                if ((may_persist && rec.kmax == -1) || (may_level && rec.tiles_per_wg == -1)) {
-                    const auto t0 = clock::now();
-                    tune_size(h, in, kv.second, n, term0, nterms, z_masks, may_persist, may_level, rec);
-                    store_tuned(arch, n, rec);
-                    b->tune_s += std::chrono::duration<double>(clock::now() - t0).count();
-                }
                 p.tuned = true;
-                p.level = may_level && (!may_persist || rec.level_ms < rec.persistent_ms);
-                p.kmax = p.level ? std::min(kBatchMaxK, n) : rec.kmax;
                 if (p.level) {
-                    p.shape.tiles_per_wg = rec.tiles_per_wg;
-                    p.shape.spread = rec.spread;
+                    p.kmax = std::min(kBatchMaxK, n);
+                    if (rec.tiles_per_wg != -1) {
+                        p.shape.tiles_per_wg = int(std::min<uint64_t>(uint64_t(rec.tiles_per_wg), uint64_t(1) << (n - 12)));
+                        p.shape.spread = rec.spread;
+                    } else {
+                        level_untuned[n] = kv.second;
+                    }
+                } else {
+                    if (rec.kmax == -1) {
+                        const auto t0 = clock::now();
+                        tune_width(h, in, kv.second, n, term0, nterms, z_masks, rec);
+                        store_tuned(arch, n, rec);
+                        b->tune_s += std::chrono::duration<double>(clock::now() - t0).count();
+                    }
+                    p.kmax = rec.kmax;
                 }
             }
             b->plans[n] = p;
+        }
+        if (!level_untuned.empty()) {
+            // one shape for the level sizes not tuned yet, timed on a mix of
+            // them, kept for each of those sizes
+            const auto t0 = clock::now();
+            double ms = 0.0;
+            const LevelShape sh = tune_level_shape(h, in, level_untuned, term0, nterms, z_masks, &ms);
+            for (const auto& kv : level_untuned) {
+                TuneRecord rec = lookup_tuned(arch, kv.first);
+                rec.tiles_per_wg = sh.tiles_per_wg;
+                rec.spread = sh.spread;
+                rec.level_ms = ms;
+                store_tuned(arch, kv.first, rec);
+                SizePlan& p = b->plans[kv.first];
+                p.shape.tiles_per_wg = int(std::min<uint64_t>(uint64_t(sh.tiles_per_wg), uint64_t(1) << (kv.first - 12)));
+                p.shape.spread = sh.spread;
+            }
+            b->tune_s += std::chrono::duration<double>(clock::now() - t0).count();
         }
         const auto t_build = clock::now();
         std::vector<int> all(n_circuits);

@@ -105,9 +105,11 @@ struct sv_handle_s {
     bool seg_event_live[sv::kMatRingSegments] = {};
     char* aux = nullptr;            // device scratch that grows with the state (sampler prefixes)
     size_t aux_bytes = 0;
+    char* acc_pinned = nullptr;     // pinned host staging of the accessor (two chunks), on first use
+    size_t acc_pinned_bytes = 0;
+    hipEvent_t acc_event[2] = {};
     int tile_mode = 0;              // sv_tile_mode_t
     int batch_level_qubits = SV_BATCH_LEVEL_DEFAULT;  // batches: circuits of >= this many qubits take the level path
-    bool batch_level_fixed = false;  // set by the caller: the autotuner does not choose the path
     sv::TileTuner* tuner = nullptr;
 };
 

@@ -16,6 +16,7 @@
 #include <mutex>
 #include <string>
 #include <type_traits>
+#include <thread>
 #include <vector>
 
 #include "sv_internal.h"
@@ -1938,6 +1939,50 @@ void launch_swap_bits(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, const int
     SV_HIP(hipGetLastError());
 }
 
+namespace {
+
+// memcpy on up to 8 host threads for large copies (the caller's pages are
+// often touched for the first time here, and page faults then dominate a
+// single-threaded copy).
+void host_copy(char* dst, const char* src, size_t bytes)
+{
+    constexpr size_t kPart = size_t(4) << 20;
+    unsigned nt = std::min(8u, std::max(1u, std::thread::hardware_concurrency()));
+    nt = unsigned(std::min<size_t>(nt, bytes / kPart));
+    if (nt < 2) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    const size_t per = ((bytes + nt - 1) / nt + 4095) & ~size_t(4095);
+    std::vector<std::thread> th;
+    th.reserve(nt);
+    for (unsigned t = 0; t < nt; ++t) {
+        const size_t lo = std::min(bytes, size_t(t) * per), hi = std::min(bytes, lo + per);
+        if (hi > lo) th.emplace_back([=] { std::memcpy(dst + lo, src + lo, hi - lo); });
+    }
+    for (auto& x : th) x.join();
+}
+
+template <typename R>
+void launch_access(sv_handle_s* h, void* psi, char* stage, const AccessArgs& a, bool set)
+{
+    using T2 = typename Cx<R>::T;
+    if (set)
+        hipLaunchKernelGGL((k_access<R, true>), dim3(grid_for(h, a.count)), dim3(kThreads), 0, h->stream,
+                           static_cast<T2*>(psi), reinterpret_cast<T2*>(stage), a);
+    else
+        hipLaunchKernelGGL((k_access<R, false>), dim3(grid_for(h, a.count)), dim3(kThreads), 0, h->stream,
+                           static_cast<T2*>(psi), reinterpret_cast<T2*>(stage), a);
+    SV_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+// The accessor moves its elements in chunks through two device staging
+// regions of the workspace and two pinned host buffers of the handle, so
+// that the device gathers (or scatters) one chunk and the host link carries
+// it while host threads copy the previous chunk to (or from) the caller's
+// memory.
 void run_accessor(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, const int32_t* ordering, int n_bits,
                   const int32_t* mask_bits, const int32_t* mask_values, int n_mask, void* host, int64_t begin,
                   int64_t end, bool set)
@@ -1949,35 +1994,67 @@ void run_accessor(sv_handle_s* h, sv_dtype_t dt, void* psi, int n, const int32_t
     for (int m = 0; m < n_mask; ++m)
         if (mask_values[m]) a.mval |= uint64_t(1) << mask_bits[m];
     const size_t amp = dt == SV_C64 ? 8 : 16;
-    // staged through the workspace after the matrix ring, one chunk at a time
-    const size_t stage_bytes = std::min<size_t>(h->ws_bytes - kMatRingBytes, size_t(32) << 20);
-    const uint64_t chunk = stage_bytes / amp;
-    char* stage = h->ws + kMatRingBytes;
-    char* hb = static_cast<char*>(host);
-    for (int64_t k0 = begin; k0 < end; k0 += int64_t(chunk)) {
-        a.first = uint64_t(k0);
-        a.count = std::min<uint64_t>(chunk, uint64_t(end - k0));
-        char* hp = hb + size_t(k0 - begin) * amp;
-        if (set) SV_HIP(hipMemcpyAsync(stage, hp, a.count * amp, hipMemcpyHostToDevice, h->stream));
-        if (dt == SV_C64) {
-            if (set)
-                hipLaunchKernelGGL((k_access<float, true>), dim3(grid_for(h, a.count)), dim3(kThreads), 0, h->stream,
-                                   static_cast<float2*>(psi), reinterpret_cast<float2*>(stage), a);
-            else
-                hipLaunchKernelGGL((k_access<float, false>), dim3(grid_for(h, a.count)), dim3(kThreads), 0,
-                                   h->stream, static_cast<float2*>(psi), reinterpret_cast<float2*>(stage), a);
-        } else {
-            if (set)
-                hipLaunchKernelGGL((k_access<double, true>), dim3(grid_for(h, a.count)), dim3(kThreads), 0,
-                                   h->stream, static_cast<double2*>(psi), reinterpret_cast<double2*>(stage), a);
-            else
-                hipLaunchKernelGGL((k_access<double, false>), dim3(grid_for(h, a.count)), dim3(kThreads), 0,
-                                   h->stream, static_cast<double2*>(psi), reinterpret_cast<double2*>(stage), a);
-        }
-        SV_HIP(hipGetLastError());
-        if (!set) SV_HIP(hipMemcpyAsync(hp, stage, a.count * amp, hipMemcpyDeviceToHost, h->stream));
-        SV_HIP(hipStreamSynchronize(h->stream));
+    const size_t avail = h->ws_bytes - kMatRingBytes;
+    const uint64_t chunk = std::min<size_t>(avail / 2, size_t(16) << 20) / amp;
+    const size_t stage_bytes = chunk * amp;
+    if (h->acc_pinned_bytes < 2 * stage_bytes) {
+        if (h->acc_pinned) SV_HIP(hipHostFree(h->acc_pinned));
+        h->acc_pinned = nullptr;
+        h->acc_pinned_bytes = 0;
+        SV_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->acc_pinned), 2 * stage_bytes, hipHostMallocDefault));
+        h->acc_pinned_bytes = 2 * stage_bytes;
     }
+    for (hipEvent_t& ev : h->acc_event)
+        if (!ev) SV_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    char* dstage[2] = {h->ws + kMatRingBytes, h->ws + kMatRingBytes + stage_bytes};
+    char* hstage[2] = {h->acc_pinned, h->acc_pinned + stage_bytes};
+    char* hb = static_cast<char*>(host);
+    const uint64_t total = uint64_t(end - begin);
+    const uint64_t n_chunks = (total + chunk - 1) / chunk;
+    auto args_of = [&](uint64_t i) {
+        AccessArgs c = a;
+        c.first = uint64_t(begin) + i * chunk;
+        c.count = std::min<uint64_t>(chunk, total - i * chunk);
+        return c;
+    };
+    auto launch = [&](char* stage, const AccessArgs& c) {
+        if (dt == SV_C64)
+            launch_access<float>(h, psi, stage, c, set);
+        else
+            launch_access<double>(h, psi, stage, c, set);
+    };
+    if (!set) {
+        // chunk i: gather into dstage, copy to hstage, event; the host copies
+        // chunk i out of hstage while chunk i + 1 is on the device
+        auto issue = [&](uint64_t i) {
+            const int sl = int(i & 1);
+            const AccessArgs c = args_of(i);
+            launch(dstage[sl], c);
+            SV_HIP(hipMemcpyAsync(hstage[sl], dstage[sl], c.count * amp, hipMemcpyDeviceToHost, h->stream));
+            SV_HIP(hipEventRecord(h->acc_event[sl], h->stream));
+        };
+        for (uint64_t i = 0; i < std::min<uint64_t>(2, n_chunks); ++i) issue(i);
+        for (uint64_t i = 0; i < n_chunks; ++i) {
+            const int sl = int(i & 1);
+            SV_HIP(hipEventSynchronize(h->acc_event[sl]));
+            const AccessArgs c = args_of(i);
+            host_copy(hb + i * chunk * amp, hstage[sl], c.count * amp);
+            if (i + 2 < n_chunks) issue(i + 2);
+        }
+    } else {
+        // chunk i: the host fills hstage (once its previous copy to the
+        // device is done), then copy to dstage, event, scatter
+        for (uint64_t i = 0; i < n_chunks; ++i) {
+            const int sl = int(i & 1);
+            if (i >= 2) SV_HIP(hipEventSynchronize(h->acc_event[sl]));
+            const AccessArgs c = args_of(i);
+            host_copy(hstage[sl], hb + i * chunk * amp, c.count * amp);
+            SV_HIP(hipMemcpyAsync(dstage[sl], hstage[sl], c.count * amp, hipMemcpyHostToDevice, h->stream));
+            SV_HIP(hipEventRecord(h->acc_event[sl], h->stream));
+            launch(dstage[sl], c);
+        }
+    }
+    SV_HIP(hipStreamSynchronize(h->stream));
 }
 
 }  // namespace sv

@@ -3,9 +3,11 @@
 Compiles tests/tile_geometry_check.hip, which includes the library's
 sv_apply.hip and replays the tile kernels' index arithmetic on the CPU with
 the tile arguments the library builds (plain, spread and strided layouts,
-every tile shape), and runs it.  A layout that drops, duplicates or
-misplaces an amplitude, or puts a group member anywhere but its base plus
-its target bits, fails here before any kernel runs with it.
+every tile shape), and runs it: every tile of states up to 7 qubits above
+the tile, and a sample of 64 tiles of states up to 34 qubits (targets up to
+the top qubit).  A layout that drops, duplicates or misplaces an amplitude,
+or puts a group member anywhere but its base plus its target bits, fails
+here before any kernel runs with it.
 """
 import os
 import shutil

@@ -109,6 +109,61 @@ static void check(int n, int tb, int min_L, const std::vector<int>& tg, int spre
     }
 }
 
+// The same checks on a sample of the tiles, for states too large to
+// enumerate (up to 34 qubits): the first, the last and 62 random tiles; the
+// amplitudes of distinct sampled tiles must all differ and lie below 2^n.
+static void check_sampled(int n, int tb, int min_L, const std::vector<int>& tg, int spread, bool strided, int cu,
+                          std::mt19937_64& rng)
+{
+    GateDesc d{};
+    d.n = n;
+    d.k = int(tg.size());
+    for (int a = 0; a < d.k; ++a) d.tbit[a] = uint64_t(1) << tg[a];
+    const TileArgs t = make_tile_args(d, n, tb, cu, spread, strided);
+    if (t.L < min_L) return fail("run shorter than a wave (sampled)", n, tb, tg, spread, strided);
+    if (t.L + t.n_hi != tb || t.n_lo != d.k) return fail("tile bit counts (sampled)", n, tb, tg, spread, strided);
+    if (t.n_tiles != (uint64_t(1) << (n - tb))) return fail("tile count (sampled)", n, tb, tg, spread, strided);
+    strided_used += t.trot > 0;
+    const uint64_t N = uint64_t(1) << n;
+    const uint64_t T = uint64_t(1) << tb;
+    const uint64_t mask = (uint64_t(1) << t.L) - 1;
+    uint64_t tbits = 0;
+    for (int a = 0; a < d.k; ++a) tbits |= d.tbit[a];
+    std::vector<uint64_t> tiles = {0, t.n_tiles - 1};
+    for (int r = 0; r < 62; ++r) tiles.push_back(rng() % t.n_tiles);
+    std::sort(tiles.begin(), tiles.end());
+    tiles.erase(std::unique(tiles.begin(), tiles.end()), tiles.end());
+    std::vector<uint64_t> all;
+    all.reserve(tiles.size() * T);
+    std::vector<uint8_t> lseen(T);
+    for (uint64_t tile : tiles) {
+        const uint64_t base = h_tile_base(tile, t);
+        auto glob = [&](uint64_t i) { return base + h_deposit(i >> t.L, t.hi_pos, t.n_hi) + (i & mask); };
+        for (uint64_t i = 0; i < T; ++i) {
+            const uint64_t gi = glob(i);
+            if (gi >= N) return fail("tile coverage (sampled)", n, tb, tg, spread, strided);
+            all.push_back(gi);
+        }
+        std::fill(lseen.begin(), lseen.end(), 0);
+        for (uint64_t g = 0; g < (T >> d.k); ++g) {
+            const uint64_t pb = h_insert(g, t.lo_pos, t.n_lo);
+            const uint64_t g0 = glob(pb);
+            if (pb >= T || (g0 & tbits)) return fail("group base (sampled)", n, tb, tg, spread, strided);
+            for (int c = 0; c < (1 << d.k); ++c) {
+                const uint64_t li = pb + uint64_t(t.lds_off[c]);
+                uint64_t want = g0;
+                for (int a = 0; a < d.k; ++a)
+                    if ((c >> a) & 1) want |= d.tbit[a];
+                if (li >= T || lseen[li] || glob(li) != want) return fail("group member (sampled)", n, tb, tg, spread, strided);
+                lseen[li] = 1;
+            }
+        }
+    }
+    std::sort(all.begin(), all.end());
+    if (std::adjacent_find(all.begin(), all.end()) != all.end())
+        return fail("tiles overlap (sampled)", n, tb, tg, spread, strided);
+}
+
 int main()
 {
     // (tile bits, targets, min run width) of every tile kernel
@@ -140,6 +195,30 @@ int main()
                     ++cases;
                 }
             }
-    printf("cases %d fails %d spread-layout %d strided %d\n", cases, fails, spread_used, strided_used);
+    // large states, sampled tiles: targets anywhere up to the top qubit
+    std::mt19937_64 rng64(11);
+    int sampled = 0;
+    for (const Shape& sh : shapes)
+        for (int n : {sh.tb + 8, 24, 28, 31, 33, 34}) {
+            if (n <= sh.tb + 7) continue;
+            for (int layout = 0; layout < 4; ++layout) {
+                const int spread = (layout & 1) ? 12 : 0;
+                const bool strided = (layout & 2) != 0;
+                for (int rep = 0; rep < 3; ++rep) {
+                    std::vector<int> q(n);
+                    for (int i = 0; i < n; ++i) q[i] = i;
+                    std::shuffle(q.begin(), q.end(), rng);
+                    std::vector<int> tg(q.begin(), q.begin() + sh.k);
+                    if (rep == 0) tg[0] = n - 1;  // the top qubit
+                    std::sort(tg.begin(), tg.end());
+                    tg.erase(std::unique(tg.begin(), tg.end()), tg.end());
+                    if (int(tg.size()) != sh.k) continue;
+                    check_sampled(n, sh.tb, sh.min_L, tg, spread, strided, (rep & 1) ? 1 : 256, rng64);
+                    ++sampled;
+                }
+            }
+        }
+    printf("cases %d sampled %d fails %d spread-layout %d strided %d\n", cases, sampled, fails, spread_used,
+           strided_used);
     return (fails == 0 && spread_used > 0 && strided_used > 0) ? 0 : 1;
 }
