@@ -1,7 +1,9 @@
 """Continuous-batching server for circuit requests on one GPU.
 
 Requests (a named-gate circuit on n qubits, Pauli strings to evaluate, and
-uniforms to sample with) arrive over time.  A dispatcher admits them in
+uniforms to sample with) arrive over time.  Each is fused on a host thread
+pool as soon as it arrives, so fusion overlaps its wait for admission and
+the device work of other requests.  A dispatcher admits them in
 arrival order as soon as a slot is free and the request's state fits the
 HBM budget; later requests may pass a blocked head only a bounded number of
 times, so large requests do not starve.  Some slots may be kept for small
@@ -23,6 +25,7 @@ import collections
 import os
 import threading
 import time
+from concurrent.futures import Future, ThreadPoolExecutor
 from dataclasses import dataclass
 
 import numpy as np
@@ -76,6 +79,7 @@ class Request:
     terms: list
     uniforms: np.ndarray
     arrival: float = 0.0          # host monotonic time of arrival (set on submit)
+    fused: Future | None = None   # the fused program, being made on the fusion pool (set on submit)
 
 
 @dataclass
@@ -182,7 +186,8 @@ class Server:
     rejected."""
 
     def __init__(self, slots: int = 4, budget_bytes: int | None = None, dtype: str = "c64", kmax: int = 5,
-                 max_bypass: int = 8, max_qubits: int = 28, small_slots: int = 0, small_qubits: int = 16):
+                 max_bypass: int = 8, max_qubits: int = 28, small_slots: int = 0, small_qubits: int = 16,
+                 fuse_threads: int = 4):
         import torch
         self.dtype = dtype
         self.kmax = kmax
@@ -198,6 +203,7 @@ class Server:
         self.results = {}        # rid -> Result
         self.ready = {False: collections.deque(), True: collections.deque()}  # admitted, per slot class
         self.stop = False
+        self.fuse_pool = ThreadPoolExecutor(max_workers=fuse_threads) if kmax > 0 else None
         n_workers = slots + small_slots
         self.handles = [Handle(stream=torch.cuda.Stream()) for _ in range(n_workers)]
         self.workers = [threading.Thread(target=self._worker, args=(i, i >= slots), daemon=True)
@@ -218,6 +224,8 @@ class Server:
         req.arrival = time.monotonic()
         with self.cv:
             self.adm.add(req.rid, self.footprint(req.n), req.n <= self.small_qubits)
+            if self.fuse_pool is not None:
+                req.fused = self.fuse_pool.submit(fuse, req.gates, self.kmax)
             self.pending[req.rid] = req
             self.cv.notify_all()
 
@@ -256,8 +264,13 @@ class Server:
                 self.cv.notify_all()
 
     def _run(self, h: Handle, req: Request, admitted: float) -> Result:
-        st = State(h, req.n, self.dtype)
-        f = fuse(req.gates, self.kmax) if self.kmax > 0 else None
+        f = req.fused.result() if req.fused is not None else None
+        try:
+            st = State(h, req.n, self.dtype)
+        except Exception:
+            if f is not None:
+                f.free()
+            raise
         try:
             if f is not None:
                 sv_apply_fused(st.s, f.f)
@@ -290,6 +303,8 @@ class Server:
         self.dispatcher.join()
         for w in self.workers:
             w.join()
+        if self.fuse_pool is not None:
+            self.fuse_pool.shutdown(wait=True)
         for h in self.handles:
             h.close()
 

@@ -137,6 +137,7 @@ def test_rejected_request_leaves_no_state():
     srv.dtype = "c64"
     srv.max_qubits = 28
     srv.small_qubits = 0
+    srv.fuse_pool = None
     srv.adm = Admission(1 << 20, 1)
     with pytest.raises(ValueError):
         srv.submit(serve.Request(7, 20, [], [], None))     # 8 MiB > 1 MiB
@@ -146,3 +147,32 @@ def test_rejected_request_leaves_no_state():
     assert srv.pending == {}
     srv.submit(serve.Request(9, 10, [], [], None))
     assert list(srv.pending) == [9] and list(srv.adm.queue) == [(9, 8 << 10, False)]
+
+
+def test_submit_starts_fusion_on_the_pool():
+    # an admitted request is fused on the host pool right away (libsv's
+    # host fuser runs without a GPU); a rejected one starts nothing
+    from concurrent.futures import ThreadPoolExecutor
+    import threading
+
+    import workloads as W
+    srv = serve.Server.__new__(serve.Server)
+    srv.cv = threading.Condition()
+    srv.pending = {}
+    srv.dtype = "c64"
+    srv.max_qubits = 28
+    srv.small_qubits = 0
+    srv.kmax = 5
+    srv.fuse_pool = ThreadPoolExecutor(max_workers=1)
+    srv.adm = Admission(1 << 20, 1)
+    gates = W.brickwork(10, 6, 3)
+    srv.submit(serve.Request(1, 10, gates, [], None))
+    f = srv.pending[1].fused.result(timeout=60)
+    try:
+        assert 0 < f.count <= len(gates)
+    finally:
+        f.free()
+    with pytest.raises(ValueError):
+        srv.submit(serve.Request(2, 20, gates, [], None))   # 8 MiB > 1 MiB
+    assert 2 not in srv.pending
+    srv.fuse_pool.shutdown(wait=True)
