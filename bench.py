@@ -40,13 +40,13 @@ HBM_PEAK_GBS = 8000.0
 _K5_SOURCES = {"paper_2308_01999_amd/csrc/sv_apply.hip":
                "85353f05b4dde9a2e25210ff1c61db0ca5c87b6ed0188fee5334b05aebb09f8e",
                "paper_2308_01999_amd/csrc/sv_tile.h":
-               "666e279461e0e28b6f6fec1e309576162839c3bd41b1dca9e6f1de30a5c9b6d7"}
+               "d60bf5b71681c7000bafd8f3fd58e0b64288e10c23283db46ed2803a25f8675b"}
 PMC_TRAFFIC = {
     # 30-qubit brickwork sweep, dispatch-weighted over all tile variants (676
     # launches of each dtype in one pass: 13 steps of 52 blocks)
-    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194398.5, "write_kib": 8389610.9,
+    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194398.4, "write_kib": 8389595.1,
                       "fetch_scale": 2.0, "write_scale": 1.0, "sources": _K5_SOURCES},
-    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388720.9, "write_kib": 16780255.6,
+    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388720.9, "write_kib": 16780129.8,
                        "fetch_scale": 2.0, "write_scale": 1.0, "sources": _K5_SOURCES},
 }
 
@@ -112,6 +112,8 @@ def parse():
                     help="skip the unfused / kmax 4, 5, 6 comparison on the same circuit")
     ap.add_argument("--gate-sweep", action="store_true",
                     help="also time single k-qubit gates (k = 1..6) on random target sets, both dtypes")
+    ap.add_argument("--seeds", type=int, default=10,
+                    help="also run the headline circuit at seeds 0..K-1 (fused, one timed pass each, both dtypes)")
     ap.add_argument("--sweep-sets", type=int, default=100)
     ap.add_argument("--sweep-n64", type=int, default=None,
                     help="qubits of the gate sweep's complex64 state (default: --n; the paper's Fig. 2: 33)")
@@ -285,6 +287,36 @@ def run_leg(P, W, torch, H, gates, n, dt, kmax, shots, steps, warmup):
     }
     state = st
     return out, state
+
+
+def seeds_leg(P, W, torch, H, n, depth, kmax, seeds):
+    """The headline circuit at seeds 0..seeds-1 (the brickwork construction
+    with other angles: the same qubit windows, so the handle's tile choices
+    from the timed legs carry over), fused at kmax, one pass each from
+    |0..0>, timed with HIP events on the handle's stream, complex64 and
+    complex128: GB/s of the fused sweeps per seed."""
+    import numpy as np
+    out = {}
+    for dt, s in (("c64", 8), ("c128", 16)):
+        st = P.State(H, n, dt)
+        sweep = 2 * (1 << n) * s
+        vals = []
+        for seed in range(seeds):
+            f = P.fuse(W.brickwork(n, depth, seed), kmax)
+            P.sv_set_basis_state(st.s, 0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(H.stream)
+            P.sv_apply_fused(st.s, f.f)
+            e1.record(H.stream)
+            e1.synchronize()
+            vals.append(f.count * sweep / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+            f.free()
+        st.close()
+        out[dt] = {"seeds": seeds, "mean_GBps": round(float(np.mean(vals)), 1),
+                   "min_GBps": round(float(np.min(vals)), 1), "max_GBps": round(float(np.max(vals)), 1),
+                   "mean_frac_of_8TBps": round(float(np.mean(vals)) / HBM_PEAK_GBS, 4)}
+        torch.cuda.synchronize()
+    return out
 
 
 def kmax_leg(P, W, torch, H, gates, n):
@@ -1118,6 +1150,9 @@ def main():
         print("[bench] unfused / kmax sweep", file=sys.stderr, flush=True)
         # on the main handle, whose k = 5 tile choices for this circuit are settled
         line["fusion_widths"] = kmax_leg(P, W, torch, H, gates, n)
+    if args.seeds > 0 and not args.no_c128:
+        print(f"[bench] seeds 0-{args.seeds - 1}", file=sys.stderr, flush=True)
+        line["seeds"] = seeds_leg(P, W, torch, H, n, depth, kmax, args.seeds)
     H.close()
     print("[bench] graph leg", file=sys.stderr, flush=True)
     H5 = P.Handle()

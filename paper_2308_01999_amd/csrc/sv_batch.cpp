@@ -400,9 +400,11 @@ BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>
         if (cum > kShortShare * total) break;
     }
     std::reverse(H.order.begin() + std::ptrdiff_t(n_short), H.order.end());
-    // Level path: launch l sweeps block l of every circuit that has one, the
-    // circuits with the most blocks first; after it, the circuits whose last
-    // block it was are reduced.
+    // Level path: launch l sweeps block l of every circuit that has one;
+    // after it, the circuits whose last block it was are reduced.  In a
+    // launch, the circuits that end there come first (their tiles also take
+    // the Z-type sums, so they should not be the launch's last
+    // workgroups), then the others, most blocks first.
     std::vector<size_t> lorder(level_circuits.size());
     std::iota(lorder.begin(), lorder.end(), size_t(0));
     std::stable_sort(lorder.begin(), lorder.end(), [&](size_t a, size_t b) {
@@ -414,9 +416,13 @@ BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>
         BatchLevel L;
         L.entry0 = H.entries.size();
         L.finish0 = H.finish.size();
-        for (size_t q : lorder) {
+        std::vector<size_t> here;
+        for (size_t q : lorder)
+            if (H.circuits[level_circuits[q]].n_blocks == l + 1) here.push_back(q);
+        for (size_t q : lorder)
+            if (H.circuits[level_circuits[q]].n_blocks > l + 1) here.push_back(q);
+        for (size_t q : here) {
             const BatchCircuit& c = H.circuits[level_circuits[q]];
-            if (c.n_blocks <= l) continue;
             const uint32_t di = level_first[q] + l;
             const TileArgs& t = H.tdescs[di].t;
             const uint64_t n_wg = (t.n_tiles + t.tiles_per_wg - 1) / t.tiles_per_wg;

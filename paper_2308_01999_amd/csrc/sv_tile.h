@@ -346,6 +346,10 @@ __device__ __forceinline__ void tile_c64_k5_sweep(float2* __restrict__ psi, cons
             const int mask = (1 << a.L) - 1;
             for (int t0 = 0; t0 == 0 || t0 < zs.n_terms; t0 += 8) {
                 double s[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                // the pass's masks, loaded once (not once per vector)
+                uint64_t mk[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) mk[t] = t0 + t < zs.n_terms ? zs.zm[t0 + t] : 0;
                 // one vector at a time (the next tile's loads are in flight
                 // in registers meanwhile); its global index recomputed from
                 // its tile position as tile_offsets does
@@ -360,7 +364,7 @@ __device__ __forceinline__ void tile_c64_k5_sweep(float2* __restrict__ psi, cons
 #pragma unroll
                     for (int t = 0; t < 8; ++t) {
                         if (t0 + t < zs.n_terms) {
-                            const uint64_t m = zs.zm[t0 + t];
+                            const uint64_t m = mk[t];
                             s[t] = __dadd_rn(s[t], (__popcll(g & m) & 1) ? -q0 : q0);
                             s[t] = __dadd_rn(s[t], (__popcll((g + 1) & m) & 1) ? -q1 : q1);
                         }
