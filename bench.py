@@ -805,6 +805,23 @@ def large_leg(P, W, torch, H):
             out[dt][label] = {"gates": len(g), "fused_blocks": fc.count, "apply_ms": round(ms, 1),
                               "GBps": round(fc.count * sweep / (ms * 1e-3) / 1e9, 1)}
             fc.free()
+        # 2^20 samples of the QFT's output state from seeded uniforms, in
+        # device memory (one untimed call, then one timed)
+        with torch.cuda.stream(H.stream):
+            du = torch.from_numpy(W.uniforms(1 << 20, 7)).to("cuda")
+            dsmp = torch.empty(1 << 20, dtype=torch.int64, device="cuda")
+        H.stream.synchronize()
+        P.sv_sample_device(st.s, du.data_ptr(), 1 << 20, dsmp.data_ptr())
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(H.stream)
+        P.sv_sample_device(st.s, du.data_ptr(), 1 << 20, dsmp.data_ptr())
+        e1.record(H.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        out[dt]["sample_2^20"] = {"ms": round(ms, 2),
+                                  "state_read_GBps": round((1 << n) * ab / (ms * 1e-3) / 1e9, 1),
+                                  "note": "uniforms and outcomes in device memory; the state after the QFT"}
+        del du, dsmp
         st.close()
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
