@@ -471,6 +471,58 @@ __global__ __launch_bounds__(kThreads) void k_block_prefix(const typename Cx<R>:
     }
 }
 
+// Block prefixes C and chunk totals S for chunks of whole segments of
+// kSegBlocks blocks of kBlk amplitudes (states of >= 14 qubits): one
+// workgroup per chunk, one block per thread.  Each thread sums its block's
+// probabilities in index order straight from its loads (no LDS staging),
+// then the waves extend the chunk's running prefix over their blocks in
+// order, lane by lane, wave after wave, segment after segment: the same
+// sums in the same order as k_block_prefix, so C and S are bitwise the same.
+constexpr int kSegBlocks = kThreads;  // blocks per segment (one per thread)
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_block_prefix_rows(const typename Cx<R>::T* __restrict__ psi,
+                                                               SampleLayout L, double* __restrict__ C,
+                                                               double* __restrict__ S)
+{
+    using T2 = typename Cx<R>::T;
+    constexpr int kQ = sizeof(R) == 4 ? 16 : 8;  // amplitudes loaded at a time
+    __shared__ double carry_out;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t c = blockIdx.x;
+    const uint64_t nseg = L.nbk / kSegBlocks;
+    double carry = 0.0;  // the chunk's running prefix (uniform)
+    for (uint64_t sg = 0; sg < nseg; ++sg) {
+        const uint64_t b = sg * kSegBlocks + uint64_t(tid);
+        const T2* blk = psi + c * L.cs + b * kBlk;
+        double sum = 0.0;
+        for (int j0 = 0; j0 < kBlk; j0 += kQ) {
+            T2 v[kQ];
+#pragma unroll
+            for (int j = 0; j < kQ; ++j) v[j] = blk[j0 + j];
+#pragma unroll
+            for (int j = 0; j < kQ; ++j) sum = __dadd_rn(sum, prob(v[j]));
+        }
+        // wave w extends the prefix over its 64 blocks once waves 0..w-1 have
+        for (int w = 0; w < kSegBlocks / 64; ++w) {
+            if (wave == w) {
+                if (w > 0) carry = carry_out;
+                double mine = 0.0;
+                for (int l = 0; l < 64; ++l) {
+                    carry = __dadd_rn(carry, readlane_f64(sum, l));
+                    if (lane == l) mine = carry;
+                }
+                C[c * L.nbk + b] = mine;
+                if (lane == 0) carry_out = carry;
+            }
+            __syncthreads();
+        }
+        carry = carry_out;
+        __syncthreads();
+    }
+    if (tid == 0) S[c] = carry;
+}
+
 constexpr int kScanThreads = 1024;
 constexpr int kScanRound = 8192;                      // chunk totals staged in LDS per round
 constexpr int kScanPad = kScanRound + kScanRound / 64;  // one pad slot per 64
@@ -1047,8 +1099,12 @@ void sample_core(hipStream_t stream, int cu_count, const void* psi_v, int n, con
     using T2 = typename Cx<R>::T;
     const T2* psi = static_cast<const T2*>(psi_v);
     const SampleLayout L = sample_layout(n);
-    hipLaunchKernelGGL((k_block_prefix<R>), dim3(unsigned(std::min<uint64_t>(L.nc, uint64_t(cu_count) * 8))),
-                       dim3(kThreads), 0, stream, psi, L, sb.C, sb.S);
+    if (L.w == kBlk && L.nbk % kSegBlocks == 0)
+        hipLaunchKernelGGL((k_block_prefix_rows<R>), dim3(unsigned(L.nc)), dim3(kThreads), 0, stream, psi, L, sb.C,
+                           sb.S);
+    else
+        hipLaunchKernelGGL((k_block_prefix<R>), dim3(unsigned(std::min<uint64_t>(L.nc, uint64_t(cu_count) * 8))),
+                           dim3(kThreads), 0, stream, psi, L, sb.C, sb.S);
     SV_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(kScanThreads), 0, stream, sb.S, L.nc, sb.B);
     SV_HIP(hipGetLastError());
