@@ -161,6 +161,51 @@ void left_multiply(BlockMatrix& U, const HostGate& g, const std::vector<int>& po
             if ((r >> a) & 1) o |= uint64_t(1) << pos_t[a];
         off[r] = o;
     }
+    if (k <= 2) {
+        // one and two targets (nearly every named gate): the group's rows
+        // are combined in registers, column by column, with no staging
+        double mr[16], mi[16];
+        for (int e = 0; e < d * d; ++e) {
+            mr[e] = g.m[size_t(e)].real();
+            mi[e] = g.m[size_t(e)].imag();
+        }
+        for (uint64_t row = 0; row < dim; ++row) {
+            if ((row & tmask) || (row & cmask) != cset) continue;
+            double* __restrict pr[4];
+            double* __restrict pi[4];
+            for (int r = 0; r < d; ++r) {
+                pr[r] = &U.re[(row + off[r]) * dim];
+                pi[r] = &U.im[(row + off[r]) * dim];
+            }
+            if (k == 1) {
+                for (uint64_t col = 0; col < dim; ++col) {
+                    const double x0r = pr[0][col], x0i = pi[0][col], x1r = pr[1][col], x1i = pi[1][col];
+                    pr[0][col] = mr[0] * x0r - mi[0] * x0i + (mr[1] * x1r - mi[1] * x1i);
+                    pi[0][col] = mr[0] * x0i + mi[0] * x0r + (mr[1] * x1i + mi[1] * x1r);
+                    pr[1][col] = mr[2] * x0r - mi[2] * x0i + (mr[3] * x1r - mi[3] * x1i);
+                    pi[1][col] = mr[2] * x0i + mi[2] * x0r + (mr[3] * x1i + mi[3] * x1r);
+                }
+            } else {
+                for (uint64_t col = 0; col < dim; ++col) {
+                    double xr[4], xi[4];
+                    for (int c = 0; c < 4; ++c) {
+                        xr[c] = pr[c][col];
+                        xi[c] = pi[c][col];
+                    }
+                    for (int r = 0; r < 4; ++r) {
+                        double yr = 0.0, yi = 0.0;
+                        for (int c = 0; c < 4; ++c) {
+                            yr += mr[4 * r + c] * xr[c] - mi[4 * r + c] * xi[c];
+                            yi += mr[4 * r + c] * xi[c] + mi[4 * r + c] * xr[c];
+                        }
+                        pr[r][col] = yr;
+                        pi[r][col] = yi;
+                    }
+                }
+            }
+        }
+        return;
+    }
     thread_local std::vector<double> in_re, in_im;
     in_re.resize(size_t(d) * dim);
     in_im.resize(size_t(d) * dim);

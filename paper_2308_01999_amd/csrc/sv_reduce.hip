@@ -472,8 +472,8 @@ __global__ __launch_bounds__(kThreads) void k_block_prefix(const typename Cx<R>:
 }
 
 // Block prefixes C and chunk totals S for chunks of whole segments of
-// kSegBlocks blocks of kBlk amplitudes (states of >= 14 qubits): one
-// workgroup per chunk, one block per thread.  Each thread sums its block's
+// kSegBlocks blocks of kBlk amplitudes (complex64 states of >= 14 qubits):
+// one workgroup per chunk, one block per thread.  Each thread sums its block's
 // probabilities in index order straight from its loads (no LDS staging),
 // then the waves extend the chunk's running prefix over their blocks in
 // order, lane by lane, wave after wave, segment after segment: the same
@@ -1099,7 +1099,11 @@ void sample_core(hipStream_t stream, int cu_count, const void* psi_v, int n, con
     using T2 = typename Cx<R>::T;
     const T2* psi = static_cast<const T2*>(psi_v);
     const SampleLayout L = sample_layout(n);
-    if (L.w == kBlk && L.nbk % kSegBlocks == 0)
+    // complex64 rows (512 B per thread) stream well from the threads'
+    // own loads; complex128 rows (1 KB) lose lines to eviction before
+    // their threads have read them (1.46x the bytes in the HBM counters)
+    // and take the LDS-staged sweep
+    if (sizeof(R) == 4 && L.w == kBlk && L.nbk % kSegBlocks == 0)
         hipLaunchKernelGGL((k_block_prefix_rows<R>), dim3(unsigned(L.nc)), dim3(kThreads), 0, stream, psi, L, sb.C,
                            sb.S);
     else
