@@ -461,7 +461,10 @@ sv_status_t sv_expect_pauli(sv_state_t s, const sv_pauli_term_t* terms, int32_t 
  * |psi_j|^2 over j <= i and N its total; zero-probability indices are never
  * returned.  With bit_ordering (q_0 .. q_{m-1}, distinct), bit a of each
  * output is bit q_a of the outcome; NULL returns the full index.  Outputs
- * are in the order of the uniforms.  Blocks.
+ * are in the order of the uniforms.  A uniform outside [0, 1) is rejected
+ * (SV_ERR_INVALID_VALUE) before any device work; a state of zero norm is
+ * reported (SV_ERR_INVALID_VALUE) once the sampler has run, and out's
+ * contents are then unspecified.  Blocks.
  */
 sv_status_t sv_sample(sv_state_t s, const double* uniforms, int64_t n_shots,
                       const int32_t* bit_ordering, int32_t n_bits, uint64_t* out);
