@@ -292,15 +292,18 @@ uint32_t add_level_circuit(BatchHost& H, const BatchCircuit& c, const sv_fused_s
         BatchTileDesc td{};
         // the single-state sweep's narrow tiles, in the spread or the plain
         // layout; a workgroup takes tiles_per_wg tiles in strided order
+        // (the circuit's last block one tile per workgroup: its Z-type sums
+        // are then kept per tile, in an order that no plan changes)
         td.t = make_tile_args(d, c.n, 12, cu_count, s.spread ? 12 : 0, false);
-        td.t.tiles_per_wg = std::min<uint64_t>(uint64_t(s.tiles_per_wg), td.t.n_tiles);
+        const bool last = bi + 1 == f->n_blocks;
+        td.t.tiles_per_wg = last ? 1 : std::min<uint64_t>(uint64_t(s.tiles_per_wg), td.t.n_tiles);
         td.t.trot = 0;
         while ((uint64_t(1) << td.t.trot) < td.t.tiles_per_wg) ++td.t.trot;
         td.state_off = c.state_off;
         td.term0 = c.term0;
         td.n_terms = -1;
         td.red_off = 0;
-        if (bi + 1 == f->n_blocks) {
+        if (last) {
             td.n_terms = int32_t(c.n_terms);
             td.red_off = H.n_partials;
             const uint64_t n_wg = (td.t.n_tiles + td.t.tiles_per_wg - 1) / td.t.tiles_per_wg;
@@ -412,6 +415,33 @@ BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>
     });
     uint32_t depth = 0;
     for (uint32_t j : level_circuits) depth = std::max(depth, H.circuits[j].n_blocks);
+    // A level with few tiles (the last levels, where a few deep circuits are
+    // left) takes fewer tiles per workgroup, so that it still has about four
+    // rounds of workgroups for the device: at most its tiles / (4 x the
+    // workgroups that fit at once, three per CU), a power of two.  Only the
+    // schedule changes, not the arithmetic (the last blocks, which keep Z
+    // sums, already take one tile per workgroup).
+    {
+        std::vector<uint64_t> level_tiles(depth, 0);
+        for (size_t q = 0; q < level_circuits.size(); ++q) {
+            const BatchCircuit& c = H.circuits[level_circuits[q]];
+            for (uint32_t l = 0; l < c.n_blocks; ++l) level_tiles[l] += H.tdescs[level_first[q] + l].t.n_tiles;
+        }
+        const uint64_t fill = uint64_t(cu_count) * 3 * 4;
+        for (size_t q = 0; q < level_circuits.size(); ++q) {
+            const BatchCircuit& c = H.circuits[level_circuits[q]];
+            for (uint32_t l = 0; l + 1 < c.n_blocks; ++l) {
+                TileArgs& t = H.tdescs[level_first[q] + l].t;
+                uint64_t cap = 1;
+                while (cap * 2 * fill <= level_tiles[l]) cap *= 2;
+                if (t.tiles_per_wg > cap) {
+                    t.tiles_per_wg = cap;
+                    t.trot = 0;
+                    while ((uint64_t(1) << t.trot) < t.tiles_per_wg) ++t.trot;
+                }
+            }
+        }
+    }
     for (uint32_t l = 0; l < depth; ++l) {
         BatchLevel L;
         L.entry0 = H.entries.size();

@@ -448,22 +448,37 @@ __global__ __launch_bounds__(tile::kTileThreads, 3) void k_batch_level(float2* _
                                                        amat, zs);
 }
 
-// Level path: a finished circuit's expectations from its workgroups' sums
-// (in workgroup order), then its completion time.
+// Level path: a finished circuit's expectations from its workgroups' sums,
+// then its completion time.  Thread (g, c) of G = kThreads / S groups of S =
+// n_terms + 1 columns (the norm last) adds the rows g, g + G, ... of column
+// c; the groups' sums are then added in group order: a fixed order for a
+// given workgroup count.
 __global__ __launch_bounds__(kThreads) void k_batch_finish(BatchArgs A, const BatchFinish* __restrict__ fin)
 {
+    __shared__ double part[kThreads];
     __shared__ double nrm;
     const BatchFinish f = fin[blockIdx.x];
     const BatchCircuit c = A.circuits[f.circuit];
-    const int nt = int(c.n_terms);
+    const int nt = int(c.n_terms), S = nt + 1, G = kThreads / S;
+    const int tid = int(threadIdx.x), g = tid / S, col = tid - g * S;
     double v = 0.0;
-    if (int(threadIdx.x) <= nt)
-        for (uint32_t w = 0; w < f.n_wg; ++w) v = __dadd_rn(v, A.partials[f.red_off + uint64_t(w) * (nt + 1) + threadIdx.x]);
-    if (int(threadIdx.x) == nt) nrm = v;
+    if (g < G) {
+        const double* p = A.partials + f.red_off + col;
+#pragma unroll 4
+        for (uint32_t w = uint32_t(g); w < f.n_wg; w += uint32_t(G)) v = __dadd_rn(v, p[uint64_t(w) * S]);
+    }
+    part[tid] = v;
     __syncthreads();
-    if (int(threadIdx.x) < nt) A.expect[c.term0 + threadIdx.x] = v / nrm;
+    if (tid < S) {
+        double s = 0.0;
+        for (int q = 0; q < G; ++q) s = __dadd_rn(s, part[q * S + tid]);
+        v = s;
+        if (tid == nt) nrm = s;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) A.t_done[f.circuit] = wall_clock64();
+    if (tid < nt) A.expect[c.term0 + tid] = v / nrm;
+    __syncthreads();
+    if (tid == 0) A.t_done[f.circuit] = wall_clock64();
 }
 
 }  // namespace

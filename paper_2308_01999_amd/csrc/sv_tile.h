@@ -180,8 +180,9 @@ constexpr int kK5AParts = 3;
 // tiles in LDS (no extra read of the state): for a workgroup, out[t] =
 // sum over its amplitudes i of |psi_i|^2 (-1)^popcount(i & zm[t]) for
 // t < n_terms, and out[n_terms] = sum |psi_i|^2, all FP64 in a fixed order
-// (per thread, per wave by a butterfly, waves and tiles in order).  acc: LDS
-// of 4 x (kZSumsMax + 1) doubles.  n_terms < 0: no sums.
+// (per thread by a Walsh-Hadamard transform, per wave by a butterfly, waves
+// and tiles in order).  acc: LDS of 4 x (kZSumsMax + 1) doubles.
+// n_terms < 0: no sums.
 constexpr int kZSumsMax = 32;
 struct ZSums {
     const uint64_t* zm;
@@ -190,11 +191,17 @@ struct ZSums {
     double* acc;
 };
 
-__device__ __forceinline__ double wave_sum_f64(double v)
+// A double's bits as two floats and back (for LDS that the sweep accesses as
+// floats).
+__device__ __forceinline__ float2 f64_as_f32x2(double d)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = __dadd_rn(v, __shfl_xor(v, o, 64));
-    return v;
+    const uint64_t b = uint64_t(__double_as_longlong(d));
+    return float2{__uint_as_float(uint32_t(b)), __uint_as_float(uint32_t(b >> 32))};
+}
+__device__ __forceinline__ double f32x2_as_f64(float2 f)
+{
+    return __longlong_as_double(
+        static_cast<long long>(uint64_t(__float_as_uint(f.x)) | (uint64_t(__float_as_uint(f.y)) << 32)));
 }
 
 // L_a (units of pi, reduced to [-1, 1]) of the group whose base index (block
@@ -340,47 +347,88 @@ __device__ __forceinline__ void tile_c64_k5_sweep(float2* __restrict__ psi, cons
                    swap_pair(*reinterpret_cast<const float4*>(lds2 + pair_slot(i)), pair_swapped(i)));
         }
         if (zs.n_terms >= 0) {
-            // the tile is still in LDS: each wave adds its amplitudes' sums
-            // to its own row of acc, terms in passes of eight (the norm in
-            // the first pass)
-            const int mask = (1 << a.L) - 1;
-            for (int t0 = 0; t0 == 0 || t0 < zs.n_terms; t0 += 8) {
-                double s[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                // the pass's masks, loaded once (not once per vector)
-                uint64_t mk[8];
+            // The tile is still in LDS.  A thread's 16 amplitudes differ in
+            // the tile-local bits 0 and kUBit..kUBit+2 (amplitude j = e + 2u
+            // is element e of vector u) and share all others, so a term's
+            // sum over them is s * c[k]: c the Walsh-Hadamard transform of
+            // their probabilities over j, c[k] = sum_j p_j (-1)^popcount(j & k),
+            // k the term mask's bits at those four index bits, s its parity
+            // over the bits the 16 share.  The norm is the term of mask 0.
+            constexpr int kUBit = 1 + __builtin_ctz(NT);
+            static_assert(kTileVecs == 8, "the transform spans one pair bit and three vector bits");
+            double c[16];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) mk[t] = t0 + t < zs.n_terms ? zs.zm[t0 + t] : 0;
-                // one vector at a time (the next tile's loads are in flight
-                // in registers meanwhile); its global index recomputed from
-                // its tile position as tile_offsets does
-#pragma unroll 1
-                for (int u = 0; u < kTileVecs; ++u) {
-                    const int i = (u * NT + tid) * 2;
-                    const float4 v = swap_pair(*reinterpret_cast<const float4*>(lds2 + pair_slot(i)), pair_swapped(i));
-                    const uint64_t g = base + deposit_bits(uint32_t(i >> a.L), a.hi_pos, a.n_hi) + uint64_t(i & mask);
-                    const double q0 = fma(double(v.x), double(v.x), __dmul_rn(double(v.y), double(v.y)));
-                    const double q1 = fma(double(v.z), double(v.z), __dmul_rn(double(v.w), double(v.w)));
-                    s[8] = __dadd_rn(__dadd_rn(s[8], q0), q1);
+            for (int u = 0; u < kTileVecs; ++u) {
+                const int i = (u * NT + tid) * 2;
+                const float4 v = swap_pair(*reinterpret_cast<const float4*>(lds2 + pair_slot(i)), pair_swapped(i));
+                c[2 * u] = fma(double(v.x), double(v.x), __dmul_rn(double(v.y), double(v.y)));
+                c[2 * u + 1] = fma(double(v.z), double(v.z), __dmul_rn(double(v.w), double(v.w)));
+            }
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) {
-                        if (t0 + t < zs.n_terms) {
-                            const uint64_t m = mk[t];
-                            s[t] = __dadd_rn(s[t], (__popcll(g & m) & 1) ? -q0 : q0);
-                            s[t] = __dadd_rn(s[t], (__popcll((g + 1) & m) & 1) ? -q1 : q1);
-                        }
-                    }
+            for (int h = 1; h < 16; h <<= 1) {
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    if (j & h) continue;
+                    const double x = c[j], y = c[j | h];
+                    c[j] = __dadd_rn(x, y);
+                    c[j | h] = __dsub_rn(x, y);
                 }
-                double* row = zs.acc + wave * (kZSumsMax + 1);
+            }
+            // the coefficients take the thread's own slots (its amplitudes
+            // are read; no other thread reads these slots before the next
+            // barrier): c[2u], c[2u + 1] in vector u's slot, their bits
+            // moved as floats, the slots' type
+#pragma unroll
+            for (int u = 0; u < kTileVecs; ++u) {
+                float2* slot = lds2 + pair_slot((u * NT + tid) * 2);
+                slot[0] = f64_as_f32x2(c[2 * u]);
+                slot[1] = f64_as_f32x2(c[2 * u + 1]);
+            }
+            // global index of the thread's amplitude j = 0, and the global
+            // positions of the tile-local bits 0 and kUBit..kUBit+2
+            const int mask = (1 << a.L) - 1;
+            const uint64_t gt =
+                base + deposit_bits(uint32_t((tid * 2) >> a.L), a.hi_pos, a.n_hi) + uint64_t((tid * 2) & mask);
+            int jpos[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int b = q == 0 ? 0 : kUBit + q - 1;
+                jpos[q] = b < a.L ? b : a.hi_pos[b - a.L];
+            }
+            // terms (the norm last, as term n_terms) in passes of eight; a
+            // pass's wave sums by a reduce-scatter butterfly: after the
+            // exchanges over lane bits 5, 4, 3 a lane holds one term, term
+            // (lane >> 3) & 7 of the pass, summed over 8 lanes, and three
+            // more exchanges sum the rest
+            double* row = zs.acc + wave * (kZSumsMax + 1);
+            const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0, b3 = (lane & 8) != 0;
+            for (int p0 = 0; p0 <= zs.n_terms; p0 += 8) {
+                double v[8];
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
-                    if (t0 + t < zs.n_terms) {
-                        const double w = wave_sum_f64(s[t]);
-                        if (lane == 0) row[t0 + t] = __dadd_rn(row[t0 + t], w);
-                    }
+                    const int tt = p0 + t;
+                    const uint64_t m = tt < zs.n_terms ? zs.zm[tt] : 0;
+                    const int k = int((m >> jpos[0]) & 1) | int(((m >> jpos[1]) & 1) << 1) |
+                                  int(((m >> jpos[2]) & 1) << 2) | int(((m >> jpos[3]) & 1) << 3);
+                    const double x = f32x2_as_f64(lds2[pair_slot(((k >> 1) * NT + tid) * 2) + (k & 1)]);
+                    v[t] = tt > zs.n_terms ? 0.0 : ((__popcll(gt & m) & 1) ? -x : x);
                 }
-                if (t0 == 0) {
-                    const double w = wave_sum_f64(s[8]);
-                    if (lane == 0) row[kZSumsMax] = __dadd_rn(row[kZSumsMax], w);
+                double w4[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    w4[j] = __dadd_rn(b5 ? v[j + 4] : v[j], __shfl_xor(b5 ? v[j] : v[j + 4], 32, 64));
+                double w2[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    w2[j] = __dadd_rn(b4 ? w4[j + 2] : w4[j], __shfl_xor(b4 ? w4[j] : w4[j + 2], 16, 64));
+                double w = __dadd_rn(b3 ? w2[1] : w2[0], __shfl_xor(b3 ? w2[0] : w2[1], 8, 64));
+                w = __dadd_rn(w, __shfl_xor(w, 4, 64));
+                w = __dadd_rn(w, __shfl_xor(w, 2, 64));
+                w = __dadd_rn(w, __shfl_xor(w, 1, 64));
+                const int tt = p0 + ((lane >> 3) & 7);
+                if ((lane & 7) == 0 && tt <= zs.n_terms) {
+                    const int r = tt == zs.n_terms ? kZSumsMax : tt;
+                    row[r] = __dadd_rn(row[r], w);
                 }
             }
         }
