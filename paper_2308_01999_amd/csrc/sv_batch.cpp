@@ -291,24 +291,17 @@ uint32_t add_level_circuit(BatchHost& H, const BatchCircuit& c, const sv_fused_s
         for (int a = 0; a < 5; ++a) d.tbit[a] = uint64_t(1) << t5[a];
         BatchTileDesc td{};
         // the single-state sweep's narrow tiles, in the spread or the plain
-        // layout; a workgroup takes tiles_per_wg tiles in strided order
-        // (the circuit's last block one tile per workgroup: its Z-type sums
-        // are then kept per tile, in an order that no plan changes)
+        // layout; a workgroup takes tiles_per_wg tiles in strided order.
+        // The last block also takes the Z-type sums (its partial sums are
+        // placed once the level schedule is fixed).
         td.t = make_tile_args(d, c.n, 12, cu_count, s.spread ? 12 : 0, false);
-        const bool last = bi + 1 == f->n_blocks;
-        td.t.tiles_per_wg = last ? 1 : std::min<uint64_t>(uint64_t(s.tiles_per_wg), td.t.n_tiles);
+        td.t.tiles_per_wg = std::min<uint64_t>(uint64_t(s.tiles_per_wg), td.t.n_tiles);
         td.t.trot = 0;
         while ((uint64_t(1) << td.t.trot) < td.t.tiles_per_wg) ++td.t.trot;
         td.state_off = c.state_off;
         td.term0 = c.term0;
-        td.n_terms = -1;
+        td.n_terms = bi + 1 == f->n_blocks ? int32_t(c.n_terms) : -1;
         td.red_off = 0;
-        if (last) {
-            td.n_terms = int32_t(c.n_terms);
-            td.red_off = H.n_partials;
-            const uint64_t n_wg = (td.t.n_tiles + td.t.tiles_per_wg - 1) / td.t.tiles_per_wg;
-            H.n_partials += n_wg * (c.n_terms + 1);
-        }
         td.mat_off = H.tmats.size();
         H.tmats.resize(H.tmats.size() + mat_bytes / sizeof(float4));
         pack_matrix(SV_C64, c.n, 5, 0, m5, 0, H.tmats.data() + td.mat_off);
@@ -418,9 +411,10 @@ BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>
     // A level with few tiles (the last levels, where a few deep circuits are
     // left) takes fewer tiles per workgroup, so that it still has about four
     // rounds of workgroups for the device: at most its tiles / (4 x the
-    // workgroups that fit at once, three per CU), a power of two.  Only the
-    // schedule changes, not the arithmetic (the last blocks, which keep Z
-    // sums, already take one tile per workgroup).
+    // workgroups that fit at once, three per CU), a power of two.  Not a
+    // circuit's last block: the order of its Z-type sums follows its tiles
+    // per workgroup, which thus stays the plan's, whatever the rest of the
+    // batch.  The last block gets room for its workgroups' sums.
     {
         std::vector<uint64_t> level_tiles(depth, 0);
         for (size_t q = 0; q < level_circuits.size(); ++q) {
@@ -430,14 +424,19 @@ BatchHost build_host(const std::vector<CircuitInput>& in, const std::vector<int>
         const uint64_t fill = uint64_t(cu_count) * 3 * 4;
         for (size_t q = 0; q < level_circuits.size(); ++q) {
             const BatchCircuit& c = H.circuits[level_circuits[q]];
-            for (uint32_t l = 0; l + 1 < c.n_blocks; ++l) {
-                TileArgs& t = H.tdescs[level_first[q] + l].t;
+            for (uint32_t l = 0; l < c.n_blocks; ++l) {
+                BatchTileDesc& td = H.tdescs[level_first[q] + l];
+                TileArgs& t = td.t;
                 uint64_t cap = 1;
                 while (cap * 2 * fill <= level_tiles[l]) cap *= 2;
-                if (t.tiles_per_wg > cap) {
+                if (l + 1 < c.n_blocks && t.tiles_per_wg > cap) {
                     t.tiles_per_wg = cap;
                     t.trot = 0;
                     while ((uint64_t(1) << t.trot) < t.tiles_per_wg) ++t.trot;
+                }
+                if (l + 1 == c.n_blocks) {
+                    td.red_off = H.n_partials;
+                    H.n_partials += (t.n_tiles + t.tiles_per_wg - 1) / t.tiles_per_wg * (c.n_terms + 1);
                 }
             }
         }
