@@ -381,17 +381,17 @@ def sv_fused_block_coupling(f: int, i: int, k: int):
 
 def gate_list_arrays(gates):
     """Workload gates (named gates only) -> (codes, qubits, params) arrays."""
-    codes, qubits, params = [], [], []
-    for name, qs, ps in gates:
-        code = _GATE_CODE_OF.get(name)
-        if code is None:
-            raise KeyError(f"unknown gate {name!r}")
-        codes.append(code)
-        qubits.append((qs[0], qs[1] if len(qs) > 1 else 0))
-        params.append((tuple(ps) + (0.0, 0.0, 0.0))[:3])
-    G = len(codes)
-    return (np.array(codes, dtype=np.int32).reshape(G), np.array(qubits, dtype=np.int32).reshape(G, 2),
-            np.array(params, dtype=np.float64).reshape(G, 3))
+    G = len(gates)
+    try:
+        codes = np.fromiter((_GATE_CODE_OF[g[0]] for g in gates), dtype=np.int32, count=G)
+    except KeyError as e:
+        raise KeyError(f"unknown gate {e.args[0]!r}") from None
+    qubits = np.fromiter((x for g in gates for x in (g[1][0], g[1][1] if len(g[1]) > 1 else 0)),
+                         dtype=np.int32, count=2 * G).reshape(G, 2)
+    pad = (0.0, 0.0, 0.0)
+    params = np.fromiter((x for g in gates for x in (tuple(g[2]) + pad)[:3]),
+                         dtype=np.float64, count=3 * G).reshape(G, 3)
+    return codes, qubits, params
 
 
 def sv_fused_count(f: int) -> int:

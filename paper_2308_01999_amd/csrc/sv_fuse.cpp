@@ -143,7 +143,9 @@ struct BlockMatrix {
 // parts apart, so the inner loop is plain multiply-adds on contiguous
 // doubles.  No std::complex products: those would go through the C99
 // special-value path.
-void left_multiply(BlockMatrix& U, const HostGate& g, const std::vector<int>& pos_t, const std::vector<int>& pos_c)
+__attribute__((always_inline)) inline void left_multiply_body(BlockMatrix& U, const HostGate& g,
+                                                              const std::vector<int>& pos_t,
+                                                              const std::vector<int>& pos_c)
 {
     const int k = int(pos_t.size());
     const int d = 1 << k;
@@ -234,7 +236,80 @@ void left_multiply(BlockMatrix& U, const HostGate& g, const std::vector<int>& po
     }
 }
 
+// The same, built for AVX2 (four doubles per vector instruction; the same
+// operations in the same order, so the same results), taken where the CPU
+// has it.
+__attribute__((target("avx2"))) void left_multiply_avx2(BlockMatrix& U, const HostGate& g,
+                                                        const std::vector<int>& pos_t, const std::vector<int>& pos_c)
+{
+    left_multiply_body(U, g, pos_t, pos_c);
+}
+
+void left_multiply_base(BlockMatrix& U, const HostGate& g, const std::vector<int>& pos_t, const std::vector<int>& pos_c)
+{
+    left_multiply_body(U, g, pos_t, pos_c);
+}
+
+void left_multiply(BlockMatrix& U, const HostGate& g, const std::vector<int>& pos_t, const std::vector<int>& pos_c)
+{
+    static const bool avx2 = __builtin_cpu_supports("avx2");
+    if (avx2)
+        left_multiply_avx2(U, g, pos_t, pos_c);
+    else
+        left_multiply_base(U, g, pos_t, pos_c);
+}
+
 int popcount64(uint64_t v) { return __builtin_popcountll(v); }
+
+// Block selection's absorb count (see select_blocks) for several qubit sets
+// at once, over the gate masks m[0, n): one scan with one independent chain
+// per set (the chains overlap in the CPU where one set's scan would wait on
+// each step).  A set whose qubits are all blocked takes no further gate (a
+// gate inside it touches a blocked qubit), so scanning on past that point
+// changes none of its counts.  At most 64 sets.
+__attribute__((always_inline)) inline void count_absorbed_many_body(const uint64_t* m, size_t n,
+                                                                    const uint64_t* sets, int n_sets, int* counts)
+{
+    uint64_t blocked[64];
+    for (int c = 0; c < n_sets; ++c) {
+        blocked[c] = 0;
+        counts[c] = 0;
+    }
+    for (size_t j0 = 0; j0 < n; j0 += 8) {
+        const size_t j1 = std::min(n, j0 + 8);
+        for (size_t j = j0; j < j1; ++j) {
+            const uint64_t Q = m[j];
+            for (int c = 0; c < n_sets; ++c) {
+                const bool ok = (Q & (blocked[c] | ~sets[c])) == 0;
+                counts[c] += ok;
+                blocked[c] |= ok ? uint64_t(0) : Q;
+            }
+        }
+        bool open = false;
+        for (int c = 0; c < n_sets; ++c) open |= (sets[c] & ~blocked[c]) != 0;
+        if (!open) break;
+    }
+}
+
+__attribute__((target("avx2"))) void count_absorbed_many_avx2(const uint64_t* m, size_t n, const uint64_t* sets,
+                                                              int n_sets, int* counts)
+{
+    count_absorbed_many_body(m, n, sets, n_sets, counts);
+}
+
+void count_absorbed_many_base(const uint64_t* m, size_t n, const uint64_t* sets, int n_sets, int* counts)
+{
+    count_absorbed_many_body(m, n, sets, n_sets, counts);
+}
+
+void count_absorbed_many(const uint64_t* m, size_t n, const uint64_t* sets, int n_sets, int* counts)
+{
+    static const bool avx2 = __builtin_cpu_supports("avx2");
+    if (avx2)
+        count_absorbed_many_avx2(m, n, sets, n_sets, counts);
+    else
+        count_absorbed_many_base(m, n, sets, n_sets, counts);
+}
 
 // Block selection over the gate dependency order.
 //
@@ -275,17 +350,20 @@ std::vector<Selected> select_blocks(const std::vector<HostGate>& gates, int kmax
     auto absorb = [&](uint64_t S, bool mark) {
         uint64_t blocked = 0;
         int count = 0;
-        for (size_t j = 0; j < live.size(); ++j) {
-            const uint64_t Q = mask[j];
-            if ((Q & blocked) == 0 && (Q & ~S) == 0) {
-                ++count;
-                if (mark) take[j] = 1;
-            } else {
-                blocked |= Q;
-            }
+        const uint64_t* m = mask.data();
+        for (size_t j = 0, n = live.size(); j < n; ++j) {
+            // taken: inside S and on no blocked qubit (no branch on it)
+            const uint64_t Q = m[j];
+            const bool ok = (Q & (blocked | ~S)) == 0;
+            count += ok;
+            if (mark) take[j] = ok;
+            blocked |= ok ? uint64_t(0) : Q;
             if ((S & ~blocked) == 0) break;  // every qubit of S is blocked
         }
         return count;
+    };
+    auto absorb_many = [&](const uint64_t* sets, int n_sets, int* counts) {
+        count_absorbed_many(mask.data(), live.size(), sets, n_sets, counts);
     };
     auto absorb_diag = [&](uint64_t S, bool mark) {
         uint64_t blocked = 0;
@@ -324,27 +402,32 @@ std::vector<Selected> select_blocks(const std::vector<HostGate>& gates, int kmax
         }
         return S;
     };
+    // per round, for every qubit q: the qubits of the window's gates that
+    // touch q (a set's candidates are then those of its qubits)
+    uint64_t nbr[64];
     auto grow = [&](uint64_t S) {
         while (popcount64(S) < kmax) {
             uint64_t cand = 0;
-            const size_t lim = std::min(live.size(), kWindow);
-            for (size_t j = 0; j < lim; ++j)
-                if (mask[j] & S) cand |= mask[j] & ~S;
+            for (uint64_t r = S; r; r &= r - 1) cand |= nbr[__builtin_ctzll(r)];
+            cand &= ~S;
             if (!cand) break;
-            int best_q = -1, best_c = -1;
-            for (int q = 0; q < 64; ++q) {
-                if (!((cand >> q) & 1)) continue;
-                const int c = absorb(S | (uint64_t(1) << q), false);
-                if (c > best_c) {
-                    best_c = c;
-                    best_q = q;
-                }
-            }
-            S |= uint64_t(1) << best_q;
+            // every candidate qubit's set, lowest qubit first; the first
+            // that absorbs the most wins
+            uint64_t sets[64];
+            int counts[64], n_sets = 0;
+            for (uint64_t r = cand; r; r &= r - 1) sets[n_sets++] = S | (uint64_t(1) << __builtin_ctzll(r));
+            absorb_many(sets, n_sets, counts);
+            int best = 0;
+            for (int c = 1; c < n_sets; ++c)
+                if (counts[c] > counts[best]) best = c;
+            S = sets[best];
         }
         return S;
     };
     while (!live.empty()) {
+        std::fill(std::begin(nbr), std::end(nbr), uint64_t(0));
+        for (size_t j = 0, lim = std::min(live.size(), kWindow); j < lim; ++j)
+            for (uint64_t r = mask[j]; r; r &= r - 1) nbr[__builtin_ctzll(r)] |= mask[j];
         ready.clear();
         uint64_t seen = 0;
         for (size_t j = 0; j < live.size(); ++j) {
