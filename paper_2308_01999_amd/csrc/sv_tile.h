@@ -252,7 +252,9 @@ __device__ __forceinline__ void tile_c64_k5_sweep(float2* __restrict__ psi, cons
     if (t0 >= a.n_tiles) return;
     const uint64_t t1 = (a.n_tiles - t0 < a.tiles_per_wg) ? a.n_tiles : t0 + a.tiles_per_wg;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 31, half = lane >> 5;
-    for (int e = tid; e < kK5AParts * 64 * 4; e += NT) amat[e] = mats[e];
+    // (from |0..0> only the workgroup with tile 0 multiplies; see below)
+    if (!FIRST || t0 == 0)
+        for (int e = tid; e < kK5AParts * 64 * 4; e += NT) amat[e] = mats[e];
     if (zs.n_terms >= 0 && lane <= kZSumsMax) zs.acc[wave * (kZSumsMax + 1) + lane] = 0.0;
     uint64_t roff[kTileVecs];
     uint32_t poff[kTileVecs];
@@ -271,6 +273,23 @@ __device__ __forceinline__ void tile_c64_k5_sweep(float2* __restrict__ psi, cons
     SV_REP8(SV_LOAD)
 #undef SV_LOAD
     for (uint64_t t = t0; t < t1; ++t) {
+        if constexpr (FIRST) {
+            // |0..0> is zero on every tile but tile 0 (the one holding index
+            // 0), and so is the gate's image of it there: such a tile is
+            // only written
+            if (base != 0) {
+#pragma unroll
+                for (int u = 0; u < kTileVecs; ++u)
+                    gstore(reinterpret_cast<float4*>(psi + base + roff[u] + poff[u]), float4{0.f, 0.f, 0.f, 0.f});
+                if (t + 1 < t1) {
+                    base = tile_base(t + 1, a);
+#define SV_LOAD(u) buf##u = basis0_pair(base + roff[u] + poff[u]);
+                    SV_REP8(SV_LOAD)
+#undef SV_LOAD
+                }
+                continue;
+            }
+        }
 #define SV_STAGE(u)                                                                        \
     {                                                                                      \
         const int i = (u * NT + tid) * 2;                                        \
