@@ -36,33 +36,59 @@ const NamedGate kGates[] = {
     {"cx", 0, 1, 1}, {"cz", 0, 1, 1}, {"cp", 1, 1, 1}, {"swap", 0, 2, 0},
 };
 
-// Target matrix of a named gate, row-major, in std::complex.
-void named_matrix(const std::string& name, const double* p, cd* m)
+// Target matrix of gate kGates[gi], row-major, in std::complex.
+void named_matrix(int gi, const double* p, cd* m)
 {
     const cd I(0.0, 1.0);
-    if (name == "u3") {
+    switch (gi) {
+    case 0: {  // u3
         // OpenQASM U3: [[cos, -e^{i lambda} sin], [e^{i phi} sin, e^{i(phi+lambda)} cos]]
         const double c = std::cos(0.5 * p[0]), s = std::sin(0.5 * p[0]);
         m[0] = c;
         m[1] = -std::polar(1.0, p[2]) * s;
         m[2] = std::polar(1.0, p[1]) * s;
         m[3] = std::polar(1.0, p[1] + p[2]) * c;
-    } else if (name == "h") {
+        break;
+    }
+    case 1: {  // h
         const double r = 1.0 / std::sqrt(2.0);
         m[0] = r; m[1] = r; m[2] = r; m[3] = -r;
-    } else if (name == "x" || name == "cx") {
+        break;
+    }
+    case 2:  // x
+    case 5:  // cx
         m[0] = 0; m[1] = 1; m[2] = 1; m[3] = 0;
-    } else if (name == "y") {
+        break;
+    case 3:  // y
         m[0] = 0; m[1] = -I; m[2] = I; m[3] = 0;
-    } else if (name == "z" || name == "cz") {
+        break;
+    case 4:  // z
+    case 6:  // cz
         m[0] = 1; m[1] = 0; m[2] = 0; m[3] = -1;
-    } else if (name == "cp") {
+        break;
+    case 7:  // cp
         m[0] = 1; m[1] = 0; m[2] = 0; m[3] = std::polar(1.0, p[0]);
-    } else if (name == "swap") {
-        // basis |b1 b0>: swaps |01> and |10>
+        break;
+    case 8:  // swap; basis |b1 b0>: swaps |01> and |10>
         for (int i = 0; i < 16; ++i) m[i] = 0;
         m[0] = 1; m[1 * 4 + 2] = 1; m[2 * 4 + 1] = 1; m[3 * 4 + 3] = 1;
+        break;
     }
+}
+
+// The matrix of gate kGates[gi] (its adjoint if adj), complex128
+// interleaved, row-major.
+void code_matrix(int gi, bool adj, const double* params, double* out)
+{
+    cd m[16];
+    named_matrix(gi, params, m);
+    const int d = 1 << kGates[gi].n_targets;
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+            const cd v = adj ? std::conj(m[c * d + r]) : m[r * d + c];
+            out[2 * (r * d + c)] = v.real();
+            out[2 * (r * d + c) + 1] = v.imag();
+        }
 }
 
 }  // namespace
@@ -77,23 +103,16 @@ void gate_matrix(const char* name_c, const double* params, int n_params, double*
         adj = true;
         name.resize(name.size() - 3);
     }
-    const NamedGate* g = nullptr;
-    for (const auto& e : kGates)
-        if (name == e.name) g = &e;
-    SV_CHECK(g != nullptr, "unknown gate name '" + std::string(name_c) + "'");
+    int gi = -1;
+    for (int e = 0; e < int(sizeof(kGates) / sizeof(kGates[0])); ++e)
+        if (name == kGates[e].name) gi = e;
+    SV_CHECK(gi >= 0, "unknown gate name '" + std::string(name_c) + "'");
+    const NamedGate* g = &kGates[gi];
     SV_CHECK(n_params == g->n_params, "gate '" + name + "' takes " + std::to_string(g->n_params) + " parameters");
     SV_CHECK(g->n_params == 0 || params != nullptr, "gate parameters are NULL");
     for (int i = 0; i < n_params; ++i) SV_CHECK(std::isfinite(params[i]), "gate parameter is not finite");
     SV_CHECK(out != nullptr, "matrix output is NULL");
-    cd m[16];
-    named_matrix(name, params, m);
-    const int d = 1 << g->n_targets;
-    for (int r = 0; r < d; ++r)
-        for (int c = 0; c < d; ++c) {
-            const cd v = adj ? std::conj(m[c * d + r]) : m[r * d + c];
-            out[2 * (r * d + c)] = v.real();
-            out[2 * (r * d + c) + 1] = v.imag();
-        }
+    code_matrix(gi, adj, params, out);
     if (n_targets) *n_targets = g->n_targets;
     if (n_controls) *n_controls = g->n_controls;
 }
@@ -102,11 +121,31 @@ void gate_matrix(const char* name_c, const double* params, int n_params, double*
 
 namespace {
 
+// At most SV_MAX_TARGETS qubit indices (or control values), kept inline.
+struct QubitList {
+    int v[SV_MAX_TARGETS];
+    int n = 0;
+    void push_back(int x) { v[n++] = x; }
+    size_t size() const { return size_t(n); }
+    int operator[](size_t i) const { return v[i]; }
+    const int* begin() const { return v; }
+    const int* end() const { return v + n; }
+};
+
 struct HostGate {
-    std::vector<int> targets, controls, cvals;
-    std::vector<cd> m;
+    QubitList targets, controls, cvals;
     uint64_t qmask = 0;  // targets | controls
-    bool diagonal = false;  // every off-diagonal entry of m is exactly 0
+    bool diagonal = false;  // every off-diagonal entry of the matrix is exactly 0
+    // the 2^k x 2^k target matrix, row-major: inline up to two targets
+    cd m_small[16];
+    std::vector<cd> m_big;
+    cd* set_size(int d)
+    {
+        if (d * d <= 16) return m_small;
+        m_big.resize(size_t(d) * d);
+        return m_big.data();
+    }
+    const cd* mat() const { return m_big.empty() ? m_small : m_big.data(); }
 };
 
 // A selected block: its gates (circuit order) and whether it is a diagonal
@@ -144,8 +183,7 @@ struct BlockMatrix {
 // doubles.  No std::complex products: those would go through the C99
 // special-value path.
 __attribute__((always_inline)) inline void left_multiply_body(BlockMatrix& U, const HostGate& g,
-                                                              const std::vector<int>& pos_t,
-                                                              const std::vector<int>& pos_c)
+                                                              const QubitList& pos_t, const QubitList& pos_c)
 {
     const int k = int(pos_t.size());
     const int d = 1 << k;
@@ -168,8 +206,8 @@ __attribute__((always_inline)) inline void left_multiply_body(BlockMatrix& U, co
         // are combined in registers, column by column, with no staging
         double mr[16], mi[16];
         for (int e = 0; e < d * d; ++e) {
-            mr[e] = g.m[size_t(e)].real();
-            mi[e] = g.m[size_t(e)].imag();
+            mr[e] = g.mat()[e].real();
+            mi[e] = g.mat()[e].imag();
         }
         for (uint64_t row = 0; row < dim; ++row) {
             if ((row & tmask) || (row & cmask) != cset) continue;
@@ -222,7 +260,7 @@ __attribute__((always_inline)) inline void left_multiply_body(BlockMatrix& U, co
             double* __restrict oim = &U.im[(row + off[r]) * dim];
             for (uint64_t col = 0; col < dim; ++col) ore[col] = oim[col] = 0.0;
             for (int c = 0; c < d; ++c) {
-                const cd e = g.m[size_t(r) * d + c];
+                const cd e = g.mat()[size_t(r) * d + c];
                 const double mr = e.real(), mi = e.imag();
                 if (mr == 0.0 && mi == 0.0) continue;
                 const double* __restrict xr = &in_re[c * dim];
@@ -239,18 +277,18 @@ __attribute__((always_inline)) inline void left_multiply_body(BlockMatrix& U, co
 // The same, built for AVX2 (four doubles per vector instruction; the same
 // operations in the same order, so the same results), taken where the CPU
 // has it.
-__attribute__((target("avx2"))) void left_multiply_avx2(BlockMatrix& U, const HostGate& g,
-                                                        const std::vector<int>& pos_t, const std::vector<int>& pos_c)
+__attribute__((target("avx2"))) void left_multiply_avx2(BlockMatrix& U, const HostGate& g, const QubitList& pos_t,
+                                                        const QubitList& pos_c)
 {
     left_multiply_body(U, g, pos_t, pos_c);
 }
 
-void left_multiply_base(BlockMatrix& U, const HostGate& g, const std::vector<int>& pos_t, const std::vector<int>& pos_c)
+void left_multiply_base(BlockMatrix& U, const HostGate& g, const QubitList& pos_t, const QubitList& pos_c)
 {
     left_multiply_body(U, g, pos_t, pos_c);
 }
 
-void left_multiply(BlockMatrix& U, const HostGate& g, const std::vector<int>& pos_t, const std::vector<int>& pos_c)
+void left_multiply(BlockMatrix& U, const HostGate& g, const QubitList& pos_t, const QubitList& pos_c)
 {
     static const bool avx2 = __builtin_cpu_supports("avx2");
     if (avx2)
@@ -541,7 +579,7 @@ bool phase_terms(const HostGate& g, PhasePoly& out)
         if (on) {
             int r = 0;
             for (size_t a = 0; a < g.targets.size(); ++a) r |= bit(g.targets[a]) << a;
-            e = g.m[size_t(r) * d + r];
+            e = g.mat()[size_t(r) * d + r];
         }
         if (std::fabs(std::abs(e) - 1.0) > 1e-12) return false;
         th[x] = std::arg(e);
@@ -781,7 +819,6 @@ sv_fused_s* fuse_gate_list(const int32_t* codes, const int32_t* qubits, const do
 {
     SV_CHECK(n_gates >= 0, "n_gates is negative");
     SV_CHECK(n_gates == 0 || (codes && qubits && params), "NULL gate arrays");
-    static const char* kNames[] = {"u3", "h", "x", "y", "z", "cx", "cz", "cp", "swap"};
     std::vector<sv_gate_t> gates(n_gates);
     std::vector<double> mats(size_t(n_gates) * 32);
     std::vector<int32_t> qs(size_t(n_gates) * 2);
@@ -789,11 +826,13 @@ sv_fused_s* fuse_gate_list(const int32_t* codes, const int32_t* qubits, const do
         const int code = codes[g] & ~int(SV_GATE_ADJOINT);
         const bool adj = (codes[g] & SV_GATE_ADJOINT) != 0;
         SV_CHECK(code >= SV_GATE_U3 && code <= SV_GATE_SWAP, "gate " + std::to_string(g) + ": unknown code");
-        std::string name = kNames[code];
-        if (adj) name += "_dg";
-        const int np = code == SV_GATE_U3 ? 3 : code == SV_GATE_CP ? 1 : 0;
-        int nt = 0, nc = 0;
-        gate_matrix(name.c_str(), params + 3 * size_t(g), np, &mats[size_t(g) * 32], &nt, &nc);
+        // the gate codes follow the gate table's order
+        const NamedGate& ng = kGates[code];
+        const double* p = params + 3 * size_t(g);
+        for (int i = 0; i < ng.n_params; ++i)
+            SV_CHECK(std::isfinite(p[i]), "gate " + std::to_string(g) + ": parameter is not finite");
+        code_matrix(code, adj, p, &mats[size_t(g) * 32]);
+        const int nt = ng.n_targets, nc = ng.n_controls;
         // qubit order: controls first, then targets
         qs[2 * g] = qubits[2 * g];
         qs[2 * g + 1] = qubits[2 * g + 1];
@@ -861,7 +900,7 @@ sv_fused_s* build_coupled(const std::vector<HostGate>& hg, const std::vector<Cou
         BlockMatrix U(m);
         for (int gi : c.gates) {
             const HostGate& g = hg[gi];
-            std::vector<int> pt, pc;
+            QubitList pt, pc;
             for (int q : g.targets) pt.push_back(pos(q));
             for (int q : g.controls) pc.push_back(pos(q));
             left_multiply(U, g, pt, pc);
@@ -937,7 +976,7 @@ sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag, bool 
             h.cvals.push_back(cv);
         }
         const int d = 1 << g.n_targets;
-        h.m.resize(size_t(d) * d);
+        cd* hm = h.set_size(d);
         h.diagonal = true;
         for (int e = 0; e < d * d; ++e) {
             SV_CHECK(std::isfinite(g.matrix[2 * e]) && std::isfinite(g.matrix[2 * e + 1]),
@@ -945,8 +984,8 @@ sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag, bool 
             // the adjoint's entry (r, c) is the conjugate of entry (c, r)
             const int src = g.adjoint ? (e % d) * d + e / d : e;
             const double im = g.matrix[2 * src + 1];
-            h.m[e] = cd(g.matrix[2 * src], g.adjoint ? -im : im);
-            if (e / d != e % d && h.m[e] != cd(0.0, 0.0)) h.diagonal = false;
+            hm[e] = cd(g.matrix[2 * src], g.adjoint ? -im : im);
+            if (e / d != e % d && hm[e] != cd(0.0, 0.0)) h.diagonal = false;
         }
     }
     if (coupled) return build_coupled(hg, select_blocks_coupled(hg, kmax));
@@ -991,7 +1030,7 @@ sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag, bool 
                     if (!on) continue;
                     int r = 0;
                     for (size_t a = 0; a < g.targets.size(); ++a) r |= int((i >> pos(g.targets[a])) & 1) << a;
-                    const cd e = g.m[size_t(r) * d + r];
+                    const cd e = g.mat()[size_t(r) * d + r];
                     D[i] = cd(D[i].real() * e.real() - D[i].imag() * e.imag(),
                               D[i].real() * e.imag() + D[i].imag() * e.real());
                 }
@@ -1006,7 +1045,7 @@ sv_fused_s* fuse(const sv_gate_t* gates, int n_gates, int kmax, int kdiag, bool 
         BlockMatrix U(m);
         for (int gi : sel[b].gates) {
             const HostGate& g = hg[gi];
-            std::vector<int> pt, pc;
+            QubitList pt, pc;
             for (int q : g.targets) pt.push_back(pos(q));
             for (int q : g.controls) pc.push_back(pos(q));
             left_multiply(U, g, pt, pc);
