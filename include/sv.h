@@ -111,7 +111,10 @@ sv_status_t sv_handle_set_stream(sv_handle_t h, void* hip_stream);
  *     times, in rotating order, on the sweeps of every (dtype, state size,
  *     target set) it sees, with HIP events on its stream, then keeps the
  *     variant with the lowest mean (no timing while the stream is being
- *     captured; the spread variant until a target set has timings);
+ *     captured; the spread variant until a target set has timings).
+ *     States of fewer than SV_TILE_TUNE_MIN_QUBITS qubits, whose sweeps
+ *     are bound by the launch rather than by the tile shape, always take
+ *     the spread variant, untimed;
  *   SV_TILE_NARROW / SV_TILE_WIDE: always that shape, each workgroup on
  *     consecutive tiles (wide needs n >= 13 for complex64 and n >= 12 for
  *     complex128; smaller states use the narrow one);
@@ -125,6 +128,8 @@ typedef enum { SV_TILE_AUTO = 0, SV_TILE_NARROW = 1, SV_TILE_WIDE = 2, SV_TILE_S
 /* Untimed five-qubit sweeps an SV_TILE_AUTO handle runs before its first
  * timed trial. */
 #define SV_TILE_WARM_SWEEPS 64
+/* Smallest state an SV_TILE_AUTO handle times tile variants on. */
+#define SV_TILE_TUNE_MIN_QUBITS 22
 sv_status_t sv_handle_set_tile_mode(sv_handle_t h, int32_t mode);
 
 /* Blocks until all work issued on the handle's stream has finished. */

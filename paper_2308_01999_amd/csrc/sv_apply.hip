@@ -827,16 +827,15 @@ hipEvent_t tuner_event(TileTuner& T)
     return e;
 }
 
-// Folds finished trials into their entries.
+// Folds finished trials into their entries, oldest first, up to the first
+// one still running (trials finish in launch order on the handle's stream;
+// one per launch query while the device runs behind the host).
 void tuner_poll(TileTuner& T)
 {
-    for (size_t i = 0; i < T.pending.size();) {
-        TileTrial& tr = T.pending[i];
+    while (!T.pending.empty()) {
+        TileTrial& tr = T.pending.front();
         const hipError_t q = hipEventQuery(tr.e1);
-        if (q == hipErrorNotReady) {
-            ++i;
-            continue;
-        }
+        if (q == hipErrorNotReady) return;
         TileTuneEntry& e = T.entries[tr.key];
         float ms = 0.f;
         if (q == hipSuccess && hipEventElapsedTime(&ms, tr.e0, tr.e1) == hipSuccess) {
@@ -849,8 +848,7 @@ void tuner_poll(TileTuner& T)
         --e.in_flight[tr.shape];
         T.pool.push_back(tr.e0);
         T.pool.push_back(tr.e1);
-        T.pending[i] = T.pending.back();
-        T.pending.pop_back();
+        T.pending.pop_front();
     }
 }
 
@@ -892,6 +890,9 @@ int tile_shape(sv_handle_s* h, Path p, const GateDesc& d, bool* trial, bool allo
     if (h->tile_mode == SV_TILE_NARROW) return kVariantNarrow;
     if (h->tile_mode == SV_TILE_WIDE) return kVariantWide;
     if (h->tile_mode == SV_TILE_SPREAD) return kVariantSpread;
+    // a small state sweeps from the caches in a few microseconds, bound by
+    // the launch more than by any tile shape: the default, untimed
+    if (d.n < SV_TILE_TUNE_MIN_QUBITS) return kVariantSpread;
     TileTuner& T = *h->tuner;
     const uint64_t key = tune_key(p, d);
     // while the stream is being recorded into a graph: no event queries and

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <deque>
 #include <unordered_map>
 #include <vector>
 
@@ -67,7 +68,7 @@ constexpr size_t kMinWorkspace = 12u << 20;
 // default variant, while clocks and caches settle), per key (dtype, n, target mask) kTileTrials
 // timings of each variant, taken in rotating round-robin order so that every
 // variant meets the same mix of neighbouring work, then the variant with
-// the lowest mean.
+// the lowest mean.  States below SV_TILE_TUNE_MIN_QUBITS are not tuned.
 namespace sv {
 constexpr int kTileShapes = 3;
 constexpr int kTileTrials = 3;
@@ -85,7 +86,7 @@ struct TileTrial {
 };
 struct TileTuner {
     std::unordered_map<uint64_t, TileTuneEntry> entries;
-    std::vector<TileTrial> pending;
+    std::deque<TileTrial> pending;  // in launch order
     std::vector<hipEvent_t> pool;
     uint64_t sweeps = 0;  // tuned sweeps launched (warm-up count)
 };

@@ -976,36 +976,52 @@ void run_expect_t(sv_handle_s* h, const void* psi_v, int n, const PauliMasks* te
         }
         i = j;
     }
-    double* res_dev = part;  // reused per launch after the partials are consumed
-    for (const Launch& L : launches) {
-        const int nt = int(L.idx.size());
-        const uint64_t x = terms[L.idx[0]].x;
-        const bool pairs = x != 0;
-        const uint64_t items = pairs ? dim / 2 : dim;
-        const Partition P = partition(items);
-        double* p = part + 64;  // first 64 doubles hold the finished sums
-        ExpectArgs a{};
-        a.per = P.per;
-        a.x = x;
-        a.hbit = pairs ? highest_bit(x) : 0;
-        a.n_terms = nt;
-        a.n_active = L.n_active;
-        for (int t = 0; t < nt; ++t) {
-            a.z[t] = terms[L.idx[t]].z;
-            a.ny[t] = terms[L.idx[t]].ny;
+    // Launches in groups of up to kGroup: each launch's finished sums go to
+    // its own slot of the results area, read back once per group; the
+    // partials after it are reused launch after launch (each launch's finish
+    // consumes them before the next sweep writes them: one stream).
+    constexpr size_t kGroup = 64, kSlot = kMaxTermsPerSweep + 1;
+    double* res_dev = part;
+    std::vector<double> host(kGroup * kSlot);
+    for (size_t g0 = 0; g0 < launches.size(); g0 += kGroup) {
+        const size_t g1 = std::min(launches.size(), g0 + kGroup);
+        for (size_t li = g0; li < g1; ++li) {
+            const Launch& L = launches[li];
+            const int nt = int(L.idx.size());
+            const uint64_t x = terms[L.idx[0]].x;
+            const bool pairs = x != 0;
+            const uint64_t items = pairs ? dim / 2 : dim;
+            const Partition P = partition(items);
+            double* p = part + kGroup * kSlot;
+            ExpectArgs a{};
+            a.per = P.per;
+            a.x = x;
+            a.hbit = pairs ? highest_bit(x) : 0;
+            a.n_terms = nt;
+            a.n_active = L.n_active;
+            for (int t = 0; t < nt; ++t) {
+                a.z[t] = terms[L.idx[t]].z;
+                a.ny[t] = terms[L.idx[t]].ny;
+            }
+            if (pairs)
+                hipLaunchKernelGGL((k_expect_xy<R>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a, p);
+            else
+                hipLaunchKernelGGL((k_expect_z<R>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a, p);
+            SV_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_finish_sums, dim3(unsigned(nt + 1)), dim3(kThreads), 0, h->stream, p, P.nb,
+                               res_dev + (li - g0) * kSlot);
+            SV_HIP(hipGetLastError());
         }
-        if (pairs)
-            hipLaunchKernelGGL((k_expect_xy<R>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a, p);
-        else
-            hipLaunchKernelGGL((k_expect_z<R>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a, p);
-        SV_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_finish_sums, dim3(unsigned(nt + 1)), dim3(kThreads), 0, h->stream, p, P.nb, res_dev);
-        SV_HIP(hipGetLastError());
-        double host[kMaxTermsPerSweep + 1];
-        SV_HIP(hipMemcpyAsync(host, res_dev, sizeof(double) * (nt + 1), hipMemcpyDeviceToHost, h->stream));
+        SV_HIP(hipMemcpyAsync(host.data(), res_dev, sizeof(double) * kSlot * (g1 - g0), hipMemcpyDeviceToHost,
+                              h->stream));
         SV_HIP(hipStreamSynchronize(h->stream));
-        for (int t = 0; t < nt; ++t) sums[L.idx[t]] = host[t];
-        if (norm < 0.0) norm = host[nt];
+        for (size_t li = g0; li < g1; ++li) {
+            const Launch& L = launches[li];
+            const int nt = int(L.idx.size());
+            const double* r = host.data() + (li - g0) * kSlot;
+            for (int t = 0; t < nt; ++t) sums[L.idx[t]] = r[t];
+            if (norm < 0.0) norm = r[nt];
+        }
     }
     if (!(norm > 0.0)) throw Error{SV_ERR_INVALID_VALUE, "state has zero norm"};
     for (int t = 0; t < n_terms; ++t) out[t] = sums[t] / norm;
