@@ -38,15 +38,15 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources the counters were taken on: their SHA-256 are recorded and
 # checked at run time.
 _K5_SOURCES = {"paper_2308_01999_amd/csrc/sv_apply.hip":
-               "85353f05b4dde9a2e25210ff1c61db0ca5c87b6ed0188fee5334b05aebb09f8e",
+               "6dca62546123f1d77c95619e8af077d6c84822a95b991a578cd528cd71d68963",
                "paper_2308_01999_amd/csrc/sv_tile.h":
-               "d60bf5b71681c7000bafd8f3fd58e0b64288e10c23283db46ed2803a25f8675b"}
+               "c5add302b4b2ffb570a4d879c24b9d6c9ba1c85a2392c54663058f74727a1620"}
 PMC_TRAFFIC = {
-    # 30-qubit brickwork sweep, dispatch-weighted over all tile variants (676
-    # launches of each dtype in one pass: 13 steps of 52 blocks)
-    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194398.4, "write_kib": 8389595.1,
+    # 30-qubit brickwork sweep, dispatch-weighted over all tile variants (728
+    # launches of each dtype in one pass: 14 steps of 52 blocks)
+    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194398.4, "write_kib": 8389778.9,
                       "fetch_scale": 2.0, "write_scale": 1.0, "sources": _K5_SOURCES},
-    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388720.9, "write_kib": 16780129.8,
+    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388721.0, "write_kib": 16780453.0,
                        "fetch_scale": 2.0, "write_scale": 1.0, "sources": _K5_SOURCES},
 }
 
