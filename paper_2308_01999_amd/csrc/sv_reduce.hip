@@ -178,8 +178,8 @@ __device__ __forceinline__ void write_partials(const double* val, double norm, i
 // round's four probabilities.  The next round's loads are in flight while a
 // round is summed.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_expect_z(const typename Cx<R>::T* __restrict__ psi,
-                                                      ExpectArgs a, double* __restrict__ part)
+__device__ __forceinline__ void expect_z_body(const typename Cx<R>::T* __restrict__ psi, const ExpectArgs a,
+                                              double* __restrict__ part)
 {
     using T2 = typename Cx<R>::T;
     static_assert(kExpectUnroll == 4 && kThreads == 256, "a round spans bits 8-9 of it");
@@ -251,14 +251,31 @@ __global__ __launch_bounds__(kThreads) void k_expect_z(const typename Cx<R>::T* 
     write_partials(val, norm, a.n_terms, part, wsum);
 }
 
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_expect_z(const typename Cx<R>::T* __restrict__ psi,
+                                                      ExpectArgs a, double* __restrict__ part)
+{
+    expect_z_body<R>(psi, a, part);
+}
+
+// Several x == 0 sweeps in one launch (small states, where a launch costs
+// more than its sweep): sweep y takes args[y] and part + y * stride.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_expect_z_group(const typename Cx<R>::T* __restrict__ psi,
+                                                            const ExpectArgs* __restrict__ args,
+                                                            double* __restrict__ part, uint64_t stride)
+{
+    expect_z_body<R>(psi, args[blockIdx.y], part + blockIdx.y * stride);
+}
+
 // Pair sweeps for terms sharing one X/Y mask x != 0: item q is the pair
 // (i, j = i ^ x), i = q with a zero inserted at bit hbit (the highest bit
 // of x).  With w = conj(psi_j) psi_i the pair contributes
 // 2 Re(w * i^ny) * (-1)^popcount(i & z), because P|i> = ph(i)|j> and
 // ph(j) = conj(ph(i)) for a Hermitian Pauli string.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_expect_xy(const typename Cx<R>::T* __restrict__ psi,
-                                                       ExpectArgs a, double* __restrict__ part)
+__device__ __forceinline__ void expect_xy_body(const typename Cx<R>::T* __restrict__ psi, const ExpectArgs a,
+                                               double* __restrict__ part)
 {
     using T2 = typename Cx<R>::T;
     __shared__ double wsum[kMaxTermsPerSweep + 1][kThreads / 64];
@@ -318,6 +335,21 @@ __global__ __launch_bounds__(kThreads) void k_expect_xy(const typename Cx<R>::T*
     write_partials(acc, norm, a.n_terms, part, wsum);
 }
 
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_expect_xy(const typename Cx<R>::T* __restrict__ psi,
+                                                       ExpectArgs a, double* __restrict__ part)
+{
+    expect_xy_body<R>(psi, a, part);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_expect_xy_group(const typename Cx<R>::T* __restrict__ psi,
+                                                             const ExpectArgs* __restrict__ args,
+                                                             double* __restrict__ part, uint64_t stride)
+{
+    expect_xy_body<R>(psi, args[blockIdx.y], part + blockIdx.y * stride);
+}
+
 // out[t] = sum over blocks of part[t * nb + b], fixed order.  One block per t.
 __global__ __launch_bounds__(kThreads) void k_finish_sums(const double* __restrict__ part, uint64_t nb,
                                                          double* __restrict__ out)
@@ -328,6 +360,26 @@ __global__ __launch_bounds__(kThreads) void k_finish_sums(const double* __restri
     for (uint64_t b = threadIdx.x; b < nb; b += kThreads) acc = __dadd_rn(acc, p[b]);
     const double s = block_sum(acc, lds);
     if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// k_finish_sums for a group of sweeps: block (t, y) finishes term t of
+// sweep y (its partials at part + y * stride, nb_z blocks for the first
+// n_z sweeps, nb_xy for the others) into out[y * slot + t], in the same
+// order as k_finish_sums.
+__global__ __launch_bounds__(kThreads) void k_finish_group(const double* __restrict__ part, uint64_t stride,
+                                                          const ExpectArgs* __restrict__ args, uint32_t n_z,
+                                                          uint64_t nb_z, uint64_t nb_xy, double* __restrict__ out,
+                                                          uint32_t slot)
+{
+    __shared__ double lds[kThreads];
+    const uint32_t y = blockIdx.y;
+    if (int(blockIdx.x) > args[y].n_terms) return;
+    const uint64_t nb = y < n_z ? nb_z : nb_xy;
+    const double* p = part + y * stride + uint64_t(blockIdx.x) * nb;
+    double acc = 0.0;
+    for (uint64_t b = threadIdx.x; b < nb; b += kThreads) acc = __dadd_rn(acc, p[b]);
+    const double s = block_sum(acc, lds);
+    if (threadIdx.x == 0) out[uint64_t(y) * slot + blockIdx.x] = s;
 }
 
 // ----------------------------------------------------------------- sampler
@@ -976,41 +1028,78 @@ void run_expect_t(sv_handle_s* h, const void* psi_v, int n, const PauliMasks* te
         }
         i = j;
     }
-    // Launches in groups of up to kGroup: each launch's finished sums go to
-    // its own slot of the results area, read back once per group; the
-    // partials after it are reused launch after launch (each launch's finish
-    // consumes them before the next sweep writes them: one stream).
+    // Sweeps in groups of up to kGroup, read back once per group: each
+    // sweep's finished sums go to its own slot of the results area.  A large
+    // state's sweeps are launched one by one and reuse the partials after
+    // the results area (each finish consumes them before the next sweep
+    // writes them: one stream).  A small state's group takes one launch per
+    // kind (its Z-type sweeps, which come first, then its pair sweeps) and
+    // one finish, each sweep with partials of its own.
     constexpr size_t kGroup = 64, kSlot = kMaxTermsPerSweep + 1;
+    constexpr int kGroupedQubits = 22;
+    auto make_args = [&](const Launch& L) {
+        const uint64_t x = terms[L.idx[0]].x;
+        ExpectArgs a{};
+        a.per = partition(x != 0 ? dim / 2 : dim).per;
+        a.x = x;
+        a.hbit = x != 0 ? highest_bit(x) : 0;
+        a.n_terms = int(L.idx.size());
+        a.n_active = L.n_active;
+        for (int t = 0; t < a.n_terms; ++t) {
+            a.z[t] = terms[L.idx[t]].z;
+            a.ny[t] = terms[L.idx[t]].ny;
+        }
+        return a;
+    };
+    const bool grouped = n <= kGroupedQubits;
+    const Partition Pz = partition(dim), Pxy = partition(dim > 1 ? dim / 2 : 1);
+    const uint64_t stride = kSlot * Pz.nb;  // one sweep's partials (pair sweeps have fewer blocks)
     double* res_dev = part;
+    double* parts = part + kGroup * kSlot;
+    size_t group = kGroup;
+    if (grouped) {
+        const size_t room = (h->ws_bytes - kMatRingBytes) / sizeof(double) - kGroup * kSlot;
+        group = std::max<size_t>(1, std::min<size_t>(kGroup, room / stride));
+    }
     std::vector<double> host(kGroup * kSlot);
-    for (size_t g0 = 0; g0 < launches.size(); g0 += kGroup) {
-        const size_t g1 = std::min(launches.size(), g0 + kGroup);
-        for (size_t li = g0; li < g1; ++li) {
-            const Launch& L = launches[li];
-            const int nt = int(L.idx.size());
-            const uint64_t x = terms[L.idx[0]].x;
-            const bool pairs = x != 0;
-            const uint64_t items = pairs ? dim / 2 : dim;
-            const Partition P = partition(items);
-            double* p = part + kGroup * kSlot;
-            ExpectArgs a{};
-            a.per = P.per;
-            a.x = x;
-            a.hbit = pairs ? highest_bit(x) : 0;
-            a.n_terms = nt;
-            a.n_active = L.n_active;
-            for (int t = 0; t < nt; ++t) {
-                a.z[t] = terms[L.idx[t]].z;
-                a.ny[t] = terms[L.idx[t]].ny;
+    std::vector<ExpectArgs> ga;
+    for (size_t g0 = 0; g0 < launches.size(); g0 += group) {
+        const size_t g1 = std::min(launches.size(), g0 + group);
+        if (grouped) {
+            ga.clear();
+            uint32_t n_z = 0;
+            for (size_t li = g0; li < g1; ++li) {
+                ga.push_back(make_args(launches[li]));
+                if (ga.back().x == 0) ++n_z;
             }
-            if (pairs)
-                hipLaunchKernelGGL((k_expect_xy<R>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a, p);
-            else
-                hipLaunchKernelGGL((k_expect_z<R>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a, p);
+            const uint32_t n_all = uint32_t(ga.size());
+            const ExpectArgs* dargs =
+                static_cast<const ExpectArgs*>(stage_matrix(h, ga.data(), sizeof(ExpectArgs) * ga.size()));
+            if (n_z > 0)
+                hipLaunchKernelGGL((k_expect_z_group<R>), dim3(unsigned(Pz.nb), n_z), dim3(kThreads), 0, h->stream,
+                                   psi, dargs, parts, stride);
+            if (n_all > n_z)
+                hipLaunchKernelGGL((k_expect_xy_group<R>), dim3(unsigned(Pxy.nb), n_all - n_z), dim3(kThreads), 0,
+                                   h->stream, psi, dargs + n_z, parts + n_z * stride, stride);
             SV_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_finish_sums, dim3(unsigned(nt + 1)), dim3(kThreads), 0, h->stream, p, P.nb,
-                               res_dev + (li - g0) * kSlot);
+            hipLaunchKernelGGL(k_finish_group, dim3(unsigned(kSlot), n_all), dim3(kThreads), 0, h->stream, parts,
+                               stride, dargs, n_z, Pz.nb, Pxy.nb, res_dev, uint32_t(kSlot));
             SV_HIP(hipGetLastError());
+        } else {
+            for (size_t li = g0; li < g1; ++li) {
+                const ExpectArgs a = make_args(launches[li]);
+                const Partition P = partition(a.x != 0 ? dim / 2 : dim);
+                if (a.x != 0)
+                    hipLaunchKernelGGL((k_expect_xy<R>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a,
+                                       parts);
+                else
+                    hipLaunchKernelGGL((k_expect_z<R>), dim3(unsigned(P.nb)), dim3(kThreads), 0, h->stream, psi, a,
+                                       parts);
+                SV_HIP(hipGetLastError());
+                hipLaunchKernelGGL(k_finish_sums, dim3(unsigned(a.n_terms + 1)), dim3(kThreads), 0, h->stream,
+                                   parts, P.nb, res_dev + (li - g0) * kSlot);
+                SV_HIP(hipGetLastError());
+            }
         }
         SV_HIP(hipMemcpyAsync(host.data(), res_dev, sizeof(double) * kSlot * (g1 - g0), hipMemcpyDeviceToHost,
                               h->stream));

@@ -124,6 +124,41 @@ def test_batch_level_path_matches_oracle(P, level, kmax):
     h.close()
 
 
+def test_batch_level_path_z_sums_many_terms(P):
+    # shallow circuits (expectations of order one) on the level path with up
+    # to 32 random Z strings each, over every qubit: the last block's sums
+    # take each term from one coefficient of a per-thread transform over
+    # four tile-local index bits and a sign over the others, so terms on
+    # every bit position, on several at once and on none of the transform's
+    # bits are all needed; one circuit has no terms at all (the norm only)
+    rng = np.random.default_rng(77)
+    sizes = [13, 15, 17, 20, 14, 19]
+    counts = [32, 32, 17, 32, 0, 9]
+    ns, circuits, terms = [], [], []
+    for i, (n, t) in enumerate(zip(sizes, counts)):
+        ns.append(n)
+        circuits.append(W.brickwork(n, 1 + i % 2, 500 + i))
+        masks = [1 << q for q in range(min(t, n))]
+        while len(masks) < t:
+            m = int(rng.integers(1, 1 << n))
+            masks.append(m)
+        terms.append(masks[:t])
+    h = P.Handle()
+    h.set_batch_level_qubits(13)
+    b = P.Batch(h, ns, circuits, terms, max_fused_qubits=5)
+    exps, _, _ = b.run()
+    for i, (n, g, zm) in enumerate(zip(ns, circuits, terms)):
+        assert len(exps[i]) == len(zm)
+        if not zm:
+            continue
+        ref = oracle.run(n, g)
+        zr = np.array([oracle.expect_pauli(ref, [(q, "Z") for q in range(n) if (m >> q) & 1]) for m in zm])
+        assert np.max(np.abs(zr)) > 0.1, (i, n)  # the terms are not all near zero
+        assert np.max(np.abs(exps[i] - zr)) <= 2e-6, (i, n, np.max(np.abs(exps[i] - zr)))
+    b.close()
+    h.close()
+
+
 def test_batch_level_path_alone_equals_in_mix(P):
     sizes = [17, 20, 9, 18, 13, 19, 15, 20, 12]
     ns, circuits, terms = _mixed(6, sizes, 6, 16)
