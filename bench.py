@@ -38,15 +38,15 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources the counters were taken on: their SHA-256 are recorded and
 # checked at run time.
 _K5_SOURCES = {"paper_2308_01999_amd/csrc/sv_apply.hip":
-               "6dca62546123f1d77c95619e8af077d6c84822a95b991a578cd528cd71d68963",
+               "cf79059f6f509d8abd8860f662118b5c5ff6710a5ea28dc36f83deb7742e688b",
                "paper_2308_01999_amd/csrc/sv_tile.h":
-               "c5add302b4b2ffb570a4d879c24b9d6c9ba1c85a2392c54663058f74727a1620"}
+               "14df7118bbe9218d6f281185a9817e4518b765bfcec4ed09243b2a5b993b5984"}
 PMC_TRAFFIC = {
     # 30-qubit brickwork sweep, dispatch-weighted over all tile variants (728
     # launches of each dtype in one pass: 14 steps of 52 blocks)
-    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194398.4, "write_kib": 8389778.9,
+    "k_tile_c64_k5": {"n": 30, "fetch_kib": 4194384.0, "write_kib": 8389899.5,
                       "fetch_scale": 2.0, "write_scale": 1.0, "sources": _K5_SOURCES},
-    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388721.0, "write_kib": 16780453.0,
+    "k_tile_c128_k5": {"n": 30, "fetch_kib": 8388720.9, "write_kib": 16780158.6,
                        "fetch_scale": 2.0, "write_scale": 1.0, "sources": _K5_SOURCES},
 }
 

@@ -261,7 +261,7 @@ __global__ __launch_bounds__(NT, NT == 512 ? SV_K5_WIDE_WAVES : 1) void k_tile_c
     __shared__ float4 lds[NT * kTileVecs];
     // the packed A operands (same for every wave): 3 x 64 lanes x 4 float4,
     // read back four k-steps at a time so only 12 of them are live at once
-    __shared__ float4 amat[kK5AParts * 64 * 4];
+    __shared__ float4 amat[kK5AStaged * 64 * 4];
     tile_c64_k5_sweep<NT, false>(psi, mats, a, blockIdx.x, lds, amat, ZSums{nullptr, -1, nullptr, nullptr});
 }
 
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(NT, NT == 512 ? SV_K5_WIDE_WAVES : 3) void k_tile_c
     float2* __restrict__ psi, const float4* __restrict__ mats, TileArgs a, const CoupleDev* __restrict__ cp)
 {
     __shared__ float4 lds[NT * kTileVecs];
-    __shared__ float4 amat[kK5AParts * 64 * 4];
+    __shared__ float4 amat[kK5AStaged * 64 * 4];
     tile_c64_k5_sweep<NT, false, true>(psi, mats, a, blockIdx.x, lds, amat, ZSums{nullptr, -1, nullptr, nullptr},
                                        cp);
 }

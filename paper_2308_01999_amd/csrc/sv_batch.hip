@@ -438,7 +438,7 @@ __global__ __launch_bounds__(tile::kTileThreads, 3) void k_batch_level(float2* _
                                                                     double* __restrict__ partials)
 {
     __shared__ float4 lds[tile::kTileThreads * tile::kTileVecs];
-    __shared__ float4 amat[tile::kK5AParts * 64 * 4];
+    __shared__ float4 amat[tile::kK5AStaged * 64 * 4];
     __shared__ double zacc[(tile::kTileThreads / 64) * (tile::kZSumsMax + 1)];
     const BatchLevelEntry e = entries[blockIdx.x];
     const BatchTileDesc& d = descs[e.desc];

@@ -174,6 +174,10 @@ __device__ __forceinline__ float4 swap_pair(const float4 v, bool sw)
 // The three A operands (Re M, Im M, Re M + Im M) of the complex64 k = 5
 // sweep, kept in LDS (44 KiB per workgroup with the tile: three per CU).
 constexpr int kK5AParts = 3;
+// Of those, the parts a sweep stages in LDS: Re M and Im M (Re M + Im M is
+// formed as they are read), so that a 32 KiB tile and its operands take
+// 40 KiB: four workgroups per CU.
+constexpr int kK5AStaged = 2;
 
 
 // Z-type expectation sums of the state a sweep leaves behind, taken from the
@@ -240,7 +244,7 @@ __device__ __forceinline__ float4 basis0_pair(uint64_t i) { return i == 0 ? floa
 // Re x - A_1 Im x, Im = A_2 (Re x + Im x) - A_0 Re x - A_1 Im x with A_0 =
 // Re M, A_1 = Im M, A_2 = Re M + Im M), the next tile's loads in flight
 // meanwhile.  mats: the packed A operands (3 x 64 lanes x 4 float4); lds:
-// NT * kTileVecs float4 of LDS; amat: kK5AParts * 64 * 4 float4 of LDS.
+// NT * kTileVecs float4 of LDS; amat: kK5AStaged * 64 * 4 float4 of LDS.
 // FIRST: the input is the basis state |0..0>, which is not read.  COUPLED:
 // the block's phase coupling cp multiplies each group's inputs first.
 template <int NT, bool FIRST, bool COUPLED = false>
@@ -254,7 +258,7 @@ __device__ __forceinline__ void tile_c64_k5_sweep(float2* __restrict__ psi, cons
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 31, half = lane >> 5;
     // (from |0..0> only the workgroup with tile 0 multiplies; see below)
     if (!FIRST || t0 == 0)
-        for (int e = tid; e < kK5AParts * 64 * 4; e += NT) amat[e] = mats[e];
+        for (int e = tid; e < kK5AStaged * 64 * 4; e += NT) amat[e] = mats[e];
     if (zs.n_terms >= 0 && lane <= kZSumsMax) zs.acc[wave * (kZSumsMax + 1) + lane] = 0.0;
     uint64_t roff[kTileVecs];
     uint32_t poff[kTileVecs];
@@ -343,7 +347,7 @@ __device__ __forceinline__ void tile_c64_k5_sweep(float2* __restrict__ psi, cons
         for (int q = 0; q < 4; ++q) {
             const float4 vr = amat[(0 * 64 + lane) * 4 + q];
             const float4 vi = amat[(1 * 64 + lane) * 4 + q];
-            const float4 vs = amat[(2 * 64 + lane) * 4 + q];
+            const float4 vs = float4{vr.x + vi.x, vr.y + vi.y, vr.z + vi.z, vr.w + vi.w};
             const float ar[4] = {vr.x, vr.y, vr.z, vr.w};
             const float ai[4] = {vi.x, vi.y, vi.z, vi.w};
             const float as[4] = {vs.x, vs.y, vs.z, vs.w};
