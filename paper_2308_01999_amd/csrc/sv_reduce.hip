@@ -1692,7 +1692,10 @@ __global__ __launch_bounds__(kThreads) void k_expect_matrix(const typename Cx<R>
             double yr = 0.0, yi = 0.0;
 #pragma unroll
             for (int c = 0; c < D; ++c) {
-                const double mx = M[r * D + c].x, my = M[r * D + c].y;
+                // K <= 3: the row straight from memory (a uniform address:
+                // scalar loads, no LDS traffic per group)
+                const double2 m = K <= 3 ? mat[r * D + c] : M[r * D + c];
+                const double mx = m.x, my = m.y;
                 yr = fma(mx, double(x[c].x), fma(-my, double(x[c].y), yr));
                 yi = fma(mx, double(x[c].y), fma(my, double(x[c].x), yi));
             }
