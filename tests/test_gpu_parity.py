@@ -304,6 +304,28 @@ def test_pauli_expectations_vs_oracle(P, H, dt, n):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 2, 11, 22, 23])
+def test_many_pauli_strings_in_groups(P, H, dt, n):
+    # more distinct X/Y masks than one group of sweeps (64) holds, mixed with
+    # Z strings: states of at most 22 qubits run each group as one launch
+    # per kind of sweep, larger ones sweep by sweep; both against the
+    # oracle on the GPU's own state, and the same terms one at a time agree
+    # (up to the norm, which a call takes from its first sweep)
+    rng = np.random.default_rng(400 + n)
+    st = _state(P, H, n, dt)
+    st.run(W.brickwork(n, 3, 40 + n))
+    gpu = st.to_numpy().astype(np.complex128)
+    count = 150 if n >= 11 else 40
+    terms = W.random_pauli_terms(n, count, rng) + W.z_terms(n)
+    e = st.expect(terms)
+    e_own = np.array([oracle.expect_pauli(gpu, t) for t in terms])
+    assert np.max(np.abs(e - e_own)) <= (1e-12 if dt == "c128" else 1e-6)
+    for i in range(0, len(terms), max(1, len(terms) // 7)):
+        np.testing.assert_allclose(st.expect([terms[i]]), e[i : i + 1], rtol=0, atol=1e-13)
+    st.close()
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
 def test_norm_renormalize_and_determinism(P, H, dt):
     n = 18
     st = _state(P, H, n, dt)
