@@ -966,7 +966,7 @@ def serving_leg(P, W, torch, n_requests, slots, small_slots, check=16):
     state's probabilities, rebuilt by the same fused program)."""
     import numpy as np
     import oracle
-    from paper_2308_01999_amd.serve import Server, replay
+    from paper_2308_01999_amd.serve import Server, fusion_pieces, replay
     capacity = serving_capacity(Server, replay, W, slots, small_slots)
     rate = 0.75 * capacity
     reqs = W.serving_requests(n_requests, rate_per_s=rate, seed=0)
@@ -999,8 +999,12 @@ def serving_leg(P, W, torch, n_requests, slots, small_slots, check=16):
         er = np.array([oracle.expect_pauli(ref, t) for t in r.terms])
         t_or.append(time.perf_counter() - t1)
         dexp.append(float(np.max(np.abs(res[r.rid].expectations - er))))
+        # the served state rebuilt from the same fused pieces the server ran
         st = P.State(h, r.n, "c64")
-        st.run(r.gates, max_fused_qubits=5)
+        for part in fusion_pieces(r.n, r.gates):
+            f = P.fuse(part, 5)
+            P.sv_apply_fused(st.s, f.f)
+            f.free()
         p_g = np.abs(st.to_numpy().astype(np.complex128)) ** 2
         same = np.array_equal(st.sample(np.asarray(r.uniforms)), res[r.rid].samples)
         st.close()

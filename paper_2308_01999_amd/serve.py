@@ -64,6 +64,27 @@ def request_budget(total_bytes: int, slots: int, max_qubits: int) -> int:
     return left
 
 
+# Requests of up to CHUNK_QUBITS qubits (whose sweeps are short) are fused in
+# contiguous pieces of about CHUNK_GATES gates, at most MAX_CHUNKS, each on
+# its own pool thread: fusion, which dominates such a request's time, then
+# takes a fraction as long, and the first piece is applied while the others
+# are still being fused.  A piece boundary can cost a block or two; larger
+# states, whose sweeps dominate, are fused whole.
+CHUNK_QUBITS = 20
+CHUNK_GATES = 400
+MAX_CHUNKS = 4
+
+
+def fusion_pieces(n: int, gates: list) -> list:
+    """The contiguous pieces of a request's gate list that are fused
+    separately (one piece above CHUNK_QUBITS qubits)."""
+    if n > CHUNK_QUBITS or len(gates) <= CHUNK_GATES:
+        return [gates]
+    k = min(MAX_CHUNKS, -(-len(gates) // CHUNK_GATES))
+    size = -(-len(gates) // k)
+    return [gates[i:i + size] for i in range(0, len(gates), size)]
+
+
 def default_budget() -> int:
     """SV_HBM_BUDGET_BYTES if set (the same cap libsv applies to its own
     allocations), else 64 GiB."""
@@ -79,7 +100,7 @@ class Request:
     terms: list
     uniforms: np.ndarray
     arrival: float = 0.0          # host monotonic time of arrival (set on submit)
-    fused: Future | None = None   # the fused program, being made on the fusion pool (set on submit)
+    fused: list | None = None     # futures of the fused pieces, made on the fusion pool (set on submit)
 
 
 @dataclass
@@ -225,7 +246,7 @@ class Server:
         with self.cv:
             self.adm.add(req.rid, self.footprint(req.n), req.n <= self.small_qubits)
             if self.fuse_pool is not None:
-                req.fused = self.fuse_pool.submit(fuse, req.gates, self.kmax)
+                req.fused = [self.fuse_pool.submit(fuse, part, self.kmax) for part in fusion_pieces(req.n, req.gates)]
             self.pending[req.rid] = req
             self.cv.notify_all()
 
@@ -264,26 +285,33 @@ class Server:
                 self.cv.notify_all()
 
     def _run(self, h: Handle, req: Request, admitted: float) -> Result:
-        f = req.fused.result() if req.fused is not None else None
+        pieces = list(req.fused) if req.fused is not None else None
+        st = None
         try:
             st = State(h, req.n, self.dtype)
-        except Exception:
-            if f is not None:
-                f.free()
-            raise
-        try:
-            if f is not None:
-                sv_apply_fused(st.s, f.f)
-                nb = f.count
+            if pieces is not None:
+                # each piece as soon as it is fused, in order
+                nb = 0
+                while pieces:
+                    f = pieces.pop(0).result()
+                    try:
+                        sv_apply_fused(st.s, f.f)
+                        nb += f.count
+                    finally:
+                        f.free()
             else:
                 st.run(req.gates)  # one sweep per gate
                 nb = len(req.gates)
             exps = sv_expect_pauli(st.s, req.terms)
             smp = sv_sample(st.s, req.uniforms)
         finally:
-            if f is not None:
-                f.free()
-            st.close()
+            for fut in pieces or []:
+                try:
+                    fut.result().free()
+                except Exception:
+                    pass
+            if st is not None:
+                st.close()
         return Result(req.rid, exps, smp, nb, req.arrival, admitted, time.monotonic())
 
     def wait(self, rids, timeout: float = 600.0) -> dict:

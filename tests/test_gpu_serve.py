@@ -31,6 +31,7 @@ def _eps_ok(psi_gpu_p, psi_ref, u, got):
 
 
 def test_serving_mix_matches_alone_and_oracle(P):
+    from paper_2308_01999_amd import serve
     from paper_2308_01999_amd.serve import Server, replay, slot_reserve
     reqs = W.serving_requests(14, rate_per_s=400.0, seed=3, n_lo=6, n_hi=16, d_lo=4, d_hi=20,
                               n_terms=6, n_shots=256)
@@ -57,10 +58,13 @@ def test_serving_mix_matches_alone_and_oracle(P):
         assert np.max(np.abs(mixed[r.rid].expectations - er)) <= 1e-4
         assert mixed[r.rid].latency > 0
         # the served samples against the oracle's CDF by the epsilon rule,
-        # with epsilon from the served state: the same fused program rebuilt
+        # with epsilon from the served state: the same fused pieces rebuilt
         # on a fresh state, which samples bitwise the same outcomes
         st = P.State(h, r.n, "c64")
-        st.run(r.gates, max_fused_qubits=5)
+        for part in serve.fusion_pieces(r.n, r.gates):
+            f = P.fuse(part, 5)
+            P.sv_apply_fused(st.s, f.f)
+            f.free()
         psi = st.to_numpy().astype(np.complex128)
         np.testing.assert_array_equal(st.sample(np.asarray(r.uniforms)), mixed[r.rid].samples)
         st.close()

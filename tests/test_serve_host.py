@@ -167,12 +167,28 @@ def test_submit_starts_fusion_on_the_pool():
     srv.adm = Admission(1 << 20, 1)
     gates = W.brickwork(10, 6, 3)
     srv.submit(serve.Request(1, 10, gates, [], None))
-    f = srv.pending[1].fused.result(timeout=60)
-    try:
-        assert 0 < f.count <= len(gates)
-    finally:
-        f.free()
+    futs = srv.pending[1].fused
+    assert len(futs) == len(serve.fusion_pieces(10, gates))
+    for fut in futs:
+        f = fut.result(timeout=60)
+        try:
+            assert 0 < f.count <= len(gates)
+        finally:
+            f.free()
     with pytest.raises(ValueError):
         srv.submit(serve.Request(2, 20, gates, [], None))   # 8 MiB > 1 MiB
     assert 2 not in srv.pending
     srv.fuse_pool.shutdown(wait=True)
+
+
+def test_fusion_pieces_cover_the_gate_list_in_order():
+    import workloads as W
+    gates = W.brickwork(16, 60, 4)
+    pieces = serve.fusion_pieces(16, gates)
+    assert 1 < len(pieces) <= serve.MAX_CHUNKS
+    assert [g for p in pieces for g in p] == gates
+    assert max(len(p) for p in pieces) - min(len(p) for p in pieces) <= len(pieces)
+    # large states and short lists are fused whole
+    assert serve.fusion_pieces(serve.CHUNK_QUBITS + 1, gates) == [gates]
+    short = gates[: serve.CHUNK_GATES]
+    assert serve.fusion_pieces(16, short) == [short]
