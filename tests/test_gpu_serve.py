@@ -72,3 +72,34 @@ def test_serving_mix_matches_alone_and_oracle(P):
     h.close()
     # results arrive for every request; latency covers queueing
     assert all(m.done >= m.admitted >= m.arrival for m in mixed.values())
+
+
+def test_large_request_with_coupled_fusion_matches_oracle(P):
+    # a request above the coupled-fusion size: served expectations against
+    # the oracle, samples by the epsilon rule on the served state (rebuilt
+    # with the same coupled program, which samples bitwise the same)
+    from paper_2308_01999_amd import serve
+    from paper_2308_01999_amd.serve import Server, replay, slot_reserve
+    n = serve.COUPLED_QUBITS
+    reqs = W.serving_requests(1, rate_per_s=100.0, seed=11, n_lo=n, n_hi=n, d_lo=8, d_hi=8,
+                              n_terms=6, n_shots=512)
+    r = reqs[0]
+    srv = Server(slots=1, budget_bytes=(1 << n) * 8 + slot_reserve(n), dtype="c64", kmax=5, max_qubits=n)
+    res = replay(srv, reqs)[r.rid]
+    srv.close()
+    assert not res.error, res.error
+    f = P.fuse(r.gates, 5, coupled=True)
+    assert res.fused_blocks == f.count
+    h = P.Handle()
+    st = P.State(h, n, "c64")
+    P.sv_apply_fused(st.s, f.f)
+    f.free()
+    psi = st.to_numpy().astype(np.complex128)
+    np.testing.assert_array_equal(st.sample(np.asarray(r.uniforms)), res.samples)
+    st.close()
+    h.close()
+    ref = oracle.run(n, r.gates)
+    er = np.array([oracle.expect_pauli(ref, t) for t in r.terms])
+    assert np.max(np.abs(res.expectations - er)) <= 1e-4
+    assert oracle.fidelity(ref, psi) >= 1 - 1e-5
+    assert _eps_ok(np.abs(psi) ** 2, ref, np.asarray(r.uniforms), res.samples)
