@@ -3,7 +3,9 @@
 Requests (a named-gate circuit on n qubits, Pauli strings to evaluate, and
 uniforms to sample with) arrive over time.  Each is fused on a host thread
 pool as soon as it arrives, so fusion overlaps its wait for admission and
-the device work of other requests.  A dispatcher admits them in
+the device work of other requests: a small request in a few pieces at
+once, each applied as soon as it is fused; a large one whole, with coupled
+fusion, which saves it sweeps.  A dispatcher admits them in
 arrival order as soon as a slot is free and the request's state fits the
 HBM budget; later requests may pass a blocked head only a bounded number of
 times, so large requests do not starve.  Some slots may be kept for small
